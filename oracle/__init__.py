@@ -1,0 +1,214 @@
+"""CPU ORACLE for the sample-based closeness estimators -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import, build, load or call anything in this package.  The
+GPU library (``paper_1409_0035_amd``) never imports it and shares no code with
+it; the only module both sides use is ``graphgen`` (input construction).
+
+What it computes (Cohen, Delling, Pajor & Werneck 2014):
+  * distances from each sampled node by plain BFS / binary-heap Dijkstra
+    (Sec. 3), round-trip distances on strongly connected digraphs (Sec. 6.1);
+  * the pivot c(v) and Delta(v) (Sec. 2), the sample average Eq. (5), the
+    pivot estimate, the pivoting upper bound (Sec. 1), and the hybrid
+    estimate Eq. (6), by an explicit walk over all nodes per estimated node;
+  * exact S(v) for every node (Eq. (1)) by one search per node.
+
+Pins (closed forms, special cases, worked examples, brute force) live in
+``tests/test_oracle_pins.py``.  Parity status of each function: pinned, see
+the design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+from .sampler import draw_samples  # noqa: F401  (re-export)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c (gcc -O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class NodeOut(ctypes.Structure):
+    _fields_ = [("pivot", ctypes.c_int32), ("delta", ctypes.c_int64), ("sampsum", ctypes.c_int64),
+                ("S_piv", ctypes.c_int64), ("S_pub", ctypes.c_int64), ("S_samp", ctypes.c_double),
+                ("S_hyb", ctypes.c_double), ("L_num", ctypes.c_int64), ("LC_num", ctypes.c_int64),
+                ("HC_num", ctypes.c_int64), ("H_num", ctypes.c_int64), ("LC_sum", ctypes.c_int64),
+                ("HC_sum", ctypes.c_int64), ("H_sum", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("overflow", ctypes.c_int32), ("sampled", ctypes.c_int32)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    lib.orc_bfs.restype = i64
+    lib.orc_bfs.argtypes = [i64, P, P, i32, P]
+    lib.orc_dijkstra.restype = i64
+    lib.orc_dijkstra.argtypes = [i64, P, P, P, i32, P]
+    lib.orc_sample_distances.restype = ctypes.c_int
+    lib.orc_sample_distances.argtypes = [i64, P, P, P, P, P, P, i32, P, i32, P]
+    lib.orc_pivot.restype = i32
+    lib.orc_pivot.argtypes = [i32, P]
+    lib.orc_node_estimates.restype = ctypes.c_int
+    lib.orc_node_estimates.argtypes = [i64, i32, i64, P, P, P, i64, i64, i64, ctypes.POINTER(NodeOut)]
+    lib.orc_estimate_all.restype = ctypes.c_int
+    lib.orc_estimate_all.argtypes = [i64, i32, P, P, i64, i64, i32, P, P, P, P, P, P, P]
+    lib.orc_exact_sums.restype = ctypes.c_int
+    lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def default_eps(k: int) -> tuple[int, int]:
+    """eps = 1/round(sqrt(k)) as num/den (the paper's eps = sqrt(1/k), Sec. 8)."""
+    return 1, max(1, int(round(math.sqrt(k))))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def sssp(g, src: int, reverse_graph=None) -> np.ndarray:
+    """Distances from src (int64, -1 = unreachable).  With reverse_graph (the
+    transpose of a digraph) the result is the round-trip distance."""
+    lib = _load()
+    out = np.empty(g.n, dtype=np.int64)
+    rp, col, w = _c(g.row_ptr, np.int64), _c(g.col_idx, np.int32), _c(g.w, np.int32)
+    if w is None:
+        lib.orc_bfs(g.n, _p(rp), _p(col), int(src), _p(out))
+    else:
+        lib.orc_dijkstra(g.n, _p(rp), _p(col), _p(w), int(src), _p(out))
+    if reverse_graph is not None:
+        back = sssp(reverse_graph, src)
+        bad = (out < 0) | (back < 0)
+        out = out + back
+        out[bad] = -1
+    return out
+
+
+def sample_distances(g, samples, threads: int = 1, reverse_graph=None) -> np.ndarray:
+    """Node-major D[v, i] = d(c_i, v) (int64), round-trip when reverse_graph is given."""
+    lib = _load()
+    samples = np.ascontiguousarray(samples, dtype=np.int32)
+    k = int(samples.shape[0])
+    D = np.empty((g.n, k), dtype=np.int64)
+    rg = reverse_graph
+    st = lib.orc_sample_distances(
+        g.n, _p(_c(g.row_ptr, np.int64)), _p(_c(g.col_idx, np.int32)), _p(_c(g.w, np.int32)),
+        None if rg is None else _p(_c(rg.row_ptr, np.int64)),
+        None if rg is None else _p(_c(rg.col_idx, np.int32)),
+        None if rg is None else _p(_c(rg.w, np.int32)),
+        k, _p(samples), int(threads), _p(D))
+    if st == 2:
+        raise OracleError("graph is not (strongly) connected: a node is unreachable from a sample")
+    if st != 0:
+        raise OracleError(f"orc_sample_distances failed ({st})")
+    return D
+
+
+def sample_index(n: int, samples) -> np.ndarray:
+    sidx = np.full(n, -1, dtype=np.int32)
+    for i, c in enumerate(samples):
+        sidx[int(c)] = i
+    return sidx
+
+
+def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=None) -> dict:
+    """Every estimator for every node (O(n^2) hybrid walk: small graphs only).
+    Also returns D, the per-sample sums S(c_i) and the sample distance matrix
+    dmat[i, j] = d(c_i, c_j)."""
+    lib = _load()
+    samples = np.ascontiguousarray(samples, dtype=np.int32)
+    k = int(samples.shape[0])
+    en, ed = eps if eps is not None else default_eps(k)
+    if D is None:
+        D = sample_distances(g, samples, threads=threads, reverse_graph=reverse_graph)
+    D = np.ascontiguousarray(D, dtype=np.int64)
+    n = g.n
+    sidx = sample_index(n, samples)
+    out = dict(pivot=np.empty(n, np.int32), delta=np.empty(n, np.int64), sampsum=np.empty(n, np.int64),
+               S_piv=np.empty(n, np.int64), S_pub=np.empty(n, np.int64), S_samp=np.empty(n, np.float64),
+               S_hyb=np.empty(n, np.float64))
+    st = lib.orc_estimate_all(n, k, _p(sidx), _p(D), int(en), int(ed), int(threads),
+                              _p(out["pivot"]), _p(out["delta"]), _p(out["sampsum"]), _p(out["S_piv"]),
+                              _p(out["S_pub"]), _p(out["S_samp"]), _p(out["S_hyb"]))
+    if st != 0:
+        raise OracleError(f"orc_estimate_all failed ({st})")
+    out["D"] = D
+    out["src_sum"] = D.sum(axis=0)               # S(c_i) = sum_v d(c_i, v)
+    out["dmat"] = D[samples, :].T.copy()         # dmat[i, j] = D[c_j, i] = d(c_i, c_j)
+    out["samples"] = samples
+    out["eps"] = (en, ed)
+    return out
+
+
+def node_estimates(g, samples, v: int, eps=None, reverse_graph=None, row=None) -> NodeOut:
+    """Estimators for one node v straight from the definitions, with two
+    searches: one from v (its distances to the samples) and one from its
+    pivot c_p (the column d(c_p, .)).  Works at any graph size."""
+    lib = _load()
+    samples = np.ascontiguousarray(samples, dtype=np.int32)
+    k = int(samples.shape[0])
+    en, ed = eps if eps is not None else default_eps(k)
+    if row is None:
+        # undirected: d(c_i, v) = d(v, c_i); round trip is symmetric as well
+        dv = sssp(g, v, reverse_graph)
+        row = dv[samples]
+    row = np.ascontiguousarray(row, dtype=np.int64)
+    if (row < 0).any():
+        raise OracleError("unreachable sample")
+    p = int(lib.orc_pivot(k, _p(row)))
+    colp = sssp(g, int(samples[p]), reverse_graph)
+    if (colp < 0).any():
+        raise OracleError("unreachable node")
+    sidx = sample_index(g.n, samples)
+    o = NodeOut()
+    st = lib.orc_node_estimates(g.n, k, int(v), _p(sidx), _p(row), _p(colp), 1, int(en), int(ed),
+                                ctypes.byref(o))
+    if st not in (0, 4):
+        raise OracleError(f"orc_node_estimates failed ({st})")
+    return o
+
+
+def exact_sums(g, threads: int = 1, reverse_graph=None) -> np.ndarray:
+    """S(v) for every node, n searches (round-trip with reverse_graph)."""
+    lib = _load()
+    S = np.empty(g.n, dtype=np.int64)
+    rg = reverse_graph
+    st = lib.orc_exact_sums(g.n, _p(_c(g.row_ptr, np.int64)), _p(_c(g.col_idx, np.int32)),
+                            _p(_c(g.w, np.int32)),
+                            None if rg is None else _p(_c(rg.row_ptr, np.int64)),
+                            None if rg is None else _p(_c(rg.col_idx, np.int32)),
+                            None if rg is None else _p(_c(rg.w, np.int32)), int(threads), _p(S))
+    if st != 0:
+        raise OracleError(f"orc_exact_sums failed ({st})")
+    return S

@@ -1,0 +1,401 @@
+/*
+ * CPU ORACLE -- test infrastructure only.
+ *
+ * Plain, slow, obviously correct reference for the sample-based closeness
+ * estimators of Cohen, Delling, Pajor & Werneck, "Computing Classic Closeness
+ * Centrality, at Scale" (2014).  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may build, load or call this code; the GPU
+ * library neither links nor calls it, and it shares no code with the GPU
+ * library.
+ *
+ * Contents
+ *   orc_bfs / orc_dijkstra      single-source distances (Sec. 3: one
+ *                               shortest-path computation per sampled node);
+ *                               FIFO-queue BFS for unit lengths, binary-heap
+ *                               Dijkstra for positive integer arc lengths.
+ *   orc_sample_distances        D[v][i] = d(c_i, v) for every node and sample,
+ *                               or the round-trip distance d(c_i,v)+d(v,c_i)
+ *                               on a strongly connected digraph (Sec. 6.1).
+ *   orc_node_estimates          the estimators for ONE node written out from
+ *                               their definitions (Sec. 2): pivot and its
+ *                               distance, sample average Eq. (5), pivot
+ *                               estimate and pivoting upper bound, and the
+ *                               hybrid estimate Eq. (6) by an explicit walk
+ *                               over every node u of V \ {v} that places u in
+ *                               L(v), HC(v) or H(v).
+ *   orc_estimate_all            the above for every node, O(n^2): small graphs.
+ *   orc_exact_sums              S(v) for every node by n searches (Eq. (1)).
+ *
+ * Readings of the paper used here (all listed with reasons in the design notes):
+ *   - pivot ties go to the lowest sample index (Alg. 2 updates the pivot only
+ *     on a strictly smaller distance while scanning samples in index order);
+ *   - u is in L(v) iff d(c(v),u) <= Delta(v)/eps, compared exactly as
+ *     d*eps_num <= Delta*eps_den with eps = eps_num/eps_den in (0, 1];
+ *   - for v in C every estimator returns the exact S(v) (Sec. 2);
+ *   - the sample average is reported as a sum: S_samp = (n-1)/k * sum_i d;
+ *   - the hybrid value is the rational N/|L cap C| with
+ *     N = (sum_H + sum_HC)*|L cap C| + |L|*sum_{L cap C}, rounded once to
+ *     double (N is checked to be below 2^53 so the conversion is exact).
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EUNREACHED 2
+#define ORC_ENOMEM 3
+#define ORC_EOVERFLOW 4
+
+/* ------------------------------------------------------------------------ */
+/* Breadth-first search: dist[v] = number of arcs on a shortest path from src,
+ * -1 if unreachable.  Returns the largest finite distance. */
+int64_t orc_bfs(int64_t n, const int64_t* rp, const int32_t* col, int32_t src, int64_t* dist) {
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return -1;
+    for (int64_t v = 0; v < n; v++) dist[v] = -1;
+    int64_t head = 0, tail = 0, maxd = 0;
+    dist[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        int32_t v = queue[head++];
+        int64_t dv = dist[v];
+        if (dv > maxd) maxd = dv;
+        for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+            int32_t u = col[e];
+            if (dist[u] < 0) {
+                dist[u] = dv + 1;
+                queue[tail++] = u;
+            }
+        }
+    }
+    free(queue);
+    return maxd;
+}
+
+/* Dijkstra's algorithm with a binary min-heap keyed by tentative distance
+ * (lazy deletion: stale heap entries are skipped when popped). */
+typedef struct { int64_t d; int32_t v; } orc_item;
+
+static void heap_push(orc_item* h, int64_t* size, orc_item it) {
+    int64_t i = (*size)++;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].d <= it.d) break;
+        h[i] = h[p];
+        i = p;
+    }
+    h[i] = it;
+}
+
+static orc_item heap_pop(orc_item* h, int64_t* size) {
+    orc_item top = h[0];
+    orc_item last = h[--(*size)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        int64_t dm = last.d;
+        if (l < *size && h[l].d < dm) { m = l; dm = h[l].d; }
+        if (r < *size && h[r].d < dm) { m = r; }
+        if (m == i) break;
+        h[i] = h[m];
+        i = m;
+    }
+    if (*size > 0) h[i] = last;
+    return top;
+}
+
+int64_t orc_dijkstra(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* w, int32_t src,
+                     int64_t* dist) {
+    int64_t arcs = rp[n];
+    orc_item* heap = (orc_item*)malloc(sizeof(orc_item) * (size_t)(arcs + 2));
+    char* done = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!heap || !done) { free(heap); free(done); return -1; }
+    for (int64_t v = 0; v < n; v++) dist[v] = -1;
+    int64_t size = 0, maxd = 0;
+    dist[src] = 0;
+    orc_item s0 = {0, src};
+    heap_push(heap, &size, s0);
+    while (size > 0) {
+        orc_item it = heap_pop(heap, &size);
+        int32_t v = it.v;
+        if (done[v]) continue;
+        done[v] = 1;
+        if (it.d > maxd) maxd = it.d;
+        for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+            int32_t u = col[e];
+            int64_t nd = it.d + (int64_t)w[e];
+            if (!done[u] && (dist[u] < 0 || nd < dist[u])) {
+                dist[u] = nd;
+                orc_item x = {nd, u};
+                heap_push(heap, &size, x);
+            }
+        }
+    }
+    free(heap); free(done);
+    return maxd;
+}
+
+/* one search; w == NULL selects BFS */
+static int64_t sssp(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* w, int32_t src,
+                    int64_t* dist) {
+    return w ? orc_dijkstra(n, rp, col, w, src, dist) : orc_bfs(n, rp, col, src, dist);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Distances from every sample.  D is node-major: D[v*k + i] = d(c_i, v).
+ * If rrp != NULL the graph is a digraph and (rrp, rcol, rw) is its transpose;
+ * then D holds round-trip distances d(c_i -> v) + d(v -> c_i), the second term
+ * being the distance from c_i in the transposed graph.
+ * Returns ORC_EUNREACHED if some node is unreachable from some sample. */
+typedef struct {
+    int64_t n; const int64_t* rp; const int32_t* col; const int32_t* w;
+    const int64_t* rrp; const int32_t* rcol; const int32_t* rw;
+    int32_t k; const int32_t* samples; int64_t* D;
+    int32_t next; pthread_mutex_t lock; int status;
+} dist_job;
+
+static void* dist_worker(void* arg) {
+    dist_job* J = (dist_job*)arg;
+    int64_t* a = (int64_t*)malloc(sizeof(int64_t) * (size_t)J->n);
+    int64_t* b = J->rrp ? (int64_t*)malloc(sizeof(int64_t) * (size_t)J->n) : NULL;
+    if (!a || (J->rrp && !b)) {
+        pthread_mutex_lock(&J->lock); J->status = ORC_ENOMEM; pthread_mutex_unlock(&J->lock);
+        free(a); free(b); return NULL;
+    }
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int32_t i = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (i >= J->k) break;
+        sssp(J->n, J->rp, J->col, J->w, J->samples[i], a);
+        if (b) sssp(J->n, J->rrp, J->rcol, J->rw, J->samples[i], b);
+        int bad = 0;
+        for (int64_t v = 0; v < J->n; v++) {
+            int64_t d = a[v];
+            if (d < 0 || (b && b[v] < 0)) { bad = 1; d = -1; }
+            else if (b) d += b[v];
+            J->D[v * J->k + i] = d;
+        }
+        if (bad) { pthread_mutex_lock(&J->lock); J->status = ORC_EUNREACHED; pthread_mutex_unlock(&J->lock); }
+    }
+    free(a); free(b);
+    return NULL;
+}
+
+int orc_sample_distances(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* w,
+                         const int64_t* rrp, const int32_t* rcol, const int32_t* rw,
+                         int32_t k, const int32_t* samples, int32_t threads, int64_t* D) {
+    dist_job J;
+    J.n = n; J.rp = rp; J.col = col; J.w = w; J.rrp = rrp; J.rcol = rcol; J.rw = rw;
+    J.k = k; J.samples = samples; J.D = D; J.next = 0; J.status = ORC_OK;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads < 1) threads = 1;
+    if (threads == 1) {
+        dist_worker(&J);
+    } else {
+        pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+        for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, dist_worker, &J);
+        for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
+    pthread_mutex_destroy(&J.lock);
+    return J.status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Estimates for one node v, from the definitions of Sec. 2.
+ *
+ *   row[i]          = d(v, c_i), i = 0..k-1 (distances to the samples)
+ *   colp[u*stride]  = d(c_p, u) for every node u, where p is the pivot of v;
+ *                     the caller finds p with orc_pivot(row) first.
+ *   sidx[u]         = index i with c_i = u, or -1 when u is not sampled.
+ *
+ * The walk over u in V \ {v} is the partition of Sec. 2 written out:
+ *   d(c_p,u) <= Delta/eps  ->  u in L(v)   (u in C: also in L cap C)
+ *   otherwise, u in C      ->  u in HC(v), contributes d(v,u) exactly
+ *   otherwise              ->  u in H(v),  contributes d(c_p,u)
+ */
+typedef struct {
+    int32_t pivot;      /* sample index of c(v) */
+    int64_t delta;      /* Delta(v) = d(v, c(v)) */
+    int64_t sampsum;    /* sum_i d(v, c_i) */
+    int64_t S_piv;      /* pivot estimate S(c(v)) */
+    int64_t S_pub;      /* pivoting upper bound S(c(v)) + (n-1) Delta(v) */
+    double S_samp;      /* sample-average estimate, as a sum */
+    double S_hyb;       /* hybrid estimate Eq. (6) */
+    /* the parts of Eq. (6), for inspection */
+    int64_t L_num, LC_num, HC_num, H_num;
+    int64_t LC_sum, HC_sum, H_sum;
+    int64_t N;          /* numerator of S_hyb = N / LC_num */
+    int32_t overflow;   /* N or (n-1)*sampsum reached 2^53 */
+    int32_t sampled;    /* v is in C */
+} orc_node_out;
+
+int32_t orc_pivot(int32_t k, const int64_t* row) {
+    int32_t p = 0;
+    for (int32_t i = 1; i < k; i++)
+        if (row[i] < row[p]) p = i; /* strict: ties keep the lower index */
+    return p;
+}
+
+int orc_node_estimates(int64_t n, int32_t k, int64_t v, const int32_t* sidx, const int64_t* row,
+                       const int64_t* colp, int64_t stride, int64_t eps_num, int64_t eps_den,
+                       orc_node_out* out) {
+    const int64_t LIM = (int64_t)1 << 53;
+    memset(out, 0, sizeof(*out));
+    int32_t p = orc_pivot(k, row);
+    int64_t delta = row[p];
+    int64_t sampsum = 0;
+    for (int32_t i = 0; i < k; i++) sampsum += row[i];
+    int64_t Sp = 0; /* S(c_p) = sum over all u of d(c_p, u) */
+    for (int64_t u = 0; u < n; u++) Sp += colp[u * stride];
+    out->pivot = p;
+    out->delta = delta;
+    out->sampsum = sampsum;
+    if (sidx[v] >= 0) {
+        /* v = c_j is its own pivot and its distances to all nodes are known */
+        out->sampled = 1;
+        out->S_piv = out->S_pub = Sp;
+        out->S_samp = out->S_hyb = (double)Sp;
+        out->N = Sp; out->LC_num = 1;
+        out->overflow = Sp >= LIM;
+        return Sp >= LIM ? ORC_EOVERFLOW : ORC_OK;
+    }
+    out->S_piv = Sp;
+    out->S_pub = Sp + (n - 1) * delta;
+    int64_t ss = (n - 1) * sampsum;
+    out->S_samp = (double)ss / (double)k;
+    int64_t Lnum = 0, LCnum = 0, HCnum = 0, Hnum = 0, LCsum = 0, HCsum = 0, Hsum = 0;
+    for (int64_t u = 0; u < n; u++) {
+        if (u == v) continue;
+        int64_t dpu = colp[u * stride];
+        int in_L = dpu * eps_num <= delta * eps_den;
+        int32_t i = sidx[u];
+        if (in_L) {
+            Lnum++;
+            if (i >= 0) { LCnum++; LCsum += row[i]; }
+        } else if (i >= 0) {
+            HCnum++; HCsum += row[i];
+        } else {
+            Hnum++; Hsum += dpu;
+        }
+    }
+    out->L_num = Lnum; out->LC_num = LCnum; out->HC_num = HCnum; out->H_num = Hnum;
+    out->LC_sum = LCsum; out->HC_sum = HCsum; out->H_sum = Hsum;
+    /* LCnum >= 1 always: the pivot is in L cap C when eps <= 1 */
+    if (LCnum < 1) { out->S_hyb = -1.0; return ORC_EOVERFLOW; }
+    /* S_hyb = Hsum + HCsum + Lnum * LCsum / LCnum = N / LCnum */
+    __int128 N = (__int128)(Hsum + HCsum) * LCnum + (__int128)Lnum * LCsum;
+    int ovf = (N >= (__int128)LIM) || (ss >= LIM);
+    out->N = (int64_t)N;
+    out->S_hyb = (double)(int64_t)N / (double)LCnum;
+    out->overflow = ovf;
+    return ovf ? ORC_EOVERFLOW : ORC_OK;
+}
+
+/* All nodes of a small graph from the full distance matrix D (node-major,
+ * n x k).  Output arrays have n entries; any may be NULL. Multithreaded over
+ * nodes when threads > 1. */
+typedef struct {
+    int64_t n; int32_t k; const int32_t* sidx; const int64_t* D; int64_t en, ed;
+    int32_t* pivot; int64_t* delta; int64_t* sampsum; int64_t* S_piv; int64_t* S_pub;
+    double* S_samp; double* S_hyb;
+    int64_t next; pthread_mutex_t lock; int status;
+} all_job;
+
+static void* all_worker(void* arg) {
+    all_job* J = (all_job*)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t v0 = J->next; J->next += 64;
+        pthread_mutex_unlock(&J->lock);
+        if (v0 >= J->n) break;
+        int64_t v1 = v0 + 64 < J->n ? v0 + 64 : J->n;
+        for (int64_t v = v0; v < v1; v++) {
+            const int64_t* row = J->D + v * J->k;
+            int32_t p = orc_pivot(J->k, row);
+            orc_node_out o;
+            int st = orc_node_estimates(J->n, J->k, v, J->sidx, row, J->D + p, J->k, J->en, J->ed, &o);
+            if (st != ORC_OK) { pthread_mutex_lock(&J->lock); J->status = st; pthread_mutex_unlock(&J->lock); }
+            if (J->pivot) J->pivot[v] = o.pivot;
+            if (J->delta) J->delta[v] = o.delta;
+            if (J->sampsum) J->sampsum[v] = o.sampsum;
+            if (J->S_piv) J->S_piv[v] = o.S_piv;
+            if (J->S_pub) J->S_pub[v] = o.S_pub;
+            if (J->S_samp) J->S_samp[v] = o.S_samp;
+            if (J->S_hyb) J->S_hyb[v] = o.S_hyb;
+        }
+    }
+    return NULL;
+}
+
+int orc_estimate_all(int64_t n, int32_t k, const int32_t* sidx, const int64_t* D, int64_t eps_num,
+                     int64_t eps_den, int32_t threads, int32_t* pivot, int64_t* delta, int64_t* sampsum,
+                     int64_t* S_piv, int64_t* S_pub, double* S_samp, double* S_hyb) {
+    all_job J;
+    J.n = n; J.k = k; J.sidx = sidx; J.D = D; J.en = eps_num; J.ed = eps_den;
+    J.pivot = pivot; J.delta = delta; J.sampsum = sampsum; J.S_piv = S_piv; J.S_pub = S_pub;
+    J.S_samp = S_samp; J.S_hyb = S_hyb; J.next = 0; J.status = ORC_OK;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads <= 1) {
+        all_worker(&J);
+    } else {
+        pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+        for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, all_worker, &J);
+        for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
+    pthread_mutex_destroy(&J.lock);
+    return J.status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact S(v) = sum_u d(v,u) for every node: one search per node (Eq. (1)).
+ * Round-trip when the transpose is given. */
+typedef struct {
+    int64_t n; const int64_t* rp; const int32_t* col; const int32_t* w;
+    const int64_t* rrp; const int32_t* rcol; const int32_t* rw;
+    int64_t* S; int64_t next; pthread_mutex_t lock; int status;
+} exact_job;
+
+static void* exact_worker(void* arg) {
+    exact_job* J = (exact_job*)arg;
+    int64_t* a = (int64_t*)malloc(sizeof(int64_t) * (size_t)J->n);
+    int64_t* b = J->rrp ? (int64_t*)malloc(sizeof(int64_t) * (size_t)J->n) : NULL;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t v = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (v >= J->n) break;
+        sssp(J->n, J->rp, J->col, J->w, (int32_t)v, a);
+        if (b) sssp(J->n, J->rrp, J->rcol, J->rw, (int32_t)v, b);
+        int64_t s = 0; int bad = 0;
+        for (int64_t u = 0; u < J->n; u++) {
+            if (a[u] < 0 || (b && b[u] < 0)) { bad = 1; continue; }
+            s += a[u] + (b ? b[u] : 0);
+        }
+        J->S[v] = bad ? -1 : s;
+        if (bad) { pthread_mutex_lock(&J->lock); J->status = ORC_EUNREACHED; pthread_mutex_unlock(&J->lock); }
+    }
+    free(a); free(b);
+    return NULL;
+}
+
+int orc_exact_sums(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* w, const int64_t* rrp,
+                   const int32_t* rcol, const int32_t* rw, int32_t threads, int64_t* S) {
+    exact_job J;
+    J.n = n; J.rp = rp; J.col = col; J.w = w; J.rrp = rrp; J.rcol = rcol; J.rw = rw;
+    J.S = S; J.next = 0; J.status = ORC_OK;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads <= 1) {
+        exact_worker(&J);
+    } else {
+        pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+        for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, exact_worker, &J);
+        for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
+    pthread_mutex_destroy(&J.lock);
+    return J.status;
+}

@@ -1,0 +1,78 @@
+"""Set-level brute force for tiny graphs (test infrastructure only).
+
+Distances by Floyd-Warshall over an adjacency matrix (all pairs, no search
+order at all), then every estimator of Sec. 2 evaluated with explicit Python
+sets and exact rationals (fractions.Fraction): L(j), HC(j) and H(j) are built
+as sets and Eq. (6) is evaluated as written.  Used to cross-check the C oracle
+on many random tiny graphs; O(n^3) time.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+INF = float("inf")
+
+
+def floyd_warshall(n, row_ptr, col_idx, w=None):
+    d = [[INF] * n for _ in range(n)]
+    for v in range(n):
+        d[v][v] = 0
+        for e in range(int(row_ptr[v]), int(row_ptr[v + 1])):
+            u = int(col_idx[e])
+            c = 1 if w is None else int(w[e])
+            if u != v and c < d[v][u]:
+                d[v][u] = c
+    for m in range(n):
+        dm = d[m]
+        for a in range(n):
+            dam = d[a][m]
+            if dam == INF:
+                continue
+            da = d[a]
+            for b in range(n):
+                x = dam + dm[b]
+                if x < da[b]:
+                    da[b] = x
+    return d
+
+
+def round_trip(d):
+    n = len(d)
+    return [[d[a][b] + d[b][a] for b in range(n)] for a in range(n)]
+
+
+def estimates(dist, samples, eps: Fraction):
+    """dist: full n x n metric (list of lists); samples: ordered list C.
+    Returns dict of per-node lists: pivot, delta, S_exact, S_samp, S_piv, S_pub, S_hyb
+    (Fractions for the fractional ones)."""
+    n = len(dist)
+    k = len(samples)
+    C = set(samples)
+    S = [sum(dist[v]) for v in range(n)]
+    out = {key: [] for key in ("pivot", "delta", "S_exact", "S_samp", "S_piv", "S_pub", "S_hyb")}
+    for j in range(n):
+        out["S_exact"].append(S[j])
+        dists = [dist[j][c] for c in samples]
+        m = min(dists)
+        p = dists.index(m)              # first (lowest) index among ties
+        cp = samples[p]
+        out["pivot"].append(p)
+        out["delta"].append(m)
+        if j in C:
+            for key in ("S_samp", "S_piv", "S_pub", "S_hyb"):
+                out[key].append(Fraction(S[j]))
+            continue
+        T = Fraction(m) / eps
+        others = set(range(n)) - {j}
+        L = {i for i in others if dist[cp][i] <= T}
+        HC = {i for i in others if i in C and dist[cp][i] > T}
+        H = {i for i in others if i not in C and dist[cp][i] > T}
+        assert L | HC | H == others and not (L & HC) and not (L & H) and not (HC & H)
+        LC = L & C
+        s_hyb = (sum(Fraction(dist[cp][i]) for i in H) + sum(Fraction(dist[j][i]) for i in HC)
+                 + Fraction(len(L), len(LC)) * sum(Fraction(dist[j][i]) for i in LC))
+        out["S_hyb"].append(s_hyb)
+        out["S_samp"].append(Fraction(n - 1, k) * sum(dists))
+        out["S_piv"].append(Fraction(S[cp]))
+        out["S_pub"].append(Fraction(S[cp] + (n - 1) * m))
+    return out

@@ -1,0 +1,300 @@
+"""Pins for the CPU oracle: it is checked against things other than itself --
+closed forms, special cases where Eq. (6) collapses to a known value, hand
+derivations (tests/golden), deterministic inequalities from Sec. 1, and an
+all-pairs brute force that shares no search code with it."""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import tiny
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([int(x) for x in line.split()])
+    return np.array(rows, dtype=np.int64)
+
+
+# ---------------------------------------------------------------- distances
+
+def _s_path(n, v):
+    return v * (v + 1) // 2 + (n - 1 - v) * (n - v) // 2
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 50])
+def test_bfs_path_closed_form(n):
+    g = graphgen.path(n) if n > 1 else graphgen.Graph(1, np.zeros(2, np.int64), np.zeros(0, np.int32))
+    for s in {0, n // 2, n - 1}:
+        d = oracle.sssp(g, s)
+        assert (d == np.abs(np.arange(n) - s)).all()
+
+
+@pytest.mark.parametrize("n", [3, 8, 33])
+def test_bfs_cycle_star_complete(n):
+    d = oracle.sssp(graphgen.cycle(n), 0)
+    i = np.arange(n)
+    assert (d == np.minimum(i, n - i)).all()
+    d = oracle.sssp(graphgen.star(n), 0)
+    assert d[0] == 0 and (d[1:] == 1).all()
+    d = oracle.sssp(graphgen.star(n), 1)
+    assert d[0] == 1 and d[1] == 0 and (d[2:] == 2).all()
+    d = oracle.sssp(graphgen.complete(n), n - 1)
+    assert (d[:-1] == 1).all() and d[-1] == 0
+
+
+@pytest.mark.parametrize("rows,cols", [(5, 7), (9, 4)])
+def test_bfs_grids_closed_form(rows, cols):
+    g4 = graphgen.grid(rows, cols, 4)
+    g8 = graphgen.grid(rows, cols, 8)
+    y, x = np.divmod(np.arange(rows * cols), cols)
+    for s in (0, rows * cols // 2 + 1, rows * cols - 1):
+        sy, sx = divmod(s, cols)
+        assert (oracle.sssp(g4, s) == np.abs(y - sy) + np.abs(x - sx)).all()           # L1
+        assert (oracle.sssp(g8, s) == np.maximum(np.abs(y - sy), np.abs(x - sx))).all()  # Chebyshev
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_sssp_vs_floyd_warshall(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 24))
+    directed = seed % 3 == 2
+    wmax = 1 if seed % 2 == 0 else 9
+    g = graphgen.gnp(n, float(rng.uniform(0.05, 0.4)), seed, directed=directed, wmax=wmax)
+    fw = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    for s in range(n):
+        d = oracle.sssp(g, s)
+        assert list(d) == [int(x) for x in fw[s]]
+    if directed:
+        gt = graphgen.transpose(g)
+        rt = tiny.round_trip(fw)
+        for s in range(n):
+            assert list(oracle.sssp(g, s, gt)) == [int(x) for x in rt[s]]
+
+
+def test_dijkstra_unit_weights_equals_bfs():
+    g = graphgen.rmat(10, 8, seed=7)
+    gw = graphgen.Graph(g.n, g.row_ptr, g.col_idx, np.ones(g.arcs, np.int32))
+    for s in (0, 5, g.n - 1):
+        assert (oracle.sssp(g, s) == oracle.sssp(gw, s)).all()
+
+
+def test_directed_cycle_round_trip():
+    n = 11
+    g = graphgen.directed_cycle(n)
+    gt = graphgen.transpose(g)
+    for s in range(n):
+        d = oracle.sssp(g, s, gt)
+        assert d[s] == 0 and (np.delete(d, s) == n).all()
+
+
+# ---------------------------------------------------------------- exact sums
+
+def test_exact_sums_closed_forms():
+    n = 13
+    assert (oracle.exact_sums(graphgen.path(n)) == [_s_path(n, v) for v in range(n)]).all()
+    assert (oracle.exact_sums(graphgen.cycle(n)) == n * n // 4).all()
+    assert (oracle.exact_sums(graphgen.cycle(12)) == 12 * 12 // 4).all()
+    s = oracle.exact_sums(graphgen.star(n))
+    assert s[0] == n - 1 and (s[1:] == 2 * n - 3).all()
+    assert (oracle.exact_sums(graphgen.complete(n)) == n - 1).all()
+    R, C = 6, 5
+    g = graphgen.grid(R, C, 4)
+    y, x = np.divmod(np.arange(R * C), C)
+    want = [C * _s_path(R, yy) + R * _s_path(C, xx) for yy, xx in zip(y, x)]
+    assert (oracle.exact_sums(g) == want).all()
+    gd = graphgen.directed_cycle(9)
+    assert (oracle.exact_sums(gd, reverse_graph=graphgen.transpose(gd)) == 9 * 8).all()
+
+
+# ---------------------------------------------------------------- estimators
+
+@pytest.mark.parametrize("name,C,n", [("path9_C048_eps1_2.txt", [0, 4, 8], 9),
+                                      ("path5_C04_eps1_2.txt", [0, 4], 5)])
+def test_worked_examples(name, C, n):
+    gold = _read_golden(name)
+    r = oracle.estimate_all(graphgen.path(n), C, eps=(1, 2))
+    assert (r["pivot"] == gold[:, 1]).all()
+    assert (r["delta"] == gold[:, 2]).all()
+    assert (r["S_hyb"] == gold[:, 4] / gold[:, 5]).all()      # one rounding of an exact rational
+    assert (r["S_samp"] == gold[:, 6] / gold[:, 7]).all()
+    sampled = np.isin(np.arange(n), C)
+    assert (r["S_hyb"][sampled] == gold[sampled, 3]).all()
+
+
+def test_tie_break_changes_result():
+    """Pivot ties go to the lowest sample index: listing the samples in the
+    other order moves node 2 of P_9 to the 80/3 value (and node 6 to 32)."""
+    r = oracle.estimate_all(graphgen.path(9), [8, 4, 0], eps=(1, 2))
+    assert r["S_hyb"][2] == 80 / 3 and r["S_hyb"][6] == 32.0
+
+
+@pytest.mark.parametrize("n", [6, 17])
+def test_all_sampled_gives_exact(n):
+    g = graphgen.gnp(n, 0.3, n, wmax=5)
+    S = oracle.exact_sums(g)
+    r = oracle.estimate_all(g, list(np.random.default_rng(n).permutation(n)), eps=(1, 3))
+    for key in ("S_hyb", "S_samp", "S_piv", "S_pub"):
+        assert (r[key] == S).all(), key
+    assert (r["delta"] == 0).all()
+
+
+@pytest.mark.parametrize("k", [1, 3, 10])
+def test_complete_graph_exact(k):
+    n = 12
+    r = oracle.estimate_all(graphgen.complete(n), list(range(2, 2 + k)), eps=(1, 4))
+    assert (r["S_hyb"] == n - 1).all()
+
+
+def test_star_closed_forms():
+    n, k = 15, 4
+    g = graphgen.star(n)
+    # centre sampled (listed second), eps <= 1: an unsampled leaf gets (n-1)(2k-1)/k
+    C = [3, 0, 7, 9]
+    r = oracle.estimate_all(g, C, eps=(1, 1))
+    leaves = [v for v in range(1, n) if v not in C]
+    assert (r["S_hyb"][leaves] == (n - 1) * (2 * k - 1) / k).all()
+    assert (r["pivot"][leaves] == 1).all()
+    # centre unsampled: eps <= 1/2 -> exact n-1 ; 1/2 < eps <= 1 -> 2n-2-k
+    C = [3, 5, 7, 9]
+    assert oracle.estimate_all(g, C, eps=(1, 2))["S_hyb"][0] == n - 1
+    assert oracle.estimate_all(g, C, eps=(2, 3))["S_hyb"][0] == 2 * n - 2 - k
+    assert oracle.estimate_all(g, C, eps=(1, 1))["S_hyb"][0] == 2 * n - 2 - k
+    # unsampled leaf, centre unsampled: 2(n-1) for every eps <= 1
+    for eps in ((1, 1), (1, 2), (1, 10)):
+        r = oracle.estimate_all(g, C, eps=eps)
+        assert r["S_hyb"][1] == 2 * (n - 1) and r["S_hyb"][2] == 2 * (n - 1)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tiny_eps_reduces_to_sample_average(seed):
+    """Delta/eps beyond every distance puts all of V \\ {v} in L(v): Eq. (6)
+    becomes (n-1)/k times the sum of the sampled distances, Eq. (5)."""
+    g = graphgen.gnp(30, 0.1, 200 + seed, wmax=4)
+    C = oracle.draw_samples(g.n, 7, seed)
+    D = oracle.sample_distances(g, C)
+    r = oracle.estimate_all(g, C, eps=(1, int(D.max()) + 1), D=D)
+    assert (r["S_hyb"] == r["S_samp"]).all()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pivot_bounds(seed):
+    """Sec. 1 triangle-inequality facts, deterministic for every node:
+    S(v) <= S(c(v)) + (n-1) Delta(v)  and  S(c(v)) <= S(v) + (n-1) Delta(v)."""
+    g = graphgen.gnp(40, 0.08, 300 + seed, wmax=1 + 5 * (seed % 2))
+    C = oracle.draw_samples(g.n, 5, seed)
+    S = oracle.exact_sums(g)
+    r = oracle.estimate_all(g, C)
+    assert (S <= r["S_pub"]).all()
+    assert (r["S_piv"] <= S + (g.n - 1) * r["delta"]).all()
+    D = r["D"]
+    assert (r["delta"] == D.min(axis=1)).all()
+    assert (D[np.arange(g.n), r["pivot"]] == r["delta"]).all()
+    # lowest index among ties
+    first = np.argmax(D == D.min(axis=1, keepdims=True), axis=1)
+    assert (r["pivot"] == first).all()
+
+
+def test_symmetric_digraph_round_trip_doubles():
+    g = graphgen.gnp(25, 0.15, 9, wmax=3)
+    gd = graphgen.symmetric_digraph(g)
+    C = oracle.draw_samples(g.n, 6, 3)
+    a = oracle.estimate_all(g, C, eps=(1, 2))
+    b = oracle.estimate_all(gd, C, eps=(1, 2), reverse_graph=graphgen.transpose(gd))
+    assert (b["pivot"] == a["pivot"]).all()
+    assert (b["S_hyb"] == 2 * a["S_hyb"]).all()
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_oracle_vs_set_brute_force(seed):
+    """Random tiny graphs, all eps kinds: the C oracle equals the Fraction /
+    Python-set evaluation of Eq. (6) on Floyd-Warshall distances."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 20))
+    directed = seed % 4 == 3
+    g = graphgen.gnp(n, float(rng.uniform(0.05, 0.5)), seed, directed=directed,
+                     wmax=1 if seed % 2 else 6)
+    k = int(rng.integers(1, n + 1))
+    C = oracle.draw_samples(n, k, seed)
+    eps = [(1, 1), (1, 2), (2, 3), (1, 3), (1, 10), (3, 7)][seed % 6]
+    fw = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    rg = None
+    if directed:
+        fw = tiny.round_trip(fw)
+        rg = graphgen.transpose(g)
+    t = tiny.estimates(fw, C, Fraction(*eps))
+    r = oracle.estimate_all(g, C, eps=eps, reverse_graph=rg)
+    assert list(r["pivot"]) == t["pivot"]
+    for key in ("S_hyb", "S_samp", "S_piv", "S_pub"):
+        assert [float(x) for x in t[key]] == list(r[key].astype(float)), key
+
+
+def test_node_estimates_match_all_nodes():
+    g = graphgen.ba(300, 3, seed=4)
+    C = oracle.draw_samples(g.n, 16, 8)
+    r = oracle.estimate_all(g, C)
+    for v in (0, 5, 77, 299, int(C[3])):
+        o = oracle.node_estimates(g, C, v)
+        assert o.pivot == r["pivot"][v] and o.delta == r["delta"][v]
+        assert o.S_hyb == r["S_hyb"][v] and o.S_samp == r["S_samp"][v]
+        assert o.S_pub == r["S_pub"][v] and o.sampsum == r["sampsum"][v]
+        if v not in C:
+            assert o.L_num + o.HC_num + o.H_num == g.n - 1
+            assert o.LC_num + o.HC_num == len(C)
+            assert o.LC_num >= 1
+
+
+def test_sum_invariant_per_sample():
+    """S(c_i) = sum over non-sampled u of d(c_i,u) + sum_j dmat[i][j]."""
+    g = graphgen.grid(20, 20, 8, 0.1, 1, 50, seed=5)
+    C = oracle.draw_samples(g.n, 9, 2)
+    r = oracle.estimate_all(g, C)
+    D = r["D"]
+    mask = np.ones(g.n, bool)
+    mask[C] = False
+    assert (r["src_sum"] == D[mask].sum(axis=0) + r["dmat"].sum(axis=1)).all()
+    assert (r["dmat"] == r["dmat"].T).all() and (np.diag(r["dmat"]) == 0).all()
+
+
+# ---------------------------------------------------------------- sampler
+
+def test_sampler_properties():
+    for n, k, seed in [(10, 10, 1), (1000, 64, 2), (1 << 22, 256, 3), (5, 1, 4)]:
+        s = oracle.draw_samples(n, k, seed)
+        assert len(s) == k and len(set(s)) == k and min(s) >= 0 and max(s) < n
+        assert s == oracle.draw_samples(n, k, seed)
+    assert oracle.draw_samples(1000, 64, 2) != oracle.draw_samples(1000, 64, 3)
+    # k = n is a permutation
+    assert sorted(oracle.draw_samples(50, 50, 9)) == list(range(50))
+
+
+def test_sampler_uniformity():
+    """First draw over n=10 from 20,000 seeds: chi-square well below the
+    0.999 quantile for 9 degrees of freedom (27.9)."""
+    counts = np.zeros(10)
+    for seed in range(20000):
+        counts[oracle.draw_samples(10, 1, seed)[0]] += 1
+    chi2 = ((counts - 2000) ** 2 / 2000).sum()
+    assert chi2 < 27.9
+
+
+def test_splitmix_bounded_is_exact_on_small_ranges():
+    """below(s) is a deterministic function of the 64-bit draws; check its
+    range and that s = 1 always yields 0 and s = 2^k uses the top bits."""
+    from oracle.sampler import SplitMix64
+    r1, r2 = SplitMix64(42), SplitMix64(42)
+    for _ in range(1000):
+        x = r2.next()
+        assert r1.below(8) == x >> 61           # power of two: never rejects
+    r = SplitMix64(7)
+    assert all(r.below(1) == 0 for _ in range(100))
