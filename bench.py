@@ -1,0 +1,218 @@
+"""Benchmark: k-source shortest-path traversal + hybrid closeness estimate on one MI355X.
+
+One step = one full estimate (sample draw, all k traversals, every estimator
+of Sec. 2 for every node, outputs left in device memory) on a resident graph.
+Default workload: undirected R-MAT scale 20 (a,b,c,d = .57,.19,.19,.05, edge
+factor 16, duplicates and self-loops removed, largest connected component),
+k = 256 samples, batched 64-samples-per-word BFS.
+
+Prints ONE JSON line.  `value` = GTEPS of the batched path = k * m / t with m
+the undirected edge count (each edge once) and t the wall time of one step.
+Also reported: the plain one-sample-at-a-time GPU path, per-step latency
+percentiles, the roofline of the dominant kernel (the batched traversal
+kernel: algorithmic bytes / its HIP-event-timed duration), and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "GTEPS of k-source SSSP + hybrid estimate, batched vs plain; p99 job latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def algorithmic_bytes(t: dict, n: int, k: int, W: int) -> float:
+    """Bytes the batched pull traversal must move, from its own work counters:
+    per scanned arc 4 B (target id) + db B (level stamp of the target); per
+    arc whose target was on the previous level 8W B (its seen mask); per node
+    processed in a level 8 B (row bounds) + 16W B (seen mask in and out) +
+    8 B (work-list entry in and out); and the distance matrix written once,
+    n*k*db B."""
+    db = t["dist_bytes"]
+    return (t["arcs_scanned"] * (4 + db) + t["arcs_matched"] * 8 * W + t["nodes_visited"] * (16 + 16 * W)
+            + n * k * db)
+
+
+def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
+    """The CPU oracle on a bounded sample of the same workload: ks sources'
+    searches (all host threads, over sources) and the literal Eq. (6) walk for
+    ns nodes (all host threads, over nodes), extrapolated to k sources and all
+    n nodes, as GTEPS."""
+    import concurrent.futures as cf
+    import ctypes
+
+    import oracle
+
+    threads = min(os.cpu_count() or 1, 16)
+    samples = oracle.draw_samples(g.n, k, seed)
+    ks = min(k, max(threads, 8))
+    t0 = time.perf_counter()
+    D = oracle.sample_distances(g, samples[:ks], threads=threads, reverse_graph=rg)
+    t_src = (time.perf_counter() - t0) / ks * threads  # single-source cost on one thread
+    # per-node literal walk: needs a row and the pivot's column; take rows
+    # from the partial D (pivot among the first ks samples) -- same O(n) work
+    lib = oracle._load()
+    sidx = oracle.sample_index(g.n, samples[:ks])
+    rng = np.random.default_rng(seed)
+    nodes = rng.integers(0, g.n, size=4 * threads)
+    Dc = np.ascontiguousarray(D)
+
+    # column access through the node-major matrix with stride ks (pivot column p)
+    def one_col(v):
+        row = np.ascontiguousarray(Dc[v])
+        p = int(lib.orc_pivot(ks, oracle._p(row)))
+        o = oracle.NodeOut()
+        col = Dc[:, p:]
+        lib.orc_node_estimates(g.n, ks, int(v), oracle._p(sidx), oracle._p(row),
+                               ctypes.c_void_p(col.ctypes.data), ks, 1, 10, ctypes.byref(o))
+        return o.S_hyb
+
+    t1 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one_col, nodes))
+    t_node = (time.perf_counter() - t1) / len(nodes) * threads  # one node on one thread
+    t_total = (k * t_src + g.n * t_node) / threads
+    m = g.m if not g.directed else 2 * g.arcs
+    return {
+        "value": k * m / t_total / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+        "sample": (f"{ks} of {k} sources' searches on {threads} threads ({t_src * ks / threads:.2f} s) + "
+                   f"literal Eq.6 walk for {len(nodes)} nodes on {threads} threads; extrapolated to "
+                   f"k={k} sources and n={g.n} nodes: {t_total:.1f} s per estimate"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by sample "
+              "across GPUs by design but no multi-GPU run is part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen
+    import paper_1409_0035_amd as cc
+
+    spec = graphgen.WORKLOADS[args.workload]
+    t0 = time.time()
+    g = graphgen.workload(args.workload)
+    k, seed = spec["k"], spec["sample_seed"]
+    rg = graphgen.transpose(g) if g.directed else None
+    m = g.m
+    teps_edges = k * m * (2 if g.directed else 1)  # round trip: forward + reverse searches
+    log(f"workload {args.workload}: n={g.n} m={m} arcs={g.arcs} k={k} (generated in {time.time() - t0:.1f}s)")
+
+    dev = torch.device("cuda:0")
+    ctx = cc.Context(0)
+    gh = ctx.upload(g)
+    out = {
+        "S_hyb": torch.empty(g.n, dtype=torch.float64, device=dev),
+        "S_samp": torch.empty(g.n, dtype=torch.float64, device=dev),
+        "S_piv": torch.empty(g.n, dtype=torch.int64, device=dev),
+        "S_pub": torch.empty(g.n, dtype=torch.int64, device=dev),
+        "pivot": torch.empty(g.n, dtype=torch.int32, device=dev),
+        "delta": torch.empty(g.n, dtype=torch.int32, device=dev),
+        "sampsum": torch.empty(g.n, dtype=torch.int64, device=dev),
+    }
+    stream = torch.cuda.current_stream()
+
+    def step(mode):
+        cc.cc_estimate_device(ctx.handle, gh, k, out, mode=mode, seed=seed, stream=stream)
+
+    for i in range(args.warmup):
+        step(cc.CC_BATCHED)
+    log(f"warmup done ({args.warmup} steps)")
+    torch.cuda.synchronize()
+    lat, kern_ms, timings = [], [], []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        step(cc.CC_BATCHED)
+        lat.append((time.perf_counter() - a) * 1e3)
+        tm = cc.cc_last_timing(ctx.handle)
+        timings.append(tm)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / args.steps
+    gteps = teps_edges / (ms_per_step / 1e3) / 1e9
+    log(f"batched: {ms_per_step:.3f} ms/step, {gteps:.1f} GTEPS")
+
+    # roofline of the dominant kernel (batched traversal), live HIP-event timing
+    tm = timings[-1]
+    W = (min(k, 256) + 63) // 64
+    kernel_ms = float(np.median([t["kernel_ms"] for t in timings]))
+    launches = tm["kernel_launches"]
+    abytes = algorithmic_bytes(tm, g.n, k, W)
+    achieved = abytes / (kernel_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_pull_level", "launches_per_step": launches,
+                "avg_launch_ms": round(kernel_ms / max(launches, 1), 5),
+                "algorithmic_bytes_per_step": int(abytes)}
+
+    plain = None
+    if not args.no_plain and args.plain_steps > 0:
+        step(cc.CC_PLAIN)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(cc.CC_PLAIN)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - a) * 1e3 / args.plain_steps
+        plain = {"ms_per_step": round(pms, 3), "gteps": round(teps_edges / (pms / 1e3) / 1e9, 3)}
+        log(f"plain: {pms:.3f} ms/step, {plain['gteps']} GTEPS")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(g, k, seed, rg)
+        log(f"cpu baseline: {cpu['value']:.4f} GTEPS")
+
+    line = {
+        "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8" if tm["dist_bytes"] == 1 else f"u{8 * tm['dist_bytes']}",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {g.name} n={g.n} m={m} k={k} batched", "n": g.n, "m": m,
+                   "k": k, "eps": f"1/{int(round(math.sqrt(k)))}"},
+        "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
+        "plain": plain,
+        "speedup_vs_plain": None if plain is None else round(gteps / plain["gteps"], 2),
+        "breakdown_ms": {"traverse": round(tm["traverse_ms"], 4), "epilogue": round(tm["epilogue_ms"], 4),
+                         "traversal_kernels": round(kernel_ms, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

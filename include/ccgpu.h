@@ -1,0 +1,186 @@
+/*
+ * ccgpu -- sample-based classic closeness centrality on one AMD Instinct
+ * MI355X (gfx950).  C ABI.
+ *
+ * Method: Cohen, Delling, Pajor & Werneck, "Computing Classic Closeness
+ * Centrality, at Scale" (2014).  For a graph G = (V, E) with n nodes the
+ * classic closeness of v is (n-1) / S(v) with S(v) = sum_u d(v,u) (Eq. (1)).
+ * The library draws k sample nodes C = (c_0 .. c_{k-1}), computes the
+ * distances d(c_i, v) from every sample to every node (k single-source
+ * shortest-path computations, Sec. 3), and returns, for every node v:
+ *
+ *   pivot[v]   index p of the nearest sample c(v) (Sec. 2), ties -> lowest p
+ *   delta[v]   Delta(v) = d(v, c(v))
+ *   sampsum[v] sum_i d(v, c_i)
+ *   S_samp[v]  sample-average estimate, Eq. (5), as a sum: (n-1)/k * sampsum
+ *   S_piv[v]   pivot estimate S(c(v)) (Sec. 1)
+ *   S_pub[v]   pivoting upper bound S(c(v)) + (n-1) * Delta(v) (Sec. 1)
+ *   S_hyb[v]   hybrid estimate, Eq. (6), threshold Delta(v)/eps
+ *
+ * and for v in C the exact S(v) in all four estimate fields (Sec. 2).  The
+ * closeness estimate is (n-1) / S_*[v].
+ *
+ * Graphs are undirected (every edge stored as two arcs), or strongly
+ * connected digraphs, for which distances are round-trip distances
+ * d(u,v) + d(v,u) (Sec. 6.1).  Arc lengths are int32 >= 1; NULL lengths mean
+ * unit lengths (breadth-first search).  Distances are int32, sums int64, and
+ * S_hyb / S_samp are one correctly rounded IEEE double division of exact
+ * integers (CC_EOVERFLOW when a numerator reaches 2^53).
+ *
+ * Conventions for every call:
+ *   - Return value: CC_OK (0) or an error code; no exceptions, aborts or
+ *     longjmp cross this boundary.  On error, caller-owned outputs are left
+ *     untouched (device outputs may be partially written for CC_EDEVICE).
+ *     cc_last_error() gives a text for the calling thread's last error.
+ *   - Ownership: the caller owns every buffer it passes (host or device) and
+ *     every handle it receives until the matching release/destroy call.  The
+ *     library never returns memory the caller must free with anything but the
+ *     functions below.
+ *   - Threads: one context may be used from several host threads; calls on
+ *     the same context are serialised internally.
+ */
+#ifndef CCGPU_H
+#define CCGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CC_OK = 0,
+    CC_EINVAL = 1,        /* bad argument: k < 1 or k > n, eps outside (0,1], bad CSR,
+                             arc length < 1, duplicate or out-of-range sample */
+    CC_EDISCONNECTED = 2, /* some node is unreachable from some sample: the graph is not
+                             connected (strongly connected for digraphs), where the
+                             classic centrality is not defined (Sec. 1) */
+    CC_ENOMEM = 3,        /* device or host allocation failed */
+    CC_EOVERFLOW = 4,     /* a distance left int32, or an estimate numerator reached 2^53 */
+    CC_EDEVICE = 5,       /* HIP runtime error, or a kernel's bounded wait expired */
+    CC_EBUSY = 6,         /* serving: not admitted yet (memory or slot limit); retry */
+    CC_ECANCELLED = 7,    /* serving: job cancelled before it ran */
+    CC_ENOTREADY = 8      /* serving: job still running (cc_poll) */
+} cc_status;
+
+/* Graph flags */
+#define CC_DIRECTED 1u  /* arcs are directed; estimates use round-trip distances */
+#define CC_VALIDATE 2u  /* check CSR shape, ids, lengths and (undirected) symmetry on upload */
+
+/* Traversal mode */
+#define CC_BATCHED 0    /* 64 samples per 64-bit word, all words of a node together */
+#define CC_PLAIN 1      /* one sample at a time (the one-source baseline) */
+
+typedef struct cc_context cc_context;
+typedef struct cc_graph cc_graph;
+typedef struct cc_job cc_job;
+
+typedef struct {
+    int64_t mem_budget_bytes; /* serving admission budget; 0 = 80% of free device memory */
+    int32_t max_inflight;     /* serving: jobs on the device at once; 0 = 8 */
+    int32_t reserved;
+} cc_config;
+
+/* Create a context on HIP device `device`.  cfg may be NULL (defaults).
+ * Creates a library-owned HIP stream used when callers pass stream NULL. */
+cc_status cc_context_create(int device, const cc_config* cfg, cc_context** out);
+void cc_context_destroy(cc_context* ctx);
+
+/* Upload a CSR graph: row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing),
+ * col_idx int32[arcs] (targets in [0,n)), w int32[arcs] or NULL (unit
+ * lengths).  All three are HOST pointers; they are copied into library-owned
+ * device memory (and, for CC_DIRECTED, the transposed graph is built once).
+ * arcs must be < 2^32.  Self-loops are allowed and ignored by the distances.
+ * The graph is released with cc_graph_release (it stays alive while jobs
+ * that use it are running). */
+cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, const int64_t* row_ptr,
+                          const int32_t* col_idx, const int32_t* w, uint32_t flags, cc_graph** out);
+void cc_graph_release(cc_graph* g);
+cc_status cc_graph_info(const cc_graph* g, int64_t* n, int64_t* arcs, uint32_t* flags);
+
+/* The sample draw of Sec. 2 (k nodes uniformly at random, as a set), fixed
+ * so that independent implementations agree: SplitMix64 seeded with `seed`,
+ * bounded integers by Lemire's multiply-shift with rejection (64-bit draws),
+ * partial Fisher-Yates over 0..n-1; out[i] = c_i in draw order.  Host only;
+ * needs no device. */
+cc_status cc_draw_samples(int64_t n, int32_t k, uint64_t seed, int32_t* out);
+
+typedef struct {
+    int32_t k;                /* number of samples, 1 <= k <= n (k <= 4096) */
+    int32_t mode;             /* CC_BATCHED or CC_PLAIN */
+    uint64_t seed;            /* used when samples == NULL */
+    const int32_t* samples;   /* HOST int32[k] explicit samples (distinct), or NULL */
+    int32_t eps_num, eps_den; /* eps = eps_num / eps_den in (0, 1]; 0/0 = 1/round(sqrt(k)) */
+} cc_params;
+
+/* Outputs; every field may be NULL (= not wanted).  Per-node arrays have n
+ * entries, per-sample arrays k entries, dmat k*k (dmat[i*k+j] = d(c_i,c_j)),
+ * D n*k node-major (D[v*k+i] = d(c_i, v)). */
+typedef struct {
+    double* S_hyb;
+    double* S_samp;
+    int64_t* S_piv;
+    int64_t* S_pub;
+    int32_t* pivot;
+    int32_t* delta;
+    int64_t* sampsum;
+    int64_t* src_sum;  /* S(c_i), exact */
+    int32_t* samples;  /* the samples used */
+    int32_t* dmat;
+    int32_t* D;
+} cc_result;
+
+/* Synchronous estimate; `out` holds HOST pointers. */
+cc_status cc_estimate(cc_context* ctx, const cc_graph* g, const cc_params* p, cc_result* out);
+
+/* Estimate into DEVICE pointers, enqueued on `hip_stream` (a hipStream_t;
+ * NULL = the context's stream).  Returns after the work is enqueued and its
+ * status is known (the call synchronises the stream once at the end to read
+ * the device-side error flags). */
+cc_status cc_estimate_device(cc_context* ctx, const cc_graph* g, const cc_params* p, cc_result* out,
+                             void* hip_stream);
+
+/* Timing of the last cc_estimate / cc_estimate_device on this context, from
+ * HIP events recorded on the stream the kernels ran on (milliseconds), plus
+ * the work counters the bench turns into bytes. */
+typedef struct {
+    double total_ms;       /* samples on device -> all outputs in device memory */
+    double traverse_ms;    /* all traversal kernels (both directions for digraphs) */
+    double epilogue_ms;    /* reductions, suffix tables, estimates */
+    int64_t levels;        /* BFS levels / delta-stepping phases executed */
+    int64_t arcs_scanned;  /* adjacency entries read by the traversal kernels */
+    int64_t nodes_visited; /* node-level work items processed by the traversal */
+    int64_t launches;      /* all traversal launches (including bookkeeping kernels) */
+    int32_t dist_bytes;    /* bytes per stored distance (1, 2 or 4) */
+    int32_t reserved;
+    double kernel_ms;      /* summed duration of the main traversal kernel's launches */
+    int64_t kernel_launches; /* number of those launches */
+    int64_t arcs_matched;  /* scanned arcs whose far end was on the previous level */
+} cc_timing;
+cc_status cc_last_timing(const cc_context* ctx, cc_timing* t);
+
+/* ---- serving: continuous batching over resident graphs ---------------- */
+
+/* Submit a job; `out` holds HOST pointers that must stay valid until the job
+ * completes.  Returns CC_OK with a job handle (queued), or CC_EINVAL.  Jobs
+ * are admitted onto the device as memory (cc_config.mem_budget_bytes) and
+ * slots (max_inflight) free up, and run concurrently on several streams. */
+cc_status cc_submit(cc_context* ctx, const cc_graph* g, const cc_params* p, const cc_result* out,
+                    cc_job** job);
+/* CC_OK when done successfully, CC_ENOTREADY while queued or running,
+ * otherwise the job's error code. */
+cc_status cc_poll(cc_job* job);
+cc_status cc_wait(cc_job* job);
+/* Cancels a job that has not started (CC_OK), else CC_EBUSY. */
+cc_status cc_cancel(cc_job* job);
+/* Latency bookkeeping of a finished job: submit->admit and submit->done, ms. */
+cc_status cc_job_times(const cc_job* job, double* queue_ms, double* total_ms);
+void cc_job_release(cc_job* job);
+
+const char* cc_status_str(cc_status s);
+const char* cc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,322 @@
+"""Sample-based classic closeness centrality on AMD Instinct MI355X (gfx950).
+
+Python binding of the C-ABI library ``libccgpu.so`` (declared in
+``include/ccgpu.h``).  The functions below carry the C names and only marshal
+arguments: every step of the estimate runs in the library's HIP kernels.
+PyTorch is used only to hold device buffers and to name HIP streams.
+
+Importing this package does not need a GPU; the library is loaded on first
+use and its absence is an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccgpu.so")
+
+CC_OK, CC_EINVAL, CC_EDISCONNECTED, CC_ENOMEM, CC_EOVERFLOW = 0, 1, 2, 3, 4
+CC_EDEVICE, CC_EBUSY, CC_ECANCELLED, CC_ENOTREADY = 5, 6, 7, 8
+CC_DIRECTED, CC_VALIDATE = 1, 2
+CC_BATCHED, CC_PLAIN = 0, 1
+
+EXPORTED = [
+    "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_release", "cc_graph_info",
+    "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
+    "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
+]
+
+
+class cc_config(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class cc_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("mode", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("samples", ctypes.c_void_p), ("eps_num", ctypes.c_int32), ("eps_den", ctypes.c_int32)]
+
+
+_RESULT_FIELDS = ["S_hyb", "S_samp", "S_piv", "S_pub", "pivot", "delta", "sampsum", "src_sum", "samples",
+                  "dmat", "D"]
+
+
+class cc_result(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in _RESULT_FIELDS]
+
+
+class cc_timing(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("traverse_ms", ctypes.c_double),
+                ("epilogue_ms", ctypes.c_double), ("levels", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
+                ("nodes_visited", ctypes.c_int64), ("launches", ctypes.c_int64), ("dist_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
+                ("arcs_matched", ctypes.c_int64)]
+
+
+# per-field element type and whether the length is n, k or k*k / n*k
+_FIELD_SPEC = {
+    "S_hyb": (np.float64, "n"), "S_samp": (np.float64, "n"), "S_piv": (np.int64, "n"), "S_pub": (np.int64, "n"),
+    "pivot": (np.int32, "n"), "delta": (np.int32, "n"), "sampsum": (np.int64, "n"), "src_sum": (np.int64, "k"),
+    "samples": (np.int32, "k"), "dmat": (np.int32, "kk"), "D": (np.int32, "nk"),
+}
+
+_lib = None
+
+
+class CCError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{cc_status_str(status)} ({status}): {message}")
+        self.status = status
+        self.message = message
+
+
+def load_library():
+    """Load libccgpu.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1409_0035_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback implementation")
+    # PyTorch ships its own HIP runtime under the same soname as ROCm's; load
+    # it first so that the library and torch's device memory and streams share
+    # one runtime in this process.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "cc_context_create": (i32, [ctypes.c_int, ctypes.POINTER(cc_config), PP]),
+        "cc_context_destroy": (None, [P]),
+        "cc_graph_upload": (i32, [P, i64, i64, P, P, P, u32, PP]),
+        "cc_graph_release": (None, [P]),
+        "cc_graph_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(u32)]),
+        "cc_draw_samples": (i32, [i64, i32, u64, P]),
+        "cc_estimate": (i32, [P, P, ctypes.POINTER(cc_params), ctypes.POINTER(cc_result)]),
+        "cc_estimate_device": (i32, [P, P, ctypes.POINTER(cc_params), ctypes.POINTER(cc_result), P]),
+        "cc_last_timing": (i32, [P, ctypes.POINTER(cc_timing)]),
+        "cc_submit": (i32, [P, P, ctypes.POINTER(cc_params), ctypes.POINTER(cc_result), PP]),
+        "cc_poll": (i32, [P]),
+        "cc_wait": (i32, [P]),
+        "cc_cancel": (i32, [P]),
+        "cc_job_times": (i32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "cc_job_release": (None, [P]),
+        "cc_status_str": (ctypes.c_char_p, [i32]),
+        "cc_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != CC_OK:
+        raise CCError(status, cc_last_error())
+
+
+def cc_status_str(status: int) -> str:
+    return load_library().cc_status_str(int(status)).decode()
+
+
+def cc_last_error() -> str:
+    return load_library().cc_last_error().decode()
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+# ---------------------------------------------------------------- context / graphs
+
+def cc_context_create(device: int = 0, mem_budget_bytes: int = 0, max_inflight: int = 0) -> ctypes.c_void_p:
+    lib = load_library()
+    cfg = cc_config(mem_budget_bytes, max_inflight, 0)
+    out = ctypes.c_void_p()
+    _check(lib.cc_context_create(int(device), ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def cc_context_destroy(ctx) -> None:
+    load_library().cc_context_destroy(ctx)
+
+
+def cc_graph_upload(ctx, n: int, arcs: int, row_ptr, col_idx, w=None, flags: int = 0) -> ctypes.c_void_p:
+    lib = load_library()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col_idx, dtype=np.int32)
+    wa = None if w is None else np.ascontiguousarray(w, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(lib.cc_graph_upload(ctx, int(n), int(arcs), _ptr(rp), _ptr(col), _ptr(wa), int(flags),
+                               ctypes.byref(out)))
+    return out
+
+
+def cc_graph_release(g) -> None:
+    load_library().cc_graph_release(g)
+
+
+def cc_graph_info(g):
+    n, arcs, fl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint32()
+    _check(load_library().cc_graph_info(g, ctypes.byref(n), ctypes.byref(arcs), ctypes.byref(fl)))
+    return n.value, arcs.value, fl.value
+
+
+def cc_draw_samples(n: int, k: int, seed: int) -> np.ndarray:
+    out = np.empty(k, dtype=np.int32)
+    _check(load_library().cc_draw_samples(int(n), int(k), int(seed), _ptr(out)))
+    return out
+
+
+def _params(k, mode, seed, samples, eps):
+    s = None if samples is None else np.ascontiguousarray(samples, dtype=np.int32)
+    en, ed = (0, 0) if eps is None else eps
+    p = cc_params(int(k), int(mode), int(seed), None if s is None else s.ctypes.data, int(en), int(ed))
+    return p, s
+
+
+def _sizes(n, k):
+    return {"n": n, "k": k, "kk": k * k, "nk": n * k}
+
+
+def cc_estimate(ctx, g, k: int, mode: int = CC_BATCHED, seed: int = 0, samples=None, eps=None,
+                outputs=("S_hyb", "S_samp", "S_piv", "S_pub", "pivot", "delta", "sampsum", "src_sum",
+                         "samples", "dmat")) -> dict:
+    """Synchronous estimate into host numpy arrays (one per requested field)."""
+    n, _, _ = cc_graph_info(g)
+    p, keep = _params(k, mode, seed, samples, eps)
+    sz = _sizes(n, k)
+    res = cc_result()
+    arrays = {}
+    for f in outputs:
+        dt, which = _FIELD_SPEC[f]
+        arrays[f] = np.empty(sz[which], dtype=dt)
+        setattr(res, f, arrays[f].ctypes.data)
+    _check(load_library().cc_estimate(ctx, g, ctypes.byref(p), ctypes.byref(res)))
+    if "dmat" in arrays:
+        arrays["dmat"] = arrays["dmat"].reshape(k, k)
+    if "D" in arrays:
+        arrays["D"] = arrays["D"].reshape(n, k)
+    del keep
+    return arrays
+
+
+def cc_estimate_device(ctx, g, k: int, out: dict, mode: int = CC_BATCHED, seed: int = 0, samples=None,
+                       eps=None, stream=None) -> None:
+    """Estimate into device tensors.  `out` maps result field names to torch
+    tensors on the context's device (contiguous, of the field's dtype and
+    length); `stream` is a torch.cuda.Stream (default: torch's current)."""
+    import torch
+    p, keep = _params(k, mode, seed, samples, eps)
+    res = cc_result()
+    for f, t in out.items():
+        dt, _ = _FIELD_SPEC[f]
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{f}: need a contiguous device tensor")
+        if t.element_size() != np.dtype(dt).itemsize:
+            raise ValueError(f"{f}: wrong element type")
+        setattr(res, f, t.data_ptr())
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(load_library().cc_estimate_device(ctx, g, ctypes.byref(p), ctypes.byref(res),
+                                             ctypes.c_void_p(stream.cuda_stream)))
+    del keep
+
+
+def cc_last_timing(ctx) -> dict:
+    t = cc_timing()
+    _check(load_library().cc_last_timing(ctx, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in cc_timing._fields_ if f != "reserved"}
+
+
+# ---------------------------------------------------------------- serving
+
+@dataclass
+class Job:
+    handle: ctypes.c_void_p
+    arrays: dict
+    keep: object
+
+
+def cc_submit(ctx, g, k: int, mode: int = CC_BATCHED, seed: int = 0, samples=None, eps=None,
+              outputs=("S_hyb", "pivot", "delta")) -> Job:
+    n, _, _ = cc_graph_info(g)
+    p, keep = _params(k, mode, seed, samples, eps)
+    sz = _sizes(n, k)
+    res = cc_result()
+    arrays = {}
+    for f in outputs:
+        dt, which = _FIELD_SPEC[f]
+        arrays[f] = np.empty(sz[which], dtype=dt)
+        setattr(res, f, arrays[f].ctypes.data)
+    h = ctypes.c_void_p()
+    _check(load_library().cc_submit(ctx, g, ctypes.byref(p), ctypes.byref(res), ctypes.byref(h)))
+    return Job(h, arrays, keep)
+
+
+def cc_poll(job: Job) -> int:
+    return int(load_library().cc_poll(job.handle))
+
+
+def cc_wait(job: Job) -> dict:
+    _check(load_library().cc_wait(job.handle))
+    return job.arrays
+
+
+def cc_cancel(job: Job) -> int:
+    return int(load_library().cc_cancel(job.handle))
+
+
+def cc_job_times(job: Job):
+    q, t = ctypes.c_double(), ctypes.c_double()
+    st = load_library().cc_job_times(job.handle, ctypes.byref(q), ctypes.byref(t))
+    if st == CC_ENOTREADY:
+        return None
+    _check(st)
+    return q.value, t.value
+
+
+def cc_job_release(job: Job) -> None:
+    load_library().cc_job_release(job.handle)
+    job.handle = None
+
+
+# ---------------------------------------------------------------- convenience
+
+class Context:
+    """Owns a context handle; uploads graph objects with .n/.row_ptr/.col_idx/.w/.directed."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0, max_inflight: int = 0):
+        self.handle = cc_context_create(device, mem_budget_bytes, max_inflight)
+        self._graphs = []
+
+    def upload(self, graph, validate: bool = False):
+        flags = (CC_DIRECTED if graph.directed else 0) | (CC_VALIDATE if validate else 0)
+        h = cc_graph_upload(self.handle, graph.n, graph.arcs, graph.row_ptr, graph.col_idx, graph.w, flags)
+        self._graphs.append(h)
+        return h
+
+    def release(self, gh):
+        cc_graph_release(gh)
+        self._graphs = [x for x in self._graphs if x is not gh]
+
+    def close(self):
+        for h in self._graphs:
+            cc_graph_release(h)
+        self._graphs = []
+        if self.handle is not None:
+            cc_context_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,946 @@
+// Host runtime and C ABI of the closeness-centrality library (see
+// include/ccgpu.h).  Orchestrates: sample draw -> k-source traversal (batched
+// bit-parallel BFS, plain BFS, or delta-stepping for integer lengths) ->
+// estimator epilogue, on one HIP stream, plus a continuous-batching job
+// service over resident graphs.
+#include "ccgpu.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ccg;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+static cc_status fail(cc_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+extern "C" const char* cc_status_str(cc_status s) {
+    switch (s) {
+        case CC_OK: return "ok";
+        case CC_EINVAL: return "invalid argument";
+        case CC_EDISCONNECTED: return "graph not (strongly) connected";
+        case CC_ENOMEM: return "out of memory";
+        case CC_EOVERFLOW: return "overflow";
+        case CC_EDEVICE: return "device error";
+        case CC_EBUSY: return "busy";
+        case CC_ECANCELLED: return "cancelled";
+        case CC_ENOTREADY: return "not ready";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* cc_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------- sampler
+
+namespace {
+
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    // Lemire: uniform in [0, range)
+    uint64_t below(uint64_t range) {
+        unsigned __int128 m = (unsigned __int128)next() * range;
+        uint64_t lo = (uint64_t)m;
+        if (lo < range) {
+            const uint64_t t = (0 - range) % range;
+            while (lo < t) {
+                m = (unsigned __int128)next() * range;
+                lo = (uint64_t)m;
+            }
+        }
+        return (uint64_t)(m >> 64);
+    }
+};
+
+}  // namespace
+
+extern "C" cc_status cc_draw_samples(int64_t n, int32_t k, uint64_t seed, int32_t* out) {
+    if (!out || k < 1 || n < k || n > INT32_MAX) return fail(CC_EINVAL, "cc_draw_samples: need 1 <= k <= n < 2^31");
+    SplitMix64 r{seed};
+    std::unordered_map<int64_t, int64_t> moved;
+    moved.reserve((size_t)k * 2);
+    for (int32_t i = 0; i < k; i++) {
+        const int64_t j = i + (int64_t)r.below((uint64_t)(n - i));
+        auto it_i = moved.find(i);
+        auto it_j = moved.find(j);
+        const int64_t ai = it_i == moved.end() ? i : it_i->second;
+        const int64_t aj = it_j == moved.end() ? j : it_j->second;
+        moved[i] = aj;
+        moved[j] = ai;
+        out[i] = (int32_t)aj;
+    }
+    return CC_OK;
+}
+
+// ---------------------------------------------------------------- device arena
+
+namespace {
+
+// A growable device buffer; one per stream that runs jobs.
+struct Arena {
+    void* ptr = nullptr;
+    size_t size = 0;
+    ~Arena() {
+        if (ptr) (void)hipFree(ptr);
+    }
+    void* get(size_t need) {
+        if (need <= size) return ptr;
+        if (ptr) {
+            CCG_HIP(hipFree(ptr));
+            ptr = nullptr;
+            size = 0;
+        }
+        need = (need + (1u << 20)) & ~size_t((1u << 20) - 1);
+        hipError_t e = hipMalloc(&ptr, need);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            (void)hipGetLastError();
+            throw std::bad_alloc();
+        }
+        size = need;
+        return ptr;
+    }
+};
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(size_t count) {
+        T* p = (T*)(base + off);
+        off += (sizeof(T) * count + 255) & ~size_t(255);
+        return p;
+    }
+    static size_t sz(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+};
+
+// Everything one job needs on one stream.
+struct Lane {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Arena arena;      // distances, traversal state, per-job small buffers
+    Arena arena2;     // epilogue tables (sized once the largest distance is known)
+    LevelCounters* cnt_host = nullptr;  // pinned
+    hipEvent_t ev[4] = {};
+    void init(hipStream_t s) {
+        if (s) {
+            stream = s;
+        } else {
+            CCG_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        CCG_HIP(hipHostMalloc((void**)&cnt_host, sizeof(LevelCounters), hipHostMallocDefault));
+        for (auto& e : ev) CCG_HIP(hipEventCreate(&e));
+    }
+    void destroy() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cnt_host) (void)hipHostFree(cnt_host);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        cnt_host = nullptr;
+        stream = nullptr;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- objects
+
+struct cc_graph {
+    cc_context* ctx = nullptr;
+    DevGraph dg;
+    uint32_t flags = 0;
+    std::atomic<int> refs{1};
+    void* mem[6] = {};
+    size_t bytes = 0;
+};
+
+struct cc_job {
+    cc_context* ctx = nullptr;
+    cc_graph* g = nullptr;
+    cc_params p{};
+    std::vector<int32_t> samples;
+    cc_result out{};
+    std::atomic<int> state{0};  // 0 queued, 1 running, 2 done, 3 cancelled
+    cc_status status = CC_ENOTREADY;
+    std::string err;
+    size_t need = 0;
+    std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+    std::mutex m;
+    std::condition_variable cv;
+    std::atomic<int> refs{2};  // caller + service
+};
+
+struct cc_context {
+    int device = 0;
+    cc_config cfg{};
+    std::mutex mu;  // serialises synchronous calls on the default lane
+    Lane lane;
+    cc_timing last{};
+    // serving
+    std::mutex qmu;
+    std::condition_variable qcv;
+    std::deque<cc_job*> queue;
+    std::vector<std::thread> workers;
+    std::vector<std::unique_ptr<Lane>> worker_lanes;
+    int64_t budget = 0;
+    int64_t in_use = 0;
+    int inflight = 0;
+    bool stopping = false;
+    bool service_started = false;
+};
+
+static void graph_unref(cc_graph* g) {
+    if (!g) return;
+    if (g->refs.fetch_sub(1) == 1) {
+        (void)hipSetDevice(g->ctx->device);
+        for (void* p : g->mem)
+            if (p) (void)hipFree(p);
+        delete g;
+    }
+}
+
+// ---------------------------------------------------------------- context
+
+extern "C" cc_status cc_context_create(int device, const cc_config* cfg, cc_context** out) {
+    if (!out) return fail(CC_EINVAL, "cc_context_create: out is NULL");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return fail(CC_EDEVICE, "cc_context_create: no such HIP device");
+    }
+    cc_context* ctx = new (std::nothrow) cc_context();
+    if (!ctx) return fail(CC_ENOMEM, "cc_context_create: host allocation");
+    ctx->device = device;
+    if (cfg) ctx->cfg = *cfg;
+    try {
+        CCG_HIP(hipSetDevice(device));
+        ctx->lane.init(nullptr);
+        size_t fr = 0, tot = 0;
+        CCG_HIP(hipMemGetInfo(&fr, &tot));
+        ctx->budget = ctx->cfg.mem_budget_bytes > 0 ? ctx->cfg.mem_budget_bytes : (int64_t)(0.8 * (double)fr);
+    } catch (const HipError& e) {
+        delete ctx;
+        return fail(CC_EDEVICE, "cc_context_create: " + e.where + ": " + hipGetErrorString(e.err));
+    }
+    *out = ctx;
+    return CC_OK;
+}
+
+extern "C" void cc_context_destroy(cc_context* ctx) {
+    if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        ctx->stopping = true;
+        for (cc_job* j : ctx->queue) {
+            j->state = 3;
+            j->status = CC_ECANCELLED;
+            graph_unref(j->g);
+            j->g = nullptr;
+            {
+                std::lock_guard<std::mutex> jl(j->m);
+            }
+            j->cv.notify_all();
+            if (j->refs.fetch_sub(1) == 1) delete j;
+        }
+        ctx->queue.clear();
+    }
+    ctx->qcv.notify_all();
+    for (auto& t : ctx->workers) t.join();
+    (void)hipSetDevice(ctx->device);
+    for (auto& l : ctx->worker_lanes) {
+        (void)hipStreamSynchronize(l->stream);
+        l->destroy();
+    }
+    ctx->worker_lanes.clear();
+    (void)hipStreamSynchronize(ctx->lane.stream);
+    ctx->lane.destroy();
+    delete ctx;
+}
+
+// ---------------------------------------------------------------- graphs
+
+static bool check_csr(int64_t n, int64_t arcs, const int64_t* rp, const int32_t* col, const int32_t* w,
+                      bool directed, std::string& why) {
+    if (rp[0] != 0 || rp[n] != arcs) {
+        why = "row_ptr[0] must be 0 and row_ptr[n] must equal arcs";
+        return false;
+    }
+    for (int64_t v = 0; v < n; v++)
+        if (rp[v + 1] < rp[v]) {
+            why = "row_ptr must be non-decreasing";
+            return false;
+        }
+    for (int64_t e = 0; e < arcs; e++) {
+        if (col[e] < 0 || col[e] >= n) {
+            why = "col_idx out of range";
+            return false;
+        }
+        if (w && w[e] < 1) {
+            why = "arc lengths must be >= 1";
+            return false;
+        }
+    }
+    if (!directed) {
+        // symmetric: count (u,v) pairs both ways with a transpose and compare
+        std::vector<int64_t> trp(n + 1, 0);
+        for (int64_t e = 0; e < arcs; e++) trp[col[e] + 1]++;
+        for (int64_t v = 0; v < n; v++) trp[v + 1] += trp[v];
+        for (int64_t v = 0; v < n; v++)
+            if (trp[v + 1] - trp[v] != rp[v + 1] - rp[v]) {
+                why = "undirected CSR is not symmetric (in-degree != out-degree)";
+                return false;
+            }
+        std::vector<int64_t> pos(trp.begin(), trp.end() - 1);
+        std::vector<std::pair<int32_t, int32_t>> t((size_t)arcs);
+        for (int64_t u = 0; u < n; u++)
+            for (int64_t e = rp[u]; e < rp[u + 1]; e++) t[(size_t)pos[col[e]]++] = {(int32_t)u, w ? w[e] : 1};
+        for (int64_t v = 0; v < n; v++) {
+            std::vector<std::pair<int32_t, int32_t>> a, b;
+            for (int64_t e = rp[v]; e < rp[v + 1]; e++) a.push_back({col[e], w ? w[e] : 1});
+            for (int64_t e = trp[v]; e < trp[v + 1]; e++) b.push_back(t[(size_t)e]);
+            std::sort(a.begin(), a.end());
+            std::sort(b.begin(), b.end());
+            if (a != b) {
+                why = "undirected CSR is not symmetric";
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, const int64_t* row_ptr,
+                                     const int32_t* col_idx, const int32_t* w, uint32_t flags, cc_graph** out) {
+    if (!ctx || !out || !row_ptr || (arcs > 0 && !col_idx)) return fail(CC_EINVAL, "cc_graph_upload: null argument");
+    if (n < 1 || n >= INT32_MAX || arcs < 0 || arcs >= (int64_t)UINT32_MAX)
+        return fail(CC_EINVAL, "cc_graph_upload: need 1 <= n < 2^31 and arcs < 2^32");
+    const bool directed = (flags & CC_DIRECTED) != 0;
+    if (row_ptr[0] != 0 || row_ptr[n] != arcs) return fail(CC_EINVAL, "cc_graph_upload: row_ptr[0]/row_ptr[n] mismatch");
+    {
+        // shape, id range and lengths are always checked (kernels index with
+        // them); symmetry of undirected graphs only with CC_VALIDATE
+        std::string why;
+        if (!check_csr(n, arcs, row_ptr, col_idx, w, directed || !(flags & CC_VALIDATE), why))
+            return fail(CC_EINVAL, "cc_graph_upload: " + why);
+    }
+    cc_graph* g = new (std::nothrow) cc_graph();
+    if (!g) return fail(CC_ENOMEM, "cc_graph_upload: host allocation");
+    g->ctx = ctx;
+    g->flags = flags;
+    g->dg.n = n;
+    g->dg.arcs = arcs;
+    g->dg.directed = directed;
+    g->dg.weighted = w != nullptr;
+    try {
+        CCG_HIP(hipSetDevice(ctx->device));
+        std::vector<uint32_t> rp32((size_t)n + 1);
+        for (int64_t v = 0; v <= n; v++) rp32[(size_t)v] = (uint32_t)row_ptr[v];
+        auto up = [&](int slot, const void* src, size_t bytes) -> void* {
+            void* d = nullptr;
+            hipError_t e = hipMalloc(&d, bytes ? bytes : 4);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw std::bad_alloc();
+            }
+            g->mem[slot] = d;
+            g->bytes += bytes;
+            if (bytes) CCG_HIP(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+            return d;
+        };
+        g->dg.rp = (const uint32_t*)up(0, rp32.data(), sizeof(uint32_t) * (n + 1));
+        g->dg.col = (const int32_t*)up(1, col_idx, sizeof(int32_t) * arcs);
+        if (w) g->dg.w = (const int32_t*)up(2, w, sizeof(int32_t) * arcs);
+        if (directed) {
+            // transpose on the host (counting sort by target), lists stay sorted by source
+            std::vector<uint32_t> trp((size_t)n + 1, 0);
+            for (int64_t e = 0; e < arcs; e++) trp[(size_t)col_idx[e] + 1]++;
+            for (int64_t v = 0; v < n; v++) trp[(size_t)v + 1] += trp[(size_t)v];
+            std::vector<uint32_t> pos(trp.begin(), trp.end() - 1);
+            std::vector<int32_t> tcol((size_t)arcs), tw(w ? (size_t)arcs : 0);
+            for (int64_t u = 0; u < n; u++)
+                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+                    const uint32_t q = pos[(size_t)col_idx[e]]++;
+                    tcol[q] = (int32_t)u;
+                    if (w) tw[q] = w[e];
+                }
+            g->dg.rrp = (const uint32_t*)up(3, trp.data(), sizeof(uint32_t) * (n + 1));
+            g->dg.rcol = (const int32_t*)up(4, tcol.data(), sizeof(int32_t) * arcs);
+            if (w) g->dg.rw = (const int32_t*)up(5, tw.data(), sizeof(int32_t) * arcs);
+        } else {
+            g->dg.rrp = g->dg.rp;
+            g->dg.rcol = g->dg.col;
+            g->dg.rw = g->dg.w;
+        }
+    } catch (const std::bad_alloc&) {
+        graph_unref(g);
+        return fail(CC_ENOMEM, "cc_graph_upload: device allocation failed");
+    } catch (const HipError& e) {
+        graph_unref(g);
+        return fail(CC_EDEVICE, "cc_graph_upload: " + e.where + ": " + hipGetErrorString(e.err));
+    }
+    *out = g;
+    return CC_OK;
+}
+
+extern "C" void cc_graph_release(cc_graph* g) { graph_unref(g); }
+
+extern "C" cc_status cc_graph_info(const cc_graph* g, int64_t* n, int64_t* arcs, uint32_t* flags) {
+    if (!g) return fail(CC_EINVAL, "cc_graph_info: null graph");
+    if (n) *n = g->dg.n;
+    if (arcs) *arcs = g->dg.arcs;
+    if (flags) *flags = g->flags;
+    return CC_OK;
+}
+
+// ---------------------------------------------------------------- estimate
+
+namespace {
+
+struct Resolved {
+    int32_t k = 0;
+    int32_t mode = CC_BATCHED;
+    int64_t en = 1, ed = 1;
+    std::vector<int32_t> samples;
+};
+
+cc_status resolve_params(const cc_graph* g, const cc_params* p, Resolved& r) {
+    if (!g || !p) return fail(CC_EINVAL, "null graph or params");
+    const int64_t n = g->dg.n;
+    if (p->k < 1 || p->k > n || p->k > 4096) return fail(CC_EINVAL, "need 1 <= k <= min(n, 4096)");
+    if (p->mode != CC_BATCHED && p->mode != CC_PLAIN) return fail(CC_EINVAL, "mode must be CC_BATCHED or CC_PLAIN");
+    r.k = p->k;
+    r.mode = p->mode;
+    if (p->eps_num == 0 && p->eps_den == 0) {
+        r.en = 1;
+        r.ed = std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)p->k)));
+    } else {
+        if (p->eps_num < 1 || p->eps_den < p->eps_num) return fail(CC_EINVAL, "eps = num/den must lie in (0, 1]");
+        r.en = p->eps_num;
+        r.ed = p->eps_den;
+    }
+    r.samples.resize((size_t)r.k);
+    if (p->samples) {
+        std::vector<char> seen((size_t)n, 0);
+        for (int32_t i = 0; i < r.k; i++) {
+            const int32_t v = p->samples[i];
+            if (v < 0 || v >= n) return fail(CC_EINVAL, "sample id out of range");
+            if (seen[(size_t)v]) return fail(CC_EINVAL, "duplicate sample");
+            seen[(size_t)v] = 1;
+            r.samples[(size_t)i] = v;
+        }
+    } else {
+        cc_status s = cc_draw_samples(n, r.k, p->seed, r.samples.data());
+        if (s != CC_OK) return s;
+    }
+    return CC_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms;
+}
+
+// Device bytes one job needs (excluding the caller's outputs).
+size_t job_bytes(const DevGraph& g, int32_t k, int32_t mode, int db) {
+    const int64_t n = g.n;
+    size_t b = Carver::sz(sizeof(int32_t) * k) + Carver::sz(sizeof(DevFlags)) + Carver::sz(sizeof(LevelCounters));
+    const size_t dbytes = Carver::sz((size_t)n * k * db);
+    b += dbytes * (g.directed ? 2 : 1);
+    size_t trav;
+    if (g.weighted) {
+        trav = mode == CC_PLAIN ? dbytes + sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
+    } else {
+        trav = mode == CC_PLAIN ? dbytes + bfs_plain_scratch(n) : bfs_batched_scratch(n, std::min(k, 256));
+    }
+    // epilogue with a generous distance bound is sized after the traversal;
+    // reserve the BFS-sized part here
+    b += trav;
+    b += Carver::sz(sizeof(int64_t) * k) + Carver::sz(sizeof(int32_t) * (size_t)k * k);
+    return b;
+}
+
+// Runs the whole pipeline on lane `L`; `out` holds DEVICE pointers.
+cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const cc_result* out, Lane& L,
+                  cc_timing* timing) {
+    const DevGraph& g = gr->dg;
+    const int64_t n = g.n;
+    const int32_t k = r.k;
+    hipStream_t st = L.stream;
+    TravStats stats;
+
+    std::vector<DistKind> kinds;
+    if (g.weighted) kinds = {DistKind::U32};
+    else kinds = {DistKind::U8, DistKind::U16, DistKind::U32};
+
+    for (DistKind dk : kinds) {
+        const int db = (int)dk;
+        stats = TravStats();
+        // ---- layout
+        const size_t dbytes = (size_t)n * k * db;
+        size_t trav_scratch;
+        if (g.weighted)
+            trav_scratch = r.mode == CC_PLAIN ? sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
+        else
+            trav_scratch = r.mode == CC_PLAIN ? bfs_plain_scratch(n) : bfs_batched_scratch(n, std::min(k, 256));
+        const size_t fixed = Carver::sz(sizeof(int32_t) * k) + Carver::sz(sizeof(DevFlags)) +
+                             Carver::sz(sizeof(LevelCounters)) + Carver::sz(dbytes) * (g.directed ? 2 : 1) +
+                             (r.mode == CC_PLAIN ? Carver::sz(dbytes) : 0) + Carver::sz(trav_scratch) +
+                             Carver::sz(sizeof(int64_t) * k) + Carver::sz(sizeof(int32_t) * (size_t)k * k);
+        void* base = L.arena.get(fixed);
+        Carver c(base);
+        int32_t* samples_dev = c.take<int32_t>(k);
+        DevFlags* flags = c.take<DevFlags>(1);
+        LevelCounters* cnt = c.take<LevelCounters>(1);
+        void* D = c.take<char>(dbytes);
+        void* Dr = g.directed ? c.take<char>(dbytes) : nullptr;
+        void* Dt = r.mode == CC_PLAIN ? c.take<char>(dbytes) : nullptr;
+        void* ts = c.take<char>(trav_scratch);
+        int64_t* src_sum = out->src_sum ? out->src_sum : c.take<int64_t>(k);
+        int32_t* dmat = out->dmat ? out->dmat : c.take<int32_t>((size_t)k * k);
+
+        CCG_HIP(hipMemcpyAsync(samples_dev, r.samples.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+        fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+        CCG_HIP(hipEventRecord(L.ev[0], st));
+
+        // ---- traversal
+        bool ok = true;
+        int64_t maxd_f = 0, maxd_r = 0;
+        for (int dir = 0; dir < (g.directed ? 2 : 1) && ok; dir++) {
+            // forward distances d(c_i -> v): push over out-arcs, pull over in-arcs;
+            // reverse distances d(v -> c_i): the same on the transposed graph
+            const uint32_t* out_rp = dir == 0 ? g.rp : g.rrp;
+            const int32_t* out_col = dir == 0 ? g.col : g.rcol;
+            const uint32_t* in_rp = dir == 0 ? g.rrp : g.rp;
+            const int32_t* in_col = dir == 0 ? g.rcol : g.col;
+            void* Dd = dir == 0 ? D : Dr;
+            TravStats ds;
+            if (g.weighted) {
+                throw HipError{hipErrorNotSupported, "weighted traversal not built yet"};
+            } else if (r.mode == CC_PLAIN) {
+                ok = bfs_plain(st, out_rp, out_col, in_rp, in_col, n, g.arcs, r.samples.data(), k, Dt, dk, ts,
+                               trav_scratch, flags, cnt, L.cnt_host, &ds);
+                if (ok) transpose_dist(st, Dt, Dd, n, k, dk);
+            } else {
+                for (int32_t s0 = 0; s0 < k && ok; s0 += 256) {
+                    const int32_t kg = std::min(256, k - s0);
+                    ok = bfs_batched(st, in_rp, in_col, n, samples_dev, kg, s0, k, Dd, dk, ts, trav_scratch, flags,
+                                     cnt, L.cnt_host, &ds);
+                }
+            }
+            (dir == 0 ? maxd_f : maxd_r) = ds.maxd;
+            stats.levels += ds.levels;
+            stats.arcs_scanned += ds.arcs_scanned;
+            stats.nodes_visited += ds.nodes_visited;
+            stats.launches += ds.launches;
+            stats.arcs_matched += ds.arcs_matched;
+            stats.kernel_ms += ds.kernel_ms;
+            stats.kernel_launches += ds.kernel_launches;
+        }
+        if (!ok) continue;  // distance type too narrow: retry wider
+        CCG_HIP(hipEventRecord(L.ev[1], st));
+
+        // ---- check traversal flags before the epilogue
+        DevFlags hf;
+        CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (hf.bad_sample) return fail(CC_EINVAL, "bad sample");
+        if (hf.disconnected) return fail(CC_EDISCONNECTED, "some node is unreachable from some sample");
+        if (hf.timeout) return fail(CC_EDEVICE, "traversal wait expired");
+
+        // ---- epilogue
+        EpilogueArgs ea;
+        ea.n = n;
+        ea.k = k;
+        ea.dk = dk;
+        ea.D = D;
+        ea.Dr = Dr;
+        ea.samples = samples_dev;
+        ea.maxd = maxd_f + maxd_r;
+        ea.eps_num = r.en;
+        ea.eps_den = r.ed;
+        ea.S_hyb = out->S_hyb;
+        ea.S_samp = out->S_samp;
+        ea.S_piv = out->S_piv;
+        ea.S_pub = out->S_pub;
+        ea.pivot = out->pivot;
+        ea.delta = out->delta;
+        ea.sampsum = out->sampsum;
+        ea.src_sum = src_sum;
+        ea.dmat = dmat;
+        ea.Dout = out->D;
+        // the epilogue scratch is carved behind the traversal layout (the
+        // traversal scratch is dead by now and is reused)
+        const size_t es = epilogue_scratch(n, k, ea.maxd);
+        void* escr = es <= trav_scratch ? ts : L.arena2.get(es);
+        run_epilogue(st, ea, escr, es, flags);
+        if (out->samples)
+            CCG_HIP(hipMemcpyAsync(out->samples, samples_dev, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, st));
+        CCG_HIP(hipEventRecord(L.ev[2], st));
+        CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (timing) {
+            timing->traverse_ms = elapsed(L.ev[0], L.ev[1]);
+            timing->epilogue_ms = elapsed(L.ev[1], L.ev[2]);
+            timing->total_ms = elapsed(L.ev[0], L.ev[2]);
+            timing->levels = stats.levels;
+            timing->arcs_scanned = stats.arcs_scanned;
+            timing->nodes_visited = stats.nodes_visited;
+            timing->launches = stats.launches;
+            timing->dist_bytes = db;
+            timing->kernel_ms = stats.kernel_ms;
+            timing->kernel_launches = stats.kernel_launches;
+            timing->arcs_matched = stats.arcs_matched;
+        }
+        if (hf.disconnected) return fail(CC_EDISCONNECTED, "some node is unreachable from some sample");
+        if (hf.overflow) return fail(CC_EOVERFLOW, "an estimate numerator reached 2^53");
+        if (hf.bad_sample) return fail(CC_EINVAL, "bad sample");
+        return CC_OK;
+    }
+    return fail(CC_EOVERFLOW, "a distance does not fit in 32 bits");
+}
+
+cc_status guarded(cc_context* ctx, const std::function<cc_status()>& fn) {
+    try {
+        CCG_HIP(hipSetDevice(ctx->device));
+        return fn();
+    } catch (const std::bad_alloc&) {
+        return fail(CC_ENOMEM, "device allocation failed");
+    } catch (const HipError& e) {
+        if (e.err == hipErrorOutOfMemory) return fail(CC_ENOMEM, e.where);
+        if (e.err == hipErrorNotSupported) return fail(CC_EINVAL, e.where);
+        return fail(CC_EDEVICE, e.where + ": " + hipGetErrorString(e.err));
+    }
+}
+
+}  // namespace
+
+extern "C" cc_status cc_estimate_device(cc_context* ctx, const cc_graph* g, const cc_params* p, cc_result* out,
+                                        void* hip_stream) {
+    if (!ctx || !g || !p || !out) return fail(CC_EINVAL, "cc_estimate_device: null argument");
+    Resolved r;
+    cc_status s = resolve_params(g, p, r);
+    if (s != CC_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return guarded(ctx, [&]() -> cc_status {
+        Lane* L = &ctx->lane;
+        hipStream_t saved = L->stream;
+        if (hip_stream) L->stream = (hipStream_t)hip_stream;
+        cc_timing t{};
+        cc_status st;
+        try {
+            st = run_job(ctx, g, r, out, *L, &t);
+        } catch (...) {
+            L->stream = saved;
+            throw;
+        }
+        L->stream = saved;
+        if (st == CC_OK) ctx->last = t;
+        return st;
+    });
+}
+
+namespace {
+
+// Device staging for host outputs: allocate device buffers for the
+// requested fields, run, copy back.
+cc_status estimate_to_host(cc_context* ctx, const cc_graph* g, const Resolved& r, const cc_result* host, Lane& L,
+                           cc_timing* t) {
+    const int64_t n = g->dg.n;
+    const int32_t k = r.k;
+    struct F {
+        void* h;
+        size_t bytes;
+        void* d;
+    };
+    std::vector<F> fields;
+    cc_result dev{};
+    auto add = [&](void* h, size_t bytes) -> void* {
+        if (!h) return nullptr;
+        fields.push_back({h, bytes, nullptr});
+        return h;
+    };
+    add(host->S_hyb, sizeof(double) * n);
+    add(host->S_samp, sizeof(double) * n);
+    add(host->S_piv, sizeof(int64_t) * n);
+    add(host->S_pub, sizeof(int64_t) * n);
+    add(host->pivot, sizeof(int32_t) * n);
+    add(host->delta, sizeof(int32_t) * n);
+    add(host->sampsum, sizeof(int64_t) * n);
+    add(host->src_sum, sizeof(int64_t) * k);
+    add(host->samples, sizeof(int32_t) * k);
+    add(host->dmat, sizeof(int32_t) * (size_t)k * k);
+    add(host->D, sizeof(int32_t) * (size_t)n * k);
+    size_t total = 0;
+    for (auto& f : fields) total += Carver::sz(f.bytes);
+    void* buf = nullptr;
+    if (total) {
+        if (hipMalloc(&buf, total) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CC_ENOMEM, "output staging allocation failed");
+        }
+    }
+    Carver c(buf);
+    for (auto& f : fields) f.d = c.take<char>(f.bytes);
+    auto dptr = [&](void* h) -> void* {
+        for (auto& f : fields)
+            if (f.h == h) return f.d;
+        return nullptr;
+    };
+    dev.S_hyb = (double*)dptr(host->S_hyb);
+    dev.S_samp = (double*)dptr(host->S_samp);
+    dev.S_piv = (int64_t*)dptr(host->S_piv);
+    dev.S_pub = (int64_t*)dptr(host->S_pub);
+    dev.pivot = (int32_t*)dptr(host->pivot);
+    dev.delta = (int32_t*)dptr(host->delta);
+    dev.sampsum = (int64_t*)dptr(host->sampsum);
+    dev.src_sum = (int64_t*)dptr(host->src_sum);
+    dev.samples = (int32_t*)dptr(host->samples);
+    dev.dmat = (int32_t*)dptr(host->dmat);
+    dev.D = (int32_t*)dptr(host->D);
+    cc_status s;
+    try {
+        s = run_job(ctx, g, r, &dev, L, t);
+        if (s == CC_OK) {
+            for (auto& f : fields) CCG_HIP(hipMemcpyAsync(f.h, f.d, f.bytes, hipMemcpyDeviceToHost, L.stream));
+            CCG_HIP(hipStreamSynchronize(L.stream));
+        }
+    } catch (...) {
+        if (buf) (void)hipFree(buf);
+        throw;
+    }
+    if (buf) (void)hipFree(buf);
+    return s;
+}
+
+}  // namespace
+
+extern "C" cc_status cc_estimate(cc_context* ctx, const cc_graph* g, const cc_params* p, cc_result* out) {
+    if (!ctx || !g || !p || !out) return fail(CC_EINVAL, "cc_estimate: null argument");
+    Resolved r;
+    cc_status s = resolve_params(g, p, r);
+    if (s != CC_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return guarded(ctx, [&]() -> cc_status {
+        cc_timing t{};
+        cc_status st = estimate_to_host(ctx, g, r, out, ctx->lane, &t);
+        if (st == CC_OK) ctx->last = t;
+        return st;
+    });
+}
+
+extern "C" cc_status cc_last_timing(const cc_context* ctx, cc_timing* t) {
+    if (!ctx || !t) return fail(CC_EINVAL, "cc_last_timing: null argument");
+    *t = ctx->last;
+    return CC_OK;
+}
+
+// ---------------------------------------------------------------- serving
+
+namespace {
+
+double ms_between(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+void finish_job(cc_context* ctx, cc_job* j, cc_status s, const std::string& err) {
+    j->status = s;
+    j->err = err;
+    j->t_done = std::chrono::steady_clock::now();
+    graph_unref(j->g);
+    j->g = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(j->m);
+        j->state = 2;
+    }
+    j->cv.notify_all();
+    if (j->refs.fetch_sub(1) == 1) delete j;
+}
+
+void worker_main(cc_context* ctx, Lane* L) {
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        cc_job* j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(ctx->qmu);
+            for (;;) {
+                if (ctx->stopping) return;
+                // admit the oldest job that fits the memory budget (continuous
+                // batching: a small job may overtake a large one that waits for
+                // memory, but never a job of the same or smaller size)
+                auto it = ctx->queue.begin();
+                for (; it != ctx->queue.end(); ++it) {
+                    if (ctx->in_use + (int64_t)(*it)->need <= ctx->budget || ctx->inflight == 0) break;
+                }
+                if (it != ctx->queue.end()) {
+                    j = *it;
+                    ctx->queue.erase(it);
+                    ctx->in_use += (int64_t)j->need;
+                    ctx->inflight += 1;
+                    break;
+                }
+                ctx->qcv.wait(lk);
+            }
+        }
+        j->state = 1;
+        j->t_admit = std::chrono::steady_clock::now();
+        Resolved r;
+        r.k = j->p.k;
+        r.mode = j->p.mode;
+        r.en = j->p.eps_num;
+        r.ed = j->p.eps_den;
+        r.samples = j->samples;
+        cc_status s;
+        std::string err;
+        try {
+            cc_timing t{};
+            s = estimate_to_host(ctx, j->g, r, &j->out, *L, &t);
+            if (s != CC_OK) err = g_last_error;
+        } catch (const std::bad_alloc&) {
+            s = CC_ENOMEM;
+            err = "device allocation failed";
+        } catch (const HipError& e) {
+            s = CC_EDEVICE;
+            err = e.where + ": " + hipGetErrorString(e.err);
+        }
+        {
+            std::lock_guard<std::mutex> lk(ctx->qmu);
+            ctx->in_use -= (int64_t)j->need;
+            ctx->inflight -= 1;
+        }
+        ctx->qcv.notify_all();
+        finish_job(ctx, j, s, err);
+    }
+}
+
+void start_service(cc_context* ctx) {
+    if (ctx->service_started) return;
+    const int slots = ctx->cfg.max_inflight > 0 ? ctx->cfg.max_inflight : 8;
+    for (int i = 0; i < slots; i++) {
+        auto L = std::make_unique<Lane>();
+        L->init(nullptr);
+        ctx->worker_lanes.push_back(std::move(L));
+    }
+    for (int i = 0; i < slots; i++) ctx->workers.emplace_back(worker_main, ctx, ctx->worker_lanes[(size_t)i].get());
+    ctx->service_started = true;
+}
+
+}  // namespace
+
+extern "C" cc_status cc_submit(cc_context* ctx, const cc_graph* g, const cc_params* p, const cc_result* out,
+                               cc_job** job) {
+    if (!ctx || !g || !p || !out || !job) return fail(CC_EINVAL, "cc_submit: null argument");
+    Resolved r;
+    cc_status s = resolve_params(g, p, r);
+    if (s != CC_OK) return s;
+    cc_job* j = new (std::nothrow) cc_job();
+    if (!j) return fail(CC_ENOMEM, "cc_submit: host allocation");
+    j->ctx = ctx;
+    j->g = const_cast<cc_graph*>(g);
+    j->g->refs.fetch_add(1);
+    j->p = *p;
+    j->p.eps_num = (int32_t)r.en;
+    j->p.eps_den = (int32_t)r.ed;
+    j->samples = r.samples;
+    j->p.samples = nullptr;
+    j->out = *out;
+    j->need = job_bytes(g->dg, r.k, r.mode, g->dg.weighted ? 4 : 1);
+    j->t_submit = std::chrono::steady_clock::now();
+    {
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        try {
+            CCG_HIP(hipSetDevice(ctx->device));
+            start_service(ctx);
+        } catch (const HipError& e) {
+            graph_unref(j->g);
+            delete j;
+            return fail(CC_EDEVICE, "cc_submit: " + e.where);
+        }
+        ctx->queue.push_back(j);
+    }
+    ctx->qcv.notify_all();
+    *job = j;
+    return CC_OK;
+}
+
+extern "C" cc_status cc_poll(cc_job* j) {
+    if (!j) return fail(CC_EINVAL, "cc_poll: null job");
+    const int s = j->state.load();
+    if (s == 2 || s == 3) return j->status;
+    return CC_ENOTREADY;
+}
+
+extern "C" cc_status cc_wait(cc_job* j) {
+    if (!j) return fail(CC_EINVAL, "cc_wait: null job");
+    std::unique_lock<std::mutex> lk(j->m);
+    j->cv.wait(lk, [&] { return j->state.load() >= 2; });
+    if (j->status != CC_OK && !j->err.empty()) g_last_error = j->err;
+    return j->status;
+}
+
+extern "C" cc_status cc_cancel(cc_job* j) {
+    if (!j) return fail(CC_EINVAL, "cc_cancel: null job");
+    cc_context* ctx = j->ctx;
+    std::lock_guard<std::mutex> lk(ctx->qmu);
+    auto it = std::find(ctx->queue.begin(), ctx->queue.end(), j);
+    if (it == ctx->queue.end()) return fail(CC_EBUSY, "job already running or finished");
+    ctx->queue.erase(it);
+    j->status = CC_ECANCELLED;
+    j->t_done = std::chrono::steady_clock::now();
+    graph_unref(j->g);
+    j->g = nullptr;
+    {
+        std::lock_guard<std::mutex> jl(j->m);
+        j->state = 3;
+    }
+    j->cv.notify_all();
+    if (j->refs.fetch_sub(1) == 1) delete j;
+    return CC_OK;
+}
+
+extern "C" cc_status cc_job_times(const cc_job* j, double* queue_ms, double* total_ms) {
+    if (!j) return fail(CC_EINVAL, "cc_job_times: null job");
+    if (j->state.load() < 2) return CC_ENOTREADY;
+    if (queue_ms) *queue_ms = j->state.load() == 3 ? ms_between(j->t_submit, j->t_done)
+                                                  : ms_between(j->t_submit, j->t_admit);
+    if (total_ms) *total_ms = ms_between(j->t_submit, j->t_done);
+    return CC_OK;
+}
+
+extern "C" void cc_job_release(cc_job* j) {
+    if (!j) return;
+    if (j->refs.fetch_sub(1) == 1) delete j;
+}

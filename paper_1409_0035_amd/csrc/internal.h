@@ -1,0 +1,233 @@
+// Internal declarations shared by the HIP kernel files and the runtime.
+// Not part of the C ABI (see include/ccgpu.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace ccg {
+
+// ---------------------------------------------------------------- errors
+struct HipError {
+    hipError_t err;
+    std::string where;
+};
+
+#define CCG_HIP(call)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) throw ::ccg::HipError{e_, std::string(#call) + " @ " + \
+                                                              __FILE__ + ":" + std::to_string(__LINE__)}; \
+    } while (0)
+
+// Device-side status words, one block per job.  Kernels only ever set flags
+// (plain stores of 1) or add to counters, so the order of updates is
+// irrelevant.
+struct DevFlags {
+    int32_t disconnected;   // a node never reached by some sample
+    int32_t overflow;       // a distance or numerator out of range
+    int32_t bad_sample;     // duplicate / out-of-range sample
+    int32_t timeout;        // a bounded wait expired (persistent kernels)
+    int64_t maxd;           // largest distance seen (weighted traversal)
+    int64_t reserved[3];
+};
+
+// Per-level counters written by one traversal launch and read by the host.
+struct LevelCounters {
+    int32_t n_out;          // entries appended to the next work list
+    int32_t n_new;          // nodes that received new bits / distances this level
+    int64_t arcs;           // adjacency entries scanned
+    int64_t frontier_arcs;  // sum of degrees of the nodes appended (push heuristics)
+    int64_t matched;        // scanned arcs whose tail was on the previous level (mask reads)
+};
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int readlane32(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off);
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+__device__ __forceinline__ int32_t wave_sum32(int32_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_min64(uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        uint64_t y = __shfl_xor(x, off);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Append-to-list index for the lanes with pred set; works in divergent code
+// (only active lanes take part).  One atomic per call per wave.
+__device__ __forceinline__ int wave_append(int32_t* counter, bool pred) {
+    uint64_t act = __ballot(1);
+    uint64_t m = __ballot(pred);
+    int leader = __ffsll((unsigned long long)act) - 1;
+    int base = 0;
+    if (lane_id() == leader && m) base = atomicAdd(counter, (int32_t)__popcll(m));
+    base = __shfl(base, leader);
+    return pred ? base + (int)__popcll(m & lanemask_lt()) : -1;
+}
+
+// ---------------------------------------------------------------- distances
+template <typename DT> struct DistT;
+template <> struct DistT<uint8_t> {
+    static constexpr uint32_t never = 0xFFu;
+    static constexpr int64_t max_level = 254;
+};
+template <> struct DistT<uint16_t> {
+    static constexpr uint32_t never = 0xFFFFu;
+    static constexpr int64_t max_level = 65534;
+};
+template <> struct DistT<uint32_t> {
+    static constexpr uint32_t never = 0xFFFFFFFFu;
+    static constexpr int64_t max_level = 0x7FFFFFFE;
+};
+
+// ---------------------------------------------------------------- graph
+struct DevGraph {
+    int64_t n = 0;
+    int64_t arcs = 0;
+    bool directed = false;
+    bool weighted = false;
+    // out-arcs (as uploaded)
+    const uint32_t* rp = nullptr;
+    const int32_t* col = nullptr;
+    const int32_t* w = nullptr;
+    // in-arcs (transpose); equal to the out-arcs for undirected graphs
+    const uint32_t* rrp = nullptr;
+    const int32_t* rcol = nullptr;
+    const int32_t* rw = nullptr;
+};
+
+// ---------------------------------------------------------------- traversal API
+// Traversal statistics accumulated by the drivers.
+struct TravStats {
+    int64_t levels = 0;
+    int64_t arcs_scanned = 0;
+    int64_t nodes_visited = 0;
+    int64_t launches = 0;
+    int64_t maxd = 0;        // largest distance written
+    int64_t arcs_matched = 0;
+    double kernel_ms = 0;    // summed duration of the per-level traversal kernels
+    int64_t kernel_launches = 0;
+};
+
+// Event pair for timing one kernel launch on a stream.
+struct KernelTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer() {
+        CCG_HIP(hipEventCreate(&a));
+        CCG_HIP(hipEventCreate(&b));
+    }
+    ~KernelTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void start(hipStream_t s) { CCG_HIP(hipEventRecord(a, s)); }
+    void stop(hipStream_t s) { CCG_HIP(hipEventRecord(b, s)); }
+    // call after the stream has been synchronised
+    double ms() const {
+        float t = 0.f;
+        CCG_HIP(hipEventElapsedTime(&t, a, b));
+        return t;
+    }
+};
+
+// Device scratch the traversal drivers carve up; owned by the runtime.
+struct Scratch {
+    void* base = nullptr;
+    size_t size = 0;
+};
+
+enum class DistKind { U8 = 1, U16 = 2, U32 = 4 };
+
+// Batched bit-parallel BFS over one group of up to 256 samples, written to
+// D columns [src_base, src_base + kg) of the node-major n x k matrix D.
+// `in_rp/in_col` is the pull adjacency (in-arcs).  Returns false when the
+// distance type overflowed (retry with a wider type); sets flags->disconnected
+// when some node is unreachable.
+bool bfs_batched(hipStream_t st, const uint32_t* in_rp, const int32_t* in_col, int64_t n,
+                 const int32_t* samples_dev, int32_t kg, int32_t src_base, int32_t k, void* D,
+                 DistKind dk, void* scratch, size_t scratch_size, DevFlags* flags, LevelCounters* cnt_dev,
+                 LevelCounters* cnt_host, TravStats* stats);
+size_t bfs_batched_scratch(int64_t n, int32_t kg);
+
+// Plain single-source BFS for every sample, source-major output Dt[k][n].
+bool bfs_plain(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
+               const int32_t* in_col, int64_t n, int64_t arcs, const int32_t* samples_host, int32_t k,
+               void* Dt, DistKind dk, void* scratch, size_t scratch_size, DevFlags* flags,
+               LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
+size_t bfs_plain_scratch(int64_t n);
+
+// Transpose source-major Dt[k][n] into node-major D[n][k].
+void transpose_dist(hipStream_t st, const void* Dt, void* D, int64_t n, int32_t k, DistKind dk);
+
+// Weighted: batched delta-stepping over groups of 64 samples, and the plain
+// single-source version.  D is int32 node-major (unreached = INT32_MAX).
+void sssp_weighted_batched(hipStream_t st, const DevGraph& g, bool reverse, const int32_t* samples_dev,
+                           int32_t k, int32_t* D, int32_t delta, void* scratch, size_t scratch_size,
+                           DevFlags* flags, LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
+size_t sssp_weighted_batched_scratch(int64_t n);
+void sssp_weighted_plain(hipStream_t st, const DevGraph& g, bool reverse, const int32_t* samples_host,
+                         int32_t k, int32_t* Dt, int32_t delta, void* scratch, size_t scratch_size,
+                         DevFlags* flags, LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
+size_t sssp_weighted_plain_scratch(int64_t n);
+
+// ---------------------------------------------------------------- epilogue API
+struct EpilogueArgs {
+    int64_t n = 0;
+    int32_t k = 0;
+    DistKind dk = DistKind::U8;
+    const void* D = nullptr;     // node-major distances
+    const void* Dr = nullptr;    // reverse-direction distances (round trip) or nullptr
+    const int32_t* samples = nullptr;  // device
+    int64_t maxd = 0;            // upper bound on every (combined) distance
+    int64_t eps_num = 1, eps_den = 1;
+    // outputs (device, may be null)
+    double* S_hyb = nullptr;
+    double* S_samp = nullptr;
+    int64_t* S_piv = nullptr;
+    int64_t* S_pub = nullptr;
+    int32_t* pivot = nullptr;
+    int32_t* delta = nullptr;
+    int64_t* sampsum = nullptr;
+    int64_t* src_sum = nullptr;  // required (workspace if caller does not want it)
+    int32_t* dmat = nullptr;     // required (workspace if caller does not want it)
+    int32_t* Dout = nullptr;     // optional int32 copy of D (combined)
+};
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd);
+void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
+
+void fill_u32(hipStream_t st, void* p, uint32_t value, size_t count);
+
+}  // namespace ccg

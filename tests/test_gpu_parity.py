@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.  Integer outputs (distances, pivots, Delta, sums,
+sample distance matrix) must be bit-exact; the two double estimates must agree
+within a relative error of 1e-12 (both sides divide the same exact integer
+numerator once, so they are expected to be identical)."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_1409_0035_amd as cc
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-12
+ALL = ("S_hyb", "S_samp", "S_piv", "S_pub", "pivot", "delta", "sampsum", "src_sum", "samples", "dmat", "D")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = cc.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(ctx, g, k, mode, samples=None, seed=0, eps=None, outputs=ALL):
+    gh = ctx.upload(g)
+    try:
+        return cc.cc_estimate(ctx.handle, gh, k, mode=mode, seed=seed, samples=samples, eps=eps, outputs=outputs)
+    finally:
+        ctx.release(gh)
+
+
+def check_all(res, ref, samples, with_D=True):
+    if with_D:
+        assert (res["D"] == ref["D"]).all(), "D"
+    assert (res["samples"] == np.asarray(samples)).all()
+    assert (res["pivot"] == ref["pivot"]).all(), "pivot"
+    assert (res["delta"] == ref["delta"]).all(), "delta"
+    assert (res["sampsum"] == ref["sampsum"]).all(), "sampsum"
+    assert (res["src_sum"] == ref["src_sum"]).all(), "src_sum"
+    assert (res["dmat"] == ref["dmat"]).all(), "dmat"
+    assert (res["S_piv"] == ref["S_piv"]).all(), "S_piv"
+    assert (res["S_pub"] == ref["S_pub"]).all(), "S_pub"
+    for f in ("S_hyb", "S_samp"):
+        a, b = res[f], ref[f]
+        assert np.all(np.abs(a - b) <= RTOL * np.abs(b)), f
+        assert (a == b).all(), f + " (not bit-identical)"
+
+
+def parity(ctx, g, k, seed, eps=None, modes=(cc.CC_BATCHED, cc.CC_PLAIN)):
+    samples = cc.cc_draw_samples(g.n, k, seed)
+    rg = graphgen.transpose(g) if g.directed else None
+    ref = oracle.estimate_all(g, samples, eps=eps, threads=8, reverse_graph=rg)
+    out = {}
+    for mode in modes:
+        _say(f"  gpu {g.name} n={g.n} arcs={g.arcs} k={k} mode={mode} eps={eps}")
+        res = run_gpu(ctx, g, k, mode, seed=seed, eps=eps)
+        check_all(res, ref, samples)
+        out[mode] = res
+    return out
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("make,k", [(lambda: graphgen.path(50), 5), (lambda: graphgen.star(40), 7),
+                                    (lambda: graphgen.cycle(33), 4), (lambda: graphgen.complete(20), 3),
+                                    (lambda: graphgen.grid(13, 11, 4), 9), (lambda: graphgen.grid(12, 9, 8), 64)])
+def test_closed_form_families(ctx, make, k):
+    parity(ctx, make(), k, seed=7)
+
+
+def test_worked_example_path9(ctx):
+    g = graphgen.path(9)
+    res = run_gpu(ctx, g, 3, cc.CC_BATCHED, samples=[0, 4, 8], eps=(1, 2))
+    assert list(res["S_hyb"]) == [36, 33, 32, 18, 20, 18, 80 / 3, 33, 36]
+    assert list(res["pivot"]) == [0, 0, 0, 1, 1, 1, 1, 2, 2]
+
+
+# ---------------------------------------------------------------- random / ragged
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_graphs(ctx, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 200))
+    directed = seed % 3 == 2
+    g = graphgen.gnp(n, float(rng.uniform(0.01, 0.1)), seed, directed=directed)
+    k = int(rng.integers(1, min(n, 130) + 1))
+    eps = [(1, 1), (1, 3), (2, 5), None][seed % 4]
+    parity(ctx, g, k, seed, eps=eps)
+
+
+@pytest.mark.parametrize("k", [1, 63, 64, 65, 100, 192, 256, 257, 300])
+def test_ragged_sample_counts(ctx, k):
+    """k around the 64-bit word and 256-sample group boundaries."""
+    g = graphgen.ba(3000, 3, seed=11)
+    parity(ctx, g, k, seed=k)
+
+
+def test_deep_graph_widens_distance_type(ctx):
+    """More than 254 BFS levels: 8-bit distances overflow and the library
+    reruns with 16-bit ones."""
+    g = graphgen.path(700)
+    parity(ctx, g, 6, seed=3)
+
+
+# ---------------------------------------------------------------- workload shapes
+
+def test_ba10k_k64_full(ctx):
+    """Barabasi-Albert n=10,000, 4 edges per node, 64 samples: every output."""
+    g = graphgen.workload("ba10k")
+    out = parity(ctx, g, 64, seed=1)
+    S = oracle.exact_sums(g, threads=8)
+    err = np.abs(out[cc.CC_BATCHED]["S_hyb"] - S) / S
+    _say(f"  ba10k hybrid mean rel err {err.mean():.4f}")
+    assert err.mean() < 0.1
+
+
+def test_rmat14_k256(ctx):
+    g = graphgen.rmat(14, 16, seed=5)
+    parity(ctx, g, 256, seed=5)
+
+
+def test_directed_rmat_round_trip(ctx):
+    g = graphgen.rmat(12, 16, seed=6, directed=True)
+    parity(ctx, g, 128, seed=6)
+
+
+def test_symmetric_digraph_round_trip_is_twice(ctx):
+    g = graphgen.ba(800, 3, seed=2)
+    gd = graphgen.symmetric_digraph(g)
+    a = run_gpu(ctx, g, 40, cc.CC_BATCHED, seed=9, eps=(1, 2))
+    b = run_gpu(ctx, gd, 40, cc.CC_BATCHED, seed=9, eps=(1, 2))
+    assert (a["pivot"] == b["pivot"]).all()
+    assert (2 * a["S_hyb"] == b["S_hyb"]).all()
+
+
+# ---------------------------------------------------------------- errors
+
+def test_error_paths(ctx):
+    g = graphgen.path(10)
+    gh = ctx.upload(g)
+    try:
+        for kw in (dict(k=11), dict(k=0), dict(k=3, eps=(3, 2)), dict(k=3, eps=(0, 1)),
+                   dict(k=3, samples=[1, 1, 2]), dict(k=2, samples=[0, 10])):
+            with pytest.raises(cc.CCError) as e:
+                cc.cc_estimate(ctx.handle, gh, **kw)
+            assert e.value.status == cc.CC_EINVAL, kw
+    finally:
+        ctx.release(gh)
+    # two components
+    two = graphgen.csr_from_arcs(6, [0, 1, 3, 4], [1, 2, 4, 5])
+    gh = ctx.upload(two)
+    try:
+        for mode in (cc.CC_BATCHED, cc.CC_PLAIN):
+            with pytest.raises(cc.CCError) as e:
+                cc.cc_estimate(ctx.handle, gh, 2, mode=mode, samples=[0, 1])
+            assert e.value.status == cc.CC_EDISCONNECTED
+    finally:
+        ctx.release(gh)
+    with pytest.raises(cc.CCError) as e:
+        ctx.upload(graphgen.csr_from_arcs(3, [0], [1], symmetrize=False), validate=True)
+    assert e.value.status == cc.CC_EINVAL
+
+
+def test_device_outputs_on_torch_stream(ctx):
+    import torch
+    g = graphgen.ba(2000, 4, seed=3)
+    gh = ctx.upload(g)
+    try:
+        n, k = g.n, 64
+        out = {"S_hyb": torch.empty(n, dtype=torch.float64, device="cuda"),
+               "pivot": torch.empty(n, dtype=torch.int32, device="cuda")}
+        s = torch.cuda.Stream()
+        cc.cc_estimate_device(ctx.handle, gh, k, out, seed=4, stream=s)
+        s.synchronize()
+        ref = cc.cc_estimate(ctx.handle, gh, k, seed=4, outputs=("S_hyb", "pivot"))
+        assert (out["S_hyb"].cpu().numpy() == ref["S_hyb"]).all()
+        assert (out["pivot"].cpu().numpy() == ref["pivot"]).all()
+        t = cc.cc_last_timing(ctx.handle)
+        assert t["total_ms"] > 0 and t["levels"] > 0
+    finally:
+        ctx.release(gh)
