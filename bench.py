@@ -41,15 +41,12 @@ def pct(xs, q):
 
 
 def algorithmic_bytes(t: dict, n: int, k: int, W: int) -> float:
-    """Bytes the batched pull traversal must move, from its own work counters:
-    per scanned arc 4 B (target id) + db B (level stamp of the target); per
-    arc whose target was on the previous level 8W B (its seen mask); per node
-    processed in a level 8 B (row bounds) + 16W B (seen mask in and out) +
-    8 B (work-list entry in and out); and the distance matrix written once,
-    n*k*db B."""
-    db = t["dist_bytes"]
-    return (t["arcs_scanned"] * (4 + db) + t["arcs_matched"] * 8 * W + t["nodes_visited"] * (16 + 16 * W)
-            + n * k * db)
+    """Bytes the batched traversal kernels must move, from their own work
+    counters: per arc scanned by a pull or pushed along by a push, 4 B (the
+    arc's end id) + 8W B (the neighbour's seen mask, or the atomic OR of it);
+    per node of a listed 64-node group per level, 4 B (its row bound) + 3 x 8W B
+    (seen mask in, seen mask out, level mask out)."""
+    return t["arcs_scanned"] * (4 + 8 * W) + t["nodes_visited"] * (4 + 24 * W)
 
 
 def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
@@ -173,7 +170,7 @@ def main():
     achieved = abytes / (kernel_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_pull_level", "launches_per_step": launches,
+                "kernel": "BFS level (k_hub_level|k_push + k_group_level)", "launches_per_step": launches,
                 "avg_launch_ms": round(kernel_ms / max(launches, 1), 5),
                 "algorithmic_bytes_per_step": int(abytes)}
 
@@ -198,7 +195,7 @@ def main():
     line = {
         "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u8" if tm["dist_bytes"] == 1 else f"u{8 * tm['dist_bytes']}",
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64 bitmask / int32 dist / int64 sums",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {g.name} n={g.n} m={m} k={k} batched", "n": g.n, "m": m,
                    "k": k, "eps": f"1/{int(round(math.sqrt(k)))}"},

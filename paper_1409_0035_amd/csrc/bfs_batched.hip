@@ -1,22 +1,38 @@
 // Batched bit-parallel breadth-first search: up to 256 samples at once, one
 // bit per sample in W = ceil(kg/64) 64-bit words per node.
 //
-// Computes D[v][i] = d(c_i, v) (hop distances) for one group of samples: the
-// k single-source computations of Sec. 3 of the paper, run together.  The
-// paper runs them one after another with Dijkstra; on the GPU the samples
-// share every adjacency read.
+// This is the k single-source computations of Sec. 3 of the paper run
+// together: every adjacency read serves all samples of the group.  The
+// traversal never materialises the distance matrix; it records, for every
+// level L, the seen mask S_L(v) = {i : d(c_i, v) <= L} (a "snapshot").  The
+// estimator epilogue derives distances, pivots, sums and the L/HC split from
+// these masks with bit operations (d(c_i, v) = number of levels at which bit
+// i is still clear).
 //
-// Level-synchronous pull ("bottom-up") formulation with double-buffered seen
-// masks S_prev / S_cur:
-//   new_L(v) = (OR_{u in N_in(v)} S_{L-1}(u)) & ~S_{L-1}(v)
-// This is exact without a separate frontier set: if v has not been reached
-// from c_i by level L-1, then any in-neighbour u that has been reached from
-// c_i satisfies d(c_i,u) >= d(c_i,v) - 1 >= L-1, hence d(c_i,u) = L-1.
-// A per-node level stamp (parity double-buffered, same width as a distance)
-// marks nodes that gained bits at the previous level, so only those
-// neighbours' masks are read.  Nodes whose mask is full (all samples have
-// reached them) leave the work list one level after they fill up (so both
-// buffers hold the full mask).
+// Level-synchronous, direction-optimising:
+//   pull  new_L(v) = (OR_{u in N_in(v)} S_{L-1}(u)) & ~S_{L-1}(v).  Exact with
+//         no frontier test: if bit i is clear in S_{L-1}(v), every in-neighbour
+//         u with bit i set has d(c_i,u) >= d(c_i,v) - 1 >= L-1, i.e. = L-1.
+//   push  for every node u that gained bits at level L-1 and every out-arc
+//         u->v: NX(v) |= S_{L-1}(u) (atomic OR); then new_L(v) = NX(v) & ~S_{L-1}(v).
+//         The same triangle argument makes the extra (older) bits harmless.
+// The host picks push while the frontier's out-arcs are few compared with the
+// arcs a pull would scan.
+//
+// Pull work decomposition (node ids are degree-sorted by the graph builder):
+//   * hub nodes (the leading nh ids) are scanned by k_hub_level in fixed chunks
+//     of arcs, one wave per chunk, reduced with DPP and OR-ed atomically into
+//     NX(hub);
+//   * every other node belongs to a group of 64 consecutive ids handled by one
+//     wave in k_group_level: G lanes per node (G from the group's largest
+//     degree) read the node's arcs in coalesced runs and OR-reduce with DPP.
+// k_group_level then finalises every node of the group (in both modes): the
+// new bits, the next seen mask, the level snapshot, the frontier list for a
+// following push level, and the per-sample histogram
+// hist[i][L] = #{v not sampled : d(c_i, v) = L} by ballot transposition.
+// A group leaves the work list once all of its nodes were full (reached by
+// every sample) at the start of a level; fill_level[g] records the last level
+// whose snapshot the group wrote -- later snapshots of it are all-ones.
 #include "internal.h"
 
 namespace ccg {
@@ -24,292 +40,520 @@ namespace ccg {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kSmallDeg = 32;   // degree up to which one lane scans a node alone
-constexpr int kCheckEvery = 8;       // wave path: test for a full mask every 8*64 arcs
+constexpr int kWaves = kBlock / 64;
 
 template <int W>
 __device__ __forceinline__ uint64_t full_word(int w, uint64_t lastmask) {
     return w == W - 1 ? lastmask : ~0ull;
 }
 
-template <int W, typename DT>
-__global__ __launch_bounds__(kBlock) void k_init_nodes(int64_t n, uint64_t* S0, DT* st0, DT* st1,
-                                                       int32_t* act) {
-    int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (v >= n) return;
-#pragma unroll
-    for (int w = 0; w < W; w++) S0[v * W + w] = 0;
-    st0[v] = (DT)DistT<DT>::never;
-    st1[v] = (DT)DistT<DT>::never;
-    act[v] = (int32_t)v;
+// OR over aligned groups of 2^lg lanes (lg <= 4) inside a 16-lane row, by DPP
+// lane permutations; afterwards every lane holds its group's OR.
+__device__ __forceinline__ uint32_t dpp_or_group32(uint32_t x, int lg) {
+    if (lg >= 1) x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    if (lg >= 2) x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    if (lg >= 3) x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    if (lg >= 4) x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false);  // row_mirror
+    return x;
 }
 
-// Sets the level-0 state of the samples: bit i in c_i's mask, stamp 0 and
-// D[c_i][src_base+i] = 0.  Samples are distinct, so every thread writes its
-// own word.
-template <int W, typename DT>
-__global__ void k_init_samples(const int32_t* samples, int32_t kg, uint64_t* S0, DT* st0, DT* D, int64_t k,
-                               int32_t src_base) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kg) return;
-    int64_t v = samples[src_base + i];
-    atomicOr((unsigned long long*)&S0[v * W + (i >> 6)], 1ull << (i & 63));
-    st0[v] = (DT)0;
-    D[v * k + src_base + i] = (DT)0;
+__device__ __forceinline__ uint64_t dpp_or_group64(uint64_t x, int lg) {
+    const uint32_t lo = dpp_or_group32((uint32_t)x, lg);
+    const uint32_t hi = dpp_or_group32((uint32_t)(x >> 32), lg);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-template <int W, typename DT>
-__global__ __launch_bounds__(kBlock) void k_pull_level(
-    const uint32_t* __restrict__ rp, const int32_t* __restrict__ col, const uint64_t* __restrict__ Sprev,
-    uint64_t* __restrict__ Scur, const DT* __restrict__ st_prev, DT* __restrict__ st_cur,
-    const int32_t* __restrict__ act_in, int32_t n_act, int32_t* __restrict__ act_out, DT* __restrict__ D,
-    int64_t k, int32_t src_base, uint64_t lastmask, uint32_t level, LevelCounters* __restrict__ cnt) {
-    const int lane = lane_id();
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = idx < n_act;
-    const int32_t v = valid ? act_in[idx] : 0;
-    const DT want = (DT)(level - 1);
+// OR of a value over the whole wave, valid in every lane: rows by DPP, then
+// the four row results by lane reads.
+__device__ __forceinline__ uint32_t wave_or32_dpp(uint32_t x) {
+    x = dpp_or_group32(x, 4);
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 0) | (uint32_t)__builtin_amdgcn_readlane((int)x, 16) |
+           (uint32_t)__builtin_amdgcn_readlane((int)x, 32) | (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+}
 
-    uint64_t sv[W], acc[W];
-    bool full = true;
-#pragma unroll
-    for (int w = 0; w < W; w++) {
-        sv[w] = valid ? Sprev[(int64_t)v * W + w] : ~0ull;
-        acc[w] = 0;
-        full = full && (sv[w] == full_word<W>(w, lastmask));
-    }
-    const bool active = valid && !full;
-    uint32_t beg = 0, end = 0;
-    if (active) {
-        beg = rp[v];
-        end = rp[v + 1];
-    }
-    const bool big = active && (end - beg > kSmallDeg);
-    int64_t scanned = 0, matched = 0;
+__device__ __forceinline__ uint64_t wave_or64_dpp(uint64_t x) {
+    const uint32_t lo = wave_or32_dpp((uint32_t)x);
+    const uint32_t hi = wave_or32_dpp((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
 
-    // one lane per low-degree node
-    if (active && !big) {
-        for (uint32_t e = beg; e < end; ++e) {
-            const int32_t u = col[e];
-            ++scanned;
-            if (st_prev[u] == want) {
-                ++matched;
-                bool done = true;
+// Loads the words of node u's mask that `need` selects (bit p = word pair p,
+// words 2p and 2p+1), as 16-byte loads where two words are present.
+template <int W>
+__device__ __forceinline__ void load_mask(const uint64_t* __restrict__ S, int64_t u, uint32_t need, uint64_t out[W]) {
+    const uint64_t* row = S + u * W;
 #pragma unroll
-                for (int w = 0; w < W; w++) {
-                    acc[w] |= Sprev[(int64_t)u * W + w];
-                    done = done && ((acc[w] | sv[w]) == full_word<W>(w, lastmask));
-                }
-                if (done) break;
-            }
+    for (int p = 0; p < (W + 1) / 2; p++) {
+        if (2 * p + 1 < W) {
+            uint4 q = make_uint4(0, 0, 0, 0);
+            if (need & (1u << p)) q = *(const uint4*)(row + 2 * p);
+            out[2 * p] = ((uint64_t)q.y << 32) | q.x;
+            out[2 * p + 1] = ((uint64_t)q.w << 32) | q.z;
+        } else {
+            out[2 * p] = (need & (1u << p)) ? row[2 * p] : 0ull;
         }
     }
+}
 
-    // the whole wave per high-degree node
-    uint64_t bm = __ballot(big);
-    while (bm) {
-        const int s = __ffsll((unsigned long long)bm) - 1;
-        bm &= bm - 1;
-        const uint32_t b = (uint32_t)readlane32((int)beg, s);
-        const uint32_t en = (uint32_t)readlane32((int)end, s);
-        uint64_t svs[W], a[W];
+template <int W>
+__device__ __forceinline__ void store_mask(uint64_t* __restrict__ S, int64_t v, const uint64_t x[W]) {
+    uint64_t* row = S + v * W;
 #pragma unroll
-        for (int w = 0; w < W; w++) {
-            svs[w] = readlane64(sv[w], s);
-            a[w] = 0;
-        }
-        int round = 0;
-        for (uint32_t e0 = b; e0 < en; e0 += 64) {
-            const uint32_t e = e0 + lane;
-            if (e < en) {
-                const int32_t u = col[e];
-                ++scanned;
-                if (st_prev[u] == want) {
-                    ++matched;
-#pragma unroll
-                    for (int w = 0; w < W; w++) a[w] |= Sprev[(int64_t)u * W + w];
-                }
-            }
-            if (++round == kCheckEvery) {
-                round = 0;
-                bool done = true;
-#pragma unroll
-                for (int w = 0; w < W; w++) {
-                    a[w] = wave_or64(a[w]);
-                    done = done && ((a[w] | svs[w]) == full_word<W>(w, lastmask));
-                }
-                if (done) break;
-            }
-        }
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            const uint64_t r = wave_or64(a[w]);
-            if (lane == s) acc[w] = r;
+    for (int p = 0; p < (W + 1) / 2; p++) {
+        if (2 * p + 1 < W) {
+            *(uint4*)(row + 2 * p) = make_uint4((uint32_t)x[2 * p], (uint32_t)(x[2 * p] >> 32), (uint32_t)x[2 * p + 1],
+                                                (uint32_t)(x[2 * p + 1] >> 32));
+        } else {
+            row[2 * p] = x[2 * p];
         }
     }
+}
 
-    uint64_t nw[W];
-    bool anynew = false;
+// word pairs of a mask that are not yet all-ones
+template <int W>
+__device__ __forceinline__ uint32_t pairs_needed(const uint64_t s[W], uint64_t lastmask) {
+    uint32_t need = 0;
 #pragma unroll
-    for (int w = 0; w < W; w++) {
-        nw[w] = active ? (acc[w] & ~sv[w]) : 0ull;
-        anynew = anynew || (nw[w] != 0);
+    for (int p = 0; p < (W + 1) / 2; p++) {
+        bool f = s[2 * p] == full_word<W>(2 * p, lastmask);
+        if (2 * p + 1 < W) f = f && (s[2 * p + 1] == full_word<W>(2 * p + 1, lastmask));
+        if (!f) need |= 1u << p;
     }
-    if (valid) {
-#pragma unroll
-        for (int w = 0; w < W; w++) Scur[(int64_t)v * W + w] = sv[w] | nw[w];
-        if (anynew) st_cur[v] = (DT)level;
-    }
+    return need;
+}
 
-    // distances: for every node with new bits, lane j writes D[v][w*64+j]
-    uint64_t m = __ballot(anynew);
-    const int32_t n_new = (int32_t)__popcll(m);
-    while (m) {
-        const int s = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const int64_t vs = readlane32(v, s);
-        DT* row = D + vs * k + src_base;
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            const uint64_t x = readlane64(nw[w], s);
-            if ((x >> lane) & 1ull) row[w * 64 + lane] = (DT)level;
-        }
-    }
+// Adds per-wave partial counts into the block's counter slot: one atomic
+// per field per block.
+struct WaveCounts {
+    int64_t arcs = 0, farcs = 0;
+    int32_t n_new = 0, n_out = 0;
+};
 
-    // nodes not full at the start of this level stay on the list
-    const int pos = wave_append(&cnt->n_out, active);
-    if (active) act_out[pos] = v;
-    const int64_t tot = wave_sum64(scanned);
-    const int64_t mat = wave_sum64(matched);
+__device__ __forceinline__ void flush_counts(WaveCounts c, LevelCounters* slots) {
+    __shared__ int64_t red[kWaves][4];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int64_t a = wave_sum64(c.arcs), f = wave_sum64(c.farcs);
+    const int32_t nn = wave_sum32(c.n_new), no = wave_sum32(c.n_out);
     if (lane == 0) {
-        if (n_new) atomicAdd(&cnt->n_new, n_new);
-        if (tot) atomicAdd((unsigned long long*)&cnt->arcs, (unsigned long long)tot);
-        if (mat) atomicAdd((unsigned long long*)&cnt->matched, (unsigned long long)mat);
+        red[wave][0] = a;
+        red[wave][1] = f;
+        red[wave][2] = nn;
+        red[wave][3] = no;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t[4] = {0, 0, 0, 0};
+        for (int w = 0; w < kWaves; w++)
+            for (int q = 0; q < 4; q++) t[q] += red[w][q];
+        LevelCounters* c0 = slots + (blockIdx.x % kCounterSlots);
+        if (t[0]) atomicAdd((unsigned long long*)&c0->arcs, (unsigned long long)t[0]);
+        if (t[1]) atomicAdd((unsigned long long*)&c0->frontier_arcs, (unsigned long long)t[1]);
+        if (t[2]) atomicAdd(&c0->n_new, (int32_t)t[2]);
+        if (t[3]) atomicAdd(&c0->n_out, (int32_t)t[3]);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uint64_t* S0, uint64_t* snap0,
+                                                 uint64_t* NX, int32_t* chg, uint8_t* gfull, int32_t* fill_level) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) {
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            S0[t * W + w] = 0;
+            snap0[t * W + w] = 0;
+            NX[t * W + w] = 0;
+        }
+        chg[t] = -1;
+    }
+    if (t < ngroups) {
+        gfull[t] = 0;
+        fill_level[t] = 0;
+    }
+}
+
+// Level-0 state: bit i in c_i's mask (both the working mask and snapshot 0);
+// the samples form the level-0 frontier.  Samples are distinct nodes.
+template <int W>
+__global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_base, uint64_t* S0, uint64_t* snap0,
+                               int32_t* chg, const uint32_t* out_rp, LevelCounters* cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kg) return;
+    const int64_t v = samples[src_base + i];
+    const unsigned long long bit = 1ull << (i & 63);
+    atomicOr((unsigned long long*)&S0[v * W + (i >> 6)], bit);
+    atomicOr((unsigned long long*)&snap0[v * W + (i >> 6)], bit);
+    chg[v] = 0;
+    atomicAdd((unsigned long long*)&cnt[i % kCounterSlots].frontier_arcs, (unsigned long long)(out_rp[v + 1] - out_rp[v]));
+}
+
+// push: one wave per group of 64 nodes; every node of the group that gained
+// bits at the previous level sends its mask along its out-arcs (lanes over arcs)
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col,
+                                                 const int32_t* __restrict__ chg, const uint8_t* __restrict__ gfull,
+                                                 int64_t n, int32_t ngroups, int32_t prev_level,
+                                                 const uint64_t* __restrict__ Sprev, uint64_t* NX,
+                                                 LevelCounters* cnt) {
+    const int lane = lane_id();
+    const int32_t waves = gridDim.x * kWaves;
+    WaveCounts wc;
+    for (int32_t g = blockIdx.x * kWaves + (threadIdx.x >> 6); g < ngroups; g += waves) {
+        if (gfull[g]) continue;
+        const int64_t v = (int64_t)g * 64 + lane;
+        uint64_t m = __ballot(v < n && chg[v] == prev_level);
+        while (m) {
+            const int s = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int64_t u = (int64_t)g * 64 + s;
+            uint64_t su[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) su[w] = Sprev[u * W + w];
+            const uint32_t b = out_rp[u], e = out_rp[u + 1];
+            for (uint32_t t = b + lane; t < e; t += 64) {
+                const int64_t x = out_col[t];
+                ++wc.arcs;
+#pragma unroll
+                for (int w = 0; w < W; w++)
+                    if (su[w]) atomicOr((unsigned long long*)&NX[x * W + w], (unsigned long long)su[w]);
+            }
+        }
+    }
+    flush_counts(wc, cnt);
+}
+
+// pull over a hub's in-arcs: one wave per chunk (hub, first arc, end arc)
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_hub_level(const int32_t* __restrict__ col,
+                                                      const uint64_t* __restrict__ Sprev,
+                                                      const int32_t* __restrict__ chunks, int32_t n_chunks,
+                                                      uint64_t* NX, uint64_t lastmask, LevelCounters* cnt) {
+    const int lane = lane_id();
+    const int32_t waves = gridDim.x * kWaves;
+    int64_t scanned = 0;
+    WaveCounts wc;
+    for (int32_t c = blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_chunks; c += waves) {
+        const int64_t h = chunks[3 * c];
+        const uint32_t b = (uint32_t)chunks[3 * c + 1], e = (uint32_t)chunks[3 * c + 2];
+        uint64_t sh[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) sh[w] = Sprev[h * W + w];
+        const uint32_t need = pairs_needed<W>(sh, lastmask);
+        if (!need) continue;  // full hub: nothing to find
+        uint64_t acc[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) acc[w] = 0;
+        uint32_t t = b + lane;
+        for (; t + 64 < e; t += 128) {
+            const int64_t u0 = col[t], u1 = col[t + 64];
+            uint64_t a0[W], a1[W];
+            load_mask<W>(Sprev, u0, need, a0);
+            load_mask<W>(Sprev, u1, need, a1);
+#pragma unroll
+            for (int w = 0; w < W; w++) acc[w] |= a0[w] | a1[w];
+            scanned += 2;
+        }
+        if (t < e) {
+            uint64_t a0[W];
+            load_mask<W>(Sprev, col[t], need, a0);
+#pragma unroll
+            for (int w = 0; w < W; w++) acc[w] |= a0[w];
+            scanned += 1;
+        }
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const uint64_t r = wave_or64_dpp(acc[w]) & ~sh[w];
+            if (lane == 0 && r) atomicOr((unsigned long long*)&NX[h * W + w], (unsigned long long)r);
+        }
+    }
+    wc.arcs = scanned;
+    flush_counts(wc, cnt);
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_group_level(
+    const uint32_t* __restrict__ rp, const int32_t* __restrict__ col, const uint32_t* __restrict__ out_rp,
+    const uint64_t* __restrict__ Sprev, uint64_t* __restrict__ Scur, uint64_t* __restrict__ snap,
+    int32_t* __restrict__ fill_level, uint8_t* __restrict__ gfull, int32_t* __restrict__ chg, int32_t ngroups,
+    int64_t n, int64_t nh, uint64_t* __restrict__ NX, int pull, uint64_t lastmask, int32_t level,
+    const int32_t* __restrict__ sidx, int32_t* __restrict__ hist, int64_t hlen, int64_t k, int32_t src_base,
+    LevelCounters* __restrict__ cnt) {
+    __shared__ uint64_t lds_acc[kWaves][64][W];
+    __shared__ int32_t lds_hist[W * 64];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const bool do_hist = hist != nullptr;
+    if (do_hist) {
+        for (int t = threadIdx.x; t < W * 64; t += kBlock) lds_hist[t] = 0;
+        __syncthreads();
+    }
+    int32_t hcnt[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) hcnt[w] = 0;
+    WaveCounts wc;
+
+    const int32_t stride = gridDim.x * kWaves;
+    for (int32_t g = blockIdx.x * kWaves + wave; g < ngroups; g += stride) {
+        if (gfull[g]) continue;  // every node of the group is full in every later mask
+        const int64_t v = (int64_t)g * 64 + lane;
+        const bool valid = v < n;
+        uint64_t sv[W];
+        if (valid) {
+            load_mask<W>(Sprev, v, 0xFu, sv);
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; w++) sv[w] = full_word<W>(w, lastmask);
+        }
+        const uint32_t need = pairs_needed<W>(sv, lastmask);
+        const bool fullv = need == 0;
+        const bool ishub = v < nh;
+        uint64_t acc[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) acc[w] = 0;
+
+        if (pull) {
+            uint32_t rb = 0, deg = 0;
+            if (valid && !ishub && !fullv) {
+                rb = rp[v];
+                deg = rp[v + 1] - rb;
+            }
+            uint32_t maxdeg = deg;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint32_t o = (uint32_t)__shfl_xor((int)maxdeg, off);
+                maxdeg = o > maxdeg ? o : maxdeg;
+            }
+            if (maxdeg > 0) {
+                // G = 2^lg lanes per node, about maxdeg/G >= 2 arcs per lane
+                int lg = 0;
+                while (lg < 3 && (2u << lg) <= maxdeg / 2) lg++;
+                const int G = 1 << lg;
+                const int npp = 64 >> lg;
+                const int sub = lane & (G - 1);
+                const int slot = lane >> lg;
+                int64_t scanned = 0;
+                for (int pass = 0; pass < G; pass++) {
+                    const int r = pass * npp + slot;
+                    const uint32_t b = (uint32_t)__shfl((int)rb, r);
+                    const uint32_t dg = (uint32_t)__shfl((int)deg, r);
+                    const uint32_t nd = (uint32_t)__shfl((int)need, r);
+                    uint64_t x[W];
+#pragma unroll
+                    for (int w = 0; w < W; w++) x[w] = 0;
+                    uint32_t t = sub;
+                    for (; t + G < dg; t += 2 * G) {
+                        const int64_t u0 = col[b + t], u1 = col[b + t + G];
+                        uint64_t a0[W], a1[W];
+                        load_mask<W>(Sprev, u0, nd, a0);
+                        load_mask<W>(Sprev, u1, nd, a1);
+#pragma unroll
+                        for (int w = 0; w < W; w++) x[w] |= a0[w] | a1[w];
+                        scanned += 2;
+                    }
+                    if (t < dg) {
+                        uint64_t a0[W];
+                        load_mask<W>(Sprev, col[b + t], nd, a0);
+#pragma unroll
+                        for (int w = 0; w < W; w++) x[w] |= a0[w];
+                        scanned += 1;
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; w++) x[w] = dpp_or_group64(x[w], lg);
+                    if (sub == 0) {
+#pragma unroll
+                        for (int w = 0; w < W; w++) lds_acc[wave][r][w] = x[w];
+                    }
+                }
+                wc.arcs += scanned;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+                for (int w = 0; w < W; w++) acc[w] = lds_acc[wave][lane][w];
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (valid && !fullv && (!pull || ishub)) {
+            uint64_t nx[W];
+            load_mask<W>(NX, v, 0xFu, nx);
+            bool nz = false;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                acc[w] |= nx[w];
+                nz = nz || nx[w] != 0;
+            }
+            if (nz) {
+                const uint64_t zero[W] = {};
+                store_mask<W>(NX, v, zero);  // ready for the next level
+            }
+        }
+
+        uint64_t nw[W], sn[W];
+        bool anynew = false;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            nw[w] = (valid && !fullv) ? (acc[w] & ~sv[w]) : 0ull;
+            sn[w] = sv[w] | nw[w];
+            anynew = anynew || (nw[w] != 0);
+        }
+        if (valid) {
+            store_mask<W>(Scur, v, sn);
+            store_mask<W>(snap, v, sn);
+        }
+        if (anynew) {
+            chg[v] = level;
+            wc.farcs += out_rp[v + 1] - out_rp[v];
+        }
+        wc.n_new += (int32_t)__popcll(__ballot(anynew));
+        const bool active = __ballot(valid && !fullv) != 0;
+        if (lane == 0) {
+            fill_level[g] = level;
+            if (!active) gfull[g] = 1;  // all full at the start of this level; masks written full
+        }
+        if (active && lane == 0) wc.n_out += 1;
+
+        // histogram: lane j accumulates, for word w, how many non-sampled
+        // nodes of the group gained bit w*64+j at this level
+        if (do_hist) {
+            const bool counted = anynew && sidx[v] < 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                const uint64_t x = counted ? nw[w] : 0ull;
+                if (!__ballot(x != 0)) continue;
+                for (int j = 0; j < 64; j++) {
+                    const int c = (int)__popcll(__ballot((x >> j) & 1ull));
+                    if (lane == j) hcnt[w] += c;
+                }
+            }
+        }
+    }
+
+    flush_counts(wc, cnt);
+    if (do_hist) {
+#pragma unroll
+        for (int w = 0; w < W; w++)
+            if (hcnt[w]) atomicAdd(&lds_hist[w * 64 + lane], hcnt[w]);
+        __syncthreads();
+        const int32_t slot = blockIdx.x % kHistSlotsBatched;
+        for (int t = threadIdx.x; t < W * 64; t += kBlock) {
+            const int32_t c = lds_hist[t];
+            if (c) atomicAdd(&hist[((int64_t)slot * k + src_base + t) * hlen + level], c);
+        }
     }
 }
 
 __global__ void k_zero_counters(LevelCounters* c) {
-    if (threadIdx.x == 0) {
-        c->n_out = 0;
-        c->n_new = 0;
-        c->arcs = 0;
-        c->frontier_arcs = 0;
-        c->matched = 0;
-    }
+    const int t = threadIdx.x;
+    if (t < kCounterSlots) c[t] = LevelCounters{};
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-template <int W, typename DT>
-int bfs_batched_t(hipStream_t st, const uint32_t* in_rp, const int32_t* in_col, int64_t n,
-                  const int32_t* samples_dev, int32_t kg, int32_t src_base, int32_t k, DT* D, void* scratch,
-                  LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats) {
+inline void read_counters(hipStream_t st, LevelCounters* dev, LevelCounters* host, LevelCounters& sum) {
+    CCG_HIP(hipMemcpyAsync(host, dev, sizeof(LevelCounters) * kCounterSlots, hipMemcpyDeviceToHost, st));
+    CCG_HIP(hipStreamSynchronize(st));
+    sum_counters(host, kCounterSlots, sum);
+}
+
+template <int W>
+int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
+                  int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, LevelCounters* cnt_dev,
+                  LevelCounters* cnt_host, TravStats* stats) {
+    const int64_t n = gv.n;
+    const int32_t ngroups = (int32_t)((n + 63) / 64);
     char* p = (char*)scratch;
     uint64_t* S0 = (uint64_t*)p;
     p += align256(sizeof(uint64_t) * n * W);
     uint64_t* S1 = (uint64_t*)p;
     p += align256(sizeof(uint64_t) * n * W);
-    DT* st0 = (DT*)p;
-    p += align256(sizeof(DT) * n);
-    DT* st1 = (DT*)p;
-    p += align256(sizeof(DT) * n);
-    int32_t* act0 = (int32_t*)p;
+    uint64_t* NX = (uint64_t*)p;
+    p += align256(sizeof(uint64_t) * n * W);
+    int32_t* chg = (int32_t*)p;
     p += align256(sizeof(int32_t) * n);
-    int32_t* act1 = (int32_t*)p;
+    uint8_t* gfull = (uint8_t*)p;
 
+    const size_t plane = (size_t)n * W;
     const int rem = kg - (W - 1) * 64;
     const uint64_t lastmask = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
-    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_init_nodes<W, DT>), dim3(nb), dim3(kBlock), 0, st, n, S0, st0, st1, act0);
-    hipLaunchKernelGGL((k_init_samples<W, DT>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, S0, st0,
-                       D, (int64_t)k, src_base);
-    stats->launches += 2;
+    const int64_t nmax = std::max<int64_t>(n, ngroups);
+    hipLaunchKernelGGL((k_init<W>), dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, ngroups,
+                       S0, out.snap, NX, chg, gfull, out.fill_level);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
+    hipLaunchKernelGGL((k_init_samples<W>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, src_base, S0,
+                       out.snap, chg, gv.out_rp, cnt_dev);
+    LevelCounters sum;
+    read_counters(st, cnt_dev, cnt_host, sum);
+    stats->launches += 3;
 
-    int32_t n_act = (int32_t)n;
+    int64_t frontier_arcs = sum.frontier_arcs;
+    int64_t pull_arcs = gv.arcs;  // arcs a pull level would scan (refreshed after each pull)
     uint64_t* Sp = S0;
     uint64_t* Sc = S1;
-    DT* sp = st0;
-    DT* sc = st1;
-    int32_t* ain = act0;
-    int32_t* aout = act1;
     KernelTimer kt;
-    for (uint32_t level = 1;; ++level) {
-        if ((int64_t)level > DistT<DT>::max_level) return 1;  // distance type too narrow
-        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, cnt_dev);
-        const unsigned g = (unsigned)((n_act + kBlock - 1) / kBlock);
+    int32_t lmax = 0;
+    const unsigned gb = (unsigned)std::min<int64_t>((ngroups + kWaves - 1) / kWaves, 2048);
+    for (int32_t level = 1;; ++level) {
+        if (level >= out.cap) return 1;  // level-mask capacity exhausted: retry with more levels
+        const int pull = frontier_arcs * 4 >= pull_arcs ? 1 : 0;
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
         kt.start(st);
-        hipLaunchKernelGGL((k_pull_level<W, DT>), dim3(g), dim3(kBlock), 0, st, in_rp, in_col, Sp, Sc, sp, sc,
-                           ain, n_act, aout, D, (int64_t)k, src_base, lastmask, level, cnt_dev);
+        if (!pull) {
+            hipLaunchKernelGGL((k_push<W>), dim3(gb), dim3(kBlock), 0, st, gv.out_rp, gv.out_col, chg, gfull, n, ngroups,
+                               level - 1, Sp, NX, cnt_dev);
+        } else if (gv.n_hub_chunks > 0) {
+            const int64_t hb = std::min<int64_t>((gv.n_hub_chunks + kWaves - 1) / kWaves, 4096);
+            hipLaunchKernelGGL((k_hub_level<W>), dim3((unsigned)hb), dim3(kBlock), 0, st, gv.col, Sp, gv.hub_chunks,
+                               gv.n_hub_chunks, NX, lastmask, cnt_dev);
+        }
+        hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp, Sc,
+                           out.snap + (size_t)level * plane, out.fill_level, gfull, chg, ngroups, n, gv.nh, NX, pull,
+                           lastmask, level, sidx, out.hist, out.hlen, (int64_t)k, src_base, cnt_dev);
         CCG_HIP(hipGetLastError());
         kt.stop(st);
-        CCG_HIP(hipMemcpyAsync(cnt_host, cnt_dev, sizeof(LevelCounters), hipMemcpyDeviceToHost, st));
-        CCG_HIP(hipStreamSynchronize(st));
+        read_counters(st, cnt_dev, cnt_host, sum);
         stats->kernel_ms += kt.ms();
         stats->kernel_launches += 1;
-        stats->arcs_matched += cnt_host->matched;
-        stats->launches += 1;
+        stats->launches += 3;
         stats->levels += 1;
-        stats->arcs_scanned += cnt_host->arcs;
-        stats->nodes_visited += n_act;
-        if (cnt_host->n_new > 0 && (int64_t)level > stats->maxd) stats->maxd = level;
-        n_act = cnt_host->n_out;
-        if (n_act == 0) break;
-        if (cnt_host->n_new == 0) return 2;  // nodes left that no sample can reach
+        stats->arcs_scanned += sum.arcs;
+        stats->nodes_visited += (int64_t)sum.n_out * 64;
+        if (pull) {
+            stats->pull_levels += 1;
+            pull_arcs = std::max<int64_t>(sum.arcs, 1);
+        } else {
+            stats->push_arcs += sum.arcs;
+        }
+        if (sum.n_new > 0) lmax = level;
+        frontier_arcs = sum.frontier_arcs;
+        if (sum.n_out == 0) break;             // every node full at the start of this level
+        if (sum.n_new == 0) return 2;          // nodes left that no sample can reach
         std::swap(Sp, Sc);
-        std::swap(sp, sc);
-        std::swap(ain, aout);
     }
+    if (lmax > stats->maxd) stats->maxd = lmax;
+    *out.lmax = std::max(*out.lmax, lmax);
     return 0;
-}
-
-template <int W>
-int dispatch_dt(hipStream_t st, const uint32_t* in_rp, const int32_t* in_col, int64_t n, const int32_t* samples_dev,
-                int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, void* scratch,
-                LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats) {
-    switch (dk) {
-        case DistKind::U8:
-            return bfs_batched_t<W, uint8_t>(st, in_rp, in_col, n, samples_dev, kg, src_base, k, (uint8_t*)D, scratch,
-                                             cnt_dev, cnt_host, stats);
-        case DistKind::U16:
-            return bfs_batched_t<W, uint16_t>(st, in_rp, in_col, n, samples_dev, kg, src_base, k, (uint16_t*)D,
-                                              scratch, cnt_dev, cnt_host, stats);
-        default:
-            return bfs_batched_t<W, uint32_t>(st, in_rp, in_col, n, samples_dev, kg, src_base, k, (uint32_t*)D,
-                                              scratch, cnt_dev, cnt_host, stats);
-    }
 }
 
 }  // namespace
 
-size_t bfs_batched_scratch(int64_t n, int32_t kg) {
+size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh) {
+    (void)nh;
     const int W = (kg + 63) / 64;
-    return align256(sizeof(uint64_t) * n * W) * 2 + align256(sizeof(uint32_t) * n) * 2 +
-           align256(sizeof(int32_t) * n) * 2 + 1024;
+    const int64_t ngroups = (n + 63) / 64;
+    return align256(sizeof(uint64_t) * n * W) * 3 + align256(sizeof(int32_t) * n) + align256((size_t)ngroups) + 1024;
 }
 
-// Returns through the bool: false = the distance type overflowed.  A
-// disconnected graph sets flags->disconnected (host-visible copy is made by
-// the caller) -- here signalled by writing to the device flag word.
-bool bfs_batched(hipStream_t st, const uint32_t* in_rp, const int32_t* in_col, int64_t n,
-                 const int32_t* samples_dev, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk,
-                 void* scratch, size_t scratch_size, DevFlags* flags, LevelCounters* cnt_dev,
-                 LevelCounters* cnt_host, TravStats* stats) {
-    if (scratch_size < bfs_batched_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "bfs_batched scratch"};
+int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
+                int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, size_t scratch_size,
+                LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats) {
+    if (scratch_size < bfs_batched_scratch(gv.n, kg, gv.nh)) throw HipError{hipErrorOutOfMemory, "bfs_batched scratch"};
     const int W = (kg + 63) / 64;
-    int r;
     switch (W) {
-        case 1: r = dispatch_dt<1>(st, in_rp, in_col, n, samples_dev, kg, src_base, k, D, dk, scratch, cnt_dev, cnt_host, stats); break;
-        case 2: r = dispatch_dt<2>(st, in_rp, in_col, n, samples_dev, kg, src_base, k, D, dk, scratch, cnt_dev, cnt_host, stats); break;
-        case 3: r = dispatch_dt<3>(st, in_rp, in_col, n, samples_dev, kg, src_base, k, D, dk, scratch, cnt_dev, cnt_host, stats); break;
-        default: r = dispatch_dt<4>(st, in_rp, in_col, n, samples_dev, kg, src_base, k, D, dk, scratch, cnt_dev, cnt_host, stats); break;
+        case 1: return bfs_batched_t<1>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
+        case 2: return bfs_batched_t<2>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
+        case 3: return bfs_batched_t<3>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
+        default: return bfs_batched_t<4>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
     }
-    if (r == 1) return false;
-    if (r == 2) {
-        int32_t one = 1;
-        CCG_HIP(hipMemcpyAsync(&flags->disconnected, &one, sizeof(one), hipMemcpyHostToDevice, st));
-        CCG_HIP(hipStreamSynchronize(st));
-    }
-    return true;
 }
 
 }  // namespace ccg

@@ -147,7 +147,8 @@ struct Carver {
 struct Lane {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    Arena arena;      // distances, traversal state, per-job small buffers
+    Arena arena;      // per-job small buffers and traversal state
+    Arena arenaD;     // distance matrices / level masks
     Arena arena2;     // epilogue tables (sized once the largest distance is known)
     LevelCounters* cnt_host = nullptr;  // pinned
     hipEvent_t ev[4] = {};
@@ -158,7 +159,7 @@ struct Lane {
             CCG_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
             own_stream = true;
         }
-        CCG_HIP(hipHostMalloc((void**)&cnt_host, sizeof(LevelCounters), hipHostMallocDefault));
+        CCG_HIP(hipHostMalloc((void**)&cnt_host, sizeof(LevelCounters) * kCounterSlots, hipHostMallocDefault));
         for (auto& e : ev) CCG_HIP(hipEventCreate(&e));
     }
     void destroy() {
@@ -180,8 +181,9 @@ struct cc_graph {
     DevGraph dg;
     uint32_t flags = 0;
     std::atomic<int> refs{1};
-    void* mem[6] = {};
+    void* mem[10] = {};
     size_t bytes = 0;
+    std::vector<int32_t> inv;  // caller's id -> internal id
 };
 
 struct cc_job {
@@ -339,6 +341,44 @@ static bool check_csr(int64_t n, int64_t arcs, const int64_t* rp, const int32_t*
     return true;
 }
 
+// Graph builder: internal ids sort nodes by degree (out + in), largest first,
+// ties by the caller's id, so that consecutive ids have similar degree (one
+// traversal wave handles 64 consecutive ids) and the high-degree nodes form a
+// prefix whose adjacency is cut into fixed chunks of arcs.
+namespace {
+constexpr uint32_t kHubDegree = 32;    // in-degree above which a node's arcs are scanned in chunks
+constexpr uint32_t kHubChunk = 1024;   // arcs per chunk
+
+std::vector<int32_t> hub_chunk_list(const std::vector<uint32_t>& rp, int64_t nh) {
+    std::vector<int32_t> c;
+    for (int64_t h = 0; h < nh; h++)
+        for (uint32_t b = rp[(size_t)h]; b < rp[(size_t)h + 1]; b += kHubChunk) {
+            c.push_back((int32_t)h);
+            c.push_back((int32_t)b);
+            c.push_back((int32_t)std::min<uint32_t>(b + kHubChunk, rp[(size_t)h + 1]));
+        }
+    return c;
+}
+
+void transpose_host(int64_t n, const std::vector<uint32_t>& rp, const std::vector<int32_t>& col,
+                    const std::vector<int32_t>& w, std::vector<uint32_t>& trp, std::vector<int32_t>& tcol,
+                    std::vector<int32_t>& tw) {
+    const size_t arcs = col.size();
+    trp.assign((size_t)n + 1, 0);
+    for (size_t e = 0; e < arcs; e++) trp[(size_t)col[e] + 1]++;
+    for (int64_t v = 0; v < n; v++) trp[(size_t)v + 1] += trp[(size_t)v];
+    std::vector<uint32_t> pos(trp.begin(), trp.end() - 1);
+    tcol.resize(arcs);
+    tw.resize(w.empty() ? 0 : arcs);
+    for (int64_t u = 0; u < n; u++)
+        for (uint32_t e = rp[(size_t)u]; e < rp[(size_t)u + 1]; e++) {
+            const uint32_t q = pos[(size_t)col[e]]++;
+            tcol[q] = (int32_t)u;
+            if (!w.empty()) tw[q] = w[e];
+        }
+}
+}  // namespace
+
 extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, const int64_t* row_ptr,
                                      const int32_t* col_idx, const int32_t* w, uint32_t flags, cc_graph** out) {
     if (!ctx || !out || !row_ptr || (arcs > 0 && !col_idx)) return fail(CC_EINVAL, "cc_graph_upload: null argument");
@@ -363,8 +403,50 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
     g->dg.weighted = w != nullptr;
     try {
         CCG_HIP(hipSetDevice(ctx->device));
-        std::vector<uint32_t> rp32((size_t)n + 1);
-        for (int64_t v = 0; v <= n; v++) rp32[(size_t)v] = (uint32_t)row_ptr[v];
+        // ---- degree order
+        std::vector<int64_t> deg((size_t)n, 0);
+        for (int64_t v = 0; v < n; v++) deg[(size_t)v] = row_ptr[v + 1] - row_ptr[v];
+        if (directed)
+            for (int64_t e = 0; e < arcs; e++) deg[(size_t)col_idx[e]]++;
+        std::vector<int32_t> orig((size_t)n);
+        for (int64_t v = 0; v < n; v++) orig[(size_t)v] = (int32_t)v;
+        std::stable_sort(orig.begin(), orig.end(),
+                         [&](int32_t a, int32_t b) { return deg[(size_t)a] > deg[(size_t)b]; });
+        g->inv.assign((size_t)n, 0);
+        for (int64_t i = 0; i < n; i++) g->inv[(size_t)orig[(size_t)i]] = (int32_t)i;
+        // ---- relabelled out-arcs
+        std::vector<uint32_t> rp((size_t)n + 1, 0);
+        std::vector<int32_t> col((size_t)arcs), ww(w ? (size_t)arcs : 0);
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t v = orig[(size_t)i];
+            rp[(size_t)i + 1] = rp[(size_t)i] + (uint32_t)(row_ptr[v + 1] - row_ptr[v]);
+        }
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t v = orig[(size_t)i];
+            uint32_t q = rp[(size_t)i];
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++, q++) {
+                col[q] = g->inv[(size_t)col_idx[e]];
+                if (w) ww[q] = w[e];
+            }
+        }
+        std::vector<uint32_t> trp;
+        std::vector<int32_t> tcol, tw;
+        if (directed) transpose_host(n, rp, col, ww, trp, tcol, tw);
+        // ---- hub prefix (by in-degree of the pull direction; for digraphs by
+        //      the larger of the two, ids being sorted by total degree)
+        const std::vector<uint32_t>& prp = directed ? trp : rp;
+        int64_t hubs = 0;
+        for (int64_t i = 0; i < n; i++) {
+            const uint32_t din = prp[(size_t)i + 1] - prp[(size_t)i];
+            const uint32_t dout = rp[(size_t)i + 1] - rp[(size_t)i];
+            if (std::max(din, dout) > kHubDegree) hubs = i + 1;
+        }
+        int64_t nh = (hubs + 63) / 64 * 64;
+        if (nh > n) nh = n;
+        g->dg.nh = nh;
+        std::vector<int32_t> ch_in = hub_chunk_list(prp, nh);
+        std::vector<int32_t> ch_out = directed ? hub_chunk_list(rp, nh) : std::vector<int32_t>();
+
         auto up = [&](int slot, const void* src, size_t bytes) -> void* {
             void* d = nullptr;
             hipError_t e = hipMalloc(&d, bytes ? bytes : 4);
@@ -377,22 +459,10 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             if (bytes) CCG_HIP(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
             return d;
         };
-        g->dg.rp = (const uint32_t*)up(0, rp32.data(), sizeof(uint32_t) * (n + 1));
-        g->dg.col = (const int32_t*)up(1, col_idx, sizeof(int32_t) * arcs);
-        if (w) g->dg.w = (const int32_t*)up(2, w, sizeof(int32_t) * arcs);
+        g->dg.rp = (const uint32_t*)up(0, rp.data(), sizeof(uint32_t) * (n + 1));
+        g->dg.col = (const int32_t*)up(1, col.data(), sizeof(int32_t) * arcs);
+        if (w) g->dg.w = (const int32_t*)up(2, ww.data(), sizeof(int32_t) * arcs);
         if (directed) {
-            // transpose on the host (counting sort by target), lists stay sorted by source
-            std::vector<uint32_t> trp((size_t)n + 1, 0);
-            for (int64_t e = 0; e < arcs; e++) trp[(size_t)col_idx[e] + 1]++;
-            for (int64_t v = 0; v < n; v++) trp[(size_t)v + 1] += trp[(size_t)v];
-            std::vector<uint32_t> pos(trp.begin(), trp.end() - 1);
-            std::vector<int32_t> tcol((size_t)arcs), tw(w ? (size_t)arcs : 0);
-            for (int64_t u = 0; u < n; u++)
-                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
-                    const uint32_t q = pos[(size_t)col_idx[e]]++;
-                    tcol[q] = (int32_t)u;
-                    if (w) tw[q] = w[e];
-                }
             g->dg.rrp = (const uint32_t*)up(3, trp.data(), sizeof(uint32_t) * (n + 1));
             g->dg.rcol = (const int32_t*)up(4, tcol.data(), sizeof(int32_t) * arcs);
             if (w) g->dg.rw = (const int32_t*)up(5, tw.data(), sizeof(int32_t) * arcs);
@@ -400,6 +470,16 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             g->dg.rrp = g->dg.rp;
             g->dg.rcol = g->dg.col;
             g->dg.rw = g->dg.w;
+        }
+        g->dg.orig = (const int32_t*)up(6, orig.data(), sizeof(int32_t) * n);
+        g->dg.hub_chunks_in = (const int32_t*)up(7, ch_in.data(), sizeof(int32_t) * ch_in.size());
+        g->dg.n_hub_chunks_in = (int32_t)(ch_in.size() / 3);
+        if (directed) {
+            g->dg.hub_chunks_out = (const int32_t*)up(8, ch_out.data(), sizeof(int32_t) * ch_out.size());
+            g->dg.n_hub_chunks_out = (int32_t)(ch_out.size() / 3);
+        } else {
+            g->dg.hub_chunks_out = g->dg.hub_chunks_in;
+            g->dg.n_hub_chunks_out = g->dg.n_hub_chunks_in;
         }
     } catch (const std::bad_alloc&) {
         graph_unref(g);
@@ -474,72 +554,144 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-// Device bytes one job needs (excluding the caller's outputs).
+// Device bytes one job needs (excluding the caller's outputs), for admission.
 size_t job_bytes(const DevGraph& g, int32_t k, int32_t mode, int db) {
     const int64_t n = g.n;
-    size_t b = Carver::sz(sizeof(int32_t) * k) + Carver::sz(sizeof(DevFlags)) + Carver::sz(sizeof(LevelCounters));
     const size_t dbytes = Carver::sz((size_t)n * k * db);
-    b += dbytes * (g.directed ? 2 : 1);
-    size_t trav;
+    size_t b = Carver::sz(sizeof(int32_t) * k) * 2 + Carver::sz(sizeof(DevFlags)) + Carver::sz(sizeof(LevelCounters) * kCounterSlots) +
+               Carver::sz(sizeof(int32_t) * n);
     if (g.weighted) {
-        trav = mode == CC_PLAIN ? dbytes + sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
+        b += dbytes * (g.directed ? 2 : 1);
+        b += mode == CC_PLAIN ? dbytes + sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
+    } else if (mode == CC_PLAIN) {
+        b += dbytes * (g.directed ? 3 : 2) + bfs_plain_scratch(n);
     } else {
-        trav = mode == CC_PLAIN ? dbytes + bfs_plain_scratch(n) : bfs_batched_scratch(n, std::min(k, 256));
+        const int32_t kg = std::min(k, 256);
+        b += bfs_batched_scratch(n, kg, g.nh) + (size_t)32 * n * ((kg + 63) / 64) * 8;
+        if (g.directed || k > 256) b += dbytes * (g.directed ? 2 : 1);
     }
-    // epilogue with a generous distance bound is sized after the traversal;
-    // reserve the BFS-sized part here
-    b += trav;
     b += Carver::sz(sizeof(int64_t) * k) + Carver::sz(sizeof(int32_t) * (size_t)k * k);
     return b;
 }
 
-// Runs the whole pipeline on lane `L`; `out` holds DEVICE pointers.
+void record_timing(cc_timing* timing, Lane& L, const TravStats& stats, int db) {
+    if (!timing) return;
+    timing->traverse_ms = elapsed(L.ev[0], L.ev[1]);
+    timing->epilogue_ms = elapsed(L.ev[1], L.ev[2]);
+    timing->total_ms = elapsed(L.ev[0], L.ev[2]);
+    timing->levels = stats.levels;
+    timing->arcs_scanned = stats.arcs_scanned;
+    timing->nodes_visited = stats.nodes_visited;
+    timing->launches = stats.launches;
+    timing->dist_bytes = db;
+    timing->kernel_ms = stats.kernel_ms;
+    timing->kernel_launches = stats.kernel_launches;
+    timing->arcs_matched = stats.push_arcs;
+}
+
+void add_stats(TravStats& a, const TravStats& b) {
+    a.levels += b.levels;
+    a.arcs_scanned += b.arcs_scanned;
+    a.nodes_visited += b.nodes_visited;
+    a.launches += b.launches;
+    a.arcs_matched += b.arcs_matched;
+    a.kernel_ms += b.kernel_ms;
+    a.kernel_launches += b.kernel_launches;
+    a.pull_levels += b.pull_levels;
+    a.push_arcs += b.push_arcs;
+    a.maxd = std::max(a.maxd, b.maxd);
+}
+
+cc_status finish_flags(const DevFlags& hf) {
+    if (hf.disconnected) return fail(CC_EDISCONNECTED, "some node is unreachable from some sample");
+    if (hf.overflow) return fail(CC_EOVERFLOW, "an estimate numerator reached 2^53");
+    if (hf.bad_sample) return fail(CC_EINVAL, "bad sample");
+    if (hf.timeout) return fail(CC_EDEVICE, "a bounded device wait expired");
+    return CC_OK;
+}
+
+void fill_epilogue_outputs(EpilogueArgs& ea, const cc_result* out, int64_t* src_sum, int32_t* dmat) {
+    ea.S_hyb = out->S_hyb;
+    ea.S_samp = out->S_samp;
+    ea.S_piv = out->S_piv;
+    ea.S_pub = out->S_pub;
+    ea.pivot = out->pivot;
+    ea.delta = out->delta;
+    ea.sampsum = out->sampsum;
+    ea.src_sum = src_sum;
+    ea.dmat = dmat;
+    ea.Dout = out->D;
+}
+
+// Runs the whole pipeline on lane `L`; `out` holds DEVICE pointers (caller's node ids).
 cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const cc_result* out, Lane& L,
                   cc_timing* timing) {
+    (void)ctx;
     const DevGraph& g = gr->dg;
     const int64_t n = g.n;
     const int32_t k = r.k;
+    const int32_t ngroups = (int32_t)((n + 63) / 64);
     hipStream_t st = L.stream;
-    TravStats stats;
+    std::vector<int32_t> samples_int((size_t)k);
+    for (int32_t i = 0; i < k; i++) samples_int[(size_t)i] = gr->inv[(size_t)r.samples[(size_t)i]];
 
-    std::vector<DistKind> kinds;
-    if (g.weighted) kinds = {DistKind::U32};
-    else kinds = {DistKind::U8, DistKind::U16, DistKind::U32};
+    // small per-job buffers
+    const size_t small = Carver::sz(sizeof(int32_t) * k) + Carver::sz(sizeof(DevFlags)) +
+                         Carver::sz(sizeof(LevelCounters) * kCounterSlots) + Carver::sz(sizeof(int32_t) * n) +
+                         Carver::sz(sizeof(int64_t) * k) + Carver::sz(sizeof(int32_t) * (size_t)k * k) +
+                         Carver::sz(sizeof(int32_t) * ngroups);
+    const int32_t kg0 = std::min(k, 256);
+    const int Wg = (kg0 + 63) / 64;
+    // level masks take cap * n * W words; deep graphs whose masks would not fit
+    // this budget are traversed one sample at a time instead
+    size_t free_b = 0, total_b = 0;
+    CCG_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t mask_budget = std::min<size_t>(free_b / 3, (size_t)32 << 30);
+    int32_t mode = r.mode;
 
-    for (DistKind dk : kinds) {
-        const int db = (int)dk;
-        stats = TravStats();
-        // ---- layout
-        const size_t dbytes = (size_t)n * k * db;
+    int32_t cap = 32;              // level-mask capacity of the batched BFS
+    DistKind dk = g.weighted ? DistKind::U32 : DistKind::U8;
+    for (int attempt = 0; attempt < 16; attempt++) {
+        const bool batched = mode == CC_BATCHED && !g.weighted;
+        const bool bits_path = batched && !g.directed && k <= 256;
+        TravStats stats;
+        const size_t dbytes = (size_t)n * k * (int)dk;
         size_t trav_scratch;
         if (g.weighted)
-            trav_scratch = r.mode == CC_PLAIN ? sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
+            trav_scratch = mode == CC_PLAIN ? sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
         else
-            trav_scratch = r.mode == CC_PLAIN ? bfs_plain_scratch(n) : bfs_batched_scratch(n, std::min(k, 256));
-        const size_t fixed = Carver::sz(sizeof(int32_t) * k) + Carver::sz(sizeof(DevFlags)) +
-                             Carver::sz(sizeof(LevelCounters)) + Carver::sz(dbytes) * (g.directed ? 2 : 1) +
-                             (r.mode == CC_PLAIN ? Carver::sz(dbytes) : 0) + Carver::sz(trav_scratch) +
-                             Carver::sz(sizeof(int64_t) * k) + Carver::sz(sizeof(int32_t) * (size_t)k * k);
-        void* base = L.arena.get(fixed);
-        Carver c(base);
+            trav_scratch = mode == CC_PLAIN ? bfs_plain_scratch(n) : bfs_batched_scratch(n, kg0, g.nh);
+        const size_t hist_elems = bits_path ? (size_t)kHistSlotsBatched * k * cap : 0;
+        Carver c(L.arena.get(small + Carver::sz(trav_scratch) + Carver::sz(sizeof(int32_t) * hist_elems)));
         int32_t* samples_dev = c.take<int32_t>(k);
         DevFlags* flags = c.take<DevFlags>(1);
-        LevelCounters* cnt = c.take<LevelCounters>(1);
-        void* D = c.take<char>(dbytes);
-        void* Dr = g.directed ? c.take<char>(dbytes) : nullptr;
-        void* Dt = r.mode == CC_PLAIN ? c.take<char>(dbytes) : nullptr;
-        void* ts = c.take<char>(trav_scratch);
+        LevelCounters* cnt = c.take<LevelCounters>(kCounterSlots);
+        int32_t* sidx = c.take<int32_t>(n);
         int64_t* src_sum = out->src_sum ? out->src_sum : c.take<int64_t>(k);
         int32_t* dmat = out->dmat ? out->dmat : c.take<int32_t>((size_t)k * k);
+        int32_t* fill_level = c.take<int32_t>(ngroups);
+        void* ts = c.take<char>(trav_scratch);
+        int32_t* hist = bits_path ? c.take<int32_t>(hist_elems) : nullptr;
+        // distance matrices and/or level masks
+        const size_t snap_bytes = batched ? Carver::sz((size_t)cap * n * Wg * 8) : 0;
+        const size_t need_D = (bits_path ? 0 : Carver::sz(dbytes) * (g.directed ? 2 : 1)) +
+                              (mode == CC_PLAIN ? Carver::sz(dbytes) : 0);
+        Carver cd(L.arenaD.get(snap_bytes + need_D + 256));
+        uint64_t* snap = batched ? cd.take<uint64_t>((size_t)cap * n * Wg) : nullptr;
+        void* D = bits_path ? nullptr : cd.take<char>(dbytes);
+        void* Dr = (!bits_path && g.directed) ? cd.take<char>(dbytes) : nullptr;
+        void* Dt = mode == CC_PLAIN ? cd.take<char>(dbytes) : nullptr;
 
-        CCG_HIP(hipMemcpyAsync(samples_dev, r.samples.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+        CCG_HIP(hipMemcpyAsync(samples_dev, samples_int.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
         fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
         CCG_HIP(hipEventRecord(L.ev[0], st));
+        compute_sidx(st, samples_dev, k, sidx, n);
+        if (hist) fill_u32(st, hist, 0u, hist_elems);
 
         // ---- traversal
-        bool ok = true;
-        int64_t maxd_f = 0, maxd_r = 0;
-        for (int dir = 0; dir < (g.directed ? 2 : 1) && ok; dir++) {
+        int rc = 0;
+        int32_t lmax_dir[2] = {0, 0};
+        for (int dir = 0; dir < (g.directed ? 2 : 1) && rc == 0; dir++) {
             // forward distances d(c_i -> v): push over out-arcs, pull over in-arcs;
             // reverse distances d(v -> c_i): the same on the transposed graph
             const uint32_t* out_rp = dir == 0 ? g.rp : g.rrp;
@@ -550,87 +702,121 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             TravStats ds;
             if (g.weighted) {
                 throw HipError{hipErrorNotSupported, "weighted traversal not built yet"};
-            } else if (r.mode == CC_PLAIN) {
-                ok = bfs_plain(st, out_rp, out_col, in_rp, in_col, n, g.arcs, r.samples.data(), k, Dt, dk, ts,
-                               trav_scratch, flags, cnt, L.cnt_host, &ds);
+            } else if (mode == CC_PLAIN) {
+                const bool ok = bfs_plain(st, out_rp, out_col, in_rp, in_col, n, g.arcs, samples_int.data(), k, Dt,
+                                          dk, ts, trav_scratch, flags, cnt, L.cnt_host, &ds);
+                rc = ok ? 0 : 3;
                 if (ok) transpose_dist(st, Dt, Dd, n, k, dk);
+                lmax_dir[dir] = (int32_t)ds.maxd;
             } else {
-                for (int32_t s0 = 0; s0 < k && ok; s0 += 256) {
+                BfsView gv;
+                gv.n = n;
+                gv.arcs = g.arcs;
+                gv.rp = in_rp;
+                gv.col = in_col;
+                gv.out_rp = out_rp;
+                gv.out_col = out_col;
+                gv.nh = g.nh;
+                gv.hub_chunks = dir == 0 ? g.hub_chunks_in : g.hub_chunks_out;
+                gv.n_hub_chunks = dir == 0 ? g.n_hub_chunks_in : g.n_hub_chunks_out;
+                for (int32_t s0 = 0; s0 < k && rc == 0; s0 += 256) {
                     const int32_t kg = std::min(256, k - s0);
-                    ok = bfs_batched(st, in_rp, in_col, n, samples_dev, kg, s0, k, Dd, dk, ts, trav_scratch, flags,
-                                     cnt, L.cnt_host, &ds);
+                    int32_t lm = 0;
+                    BfsLevels lv;
+                    lv.snap = snap;
+                    lv.cap = cap;
+                    lv.fill_level = fill_level;
+                    lv.hist = hist;
+                    lv.hlen = cap;
+                    lv.lmax = &lm;
+                    rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, L.cnt_host,
+                                     &ds);
+                    if (rc != 0) break;
+                    lmax_dir[dir] = std::max(lmax_dir[dir], lm);
+                    if (!bits_path) {
+                        if ((int64_t)lm > DistT<uint8_t>::max_level && dk == DistKind::U8) { rc = 3; break; }
+                        if ((int64_t)lm > DistT<uint16_t>::max_level && dk == DistKind::U16) { rc = 3; break; }
+                        materialize_distances(st, snap, (size_t)n * ((kg + 63) / 64), lm, fill_level, n, kg, s0, k, Dd,
+                                              dk, flags);
+                    }
                 }
             }
-            (dir == 0 ? maxd_f : maxd_r) = ds.maxd;
-            stats.levels += ds.levels;
-            stats.arcs_scanned += ds.arcs_scanned;
-            stats.nodes_visited += ds.nodes_visited;
-            stats.launches += ds.launches;
-            stats.arcs_matched += ds.arcs_matched;
-            stats.kernel_ms += ds.kernel_ms;
-            stats.kernel_launches += ds.kernel_launches;
+            add_stats(stats, ds);
         }
-        if (!ok) continue;  // distance type too narrow: retry wider
+        if (rc == 1) {  // more levels than the mask buffer holds
+            cap = (int32_t)std::min<int64_t>((int64_t)cap * 4, n + 2);
+            if ((size_t)cap * n * Wg * 8 > mask_budget) mode = CC_PLAIN;
+            continue;
+        }
+        if (rc == 3) {  // distance type too narrow
+            if (dk == DistKind::U8) dk = DistKind::U16;
+            else if (dk == DistKind::U16) dk = DistKind::U32;
+            else return fail(CC_EOVERFLOW, "a distance does not fit in 32 bits");
+            continue;
+        }
         CCG_HIP(hipEventRecord(L.ev[1], st));
-
-        // ---- check traversal flags before the epilogue
         DevFlags hf;
         CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
         CCG_HIP(hipStreamSynchronize(st));
-        if (hf.bad_sample) return fail(CC_EINVAL, "bad sample");
-        if (hf.disconnected) return fail(CC_EDISCONNECTED, "some node is unreachable from some sample");
+        if (rc == 2 || hf.disconnected) return fail(CC_EDISCONNECTED, "some node is unreachable from some sample");
         if (hf.timeout) return fail(CC_EDEVICE, "traversal wait expired");
 
         // ---- epilogue
-        EpilogueArgs ea;
-        ea.n = n;
-        ea.k = k;
-        ea.dk = dk;
-        ea.D = D;
-        ea.Dr = Dr;
-        ea.samples = samples_dev;
-        ea.maxd = maxd_f + maxd_r;
-        ea.eps_num = r.en;
-        ea.eps_den = r.ed;
-        ea.S_hyb = out->S_hyb;
-        ea.S_samp = out->S_samp;
-        ea.S_piv = out->S_piv;
-        ea.S_pub = out->S_pub;
-        ea.pivot = out->pivot;
-        ea.delta = out->delta;
-        ea.sampsum = out->sampsum;
-        ea.src_sum = src_sum;
-        ea.dmat = dmat;
-        ea.Dout = out->D;
-        // the epilogue scratch is carved behind the traversal layout (the
-        // traversal scratch is dead by now and is reused)
-        const size_t es = epilogue_scratch(n, k, ea.maxd);
-        void* escr = es <= trav_scratch ? ts : L.arena2.get(es);
-        run_epilogue(st, ea, escr, es, flags);
+        if (bits_path) {
+            BitsEpilogueArgs ba;
+            ba.n = n;
+            ba.k = k;
+            ba.snap = snap;
+            ba.plane = (size_t)n * Wg;
+            ba.lmax = lmax_dir[0];
+            ba.fill_level = fill_level;
+            ba.samples = samples_dev;
+            ba.sidx = sidx;
+            ba.orig = g.orig;
+            ba.hist = hist;
+            ba.hist_slots = kHistSlotsBatched;
+            ba.hist_len = cap;
+            ba.eps_num = r.en;
+            ba.eps_den = r.ed;
+            ba.S_hyb = out->S_hyb;
+            ba.S_samp = out->S_samp;
+            ba.S_piv = out->S_piv;
+            ba.S_pub = out->S_pub;
+            ba.pivot = out->pivot;
+            ba.delta = out->delta;
+            ba.sampsum = out->sampsum;
+            ba.src_sum = src_sum;
+            ba.dmat = dmat;
+            ba.Dout = out->D;
+            const size_t es = bits_epilogue_scratch(k, ba.lmax);
+            run_bits_epilogue(st, ba, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
+        } else {
+            EpilogueArgs ea;
+            ea.n = n;
+            ea.k = k;
+            ea.dk = dk;
+            ea.D = D;
+            ea.Dr = Dr;
+            ea.samples = samples_dev;
+            ea.sidx = sidx;
+            ea.orig = g.orig;
+            ea.maxd = (int64_t)lmax_dir[0] + lmax_dir[1];
+            ea.eps_num = r.en;
+            ea.eps_den = r.ed;
+            fill_epilogue_outputs(ea, out, src_sum, dmat);
+            const size_t es = epilogue_scratch(n, k, ea.maxd, false);
+            run_epilogue(st, ea, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
+        }
         if (out->samples)
-            CCG_HIP(hipMemcpyAsync(out->samples, samples_dev, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, st));
+            CCG_HIP(hipMemcpyAsync(out->samples, r.samples.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
         CCG_HIP(hipEventRecord(L.ev[2], st));
         CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
         CCG_HIP(hipStreamSynchronize(st));
-        if (timing) {
-            timing->traverse_ms = elapsed(L.ev[0], L.ev[1]);
-            timing->epilogue_ms = elapsed(L.ev[1], L.ev[2]);
-            timing->total_ms = elapsed(L.ev[0], L.ev[2]);
-            timing->levels = stats.levels;
-            timing->arcs_scanned = stats.arcs_scanned;
-            timing->nodes_visited = stats.nodes_visited;
-            timing->launches = stats.launches;
-            timing->dist_bytes = db;
-            timing->kernel_ms = stats.kernel_ms;
-            timing->kernel_launches = stats.kernel_launches;
-            timing->arcs_matched = stats.arcs_matched;
-        }
-        if (hf.disconnected) return fail(CC_EDISCONNECTED, "some node is unreachable from some sample");
-        if (hf.overflow) return fail(CC_EOVERFLOW, "an estimate numerator reached 2^53");
-        if (hf.bad_sample) return fail(CC_EINVAL, "bad sample");
-        return CC_OK;
+        record_timing(timing, L, stats, bits_path ? 0 : (int)dk);
+        if (timing) timing->levels = stats.levels;
+        return finish_flags(hf);
     }
-    return fail(CC_EOVERFLOW, "a distance does not fit in 32 bits");
+    return fail(CC_EDEVICE, "traversal did not settle after repeated resizing");
 }
 
 cc_status guarded(cc_context* ctx, const std::function<cc_status()>& fn) {

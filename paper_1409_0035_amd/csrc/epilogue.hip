@@ -1,20 +1,22 @@
 // Estimator epilogue: from the node-major distance matrix D[v][i] = d(c_i, v)
-// to every estimate of Sec. 2 of the paper, for every node.
+// (internal, degree-sorted node ids) to every estimate of Sec. 2 of the
+// paper, for every node, written at the caller's node ids.
 //
-//   k_reduce    one streaming pass over D: per-sample sums S(c_i) = sum_v D[v][i]
-//               (exact centrality of the samples) and, per sample, the histogram
-//               hist[i][d] = #{u not in C : d(c_i,u) = d}.
-//   k_dmat      sample-to-sample distances dmat[i][j] = d(c_i, c_j) = D[c_j][i].
+//   k_reduce    (when the traversal did not count it) per-sample histogram
+//               hist[i][d] = #{u not in C : d(c_i,u) = d}, one lane per node.
+//   k_dmat      sample-to-sample distances dmat[i][j] = d(c_i, c_j) = D[c_j][i],
+//               as int32 for the caller and in a compact width for k_estimate.
 //   k_suffix    per sample, T_cnt[i][t] = sum_{d >= t} hist[i][d] and
-//               T_sum[i][t] = sum_{d >= t} d * hist[i][d]: the tail counts and
-//               sums that Alg. 1 builds with its Thresh/bin arrays, here for
-//               every integer threshold at once.
-//   k_estimate  one wave per node: pivot (argmin of the row, lowest index on
-//               ties), Delta, sum of the row, split of the samples into L cap C
-//               and HC by dmat[pivot][i] * num <= Delta * den (eps = num/den),
-//               |H| and sum_H from the tail tables at t = floor(Delta*den/num)+1,
-//               |L| = n-1-|H|-|HC| (Alg. 1 finalisation), and Eq. (6) as the
-//               exact integer N = (sum_H + sum_HC)*|L cap C| + |L|*sum_{L cap C}
+//               T_sum[i][t] = sum_{d >= t} d * hist[i][d] -- the tail counts and
+//               sums Alg. 1 builds with its Thresh/bin arrays, here for every
+//               integer threshold -- and the exact sum of the sample,
+//               S(c_i) = T_sum[i][0] + sum_j dmat[i][j].
+//   k_estimate  one lane per node: pivot (argmin of the row, lowest index on
+//               ties), Delta, sum of the row; the samples split into L cap C
+//               and HC by dmat[pivot][i] * num <= Delta * den (eps = num/den);
+//               |H| and sum_H from the tail tables at floor(Delta*den/num)+1;
+//               |L| = n-1-|H|-|HC| (Alg. 1 finalisation); Eq. (6) as the exact
+//               integer N = (sum_H + sum_HC)*|L cap C| + |L|*sum_{L cap C},
 //               divided once by |L cap C| in IEEE double.
 // For directed graphs the distances are round-trip: D + Dr (Sec. 6.1).
 #include "internal.h"
@@ -24,101 +26,110 @@ namespace ccg {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int64_t kLdsHistMax = 256;  // LDS histogram used while maxd < 256
 
+// Reads element i of a distance row; with RT the reverse row is added.
 template <typename DT, bool RT>
-__device__ __forceinline__ int64_t load_dist(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t off,
-                                             bool& unreached) {
-    const uint32_t a = (uint32_t)D[off];
-    if (a == DistT<DT>::never) unreached = true;
-    int64_t d = a;
-    if (RT) {
-        const uint32_t b = (uint32_t)Dr[off];
-        if (b == DistT<DT>::never) unreached = true;
-        d += b;
-    }
-    return d;
+__device__ __forceinline__ uint32_t dist_at(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t off) {
+    uint32_t a = (uint32_t)D[off];
+    if (RT) a += (uint32_t)Dr[off];
+    return a;
 }
 
-// grid.y = column block of 64 samples; lane j handles sample cb*64 + j for a
-// contiguous range of nodes per wave.
+template <typename DT, bool RT>
+__device__ __forceinline__ bool unreached_at(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t off) {
+    bool u = (uint32_t)D[off] == DistT<DT>::never;
+    if (RT) u = u || (uint32_t)Dr[off] == DistT<DT>::never;
+    return u;
+}
+
+// Visits row[0..k) of D (+Dr) calling f(i, d).  Uses 16-byte loads when the
+// row length in bytes is a multiple of 16.
+template <typename DT, bool RT, typename F>
+__device__ __forceinline__ void for_row(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t v, int32_t k,
+                                        F&& f) {
+    constexpr int per = 16 / sizeof(DT);
+    const int64_t base = v * k;
+    if (((int64_t)k * sizeof(DT)) % 16 == 0) {
+        const uint4* a = (const uint4*)(D + base);
+        const uint4* b = RT ? (const uint4*)(Dr + base) : nullptr;
+        for (int32_t c = 0; c < k / per; c++) {
+            const uint4 va = a[c];
+            uint4 vb = make_uint4(0, 0, 0, 0);
+            if (RT) vb = b[c];
+            const uint32_t wa[4] = {va.x, va.y, va.z, va.w};
+            const uint32_t wb[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+#pragma unroll
+                for (int e = 0; e < 4 / (int)sizeof(DT); e++) {
+                    const int sh = e * 8 * (int)sizeof(DT);
+                    const uint32_t mask = sizeof(DT) == 4 ? 0xFFFFFFFFu : ((1u << (8 * sizeof(DT))) - 1);
+                    uint32_t d = (wa[q] >> sh) & mask;
+                    if (RT) d += (wb[q] >> sh) & mask;
+                    f(c * per + q * (4 / (int)sizeof(DT)) + e, d);
+                }
+            }
+        }
+    } else {
+        for (int32_t i = 0; i < k; i++) f(i, dist_at<DT, RT>(D, Dr, base + i));
+    }
+}
+
+// histogram over non-sampled nodes, one lane per node; LDS copy while it fits
 template <typename DT, bool RT>
 __global__ __launch_bounds__(kBlock) void k_reduce(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n,
-                                                   int32_t k, const int32_t* __restrict__ sidx, int64_t maxd,
-                                                   int32_t* __restrict__ hist, unsigned long long* __restrict__ src_sum,
-                                                   int use_lds, DevFlags* flags) {
-    extern __shared__ int32_t lds_hist[];  // [(maxd+1)][64] when use_lds
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    const int32_t cb = blockIdx.y;
-    const int32_t i = cb * 64 + lane;
-    const bool vi = i < k;
-    const int64_t hlen = maxd + 1;
+                                                   int32_t k, const int32_t* __restrict__ sidx, int64_t hlen,
+                                                   int32_t* __restrict__ hist, int use_lds, DevFlags* flags) {
+    extern __shared__ int32_t lds_hist[];  // [k][hlen] when use_lds
     if (use_lds) {
-        for (int64_t t = threadIdx.x; t < hlen * 64; t += kBlock) lds_hist[t] = 0;
+        for (int64_t t = threadIdx.x; t < (int64_t)k * hlen; t += kBlock) lds_hist[t] = 0;
         __syncthreads();
     }
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-    const int64_t wid = (int64_t)blockIdx.x * (kBlock / 64) + wave;
-    const int64_t chunk = (n + waves - 1) / waves;
-    const int64_t v0 = wid * chunk;
-    const int64_t v1 = v0 + chunk < n ? v0 + chunk : n;
-    int64_t sum = 0;
-    bool unreached = false;
-    bool too_far = false;
-    for (int64_t v = v0; v < v1; ++v) {
-        if (!vi) continue;
-        const int64_t d = load_dist<DT, RT>(D, Dr, v * k + i, unreached);
-        sum += d;
-        if (sidx[v] < 0) {
-            if (d > maxd) {
-                too_far = true;
+    bool bad = false;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+        if (sidx[v] >= 0) continue;
+        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
+            if ((int64_t)d >= hlen) {
+                bad = true;
             } else if (use_lds) {
-                atomicAdd(&lds_hist[d * 64 + lane], 1);
+                atomicAdd(&lds_hist[(int64_t)i * hlen + d], 1);
             } else {
                 atomicAdd(&hist[(int64_t)i * hlen + d], 1);
             }
-        }
+        });
     }
-    if (vi && sum) atomicAdd(&src_sum[i], (unsigned long long)sum);
-    if (unreached) flags->disconnected = 1;
-    if (too_far) flags->overflow = 1;
+    if (bad) flags->disconnected = 1;  // an unreached entry (or a distance beyond the bound)
     if (use_lds) {
         __syncthreads();
-        for (int64_t t = threadIdx.x; t < hlen * 64; t += kBlock) {
+        for (int64_t t = threadIdx.x; t < (int64_t)k * hlen; t += kBlock) {
             const int32_t c = lds_hist[t];
-            const int32_t ii = cb * 64 + (int32_t)(t & 63);
-            if (c && ii < k) atomicAdd(&hist[(int64_t)ii * hlen + (t >> 6)], c);
+            if (c) atomicAdd(&hist[t], c);
         }
     }
 }
 
-template <typename DT, bool RT>
+template <typename DT, bool RT, typename MT>
 __global__ void k_dmat(const DT* __restrict__ D, const DT* __restrict__ Dr, const int32_t* __restrict__ samples,
-                       int32_t k, int32_t* __restrict__ dmat) {
+                       int32_t k, int32_t* __restrict__ dmat_out, MT* __restrict__ dmat_c, DevFlags* flags) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)k * k) return;
     const int32_t i = (int32_t)(t / k), j = (int32_t)(t % k);
-    bool unreached = false;
-    dmat[t] = (int32_t)load_dist<DT, RT>(D, Dr, (int64_t)samples[j] * k + i, unreached);
+    const int64_t off = (int64_t)samples[j] * k + i;
+    if (unreached_at<DT, RT>(D, Dr, off)) flags->disconnected = 1;
+    const uint32_t d = dist_at<DT, RT>(D, Dr, off);
+    dmat_out[t] = (int32_t)d;
+    dmat_c[t] = (MT)d;
 }
 
-template <typename DT, bool RT>
-__global__ void k_to_i32(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t count, int32_t* __restrict__ out) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
-        bool unreached = false;
-        out[t] = (int32_t)load_dist<DT, RT>(D, Dr, t, unreached);
-    }
-}
-
-// one block per sample: reverse inclusive scan of hist[i][0..maxd] into
-// T[i][t] for t = 0..maxd+1 (T[i][maxd+1] = 0)
-__global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ hist, int64_t maxd,
-                                                   int32_t* __restrict__ Tcnt, int64_t* __restrict__ Tsum) {
+// One block per sample: sums the histogram copies, reverse inclusive scan
+// into T[i][t] for t = 0..maxd+1 (T[i][maxd+1] = 0), then S(c_i).
+__global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ hist, int32_t nslots, int32_t k,
+                                                   int64_t hlen, int64_t maxd, const int32_t* __restrict__ dmat,
+                                                   int32_t* __restrict__ Tcnt, int64_t* __restrict__ Tsum,
+                                                   int64_t* __restrict__ src_sum) {
     __shared__ int64_t wc[kBlock / 64], ws[kBlock / 64];
     const int32_t i = blockIdx.x;
-    const int64_t hlen = maxd + 1, tlen = maxd + 2;
-    const int32_t* h = hist + (int64_t)i * hlen;
+    const int64_t tlen = maxd + 2;
     int32_t* tc = Tcnt + (int64_t)i * tlen;
     int64_t* ts = Tsum + (int64_t)i * tlen;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -127,12 +138,12 @@ __global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ h
         tc[maxd + 1] = 0;
         ts[maxd + 1] = 0;
     }
-    // chunks of kBlock entries from the top: thread j takes d = top - j
     for (int64_t top = maxd; top >= 0; top -= kBlock) {
         const int64_t d = top - threadIdx.x;
-        int64_t c = d >= 0 ? h[d] : 0;
+        int64_t c = 0;
+        if (d >= 0 && d < hlen)
+            for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * k + i) * hlen + d];
         int64_t s = c * (d >= 0 ? d : 0);
-        // inclusive scan within the wave
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int64_t yc = __shfl_up(c, off);
@@ -162,57 +173,68 @@ __global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ h
         }
         __syncthreads();
     }
+    // S(c_i) = (sum over non-sampled u of d(c_i,u)) + sum_j d(c_i,c_j)
+    int64_t rs = 0;
+    for (int32_t j = threadIdx.x; j < k; j += kBlock) rs += dmat[(int64_t)i * k + j];
+    rs = wave_sum64(rs);
+    __syncthreads();
+    if (lane == 0) wc[wave] = rs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int w = 0; w < kBlock / 64; w++) tot += wc[w];
+        src_sum[i] = carry_s + tot;
+    }
 }
 
-template <typename DT, bool RT>
+template <typename DT, bool RT, typename MT>
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
-    const int32_t* __restrict__ dmat, const int32_t* __restrict__ Tcnt, const int64_t* __restrict__ Tsum,
-    int64_t tlen, const unsigned long long* __restrict__ src_sum, int64_t en, int64_t ed, double* S_hyb,
-    double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out, int64_t* sampsum_out,
-    DevFlags* flags) {
-    const int lane = lane_id();
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-    const int64_t wid = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
+    const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed,
+    double* S_hyb, double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out,
+    int64_t* sampsum_out, DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
-    for (int64_t v = wid; v < n; v += waves) {
-        bool unreached = false;
-        uint64_t best = ~0ull;
+    bool any_ovf = false, any_unreached = false;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+        uint32_t best = 0xFFFFFFFFu;
+        int32_t p = 0;
         int64_t sum = 0;
-        for (int32_t i = lane; i < k; i += 64) {
-            const int64_t d = load_dist<DT, RT>(D, Dr, v * k + i, unreached);
-            const uint64_t key = ((uint64_t)d << 32) | (uint32_t)i;
-            best = key < best ? key : best;
+        bool unreached = false;
+        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
+            if (d < best) {  // strict: ties keep the lower sample index
+                best = d;
+                p = i;
+            }
             sum += d;
+        });
+        const int64_t delta = best;
+        if (RT) {
+            // an unreached entry is the maximal code in either direction
+            unreached = unreached_at<DT, RT>(D, Dr, v * k + p);
+        } else {
+            unreached = best == DistT<DT>::never;
         }
-        best = wave_min64(best);
-        sum = wave_sum64(sum);
-        const int32_t p = (int32_t)(best & 0xffffffffu);
-        const int64_t delta = (int64_t)(best >> 32);
         const int32_t j = sidx[v];
         double hyb, samp;
         int64_t piv, pub;
         bool ovf = false;
         if (j >= 0) {
-            // sampled node: exact S(v) for every estimator
-            const int64_t S = (int64_t)src_sum[j];
+            const int64_t S = src_sum[j];
             hyb = samp = (double)S;
             piv = pub = S;
             ovf = S >= LIM;
         } else {
             const int64_t thr = delta * ed;
+            const MT* drow = dmat_c + (int64_t)p * k;
             int64_t lcsum = 0;
             int32_t lcnum = 0;
-            const int32_t* drow = dmat + (int64_t)p * k;
-            for (int32_t i = lane; i < k; i += 64) {
+            for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
                 if ((int64_t)drow[i] * en <= thr) {
-                    bool u2 = false;
-                    lcsum += load_dist<DT, RT>(D, Dr, v * k + i, u2);
+                    lcsum += d;
                     lcnum += 1;
                 }
-            }
-            lcsum = wave_sum64(lcsum);
-            lcnum = wave_sum32(lcnum);
+            });
             const int64_t tix = thr / en + 1;  // d > floor(Delta/eps)  <=>  d >= tix
             int64_t hnum = 0, hsum = 0;
             if (tix < tlen) {
@@ -222,40 +244,43 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
             const int64_t hcsum = sum - lcsum;
             const int64_t lnum = (n - 1) - hnum - (int64_t)(k - lcnum);
             const int64_t a = hsum + hcsum;
-            int64_t t1 = 0, t2 = 0, N = 0;
+            int64_t t1 = 0, t2 = 0, N = 0, ss = 0;
             ovf = __builtin_mul_overflow(a, (int64_t)lcnum, &t1) || __builtin_mul_overflow(lcsum, lnum, &t2) ||
                   __builtin_add_overflow(t1, t2, &N) || N >= LIM || lcnum < 1 || lnum < lcnum;
             hyb = (double)N / (double)lcnum;
-            int64_t ss = 0;
             ovf = ovf || __builtin_mul_overflow(n - 1, sum, &ss) || ss >= LIM;
             samp = (double)ss / (double)k;
-            piv = (int64_t)src_sum[p];
+            piv = src_sum[p];
             pub = piv + (n - 1) * delta;
         }
-        if (lane == 0) {
-            if (S_hyb) S_hyb[v] = hyb;
-            if (S_samp) S_samp[v] = samp;
-            if (S_piv) S_piv[v] = piv;
-            if (S_pub) S_pub[v] = pub;
-            if (pivot_out) pivot_out[v] = p;
-            if (delta_out) delta_out[v] = (int32_t)delta;
-            if (sampsum_out) sampsum_out[v] = sum;
-            if (ovf) flags->overflow = 1;
-        }
-        if (unreached) flags->disconnected = 1;
+        const int64_t o = orig[v];
+        if (S_hyb) S_hyb[o] = hyb;
+        if (S_samp) S_samp[o] = samp;
+        if (S_piv) S_piv[o] = piv;
+        if (S_pub) S_pub[o] = pub;
+        if (pivot_out) pivot_out[o] = p;
+        if (delta_out) delta_out[o] = (int32_t)delta;
+        if (sampsum_out) sampsum_out[o] = sum;
+        any_ovf = any_ovf || ovf;
+        any_unreached = any_unreached || unreached;
+    }
+    if (any_ovf) flags->overflow = 1;
+    if (any_unreached) flags->disconnected = 1;
+}
+
+template <typename DT, bool RT>
+__global__ void k_to_i32(const DT* __restrict__ D, const DT* __restrict__ Dr, const int32_t* __restrict__ orig,
+                         int64_t n, int32_t k, int32_t* __restrict__ out) {
+    const int64_t count = n * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = t / k, i = t % k;
+        out[(int64_t)orig[v] * k + i] = (int32_t)dist_at<DT, RT>(D, Dr, t);
     }
 }
 
-__global__ void k_sidx(const int32_t* __restrict__ samples, int32_t k, int32_t* __restrict__ sidx, int64_t n,
-                       DevFlags* flags) {
+__global__ void k_sidx(const int32_t* __restrict__ samples, int32_t k, int32_t* __restrict__ sidx) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= k) return;
-    const int32_t v = samples[i];
-    if (v < 0 || v >= n) {
-        flags->bad_sample = 1;
-        return;
-    }
-    sidx[v] = i;
+    if (i < k) sidx[samples[i]] = i;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
@@ -265,53 +290,62 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-template <typename DT, bool RT>
+inline unsigned grid_for(int64_t items, int64_t cap) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+template <typename DT, bool RT, typename MT>
 void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* flags) {
     const int64_t n = a.n;
     const int32_t k = a.k;
-    const int64_t hlen = a.maxd + 1, tlen = a.maxd + 2;
+    const int64_t maxd = a.maxd;
+    const int64_t tlen = maxd + 2;
     char* p = (char*)scratch;
-    int32_t* sidx = (int32_t*)p;
-    p += align256(sizeof(int32_t) * n);
-    int32_t* hist = (int32_t*)p;
-    p += align256(sizeof(int32_t) * k * hlen);
     int32_t* Tcnt = (int32_t*)p;
     p += align256(sizeof(int32_t) * k * tlen);
     int64_t* Tsum = (int64_t*)p;
-
-    const DT* D = (const DT*)a.D;
-    const DT* Dr = (const DT*)a.Dr;
-    fill_u32(st, sidx, 0xFFFFFFFFu, (size_t)n);
-    fill_u32(st, hist, 0u, (size_t)(k * hlen));
-    fill_u32(st, a.src_sum, 0u, (size_t)k * 2);
-    hipLaunchKernelGGL(k_sidx, dim3((k + 255) / 256), dim3(256), 0, st, a.samples, k, sidx, n, flags);
-
-    const int use_lds = a.maxd < kLdsHistMax ? 1 : 0;
-    const size_t lds = use_lds ? sizeof(int32_t) * 64 * hlen : 0;
-    int64_t gx = (n + 255) / 256;
-    if (gx > 1024) gx = 1024;
-    if (gx < 1) gx = 1;
-    dim3 grid((unsigned)gx, (unsigned)((k + 63) / 64));
-    hipLaunchKernelGGL((k_reduce<DT, RT>), grid, dim3(kBlock), lds, st, D, Dr, n, k, sidx, a.maxd, hist,
-                       (unsigned long long*)a.src_sum, use_lds, flags);
-    CCG_HIP(hipGetLastError());
+    p += align256(sizeof(int64_t) * k * tlen);
+    MT* dmat_c = (MT*)p;
+    p += align256(sizeof(MT) * (size_t)k * k);
+    int32_t* hist = a.hist;
+    int32_t nslots = a.hist_slots;
+    int64_t hlen = a.hist_len;
+    if (!a.hist_done) {
+        // histogram by a pass over D
+        hist = (int32_t*)p;
+        hlen = maxd + 1;
+        nslots = 1;
+        fill_u32(st, hist, 0u, (size_t)(k * hlen));
+        const size_t lds = sizeof(int32_t) * (size_t)k * hlen;
+        const int use_lds = lds <= 48 * 1024 ? 1 : 0;
+        hipLaunchKernelGGL((k_reduce<DT, RT>), dim3(grid_for(n, use_lds ? 1024 : 8192)), dim3(kBlock),
+                           use_lds ? lds : 0, st, (const DT*)a.D, (const DT*)a.Dr, n, k, a.sidx, hlen, hist, use_lds,
+                           flags);
+        CCG_HIP(hipGetLastError());
+    }
     const int64_t kk = (int64_t)k * k;
-    hipLaunchKernelGGL((k_dmat<DT, RT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, D, Dr, a.samples, k,
-                       a.dmat);
-    hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, a.maxd, Tcnt, Tsum);
-    int64_t ge = (n + 3) / 4;
-    if (ge > 8192) ge = 8192;
-    if (ge < 1) ge = 1;
-    hipLaunchKernelGGL((k_estimate<DT, RT>), dim3((unsigned)ge), dim3(kBlock), 0, st, D, Dr, n, k, sidx, a.dmat,
-                       Tcnt, Tsum, tlen, (const unsigned long long*)a.src_sum, a.eps_num, a.eps_den, a.S_hyb,
-                       a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
+    hipLaunchKernelGGL((k_dmat<DT, RT, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, (const DT*)a.D,
+                       (const DT*)a.Dr, a.samples, k, a.dmat, dmat_c, flags);
+    hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd, a.dmat, Tcnt, Tsum,
+                       a.src_sum);
+    hipLaunchKernelGGL((k_estimate<DT, RT, MT>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, (const DT*)a.D,
+                       (const DT*)a.Dr, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,
+                       a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
     CCG_HIP(hipGetLastError());
     if (a.Dout) {
-        const int64_t cnt = n * k;
-        int64_t g = (cnt + 255) / 256;
-        if (g > 65536) g = 65536;
-        hipLaunchKernelGGL((k_to_i32<DT, RT>), dim3((unsigned)g), dim3(256), 0, st, D, Dr, cnt, a.Dout);
+        hipLaunchKernelGGL((k_to_i32<DT, RT>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, (const DT*)a.D,
+                           (const DT*)a.Dr, a.orig, n, k, a.Dout);
     }
+}
+
+template <typename DT, bool RT>
+void epilogue_mt(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* flags) {
+    if (a.maxd < 255) epilogue_t<DT, RT, uint8_t>(st, a, scratch, flags);
+    else if (a.maxd < 65535) epilogue_t<DT, RT, uint16_t>(st, a, scratch, flags);
+    else epilogue_t<DT, RT, uint32_t>(st, a, scratch, flags);
 }
 
 }  // namespace
@@ -323,24 +357,39 @@ void fill_u32(hipStream_t st, void* p, uint32_t value, size_t count) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, st, (uint32_t*)p, value, count);
 }
 
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd) {
-    const int64_t hlen = maxd + 1, tlen = maxd + 2;
-    return align256(sizeof(int32_t) * n) + align256(sizeof(int32_t) * k * hlen) + align256(sizeof(int32_t) * k * tlen) +
-           align256(sizeof(int64_t) * k * tlen) + 1024;
+void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* sidx, int64_t n) {
+    fill_u32(st, sidx, 0xFFFFFFFFu, (size_t)n);
+    hipLaunchKernelGGL(k_sidx, dim3((k + 255) / 256), dim3(256), 0, st, samples, k, sidx);
+}
+
+void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int64_t hlen, int64_t maxd,
+                const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum) {
+    hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd, dmat, Tcnt, Tsum, src_sum);
+    CCG_HIP(hipGetLastError());
+}
+
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done) {
+    const int64_t tlen = maxd + 2;
+    size_t s = align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
+               align256(sizeof(uint32_t) * (size_t)k * k) + 1024;
+    if (!hist_done) s += align256(sizeof(int32_t) * k * (maxd + 1));
+    (void)n;
+    return s;
 }
 
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags) {
-    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd)) throw HipError{hipErrorOutOfMemory, "epilogue scratch"};
+    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done))
+        throw HipError{hipErrorOutOfMemory, "epilogue scratch"};
     const bool rt = a.Dr != nullptr;
     switch (a.dk) {
         case DistKind::U8:
-            rt ? epilogue_t<uint8_t, true>(st, a, scratch, flags) : epilogue_t<uint8_t, false>(st, a, scratch, flags);
+            rt ? epilogue_mt<uint8_t, true>(st, a, scratch, flags) : epilogue_mt<uint8_t, false>(st, a, scratch, flags);
             break;
         case DistKind::U16:
-            rt ? epilogue_t<uint16_t, true>(st, a, scratch, flags) : epilogue_t<uint16_t, false>(st, a, scratch, flags);
+            rt ? epilogue_mt<uint16_t, true>(st, a, scratch, flags) : epilogue_mt<uint16_t, false>(st, a, scratch, flags);
             break;
         default:
-            rt ? epilogue_t<uint32_t, true>(st, a, scratch, flags) : epilogue_t<uint32_t, false>(st, a, scratch, flags);
+            rt ? epilogue_mt<uint32_t, true>(st, a, scratch, flags) : epilogue_mt<uint32_t, false>(st, a, scratch, flags);
             break;
     }
 }

@@ -1,0 +1,293 @@
+// Estimator epilogue working directly on the per-level seen masks written by
+// the batched BFS (S_L(v) = {i : d(c_i, v) <= L}, L = 0..lmax), so the
+// distance matrix is never stored.  For a node v:
+//   d(c_i, v)        = #{L < lmax : i not in S_L(v)}      (levels still missing i)
+//   Delta(v)         = first L with S_L(v) non-empty, pivot = its lowest bit
+//                      (the lowest sample index among the nearest, Sec. 2 / Alg. 2)
+//   sum_i d(c_i, v)  = sum_{L < lmax} (k - |S_L(v)|)
+//   L cap C (Eq. 6)  = Lmask[p][t] = {i : d(c_p, c_i) <= t}, t = floor(Delta*den/num)
+//   sum_{L cap C} d  = sum_{L < lmax} |Lmask & ~S_L(v)|
+// and |H|, sum_H from the per-sample tail tables (see k_suffix), as in the
+// distance-matrix epilogue.  A group of 64 nodes stops writing masks after
+// the level recorded in fill_level[g]; later masks are all-ones.
+#include "internal.h"
+
+namespace ccg {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <int W>
+__device__ __forceinline__ uint64_t full_word(int w, uint64_t lastmask) {
+    return w == W - 1 ? lastmask : ~0ull;
+}
+
+template <int W>
+__device__ __forceinline__ void mask_at(const uint64_t* __restrict__ snap, size_t plane, int32_t L, int32_t fl,
+                                        int64_t v, uint64_t lastmask, uint64_t s[W]) {
+    if (L <= fl) {
+        const uint64_t* row = snap + (size_t)L * plane + v * W;
+#pragma unroll
+        for (int p = 0; p < (W + 1) / 2; p++) {
+            if (2 * p + 1 < W) {
+                const uint4 q = *(const uint4*)(row + 2 * p);
+                s[2 * p] = ((uint64_t)q.y << 32) | q.x;
+                s[2 * p + 1] = ((uint64_t)q.w << 32) | q.z;
+            } else {
+                s[2 * p] = row[2 * p];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < W; w++) s[w] = full_word<W>(w, lastmask);
+    }
+}
+
+// first level at which bit i is in the mask of node v
+template <int W>
+__device__ __forceinline__ int32_t level_of(const uint64_t* __restrict__ snap, size_t plane, int32_t lmax,
+                                            int32_t fl, int64_t v, int32_t i) {
+    for (int32_t L = 0; L <= lmax; L++) {
+        if (L > fl) return L;
+        const uint64_t x = snap[(size_t)L * plane + v * W + (i >> 6)];
+        if ((x >> (i & 63)) & 1ull) return L;
+    }
+    return -1;  // never reached
+}
+
+template <int W, typename MT>
+__global__ void k_dmat_bits(const uint64_t* __restrict__ snap, size_t plane, int32_t lmax,
+                            const int32_t* __restrict__ fill_level, const int32_t* __restrict__ samples, int32_t k,
+                            int32_t* __restrict__ dmat, MT* __restrict__ dmat_c, DevFlags* flags) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)k * k) return;
+    const int32_t i = (int32_t)(t / k), j = (int32_t)(t % k);
+    const int64_t cj = samples[j];
+    const int32_t d = level_of<W>(snap, plane, lmax, fill_level[cj >> 6], cj, i);
+    if (d < 0) flags->disconnected = 1;
+    dmat[t] = d;
+    dmat_c[t] = (MT)(d < 0 ? 0 : d);
+}
+
+// Lmask[p][t] = {i : dmat[p][i] <= t} for t = 0..lmax; one wave per p
+template <int W, typename MT>
+__global__ void k_lmask(const MT* __restrict__ dmat_c, int32_t k, int32_t lmax, uint64_t* __restrict__ lmask) {
+    const int32_t p = blockIdx.x;
+    const int lane = lane_id();
+    for (int32_t t = 0; t <= lmax; t++) {
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const int32_t i = w * 64 + lane;
+            const bool in = i < k && (int32_t)dmat_c[(int64_t)p * k + i] <= t;
+            const uint64_t m = __ballot(in);
+            if (lane == 0) lmask[((int64_t)p * (lmax + 1) + t) * W + w] = m;
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_estimate_bits(
+    const uint64_t* __restrict__ snap, size_t plane, int32_t lmax, const int32_t* __restrict__ fill_level, int64_t n,
+    int32_t k, uint64_t lastmask, const int32_t* __restrict__ sidx, const int32_t* __restrict__ orig,
+    const uint64_t* __restrict__ lmask, const int32_t* __restrict__ Tcnt, const int64_t* __restrict__ Tsum,
+    int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed, double* S_hyb, double* S_samp,
+    int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out, int64_t* sampsum_out, DevFlags* flags) {
+    const int64_t LIM = (int64_t)1 << 53;
+    bool any_ovf = false, any_unreached = false;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+        const int32_t fl = fill_level[v >> 6];
+        int32_t delta = -1, p = 0, last = 0;
+        int64_t sum = 0;
+        for (int32_t L = 0; L <= lmax; L++) {
+            uint64_t s[W];
+            mask_at<W>(snap, plane, L, fl, v, lastmask, s);
+            int32_t c = 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) c += __popcll(s[w]);
+            if (delta < 0 && c > 0) {
+                delta = L;
+#pragma unroll
+                for (int w = W - 1; w >= 0; w--)
+                    if (s[w]) p = w * 64 + __ffsll((unsigned long long)s[w]) - 1;
+            }
+            if (L < lmax) sum += k - c;
+            last = c;
+        }
+        const bool unreached = last != k;
+        const int32_t j = sidx[v];
+        double hyb, samp;
+        int64_t piv, pub;
+        bool ovf = false;
+        if (delta < 0) delta = 0;
+        if (j >= 0) {
+            const int64_t S = src_sum[j];
+            hyb = samp = (double)S;
+            piv = pub = S;
+            ovf = S >= LIM;
+        } else {
+            const int64_t thr = (int64_t)delta * ed;
+            int64_t t = thr / en;
+            if (t > lmax) t = lmax;
+            uint64_t lm[W];
+            int32_t lcnum = 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                lm[w] = lmask[((int64_t)p * (lmax + 1) + t) * W + w];
+                lcnum += __popcll(lm[w]);
+            }
+            int64_t lcsum = 0;
+            for (int32_t L = 0; L < lmax; L++) {
+                uint64_t s[W];
+                mask_at<W>(snap, plane, L, fl, v, lastmask, s);
+#pragma unroll
+                for (int w = 0; w < W; w++) lcsum += __popcll(lm[w] & ~s[w]);
+            }
+            const int64_t tix = thr / en + 1;  // d > floor(Delta/eps)  <=>  d >= tix
+            int64_t hnum = 0, hsum = 0;
+            if (tix < tlen) {
+                hnum = Tcnt[(int64_t)p * tlen + tix];
+                hsum = Tsum[(int64_t)p * tlen + tix];
+            }
+            const int64_t hcsum = sum - lcsum;
+            const int64_t lnum = (n - 1) - hnum - (int64_t)(k - lcnum);
+            const int64_t a = hsum + hcsum;
+            int64_t t1 = 0, t2 = 0, N = 0, ss = 0;
+            ovf = __builtin_mul_overflow(a, (int64_t)lcnum, &t1) || __builtin_mul_overflow(lcsum, lnum, &t2) ||
+                  __builtin_add_overflow(t1, t2, &N) || N >= LIM || lcnum < 1 || lnum < lcnum;
+            hyb = (double)N / (double)lcnum;
+            ovf = ovf || __builtin_mul_overflow(n - 1, sum, &ss) || ss >= LIM;
+            samp = (double)ss / (double)k;
+            piv = src_sum[p];
+            pub = piv + (n - 1) * (int64_t)delta;
+        }
+        const int64_t o = orig[v];
+        if (S_hyb) S_hyb[o] = hyb;
+        if (S_samp) S_samp[o] = samp;
+        if (S_piv) S_piv[o] = piv;
+        if (S_pub) S_pub[o] = pub;
+        if (pivot_out) pivot_out[o] = p;
+        if (delta_out) delta_out[o] = delta;
+        if (sampsum_out) sampsum_out[o] = sum;
+        any_ovf = any_ovf || ovf;
+        any_unreached = any_unreached || unreached;
+    }
+    if (any_ovf) flags->overflow = 1;
+    if (any_unreached) flags->disconnected = 1;
+}
+
+// Distances from the masks: thread per (node, sample).  out_internal (DT,
+// node-major, columns src_base..) or out_i32 at the caller's node ids.
+template <int W, typename DT>
+__global__ void k_materialize(const uint64_t* __restrict__ snap, size_t plane, int32_t lmax,
+                              const int32_t* __restrict__ fill_level, int64_t n, int32_t kg, int32_t src_base,
+                              int32_t k, DT* __restrict__ out_internal, const int32_t* __restrict__ orig,
+                              int32_t* __restrict__ out_i32, DevFlags* flags) {
+    const int64_t count = n * kg;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = t / kg;
+        const int32_t i = (int32_t)(t % kg);
+        const int32_t d = level_of<W>(snap, plane, lmax, fill_level[v >> 6], v, i);
+        if (d < 0) flags->disconnected = 1;
+        if (out_internal) out_internal[v * k + src_base + i] = (DT)(d < 0 ? DistT<DT>::never : (uint32_t)d);
+        if (out_i32) out_i32[(int64_t)orig[v] * k + src_base + i] = d;
+    }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline unsigned grid_for(int64_t items, int64_t cap) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+template <int W, typename MT>
+void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* flags) {
+    const int64_t n = a.n;
+    const int32_t k = a.k;
+    const int32_t lmax = a.lmax;
+    const int64_t tlen = (int64_t)lmax + 2;
+    const int rem = k - (W - 1) * 64;
+    const uint64_t lastmask = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
+    char* p = (char*)scratch;
+    int32_t* Tcnt = (int32_t*)p;
+    p += align256(sizeof(int32_t) * k * tlen);
+    int64_t* Tsum = (int64_t*)p;
+    p += align256(sizeof(int64_t) * k * tlen);
+    MT* dmat_c = (MT*)p;
+    p += align256(sizeof(MT) * (size_t)k * k);
+    uint64_t* lmask = (uint64_t*)p;
+
+    const int64_t kk = (int64_t)k * k;
+    hipLaunchKernelGGL((k_dmat_bits<W, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, a.snap, a.plane,
+                       lmax, a.fill_level, a.samples, k, a.dmat, dmat_c, flags);
+    run_suffix(st, a.hist, a.hist_slots, k, a.hist_len, lmax, a.dmat, Tcnt, Tsum, a.src_sum);
+    hipLaunchKernelGGL((k_lmask<W, MT>), dim3(k), dim3(64), 0, st, dmat_c, k, lmax, lmask);
+    hipLaunchKernelGGL((k_estimate_bits<W>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, a.snap, a.plane, lmax,
+                       a.fill_level, n, k, lastmask, a.sidx, a.orig, lmask, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,
+                       a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
+    CCG_HIP(hipGetLastError());
+    if (a.Dout) {
+        hipLaunchKernelGGL((k_materialize<W, uint8_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, a.snap,
+                           a.plane, lmax, a.fill_level, n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
+    }
+}
+
+template <int W>
+void bits_mt(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* flags) {
+    if (a.lmax < 255) bits_t<W, uint8_t>(st, a, scratch, flags);
+    else if (a.lmax < 65535) bits_t<W, uint16_t>(st, a, scratch, flags);
+    else bits_t<W, uint32_t>(st, a, scratch, flags);
+}
+
+template <int W, typename DT>
+void materialize_t(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
+                   int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DevFlags* flags) {
+    hipLaunchKernelGGL((k_materialize<W, DT>), dim3(grid_for(n * kg, 65536)), dim3(256), 0, st, snap, plane, lmax,
+                       fill_level, n, kg, src_base, k, (DT*)D, (const int32_t*)nullptr, (int32_t*)nullptr, flags);
+}
+
+template <int W>
+void materialize_w(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
+                   int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags) {
+    switch (dk) {
+        case DistKind::U8: materialize_t<W, uint8_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags); break;
+        case DistKind::U16: materialize_t<W, uint16_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags); break;
+        default: materialize_t<W, uint32_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags); break;
+    }
+}
+
+}  // namespace
+
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax) {
+    const int64_t tlen = (int64_t)lmax + 2;
+    const int W = (k + 63) / 64;
+    return align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
+           align256(sizeof(uint32_t) * (size_t)k * k) + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W) + 1024;
+}
+
+void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size,
+                       DevFlags* flags) {
+    if (scratch_size < bits_epilogue_scratch(a.k, a.lmax)) throw HipError{hipErrorOutOfMemory, "bits epilogue scratch"};
+    switch ((a.k + 63) / 64) {
+        case 1: bits_mt<1>(st, a, scratch, flags); break;
+        case 2: bits_mt<2>(st, a, scratch, flags); break;
+        case 3: bits_mt<3>(st, a, scratch, flags); break;
+        default: bits_mt<4>(st, a, scratch, flags); break;
+    }
+}
+
+void materialize_distances(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
+                           int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags) {
+    switch ((kg + 63) / 64) {
+        case 1: materialize_w<1>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
+        case 2: materialize_w<2>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
+        case 3: materialize_w<3>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
+        default: materialize_w<4>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
+    }
+    CCG_HIP(hipGetLastError());
+}
+
+}  // namespace ccg

@@ -35,13 +35,31 @@ struct DevFlags {
 };
 
 // Per-level counters written by one traversal launch and read by the host.
-struct LevelCounters {
-    int32_t n_out;          // entries appended to the next work list
+// Kernels add into kCounterSlots copies (one cache line each, slot chosen by
+// block) so that thousands of blocks do not serialise on one address; the
+// host sums the copies.
+struct alignas(128) LevelCounters {
+    int32_t n_out;          // groups (or nodes) still in play after this level
     int32_t n_new;          // nodes that received new bits / distances this level
-    int64_t arcs;           // adjacency entries scanned
-    int64_t frontier_arcs;  // sum of degrees of the nodes appended (push heuristics)
-    int64_t matched;        // scanned arcs whose tail was on the previous level (mask reads)
+    int32_t n_out_q;        // nodes appended to the next frontier list
+    int32_t pad;
+    int64_t arcs;           // adjacency entries scanned (pull) or pushed along (push)
+    int64_t frontier_arcs;  // sum of the out-degrees of the next frontier
+    int64_t matched;        // scanned arcs whose tail was on the previous level
 };
+constexpr int kCounterSlots = 64;
+
+inline void sum_counters(const LevelCounters* slots, int count, LevelCounters& out) {
+    out = LevelCounters{};
+    for (int i = 0; i < count; i++) {
+        out.n_out += slots[i].n_out;
+        out.n_new += slots[i].n_new;
+        out.n_out_q += slots[i].n_out_q;
+        out.arcs += slots[i].arcs;
+        out.frontier_arcs += slots[i].frontier_arcs;
+        out.matched += slots[i].matched;
+    }
+}
 
 // ---------------------------------------------------------------- wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -114,12 +132,14 @@ template <> struct DistT<uint32_t> {
 };
 
 // ---------------------------------------------------------------- graph
+// Device copy of a graph in the library's internal node order: ids sorted by
+// degree, largest first (the "graph builder" step of the upload).
 struct DevGraph {
     int64_t n = 0;
     int64_t arcs = 0;
     bool directed = false;
     bool weighted = false;
-    // out-arcs (as uploaded)
+    // out-arcs
     const uint32_t* rp = nullptr;
     const int32_t* col = nullptr;
     const int32_t* w = nullptr;
@@ -127,6 +147,37 @@ struct DevGraph {
     const uint32_t* rrp = nullptr;
     const int32_t* rcol = nullptr;
     const int32_t* rw = nullptr;
+    const int32_t* orig = nullptr;  // internal id -> caller's id
+    // high-degree prefix [0, nh) scanned in chunks; chunk lists per pull direction
+    int64_t nh = 0;
+    const int32_t* hub_chunks_in = nullptr;   // over in-arcs (forward distances)
+    int32_t n_hub_chunks_in = 0;
+    const int32_t* hub_chunks_out = nullptr;  // over out-arcs (reverse distances)
+    int32_t n_hub_chunks_out = 0;
+};
+
+// The adjacency one batched traversal uses: pull over rp/col (in-arcs), push
+// over out_rp/out_col (out-arcs).
+struct BfsView {
+    int64_t n = 0;
+    int64_t arcs = 0;
+    const uint32_t* rp = nullptr;
+    const int32_t* col = nullptr;
+    const uint32_t* out_rp = nullptr;
+    const int32_t* out_col = nullptr;
+    int64_t nh = 0;
+    const int32_t* hub_chunks = nullptr;  // (node, first arc, end arc) triples over rp/col
+    int32_t n_hub_chunks = 0;
+};
+
+// Where the batched BFS records its per-level seen masks.
+struct BfsLevels {
+    uint64_t* snap = nullptr;     // [cap][n][W]: snap[L][v] = {i : d(c_i, v) <= L}
+    int32_t cap = 0;              // levels the buffer holds
+    int32_t* fill_level = nullptr;  // [ceil(n/64)]: last level each 64-node group wrote
+    int32_t* hist = nullptr;      // optional [kHistSlotsBatched][k][hlen] per-sample level histogram
+    int64_t hlen = 0;
+    int32_t* lmax = nullptr;      // host: largest level with new bits (max over calls)
 };
 
 // ---------------------------------------------------------------- traversal API
@@ -140,6 +191,8 @@ struct TravStats {
     int64_t arcs_matched = 0;
     double kernel_ms = 0;    // summed duration of the per-level traversal kernels
     int64_t kernel_launches = 0;
+    int64_t pull_levels = 0;
+    int64_t push_arcs = 0;
 };
 
 // Event pair for timing one kernel launch on a stream.
@@ -163,24 +216,26 @@ struct KernelTimer {
     }
 };
 
-// Device scratch the traversal drivers carve up; owned by the runtime.
-struct Scratch {
-    void* base = nullptr;
-    size_t size = 0;
-};
-
 enum class DistKind { U8 = 1, U16 = 2, U32 = 4 };
 
-// Batched bit-parallel BFS over one group of up to 256 samples, written to
-// D columns [src_base, src_base + kg) of the node-major n x k matrix D.
-// `in_rp/in_col` is the pull adjacency (in-arcs).  Returns false when the
-// distance type overflowed (retry with a wider type); sets flags->disconnected
-// when some node is unreachable.
-bool bfs_batched(hipStream_t st, const uint32_t* in_rp, const int32_t* in_col, int64_t n,
-                 const int32_t* samples_dev, int32_t kg, int32_t src_base, int32_t k, void* D,
-                 DistKind dk, void* scratch, size_t scratch_size, DevFlags* flags, LevelCounters* cnt_dev,
-                 LevelCounters* cnt_host, TravStats* stats);
-size_t bfs_batched_scratch(int64_t n, int32_t kg);
+constexpr int kHistSlotsBatched = 32;  // spread copies of the per-level histogram counters
+
+
+// Batched bit-parallel BFS over one group of kg <= 256 samples (internal
+// ids samples_dev[src_base .. src_base+kg)), recording per-level seen masks in
+// `out`; with out.hist it also counts hist[slot][src_base+i][L] over
+// non-sampled nodes (sidx[v] < 0).
+// Returns 0 = done, 1 = snapshot capacity too small (retry with more levels),
+// 2 = some node is unreachable from some sample.
+int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
+                int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, size_t scratch_size,
+                LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
+size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh);
+
+// Distances of one sample group from its level masks into the node-major
+// matrix D (columns src_base .. src_base+kg), in the given width.
+void materialize_distances(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
+                           int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags);
 
 // Plain single-source BFS for every sample, source-major output Dt[k][n].
 bool bfs_plain(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
@@ -208,12 +263,19 @@ struct EpilogueArgs {
     int64_t n = 0;
     int32_t k = 0;
     DistKind dk = DistKind::U8;
-    const void* D = nullptr;     // node-major distances
+    const void* D = nullptr;     // node-major distances, internal node order
     const void* Dr = nullptr;    // reverse-direction distances (round trip) or nullptr
-    const int32_t* samples = nullptr;  // device
+    const int32_t* samples = nullptr;  // device, internal ids
+    const int32_t* sidx = nullptr;     // device, internal id -> sample index or -1
+    const int32_t* orig = nullptr;     // device, internal id -> caller's id
     int64_t maxd = 0;            // upper bound on every (combined) distance
     int64_t eps_num = 1, eps_den = 1;
-    // outputs (device, may be null)
+    // histogram already counted by the traversal: hist[slot][i][d], rows of hist_len
+    bool hist_done = false;
+    int32_t* hist = nullptr;
+    int32_t hist_slots = 0;
+    int64_t hist_len = 0;
+    // outputs (device, at the caller's node ids; may be null)
     double* S_hyb = nullptr;
     double* S_samp = nullptr;
     int64_t* S_piv = nullptr;
@@ -223,10 +285,44 @@ struct EpilogueArgs {
     int64_t* sampsum = nullptr;
     int64_t* src_sum = nullptr;  // required (workspace if caller does not want it)
     int32_t* dmat = nullptr;     // required (workspace if caller does not want it)
-    int32_t* Dout = nullptr;     // optional int32 copy of D (combined)
+    int32_t* Dout = nullptr;     // optional int32 copy of D (combined), caller's node order
 };
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd);
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done);
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
+void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* sidx, int64_t n);
+
+// Tail tables and exact sample sums from a histogram with `nslots` copies.
+void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int64_t hlen, int64_t maxd,
+                const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum);
+
+// Epilogue over the level masks of one sample group (k <= 256, undirected).
+struct BitsEpilogueArgs {
+    int64_t n = 0;
+    int32_t k = 0;
+    const uint64_t* snap = nullptr;
+    size_t plane = 0;            // n * W words per level
+    int32_t lmax = 0;
+    const int32_t* fill_level = nullptr;
+    const int32_t* samples = nullptr;  // device, internal ids
+    const int32_t* sidx = nullptr;
+    const int32_t* orig = nullptr;
+    const int32_t* hist = nullptr;
+    int32_t hist_slots = 0;
+    int64_t hist_len = 0;
+    int64_t eps_num = 1, eps_den = 1;
+    double* S_hyb = nullptr;
+    double* S_samp = nullptr;
+    int64_t* S_piv = nullptr;
+    int64_t* S_pub = nullptr;
+    int32_t* pivot = nullptr;
+    int32_t* delta = nullptr;
+    int64_t* sampsum = nullptr;
+    int64_t* src_sum = nullptr;  // required
+    int32_t* dmat = nullptr;     // required
+    int32_t* Dout = nullptr;     // optional int32 distances, caller's node order
+};
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax);
+void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
 
 void fill_u32(hipStream_t st, void* p, uint32_t value, size_t count);
 
