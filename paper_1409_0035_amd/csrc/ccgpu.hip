@@ -410,8 +410,11 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             for (int64_t e = 0; e < arcs; e++) deg[(size_t)col_idx[e]]++;
         std::vector<int32_t> orig((size_t)n);
         for (int64_t v = 0; v < n; v++) orig[(size_t)v] = (int32_t)v;
-        std::stable_sort(orig.begin(), orig.end(),
-                         [&](int32_t a, int32_t b) { return deg[(size_t)a] > deg[(size_t)b]; });
+        // weighted graphs keep the caller's order (delta-stepping works on
+        // (sample, node) pairs and profits from the input's own locality)
+        if (!w)
+            std::stable_sort(orig.begin(), orig.end(),
+                             [&](int32_t a, int32_t b) { return deg[(size_t)a] > deg[(size_t)b]; });
         g->inv.assign((size_t)n, 0);
         for (int64_t i = 0; i < n; i++) g->inv[(size_t)orig[(size_t)i]] = (int32_t)i;
         // ---- relabelled out-arcs
@@ -443,7 +446,14 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
         }
         int64_t nh = (hubs + 63) / 64 * 64;
         if (nh > n) nh = n;
+        if (w) nh = 0;
         g->dg.nh = nh;
+        if (w) {
+            double sw = 0;
+            for (int64_t e = 0; e < arcs; e++) sw += w[e];
+            const double mean = arcs > 0 ? sw / (double)arcs : 1.0;
+            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(2.0 * mean));
+        }
         std::vector<int32_t> ch_in = hub_chunk_list(prp, nh);
         std::vector<int32_t> ch_out = directed ? hub_chunk_list(rp, nh) : std::vector<int32_t>();
 
@@ -561,8 +571,7 @@ size_t job_bytes(const DevGraph& g, int32_t k, int32_t mode, int db) {
     size_t b = Carver::sz(sizeof(int32_t) * k) * 2 + Carver::sz(sizeof(DevFlags)) + Carver::sz(sizeof(LevelCounters) * kCounterSlots) +
                Carver::sz(sizeof(int32_t) * n);
     if (g.weighted) {
-        b += dbytes * (g.directed ? 2 : 1);
-        b += mode == CC_PLAIN ? dbytes + sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
+        b += dbytes * (g.directed ? 3 : 2) + sssp_weighted_scratch(n, mode == CC_PLAIN ? 1 : k);
     } else if (mode == CC_PLAIN) {
         b += dbytes * (g.directed ? 3 : 2) + bfs_plain_scratch(n);
     } else {
@@ -656,9 +665,15 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         const bool bits_path = batched && !g.directed && k <= 256;
         TravStats stats;
         const size_t dbytes = (size_t)n * k * (int)dk;
+        // weighted: samples per delta-stepping call (piles of n*kw pairs)
+        int32_t kw = 1;
+        if (g.weighted && mode != CC_PLAIN) {
+            const size_t per = sssp_weighted_scratch(n, 2) - sssp_weighted_scratch(n, 1);
+            kw = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)k, (free_b / 4) / std::max<size_t>(per, 1)));
+        }
         size_t trav_scratch;
         if (g.weighted)
-            trav_scratch = mode == CC_PLAIN ? sssp_weighted_plain_scratch(n) : sssp_weighted_batched_scratch(n);
+            trav_scratch = sssp_weighted_scratch(n, kw);
         else
             trav_scratch = mode == CC_PLAIN ? bfs_plain_scratch(n) : bfs_batched_scratch(n, kg0, g.nh);
         const size_t hist_elems = bits_path ? (size_t)kHistSlotsBatched * k * cap : 0;
@@ -674,13 +689,14 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         int32_t* hist = bits_path ? c.take<int32_t>(hist_elems) : nullptr;
         // distance matrices and/or level masks
         const size_t snap_bytes = batched ? Carver::sz((size_t)cap * n * Wg * 8) : 0;
+        const bool need_Dt = mode == CC_PLAIN || g.weighted;
         const size_t need_D = (bits_path ? 0 : Carver::sz(dbytes) * (g.directed ? 2 : 1)) +
-                              (mode == CC_PLAIN ? Carver::sz(dbytes) : 0);
+                              (need_Dt ? Carver::sz(dbytes) : 0);
         Carver cd(L.arenaD.get(snap_bytes + need_D + 256));
         uint64_t* snap = batched ? cd.take<uint64_t>((size_t)cap * n * Wg) : nullptr;
         void* D = bits_path ? nullptr : cd.take<char>(dbytes);
         void* Dr = (!bits_path && g.directed) ? cd.take<char>(dbytes) : nullptr;
-        void* Dt = mode == CC_PLAIN ? cd.take<char>(dbytes) : nullptr;
+        void* Dt = need_Dt ? cd.take<char>(dbytes) : nullptr;
 
         CCG_HIP(hipMemcpyAsync(samples_dev, samples_int.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
         fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
@@ -701,7 +717,17 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             void* Dd = dir == 0 ? D : Dr;
             TravStats ds;
             if (g.weighted) {
-                throw HipError{hipErrorNotSupported, "weighted traversal not built yet"};
+                const int32_t* wv = dir == 0 ? g.w : g.rw;
+                int64_t md = 0;
+                for (int32_t s0 = 0; s0 < k && rc == 0; s0 += kw) {
+                    const int32_t kg = std::min(kw, k - s0);
+                    const int wr = sssp_weighted(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
+                                                 (uint32_t*)Dt + (size_t)s0 * n, g.delta, ts, trav_scratch, &md, &ds);
+                    if (wr == 2) rc = 2;
+                    else if (wr == 4) return fail(CC_EOVERFLOW, "a weighted distance does not fit in 32 bits");
+                }
+                if (rc == 0) transpose_dist(st, Dt, Dd, n, k, dk);
+                lmax_dir[dir] = (int32_t)std::min<int64_t>(md, INT32_MAX);
             } else if (mode == CC_PLAIN) {
                 const bool ok = bfs_plain(st, out_rp, out_col, in_rp, in_col, n, g.arcs, samples_int.data(), k, Dt,
                                           dk, ts, trav_scratch, flags, cnt, L.cnt_host, &ds);

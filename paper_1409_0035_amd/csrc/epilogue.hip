@@ -187,6 +187,119 @@ __global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ h
     }
 }
 
+// Long histograms (weighted distances): the same tail tables in three
+// parallel steps over chunks of kChunk entries.
+constexpr int64_t kChunk = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(const int32_t* __restrict__ hist, int32_t nslots, int32_t k,
+                                                       int64_t hlen, int64_t* __restrict__ csum_c,
+                                                       int64_t* __restrict__ csum_s, int64_t nchunks) {
+    __shared__ int64_t wc[kBlock / 64], ws[kBlock / 64];
+    const int64_t c = blockIdx.x;
+    const int32_t i = blockIdx.y;
+    int64_t cc = 0, cs = 0;
+    for (int64_t d = c * kChunk + threadIdx.x; d < (c + 1) * kChunk && d < hlen; d += kBlock) {
+        int64_t h = 0;
+        for (int32_t s = 0; s < nslots; s++) h += hist[((int64_t)s * k + i) * hlen + d];
+        cc += h;
+        cs += h * d;
+    }
+    cc = wave_sum64(cc);
+    cs = wave_sum64(cs);
+    if (lane_id() == 0) {
+        wc[threadIdx.x >> 6] = cc;
+        ws[threadIdx.x >> 6] = cs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t a = 0, b = 0;
+        for (int w = 0; w < kBlock / 64; w++) {
+            a += wc[w];
+            b += ws[w];
+        }
+        csum_c[(int64_t)i * nchunks + c] = a;
+        csum_s[(int64_t)i * nchunks + c] = b;
+    }
+}
+
+// per sample: carry[c] = totals of the chunks above c (one thread per sample)
+__global__ void k_chunk_carry(int64_t* csum_c, int64_t* csum_s, int32_t k, int64_t nchunks) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    int64_t a = 0, b = 0;
+    for (int64_t c = nchunks - 1; c >= 0; c--) {
+        const int64_t x = csum_c[(int64_t)i * nchunks + c], y = csum_s[(int64_t)i * nchunks + c];
+        csum_c[(int64_t)i * nchunks + c] = a;
+        csum_s[(int64_t)i * nchunks + c] = b;
+        a += x;
+        b += y;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_suffix(const int32_t* __restrict__ hist, int32_t nslots, int32_t k,
+                                                         int64_t hlen, int64_t maxd, const int64_t* __restrict__ carry_c,
+                                                         const int64_t* __restrict__ carry_s, int64_t nchunks,
+                                                         int32_t* __restrict__ Tcnt, int64_t* __restrict__ Tsum) {
+    __shared__ int64_t wc[kBlock / 64], ws[kBlock / 64];
+    const int64_t ch = blockIdx.x;
+    const int32_t i = blockIdx.y;
+    const int64_t tlen = maxd + 2;
+    int32_t* tc = Tcnt + (int64_t)i * tlen;
+    int64_t* ts = Tsum + (int64_t)i * tlen;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    int64_t carry_cc = carry_c[(int64_t)i * nchunks + ch], carry_ss = carry_s[(int64_t)i * nchunks + ch];
+    if (ch == 0 && threadIdx.x == 0) {
+        tc[maxd + 1] = 0;
+        ts[maxd + 1] = 0;
+    }
+    const int64_t lo = ch * kChunk;
+    const int64_t hi_ = std::min<int64_t>((ch + 1) * kChunk, maxd + 1);
+    for (int64_t top = hi_ - 1; top >= lo; top -= kBlock) {
+        const int64_t d = top - threadIdx.x;
+        int64_t c = 0;
+        if (d >= lo && d < hlen)
+            for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * k + i) * hlen + d];
+        int64_t sm = c * (d >= 0 ? d : 0);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t yc = __shfl_up(c, off);
+            const int64_t ys = __shfl_up(sm, off);
+            if (lane >= off) {
+                c += yc;
+                sm += ys;
+            }
+        }
+        if (lane == 63) {
+            wc[wave] = c;
+            ws[wave] = sm;
+        }
+        __syncthreads();
+        int64_t pc = carry_cc, ps = carry_ss;
+        for (int w = 0; w < wave; w++) {
+            pc += wc[w];
+            ps += ws[w];
+        }
+        if (d >= lo) {
+            tc[d] = (int32_t)(pc + c);
+            ts[d] = ps + sm;
+        }
+        for (int w = 0; w < kBlock / 64; w++) {
+            carry_cc += wc[w];
+            carry_ss += ws[w];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_src_sum(const int64_t* __restrict__ Tsum, int64_t tlen, const int32_t* __restrict__ dmat, int32_t k,
+                          int64_t* __restrict__ src_sum) {
+    const int32_t i = blockIdx.x;
+    int64_t rs = 0;
+    for (int32_t j = threadIdx.x; j < k; j += 64) rs += dmat[(int64_t)i * k + j];
+    rs = wave_sum64(rs);
+    if (threadIdx.x == 0) src_sum[i] = Tsum[(int64_t)i * tlen] + rs;
+}
+
 template <typename DT, bool RT, typename MT>
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
@@ -310,6 +423,8 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
     p += align256(sizeof(int64_t) * k * tlen);
     MT* dmat_c = (MT*)p;
     p += align256(sizeof(MT) * (size_t)k * k);
+    int64_t* chunks = (int64_t*)p;
+    p += align256(suffix_chunk_scratch(k, maxd));
     int32_t* hist = a.hist;
     int32_t nslots = a.hist_slots;
     int64_t hlen = a.hist_len;
@@ -329,8 +444,7 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
     const int64_t kk = (int64_t)k * k;
     hipLaunchKernelGGL((k_dmat<DT, RT, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, (const DT*)a.D,
                        (const DT*)a.Dr, a.samples, k, a.dmat, dmat_c, flags);
-    hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd, a.dmat, Tcnt, Tsum,
-                       a.src_sum);
+    run_suffix(st, hist, nslots, k, hlen, maxd, a.dmat, Tcnt, Tsum, a.src_sum, chunks);
     hipLaunchKernelGGL((k_estimate<DT, RT, MT>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, (const DT*)a.D,
                        (const DT*)a.Dr, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,
                        a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
@@ -363,15 +477,33 @@ void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* si
 }
 
 void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int64_t hlen, int64_t maxd,
-                const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum) {
-    hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd, dmat, Tcnt, Tsum, src_sum);
+                const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum, int64_t* chunk_scratch) {
+    const int64_t nchunks = (maxd + 1 + kChunk - 1) / kChunk;
+    if (nchunks <= 1 || chunk_scratch == nullptr) {
+        hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd, dmat, Tcnt, Tsum,
+                           src_sum);
+    } else {
+        int64_t* cc = chunk_scratch;
+        int64_t* cs = chunk_scratch + (int64_t)k * nchunks;
+        hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)nchunks, k), dim3(kBlock), 0, st, hist, nslots, k, hlen, cc, cs,
+                           nchunks);
+        hipLaunchKernelGGL(k_chunk_carry, dim3((k + 63) / 64), dim3(64), 0, st, cc, cs, k, nchunks);
+        hipLaunchKernelGGL(k_chunk_suffix, dim3((unsigned)nchunks, k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd,
+                           cc, cs, nchunks, Tcnt, Tsum);
+        hipLaunchKernelGGL(k_src_sum, dim3(k), dim3(64), 0, st, Tsum, maxd + 2, dmat, k, src_sum);
+    }
     CCG_HIP(hipGetLastError());
+}
+
+size_t suffix_chunk_scratch(int32_t k, int64_t maxd) {
+    const int64_t nchunks = (maxd + 1 + kChunk - 1) / kChunk;
+    return sizeof(int64_t) * 2 * (size_t)k * (size_t)nchunks + 256;
 }
 
 size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done) {
     const int64_t tlen = maxd + 2;
     size_t s = align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
-               align256(sizeof(uint32_t) * (size_t)k * k) + 1024;
+               align256(sizeof(uint32_t) * (size_t)k * k) + align256(suffix_chunk_scratch(k, maxd)) + 1024;
     if (!hist_done) s += align256(sizeof(int32_t) * k * (maxd + 1));
     (void)n;
     return s;

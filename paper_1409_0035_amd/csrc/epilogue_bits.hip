@@ -223,7 +223,7 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
     const int64_t kk = (int64_t)k * k;
     hipLaunchKernelGGL((k_dmat_bits<W, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, a.snap, a.plane,
                        lmax, a.fill_level, a.samples, k, a.dmat, dmat_c, flags);
-    run_suffix(st, a.hist, a.hist_slots, k, a.hist_len, lmax, a.dmat, Tcnt, Tsum, a.src_sum);
+    run_suffix(st, a.hist, a.hist_slots, k, a.hist_len, lmax, a.dmat, Tcnt, Tsum, a.src_sum, nullptr);
     hipLaunchKernelGGL((k_lmask<W, MT>), dim3(k), dim3(64), 0, st, dmat_c, k, lmax, lmask);
     hipLaunchKernelGGL((k_estimate_bits<W>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, a.snap, a.plane, lmax,
                        a.fill_level, n, k, lastmask, a.sidx, a.orig, lmask, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,

@@ -148,6 +148,7 @@ struct DevGraph {
     const int32_t* rcol = nullptr;
     const int32_t* rw = nullptr;
     const int32_t* orig = nullptr;  // internal id -> caller's id
+    uint32_t delta = 1;             // delta-stepping bucket width (weighted graphs)
     // high-degree prefix [0, nh) scanned in chunks; chunk lists per pull direction
     int64_t nh = 0;
     const int32_t* hub_chunks_in = nullptr;   // over in-arcs (forward distances)
@@ -247,16 +248,13 @@ size_t bfs_plain_scratch(int64_t n);
 // Transpose source-major Dt[k][n] into node-major D[n][k].
 void transpose_dist(hipStream_t st, const void* Dt, void* D, int64_t n, int32_t k, DistKind dk);
 
-// Weighted: batched delta-stepping over groups of 64 samples, and the plain
-// single-source version.  D is int32 node-major (unreached = INT32_MAX).
-void sssp_weighted_batched(hipStream_t st, const DevGraph& g, bool reverse, const int32_t* samples_dev,
-                           int32_t k, int32_t* D, int32_t delta, void* scratch, size_t scratch_size,
-                           DevFlags* flags, LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
-size_t sssp_weighted_batched_scratch(int64_t n);
-void sssp_weighted_plain(hipStream_t st, const DevGraph& g, bool reverse, const int32_t* samples_host,
-                         int32_t k, int32_t* Dt, int32_t delta, void* scratch, size_t scratch_size,
-                         DevFlags* flags, LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
-size_t sssp_weighted_plain_scratch(int64_t n);
+// Weighted distances (positive integer lengths) from samples_dev[0..kg)
+// (internal ids) into source-major Dt[j][v] by near/far delta-stepping.
+// Returns 0 = done, 2 = some node unreached, 4 = overflow.
+int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
+                  const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
+                  size_t scratch_size, int64_t* maxd, TravStats* stats);
+size_t sssp_weighted_scratch(int64_t n, int32_t kg);
 
 // ---------------------------------------------------------------- epilogue API
 struct EpilogueArgs {
@@ -293,7 +291,8 @@ void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* si
 
 // Tail tables and exact sample sums from a histogram with `nslots` copies.
 void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int64_t hlen, int64_t maxd,
-                const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum);
+                const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum, int64_t* chunk_scratch);
+size_t suffix_chunk_scratch(int32_t k, int64_t maxd);
 
 // Epilogue over the level masks of one sample group (k <= 256, undirected).
 struct BitsEpilogueArgs {

@@ -1,18 +1,324 @@
-// Weighted single-source shortest paths (integer arc lengths >= 1).
+// Shortest paths with positive integer arc lengths (the paper's Dijkstra
+// runs, Sec. 3, with 32-bit lengths as in Sec. 8) by delta-stepping
+// (Meyer & Sanders, J. Algorithms 2003) in its near/far-pile GPU form
+// (Davidson, Baxter, Garland & Owens, IPDPS 2014), for many samples at once.
+//
+// Work items are (sample j, node v) pairs; distances are source-major,
+// Dt[j][v] (UINT32_MAX = not reached).  A round relaxes every pair of the
+// near pile (tentative distance below the window bound hi): for each arc
+// v->u of length w, cand = Dt[j][v] + w is applied with atomicMin; an
+// improved pair goes to the next near pile if cand < hi, else to the far pile.
+// When a round leaves the near pile empty, the next round splits the far
+// pile at a raised bound hi (to the first bucket that holds a far pair).
+// Label-correcting: a pair may be relaxed again after its distance drops,
+// and the result is the exact shortest distance when the piles run dry.
+//
+// Samples of one call share every round, so k samples cost about as many
+// rounds as one.  The plain mode calls the same kernel with one sample at a
+// time.
+//
+// Control without host round trips: round r reads the state round r-1 left
+// (bound, far-pile buffer, counters; three-slot rings by round) at its start,
+// so every block takes the same decision; the host enqueues rounds in batches
+// and only checks the done flag between batches.  Duplicates are kept out of
+// the piles with one bit per pair and pile.
 #include "internal.h"
 
 namespace ccg {
 
-size_t sssp_weighted_batched_scratch(int64_t n) { return 1024 + (size_t)n * 0; }
-size_t sssp_weighted_plain_scratch(int64_t n) { return 1024 + (size_t)n * 0; }
+namespace {
 
-void sssp_weighted_batched(hipStream_t, const DevGraph&, bool, const int32_t*, int32_t, int32_t*, int32_t, void*,
-                           size_t, DevFlags*, LevelCounters*, LevelCounters*, TravStats*) {
-    throw HipError{hipErrorNotSupported, "weighted traversal not built yet"};
+constexpr int kBlock = 256;
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+
+struct WState {
+    uint32_t hi;      // window bound for the round that reads this slot
+    int32_t epoch;    // far-pile epoch (number of splits so far)
+    int32_t done;
+    int32_t pad;
+};
+
+// Far pile of epoch e: buffer e % 2, size fcnt[e % 3], least distance
+// minfar[e % 3]; the split ending epoch e clears the slot of epoch e+2.
+struct WDev {
+    WState ctl[3];
+    int32_t ncnt[3];        // near pile sizes by round (mod 3)
+    int32_t fcnt[3];
+    uint32_t minfar[3];
+    int32_t overflow;
+};
+
+__device__ __forceinline__ uint64_t pair_of(int32_t j, int32_t v) { return ((uint64_t)(uint32_t)j << 32) | (uint32_t)v; }
+
+__global__ void k_winit(uint32_t* Dt, int64_t count) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        Dt[t] = kInf;
 }
-void sssp_weighted_plain(hipStream_t, const DevGraph&, bool, const int32_t*, int32_t, int32_t*, int32_t, void*, size_t,
-                         DevFlags*, LevelCounters*, LevelCounters*, TravStats*) {
-    throw HipError{hipErrorNotSupported, "weighted traversal not built yet"};
+
+__global__ void k_wzero(uint32_t* p, int64_t count) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0;
+}
+
+__global__ void k_wseed(const int32_t* samples, int32_t kg, int64_t n, uint32_t* Dt, uint32_t* inl, uint64_t* N0,
+                        WDev* dev, uint32_t delta) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < kg) {
+        const int64_t v = samples[j];
+        Dt[(int64_t)j * n + v] = 0;
+        const int64_t bit = (int64_t)j * n + v;
+        atomicOr(&inl[bit >> 5], 1u << (bit & 31));
+        N0[j] = pair_of(j, (int32_t)v);
+    }
+    if (j == 0) {
+        dev->ctl[0] = WState{delta, 0, 0, 0};
+        for (int q = 0; q < 3; q++) {
+            dev->ncnt[q] = 0;
+            dev->fcnt[q] = 0;
+            dev->minfar[q] = kInf;
+        }
+        dev->ncnt[0] = kg;
+        dev->overflow = 0;
+    }
+}
+
+// Append pairs where `pred` holds; one atomic per wave instruction.
+__device__ __forceinline__ void pile_append(uint64_t* pile, int32_t* count, int64_t cap, bool pred, uint64_t item,
+                                            int32_t* overflow) {
+    const int pos = wave_append(count, pred);
+    if (pred) {
+        if (pos < cap) pile[pos] = item;
+        else *overflow = 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wround(const uint32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ wt, int64_t n, uint32_t* Dt,
+                                                   uint32_t* inl, uint32_t* fbit, uint64_t* N0, uint64_t* N1,
+                                                   uint64_t* F0, uint64_t* F1, int64_t cap, WDev* dev, int32_t r,
+                                                   uint32_t delta) {
+    // ---- control for this round, from what round r-1 left
+    const WState c = dev->ctl[(r + 2) % 3];
+    if (c.done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) dev->ctl[r % 3] = c;  // keep the flag moving round to round
+        return;
+    }
+    // counts can exceed the pile capacity only after an overflow (flagged to
+    // the host); never read past the piles
+    const int32_t n_in = (int32_t)std::min<int64_t>(dev->ncnt[(r + 2) % 3], cap);
+    const int32_t ep = c.epoch;
+    const int32_t f_in = (int32_t)std::min<int64_t>(dev->fcnt[ep % 3], cap);
+    const bool split = n_in == 0;
+    uint32_t hi = c.hi;
+    if (split) {
+        if (f_in == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) dev->ctl[r % 3] = WState{hi, ep, 1, 0};
+            return;
+        }
+        const uint32_t mf = dev->minfar[ep % 3];
+        const uint64_t next = ((uint64_t)mf / delta + 1) * (uint64_t)delta;
+        const uint64_t step = (uint64_t)hi + delta;
+        const uint64_t h = next > step ? next : step;
+        hi = h > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)h;
+    }
+    uint64_t* nin = (r - 1) % 2 == 0 ? N0 : N1;
+    uint64_t* nout = r % 2 == 0 ? N0 : N1;
+    int32_t* ncnt_out = &dev->ncnt[r % 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dev->ctl[r % 3] = WState{hi, split ? ep + 1 : ep, 0, 0};
+        dev->ncnt[(r + 1) % 3] = 0;  // output counter of round r+1 (read by round r-1, now idle)
+        if (split) {                 // slot of epoch ep+2 (last used by epoch ep-1)
+            dev->fcnt[(ep + 2) % 3] = 0;
+            dev->minfar[(ep + 2) % 3] = kInf;
+        }
+    }
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * kBlock;
+    if (split) {
+        // far pile of epoch ep -> near pile (below hi) or far pile of epoch ep+1
+        uint64_t* fin = ep % 2 == 0 ? F0 : F1;
+        uint64_t* fout = ep % 2 == 0 ? F1 : F0;
+        uint32_t lmin = kInf;
+        const int64_t iters = (f_in + nthreads - 1) / nthreads;
+        for (int64_t it = 0; it < iters; it++) {
+            const int64_t t = tid + it * nthreads;
+            const bool ok = t < f_in;
+            uint64_t item = 0;
+            bool to_near = false, to_far = false;
+            if (ok) {
+                item = fin[t];
+                const int64_t bit = (int64_t)(item >> 32) * n + (uint32_t)item;
+                atomicAnd(&fbit[bit >> 5], ~(1u << (bit & 31)));
+                const uint32_t d = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (d < hi) {
+                    const uint32_t old = atomicOr(&inl[bit >> 5], 1u << (bit & 31));
+                    to_near = !(old & (1u << (bit & 31)));
+                } else {
+                    const uint32_t old = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
+                    to_far = !(old & (1u << (bit & 31)));
+                    if (to_far) lmin = d < lmin ? d : lmin;
+                }
+            }
+            pile_append(nout, ncnt_out, cap, to_near, item, &dev->overflow);
+            pile_append(fout, &dev->fcnt[(ep + 1) % 3], cap, to_far, item, &dev->overflow);
+        }
+        if (lmin != kInf) atomicMin(&dev->minfar[(ep + 1) % 3], lmin);
+        return;
+    }
+    // near round: relax every pair of the near pile
+    uint64_t* fpile = ep % 2 == 0 ? F0 : F1;
+    uint32_t lmin = kInf;
+    const int64_t iters = (n_in + nthreads - 1) / nthreads;
+    for (int64_t it = 0; it < iters; it++) {
+        const int64_t t = tid + it * nthreads;
+        const bool ok = t < n_in;
+        int32_t j = 0, v = 0;
+        uint32_t d = kInf;
+        uint32_t b = 0, e = 0;
+        if (ok) {
+            const uint64_t item = nin[t];
+            j = (int32_t)(item >> 32);
+            v = (int32_t)(uint32_t)item;
+            const int64_t bit = (int64_t)j * n + v;
+            atomicAnd(&inl[bit >> 5], ~(1u << (bit & 31)));
+            d = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b = rp[v];
+            e = rp[v + 1];
+        }
+        uint32_t* drow = Dt + (int64_t)j * n;
+        // lanes walk their own adjacency; appends are aggregated per step
+        uint32_t maxlen = e - b;
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)maxlen, off);
+            maxlen = o > maxlen ? o : maxlen;
+        }
+        for (uint32_t s = 0; s < maxlen; s++) {
+            bool to_near = false, to_far = false;
+            uint64_t item = 0;
+            if (s < e - b) {
+                const int32_t u = col[b + s];
+                const uint64_t cand64 = (uint64_t)d + (uint32_t)wt[b + s];
+                const uint32_t cand = cand64 >= kInf ? kInf - 1 : (uint32_t)cand64;
+                if (cand64 >= kInf) dev->overflow = 1;
+                if (cand < drow[u]) {
+                    const uint32_t old = atomicMin(&drow[u], cand);
+                    if (cand < old) {
+                        const int64_t bit = (int64_t)j * n + u;
+                        item = pair_of(j, u);
+                        if (cand < hi) {
+                            const uint32_t ob = atomicOr(&inl[bit >> 5], 1u << (bit & 31));
+                            to_near = !(ob & (1u << (bit & 31)));
+                        } else {
+                            const uint32_t ob = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
+                            to_far = !(ob & (1u << (bit & 31)));
+                            lmin = cand < lmin ? cand : lmin;
+                        }
+                    }
+                }
+            }
+            pile_append(nout, ncnt_out, cap, to_near, item, &dev->overflow);
+            pile_append(fpile, &dev->fcnt[ep % 3], cap, to_far, item, &dev->overflow);
+        }
+    }
+    if (lmin != kInf) atomicMin(&dev->minfar[ep % 3], lmin);
+}
+
+__global__ void k_wmax(const uint32_t* Dt, int64_t count, uint32_t* out, int32_t* unreached) {
+    uint32_t m = 0;
+    bool un = false;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t d = Dt[t];
+        if (d == kInf) un = true;
+        else m = d > m ? d : m;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)m, off);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0) atomicMax(out, m);
+    if (un) *unreached = 1;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+size_t sssp_weighted_scratch(int64_t n, int32_t kg) {
+    const int64_t pairs = n * kg;
+    return align256(sizeof(WDev)) + 2 * align256((size_t)((pairs + 31) / 32) * 4) + 4 * align256((size_t)pairs * 8) +
+           align256(16) + 1024;
+}
+
+// Distances from samples[0..kg) (device, internal ids) into Dt[j][v] (device,
+// source-major rows of length n).  Returns 0 = done, 2 = unreached node,
+// 4 = overflow (distance or pile capacity).
+int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
+                  const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
+                  size_t scratch_size, int64_t* maxd, TravStats* stats) {
+    if (scratch_size < sssp_weighted_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted scratch"};
+    const int64_t pairs = n * kg;
+    char* p = (char*)scratch;
+    WDev* dev = (WDev*)p;
+    p += align256(sizeof(WDev));
+    uint32_t* inl = (uint32_t*)p;
+    p += align256((size_t)((pairs + 31) / 32) * 4);
+    uint32_t* fbit = (uint32_t*)p;
+    p += align256((size_t)((pairs + 31) / 32) * 4);
+    uint64_t* N0 = (uint64_t*)p;
+    p += align256((size_t)pairs * 8);
+    uint64_t* N1 = (uint64_t*)p;
+    p += align256((size_t)pairs * 8);
+    uint64_t* F0 = (uint64_t*)p;
+    p += align256((size_t)pairs * 8);
+    uint64_t* F1 = (uint64_t*)p;
+    p += align256((size_t)pairs * 8);
+    uint32_t* mx = (uint32_t*)p;
+    if (delta < 1) delta = 1;
+
+    const int64_t words = (pairs + 31) / 32;
+    const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_winit, dim3(gz), dim3(256), 0, st, Dt, pairs);
+    hipLaunchKernelGGL(k_wzero, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0, st, inl,
+                       words);
+    hipLaunchKernelGGL(k_wzero, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0, st, fbit,
+                       words);
+    hipLaunchKernelGGL(k_wseed, dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, n, Dt, inl, N0, dev, delta);
+    stats->launches += 4;
+
+    // rounds in batches; the host checks the done flag between batches
+    WDev host;
+    KernelTimer kt;
+    int32_t r = 1;
+    int batch = 16;
+    // every round settles or moves at least one pair; far more rounds than
+    // pairs means the control state is broken -- stop instead of spinning
+    const int64_t max_rounds = std::min<int64_t>(4 * n + 10000, (int64_t)1 << 22);
+    for (;;) {
+        kt.start(st);
+        for (int q = 0; q < batch; q++, r++) {
+            hipLaunchKernelGGL(k_wround, dim3(1024), dim3(kBlock), 0, st, rp, col, w, n, Dt, inl, fbit, N0, N1, F0, F1,
+                               pairs, dev, r, delta);
+        }
+        CCG_HIP(hipGetLastError());
+        kt.stop(st);
+        CCG_HIP(hipMemcpyAsync(&host, dev, sizeof(WDev), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        stats->kernel_ms += kt.ms();
+        stats->kernel_launches += batch;
+        stats->launches += batch;
+        if (host.overflow) return 4;
+        if (host.ctl[(r + 2) % 3].done) break;  // the last round enqueued found nothing to do
+        if (r > max_rounds) return 4;
+        if (batch < 256) batch *= 2;
+    }
+    stats->levels += r - 1;
+    hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, mx, (int64_t)2);
+    hipLaunchKernelGGL(k_wmax, dim3(gz), dim3(256), 0, st, Dt, pairs, mx, (int32_t*)(mx + 1));
+    uint32_t hm[2];
+    CCG_HIP(hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, st));
+    CCG_HIP(hipStreamSynchronize(st));
+    *maxd = std::max<int64_t>(*maxd, hm[0]);
+    return hm[1] ? 2 : 0;
 }
 
 }  // namespace ccg

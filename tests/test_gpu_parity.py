@@ -187,3 +187,42 @@ def test_device_outputs_on_torch_stream(ctx):
         assert t["total_ms"] > 0 and t["levels"] > 0
     finally:
         ctx.release(gh)
+
+
+# ---------------------------------------------------------------- weighted
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weighted_random_graphs(ctx, seed):
+    rng = np.random.default_rng(50 + seed)
+    n = int(rng.integers(2, 150))
+    directed = seed % 3 == 2
+    g = graphgen.gnp(n, float(rng.uniform(0.02, 0.1)), 50 + seed, directed=directed,
+                     wmax=[3, 1000, 50][seed % 3])
+    k = int(rng.integers(1, min(n, 70) + 1))
+    parity(ctx, g, k, seed, eps=[(1, 2), None, (2, 3)][seed % 3])
+
+
+def test_weighted_grid8(ctx):
+    """8-neighbour grid, 10% of edges deleted, lengths in [1, 1000] -- the
+    weighted workload's structure at 96 x 80."""
+    g = graphgen.grid(96, 80, 8, 0.10, 1, 1000, seed=3)
+    parity(ctx, g, 64, seed=3)
+
+
+def test_weighted_unit_lengths_match_bfs(ctx):
+    g = graphgen.ba(1500, 3, seed=8)
+    gw = graphgen.Graph(g.n, g.row_ptr, g.col_idx, np.ones(g.arcs, np.int32), name="ba-unit-w")
+    a = run_gpu(ctx, g, 40, cc.CC_BATCHED, seed=5)
+    b = run_gpu(ctx, gw, 40, cc.CC_BATCHED, seed=5)
+    for f in ("D", "pivot", "delta", "sampsum", "dmat", "src_sum", "S_piv", "S_pub"):
+        assert (a[f] == b[f]).all(), f
+    assert (a["S_hyb"] == b["S_hyb"]).all()
+
+
+def test_weighted_deep_path(ctx):
+    """Long path with lengths up to 1000: many delta-stepping buckets."""
+    n = 900
+    i = np.arange(n - 1, dtype=np.int32)
+    w = (np.arange(n - 1) * 7919 % 1000 + 1).astype(np.int32)
+    g = graphgen.csr_from_arcs(n, i, i + 1, w, name="wpath900")
+    parity(ctx, g, 5, seed=2)
