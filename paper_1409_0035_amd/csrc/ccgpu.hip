@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -219,6 +220,7 @@ struct cc_context {
     int inflight = 0;
     bool stopping = false;
     bool service_started = false;
+    int wgrid = -1;  // blocks of the persistent weighted launch (0 = unavailable), found on first use
 };
 
 static void graph_unref(cc_graph* g) {
@@ -452,7 +454,9 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             double sw = 0;
             for (int64_t e = 0; e < arcs; e++) sw += w[e];
             const double mean = arcs > 0 ? sw / (double)arcs : 1.0;
-            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(2.0 * mean));
+            double mult = 2.0;
+            if (const char* e = std::getenv("CCGPU_DELTA_MULT")) mult = std::atof(e);
+            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(mult * mean));
         }
         std::vector<int32_t> ch_in = hub_chunk_list(prp, nh);
         std::vector<int32_t> ch_out = directed ? hub_chunk_list(rp, nh) : std::vector<int32_t>();
@@ -635,7 +639,6 @@ void fill_epilogue_outputs(EpilogueArgs& ea, const cc_result* out, int64_t* src_
 // Runs the whole pipeline on lane `L`; `out` holds DEVICE pointers (caller's node ids).
 cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const cc_result* out, Lane& L,
                   cc_timing* timing) {
-    (void)ctx;
     const DevGraph& g = gr->dg;
     const int64_t n = g.n;
     const int32_t k = r.k;
@@ -721,10 +724,17 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 int64_t md = 0;
                 for (int32_t s0 = 0; s0 < k && rc == 0; s0 += kw) {
                     const int32_t kg = std::min(kw, k - s0);
+                    // the all-rounds cooperative launch pays agent-scope fences at
+                    // every barrier and measures slower than one launch per round;
+                    // it is kept for experiments behind CCGPU_PERSISTENT=1
+                    if (ctx->wgrid < 0)
+                        ctx->wgrid = std::getenv("CCGPU_PERSISTENT") ? weighted_persistent_grid(ctx->device) : 0;
                     const int wr = sssp_weighted(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
-                                                 (uint32_t*)Dt + (size_t)s0 * n, g.delta, ts, trav_scratch, &md, &ds);
+                                                 (uint32_t*)Dt + (size_t)s0 * n, g.delta, ts, trav_scratch, &md, &ds,
+                                                 ctx->wgrid);
                     if (wr == 2) rc = 2;
-                    else if (wr == 4) return fail(CC_EOVERFLOW, "a weighted distance does not fit in 32 bits");
+                    else if (wr == 4) return fail(CC_EOVERFLOW, "a weighted distance or work pile overflowed");
+                    else if (wr == 5) return fail(CC_EDEVICE, "a grid barrier wait expired");
                 }
                 if (rc == 0) transpose_dist(st, Dt, Dd, n, k, dk);
                 lmax_dir[dir] = (int32_t)std::min<int64_t>(md, INT32_MAX);

@@ -116,6 +116,63 @@ __device__ __forceinline__ int wave_append(int32_t* counter, bool pred) {
     return pred ? base + (int)__popcll(m & lanemask_lt()) : -1;
 }
 
+// ---------------------------------------------------------------- grid barrier
+// Barrier across all blocks of a persistent launch (every block resident: the
+// launch goes through hipLaunchCooperativeKernel, which refuses grids that do
+// not fit).  Two levels: blocks arrive on one of kBarGroups counters, the
+// last of each group on the top counter, the last overall bumps the
+// generation everyone waits on.  Waits are bounded: after about two seconds
+// of spinning a block raises `abort`, every block leaves at its next barrier
+// and the host reports a device error instead of hanging.
+constexpr int kBarGroups = 8;
+
+struct GridSync {
+    uint32_t group[kBarGroups][32];  // one cache line each
+    uint32_t top[32];
+    uint32_t gen[32];
+    uint32_t abort[32];
+};
+
+__device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t nblocks) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (__hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            __threadfence();
+            const uint32_t g = __hip_atomic_load(&gs->gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t grp = blockIdx.x % kBarGroups;
+            const uint32_t in_grp = nblocks / kBarGroups + (grp < nblocks % kBarGroups ? 1u : 0u);
+            const uint32_t ngroups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
+            bool last = false;
+            if (__hip_atomic_fetch_add(&gs->group[grp][0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                in_grp - 1) {
+                __hip_atomic_store(&gs->group[grp][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__hip_atomic_fetch_add(&gs->top[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                    ngroups - 1) {
+                    __hip_atomic_store(&gs->top[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&gs->gen[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    last = true;
+                }
+            }
+            if (!last) {
+                uint64_t spins = 0;
+                while (__hip_atomic_load(&gs->gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > (1ull << 25)) {
+                        __hip_atomic_store(&gs->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    if ((spins & 255) == 0 &&
+                        __hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                        break;
+                }
+            }
+            __threadfence();
+        }
+    }
+    __syncthreads();
+    return __hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
+
 // ---------------------------------------------------------------- distances
 template <typename DT> struct DistT;
 template <> struct DistT<uint8_t> {
@@ -253,7 +310,9 @@ void transpose_dist(hipStream_t st, const void* Dt, void* D, int64_t n, int32_t 
 // Returns 0 = done, 2 = some node unreached, 4 = overflow.
 int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
                   const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
-                  size_t scratch_size, int64_t* maxd, TravStats* stats);
+                  size_t scratch_size, int64_t* maxd, TravStats* stats, int persistent_grid);
+// Blocks for the all-rounds cooperative launch on `device` (0 = not available).
+int weighted_persistent_grid(int device);
 size_t sssp_weighted_scratch(int64_t n, int32_t kg);
 
 // ---------------------------------------------------------------- epilogue API

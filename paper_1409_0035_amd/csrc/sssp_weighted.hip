@@ -82,32 +82,119 @@ __global__ void k_wseed(const int32_t* samples, int32_t kg, int64_t n, uint32_t*
     }
 }
 
-// Append pairs where `pred` holds; one atomic per wave instruction.
-__device__ __forceinline__ void pile_append(uint64_t* pile, int32_t* count, int64_t cap, bool pred, uint64_t item,
-                                            int32_t* overflow) {
-    const int pos = wave_append(count, pred);
-    if (pred) {
-        if (pos < cap) pile[pos] = item;
-        else *overflow = 1;
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)x, off);
+        x = o < x ? o : x;
     }
+    return x;
 }
 
-__global__ __launch_bounds__(kBlock) void k_wround(const uint32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                   const int32_t* __restrict__ wt, int64_t n, uint32_t* Dt,
-                                                   uint32_t* inl, uint32_t* fbit, uint64_t* N0, uint64_t* N1,
-                                                   uint64_t* F0, uint64_t* F1, int64_t cap, WDev* dev, int32_t r,
-                                                   uint32_t delta) {
+// Pile appends are staged in LDS per block and reserved in the global pile
+// with one atomic per block and flush (thousands of waves appending to one
+// counter would serialise on it).
+constexpr int kStage = 2048;
+
+struct Stage {
+    uint64_t item[2][kStage];
+    int32_t count[2];
+    int32_t base[2];
+};
+
+__device__ __forceinline__ void stage_put(Stage& S, int q, bool pred, uint64_t item) {
+    const uint64_t m = __ballot(pred);
+    if (!m) return;
+    const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(&S.count[q], (int32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) S.item[q][base + (int)__popcll(m & lanemask_lt())] = item;
+}
+
+// block-uniform: copies the staged items to the global piles and empties the stage
+__device__ __forceinline__ void stage_flush(Stage& S, uint64_t* pile0, int32_t* cnt0, uint64_t* pile1, int32_t* cnt1,
+                                            int64_t cap, int32_t* overflow) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S.base[0] = S.count[0] ? atomicAdd(cnt0, S.count[0]) : 0;
+        S.base[1] = S.count[1] ? atomicAdd(cnt1, S.count[1]) : 0;
+    }
+    __syncthreads();
+    for (int q = 0; q < 2; q++) {
+        uint64_t* pile = q == 0 ? pile0 : pile1;
+        for (int t = threadIdx.x; t < S.count[q]; t += kBlock) {
+            const int64_t pos = (int64_t)S.base[q] + t;
+            if (pos < cap) pile[pos] = S.item[q][t];
+            else *overflow = 1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S.count[0] = 0;
+        S.count[1] = 0;
+    }
+    __syncthreads();
+}
+
+// block-uniform: flush when another step could overfill the stage
+__device__ __forceinline__ void stage_maybe_flush(Stage& S, uint64_t* pile0, int32_t* cnt0, uint64_t* pile1,
+                                                  int32_t* cnt1, int64_t cap, int32_t* overflow) {
+    __syncthreads();
+    const bool full = S.count[0] > kStage - kBlock || S.count[1] > kStage - kBlock;
+    __syncthreads();
+    if (full) stage_flush(S, pile0, cnt0, pile1, cnt1, cap, overflow);
+}
+
+struct WArgs {
+    const uint32_t* rp;
+    const int32_t* col;
+    const int32_t* wt;
+    int64_t n;
+    uint32_t* Dt;
+    uint32_t* inl;
+    uint32_t* fbit;
+    uint64_t* N0;
+    uint64_t* N1;
+    uint64_t* F0;
+    uint64_t* F1;
+    int64_t cap;
+    WDev* dev;
+    uint32_t delta;
+};
+
+// One round (block-uniform control flow; every block returns normally).
+__device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S, uint32_t* smax, uint64_t* Wloc) {
+    const uint32_t* __restrict__ rp = A.rp;
+    const int32_t* __restrict__ col = A.col;
+    const int32_t* __restrict__ wt = A.wt;
+    const int64_t n = A.n;
+    uint32_t* Dt = A.Dt;
+    uint32_t* inl = A.inl;
+    uint32_t* fbit = A.fbit;
+    uint64_t* N0 = A.N0;
+    uint64_t* N1 = A.N1;
+    uint64_t* F0 = A.F0;
+    uint64_t* F1 = A.F1;
+    const int64_t cap = A.cap;
+    WDev* dev = A.dev;
+    const uint32_t delta = A.delta;
     // ---- control for this round, from what round r-1 left
-    const WState c = dev->ctl[(r + 2) % 3];
+    WState c;
+    c.hi = __hip_atomic_load(&dev->ctl[(r + 2) % 3].hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.epoch = __hip_atomic_load(&dev->ctl[(r + 2) % 3].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.done = __hip_atomic_load(&dev->ctl[(r + 2) % 3].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.pad = 0;
     if (c.done) {
         if (blockIdx.x == 0 && threadIdx.x == 0) dev->ctl[r % 3] = c;  // keep the flag moving round to round
         return;
     }
     // counts can exceed the pile capacity only after an overflow (flagged to
     // the host); never read past the piles
-    const int32_t n_in = (int32_t)std::min<int64_t>(dev->ncnt[(r + 2) % 3], cap);
+    const int32_t n_in = (int32_t)std::min<int64_t>(
+        __hip_atomic_load(&dev->ncnt[(r + 2) % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), cap);
     const int32_t ep = c.epoch;
-    const int32_t f_in = (int32_t)std::min<int64_t>(dev->fcnt[ep % 3], cap);
+    const int32_t f_in = (int32_t)std::min<int64_t>(
+        __hip_atomic_load(&dev->fcnt[ep % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), cap);
     const bool split = n_in == 0;
     uint32_t hi = c.hi;
     if (split) {
@@ -115,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_wround(const uint32_t* __restrict__ 
             if (blockIdx.x == 0 && threadIdx.x == 0) dev->ctl[r % 3] = WState{hi, ep, 1, 0};
             return;
         }
-        const uint32_t mf = dev->minfar[ep % 3];
+        const uint32_t mf = __hip_atomic_load(&dev->minfar[ep % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t next = ((uint64_t)mf / delta + 1) * (uint64_t)delta;
         const uint64_t step = (uint64_t)hi + delta;
         const uint64_t h = next > step ? next : step;
@@ -132,20 +219,27 @@ __global__ __launch_bounds__(kBlock) void k_wround(const uint32_t* __restrict__ 
             dev->minfar[(ep + 2) % 3] = kInf;
         }
     }
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * kBlock;
+    const int64_t items = split ? f_in : n_in;
+    const int64_t per_block = ((items + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = std::min<int64_t>(b0 + per_block, items);
+    if (b0 >= b1) return;  // block-uniform: nothing for this block
+    if (threadIdx.x == 0) {
+        S.count[0] = 0;
+        S.count[1] = 0;
+    }
+    __syncthreads();
+    uint32_t lmin = kInf;
     if (split) {
         // far pile of epoch ep -> near pile (below hi) or far pile of epoch ep+1
         uint64_t* fin = ep % 2 == 0 ? F0 : F1;
         uint64_t* fout = ep % 2 == 0 ? F1 : F0;
-        uint32_t lmin = kInf;
-        const int64_t iters = (f_in + nthreads - 1) / nthreads;
-        for (int64_t it = 0; it < iters; it++) {
-            const int64_t t = tid + it * nthreads;
-            const bool ok = t < f_in;
+        int32_t* fcnt_out = &dev->fcnt[(ep + 1) % 3];
+        for (int64_t base = b0; base < b1; base += kBlock) {
+            const int64_t t = base + threadIdx.x;
             uint64_t item = 0;
             bool to_near = false, to_far = false;
-            if (ok) {
+            if (t < b1) {
                 item = fin[t];
                 const int64_t bit = (int64_t)(item >> 32) * n + (uint32_t)item;
                 atomicAnd(&fbit[bit >> 5], ~(1u << (bit & 31)));
@@ -159,71 +253,124 @@ __global__ __launch_bounds__(kBlock) void k_wround(const uint32_t* __restrict__ 
                     if (to_far) lmin = d < lmin ? d : lmin;
                 }
             }
-            pile_append(nout, ncnt_out, cap, to_near, item, &dev->overflow);
-            pile_append(fout, &dev->fcnt[(ep + 1) % 3], cap, to_far, item, &dev->overflow);
+            stage_put(S, 0, to_near, item);
+            stage_put(S, 1, to_far, item);
+            stage_maybe_flush(S, nout, ncnt_out, fout, fcnt_out, cap, &dev->overflow);
         }
-        if (lmin != kInf) atomicMin(&dev->minfar[(ep + 1) % 3], lmin);
+        stage_flush(S, nout, ncnt_out, fout, fcnt_out, cap, &dev->overflow);
+        lmin = wave_min_u32(lmin);
+        if (lane_id() == 0 && lmin != kInf) atomicMin(&dev->minfar[(ep + 1) % 3], lmin);
         return;
     }
-    // near round: relax every pair of the near pile
+    // near round: relax every pair of the near pile; kPairLanes lanes per
+    // pair, each taking every kPairLanes-th arc, so a round costs about one
+    // chain of dependent atomics instead of one per arc.  Pairs a block finds
+    // below the bound are then relaxed by the same block from its stage for up
+    // to kLocalIters more passes before anything is flushed: relaxations may
+    // run in any order (label correcting), and improvements travel many hops
+    // per launch instead of one.
     uint64_t* fpile = ep % 2 == 0 ? F0 : F1;
-    uint32_t lmin = kInf;
-    const int64_t iters = (n_in + nthreads - 1) / nthreads;
-    for (int64_t it = 0; it < iters; it++) {
-        const int64_t t = tid + it * nthreads;
-        const bool ok = t < n_in;
-        int32_t j = 0, v = 0;
-        uint32_t d = kInf;
-        uint32_t b = 0, e = 0;
-        if (ok) {
-            const uint64_t item = nin[t];
-            j = (int32_t)(item >> 32);
-            v = (int32_t)(uint32_t)item;
-            const int64_t bit = (int64_t)j * n + v;
-            atomicAnd(&inl[bit >> 5], ~(1u << (bit & 31)));
-            d = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            b = rp[v];
-            e = rp[v + 1];
-        }
-        uint32_t* drow = Dt + (int64_t)j * n;
-        // lanes walk their own adjacency; appends are aggregated per step
-        uint32_t maxlen = e - b;
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint32_t o = (uint32_t)__shfl_xor((int)maxlen, off);
-            maxlen = o > maxlen ? o : maxlen;
-        }
-        for (uint32_t s = 0; s < maxlen; s++) {
-            bool to_near = false, to_far = false;
-            uint64_t item = 0;
-            if (s < e - b) {
-                const int32_t u = col[b + s];
-                const uint64_t cand64 = (uint64_t)d + (uint32_t)wt[b + s];
-                const uint32_t cand = cand64 >= kInf ? kInf - 1 : (uint32_t)cand64;
-                if (cand64 >= kInf) dev->overflow = 1;
-                if (cand < drow[u]) {
-                    const uint32_t old = atomicMin(&drow[u], cand);
-                    if (cand < old) {
-                        const int64_t bit = (int64_t)j * n + u;
-                        item = pair_of(j, u);
-                        if (cand < hi) {
-                            const uint32_t ob = atomicOr(&inl[bit >> 5], 1u << (bit & 31));
-                            to_near = !(ob & (1u << (bit & 31)));
-                        } else {
-                            const uint32_t ob = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
-                            to_far = !(ob & (1u << (bit & 31)));
-                            lmin = cand < lmin ? cand : lmin;
+    int32_t* fcnt_cur = &dev->fcnt[ep % 3];
+    constexpr int kPairLanes = 8;
+    constexpr int kLocalIters = 64;
+    const int sub = threadIdx.x & (kPairLanes - 1);
+    auto relax_batch = [&](auto fetch, int64_t lo, int64_t hi_ix) {
+        for (int64_t base = lo; base < hi_ix; base += kBlock / kPairLanes) {
+            const int64_t t = base + threadIdx.x / kPairLanes;
+            int32_t j = 0, v = 0;
+            uint32_t d = kInf, b = 0, e = 0;
+            if (t < hi_ix) {
+                const uint64_t item = fetch(t);
+                j = (int32_t)(item >> 32);
+                v = (int32_t)(uint32_t)item;
+                const int64_t bit = (int64_t)j * n + v;
+                if (sub == 0) {
+                    atomicAnd(&inl[bit >> 5], ~(1u << (bit & 31)));
+                    d = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                b = rp[v];
+                e = rp[v + 1];
+            }
+            d = (uint32_t)__shfl((int)d, lane_id() & ~(kPairLanes - 1));
+            uint32_t* drow = Dt + (int64_t)j * n;
+            uint32_t mx = e - b;
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint32_t o = (uint32_t)__shfl_xor((int)mx, off);
+                mx = o > mx ? o : mx;
+            }
+            if (lane_id() == 0) smax[threadIdx.x >> 6] = mx;
+            __syncthreads();
+            uint32_t maxlen = 0;
+            for (int w = 0; w < kBlock / 64; w++) maxlen = smax[w] > maxlen ? smax[w] : maxlen;
+            __syncthreads();
+            for (uint32_t s0 = 0; s0 < maxlen; s0 += kPairLanes) {
+                const uint32_t s = s0 + sub;
+                bool to_near = false, to_far = false;
+                uint64_t item = 0;
+                if (s < e - b) {
+                    const int32_t u = col[b + s];
+                    const uint64_t cand64 = (uint64_t)d + (uint32_t)wt[b + s];
+                    const uint32_t cand = cand64 >= kInf ? kInf - 1 : (uint32_t)cand64;
+                    if (cand64 >= kInf) dev->overflow = 1;
+                    if (cand < drow[u]) {
+                        const uint32_t old = atomicMin(&drow[u], cand);
+                        if (cand < old) {
+                            const int64_t bit = (int64_t)j * n + u;
+                            item = pair_of(j, u);
+                            if (cand < hi) {
+                                const uint32_t ob = atomicOr(&inl[bit >> 5], 1u << (bit & 31));
+                                to_near = !(ob & (1u << (bit & 31)));
+                            } else {
+                                const uint32_t ob = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
+                                to_far = !(ob & (1u << (bit & 31)));
+                                lmin = cand < lmin ? cand : lmin;
+                            }
                         }
                     }
                 }
+                stage_put(S, 0, to_near, item);
+                stage_put(S, 1, to_far, item);
+                stage_maybe_flush(S, nout, ncnt_out, fpile, fcnt_cur, cap, &dev->overflow);
             }
-            pile_append(nout, ncnt_out, cap, to_near, item, &dev->overflow);
-            pile_append(fpile, &dev->fcnt[ep % 3], cap, to_far, item, &dev->overflow);
         }
+    };
+    relax_batch([&](int64_t t) { return nin[t]; }, b0, b1);
+    for (int li = 0; li < kLocalIters; li++) {
+        __syncthreads();
+        const int32_t cnt = S.count[0];
+        if (cnt == 0) break;  // block-uniform
+        for (int t = threadIdx.x; t < cnt; t += kBlock) Wloc[t] = S.item[0][t];
+        __syncthreads();
+        if (threadIdx.x == 0) S.count[0] = 0;
+        __syncthreads();
+        relax_batch([&](int64_t t) { return Wloc[t]; }, 0, cnt);
     }
-    if (lmin != kInf) atomicMin(&dev->minfar[ep % 3], lmin);
+    stage_flush(S, nout, ncnt_out, fpile, fcnt_cur, cap, &dev->overflow);
+    lmin = wave_min_u32(lmin);
+    if (lane_id() == 0 && lmin != kInf) atomicMin(&dev->minfar[ep % 3], lmin);
+}
+
+__global__ __launch_bounds__(kBlock) void k_wround(WArgs A, int32_t r) {
+    __shared__ Stage S;
+    __shared__ uint32_t smax[kBlock / 64];
+    __shared__ uint64_t Wloc[kStage];
+    wround_body(A, r, S, smax, Wloc);
+}
+
+// All rounds in one launch; rounds are separated by a grid barrier.
+__global__ __launch_bounds__(kBlock) void k_wpersist(WArgs A, GridSync* gs, int32_t rmax) {
+    __shared__ Stage S;
+    __shared__ uint32_t smax[kBlock / 64];
+    __shared__ uint64_t Wloc[kStage];
+    for (int32_t r = 1; r < rmax; r++) {
+        wround_body(A, r, S, smax, Wloc);
+        if (!grid_barrier(gs, gridDim.x)) return;
+        if (__hip_atomic_load(&A.dev->ctl[r % 3].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    }
 }
 
 __global__ void k_wmax(const uint32_t* Dt, int64_t count, uint32_t* out, int32_t* unreached) {
+    __shared__ uint32_t bm[4];
     uint32_t m = 0;
     bool un = false;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
@@ -235,7 +382,13 @@ __global__ void k_wmax(const uint32_t* Dt, int64_t count, uint32_t* out, int32_t
         const uint32_t o = (uint32_t)__shfl_xor((int)m, off);
         m = o > m ? o : m;
     }
-    if (lane_id() == 0) atomicMax(out, m);
+    if (lane_id() == 0) bm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = bm[w] > m ? bm[w] : m;
+        m = bm[0] > m ? bm[0] : m;
+        atomicMax(out, m);
+    }
     if (un) *unreached = 1;
 }
 
@@ -246,15 +399,26 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t sssp_weighted_scratch(int64_t n, int32_t kg) {
     const int64_t pairs = n * kg;
     return align256(sizeof(WDev)) + 2 * align256((size_t)((pairs + 31) / 32) * 4) + 4 * align256((size_t)pairs * 8) +
-           align256(16) + 1024;
+           align256(16) + align256(sizeof(GridSync)) + 1024;
 }
 
 // Distances from samples[0..kg) (device, internal ids) into Dt[j][v] (device,
 // source-major rows of length n).  Returns 0 = done, 2 = unreached node,
-// 4 = overflow (distance or pile capacity).
+// 4 = overflow (distance or pile capacity), 5 = a bounded wait expired.
+// persistent_grid > 0 runs every round in one cooperative launch of that
+// many blocks; otherwise (or if the launch is refused) one launch per round.
+
+int weighted_persistent_grid(int device) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_wpersist, kBlock, 0) != hipSuccess) return 0;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+    return cus * std::max(1, std::min(per, 2));
+}
 int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
                   const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
-                  size_t scratch_size, int64_t* maxd, TravStats* stats) {
+                  size_t scratch_size, int64_t* maxd, TravStats* stats, int persistent_grid) {
     if (scratch_size < sssp_weighted_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted scratch"};
     const int64_t pairs = n * kg;
     char* p = (char*)scratch;
@@ -273,6 +437,8 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     uint64_t* F1 = (uint64_t*)p;
     p += align256((size_t)pairs * 8);
     uint32_t* mx = (uint32_t*)p;
+    p += align256(16);
+    GridSync* gsync = (GridSync*)p;
     if (delta < 1) delta = 1;
 
     const int64_t words = (pairs + 31) / 32;
@@ -285,19 +451,46 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     hipLaunchKernelGGL(k_wseed, dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, n, Dt, inl, N0, dev, delta);
     stats->launches += 4;
 
-    // rounds in batches; the host checks the done flag between batches
+    WArgs A{rp, col, w, n, Dt, inl, fbit, N0, N1, F0, F1, pairs, dev, delta};
     WDev host;
     KernelTimer kt;
-    int32_t r = 1;
-    int batch = 16;
     // every round settles or moves at least one pair; far more rounds than
     // pairs means the control state is broken -- stop instead of spinning
     const int64_t max_rounds = std::min<int64_t>(4 * n + 10000, (int64_t)1 << 22);
+
+    // preferred: all rounds in one cooperative (co-resident) launch
+    if (persistent_grid > 0) {
+        hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, (uint32_t*)gsync, (int64_t)(sizeof(GridSync) / 4));
+        int32_t rmax = (int32_t)max_rounds;
+        void* args[] = {&A, &gsync, &rmax};
+        kt.start(st);
+        const hipError_t e = hipLaunchCooperativeKernel((const void*)k_wpersist, dim3(persistent_grid), dim3(kBlock),
+                                                        args, 0, st);
+        if (e == hipSuccess) {
+            kt.stop(st);
+            GridSync gh;
+            CCG_HIP(hipMemcpyAsync(&host, dev, sizeof(WDev), hipMemcpyDeviceToHost, st));
+            CCG_HIP(hipMemcpyAsync(&gh.abort[0], &gsync->abort[0], 4, hipMemcpyDeviceToHost, st));
+            CCG_HIP(hipStreamSynchronize(st));
+            stats->kernel_ms += kt.ms();
+            stats->kernel_launches += 1;
+            stats->launches += 1;
+            if (gh.abort[0]) return 5;
+            if (host.overflow) return 4;
+            bool done = false;
+            for (int q = 0; q < 3; q++) done = done || host.ctl[q].done;
+            if (!done) return 4;
+            goto finished;
+        }
+        (void)hipGetLastError();  // cooperative launch not available: one round per launch
+    }
+    {
+    int32_t r = 1;
+    int batch = 16;
     for (;;) {
         kt.start(st);
         for (int q = 0; q < batch; q++, r++) {
-            hipLaunchKernelGGL(k_wround, dim3(1024), dim3(kBlock), 0, st, rp, col, w, n, Dt, inl, fbit, N0, N1, F0, F1,
-                               pairs, dev, r, delta);
+            hipLaunchKernelGGL(k_wround, dim3(1024), dim3(kBlock), 0, st, A, r);
         }
         CCG_HIP(hipGetLastError());
         kt.stop(st);
@@ -312,8 +505,11 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
         if (batch < 256) batch *= 2;
     }
     stats->levels += r - 1;
+    }
+finished:
     hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, mx, (int64_t)2);
-    hipLaunchKernelGGL(k_wmax, dim3(gz), dim3(256), 0, st, Dt, pairs, mx, (int32_t*)(mx + 1));
+    hipLaunchKernelGGL(k_wmax, dim3((unsigned)std::min<int64_t>(gz, 1024)), dim3(256), 0, st, Dt, pairs, mx,
+                       (int32_t*)(mx + 1));
     uint32_t hm[2];
     CCG_HIP(hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, st));
     CCG_HIP(hipStreamSynchronize(st));
