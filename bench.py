@@ -40,20 +40,69 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def algorithmic_bytes(t: dict, n: int, k: int, W: int) -> float:
-    """Bytes the batched traversal kernels must move, from their own work
-    counters: per arc scanned by a pull or pushed along by a push, 4 B (the
-    arc's end id) + 8W B (the neighbour's seen mask, or the atomic OR of it);
-    per node of a listed 64-node group per level, 4 B (its row bound) + 3 x 8W B
-    (seen mask in, seen mask out, level mask out)."""
-    return t["arcs_scanned"] * (4 + 8 * W) + t["nodes_visited"] * (4 + 24 * W)
+HUB_KERNEL = "k_hub_level"
+
+
+def hub_bytes_per_arc(W: int) -> int:
+    """Algorithmic bytes per arc the hub-chunk pull kernel scans: 4 B for the
+    arc's end id + 8W B for that neighbour's previous-level seen mask (the
+    chunk's one atomic OR of 8W B into the next-level mask is < 0.1% and left
+    out)."""
+    return 4 + 8 * W
+
+
+def source_digest() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1409_0035_amd", "csrc", "bfs_batched.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the hub kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes, each scaled by the same counter on a copy
+    of known size; None once the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", f"{HUB_KERNEL}_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                key, _, val = line[2:].partition(":")
+                vals[key.strip()] = val.strip().strip("`")
+    if vals.get("bfs_batched.hip sha256[:16]") != source_digest():
+        return None
+    try:
+        return float(vals["scaled HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def hub_roofline(timings, W: int, workload: str) -> dict:
+    """Per-launch algorithmic bytes / average launch duration of the hub
+    kernel, both from the library's own counters and HIP events."""
+    launches = sum(t["hub_launches"] for t in timings)
+    ms = sum(t["hub_ms"] for t in timings)
+    arcs = sum(t["hub_arcs"] for t in timings)
+    if launches == 0 or ms <= 0:
+        return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": HUB_KERNEL}
+    per_launch = arcs * hub_bytes_per_arc(W) / launches
+    avg_ms = ms / launches
+    achieved = per_launch / (avg_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload),
+            "kernel": HUB_KERNEL, "algorithmic_bytes_per_launch": int(per_launch),
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": launches / len(timings),
+            "bytes_per_arc": hub_bytes_per_arc(W)}
 
 
 def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
-    """The CPU oracle on a bounded sample of the same workload: ks sources'
-    searches (all host threads, over sources) and the literal Eq. (6) walk for
-    ns nodes (all host threads, over nodes), extrapolated to k sources and all
-    n nodes, as GTEPS."""
+    """The CPU oracle, as it stands, on a bounded sample of the same workload:
+    a prefix of the k sources' searches (all host threads, over sources) and
+    the literal Eq. (6) walk for a set of random nodes (all host threads, over
+    nodes), each grown until it has taken about half of `budget_s`, then
+    extrapolated to k sources and all n nodes, as GTEPS."""
     import concurrent.futures as cf
     import ctypes
 
@@ -61,20 +110,23 @@ def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
 
     threads = min(os.cpu_count() or 1, 16)
     samples = oracle.draw_samples(g.n, k, seed)
-    ks = min(k, max(threads, 8))
+    half = budget_s / 2
+    # searches: one batch of `threads` sources to size the rest
+    ks = min(k, threads)
+    t0 = time.perf_counter()
+    oracle.sample_distances(g, samples[:ks], threads=threads, reverse_graph=rg)
+    t_batch = time.perf_counter() - t0
+    ks = min(k, max(ks, int(ks * half / max(t_batch, 1e-3))))
     t0 = time.perf_counter()
     D = oracle.sample_distances(g, samples[:ks], threads=threads, reverse_graph=rg)
-    t_src = (time.perf_counter() - t0) / ks * threads  # single-source cost on one thread
-    # per-node literal walk: needs a row and the pivot's column; take rows
-    # from the partial D (pivot among the first ks samples) -- same O(n) work
+    t_search = time.perf_counter() - t0
+    per_source = t_search / ks  # wall time per source with all threads busy
+
     lib = oracle._load()
     sidx = oracle.sample_index(g.n, samples[:ks])
-    rng = np.random.default_rng(seed)
-    nodes = rng.integers(0, g.n, size=4 * threads)
     Dc = np.ascontiguousarray(D)
 
-    # column access through the node-major matrix with stride ks (pivot column p)
-    def one_col(v):
+    def one_node(v):
         row = np.ascontiguousarray(Dc[v])
         p = int(lib.orc_pivot(ks, oracle._p(row)))
         o = oracle.NodeOut()
@@ -83,17 +135,26 @@ def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
                                ctypes.c_void_p(col.ctypes.data), ks, 1, 10, ctypes.byref(o))
         return o.S_hyb
 
-    t1 = time.perf_counter()
+    rng = np.random.default_rng(seed)
+    nodes_done, t_walk = 0, 0.0
     with cf.ThreadPoolExecutor(threads) as ex:
-        list(ex.map(one_col, nodes))
-    t_node = (time.perf_counter() - t1) / len(nodes) * threads  # one node on one thread
-    t_total = (k * t_src + g.n * t_node) / threads
+        batch = min(threads, g.n)
+        while t_walk < half and nodes_done < g.n:
+            nodes = rng.integers(0, g.n, size=batch)
+            t1 = time.perf_counter()
+            list(ex.map(one_node, nodes))
+            dt = time.perf_counter() - t1
+            t_walk += dt
+            nodes_done += batch
+            batch = min(g.n - nodes_done, max(batch, int(batch * (half - t_walk) / max(dt, 1e-3))))
+    per_node = t_walk / nodes_done  # wall time per node with all threads busy
+    t_total = k * per_source + g.n * per_node
     m = g.m if not g.directed else 2 * g.arcs
     return {
         "value": k * m / t_total / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
-        "sample": (f"{ks} of {k} sources' searches on {threads} threads ({t_src * ks / threads:.2f} s) + "
-                   f"literal Eq.6 walk for {len(nodes)} nodes on {threads} threads; extrapolated to "
-                   f"k={k} sources and n={g.n} nodes: {t_total:.1f} s per estimate"),
+        "sample": (f"{ks} of {k} sources' searches ({t_search:.1f} s) + literal Eq.6 walk for {nodes_done} "
+                   f"random nodes ({t_walk:.1f} s), {threads} threads; extrapolated to k={k} sources and "
+                   f"n={g.n} nodes: {t_total:.1f} s per estimate"),
     }
 
 
@@ -106,6 +167,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, launch one float32 copy kernel of MIB MiB (read MIB, write MIB) so "
+                         "that counter passes can scale FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by sample "
@@ -161,18 +225,13 @@ def main():
     gteps = teps_edges / (ms_per_step / 1e3) / 1e9
     log(f"batched: {ms_per_step:.3f} ms/step, {gteps:.1f} GTEPS")
 
-    # roofline of the dominant kernel (batched traversal), live HIP-event timing
+    # roofline of the dominant kernel (the hub-chunk pull kernel), timed live
+    # with HIP events on the stream it is launched on
     tm = timings[-1]
     W = (min(k, 256) + 63) // 64
-    kernel_ms = float(np.median([t["kernel_ms"] for t in timings]))
-    launches = tm["kernel_launches"]
-    abytes = algorithmic_bytes(tm, g.n, k, W)
-    achieved = abytes / (kernel_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "BFS level (k_hub_level|k_push + k_group_level)", "launches_per_step": launches,
-                "avg_launch_ms": round(kernel_ms / max(launches, 1), 5),
-                "algorithmic_bytes_per_step": int(abytes)}
+    roofline = hub_roofline(timings, W, args.workload)
+    level_ms = float(np.median([t["kernel_ms"] for t in timings]))
+    log(f"roofline: {roofline}")
 
     plain = None
     if not args.no_plain and args.plain_steps > 0:
@@ -203,11 +262,19 @@ def main():
         "plain": plain,
         "speedup_vs_plain": None if plain is None else round(gteps / plain["gteps"], 2),
         "breakdown_ms": {"traverse": round(tm["traverse_ms"], 4), "epilogue": round(tm["epilogue_ms"], 4),
-                         "traversal_kernels": round(kernel_ms, 4)},
+                         "level_kernels": round(level_ms, 4),
+                         "hub_kernel": round(float(np.median([t["hub_ms"] for t in timings])), 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.copy_calibration > 0:
+        x = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + written by one elementwise kernel")
     ctx.close()
 
 

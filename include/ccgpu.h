@@ -153,9 +153,13 @@ typedef struct {
     int64_t launches;      /* all traversal launches (including bookkeeping kernels) */
     int32_t dist_bytes;    /* bytes per stored distance (1, 2 or 4) */
     int32_t reserved;
-    double kernel_ms;      /* summed duration of the main traversal kernel's launches */
+    double kernel_ms;      /* summed duration of the per-level traversal launches */
     int64_t kernel_launches; /* number of those launches */
-    int64_t arcs_matched;  /* scanned arcs whose far end was on the previous level */
+    int64_t arcs_matched;  /* arcs pushed along by push levels */
+    double hub_ms;         /* summed duration of the high-degree (hub-chunk) kernel launches */
+    int64_t hub_launches;  /* number of those launches */
+    int64_t hub_arcs;      /* arcs those launches scanned */
+    int64_t pull_levels;   /* levels run as pulls */
 } cc_timing;
 cc_status cc_last_timing(const cc_context* ctx, cc_timing* t);
 

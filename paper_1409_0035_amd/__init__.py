@@ -55,7 +55,8 @@ class cc_timing(ctypes.Structure):
                 ("epilogue_ms", ctypes.c_double), ("levels", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
                 ("nodes_visited", ctypes.c_int64), ("launches", ctypes.c_int64), ("dist_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
-                ("arcs_matched", ctypes.c_int64)]
+                ("arcs_matched", ctypes.c_int64), ("hub_ms", ctypes.c_double), ("hub_launches", ctypes.c_int64),
+                ("hub_arcs", ctypes.c_int64), ("pull_levels", ctypes.c_int64)]
 
 
 # per-field element type and whether the length is n, k or k*k / n*k

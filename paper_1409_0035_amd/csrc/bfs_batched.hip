@@ -125,31 +125,33 @@ __device__ __forceinline__ uint32_t pairs_needed(const uint64_t s[W], uint64_t l
 // Adds per-wave partial counts into the block's counter slot: one atomic
 // per field per block.
 struct WaveCounts {
-    int64_t arcs = 0, farcs = 0;
+    int64_t arcs = 0, farcs = 0, hub = 0;
     int32_t n_new = 0, n_out = 0;
 };
 
 __device__ __forceinline__ void flush_counts(WaveCounts c, LevelCounters* slots) {
-    __shared__ int64_t red[kWaves][4];
+    __shared__ int64_t red[kWaves][5];
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    const int64_t a = wave_sum64(c.arcs), f = wave_sum64(c.farcs);
+    const int64_t a = wave_sum64(c.arcs), f = wave_sum64(c.farcs), h = wave_sum64(c.hub);
     const int32_t nn = wave_sum32(c.n_new), no = wave_sum32(c.n_out);
     if (lane == 0) {
         red[wave][0] = a;
         red[wave][1] = f;
         red[wave][2] = nn;
         red[wave][3] = no;
+        red[wave][4] = h;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t t[4] = {0, 0, 0, 0};
+        int64_t t[5] = {0, 0, 0, 0, 0};
         for (int w = 0; w < kWaves; w++)
-            for (int q = 0; q < 4; q++) t[q] += red[w][q];
+            for (int q = 0; q < 5; q++) t[q] += red[w][q];
         LevelCounters* c0 = slots + (blockIdx.x % kCounterSlots);
         if (t[0]) atomicAdd((unsigned long long*)&c0->arcs, (unsigned long long)t[0]);
         if (t[1]) atomicAdd((unsigned long long*)&c0->frontier_arcs, (unsigned long long)t[1]);
         if (t[2]) atomicAdd(&c0->n_new, (int32_t)t[2]);
         if (t[3]) atomicAdd(&c0->n_out, (int32_t)t[3]);
+        if (t[4]) atomicAdd((unsigned long long*)&c0->matched, (unsigned long long)t[4]);
     }
 }
 
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_level(const int32_t* __restrict_
             if (lane == 0 && r) atomicOr((unsigned long long*)&NX[h * W + w], (unsigned long long)r);
         }
     }
-    wc.arcs = scanned;
+    wc.hub = scanned;
     flush_counts(wc, cnt);
 }
 
@@ -489,7 +491,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     int64_t pull_arcs = gv.arcs;  // arcs a pull level would scan (refreshed after each pull)
     uint64_t* Sp = S0;
     uint64_t* Sc = S1;
-    KernelTimer kt;
+    KernelTimer kt, kh;
     int32_t lmax = 0;
     const unsigned gb = (unsigned)std::min<int64_t>((ngroups + kWaves - 1) / kWaves, 2048);
     for (int32_t level = 1;; ++level) {
@@ -502,8 +504,10 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
                                level - 1, Sp, NX, cnt_dev);
         } else if (gv.n_hub_chunks > 0) {
             const int64_t hb = std::min<int64_t>((gv.n_hub_chunks + kWaves - 1) / kWaves, 4096);
+            kh.start(st);
             hipLaunchKernelGGL((k_hub_level<W>), dim3((unsigned)hb), dim3(kBlock), 0, st, gv.col, Sp, gv.hub_chunks,
                                gv.n_hub_chunks, NX, lastmask, cnt_dev);
+            kh.stop(st);
         }
         hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp, Sc,
                            out.snap + (size_t)level * plane, out.fill_level, gfull, chg, ngroups, n, gv.nh, NX, pull,
@@ -515,11 +519,16 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
         stats->kernel_launches += 1;
         stats->launches += 3;
         stats->levels += 1;
-        stats->arcs_scanned += sum.arcs;
+        stats->arcs_scanned += sum.arcs + sum.matched;
+        if (pull && gv.n_hub_chunks > 0) {
+            stats->hub_ms += kh.ms();
+            stats->hub_launches += 1;
+            stats->hub_arcs += sum.matched;
+        }
         stats->nodes_visited += (int64_t)sum.n_out * 64;
         if (pull) {
             stats->pull_levels += 1;
-            pull_arcs = std::max<int64_t>(sum.arcs, 1);
+            pull_arcs = std::max<int64_t>(sum.arcs + sum.matched, 1);
         } else {
             stats->push_arcs += sum.arcs;
         }

@@ -600,6 +600,10 @@ void record_timing(cc_timing* timing, Lane& L, const TravStats& stats, int db) {
     timing->kernel_ms = stats.kernel_ms;
     timing->kernel_launches = stats.kernel_launches;
     timing->arcs_matched = stats.push_arcs;
+    timing->hub_ms = stats.hub_ms;
+    timing->hub_launches = stats.hub_launches;
+    timing->hub_arcs = stats.hub_arcs;
+    timing->pull_levels = stats.pull_levels;
 }
 
 void add_stats(TravStats& a, const TravStats& b) {
@@ -612,6 +616,9 @@ void add_stats(TravStats& a, const TravStats& b) {
     a.kernel_launches += b.kernel_launches;
     a.pull_levels += b.pull_levels;
     a.push_arcs += b.push_arcs;
+    a.hub_ms += b.hub_ms;
+    a.hub_launches += b.hub_launches;
+    a.hub_arcs += b.hub_arcs;
     a.maxd = std::max(a.maxd, b.maxd);
 }
 

@@ -251,6 +251,9 @@ struct TravStats {
     int64_t kernel_launches = 0;
     int64_t pull_levels = 0;
     int64_t push_arcs = 0;
+    double hub_ms = 0;       // summed duration of the hub-chunk kernel launches
+    int64_t hub_launches = 0;
+    int64_t hub_arcs = 0;    // arcs those launches scanned
 };
 
 // Event pair for timing one kernel launch on a stream.
