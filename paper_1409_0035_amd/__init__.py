@@ -244,6 +244,8 @@ class Job:
     handle: ctypes.c_void_p
     arrays: dict
     keep: object
+    n: int = 0
+    k: int = 0
 
 
 def cc_submit(ctx, g, k: int, mode: int = CC_BATCHED, seed: int = 0, samples=None, eps=None,
@@ -259,7 +261,7 @@ def cc_submit(ctx, g, k: int, mode: int = CC_BATCHED, seed: int = 0, samples=Non
         setattr(res, f, arrays[f].ctypes.data)
     h = ctypes.c_void_p()
     _check(load_library().cc_submit(ctx, g, ctypes.byref(p), ctypes.byref(res), ctypes.byref(h)))
-    return Job(h, arrays, keep)
+    return Job(h, arrays, keep, n, k)
 
 
 def cc_poll(job: Job) -> int:
@@ -267,8 +269,14 @@ def cc_poll(job: Job) -> int:
 
 
 def cc_wait(job: Job) -> dict:
+    """Block until the job ends; its output arrays (dmat as k x k, D as n x k)."""
     _check(load_library().cc_wait(job.handle))
-    return job.arrays
+    out = dict(job.arrays)
+    if "dmat" in out:
+        out["dmat"] = out["dmat"].reshape(job.k, job.k)
+    if "D" in out:
+        out["D"] = out["D"].reshape(job.n, job.k)
+    return out
 
 
 def cc_cancel(job: Job) -> int:

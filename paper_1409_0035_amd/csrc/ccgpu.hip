@@ -220,7 +220,8 @@ struct cc_context {
     int inflight = 0;
     bool stopping = false;
     bool service_started = false;
-    int wgrid = -1;  // blocks of the persistent weighted launch (0 = unavailable), found on first use
+    std::once_flag wgrid_once;
+    int wgrid = 0;  // blocks of the persistent weighted launch (0 = unavailable), found on first use
 };
 
 static void graph_unref(cc_graph* g) {
@@ -734,8 +735,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     // the all-rounds cooperative launch pays agent-scope fences at
                     // every barrier and measures slower than one launch per round;
                     // it is kept for experiments behind CCGPU_PERSISTENT=1
-                    if (ctx->wgrid < 0)
+                    std::call_once(ctx->wgrid_once, [ctx] {
                         ctx->wgrid = std::getenv("CCGPU_PERSISTENT") ? weighted_persistent_grid(ctx->device) : 0;
+                    });
                     const int wr = sssp_weighted(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
                                                  (uint32_t*)Dt + (size_t)s0 * n, g.delta, ts, trav_scratch, &md, &ds,
                                                  ctx->wgrid);

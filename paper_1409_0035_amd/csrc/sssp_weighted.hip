@@ -285,7 +285,15 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
                 v = (int32_t)(uint32_t)item;
                 const int64_t bit = (int64_t)j * n + v;
                 if (sub == 0) {
-                    atomicAnd(&inl[bit >> 5], ~(1u << (bit & 31)));
+                    // The bit must be clear before the distance is read: an
+                    // improver that finds the bit still set relies on this
+                    // relaxation seeing its new distance, and one that finds it
+                    // clear enqueues the pair again.  A relaxed clear could
+                    // still be in flight when the load returns the old value;
+                    // the acquire makes the wave wait for the clear to complete
+                    // (and drop stale cached lines) before the load issues.
+                    (void)__hip_atomic_fetch_and(&inl[bit >> 5], ~(1u << (bit & 31)), __ATOMIC_ACQUIRE,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
                     d = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 b = rp[v];

@@ -1,0 +1,96 @@
+"""Parity at the full workload sizes, in the configuration the benchmark
+times (batched path, the workload's k and sample seed).
+
+The oracle cannot afford all k searches and the O(n^2) estimate at these
+sizes, so it checks
+  * sampled nodes one by one from their definitions (two searches each: one
+    from the node, one from its pivot), every output bit-exact;
+  * whole distance columns of a few samples (one search each), with the
+    matching exact sums S(c_i) and rows of the sample distance matrix;
+  * identities that hold for every node at any size (pivot range, Delta = 0
+    exactly on samples, S_piv = S(c_pivot), S_pub = S_piv + (n-1) Delta, the
+    sampling estimate as (n-1)/k times the distance sum)."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_1409_0035_amd as cc
+
+pytestmark = pytest.mark.gpu
+BENCH_OUT = ("S_hyb", "S_samp", "S_piv", "S_pub", "pivot", "delta", "sampsum")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = cc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("name", ["rmat20", "grid2048w", "rmat22dir"])
+def test_fullsize_sampled(ctx, name):
+    spec = graphgen.WORKLOADS[name]
+    k, seed = spec["k"], spec["sample_seed"]
+    _say(f"  generating {name}")
+    g = graphgen.workload(name)
+    rg = graphgen.transpose(g) if g.directed else None
+    n = g.n
+    _say(f"  {name}: n={n} arcs={g.arcs} k={k}")
+    gh = ctx.upload(g)
+    try:
+        res = cc.cc_estimate(ctx.handle, gh, k, seed=seed, outputs=BENCH_OUT)
+        full = cc.cc_estimate(ctx.handle, gh, k, seed=seed, outputs=("samples", "src_sum", "dmat", "D"))
+    finally:
+        ctx.release(gh)
+    samples = cc.cc_draw_samples(n, k, seed)
+    assert (full["samples"] == samples).all()
+    sampled = np.zeros(n, bool)
+    sampled[samples] = True
+
+    # identities over every node
+    piv, dl = res["pivot"], res["delta"]
+    assert ((piv >= 0) & (piv < k)).all()
+    assert ((dl == 0) == sampled).all()
+    assert (piv[samples] == np.arange(k)).all()
+    assert (res["S_piv"][~sampled] == full["src_sum"][piv[~sampled]]).all()
+    assert (res["S_pub"][~sampled] == res["S_piv"][~sampled] + (n - 1) * dl[~sampled].astype(np.int64)).all()
+    exp_samp = ((n - 1) * res["sampsum"][~sampled]).astype(np.float64) / float(k)
+    assert (res["S_samp"][~sampled] == exp_samp).all()
+    for f in ("S_hyb", "S_samp"):
+        assert (res[f][samples] == full["src_sum"].astype(np.float64)).all()
+    # the hybrid estimate lies between the sampled-only terms and the bounds it mixes
+    assert (res["S_hyb"] > 0).all()
+    # distances: whole columns for a few samples, with their sums and dmat rows
+    D = full["D"]
+    for i in sorted({0, k // 2, k - 1}):
+        _say(f"  column {i} (node {samples[i]})")
+        col = oracle.sssp(g, int(samples[i]), rg)
+        assert (D[:, i] == col).all(), f"D column {i}"
+        assert full["src_sum"][i] == col.sum()
+        assert (full["dmat"][i] == col[samples]).all()
+    assert (D.min(axis=1) == dl).all()
+    assert (D.sum(axis=1) == res["sampsum"]).all()
+    # sampled nodes, every output from the definition
+    rng = np.random.default_rng(seed)
+    deg = np.diff(g.row_ptr)
+    nodes = list(rng.integers(0, n, size=4)) + [int(np.argmax(deg)), n - 1, int(samples[0]), int(samples[k - 1])]
+    for v in nodes:
+        _say(f"  node {v}")
+        o = oracle.node_estimates(g, samples, int(v), reverse_graph=rg)
+        assert res["pivot"][v] == o.pivot, v
+        assert res["delta"][v] == o.delta, v
+        assert res["sampsum"][v] == o.sampsum, v
+        assert res["S_piv"][v] == o.S_piv, v
+        assert res["S_pub"][v] == o.S_pub, v
+        for f in ("S_hyb", "S_samp"):
+            a, b = float(res[f][v]), float(getattr(o, f))
+            assert abs(a - b) <= 1e-12 * abs(b), (v, f)
+            assert a == b, (v, f, "not bit-identical")
