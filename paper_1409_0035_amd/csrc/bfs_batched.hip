@@ -189,18 +189,47 @@ __global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_b
     atomicAdd((unsigned long long*)&cnt[i % kCounterSlots].frontier_arcs, (unsigned long long)(out_rp[v + 1] - out_rp[v]));
 }
 
-// push: one wave per group of 64 nodes; every node of the group that gained
-// bits at the previous level sends its mask along its out-arcs (lanes over arcs)
+// push along arc u->x of the mask su (u's seen mask): only bits x has not seen
+// and that are not already pending in NX(x) need the atomic, so popular
+// targets stop taking atomics once they hold the frontier's bits (a stale NX
+// read only lets a redundant atomic through)
+template <int W>
+__device__ __forceinline__ void push_arc(const uint64_t* __restrict__ Sprev, uint64_t* NX, int64_t x,
+                                         const uint64_t (&su)[W], int64_t& atomics) {
+    uint64_t nb[W];
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        nb[w] = su[w] ? su[w] & ~Sprev[x * W + w] : 0ull;
+        any = any || nb[w] != 0;
+    }
+    if (!any) return;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        if (!nb[w]) continue;
+        const uint64_t pending = __hip_atomic_load(&NX[x * W + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t r = nb[w] & ~pending;
+        if (r) {
+            atomicOr((unsigned long long*)&NX[x * W + w], (unsigned long long)r);
+            ++atomics;
+        }
+    }
+}
+
+// push, nodes past the hub prefix (out-degree <= the hub threshold): one wave
+// per group of 64 nodes; every node of the group that gained bits at the
+// previous level sends its mask along its out-arcs (lanes over arcs)
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col,
                                                  const int32_t* __restrict__ chg, const uint8_t* __restrict__ gfull,
-                                                 int64_t n, int32_t ngroups, int32_t prev_level,
+                                                 int64_t n, int32_t g0, int32_t ngroups, int32_t prev_level,
                                                  const uint64_t* __restrict__ Sprev, uint64_t* NX,
                                                  LevelCounters* cnt) {
     const int lane = lane_id();
     const int32_t waves = gridDim.x * kWaves;
     WaveCounts wc;
-    for (int32_t g = blockIdx.x * kWaves + (threadIdx.x >> 6); g < ngroups; g += waves) {
+    int64_t atomics = 0;
+    for (int32_t g = g0 + blockIdx.x * kWaves + (threadIdx.x >> 6); g < ngroups; g += waves) {
         if (gfull[g]) continue;
         const int64_t v = (int64_t)g * 64 + lane;
         uint64_t m = __ballot(v < n && chg[v] == prev_level);
@@ -213,14 +242,40 @@ __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ ou
             for (int w = 0; w < W; w++) su[w] = Sprev[u * W + w];
             const uint32_t b = out_rp[u], e = out_rp[u + 1];
             for (uint32_t t = b + lane; t < e; t += 64) {
-                const int64_t x = out_col[t];
                 ++wc.arcs;
-#pragma unroll
-                for (int w = 0; w < W; w++)
-                    if (su[w]) atomicOr((unsigned long long*)&NX[x * W + w], (unsigned long long)su[w]);
+                push_arc<W>(Sprev, NX, out_col[t], su, atomics);
             }
         }
     }
+    wc.hub = atomics;
+    flush_counts(wc, cnt);
+}
+
+// push, hub prefix: one wave per chunk (node, first arc, end arc) of out-arcs,
+// so a frontier node with a huge out-degree is spread over many waves
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_push_hub(const int32_t* __restrict__ out_col,
+                                                     const int32_t* __restrict__ chunks, int32_t n_chunks,
+                                                     const int32_t* __restrict__ chg, int32_t prev_level,
+                                                     const uint64_t* __restrict__ Sprev, uint64_t* NX,
+                                                     LevelCounters* cnt) {
+    const int lane = lane_id();
+    const int32_t waves = gridDim.x * kWaves;
+    WaveCounts wc;
+    int64_t atomics = 0;
+    for (int32_t c = blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_chunks; c += waves) {
+        const int64_t h = chunks[3 * c];
+        if (chg[h] != prev_level) continue;
+        const uint32_t b = (uint32_t)chunks[3 * c + 1], e = (uint32_t)chunks[3 * c + 2];
+        uint64_t su[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) su[w] = Sprev[h * W + w];
+        for (uint32_t t = b + lane; t < e; t += 64) {
+            ++wc.arcs;
+            push_arc<W>(Sprev, NX, out_col[t], su, atomics);
+        }
+    }
+    wc.hub = atomics;
     flush_counts(wc, cnt);
 }
 
@@ -500,8 +555,17 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
         kt.start(st);
         if (!pull) {
-            hipLaunchKernelGGL((k_push<W>), dim3(gb), dim3(kBlock), 0, st, gv.out_rp, gv.out_col, chg, gfull, n, ngroups,
-                               level - 1, Sp, NX, cnt_dev);
+            if (gv.n_push_chunks > 0) {
+                const int64_t hb = std::min<int64_t>((gv.n_push_chunks + kWaves - 1) / kWaves, 4096);
+                hipLaunchKernelGGL((k_push_hub<W>), dim3((unsigned)hb), dim3(kBlock), 0, st, gv.out_col,
+                                   gv.push_chunks, gv.n_push_chunks, chg, level - 1, Sp, NX, cnt_dev);
+            }
+            const int32_t g0 = gv.n_push_chunks > 0 ? (int32_t)((gv.nh + 63) / 64) : 0;  // hubs went by chunks
+            if (g0 < ngroups) {
+                hipLaunchKernelGGL((k_push<W>), dim3((unsigned)std::min<int64_t>((ngroups - g0 + kWaves - 1) / kWaves, 2048)),
+                                   dim3(kBlock), 0, st, gv.out_rp, gv.out_col, chg, gfull, n, g0, ngroups, level - 1, Sp,
+                                   NX, cnt_dev);
+            }
         } else if (gv.n_hub_chunks > 0) {
             const int64_t hb = std::min<int64_t>((gv.n_hub_chunks + kWaves - 1) / kWaves, 4096);
             kh.start(st);
@@ -519,7 +583,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
         stats->kernel_launches += 1;
         stats->launches += 3;
         stats->levels += 1;
-        stats->arcs_scanned += sum.arcs + sum.matched;
+        stats->arcs_scanned += sum.arcs + (pull ? sum.matched : 0);
         if (pull && gv.n_hub_chunks > 0) {
             stats->hub_ms += kh.ms();
             stats->hub_launches += 1;
@@ -531,6 +595,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
             pull_arcs = std::max<int64_t>(sum.arcs + sum.matched, 1);
         } else {
             stats->push_arcs += sum.arcs;
+            stats->push_atomics += sum.matched;
         }
         if (sum.n_new > 0) lmax = level;
         frontier_arcs = sum.frontier_arcs;

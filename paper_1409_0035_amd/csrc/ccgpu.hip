@@ -617,6 +617,7 @@ void add_stats(TravStats& a, const TravStats& b) {
     a.kernel_launches += b.kernel_launches;
     a.pull_levels += b.pull_levels;
     a.push_arcs += b.push_arcs;
+    a.push_atomics += b.push_atomics;
     a.hub_ms += b.hub_ms;
     a.hub_launches += b.hub_launches;
     a.hub_arcs += b.hub_arcs;
@@ -764,6 +765,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 gv.nh = g.nh;
                 gv.hub_chunks = dir == 0 ? g.hub_chunks_in : g.hub_chunks_out;
                 gv.n_hub_chunks = dir == 0 ? g.n_hub_chunks_in : g.n_hub_chunks_out;
+                gv.push_chunks = dir == 0 ? g.hub_chunks_out : g.hub_chunks_in;
+                gv.n_push_chunks = dir == 0 ? g.n_hub_chunks_out : g.n_hub_chunks_in;
                 for (int32_t s0 = 0; s0 < k && rc == 0; s0 += 256) {
                     const int32_t kg = std::min(256, k - s0);
                     int32_t lm = 0;

@@ -194,6 +194,68 @@ __global__ void k_materialize(const uint64_t* __restrict__ snap, size_t plane, i
     }
 }
 
+// Spreads the 8 bits of b over the 8 bytes of a word (byte j = bit j of b).
+__device__ __forceinline__ uint64_t spread8(uint32_t b) {
+    const uint64_t z = ((uint64_t)b * 0x0101010101010101ull) & 0x8040201008040201ull;
+    return (((z + 0x7F7F7F7F7F7F7F7Full) | z) & 0x8080808080808080ull) >> 7;
+}
+
+// Distances from the masks, one thread per (node, 64-sample word): the
+// distance of sample i is the number of levels 0..min(fill, lmax) whose mask
+// lacks bit i (masks only grow, and the node is full after its fill level).
+// Byte counters, eight samples per 64-bit accumulator, need lmax < 255.
+// Output DT (u8 internal, node-major columns src_base..) or int32 at the
+// caller's node ids; 16-byte stores when the row offsets allow.
+template <int W, typename OT>
+__global__ __launch_bounds__(kBlock) void k_materialize_words(
+    const uint64_t* __restrict__ snap, size_t plane, int32_t lmax, const int32_t* __restrict__ fill_level,
+    int64_t n, int32_t kg, int32_t src_base, int32_t k, OT* __restrict__ out, const int32_t* __restrict__ orig,
+    int vec, DevFlags* flags) {
+    const int64_t count = n * W;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = t / W;
+        const int w = (int)(t % W);
+        const int nb = min(64, kg - w * 64);  // samples in this word
+        if (nb <= 0) continue;
+        const uint64_t valid = nb >= 64 ? ~0ull : ((1ull << nb) - 1);
+        const int32_t last = min(fill_level[v >> 6], lmax);
+        uint64_t acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) acc[q] = 0;
+        uint64_t miss = valid;
+        for (int32_t L = 0; L <= last; L++) {
+            miss = ~snap[(size_t)L * plane + v * W + w] & valid;
+            if (!miss) break;
+#pragma unroll
+            for (int q = 0; q < 8; q++) acc[q] += spread8((uint32_t)(miss >> (8 * q)) & 0xFFu);
+        }
+        if (miss) flags->disconnected = 1;  // a bit still unset when the node stopped changing
+        const int64_t row = orig ? (int64_t)orig[v] : v;
+        OT* dst = out + row * k + src_base + (int64_t)w * 64;
+        if (vec && nb == 64) {
+            if constexpr (sizeof(OT) == 1) {
+                uint4* d4 = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    d4[q] = make_uint4((uint32_t)acc[2 * q], (uint32_t)(acc[2 * q] >> 32), (uint32_t)acc[2 * q + 1],
+                                       (uint32_t)(acc[2 * q + 1] >> 32));
+            } else {
+                int4* d4 = reinterpret_cast<int4*>(dst);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const uint64_t a = acc[q];
+                    d4[2 * q] = make_int4((int)(a & 0xFF), (int)((a >> 8) & 0xFF), (int)((a >> 16) & 0xFF),
+                                          (int)((a >> 24) & 0xFF));
+                    d4[2 * q + 1] = make_int4((int)((a >> 32) & 0xFF), (int)((a >> 40) & 0xFF),
+                                              (int)((a >> 48) & 0xFF), (int)((a >> 56) & 0xFF));
+                }
+            }
+        } else {
+            for (int i = 0; i < nb; i++) dst[i] = (OT)((acc[i >> 3] >> (8 * (i & 7))) & 0xFF);
+        }
+    }
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 inline unsigned grid_for(int64_t items, int64_t cap) {
@@ -230,8 +292,14 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
                        a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
     CCG_HIP(hipGetLastError());
     if (a.Dout) {
-        hipLaunchKernelGGL((k_materialize<W, uint8_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, a.snap,
-                           a.plane, lmax, a.fill_level, n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
+        if (lmax < 255) {
+            hipLaunchKernelGGL((k_materialize_words<W, int32_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
+                               a.snap, a.plane, lmax, a.fill_level, n, k, 0, k, a.Dout, a.orig, (int)(k % 4 == 0),
+                               flags);
+        } else {
+            hipLaunchKernelGGL((k_materialize<W, uint8_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, a.snap,
+                               a.plane, lmax, a.fill_level, n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
+        }
     }
 }
 
@@ -245,6 +313,15 @@ void bits_mt(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags*
 template <int W, typename DT>
 void materialize_t(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
                    int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DevFlags* flags) {
+    if constexpr (sizeof(DT) == 1) {
+        if (lmax < 255) {
+            const int vec = (k % 16 == 0) && (src_base % 16 == 0);
+            hipLaunchKernelGGL((k_materialize_words<W, uint8_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
+                               snap, plane, lmax, fill_level, n, kg, src_base, k, (uint8_t*)D,
+                               (const int32_t*)nullptr, vec, flags);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_materialize<W, DT>), dim3(grid_for(n * kg, 65536)), dim3(256), 0, st, snap, plane, lmax,
                        fill_level, n, kg, src_base, k, (DT*)D, (const int32_t*)nullptr, (int32_t*)nullptr, flags);
 }

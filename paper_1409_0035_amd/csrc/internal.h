@@ -226,6 +226,8 @@ struct BfsView {
     int64_t nh = 0;
     const int32_t* hub_chunks = nullptr;  // (node, first arc, end arc) triples over rp/col
     int32_t n_hub_chunks = 0;
+    const int32_t* push_chunks = nullptr;  // the same over out_rp/out_col
+    int32_t n_push_chunks = 0;
 };
 
 // Where the batched BFS records its per-level seen masks.
@@ -254,6 +256,7 @@ struct TravStats {
     double hub_ms = 0;       // summed duration of the hub-chunk kernel launches
     int64_t hub_launches = 0;
     int64_t hub_arcs = 0;    // arcs those launches scanned
+    int64_t push_atomics = 0;  // atomic ORs issued by push levels
 };
 
 // Event pair for timing one kernel launch on a stream.

@@ -20,8 +20,17 @@
 // Control without host round trips: round r reads the state round r-1 left
 // (bound, far-pile buffer, counters; three-slot rings by round) at its start,
 // so every block takes the same decision; the host enqueues rounds in batches
-// and only checks the done flag between batches.  Duplicates are kept out of
-// the piles with one bit per pair and pile.
+// and only checks the done flag between batches.
+//
+// Duplicates are kept out of the near pile by a flag in the distance word
+// itself: during the search Dt holds e = 2d + f, with f = 0 while the pair
+// sits in a near pile and f = 1 otherwise.  Taking a pair out of the pile is
+// one atomic OR of 1, which returns the distance to relax with; an improver's
+// atomic min with 2*cand clears the flag in the same operation and tells the
+// improver whether it was the one to clear it (and so must enqueue).  Both
+// act on one word, so no relaxation can miss an improvement.  The far pile
+// keeps a bit per pair; it is only drained by split rounds, which relax
+// nothing.  The last pass rewrites Dt to plain distances.
 #include "internal.h"
 
 namespace ccg {
@@ -29,7 +38,8 @@ namespace ccg {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr uint32_t kInf = 0xFFFFFFFFu;        // unreached (encoded and decoded)
+constexpr uint32_t kMaxDist = 0x7FFFFFFEu;    // largest distance the encoding (and int32 output) holds
 
 struct WState {
     uint32_t hi;      // window bound for the round that reads this slot
@@ -60,14 +70,12 @@ __global__ void k_wzero(uint32_t* p, int64_t count) {
         p[t] = 0;
 }
 
-__global__ void k_wseed(const int32_t* samples, int32_t kg, int64_t n, uint32_t* Dt, uint32_t* inl, uint64_t* N0,
-                        WDev* dev, uint32_t delta) {
+__global__ void k_wseed(const int32_t* samples, int32_t kg, int64_t n, uint32_t* Dt, uint64_t* N0, WDev* dev,
+                        uint32_t delta) {
     const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < kg) {
         const int64_t v = samples[j];
-        Dt[(int64_t)j * n + v] = 0;
-        const int64_t bit = (int64_t)j * n + v;
-        atomicOr(&inl[bit >> 5], 1u << (bit & 31));
+        Dt[(int64_t)j * n + v] = 0;  // distance 0, in the first near pile
         N0[j] = pair_of(j, (int32_t)v);
     }
     if (j == 0) {
@@ -151,7 +159,6 @@ struct WArgs {
     const int32_t* wt;
     int64_t n;
     uint32_t* Dt;
-    uint32_t* inl;
     uint32_t* fbit;
     uint64_t* N0;
     uint64_t* N1;
@@ -169,7 +176,6 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
     const int32_t* __restrict__ wt = A.wt;
     const int64_t n = A.n;
     uint32_t* Dt = A.Dt;
-    uint32_t* inl = A.inl;
     uint32_t* fbit = A.fbit;
     uint64_t* N0 = A.N0;
     uint64_t* N1 = A.N1;
@@ -243,10 +249,14 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
                 item = fin[t];
                 const int64_t bit = (int64_t)(item >> 32) * n + (uint32_t)item;
                 atomicAnd(&fbit[bit >> 5], ~(1u << (bit & 31)));
-                const uint32_t d = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // a split round relaxes nothing, so the word is stable here
+                const uint32_t e = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t d = e >> 1;
                 if (d < hi) {
-                    const uint32_t old = atomicOr(&inl[bit >> 5], 1u << (bit & 31));
-                    to_near = !(old & (1u << (bit & 31)));
+                    if (e & 1u) {  // not yet in a near pile
+                        atomicAnd(&Dt[bit], ~1u);
+                        to_near = true;
+                    }
                 } else {
                     const uint32_t old = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
                     to_far = !(old & (1u << (bit & 31)));
@@ -284,18 +294,7 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
                 j = (int32_t)(item >> 32);
                 v = (int32_t)(uint32_t)item;
                 const int64_t bit = (int64_t)j * n + v;
-                if (sub == 0) {
-                    // The bit must be clear before the distance is read: an
-                    // improver that finds the bit still set relies on this
-                    // relaxation seeing its new distance, and one that finds it
-                    // clear enqueues the pair again.  A relaxed clear could
-                    // still be in flight when the load returns the old value;
-                    // the acquire makes the wave wait for the clear to complete
-                    // (and drop stale cached lines) before the load issues.
-                    (void)__hip_atomic_fetch_and(&inl[bit >> 5], ~(1u << (bit & 31)), __ATOMIC_ACQUIRE,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-                    d = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                if (sub == 0) d = atomicOr(&Dt[bit], 1u) >> 1;  // leave the pile, read the distance
                 b = rp[v];
                 e = rp[v + 1];
             }
@@ -318,17 +317,20 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
                 if (s < e - b) {
                     const int32_t u = col[b + s];
                     const uint64_t cand64 = (uint64_t)d + (uint32_t)wt[b + s];
-                    const uint32_t cand = cand64 >= kInf ? kInf - 1 : (uint32_t)cand64;
-                    if (cand64 >= kInf) dev->overflow = 1;
-                    if (cand < drow[u]) {
-                        const uint32_t old = atomicMin(&drow[u], cand);
-                        if (cand < old) {
-                            const int64_t bit = (int64_t)j * n + u;
-                            item = pair_of(j, u);
-                            if (cand < hi) {
-                                const uint32_t ob = atomicOr(&inl[bit >> 5], 1u << (bit & 31));
-                                to_near = !(ob & (1u << (bit & 31)));
-                            } else {
+                    const uint32_t cand = cand64 > kMaxDist ? kMaxDist : (uint32_t)cand64;
+                    if (cand64 > kMaxDist) dev->overflow = 1;
+                    // a stale cached word only overstates the distance: the
+                    // atomic below decides
+                    if (cand < (drow[u] >> 1)) {
+                        item = pair_of(j, u);
+                        if (cand < hi) {
+                            const uint32_t enc = cand << 1;  // flag 0: in a near pile
+                            const uint32_t old = atomicMin(&drow[u], enc);
+                            to_near = (old & 1u) && enc < old;  // this min cleared the flag
+                        } else {
+                            const uint32_t old = atomicMin(&drow[u], (cand << 1) | 1u);
+                            if (cand < (old >> 1)) {
+                                const int64_t bit = (int64_t)j * n + u;
                                 const uint32_t ob = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
                                 to_far = !(ob & (1u << (bit & 31)));
                                 lmin = cand < lmin ? cand : lmin;
@@ -377,14 +379,21 @@ __global__ __launch_bounds__(kBlock) void k_wpersist(WArgs A, GridSync* gs, int3
     }
 }
 
-__global__ void k_wmax(const uint32_t* Dt, int64_t count, uint32_t* out, int32_t* unreached) {
+// Rewrites the search's words 2d + f as plain distances (kInf stays) and
+// finds the largest distance and whether any pair was left unreached.
+__global__ void k_wmax(uint32_t* Dt, int64_t count, uint32_t* out, int32_t* unreached) {
     __shared__ uint32_t bm[4];
     uint32_t m = 0;
     bool un = false;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t d = Dt[t];
-        if (d == kInf) un = true;
-        else m = d > m ? d : m;
+        const uint32_t e = Dt[t];
+        if (e == kInf) {
+            un = true;
+        } else {
+            const uint32_t d = e >> 1;
+            Dt[t] = d;
+            m = d > m ? d : m;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         const uint32_t o = (uint32_t)__shfl_xor((int)m, off);
@@ -406,7 +415,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t sssp_weighted_scratch(int64_t n, int32_t kg) {
     const int64_t pairs = n * kg;
-    return align256(sizeof(WDev)) + 2 * align256((size_t)((pairs + 31) / 32) * 4) + 4 * align256((size_t)pairs * 8) +
+    return align256(sizeof(WDev)) + align256((size_t)((pairs + 31) / 32) * 4) + 4 * align256((size_t)pairs * 8) +
            align256(16) + align256(sizeof(GridSync)) + 1024;
 }
 
@@ -432,8 +441,6 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     char* p = (char*)scratch;
     WDev* dev = (WDev*)p;
     p += align256(sizeof(WDev));
-    uint32_t* inl = (uint32_t*)p;
-    p += align256((size_t)((pairs + 31) / 32) * 4);
     uint32_t* fbit = (uint32_t*)p;
     p += align256((size_t)((pairs + 31) / 32) * 4);
     uint64_t* N0 = (uint64_t*)p;
@@ -452,14 +459,12 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     const int64_t words = (pairs + 31) / 32;
     const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
     hipLaunchKernelGGL(k_winit, dim3(gz), dim3(256), 0, st, Dt, pairs);
-    hipLaunchKernelGGL(k_wzero, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0, st, inl,
-                       words);
     hipLaunchKernelGGL(k_wzero, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0, st, fbit,
                        words);
-    hipLaunchKernelGGL(k_wseed, dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, n, Dt, inl, N0, dev, delta);
-    stats->launches += 4;
+    hipLaunchKernelGGL(k_wseed, dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, n, Dt, N0, dev, delta);
+    stats->launches += 3;
 
-    WArgs A{rp, col, w, n, Dt, inl, fbit, N0, N1, F0, F1, pairs, dev, delta};
+    WArgs A{rp, col, w, n, Dt, fbit, N0, N1, F0, F1, pairs, dev, delta};
     WDev host;
     KernelTimer kt;
     // every round settles or moves at least one pair; far more rounds than
