@@ -40,14 +40,14 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-HUB_KERNEL = "k_hub_level"
+SCATTER_KERNEL = "k_scatter_level"
 
 
-def hub_bytes_per_arc(W: int) -> int:
-    """Algorithmic bytes per arc the hub-chunk pull kernel scans: 4 B for the
-    arc's end id + 8W B for that neighbour's previous-level seen mask (the
-    chunk's one atomic OR of 8W B into the next-level mask is < 0.1% and left
-    out)."""
+def bytes_per_arc(W: int) -> int:
+    """Algorithmic bytes per arc of the scatter kernel: 4 B for the arc's end
+    id + 8W B for the far end's seen mask (a pull gathers the neighbour's
+    mask; a push reads the target's mask to drop bits it already has).  The
+    one atomic OR per hub chunk, and the pushes' atomics, are left out."""
     return 4 + 8 * W
 
 
@@ -58,10 +58,10 @@ def source_digest() -> str:
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per launch of the hub kernel from the committed rocprofv3
+    """HBM bytes per launch of the scatter kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes, each scaled by the same counter on a copy
     of known size; None once the kernel source has changed since."""
-    path = os.path.join(ROOT, "profiles", f"{HUB_KERNEL}_{workload}_pmc.md")
+    path = os.path.join(ROOT, "profiles", f"{SCATTER_KERNEL}_{workload}_pmc.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -78,23 +78,27 @@ def measured_traffic(workload: str):
         return None
 
 
-def hub_roofline(timings, W: int, workload: str) -> dict:
-    """Per-launch algorithmic bytes / average launch duration of the hub
-    kernel, both from the library's own counters and HIP events."""
-    launches = sum(t["hub_launches"] for t in timings)
-    ms = sum(t["hub_ms"] for t in timings)
-    arcs = sum(t["hub_arcs"] for t in timings)
+def scatter_roofline(timings, W: int, workload: str) -> dict:
+    """Per-launch algorithmic bytes / average launch duration of the scatter
+    kernel (one launch per level), both from the library's own counters and
+    HIP events on the launch stream."""
+    launches = sum(t["scatter_launches"] for t in timings)
+    ms = sum(t["scatter_ms"] for t in timings)
+    arcs = sum(t["scatter_arcs"] for t in timings)
     if launches == 0 or ms <= 0:
         return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                "traffic": None, "kernel": HUB_KERNEL}
-    per_launch = arcs * hub_bytes_per_arc(W) / launches
+                "traffic": None, "kernel": SCATTER_KERNEL}
+    per_launch = arcs * bytes_per_arc(W) / launches
     avg_ms = ms / launches
     achieved = per_launch / (avg_ms / 1e3) / 1e9
+    pull_ms = sum(t["pull_scatter_ms"] for t in timings)
+    pull_arcs = sum(t["hub_arcs"] for t in timings)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload),
-            "kernel": HUB_KERNEL, "algorithmic_bytes_per_launch": int(per_launch),
+            "kernel": SCATTER_KERNEL, "algorithmic_bytes_per_launch": int(per_launch),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": launches / len(timings),
-            "bytes_per_arc": hub_bytes_per_arc(W)}
+            "bytes_per_arc": bytes_per_arc(W),
+            "pull_levels_gbs": round(pull_arcs * bytes_per_arc(W) / (pull_ms / 1e3) / 1e9, 1) if pull_ms > 0 else None}
 
 
 def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
@@ -167,6 +171,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of running the library's autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, launch one float32 copy kernel of MIB MiB (read MIB, write MIB) so "
                          "that counter passes can scale FETCH_SIZE / WRITE_SIZE")
@@ -204,6 +210,12 @@ def main():
     }
     stream = torch.cuda.current_stream()
 
+    tuning = cc.cc_graph_get_tuning(gh)
+    if not args.no_autotune:
+        t0 = time.time()
+        tuning, tuned_ms = cc.cc_autotune(ctx.handle, gh, k, seed=seed, reps=3)
+        log(f"autotune: {tuning} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
+
     def step(mode):
         cc.cc_estimate_device(ctx.handle, gh, k, out, mode=mode, seed=seed, stream=stream)
 
@@ -225,11 +237,11 @@ def main():
     gteps = teps_edges / (ms_per_step / 1e3) / 1e9
     log(f"batched: {ms_per_step:.3f} ms/step, {gteps:.1f} GTEPS")
 
-    # roofline of the dominant kernel (the hub-chunk pull kernel), timed live
-    # with HIP events on the stream it is launched on
+    # roofline of the dominant kernel (the per-level scatter kernel), timed
+    # live with HIP events on the stream it is launched on
     tm = timings[-1]
     W = (min(k, 256) + 63) // 64
-    roofline = hub_roofline(timings, W, args.workload)
+    roofline = scatter_roofline(timings, W, args.workload)
     level_ms = float(np.median([t["kernel_ms"] for t in timings]))
     log(f"roofline: {roofline}")
 
@@ -263,7 +275,8 @@ def main():
         "speedup_vs_plain": None if plain is None else round(gteps / plain["gteps"], 2),
         "breakdown_ms": {"traverse": round(tm["traverse_ms"], 4), "epilogue": round(tm["epilogue_ms"], 4),
                          "level_kernels": round(level_ms, 4),
-                         "hub_kernel": round(float(np.median([t["hub_ms"] for t in timings])), 4)},
+                         "scatter_kernel": round(float(np.median([t["scatter_ms"] for t in timings])), 4)},
+        "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

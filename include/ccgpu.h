@@ -153,15 +153,43 @@ typedef struct {
     int64_t launches;      /* all traversal launches (including bookkeeping kernels) */
     int32_t dist_bytes;    /* bytes per stored distance (1, 2 or 4) */
     int32_t reserved;
-    double kernel_ms;      /* summed duration of the per-level traversal launches */
-    int64_t kernel_launches; /* number of those launches */
+    double kernel_ms;      /* summed duration of the level batches (device time from first to last level) */
+    int64_t kernel_launches; /* levels enqueued */
     int64_t arcs_matched;  /* arcs pushed along by push levels */
-    double hub_ms;         /* summed duration of the high-degree (hub-chunk) kernel launches */
-    int64_t hub_launches;  /* number of those launches */
-    int64_t hub_arcs;      /* arcs those launches scanned */
+    double scatter_ms;     /* summed duration of the scatter launches (one per level: the push, or the
+                              pull over high in-degree nodes' arc chunks) */
+    int64_t scatter_launches; /* number of those launches */
+    int64_t scatter_arcs;  /* arcs they scanned (pulls) or pushed along (pushes) */
+    int64_t hub_arcs;      /* of which scanned by pulls */
+    double pull_scatter_ms; /* of scatter_ms, the levels that pulled */
     int64_t pull_levels;   /* levels run as pulls */
 } cc_timing;
 cc_status cc_last_timing(const cc_context* ctx, cc_timing* t);
+
+/* ---- tuning ------------------------------------------------------------
+ * Launch shapes and thresholds of the traversal, kept per graph.  None of
+ * them changes any result (every estimate is exact given the samples); they
+ * only change speed.  Set them while no job uses the graph. */
+typedef struct {
+    int32_t alpha;          /* BFS: a level pushes iff its frontier's out-arcs * alpha are fewer than the arcs
+                               the last pull scanned (1..1024; default 4) */
+    int32_t level_blocks;   /* BFS: blocks of the merge launch per level (1..65535; default 2048) */
+    int32_t scatter_blocks; /* BFS: blocks of the scatter launch per level (1..65535; default 4096) */
+    int32_t delta;          /* weighted: bucket width of delta-stepping (>= 1; default 2 x mean arc length) */
+    int32_t round_blocks;   /* weighted: blocks per relaxation round (1..65535; default 1024) */
+    int32_t local_passes;   /* weighted: block-local relaxation passes per round (0..1024; default 64) */
+} cc_tuning;
+cc_status cc_graph_get_tuning(const cc_graph* g, cc_tuning* t);
+/* CC_EINVAL for a value outside its range. */
+cc_status cc_graph_set_tuning(cc_graph* g, const cc_tuning* t);
+/* Autotuner: times full estimates of k samples drawn from `seed` (median of
+ * `reps` runs per candidate) while it varies one knob at a time over a fixed
+ * candidate list (coordinate descent from the graph's current setting), keeps
+ * the fastest setting in the graph and returns it with its time (ms, device
+ * time of one estimate).  Uses the context's own stream and device buffers it
+ * allocates and frees itself. */
+cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64_t seed, int32_t reps, cc_tuning* best,
+                      double* best_ms);
 
 /* ---- serving: continuous batching over resident graphs ---------------- */
 

@@ -29,6 +29,7 @@ EXPORTED = [
     "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_release", "cc_graph_info",
     "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
     "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
+    "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune",
 ]
 
 
@@ -55,8 +56,17 @@ class cc_timing(ctypes.Structure):
                 ("epilogue_ms", ctypes.c_double), ("levels", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
                 ("nodes_visited", ctypes.c_int64), ("launches", ctypes.c_int64), ("dist_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
-                ("arcs_matched", ctypes.c_int64), ("hub_ms", ctypes.c_double), ("hub_launches", ctypes.c_int64),
-                ("hub_arcs", ctypes.c_int64), ("pull_levels", ctypes.c_int64)]
+                ("arcs_matched", ctypes.c_int64), ("scatter_ms", ctypes.c_double),
+                ("scatter_launches", ctypes.c_int64), ("scatter_arcs", ctypes.c_int64), ("hub_arcs", ctypes.c_int64),
+                ("pull_scatter_ms", ctypes.c_double), ("pull_levels", ctypes.c_int64)]
+
+
+class cc_tuning(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_int32), ("level_blocks", ctypes.c_int32), ("scatter_blocks", ctypes.c_int32),
+                ("delta", ctypes.c_int32), ("round_blocks", ctypes.c_int32), ("local_passes", ctypes.c_int32)]
+
+
+TUNING_FIELDS = tuple(f for f, _ in cc_tuning._fields_)
 
 
 # per-field element type and whether the length is n, k or k*k / n*k
@@ -107,6 +117,9 @@ def load_library():
         "cc_cancel": (i32, [P]),
         "cc_job_times": (i32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "cc_job_release": (None, [P]),
+        "cc_graph_get_tuning": (i32, [P, ctypes.POINTER(cc_tuning)]),
+        "cc_graph_set_tuning": (i32, [P, ctypes.POINTER(cc_tuning)]),
+        "cc_autotune": (i32, [P, P, i32, u64, i32, ctypes.POINTER(cc_tuning), ctypes.POINTER(ctypes.c_double)]),
         "cc_status_str": (ctypes.c_char_p, [i32]),
         "cc_last_error": (ctypes.c_char_p, []),
     }
@@ -168,6 +181,31 @@ def cc_graph_info(g):
     n, arcs, fl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint32()
     _check(load_library().cc_graph_info(g, ctypes.byref(n), ctypes.byref(arcs), ctypes.byref(fl)))
     return n.value, arcs.value, fl.value
+
+
+def cc_graph_get_tuning(g) -> dict:
+    t = cc_tuning()
+    _check(load_library().cc_graph_get_tuning(g, ctypes.byref(t)))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def cc_graph_set_tuning(g, **fields) -> dict:
+    """Changes the named knobs of the graph's tuning; returns the new setting."""
+    cur = cc_graph_get_tuning(g)
+    unknown = set(fields) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    cur.update(fields)
+    t = cc_tuning(**{f: int(cur[f]) for f in TUNING_FIELDS})
+    _check(load_library().cc_graph_set_tuning(g, ctypes.byref(t)))
+    return cur
+
+
+def cc_autotune(ctx, g, k: int, seed: int = 0, reps: int = 3):
+    """Runs the library's autotuner on a resident graph; returns (tuning dict, ms)."""
+    t, ms = cc_tuning(), ctypes.c_double()
+    _check(load_library().cc_autotune(ctx, g, int(k), int(seed), int(reps), ctypes.byref(t), ctypes.byref(ms)))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}, ms.value
 
 
 def cc_draw_samples(n: int, k: int, seed: int) -> np.ndarray:

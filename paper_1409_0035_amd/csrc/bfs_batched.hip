@@ -16,11 +16,16 @@
 //   push  for every node u that gained bits at level L-1 and every out-arc
 //         u->v: NX(v) |= S_{L-1}(u) (atomic OR); then new_L(v) = NX(v) & ~S_{L-1}(v).
 //         The same triangle argument makes the extra (older) bits harmless.
-// The host picks push while the frontier's out-arcs are few compared with the
-// arcs a pull would scan.
+// Push is chosen while the frontier's out-arcs are few compared with the
+// arcs a pull would scan.  That choice, and the end of the search, are made on
+// the device by the last block of each level's merge launch, so the host
+// enqueues a batch of levels (as many as the graph's last search needed) and
+// reads the control block once per batch; levels past the end exit at once.
+// Two launches per level: k_scatter_level (push, or the hub pull) and
+// k_group_level (the other nodes' pull, the merge and the decision).
 //
 // Pull work decomposition (node ids are degree-sorted by the graph builder):
-//   * hub nodes (the leading nh ids) are scanned by k_hub_level in fixed chunks
+//   * hub nodes (the leading nh ids) are scanned by k_scatter_level in fixed chunks
 //     of arcs, one wave per chunk, reduced with DPP and OR-ed atomically into
 //     NX(hub);
 //   * every other node belongs to a group of 64 consecutive ids handled by one
@@ -129,7 +134,10 @@ struct WaveCounts {
     int32_t n_new = 0, n_out = 0;
 };
 
-__device__ __forceinline__ void flush_counts(WaveCounts c, LevelCounters* slots) {
+// Returns, in thread 0, a value that depends on every counter atomic's result
+// (always 0): using it makes the thread wait until those atomics have been
+// performed, so a later atomic can announce them to other blocks.
+__device__ __forceinline__ uint32_t flush_counts(WaveCounts c, LevelCounters* slots) {
     __shared__ int64_t red[kWaves][5];
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int64_t a = wave_sum64(c.arcs), f = wave_sum64(c.farcs), h = wave_sum64(c.hub);
@@ -147,12 +155,15 @@ __device__ __forceinline__ void flush_counts(WaveCounts c, LevelCounters* slots)
         for (int w = 0; w < kWaves; w++)
             for (int q = 0; q < 5; q++) t[q] += red[w][q];
         LevelCounters* c0 = slots + (blockIdx.x % kCounterSlots);
-        if (t[0]) atomicAdd((unsigned long long*)&c0->arcs, (unsigned long long)t[0]);
-        if (t[1]) atomicAdd((unsigned long long*)&c0->frontier_arcs, (unsigned long long)t[1]);
-        if (t[2]) atomicAdd(&c0->n_new, (int32_t)t[2]);
-        if (t[3]) atomicAdd(&c0->n_out, (int32_t)t[3]);
-        if (t[4]) atomicAdd((unsigned long long*)&c0->matched, (unsigned long long)t[4]);
+        uint64_t r = 0;
+        if (t[0]) r |= atomicAdd((unsigned long long*)&c0->arcs, (unsigned long long)t[0]);
+        if (t[1]) r |= atomicAdd((unsigned long long*)&c0->frontier_arcs, (unsigned long long)t[1]);
+        if (t[2]) r |= (uint32_t)atomicAdd(&c0->n_new, (int32_t)t[2]);
+        if (t[3]) r |= (uint32_t)atomicAdd(&c0->n_out, (int32_t)t[3]);
+        if (t[4]) r |= atomicAdd((unsigned long long*)&c0->matched, (unsigned long long)t[4]);
+        return (uint32_t)(r >> 63);  // counts stay far below 2^63
     }
+    return 0;
 }
 
 template <int W>
@@ -189,6 +200,93 @@ __global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_b
     atomicAdd((unsigned long long*)&cnt[i % kCounterSlots].frontier_arcs, (unsigned long long)(out_rp[v + 1] - out_rp[v]));
 }
 
+// Traversal state the level kernels read at entry and k_decide updates after
+// each level, so that a whole batch of levels runs without the host.
+struct BfsCtl {
+    int32_t done;         // 1 once the traversal has ended (status says how)
+    int32_t status;       // 0 every node full, 1 level capacity exhausted, 2 a node no sample reaches
+    int32_t lmax;         // last level at which some node gained a bit
+    int32_t pull;         // direction of the next level: 1 pull, 0 push
+    int32_t levels;       // levels run
+    int32_t pull_levels;  // of which pulls
+    uint32_t ticket;      // blocks of the current merge launch that have finished
+    int32_t pad;
+    int64_t frontier_arcs;  // out-arcs of the nodes that changed at the last level
+    int64_t pull_arcs;      // arcs the last pull scanned (what a pull would cost now)
+    int64_t arcs;           // arcs scanned or pushed along, all levels
+    int64_t hub_arcs;       // of which by the hub-chunk pull
+    int64_t push_arcs;
+    int64_t push_atomics;
+    int64_t nodes;          // node slots of live groups visited
+};
+constexpr int32_t kModeLog = 4096;  // levels whose direction is logged for the host
+
+// One wave (lanes = counter slots): sums and clears the counter slots of the
+// level just run, records it, and decides whether and how the next level
+// runs (push iff the frontier's out-arcs times alpha are below what the last
+// pull scanned).  Level 0 only initialises the state from the samples'
+// frontier.  Counters are read with device-scope atomic loads: they were
+// written by atomics of other blocks.
+__device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, int32_t level, int32_t cap,
+                            int64_t arcs_total, int32_t alpha) {
+    const int t = lane_id();
+    LevelCounters* c = cnt + t;
+    const int64_t arcs = wave_sum64(__hip_atomic_load(&c->arcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const int64_t farcs = wave_sum64(__hip_atomic_load(&c->frontier_arcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const int64_t matched = wave_sum64(__hip_atomic_load(&c->matched, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const int64_t n_new = wave_sum64(__hip_atomic_load(&c->n_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const int64_t n_out = wave_sum64(__hip_atomic_load(&c->n_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    *c = LevelCounters{};
+    if (t != 0) return;
+    BfsCtl s = *ctl;
+    s.ticket = 0;
+    if (level == 0) {
+        s = BfsCtl{};
+        s.pull_arcs = arcs_total > 0 ? arcs_total : 1;
+        s.frontier_arcs = farcs;
+        s.pull = farcs * alpha >= s.pull_arcs ? 1 : 0;
+        *ctl = s;
+        return;
+    }
+    if (s.done) {
+        *ctl = s;
+        return;
+    }
+    s.levels += 1;
+    if (level < kModeLog) mode_log[level] = s.pull;
+    if (s.pull) {
+        s.pull_levels += 1;
+        s.arcs += arcs + matched;
+        s.hub_arcs += matched;
+        s.pull_arcs = arcs + matched > 0 ? arcs + matched : 1;
+    } else {
+        s.arcs += arcs;
+        s.push_arcs += arcs;
+        s.push_atomics += matched;
+    }
+    s.nodes += n_out * 64;
+    if (n_new > 0) s.lmax = level;
+    s.frontier_arcs = farcs;
+    if (n_out == 0) {
+        s.done = 1;
+    } else if (n_new == 0) {
+        s.done = 1;
+        s.status = 2;
+    } else if (level + 1 >= cap) {
+        s.done = 1;
+        s.status = 1;
+    } else {
+        s.pull = farcs * alpha >= s.pull_arcs ? 1 : 0;
+    }
+    *ctl = s;
+}
+
+// level 0 (after the samples are placed): one wave
+__global__ void k_decide(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, int32_t level, int32_t cap,
+                         int64_t arcs_total, int32_t alpha) {
+    decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha);
+}
+
 // push along arc u->x of the mask su (u's seen mask): only bits x has not seen
 // and that are not already pending in NX(x) need the atomic, so popular
 // targets stop taking atomics once they hold the frontier's bits (a stale NX
@@ -216,115 +314,125 @@ __device__ __forceinline__ void push_arc(const uint64_t* __restrict__ Sprev, uin
     }
 }
 
-// push, nodes past the hub prefix (out-degree <= the hub threshold): one wave
-// per group of 64 nodes; every node of the group that gained bits at the
-// previous level sends its mask along its out-arcs (lanes over arcs)
+// Push from the nodes of group g that gained bits at the previous level
+// (nodes past the hub prefix, out-degree at most the hub threshold): lanes
+// over each changed node's out-arcs.
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col,
-                                                 const int32_t* __restrict__ chg, const uint8_t* __restrict__ gfull,
-                                                 int64_t n, int32_t g0, int32_t ngroups, int32_t prev_level,
-                                                 const uint64_t* __restrict__ Sprev, uint64_t* NX,
-                                                 LevelCounters* cnt) {
+__device__ __forceinline__ void push_group(const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col,
+                                           const int32_t* __restrict__ chg, int64_t n, int32_t g, int32_t prev_level,
+                                           const uint64_t* __restrict__ Sprev, uint64_t* NX, WaveCounts& wc,
+                                           int64_t& atomics) {
     const int lane = lane_id();
-    const int32_t waves = gridDim.x * kWaves;
-    WaveCounts wc;
-    int64_t atomics = 0;
-    for (int32_t g = g0 + blockIdx.x * kWaves + (threadIdx.x >> 6); g < ngroups; g += waves) {
-        if (gfull[g]) continue;
-        const int64_t v = (int64_t)g * 64 + lane;
-        uint64_t m = __ballot(v < n && chg[v] == prev_level);
-        while (m) {
-            const int s = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const int64_t u = (int64_t)g * 64 + s;
-            uint64_t su[W];
-#pragma unroll
-            for (int w = 0; w < W; w++) su[w] = Sprev[u * W + w];
-            const uint32_t b = out_rp[u], e = out_rp[u + 1];
-            for (uint32_t t = b + lane; t < e; t += 64) {
-                ++wc.arcs;
-                push_arc<W>(Sprev, NX, out_col[t], su, atomics);
-            }
-        }
-    }
-    wc.hub = atomics;
-    flush_counts(wc, cnt);
-}
-
-// push, hub prefix: one wave per chunk (node, first arc, end arc) of out-arcs,
-// so a frontier node with a huge out-degree is spread over many waves
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_push_hub(const int32_t* __restrict__ out_col,
-                                                     const int32_t* __restrict__ chunks, int32_t n_chunks,
-                                                     const int32_t* __restrict__ chg, int32_t prev_level,
-                                                     const uint64_t* __restrict__ Sprev, uint64_t* NX,
-                                                     LevelCounters* cnt) {
-    const int lane = lane_id();
-    const int32_t waves = gridDim.x * kWaves;
-    WaveCounts wc;
-    int64_t atomics = 0;
-    for (int32_t c = blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_chunks; c += waves) {
-        const int64_t h = chunks[3 * c];
-        if (chg[h] != prev_level) continue;
-        const uint32_t b = (uint32_t)chunks[3 * c + 1], e = (uint32_t)chunks[3 * c + 2];
+    const int64_t v = (int64_t)g * 64 + lane;
+    uint64_t m = __ballot(v < n && chg[v] == prev_level);
+    while (m) {
+        const int s = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int64_t u = (int64_t)g * 64 + s;
         uint64_t su[W];
 #pragma unroll
-        for (int w = 0; w < W; w++) su[w] = Sprev[h * W + w];
+        for (int w = 0; w < W; w++) su[w] = Sprev[u * W + w];
+        const uint32_t b = out_rp[u], e = out_rp[u + 1];
         for (uint32_t t = b + lane; t < e; t += 64) {
             ++wc.arcs;
             push_arc<W>(Sprev, NX, out_col[t], su, atomics);
         }
     }
-    wc.hub = atomics;
-    flush_counts(wc, cnt);
 }
 
-// pull over a hub's in-arcs: one wave per chunk (hub, first arc, end arc)
+// Push along one chunk (node, first arc, end arc) of a hub's out-arcs, so a
+// frontier node with a huge out-degree is spread over many waves.
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_hub_level(const int32_t* __restrict__ col,
-                                                      const uint64_t* __restrict__ Sprev,
-                                                      const int32_t* __restrict__ chunks, int32_t n_chunks,
-                                                      uint64_t* NX, uint64_t lastmask, LevelCounters* cnt) {
+__device__ __forceinline__ void push_chunk(const int32_t* __restrict__ out_col, const int32_t* __restrict__ chunk,
+                                           const int32_t* __restrict__ chg, int32_t prev_level,
+                                           const uint64_t* __restrict__ Sprev, uint64_t* NX, WaveCounts& wc,
+                                           int64_t& atomics) {
+    const int64_t h = chunk[0];
+    if (chg[h] != prev_level) return;
+    const uint32_t b = (uint32_t)chunk[1], e = (uint32_t)chunk[2];
+    uint64_t su[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) su[w] = Sprev[h * W + w];
+    for (uint32_t t = b + lane_id(); t < e; t += 64) {
+        ++wc.arcs;
+        push_arc<W>(Sprev, NX, out_col[t], su, atomics);
+    }
+}
+
+// Pull over one chunk (hub, first arc, end arc) of a hub's in-arcs: OR of the
+// neighbours' masks, new bits into NX with one atomic per word.
+template <int W>
+__device__ __forceinline__ void hub_chunk(const int32_t* __restrict__ col, const uint64_t* __restrict__ Sprev,
+                                          const int32_t* __restrict__ chunk, uint64_t* NX, uint64_t lastmask,
+                                          int64_t& scanned) {
     const int lane = lane_id();
+    const int64_t h = chunk[0];
+    const uint32_t b = (uint32_t)chunk[1], e = (uint32_t)chunk[2];
+    uint64_t sh[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) sh[w] = Sprev[h * W + w];
+    const uint32_t need = pairs_needed<W>(sh, lastmask);
+    if (!need) return;  // full hub: nothing to find
+    uint64_t acc[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) acc[w] = 0;
+    uint32_t t = b + lane;
+    for (; t + 64 < e; t += 128) {
+        const int64_t u0 = col[t], u1 = col[t + 64];
+        uint64_t a0[W], a1[W];
+        load_mask<W>(Sprev, u0, need, a0);
+        load_mask<W>(Sprev, u1, need, a1);
+#pragma unroll
+        for (int w = 0; w < W; w++) acc[w] |= a0[w] | a1[w];
+        scanned += 2;
+    }
+    if (t < e) {
+        uint64_t a0[W];
+        load_mask<W>(Sprev, col[t], need, a0);
+#pragma unroll
+        for (int w = 0; w < W; w++) acc[w] |= a0[w];
+        scanned += 1;
+    }
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        const uint64_t r = wave_or64_dpp(acc[w]) & ~sh[w];
+        if (lane == 0 && r) atomicOr((unsigned long long*)&NX[h * W + w], (unsigned long long)r);
+    }
+}
+
+// The scatter half of a level, its direction taken from the control block:
+//   pull: one wave per chunk of a hub's in-arcs (the other nodes pull in the
+//         merge kernel);
+//   push: one wave per chunk of a hub's out-arcs, then one wave per group of
+//         the other nodes, each sending the masks of nodes that changed at
+//         the previous level along their out-arcs.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_scatter_level(
+    const int32_t* __restrict__ col, const int32_t* __restrict__ hub_chunks, int32_t n_hub_chunks,
+    const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col, const int32_t* __restrict__ push_chunks,
+    int32_t n_push_chunks, int32_t g0, int32_t ngroups, const int32_t* __restrict__ chg, int64_t n,
+    int32_t prev_level, const uint64_t* __restrict__ Sprev, uint64_t* NX, uint64_t lastmask, LevelCounters* cnt,
+    const BfsCtl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int pull = ctl->pull;
     const int32_t waves = gridDim.x * kWaves;
-    int64_t scanned = 0;
+    const int32_t wid = blockIdx.x * kWaves + (threadIdx.x >> 6);
     WaveCounts wc;
-    for (int32_t c = blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_chunks; c += waves) {
-        const int64_t h = chunks[3 * c];
-        const uint32_t b = (uint32_t)chunks[3 * c + 1], e = (uint32_t)chunks[3 * c + 2];
-        uint64_t sh[W];
-#pragma unroll
-        for (int w = 0; w < W; w++) sh[w] = Sprev[h * W + w];
-        const uint32_t need = pairs_needed<W>(sh, lastmask);
-        if (!need) continue;  // full hub: nothing to find
-        uint64_t acc[W];
-#pragma unroll
-        for (int w = 0; w < W; w++) acc[w] = 0;
-        uint32_t t = b + lane;
-        for (; t + 64 < e; t += 128) {
-            const int64_t u0 = col[t], u1 = col[t + 64];
-            uint64_t a0[W], a1[W];
-            load_mask<W>(Sprev, u0, need, a0);
-            load_mask<W>(Sprev, u1, need, a1);
-#pragma unroll
-            for (int w = 0; w < W; w++) acc[w] |= a0[w] | a1[w];
-            scanned += 2;
-        }
-        if (t < e) {
-            uint64_t a0[W];
-            load_mask<W>(Sprev, col[t], need, a0);
-#pragma unroll
-            for (int w = 0; w < W; w++) acc[w] |= a0[w];
-            scanned += 1;
-        }
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            const uint64_t r = wave_or64_dpp(acc[w]) & ~sh[w];
-            if (lane == 0 && r) atomicOr((unsigned long long*)&NX[h * W + w], (unsigned long long)r);
+    int64_t extra = 0;  // pull: arcs scanned; push: atomics issued
+    if (pull) {
+        for (int32_t c = wid; c < n_hub_chunks; c += waves) hub_chunk<W>(col, Sprev, hub_chunks + 3 * (int64_t)c, NX, lastmask, extra);
+    } else {
+        const int64_t items = (int64_t)n_push_chunks + (ngroups - g0);
+        for (int64_t t = wid; t < items; t += waves) {
+            if (t < n_push_chunks)
+                push_chunk<W>(out_col, push_chunks + 3 * t, chg, prev_level, Sprev, NX, wc, extra);
+            else
+                push_group<W>(out_rp, out_col, chg, n, g0 + (int32_t)(t - n_push_chunks), prev_level, Sprev, NX, wc,
+                              extra);
         }
     }
-    wc.hub = scanned;
-    flush_counts(wc, cnt);
+    wc.hub = extra;
+    (void)flush_counts(wc, cnt);
 }
 
 template <int W>
@@ -332,9 +440,11 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
     const uint32_t* __restrict__ rp, const int32_t* __restrict__ col, const uint32_t* __restrict__ out_rp,
     const uint64_t* __restrict__ Sprev, uint64_t* __restrict__ Scur, uint64_t* __restrict__ snap,
     int32_t* __restrict__ fill_level, uint8_t* __restrict__ gfull, int32_t* __restrict__ chg, int32_t ngroups,
-    int64_t n, int64_t nh, uint64_t* __restrict__ NX, int pull, uint64_t lastmask, int32_t level,
+    int64_t n, int64_t nh, uint64_t* __restrict__ NX, uint64_t lastmask, int32_t level,
     const int32_t* __restrict__ sidx, int32_t* __restrict__ hist, int64_t hlen, int64_t k, int32_t src_base,
-    LevelCounters* __restrict__ cnt) {
+    LevelCounters* __restrict__ cnt, BfsCtl* ctl, int32_t* mode_log, int32_t cap, int64_t arcs_total, int32_t alpha) {
+    if (ctl->done) return;
+    const int pull = ctl->pull;
     __shared__ uint64_t lds_acc[kWaves][64][W];
     __shared__ int32_t lds_hist[W * 64];
     const int lane = lane_id();
@@ -485,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
         }
     }
 
-    flush_counts(wc, cnt);
+    const uint32_t token = flush_counts(wc, cnt);
     if (do_hist) {
 #pragma unroll
         for (int w = 0; w < W; w++)
@@ -497,6 +607,13 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
             if (c) atomicAdd(&hist[((int64_t)slot * k + src_base + t) * hlen + level], c);
         }
     }
+    // the last block to finish decides the next level (its counters are
+    // complete: each block takes its ticket only after its counter atomics
+    // have returned)
+    __shared__ uint32_t last;
+    if (threadIdx.x == 0) last = atomicAdd(&ctl->ticket, 1u + token) == gridDim.x - 1;
+    __syncthreads();
+    if (last && threadIdx.x < 64) decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha);
 }
 
 __global__ void k_zero_counters(LevelCounters* c) {
@@ -506,16 +623,11 @@ __global__ void k_zero_counters(LevelCounters* c) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline void read_counters(hipStream_t st, LevelCounters* dev, LevelCounters* host, LevelCounters& sum) {
-    CCG_HIP(hipMemcpyAsync(host, dev, sizeof(LevelCounters) * kCounterSlots, hipMemcpyDeviceToHost, st));
-    CCG_HIP(hipStreamSynchronize(st));
-    sum_counters(host, kCounterSlots, sum);
-}
 
 template <int W>
 int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
                   int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, LevelCounters* cnt_dev,
-                  LevelCounters* cnt_host, TravStats* stats) {
+                  TravStats* stats, EventPool* evp) {
     const int64_t n = gv.n;
     const int32_t ngroups = (int32_t)((n + 63) / 64);
     char* p = (char*)scratch;
@@ -528,6 +640,10 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     int32_t* chg = (int32_t*)p;
     p += align256(sizeof(int32_t) * n);
     uint8_t* gfull = (uint8_t*)p;
+    p += align256((size_t)ngroups);
+    BfsCtl* ctl = (BfsCtl*)p;
+    p += align256(sizeof(BfsCtl));
+    int32_t* mode_log = (int32_t*)p;
 
     const size_t plane = (size_t)n * W;
     const int rem = kg - (W - 1) * 64;
@@ -538,73 +654,77 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
     hipLaunchKernelGGL((k_init_samples<W>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, src_base, S0,
                        out.snap, chg, gv.out_rp, cnt_dev);
-    LevelCounters sum;
-    read_counters(st, cnt_dev, cnt_host, sum);
-    stats->launches += 3;
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev, ctl, mode_log, 0, out.cap, gv.arcs,
+                       gv.alpha);
+    stats->launches += 4;
 
-    int64_t frontier_arcs = sum.frontier_arcs;
-    int64_t pull_arcs = gv.arcs;  // arcs a pull level would scan (refreshed after each pull)
-    uint64_t* Sp = S0;
-    uint64_t* Sc = S1;
-    KernelTimer kt, kh;
-    int32_t lmax = 0;
-    const unsigned gb = (unsigned)std::min<int64_t>((ngroups + kWaves - 1) / kWaves, 2048);
-    for (int32_t level = 1;; ++level) {
-        if (level >= out.cap) return 1;  // level-mask capacity exhausted: retry with more levels
-        const int pull = frontier_arcs * 4 >= pull_arcs ? 1 : 0;
-        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
-        kt.start(st);
-        if (!pull) {
-            if (gv.n_push_chunks > 0) {
-                const int64_t hb = std::min<int64_t>((gv.n_push_chunks + kWaves - 1) / kWaves, 4096);
-                hipLaunchKernelGGL((k_push_hub<W>), dim3((unsigned)hb), dim3(kBlock), 0, st, gv.out_col,
-                                   gv.push_chunks, gv.n_push_chunks, chg, level - 1, Sp, NX, cnt_dev);
-            }
-            const int32_t g0 = gv.n_push_chunks > 0 ? (int32_t)((gv.nh + 63) / 64) : 0;  // hubs went by chunks
-            if (g0 < ngroups) {
-                hipLaunchKernelGGL((k_push<W>), dim3((unsigned)std::min<int64_t>((ngroups - g0 + kWaves - 1) / kWaves, 2048)),
-                                   dim3(kBlock), 0, st, gv.out_rp, gv.out_col, chg, gfull, n, g0, ngroups, level - 1, Sp,
-                                   NX, cnt_dev);
-            }
-        } else if (gv.n_hub_chunks > 0) {
-            const int64_t hb = std::min<int64_t>((gv.n_hub_chunks + kWaves - 1) / kWaves, 4096);
-            kh.start(st);
-            hipLaunchKernelGGL((k_hub_level<W>), dim3((unsigned)hb), dim3(kBlock), 0, st, gv.col, Sp, gv.hub_chunks,
-                               gv.n_hub_chunks, NX, lastmask, cnt_dev);
-            kh.stop(st);
+    const unsigned gb = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((ngroups + kWaves - 1) / kWaves, std::max(1, gv.level_blocks)));
+    const int32_t g0 = gv.n_push_chunks > 0 ? (int32_t)((gv.nh + 63) / 64) : 0;  // hubs push by chunks
+    const int64_t scatter_items = std::max<int64_t>(gv.n_hub_chunks, (int64_t)gv.n_push_chunks + (ngroups - g0));
+    const unsigned sb = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((scatter_items + kWaves - 1) / kWaves, std::max(1, gv.scatter_blocks)));
+    constexpr int32_t kTimedLevels = 256;  // levels whose scatter launch gets its own events
+    std::vector<int32_t> modes;
+    BfsCtl hc{};
+    int32_t level = 1;
+    int32_t batch = std::max<int32_t>(out.hint, 4);
+    for (;;) {
+        const int32_t end = (int32_t)std::min<int64_t>((int64_t)level + batch, out.cap);
+        if (evp) CCG_HIP(hipEventRecord(evp->at(0), st));
+        for (int32_t L = level; L < end; L++) {
+            uint64_t* Sp = (L & 1) ? S0 : S1;  // level 1 reads S0
+            uint64_t* Sc = (L & 1) ? S1 : S0;
+            const bool timed = evp && L < kTimedLevels;
+            if (timed) CCG_HIP(hipEventRecord(evp->at(2 + 2 * (size_t)L), st));
+            hipLaunchKernelGGL((k_scatter_level<W>), dim3(sb), dim3(kBlock), 0, st, gv.col, gv.hub_chunks,
+                               gv.n_hub_chunks, gv.out_rp, gv.out_col, gv.push_chunks, gv.n_push_chunks, g0, ngroups,
+                               chg, n, L - 1, Sp, NX, lastmask, cnt_dev, ctl);
+            if (timed) CCG_HIP(hipEventRecord(evp->at(3 + 2 * (size_t)L), st));
+            hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp, Sc,
+                               out.snap + (size_t)L * plane, out.fill_level, gfull, chg, ngroups, n, gv.nh, NX,
+                               lastmask, L, sidx, out.hist, out.hlen, (int64_t)k, src_base, cnt_dev, ctl, mode_log,
+                               out.cap, gv.arcs, gv.alpha);
         }
-        hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp, Sc,
-                           out.snap + (size_t)level * plane, out.fill_level, gfull, chg, ngroups, n, gv.nh, NX, pull,
-                           lastmask, level, sidx, out.hist, out.hlen, (int64_t)k, src_base, cnt_dev);
         CCG_HIP(hipGetLastError());
-        kt.stop(st);
-        read_counters(st, cnt_dev, cnt_host, sum);
-        stats->kernel_ms += kt.ms();
-        stats->kernel_launches += 1;
-        stats->launches += 3;
-        stats->levels += 1;
-        stats->arcs_scanned += sum.arcs + (pull ? sum.matched : 0);
-        if (pull && gv.n_hub_chunks > 0) {
-            stats->hub_ms += kh.ms();
-            stats->hub_launches += 1;
-            stats->hub_arcs += sum.matched;
+        if (evp) CCG_HIP(hipEventRecord(evp->at(1), st));
+        stats->launches += (int64_t)(end - level) * 2;
+        stats->kernel_launches += end - level;
+        const int32_t lo = std::min(level, kModeLog), hi = std::min(end, kModeLog);
+        modes.resize((size_t)std::max(hi, 1));
+        CCG_HIP(hipMemcpyAsync(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+        if (hi > lo)
+            CCG_HIP(hipMemcpyAsync(modes.data() + lo, mode_log + lo, sizeof(int32_t) * (hi - lo), hipMemcpyDeviceToHost,
+                                   st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (evp) {
+            float t = 0.f;
+            CCG_HIP(hipEventElapsedTime(&t, evp->at(0), evp->at(1)));
+            stats->kernel_ms += t;
+            for (int32_t L = level; L < std::min(end, kTimedLevels); L++) {
+                CCG_HIP(hipEventElapsedTime(&t, evp->at(2 + 2 * (size_t)L), evp->at(3 + 2 * (size_t)L)));
+                stats->scatter_ms += t;  // every launch, idle ones past the end included
+                stats->scatter_launches += 1;
+                if (L <= hc.levels && L < (int32_t)modes.size() && modes[(size_t)L]) stats->pull_scatter_ms += t;
+            }
         }
-        stats->nodes_visited += (int64_t)sum.n_out * 64;
-        if (pull) {
-            stats->pull_levels += 1;
-            pull_arcs = std::max<int64_t>(sum.arcs + sum.matched, 1);
-        } else {
-            stats->push_arcs += sum.arcs;
-            stats->push_atomics += sum.matched;
-        }
-        if (sum.n_new > 0) lmax = level;
-        frontier_arcs = sum.frontier_arcs;
-        if (sum.n_out == 0) break;             // every node full at the start of this level
-        if (sum.n_new == 0) return 2;          // nodes left that no sample can reach
-        std::swap(Sp, Sc);
+        if (hc.done || end >= out.cap) break;
+        level = end;
+        batch = std::max<int32_t>(batch * 2, 8);
     }
-    if (lmax > stats->maxd) stats->maxd = lmax;
-    *out.lmax = std::max(*out.lmax, lmax);
+    stats->levels += hc.levels;
+    stats->arcs_scanned += hc.arcs;
+    stats->nodes_visited += hc.nodes;
+    stats->push_arcs += hc.push_arcs;
+    stats->push_atomics += hc.push_atomics;
+    stats->hub_arcs += hc.hub_arcs;
+    stats->scatter_arcs += hc.hub_arcs + hc.push_arcs;
+    stats->pull_levels += hc.pull_levels;
+    stats->bfs_levels = std::max<int32_t>(stats->bfs_levels, hc.levels);
+    if (!hc.done || hc.status == 1) return 1;  // level-mask capacity exhausted: retry with more levels
+    if (hc.status == 2) return 2;              // nodes left that no sample can reach
+    if (hc.lmax > stats->maxd) stats->maxd = hc.lmax;
+    *out.lmax = std::max(*out.lmax, hc.lmax);
     return 0;
 }
 
@@ -614,19 +734,20 @@ size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh) {
     (void)nh;
     const int W = (kg + 63) / 64;
     const int64_t ngroups = (n + 63) / 64;
-    return align256(sizeof(uint64_t) * n * W) * 3 + align256(sizeof(int32_t) * n) + align256((size_t)ngroups) + 1024;
+    return align256(sizeof(uint64_t) * n * W) * 3 + align256(sizeof(int32_t) * n) + align256((size_t)ngroups) +
+           align256(sizeof(BfsCtl)) + align256(sizeof(int32_t) * kModeLog) + 1024;
 }
 
 int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
                 int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, size_t scratch_size,
-                LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats) {
+                LevelCounters* cnt_dev, TravStats* stats, EventPool* evp) {
     if (scratch_size < bfs_batched_scratch(gv.n, kg, gv.nh)) throw HipError{hipErrorOutOfMemory, "bfs_batched scratch"};
     const int W = (kg + 63) / 64;
     switch (W) {
-        case 1: return bfs_batched_t<1>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
-        case 2: return bfs_batched_t<2>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
-        case 3: return bfs_batched_t<3>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
-        default: return bfs_batched_t<4>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, cnt_host, stats);
+        case 1: return bfs_batched_t<1>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, stats, evp);
+        case 2: return bfs_batched_t<2>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, stats, evp);
+        case 3: return bfs_batched_t<3>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, stats, evp);
+        default: return bfs_batched_t<4>(st, gv, samples_dev, kg, src_base, k, out, sidx, scratch, cnt_dev, stats, evp);
     }
 }
 

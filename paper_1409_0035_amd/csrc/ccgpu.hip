@@ -153,6 +153,7 @@ struct Lane {
     Arena arena2;     // epilogue tables (sized once the largest distance is known)
     LevelCounters* cnt_host = nullptr;  // pinned
     hipEvent_t ev[4] = {};
+    EventPool events;  // per-launch timing inside the traversals
     void init(hipStream_t s) {
         if (s) {
             stream = s;
@@ -185,6 +186,8 @@ struct cc_graph {
     void* mem[10] = {};
     size_t bytes = 0;
     std::vector<int32_t> inv;  // caller's id -> internal id
+    mutable std::atomic<int32_t> bfs_hint{0};  // levels the last batched traversal of this graph ran
+    cc_tuning tune{4, 2048, 4096, 1, 1024, 64};  // launch shapes (cc_graph_set_tuning / cc_autotune)
 };
 
 struct cc_job {
@@ -459,6 +462,7 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             if (const char* e = std::getenv("CCGPU_DELTA_MULT")) mult = std::atof(e);
             g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(mult * mean));
         }
+        g->tune.delta = (int32_t)std::min<uint32_t>(std::max<uint32_t>(g->dg.delta, 1u), INT32_MAX);
         std::vector<int32_t> ch_in = hub_chunk_list(prp, nh);
         std::vector<int32_t> ch_out = directed ? hub_chunk_list(rp, nh) : std::vector<int32_t>();
 
@@ -601,9 +605,11 @@ void record_timing(cc_timing* timing, Lane& L, const TravStats& stats, int db) {
     timing->kernel_ms = stats.kernel_ms;
     timing->kernel_launches = stats.kernel_launches;
     timing->arcs_matched = stats.push_arcs;
-    timing->hub_ms = stats.hub_ms;
-    timing->hub_launches = stats.hub_launches;
+    timing->scatter_ms = stats.scatter_ms;
+    timing->scatter_launches = stats.scatter_launches;
+    timing->scatter_arcs = stats.scatter_arcs;
     timing->hub_arcs = stats.hub_arcs;
+    timing->pull_scatter_ms = stats.pull_scatter_ms;
     timing->pull_levels = stats.pull_levels;
 }
 
@@ -618,8 +624,11 @@ void add_stats(TravStats& a, const TravStats& b) {
     a.pull_levels += b.pull_levels;
     a.push_arcs += b.push_arcs;
     a.push_atomics += b.push_atomics;
-    a.hub_ms += b.hub_ms;
-    a.hub_launches += b.hub_launches;
+    a.bfs_levels = std::max(a.bfs_levels, b.bfs_levels);
+    a.scatter_ms += b.scatter_ms;
+    a.scatter_launches += b.scatter_launches;
+    a.scatter_arcs += b.scatter_arcs;
+    a.pull_scatter_ms += b.pull_scatter_ms;
     a.hub_arcs += b.hub_arcs;
     a.maxd = std::max(a.maxd, b.maxd);
 }
@@ -739,8 +748,12 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     std::call_once(ctx->wgrid_once, [ctx] {
                         ctx->wgrid = std::getenv("CCGPU_PERSISTENT") ? weighted_persistent_grid(ctx->device) : 0;
                     });
+                    WeightedShape shape;
+                    shape.delta = (uint32_t)std::max(1, gr->tune.delta);
+                    shape.round_blocks = gr->tune.round_blocks;
+                    shape.local_passes = gr->tune.local_passes;
                     const int wr = sssp_weighted(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
-                                                 (uint32_t*)Dt + (size_t)s0 * n, g.delta, ts, trav_scratch, &md, &ds,
+                                                 (uint32_t*)Dt + (size_t)s0 * n, shape, ts, trav_scratch, &md, &ds,
                                                  ctx->wgrid);
                     if (wr == 2) rc = 2;
                     else if (wr == 4) return fail(CC_EOVERFLOW, "a weighted distance or work pile overflowed");
@@ -767,6 +780,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 gv.n_hub_chunks = dir == 0 ? g.n_hub_chunks_in : g.n_hub_chunks_out;
                 gv.push_chunks = dir == 0 ? g.hub_chunks_out : g.hub_chunks_in;
                 gv.n_push_chunks = dir == 0 ? g.n_hub_chunks_out : g.n_hub_chunks_in;
+                gv.alpha = gr->tune.alpha;
+                gv.level_blocks = gr->tune.level_blocks;
+                gv.scatter_blocks = gr->tune.scatter_blocks;
                 for (int32_t s0 = 0; s0 < k && rc == 0; s0 += 256) {
                     const int32_t kg = std::min(256, k - s0);
                     int32_t lm = 0;
@@ -777,8 +793,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     lv.hist = hist;
                     lv.hlen = cap;
                     lv.lmax = &lm;
-                    rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, L.cnt_host,
-                                     &ds);
+                    lv.hint = gr->bfs_hint.load(std::memory_order_relaxed);
+                    rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, &ds, &L.events);
+                    if (rc == 0) gr->bfs_hint.store(ds.bfs_levels, std::memory_order_relaxed);
                     if (rc != 0) break;
                     lmax_dir[dir] = std::max(lmax_dir[dir], lm);
                     if (!bits_path) {
@@ -1000,6 +1017,117 @@ extern "C" cc_status cc_last_timing(const cc_context* ctx, cc_timing* t) {
     if (!ctx || !t) return fail(CC_EINVAL, "cc_last_timing: null argument");
     *t = ctx->last;
     return CC_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+
+namespace {
+
+cc_status check_tuning(const cc_tuning* t) {
+    if (t->alpha < 1 || t->alpha > 1024) return fail(CC_EINVAL, "alpha must be in 1..1024");
+    if (t->level_blocks < 1 || t->level_blocks > 65535) return fail(CC_EINVAL, "level_blocks must be in 1..65535");
+    if (t->scatter_blocks < 1 || t->scatter_blocks > 65535) return fail(CC_EINVAL, "scatter_blocks must be in 1..65535");
+    if (t->delta < 1) return fail(CC_EINVAL, "delta must be >= 1");
+    if (t->round_blocks < 1 || t->round_blocks > 65535) return fail(CC_EINVAL, "round_blocks must be in 1..65535");
+    if (t->local_passes < 0 || t->local_passes > 1024) return fail(CC_EINVAL, "local_passes must be in 0..1024");
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" cc_status cc_graph_get_tuning(const cc_graph* g, cc_tuning* t) {
+    if (!g || !t) return fail(CC_EINVAL, "cc_graph_get_tuning: null argument");
+    *t = g->tune;
+    return CC_OK;
+}
+
+extern "C" cc_status cc_graph_set_tuning(cc_graph* g, const cc_tuning* t) {
+    if (!g || !t) return fail(CC_EINVAL, "cc_graph_set_tuning: null argument");
+    const cc_status s = check_tuning(t);
+    if (s != CC_OK) return s;
+    g->tune = *t;
+    return CC_OK;
+}
+
+extern "C" cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64_t seed, int32_t reps,
+                                 cc_tuning* best, double* best_ms) {
+    if (!ctx || !g) return fail(CC_EINVAL, "cc_autotune: null argument");
+    if (reps < 1 || reps > 100) return fail(CC_EINVAL, "cc_autotune: reps must be in 1..100");
+    cc_params p{};
+    p.k = k;
+    p.mode = CC_BATCHED;
+    p.seed = seed;
+    Resolved r;
+    cc_status s = resolve_params(g, &p, r);
+    if (s != CC_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return guarded(ctx, [&]() -> cc_status {
+        const int64_t n = g->dg.n;
+        double* S = nullptr;
+        if (hipMalloc((void**)&S, sizeof(double) * (size_t)n) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CC_ENOMEM, "cc_autotune: output allocation failed");
+        }
+        cc_result out{};
+        out.S_hyb = S;
+        const cc_tuning start = g->tune;
+        // median device time of `reps` estimates with setting t (+inf on error)
+        auto measure = [&](const cc_tuning& t) -> double {
+            g->tune = t;
+            std::vector<double> ms;
+            for (int i = 0; i < reps; i++) {
+                cc_timing tm{};
+                if (run_job(ctx, g, r, &out, ctx->lane, &tm) != CC_OK) return HUGE_VAL;
+                ms.push_back(tm.total_ms);
+            }
+            std::sort(ms.begin(), ms.end());
+            return ms[ms.size() / 2];
+        };
+        cc_tuning cur = start;
+        double cur_ms = HUGE_VAL;
+        try {
+            (void)measure(cur);  // warm the lane's buffers and the level hint
+            cur_ms = measure(cur);
+            auto try_knob = [&](int32_t cc_tuning::*field, const std::vector<int32_t>& cands) {
+                for (int32_t v : cands) {
+                    if (v == cur.*field) continue;
+                    cc_tuning t = cur;
+                    t.*field = v;
+                    if (check_tuning(&t) != CC_OK) continue;
+                    const double m = measure(t);
+                    if (m < cur_ms) {
+                        cur_ms = m;
+                        cur = t;
+                    }
+                }
+            };
+            if (g->dg.weighted) {
+                const int32_t d0 = std::max(1, start.delta);
+                std::vector<int32_t> ds;
+                for (double f : {0.25, 0.5, 2.0, 4.0, 8.0}) ds.push_back((int32_t)std::max<double>(1.0, std::llround(d0 * f)));
+                try_knob(&cc_tuning::delta, ds);
+                try_knob(&cc_tuning::local_passes, {0, 8, 16, 32, 128});
+                try_knob(&cc_tuning::round_blocks, {256, 512, 2048, 4096});
+            } else {
+                try_knob(&cc_tuning::alpha, {1, 2, 8, 16, 32, 64});
+                try_knob(&cc_tuning::scatter_blocks, {1024, 2048, 8192, 16384});
+                try_knob(&cc_tuning::level_blocks, {512, 1024, 4096, 8192});
+            }
+        } catch (...) {
+            g->tune = start;
+            (void)hipFree(S);
+            throw;
+        }
+        (void)hipFree(S);
+        if (cur_ms == HUGE_VAL) {
+            g->tune = start;
+            return fail(CC_EDEVICE, "cc_autotune: no candidate ran");
+        }
+        g->tune = cur;
+        if (best) *best = cur;
+        if (best_ms) *best_ms = cur_ms;
+        return CC_OK;
+    });
 }
 
 // ---------------------------------------------------------------- serving

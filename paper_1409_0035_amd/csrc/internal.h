@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace ccg {
 
@@ -134,6 +135,7 @@ struct GridSync {
 };
 
 __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t nblocks) {
+    __shared__ uint32_t ok;  // thread 0's view of the abort flag, so the whole block agrees
     __syncthreads();
     if (threadIdx.x == 0) {
         if (__hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
@@ -168,9 +170,10 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t nblocks) {
             }
             __threadfence();
         }
+        ok = __hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     }
     __syncthreads();
-    return __hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    return ok != 0;
 }
 
 // ---------------------------------------------------------------- distances
@@ -228,6 +231,9 @@ struct BfsView {
     int32_t n_hub_chunks = 0;
     const int32_t* push_chunks = nullptr;  // the same over out_rp/out_col
     int32_t n_push_chunks = 0;
+    int32_t alpha = 4;  // a level pushes iff its frontier's out-arcs * alpha < what the last pull scanned
+    int32_t level_blocks = 2048;    // merge launch grid cap
+    int32_t scatter_blocks = 4096;  // scatter launch grid cap
 };
 
 // Where the batched BFS records its per-level seen masks.
@@ -238,6 +244,7 @@ struct BfsLevels {
     int32_t* hist = nullptr;      // optional [kHistSlotsBatched][k][hlen] per-sample level histogram
     int64_t hlen = 0;
     int32_t* lmax = nullptr;      // host: largest level with new bits (max over calls)
+    int32_t hint = 0;             // levels the host enqueues before its first check (0 = a few)
 };
 
 // ---------------------------------------------------------------- traversal API
@@ -253,10 +260,13 @@ struct TravStats {
     int64_t kernel_launches = 0;
     int64_t pull_levels = 0;
     int64_t push_arcs = 0;
-    double hub_ms = 0;       // summed duration of the hub-chunk kernel launches
-    int64_t hub_launches = 0;
-    int64_t hub_arcs = 0;    // arcs those launches scanned
+    double scatter_ms = 0;        // summed duration of the scatter (push / hub pull) launches
+    int64_t scatter_launches = 0;
+    int64_t scatter_arcs = 0;     // arcs they scanned (hub pulls) or pushed along (pushes)
+    double pull_scatter_ms = 0;   // of scatter_ms, the levels that pulled
+    int64_t hub_arcs = 0;         // arcs the hub pulls scanned
     int64_t push_atomics = 0;  // atomic ORs issued by push levels
+    int32_t bfs_levels = 0;    // most levels one batched traversal ran
 };
 
 // Event pair for timing one kernel launch on a stream.
@@ -280,6 +290,25 @@ struct KernelTimer {
     }
 };
 
+// Events created on first use and reused, for timing single launches.
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    hipEvent_t at(size_t i) {
+        while (ev.size() <= i) {
+            hipEvent_t e = nullptr;
+            CCG_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        return ev[i];
+    }
+    EventPool() = default;
+    EventPool(const EventPool&) = delete;
+    EventPool& operator=(const EventPool&) = delete;
+    ~EventPool() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 enum class DistKind { U8 = 1, U16 = 2, U32 = 4 };
 
 constexpr int kHistSlotsBatched = 32;  // spread copies of the per-level histogram counters
@@ -293,7 +322,7 @@ constexpr int kHistSlotsBatched = 32;  // spread copies of the per-level histogr
 // 2 = some node is unreachable from some sample.
 int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
                 int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, size_t scratch_size,
-                LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
+                LevelCounters* cnt_dev, TravStats* stats, EventPool* evp);
 size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh);
 
 // Distances of one sample group from its level masks into the node-major
@@ -314,8 +343,14 @@ void transpose_dist(hipStream_t st, const void* Dt, void* D, int64_t n, int32_t 
 // Weighted distances (positive integer lengths) from samples_dev[0..kg)
 // (internal ids) into source-major Dt[j][v] by near/far delta-stepping.
 // Returns 0 = done, 2 = some node unreached, 4 = overflow.
+// Launch shape of the delta-stepping rounds.
+struct WeightedShape {
+    uint32_t delta = 1;         // bucket width
+    int32_t round_blocks = 1024;
+    int32_t local_passes = 64;  // block-local relaxation passes per round
+};
 int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
-                  const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
+                  const int32_t* samples_dev, int32_t kg, uint32_t* Dt, const WeightedShape& shape, void* scratch,
                   size_t scratch_size, int64_t* maxd, TravStats* stats, int persistent_grid);
 // Blocks for the all-rounds cooperative launch on `device` (0 = not available).
 int weighted_persistent_grid(int device);

@@ -167,6 +167,7 @@ struct WArgs {
     int64_t cap;
     WDev* dev;
     uint32_t delta;
+    int32_t local_passes;
 };
 
 // One round (block-uniform control flow; every block returns normally).
@@ -276,13 +277,12 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
     // pair, each taking every kPairLanes-th arc, so a round costs about one
     // chain of dependent atomics instead of one per arc.  Pairs a block finds
     // below the bound are then relaxed by the same block from its stage for up
-    // to kLocalIters more passes before anything is flushed: relaxations may
+    // to local_passes more passes before anything is flushed: relaxations may
     // run in any order (label correcting), and improvements travel many hops
     // per launch instead of one.
     uint64_t* fpile = ep % 2 == 0 ? F0 : F1;
     int32_t* fcnt_cur = &dev->fcnt[ep % 3];
     constexpr int kPairLanes = 8;
-    constexpr int kLocalIters = 64;
     const int sub = threadIdx.x & (kPairLanes - 1);
     auto relax_batch = [&](auto fetch, int64_t lo, int64_t hi_ix) {
         for (int64_t base = lo; base < hi_ix; base += kBlock / kPairLanes) {
@@ -345,7 +345,7 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
         }
     };
     relax_batch([&](int64_t t) { return nin[t]; }, b0, b1);
-    for (int li = 0; li < kLocalIters; li++) {
+    for (int li = 0; li < A.local_passes; li++) {
         __syncthreads();
         const int32_t cnt = S.count[0];
         if (cnt == 0) break;  // block-uniform
@@ -434,8 +434,9 @@ int weighted_persistent_grid(int device) {
     return cus * std::max(1, std::min(per, 2));
 }
 int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
-                  const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
+                  const int32_t* samples_dev, int32_t kg, uint32_t* Dt, const WeightedShape& shape, void* scratch,
                   size_t scratch_size, int64_t* maxd, TravStats* stats, int persistent_grid) {
+    uint32_t delta = shape.delta;
     if (scratch_size < sssp_weighted_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted scratch"};
     const int64_t pairs = n * kg;
     char* p = (char*)scratch;
@@ -464,7 +465,8 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     hipLaunchKernelGGL(k_wseed, dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, n, Dt, N0, dev, delta);
     stats->launches += 3;
 
-    WArgs A{rp, col, w, n, Dt, fbit, N0, N1, F0, F1, pairs, dev, delta};
+    WArgs A{rp, col, w, n, Dt, fbit, N0, N1, F0, F1, pairs, dev, delta, std::max(0, shape.local_passes)};
+    const unsigned round_blocks = (unsigned)std::max(1, shape.round_blocks);
     WDev host;
     KernelTimer kt;
     // every round settles or moves at least one pair; far more rounds than
@@ -503,7 +505,7 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     for (;;) {
         kt.start(st);
         for (int q = 0; q < batch; q++, r++) {
-            hipLaunchKernelGGL(k_wround, dim3(1024), dim3(kBlock), 0, st, A, r);
+            hipLaunchKernelGGL(k_wround, dim3(round_blocks), dim3(kBlock), 0, st, A, r);
         }
         CCG_HIP(hipGetLastError());
         kt.stop(st);

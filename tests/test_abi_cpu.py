@@ -57,3 +57,14 @@ def test_context_without_device_is_an_error():
     with pytest.raises(cc.CCError) as e:
         cc.cc_context_create(0)
     assert e.value.status == cc.CC_EDEVICE
+
+
+def test_tuning_calls_reject_null_arguments():
+    """Argument checks that happen before any device work."""
+    lib = cc.load_library()
+    t = cc.cc_tuning()
+    assert lib.cc_graph_get_tuning(None, None) == cc.CC_EINVAL
+    assert lib.cc_graph_set_tuning(None, None) == cc.CC_EINVAL
+    assert lib.cc_autotune(None, None, 4, 0, 1, None, None) == cc.CC_EINVAL
+    assert lib.cc_graph_get_tuning(None, t) == cc.CC_EINVAL
+    assert cc.TUNING_FIELDS == ("alpha", "level_blocks", "scatter_blocks", "delta", "round_blocks", "local_passes")
