@@ -171,6 +171,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager estimates instead of replays of the captured estimate (CC_GRAPH, used by "
+                         "default where it applies; the roofline then comes from extra eager steps)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of running the library's autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -219,15 +222,17 @@ def main():
     def step(mode):
         cc.cc_estimate_device(ctx.handle, gh, k, out, mode=mode, seed=seed, stream=stream)
 
+    use_graph = not args.no_graph and not g.directed and g.w is None and k <= 256
+    main_mode = cc.CC_BATCHED | (cc.CC_GRAPH if use_graph else 0)
     for i in range(args.warmup):
-        step(cc.CC_BATCHED)
+        step(main_mode)
     log(f"warmup done ({args.warmup} steps)")
     torch.cuda.synchronize()
     lat, kern_ms, timings = [], [], []
     t_start = time.perf_counter()
     for i in range(args.steps):
         a = time.perf_counter()
-        step(cc.CC_BATCHED)
+        step(main_mode)
         lat.append((time.perf_counter() - a) * 1e3)
         tm = cc.cc_last_timing(ctx.handle)
         timings.append(tm)
@@ -235,7 +240,14 @@ def main():
     wall = time.perf_counter() - t_start
     ms_per_step = wall * 1e3 / args.steps
     gteps = teps_edges / (ms_per_step / 1e3) / 1e9
-    log(f"batched: {ms_per_step:.3f} ms/step, {gteps:.1f} GTEPS")
+    replayed = sum(1 for t in timings if t["launches"] == 1)
+    log(f"batched{' (graph replays: %d)' % replayed if use_graph else ''}: {ms_per_step:.3f} ms/step, "
+        f"{gteps:.1f} GTEPS")
+    if use_graph:  # replays carry no per-launch timing: take it from eager steps
+        timings = []
+        for i in range(max(3, min(args.steps, 10))):
+            step(cc.CC_BATCHED)
+            timings.append(cc.cc_last_timing(ctx.handle))
 
     # roofline of the dominant kernel (the per-level scatter kernel), timed
     # live with HIP events on the stream it is launched on
@@ -269,7 +281,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64 bitmask / int32 dist / int64 sums",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {g.name} n={g.n} m={m} k={k} batched", "n": g.n, "m": m,
-                   "k": k, "eps": f"1/{int(round(math.sqrt(k)))}"},
+                   "k": k, "eps": f"1/{int(round(math.sqrt(k)))}", "graph_replay": use_graph},
         "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
         "plain": plain,
         "speedup_vs_plain": None if plain is None else round(gteps / plain["gteps"], 2),

@@ -70,6 +70,12 @@ typedef enum {
 /* Traversal mode */
 #define CC_BATCHED 0    /* 64 samples per 64-bit word, all words of a node together */
 #define CC_PLAIN 1      /* one sample at a time (the one-source baseline) */
+#define CC_GRAPH 0x100  /* or-ed into CC_BATCHED: capture the whole estimate as a HIP graph on the first call
+                           and replay it when the same graph, k, eps, output pointers and stream come again
+                           (undirected graphs without arc lengths, k <= 256).  A replay is checked on the host
+                           (the search ended within the captured levels, with the same deepest level) and
+                           otherwise the estimate is recomputed as usual, so results never depend on it.
+                           Samples may change between calls. */
 
 typedef struct cc_context cc_context;
 typedef struct cc_graph cc_graph;

@@ -24,6 +24,7 @@ CC_OK, CC_EINVAL, CC_EDISCONNECTED, CC_ENOMEM, CC_EOVERFLOW = 0, 1, 2, 3, 4
 CC_EDEVICE, CC_EBUSY, CC_ECANCELLED, CC_ENOTREADY = 5, 6, 7, 8
 CC_DIRECTED, CC_VALIDATE = 1, 2
 CC_BATCHED, CC_PLAIN = 0, 1
+CC_GRAPH = 0x100  # or-ed into CC_BATCHED: capture the estimate as a HIP graph and replay it
 
 EXPORTED = [
     "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_release", "cc_graph_info",

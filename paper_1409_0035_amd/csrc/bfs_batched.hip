@@ -200,25 +200,6 @@ __global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_b
     atomicAdd((unsigned long long*)&cnt[i % kCounterSlots].frontier_arcs, (unsigned long long)(out_rp[v + 1] - out_rp[v]));
 }
 
-// Traversal state the level kernels read at entry and k_decide updates after
-// each level, so that a whole batch of levels runs without the host.
-struct BfsCtl {
-    int32_t done;         // 1 once the traversal has ended (status says how)
-    int32_t status;       // 0 every node full, 1 level capacity exhausted, 2 a node no sample reaches
-    int32_t lmax;         // last level at which some node gained a bit
-    int32_t pull;         // direction of the next level: 1 pull, 0 push
-    int32_t levels;       // levels run
-    int32_t pull_levels;  // of which pulls
-    uint32_t ticket;      // blocks of the current merge launch that have finished
-    int32_t pad;
-    int64_t frontier_arcs;  // out-arcs of the nodes that changed at the last level
-    int64_t pull_arcs;      // arcs the last pull scanned (what a pull would cost now)
-    int64_t arcs;           // arcs scanned or pushed along, all levels
-    int64_t hub_arcs;       // of which by the hub-chunk pull
-    int64_t push_arcs;
-    int64_t push_atomics;
-    int64_t nodes;          // node slots of live groups visited
-};
 constexpr int32_t kModeLog = 4096;  // levels whose direction is logged for the host
 
 // One wave (lanes = counter slots): sums and clears the counter slots of the
@@ -660,6 +641,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
 
     const unsigned gb = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((ngroups + kWaves - 1) / kWaves, std::max(1, gv.level_blocks)));
+    const bool enqueue_only = out.enqueue_only > 0;  // for stream capture: no events, reads or waits
     const int32_t g0 = gv.n_push_chunks > 0 ? (int32_t)((gv.nh + 63) / 64) : 0;  // hubs push by chunks
     const int64_t scatter_items = std::max<int64_t>(gv.n_hub_chunks, (int64_t)gv.n_push_chunks + (ngroups - g0));
     const unsigned sb = (unsigned)std::max<int64_t>(
@@ -668,7 +650,8 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     std::vector<int32_t> modes;
     BfsCtl hc{};
     int32_t level = 1;
-    int32_t batch = std::max<int32_t>(out.hint, 4);
+    int32_t batch = enqueue_only ? out.enqueue_only : std::max<int32_t>(out.hint, 4);
+    if (enqueue_only) evp = nullptr;
     for (;;) {
         const int32_t end = (int32_t)std::min<int64_t>((int64_t)level + batch, out.cap);
         if (evp) CCG_HIP(hipEventRecord(evp->at(0), st));
@@ -687,6 +670,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
                                out.cap, gv.arcs, gv.alpha);
         }
         CCG_HIP(hipGetLastError());
+        if (enqueue_only) return 0;
         if (evp) CCG_HIP(hipEventRecord(evp->at(1), st));
         stats->launches += (int64_t)(end - level) * 2;
         stats->kernel_launches += end - level;
@@ -729,6 +713,14 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
 }
 
 }  // namespace
+
+BfsCtl* bfs_batched_ctl(void* scratch, int64_t n, int32_t kg) {
+    const int W = (kg + 63) / 64;
+    const int64_t ngroups = (n + 63) / 64;
+    char* p = (char*)scratch;
+    p += align256(sizeof(uint64_t) * n * W) * 3 + align256(sizeof(int32_t) * n) + align256((size_t)ngroups);
+    return (BfsCtl*)p;
+}
 
 size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh) {
     (void)nh;

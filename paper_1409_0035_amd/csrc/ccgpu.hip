@@ -109,11 +109,13 @@ namespace {
 struct Arena {
     void* ptr = nullptr;
     size_t size = 0;
+    uint64_t* gen = nullptr;  // bumped whenever the buffer moves (captured graphs refer to it)
     ~Arena() {
         if (ptr) (void)hipFree(ptr);
     }
     void* get(size_t need) {
         if (need <= size) return ptr;
+        if (gen) ++*gen;
         if (ptr) {
             CCG_HIP(hipFree(ptr));
             ptr = nullptr;
@@ -154,7 +156,34 @@ struct Lane {
     LevelCounters* cnt_host = nullptr;  // pinned
     hipEvent_t ev[4] = {};
     EventPool events;  // per-launch timing inside the traversals
+    uint64_t gen = 0;  // arena generation
+    // Captured estimates (stream capture of a whole estimate), replayed when
+    // the same graph, parameters, buffers and outputs come again.
+    struct Captured {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+        int32_t lmax = 0, levels = 0;
+    };
+    std::vector<Captured> captured;  // most recently used last
+    static constexpr size_t kMaxCaptured = 8;
+    Captured* find_captured(const std::vector<uint64_t>& key) {
+        for (size_t i = 0; i < captured.size(); i++) {
+            if (captured[i].key == key) {
+                std::rotate(captured.begin() + i, captured.begin() + i + 1, captured.end());
+                return &captured.back();
+            }
+        }
+        return nullptr;
+    }
+    void add_captured(Captured c) {
+        if (captured.size() >= kMaxCaptured) {
+            (void)hipGraphExecDestroy(captured.front().exec);
+            captured.erase(captured.begin());
+        }
+        captured.push_back(std::move(c));
+    }
     void init(hipStream_t s) {
+        arena.gen = arenaD.gen = arena2.gen = &gen;
         if (s) {
             stream = s;
         } else {
@@ -165,6 +194,8 @@ struct Lane {
         for (auto& e : ev) CCG_HIP(hipEventCreate(&e));
     }
     void destroy() {
+        for (auto& c : captured) (void)hipGraphExecDestroy(c.exec);
+        captured.clear();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         if (cnt_host) (void)hipHostFree(cnt_host);
@@ -186,6 +217,7 @@ struct cc_graph {
     void* mem[10] = {};
     size_t bytes = 0;
     std::vector<int32_t> inv;  // caller's id -> internal id
+    uint64_t id = 0;  // never reused: keys captured estimates
     mutable std::atomic<int32_t> bfs_hint{0};  // levels the last batched traversal of this graph ran
     cc_tuning tune{4, 2048, 4096, 1, 1024, 64};  // launch shapes (cc_graph_set_tuning / cc_autotune)
 };
@@ -402,6 +434,8 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
     cc_graph* g = new (std::nothrow) cc_graph();
     if (!g) return fail(CC_ENOMEM, "cc_graph_upload: host allocation");
     g->ctx = ctx;
+    static std::atomic<uint64_t> next_graph_id{1};
+    g->id = next_graph_id.fetch_add(1);
     g->flags = flags;
     g->dg.n = n;
     g->dg.arcs = arcs;
@@ -527,7 +561,8 @@ namespace {
 
 struct Resolved {
     int32_t k = 0;
-    int32_t mode = CC_BATCHED;
+    int32_t mode = CC_BATCHED;  // CC_BATCHED or CC_PLAIN
+    bool graph = false;         // CC_GRAPH requested
     int64_t en = 1, ed = 1;
     std::vector<int32_t> samples;
 };
@@ -536,9 +571,12 @@ cc_status resolve_params(const cc_graph* g, const cc_params* p, Resolved& r) {
     if (!g || !p) return fail(CC_EINVAL, "null graph or params");
     const int64_t n = g->dg.n;
     if (p->k < 1 || p->k > n || p->k > 4096) return fail(CC_EINVAL, "need 1 <= k <= min(n, 4096)");
-    if (p->mode != CC_BATCHED && p->mode != CC_PLAIN) return fail(CC_EINVAL, "mode must be CC_BATCHED or CC_PLAIN");
+    const int32_t base = p->mode & ~CC_GRAPH;
+    if (base != CC_BATCHED && base != CC_PLAIN) return fail(CC_EINVAL, "mode must be CC_BATCHED or CC_PLAIN");
+    if ((p->mode & CC_GRAPH) && base != CC_BATCHED) return fail(CC_EINVAL, "CC_GRAPH applies to CC_BATCHED");
     r.k = p->k;
-    r.mode = p->mode;
+    r.mode = base;
+    r.graph = (p->mode & CC_GRAPH) != 0;
     if (p->eps_num == 0 && p->eps_den == 0) {
         r.en = 1;
         r.ed = std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)p->k)));
@@ -720,6 +758,69 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         void* Dt = need_Dt ? cd.take<char>(dbytes) : nullptr;
 
         CCG_HIP(hipMemcpyAsync(samples_dev, samples_int.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+
+        // the adjacency a batched traversal uses in direction dir (0: forward
+        // distances, pull over in-arcs / push over out-arcs; 1: reverse)
+        auto make_view = [&](int dir) {
+            BfsView gv;
+            gv.n = n;
+            gv.arcs = g.arcs;
+            gv.rp = dir == 0 ? g.rrp : g.rp;
+            gv.col = dir == 0 ? g.rcol : g.col;
+            gv.out_rp = dir == 0 ? g.rp : g.rrp;
+            gv.out_col = dir == 0 ? g.col : g.rcol;
+            gv.nh = g.nh;
+            gv.hub_chunks = dir == 0 ? g.hub_chunks_in : g.hub_chunks_out;
+            gv.n_hub_chunks = dir == 0 ? g.n_hub_chunks_in : g.n_hub_chunks_out;
+            gv.push_chunks = dir == 0 ? g.hub_chunks_out : g.hub_chunks_in;
+            gv.n_push_chunks = dir == 0 ? g.n_hub_chunks_out : g.n_hub_chunks_in;
+            gv.alpha = gr->tune.alpha;
+            gv.level_blocks = gr->tune.level_blocks;
+            gv.scatter_blocks = gr->tune.scatter_blocks;
+            return gv;
+        };
+        // a captured estimate is keyed by everything its launches refer to
+        const bool want_graph = r.graph && bits_path;
+        auto graph_key = [&]() {
+            return std::vector<uint64_t>{gr->id, (uint64_t)k, (uint64_t)r.en, (uint64_t)r.ed, (uint64_t)cap,
+                                         (uint64_t)(uintptr_t)st, L.gen, (uint64_t)(uintptr_t)out->S_hyb,
+                                         (uint64_t)(uintptr_t)out->S_samp, (uint64_t)(uintptr_t)out->S_piv,
+                                         (uint64_t)(uintptr_t)out->S_pub, (uint64_t)(uintptr_t)out->pivot,
+                                         (uint64_t)(uintptr_t)out->delta, (uint64_t)(uintptr_t)out->sampsum,
+                                         (uint64_t)(uintptr_t)out->src_sum, (uint64_t)(uintptr_t)out->dmat,
+                                         (uint64_t)(uintptr_t)out->D, (uint64_t)gr->tune.alpha,
+                                         (uint64_t)gr->tune.level_blocks, (uint64_t)gr->tune.scatter_blocks};
+        };
+        if (want_graph) {
+            if (Lane::Captured* cap_e = L.find_captured(graph_key())) {
+                if (out->samples)
+                    CCG_HIP(hipMemcpyAsync(out->samples, r.samples.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice,
+                                           st));
+                CCG_HIP(hipEventRecord(L.ev[0], st));
+                CCG_HIP(hipGraphLaunch(cap_e->exec, st));
+                CCG_HIP(hipEventRecord(L.ev[2], st));
+                BfsCtl hc;
+                DevFlags hf;
+                CCG_HIP(hipMemcpyAsync(&hc, bfs_batched_ctl(ts, n, kg0), sizeof(hc), hipMemcpyDeviceToHost, st));
+                CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+                CCG_HIP(hipStreamSynchronize(st));
+                if (hc.done && hc.status == 0 && hc.lmax == cap_e->lmax && hc.levels <= cap_e->levels &&
+                    !hf.disconnected && !hf.overflow && !hf.bad_sample && !hf.timeout) {
+                    if (timing) {
+                        *timing = cc_timing{};
+                        timing->total_ms = timing->traverse_ms = elapsed(L.ev[0], L.ev[2]);
+                        timing->levels = hc.levels;
+                        timing->arcs_scanned = hc.arcs;
+                        timing->nodes_visited = hc.nodes;
+                        timing->launches = 1;
+                        timing->pull_levels = hc.pull_levels;
+                    }
+                    return CC_OK;
+                }
+                // the search went deeper (or elsewhere) than the captured one:
+                // recompute as usual, which rewrites every output
+            }
+        }
         fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
         CCG_HIP(hipEventRecord(L.ev[0], st));
         compute_sidx(st, samples_dev, k, sidx, n);
@@ -768,21 +869,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 if (ok) transpose_dist(st, Dt, Dd, n, k, dk);
                 lmax_dir[dir] = (int32_t)ds.maxd;
             } else {
-                BfsView gv;
-                gv.n = n;
-                gv.arcs = g.arcs;
-                gv.rp = in_rp;
-                gv.col = in_col;
-                gv.out_rp = out_rp;
-                gv.out_col = out_col;
-                gv.nh = g.nh;
-                gv.hub_chunks = dir == 0 ? g.hub_chunks_in : g.hub_chunks_out;
-                gv.n_hub_chunks = dir == 0 ? g.n_hub_chunks_in : g.n_hub_chunks_out;
-                gv.push_chunks = dir == 0 ? g.hub_chunks_out : g.hub_chunks_in;
-                gv.n_push_chunks = dir == 0 ? g.n_hub_chunks_out : g.n_hub_chunks_in;
-                gv.alpha = gr->tune.alpha;
-                gv.level_blocks = gr->tune.level_blocks;
-                gv.scatter_blocks = gr->tune.scatter_blocks;
+                const BfsView gv = make_view(dir);
                 for (int32_t s0 = 0; s0 < k && rc == 0; s0 += 256) {
                     const int32_t kg = std::min(256, k - s0);
                     int32_t lm = 0;
@@ -827,8 +914,10 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         if (hf.timeout) return fail(CC_EDEVICE, "traversal wait expired");
 
         // ---- epilogue
+        BitsEpilogueArgs ba;
+        void* ba_scratch = nullptr;
+        size_t ba_es = 0;
         if (bits_path) {
-            BitsEpilogueArgs ba;
             ba.n = n;
             ba.k = k;
             ba.snap = snap;
@@ -853,8 +942,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ba.src_sum = src_sum;
             ba.dmat = dmat;
             ba.Dout = out->D;
-            const size_t es = bits_epilogue_scratch(k, ba.lmax);
-            run_bits_epilogue(st, ba, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
+            ba_es = bits_epilogue_scratch(k, ba.lmax);
+            ba_scratch = ba_es <= trav_scratch ? ts : L.arena2.get(ba_es);
+            run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
         } else {
             EpilogueArgs ea;
             ea.n = n;
@@ -879,7 +969,57 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         CCG_HIP(hipStreamSynchronize(st));
         record_timing(timing, L, stats, bits_path ? 0 : (int)dk);
         if (timing) timing->levels = stats.levels;
-        return finish_flags(hf);
+        const cc_status fs = finish_flags(hf);
+        if (want_graph && fs == CC_OK && stats.bfs_levels > 0) {
+            // capture the same estimate (exactly the levels this search ran,
+            // the epilogue for its deepest level) for replay; nothing runs now
+            Lane::Captured cap_e;
+            cap_e.key = graph_key();
+            cap_e.lmax = ba.lmax;
+            cap_e.levels = stats.bfs_levels;
+            hipGraph_t graph = nullptr;
+            const bool began = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            bool captured_ok = began;
+            if (began) try {
+                fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+                compute_sidx(st, samples_dev, k, sidx, n);
+                fill_u32(st, hist, 0u, hist_elems);
+                int32_t lm = 0;
+                BfsLevels lv;
+                lv.snap = snap;
+                lv.cap = cap;
+                lv.fill_level = fill_level;
+                lv.hist = hist;
+                lv.hlen = cap;
+                lv.lmax = &lm;
+                lv.enqueue_only = stats.bfs_levels;
+                TravStats ignored;
+                (void)bfs_batched(st, make_view(0), samples_dev, k, 0, k, lv, sidx, ts, trav_scratch, cnt, &ignored,
+                                  nullptr);
+                run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
+            } catch (const HipError&) {
+                captured_ok = false;
+            }
+            // a stream that cannot be captured only means no replay later
+            if (began) {
+                const hipError_t ee = hipStreamEndCapture(st, &graph);  // always close a begun capture
+                captured_ok = captured_ok && ee == hipSuccess && graph != nullptr;
+            }
+            hipGraphExec_t exec = nullptr;
+            hipError_t ie = hipErrorUnknown;
+            if (captured_ok) ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (ie == hipSuccess) {
+                if (Lane::Captured* old_e = L.find_captured(cap_e.key)) {  // a deeper search replaced it
+                    (void)hipGraphExecDestroy(old_e->exec);
+                    L.captured.pop_back();
+                }
+                cap_e.exec = exec;
+                L.add_captured(std::move(cap_e));
+            }
+        }
+        return fs;
     }
     return fail(CC_EDEVICE, "traversal did not settle after repeated resizing");
 }
@@ -1181,7 +1321,8 @@ void worker_main(cc_context* ctx, Lane* L) {
         j->t_admit = std::chrono::steady_clock::now();
         Resolved r;
         r.k = j->p.k;
-        r.mode = j->p.mode;
+        r.mode = j->p.mode & ~CC_GRAPH;
+        r.graph = (j->p.mode & CC_GRAPH) != 0;
         r.en = j->p.eps_num;
         r.ed = j->p.eps_den;
         r.samples = j->samples;

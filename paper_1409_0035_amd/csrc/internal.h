@@ -236,6 +236,27 @@ struct BfsView {
     int32_t scatter_blocks = 4096;  // scatter launch grid cap
 };
 
+// Traversal state the batched BFS level kernels read at entry and the last
+// block of each merge launch updates, so that a batch of levels runs without
+// the host.
+struct BfsCtl {
+    int32_t done;         // 1 once the traversal has ended (status says how)
+    int32_t status;       // 0 every node full, 1 level capacity exhausted, 2 a node no sample reaches
+    int32_t lmax;         // last level at which some node gained a bit
+    int32_t pull;         // direction of the next level: 1 pull, 0 push
+    int32_t levels;       // levels run
+    int32_t pull_levels;  // of which pulls
+    uint32_t ticket;      // blocks of the current merge launch that have finished
+    int32_t pad;
+    int64_t frontier_arcs;  // out-arcs of the nodes that changed at the last level
+    int64_t pull_arcs;      // arcs the last pull scanned (what a pull would cost now)
+    int64_t arcs;           // arcs scanned or pushed along, all levels
+    int64_t hub_arcs;       // of which by the hub-chunk pull
+    int64_t push_arcs;
+    int64_t push_atomics;
+    int64_t nodes;          // node slots of live groups visited
+};
+
 // Where the batched BFS records its per-level seen masks.
 struct BfsLevels {
     uint64_t* snap = nullptr;     // [cap][n][W]: snap[L][v] = {i : d(c_i, v) <= L}
@@ -245,6 +266,7 @@ struct BfsLevels {
     int64_t hlen = 0;
     int32_t* lmax = nullptr;      // host: largest level with new bits (max over calls)
     int32_t hint = 0;             // levels the host enqueues before its first check (0 = a few)
+    int32_t enqueue_only = 0;     // > 0: enqueue exactly this many levels and return at once (stream capture)
 };
 
 // ---------------------------------------------------------------- traversal API
@@ -324,6 +346,8 @@ int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, i
                 int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, size_t scratch_size,
                 LevelCounters* cnt_dev, TravStats* stats, EventPool* evp);
 size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh);
+// The control block inside a batched traversal's scratch.
+BfsCtl* bfs_batched_ctl(void* scratch, int64_t n, int32_t kg);
 
 // Distances of one sample group from its level masks into the node-major
 // matrix D (columns src_base .. src_base+kg), in the given width.

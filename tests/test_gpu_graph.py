@@ -1,0 +1,73 @@
+"""Captured estimates (CC_GRAPH): the first call runs eagerly and captures a
+HIP graph; later calls with the same graph, k, eps, outputs and stream
+replay it.  Every replay is checked against an eager estimate of the same
+samples, with the program's own eager GPU work and synchronisations between
+replays, and samples that change from call to call."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import paper_1409_0035_amd as cc
+
+pytestmark = pytest.mark.gpu
+FIELDS = {"S_hyb": "float64", "S_samp": "float64", "S_piv": "int64", "S_pub": "int64", "pivot": "int32",
+          "delta": "int32", "sampsum": "int64"}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _outputs(torch, n):
+    return {f: torch.empty(n, dtype=getattr(torch, dt), device="cuda") for f, dt in FIELDS.items()}
+
+
+@pytest.mark.parametrize("make,k", [(lambda: graphgen.ba(5000, 4, seed=3), 64),
+                                    (lambda: graphgen.rmat(12, 16, seed=5), 200)])
+def test_replays_match_eager(make, k):
+    import torch
+    g = make()
+    with cc.Context(0) as ctx:
+        gh = ctx.upload(g)
+        s = torch.cuda.Stream()
+        cap_out = _outputs(torch, g.n)   # the captured graph writes these
+        ref_out = _outputs(torch, g.n)   # eager estimates to compare with
+        x = torch.randn(256, 256, device="cuda")
+        replays = 0
+        for it, seed in enumerate([1, 1, 1, 2, 2, 1, 3, 3]):
+            _say(f"  {g.name} k={k} call {it} seed {seed}")
+            cc.cc_estimate_device(ctx.handle, gh, k, cap_out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=seed,
+                                  stream=s)
+            t = cc.cc_last_timing(ctx.handle)
+            replays += t["launches"] == 1
+            # the program's own work on the same stream and a sync between calls
+            with torch.cuda.stream(s):
+                y = (x @ x).sum()
+            s.synchronize()
+            assert torch.isfinite(y)
+            cc.cc_estimate_device(ctx.handle, gh, k, ref_out, mode=cc.CC_BATCHED, seed=seed, stream=s)
+            s.synchronize()
+            for f in FIELDS:
+                assert torch.equal(cap_out[f], ref_out[f]), (it, seed, f)
+        _say(f"  replays: {replays}")
+        assert replays >= 4  # the repeated calls after the first of each level count replay
+        ctx.release(gh)
+
+
+def test_host_outputs_accept_graph_flag():
+    """With host outputs the staging buffers differ per call, so each call is
+    eager; the flag must not change results."""
+    g = graphgen.ba(2000, 3, seed=8)
+    with cc.Context(0) as ctx:
+        gh = ctx.upload(g)
+        a = cc.cc_estimate(ctx.handle, gh, 40, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=4)
+        b = cc.cc_estimate(ctx.handle, gh, 40, mode=cc.CC_BATCHED, seed=4)
+        for f in a:
+            assert np.array_equal(a[f], b[f]), f
+        with pytest.raises(cc.CCError) as e:
+            cc.cc_estimate(ctx.handle, gh, 40, mode=cc.CC_PLAIN | cc.CC_GRAPH, seed=4)
+        assert e.value.status == cc.CC_EINVAL
+        ctx.release(gh)
