@@ -57,10 +57,11 @@ def source_digest() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, tuning: dict):
     """HBM bytes per launch of the scatter kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes, each scaled by the same counter on a copy
-    of known size; None once the kernel source has changed since."""
+    of known size; None once the kernel source has changed since, or when
+    the run's launch knobs differ from the profiled ones."""
     path = os.path.join(ROOT, "profiles", f"{SCATTER_KERNEL}_{workload}_pmc.md")
     if not os.path.exists(path):
         return None
@@ -72,29 +73,33 @@ def measured_traffic(workload: str):
                 vals[key.strip()] = val.strip().strip("`")
     if vals.get("bfs_batched.hip sha256[:16]") != source_digest():
         return None
+    prof_tuning = vals.get("tuning", "")
+    bfs_knobs = ("alpha", "level_blocks", "scatter_blocks")
+    if prof_tuning != ",".join(f"{kn}={tuning[kn]}" for kn in bfs_knobs):
+        return None
     try:
         return float(vals["scaled HBM bytes per launch"])
     except (KeyError, ValueError):
         return None
 
 
-def scatter_roofline(timings, W: int, workload: str) -> dict:
+def scatter_roofline(timings, W: int, workload: str, tuning: dict) -> dict:
     """Per-launch algorithmic bytes / average launch duration of the scatter
     kernel (one launch per level), both from the library's own counters and
     HIP events on the launch stream."""
     launches = sum(t["scatter_launches"] for t in timings)
     ms = sum(t["scatter_ms"] for t in timings)
-    arcs = sum(t["scatter_arcs"] for t in timings)
     if launches == 0 or ms <= 0:
         return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
                 "traffic": None, "kernel": SCATTER_KERNEL}
+    arcs = sum(t["scatter_arcs"] for t in timings)
     per_launch = arcs * bytes_per_arc(W) / launches
     avg_ms = ms / launches
     achieved = per_launch / (avg_ms / 1e3) / 1e9
     pull_ms = sum(t["pull_scatter_ms"] for t in timings)
     pull_arcs = sum(t["hub_arcs"] for t in timings)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, tuning),
             "kernel": SCATTER_KERNEL, "algorithmic_bytes_per_launch": int(per_launch),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": launches / len(timings),
             "bytes_per_arc": bytes_per_arc(W),
@@ -176,6 +181,8 @@ def main():
                          "default where it applies; the roofline then comes from extra eager steps)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of running the library's autotuner first")
+    ap.add_argument("--tuning", default="",
+                    help="fixed knobs instead of the autotuner, e.g. alpha=4,level_blocks=2048")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, launch one float32 copy kernel of MIB MiB (read MIB, write MIB) so "
                          "that counter passes can scale FETCH_SIZE / WRITE_SIZE")
@@ -214,7 +221,11 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuning = cc.cc_graph_get_tuning(gh)
-    if not args.no_autotune:
+    if args.tuning:
+        fixed = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.tuning.split(",") if kv}
+        tuning = cc.cc_graph_set_tuning(gh, **fixed)
+        log(f"tuning fixed: {tuning}")
+    elif not args.no_autotune:
         t0 = time.time()
         tuning, tuned_ms = cc.cc_autotune(ctx.handle, gh, k, seed=seed, reps=3)
         log(f"autotune: {tuning} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
@@ -253,7 +264,7 @@ def main():
     # live with HIP events on the stream it is launched on
     tm = timings[-1]
     W = (min(k, 256) + 63) // 64
-    roofline = scatter_roofline(timings, W, args.workload)
+    roofline = scatter_roofline(timings, W, args.workload, tuning)
     level_ms = float(np.median([t["kernel_ms"] for t in timings]))
     log(f"roofline: {roofline}")
 

@@ -192,8 +192,9 @@ cc_status cc_graph_set_tuning(cc_graph* g, const cc_tuning* t);
  * `reps` runs per candidate) while it varies one knob at a time over a fixed
  * candidate list (coordinate descent from the graph's current setting), keeps
  * the fastest setting in the graph and returns it with its time (ms, device
- * time of one estimate).  Uses the context's own stream and device buffers it
- * allocates and frees itself. */
+ * time of one estimate); a candidate replaces the current setting only when it
+ * is at least 3% faster, so that timing noise does not move the setting.  Uses
+ * the context's own stream and device buffers it allocates and frees itself. */
 cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64_t seed, int32_t reps, cc_tuning* best,
                       double* best_ms);
 
