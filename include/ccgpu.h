@@ -146,6 +146,18 @@ cc_status cc_estimate(cc_context* ctx, const cc_graph* g, const cc_params* p, cc
 cc_status cc_estimate_device(cc_context* ctx, const cc_graph* g, const cc_params* p, cc_result* out,
                              void* hip_stream);
 
+/* Several estimates in one call, for many small graphs.  outs[j] holds HOST
+ * pointers for job j (graphs[j], params[j]).  Jobs on undirected graphs
+ * without arc lengths, with k <= 192 and at most 131072 nodes, are traversed
+ * together: their graphs are laid side by side and their samples share the
+ * bit words of one batched search (up to 256 samples, each job in whole
+ * 64-bit words), so one launch per level serves every job of a batch; other
+ * jobs run one by one.  Results are identical to separate calls.  statuses
+ * (may be NULL) receives each job's status; the return value is CC_OK or the
+ * first job error. */
+cc_status cc_estimate_batch(cc_context* ctx, int32_t count, const cc_graph* const* graphs, const cc_params* params,
+                            cc_result* outs, cc_status* statuses);
+
 /* Timing of the last cc_estimate / cc_estimate_device on this context, from
  * HIP events recorded on the stream the kernels ran on (milliseconds), plus
  * the work counters the bench turns into bytes. */
@@ -203,7 +215,9 @@ cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64_t seed, in
 /* Submit a job; `out` holds HOST pointers that must stay valid until the job
  * completes.  Returns CC_OK with a job handle (queued), or CC_EINVAL.  Jobs
  * are admitted onto the device as memory (cc_config.mem_budget_bytes) and
- * slots (max_inflight) free up, and run concurrently on several streams. */
+ * slots (max_inflight) free up, and run concurrently on several streams; a
+ * slot that takes a small job (as in cc_estimate_batch) also takes the small
+ * jobs queued behind it that fit, into one batched traversal. */
 cc_status cc_submit(cc_context* ctx, const cc_graph* g, const cc_params* p, const cc_result* out,
                     cc_job** job);
 /* CC_OK when done successfully, CC_ENOTREADY while queued or running,

@@ -30,7 +30,7 @@ EXPORTED = [
     "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_release", "cc_graph_info",
     "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
     "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
-    "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune",
+    "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune", "cc_estimate_batch",
 ]
 
 
@@ -118,6 +118,8 @@ def load_library():
         "cc_cancel": (i32, [P]),
         "cc_job_times": (i32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "cc_job_release": (None, [P]),
+        "cc_estimate_batch": (i32, [P, i32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(cc_params),
+                                    ctypes.POINTER(cc_result), ctypes.POINTER(i32)]),
         "cc_graph_get_tuning": (i32, [P, ctypes.POINTER(cc_tuning)]),
         "cc_graph_set_tuning": (i32, [P, ctypes.POINTER(cc_tuning)]),
         "cc_autotune": (i32, [P, P, i32, u64, i32, ctypes.POINTER(cc_tuning), ctypes.POINTER(ctypes.c_double)]),
@@ -246,6 +248,45 @@ def cc_estimate(ctx, g, k: int, mode: int = CC_BATCHED, seed: int = 0, samples=N
         arrays["D"] = arrays["D"].reshape(n, k)
     del keep
     return arrays
+
+
+def cc_estimate_batch(ctx, jobs, outputs=("S_hyb", "S_samp", "S_piv", "S_pub", "pivot", "delta", "sampsum")):
+    """Several estimates in one call.  `jobs` is a list of (graph handle, k,
+    seed) or (graph handle, k, seed, eps).  Returns (list of output dicts,
+    list of statuses); a job whose status is not CC_OK has unspecified
+    outputs."""
+    lib = load_library()
+    count = len(jobs)
+    graphs = (ctypes.c_void_p * count)()
+    params = (cc_params * count)()
+    results = (cc_result * count)()
+    statuses = (ctypes.c_int32 * count)()
+    arrays, keep = [], []
+    for j, job in enumerate(jobs):
+        g, k, seed = job[0], int(job[1]), int(job[2])
+        eps = job[3] if len(job) > 3 else None
+        graphs[j] = g.value if isinstance(g, ctypes.c_void_p) else g
+        p, kp = _params(k, CC_BATCHED, seed, None, eps)
+        params[j] = p
+        keep.append(kp)
+        n, _, _ = cc_graph_info(g)
+        sz = _sizes(n, k)
+        arr = {}
+        for f in outputs:
+            dt, which = _FIELD_SPEC[f]
+            arr[f] = np.empty(sz[which], dtype=dt)
+            setattr(results[j], f, arr[f].ctypes.data)
+        arrays.append((arr, n, k))
+    lib.cc_estimate_batch(ctx, count, graphs, params, results, statuses)
+    out = []
+    for arr, n, k in arrays:
+        if "dmat" in arr:
+            arr["dmat"] = arr["dmat"].reshape(k, k)
+        if "D" in arr:
+            arr["D"] = arr["D"].reshape(n, k)
+        out.append(arr)
+    del keep
+    return out, [int(x) for x in statuses]
 
 
 def cc_estimate_device(ctx, g, k: int, out: dict, mode: int = CC_BATCHED, seed: int = 0, samples=None,

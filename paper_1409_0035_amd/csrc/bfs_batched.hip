@@ -168,13 +168,18 @@ __device__ __forceinline__ uint32_t flush_counts(WaveCounts c, LevelCounters* sl
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uint64_t* S0, uint64_t* snap0,
-                                                 uint64_t* NX, int32_t* chg, uint8_t* gfull, int32_t* fill_level) {
+                                                 uint64_t* NX, int32_t* chg, uint8_t* gfull, int32_t* fill_level,
+                                                 const uint64_t* __restrict__ preset,
+                                                 const int32_t* __restrict__ gvalid) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < n) {
+        const int64_t g = t >> 6;
+        const bool pad = preset && (int32_t)(t & 63) >= gvalid[g];
 #pragma unroll
         for (int w = 0; w < W; w++) {
-            S0[t * W + w] = 0;
-            snap0[t * W + w] = 0;
+            const uint64_t s0 = preset ? (pad ? ~0ull : preset[g * W + w]) : 0ull;
+            S0[t * W + w] = s0;
+            snap0[t * W + w] = s0;
             NX[t * W + w] = 0;
         }
         chg[t] = -1;
@@ -193,6 +198,7 @@ __global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_b
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kg) return;
     const int64_t v = samples[src_base + i];
+    if (v < 0) return;  // a bit position no sample uses (batches)
     const unsigned long long bit = 1ull << (i & 63);
     atomicOr((unsigned long long*)&S0[v * W + (i >> 6)], bit);
     atomicOr((unsigned long long*)&snap0[v * W + (i >> 6)], bit);
@@ -300,10 +306,12 @@ __device__ __forceinline__ void push_arc(const uint64_t* __restrict__ Sprev, uin
 // over each changed node's out-arcs.
 template <int W>
 __device__ __forceinline__ void push_group(const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col,
-                                           const int32_t* __restrict__ chg, int64_t n, int32_t g, int32_t prev_level,
+                                           const int32_t* __restrict__ chg, const uint8_t* __restrict__ ghub,
+                                           int64_t n, int32_t g, int32_t prev_level,
                                            const uint64_t* __restrict__ Sprev, uint64_t* NX, WaveCounts& wc,
                                            int64_t& atomics) {
     const int lane = lane_id();
+    if (ghub && ghub[g]) return;  // hubs push by chunks
     const int64_t v = (int64_t)g * 64 + lane;
     uint64_t m = __ballot(v < n && chg[v] == prev_level);
     while (m) {
@@ -391,7 +399,8 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_scatter_level(
     const int32_t* __restrict__ col, const int32_t* __restrict__ hub_chunks, int32_t n_hub_chunks,
     const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col, const int32_t* __restrict__ push_chunks,
-    int32_t n_push_chunks, int32_t g0, int32_t ngroups, const int32_t* __restrict__ chg, int64_t n,
+    int32_t n_push_chunks, int32_t g0, int32_t ngroups, const int32_t* __restrict__ chg,
+    const uint8_t* __restrict__ ghub, int64_t n,
     int32_t prev_level, const uint64_t* __restrict__ Sprev, uint64_t* NX, uint64_t lastmask, LevelCounters* cnt,
     const BfsCtl* __restrict__ ctl) {
     if (ctl->done) return;
@@ -408,8 +417,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_level(
             if (t < n_push_chunks)
                 push_chunk<W>(out_col, push_chunks + 3 * t, chg, prev_level, Sprev, NX, wc, extra);
             else
-                push_group<W>(out_rp, out_col, chg, n, g0 + (int32_t)(t - n_push_chunks), prev_level, Sprev, NX, wc,
-                              extra);
+                push_group<W>(out_rp, out_col, chg, ghub, n, g0 + (int32_t)(t - n_push_chunks), prev_level, Sprev,
+                              NX, wc, extra);
         }
     }
     wc.hub = extra;
@@ -423,7 +432,8 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
     int32_t* __restrict__ fill_level, uint8_t* __restrict__ gfull, int32_t* __restrict__ chg, int32_t ngroups,
     int64_t n, int64_t nh, uint64_t* __restrict__ NX, uint64_t lastmask, int32_t level,
     const int32_t* __restrict__ sidx, int32_t* __restrict__ hist, int64_t hlen, int64_t k, int32_t src_base,
-    LevelCounters* __restrict__ cnt, BfsCtl* ctl, int32_t* mode_log, int32_t cap, int64_t arcs_total, int32_t alpha) {
+    LevelCounters* __restrict__ cnt, BfsCtl* ctl, int32_t* mode_log, int32_t cap, int64_t arcs_total, int32_t alpha,
+    const uint8_t* __restrict__ ghub) {
     if (ctl->done) return;
     const int pull = ctl->pull;
     __shared__ uint64_t lds_acc[kWaves][64][W];
@@ -454,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
         }
         const uint32_t need = pairs_needed<W>(sv, lastmask);
         const bool fullv = need == 0;
-        const bool ishub = v < nh;
+        const bool ishub = ghub ? ghub[g] != 0 : v < nh;
         uint64_t acc[W];
 #pragma unroll
         for (int w = 0; w < W; w++) acc[w] = 0;
@@ -631,7 +641,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     const uint64_t lastmask = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
     const int64_t nmax = std::max<int64_t>(n, ngroups);
     hipLaunchKernelGGL((k_init<W>), dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, ngroups,
-                       S0, out.snap, NX, chg, gfull, out.fill_level);
+                       S0, out.snap, NX, chg, gfull, out.fill_level, gv.preset, gv.gvalid);
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
     hipLaunchKernelGGL((k_init_samples<W>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, src_base, S0,
                        out.snap, chg, gv.out_rp, cnt_dev);
@@ -642,7 +652,8 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     const unsigned gb = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((ngroups + kWaves - 1) / kWaves, std::max(1, gv.level_blocks)));
     const bool enqueue_only = out.enqueue_only > 0;  // for stream capture: no events, reads or waits
-    const int32_t g0 = gv.n_push_chunks > 0 ? (int32_t)((gv.nh + 63) / 64) : 0;  // hubs push by chunks
+    // hubs push by chunks: a prefix of the groups, or the flagged groups of a batch
+    const int32_t g0 = (gv.n_push_chunks > 0 && !gv.ghub) ? (int32_t)((gv.nh + 63) / 64) : 0;
     const int64_t scatter_items = std::max<int64_t>(gv.n_hub_chunks, (int64_t)gv.n_push_chunks + (ngroups - g0));
     const unsigned sb = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((scatter_items + kWaves - 1) / kWaves, std::max(1, gv.scatter_blocks)));
@@ -662,12 +673,12 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
             if (timed) CCG_HIP(hipEventRecord(evp->at(2 + 2 * (size_t)L), st));
             hipLaunchKernelGGL((k_scatter_level<W>), dim3(sb), dim3(kBlock), 0, st, gv.col, gv.hub_chunks,
                                gv.n_hub_chunks, gv.out_rp, gv.out_col, gv.push_chunks, gv.n_push_chunks, g0, ngroups,
-                               chg, n, L - 1, Sp, NX, lastmask, cnt_dev, ctl);
+                               chg, gv.ghub, n, L - 1, Sp, NX, lastmask, cnt_dev, ctl);
             if (timed) CCG_HIP(hipEventRecord(evp->at(3 + 2 * (size_t)L), st));
             hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp, Sc,
                                out.snap + (size_t)L * plane, out.fill_level, gfull, chg, ngroups, n, gv.nh, NX,
                                lastmask, L, sidx, out.hist, out.hlen, (int64_t)k, src_base, cnt_dev, ctl, mode_log,
-                               out.cap, gv.arcs, gv.alpha);
+                               out.cap, gv.arcs, gv.alpha, gv.ghub);
         }
         CCG_HIP(hipGetLastError());
         if (enqueue_only) return 0;

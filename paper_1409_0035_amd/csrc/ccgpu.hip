@@ -218,6 +218,7 @@ struct cc_graph {
     size_t bytes = 0;
     std::vector<int32_t> inv;  // caller's id -> internal id
     uint64_t id = 0;  // never reused: keys captured estimates
+    std::vector<int32_t> chunks_host;  // hub chunk triples (undirected graphs), for batching
     mutable std::atomic<int32_t> bfs_hint{0};  // levels the last batched traversal of this graph ran
     cc_tuning tune{4, 2048, 4096, 1, 1024, 64};  // launch shapes (cc_graph_set_tuning / cc_autotune)
 };
@@ -499,6 +500,7 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
         g->tune.delta = (int32_t)std::min<uint32_t>(std::max<uint32_t>(g->dg.delta, 1u), INT32_MAX);
         std::vector<int32_t> ch_in = hub_chunk_list(prp, nh);
         std::vector<int32_t> ch_out = directed ? hub_chunk_list(rp, nh) : std::vector<int32_t>();
+        if (!directed) g->chunks_host = ch_in;
 
         auto up = [&](int slot, const void* src, size_t bytes) -> void* {
             void* d = nullptr;
@@ -1066,12 +1068,9 @@ extern "C" cc_status cc_estimate_device(cc_context* ctx, const cc_graph* g, cons
 
 namespace {
 
-// Device staging for host outputs: allocate device buffers for the
-// requested fields, run, copy back.
-cc_status estimate_to_host(cc_context* ctx, const cc_graph* g, const Resolved& r, const cc_result* host, Lane& L,
-                           cc_timing* t) {
-    const int64_t n = g->dg.n;
-    const int32_t k = r.k;
+// Device staging for host outputs: device buffers for the requested
+// fields, copied back after the run.
+struct Staging {
     struct F {
         void* h;
         size_t bytes;
@@ -1079,62 +1078,346 @@ cc_status estimate_to_host(cc_context* ctx, const cc_graph* g, const Resolved& r
     };
     std::vector<F> fields;
     cc_result dev{};
-    auto add = [&](void* h, size_t bytes) -> void* {
-        if (!h) return nullptr;
-        fields.push_back({h, bytes, nullptr});
-        return h;
-    };
-    add(host->S_hyb, sizeof(double) * n);
-    add(host->S_samp, sizeof(double) * n);
-    add(host->S_piv, sizeof(int64_t) * n);
-    add(host->S_pub, sizeof(int64_t) * n);
-    add(host->pivot, sizeof(int32_t) * n);
-    add(host->delta, sizeof(int32_t) * n);
-    add(host->sampsum, sizeof(int64_t) * n);
-    add(host->src_sum, sizeof(int64_t) * k);
-    add(host->samples, sizeof(int32_t) * k);
-    add(host->dmat, sizeof(int32_t) * (size_t)k * k);
-    add(host->D, sizeof(int32_t) * (size_t)n * k);
-    size_t total = 0;
-    for (auto& f : fields) total += Carver::sz(f.bytes);
     void* buf = nullptr;
-    if (total) {
-        if (hipMalloc(&buf, total) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CC_ENOMEM, "output staging allocation failed");
-        }
-    }
-    Carver c(buf);
-    for (auto& f : fields) f.d = c.take<char>(f.bytes);
-    auto dptr = [&](void* h) -> void* {
-        for (auto& f : fields)
-            if (f.h == h) return f.d;
-        return nullptr;
-    };
-    dev.S_hyb = (double*)dptr(host->S_hyb);
-    dev.S_samp = (double*)dptr(host->S_samp);
-    dev.S_piv = (int64_t*)dptr(host->S_piv);
-    dev.S_pub = (int64_t*)dptr(host->S_pub);
-    dev.pivot = (int32_t*)dptr(host->pivot);
-    dev.delta = (int32_t*)dptr(host->delta);
-    dev.sampsum = (int64_t*)dptr(host->sampsum);
-    dev.src_sum = (int64_t*)dptr(host->src_sum);
-    dev.samples = (int32_t*)dptr(host->samples);
-    dev.dmat = (int32_t*)dptr(host->dmat);
-    dev.D = (int32_t*)dptr(host->D);
-    cc_status s;
-    try {
-        s = run_job(ctx, g, r, &dev, L, t);
-        if (s == CC_OK) {
-            for (auto& f : fields) CCG_HIP(hipMemcpyAsync(f.h, f.d, f.bytes, hipMemcpyDeviceToHost, L.stream));
-            CCG_HIP(hipStreamSynchronize(L.stream));
-        }
-    } catch (...) {
+    Staging() = default;
+    Staging(const Staging&) = delete;
+    Staging& operator=(const Staging&) = delete;
+    ~Staging() {
         if (buf) (void)hipFree(buf);
-        throw;
     }
-    if (buf) (void)hipFree(buf);
+    cc_status build(const cc_result* host, int64_t n, int32_t k) {
+        auto add = [&](void* h, size_t bytes) {
+            if (h) fields.push_back({h, bytes, nullptr});
+        };
+        add(host->S_hyb, sizeof(double) * n);
+        add(host->S_samp, sizeof(double) * n);
+        add(host->S_piv, sizeof(int64_t) * n);
+        add(host->S_pub, sizeof(int64_t) * n);
+        add(host->pivot, sizeof(int32_t) * n);
+        add(host->delta, sizeof(int32_t) * n);
+        add(host->sampsum, sizeof(int64_t) * n);
+        add(host->src_sum, sizeof(int64_t) * k);
+        add(host->samples, sizeof(int32_t) * k);
+        add(host->dmat, sizeof(int32_t) * (size_t)k * k);
+        add(host->D, sizeof(int32_t) * (size_t)n * k);
+        size_t total = 0;
+        for (auto& f : fields) total += Carver::sz(f.bytes);
+        if (total) {
+            if (hipMalloc(&buf, total) != hipSuccess) {
+                buf = nullptr;
+                (void)hipGetLastError();
+                return fail(CC_ENOMEM, "output staging allocation failed");
+            }
+        }
+        Carver c(buf);
+        for (auto& f : fields) f.d = c.take<char>(f.bytes);
+        auto dptr = [&](void* h) -> void* {
+            for (auto& f : fields)
+                if (f.h == h) return f.d;
+            return nullptr;
+        };
+        dev.S_hyb = (double*)dptr(host->S_hyb);
+        dev.S_samp = (double*)dptr(host->S_samp);
+        dev.S_piv = (int64_t*)dptr(host->S_piv);
+        dev.S_pub = (int64_t*)dptr(host->S_pub);
+        dev.pivot = (int32_t*)dptr(host->pivot);
+        dev.delta = (int32_t*)dptr(host->delta);
+        dev.sampsum = (int64_t*)dptr(host->sampsum);
+        dev.src_sum = (int64_t*)dptr(host->src_sum);
+        dev.samples = (int32_t*)dptr(host->samples);
+        dev.dmat = (int32_t*)dptr(host->dmat);
+        dev.D = (int32_t*)dptr(host->D);
+        return CC_OK;
+    }
+    void copy_back(hipStream_t st) {
+        for (auto& f : fields) CCG_HIP(hipMemcpyAsync(f.h, f.d, f.bytes, hipMemcpyDeviceToHost, st));
+    }
+};
+
+cc_status estimate_to_host(cc_context* ctx, const cc_graph* g, const Resolved& r, const cc_result* host, Lane& L,
+                           cc_timing* t) {
+    Staging sg;
+    cc_status s = sg.build(host, g->dg.n, r.k);
+    if (s != CC_OK) return s;
+    s = run_job(ctx, g, r, &sg.dev, L, t);
+    if (s == CC_OK) {
+        sg.copy_back(L.stream);
+        CCG_HIP(hipStreamSynchronize(L.stream));
+    }
     return s;
+}
+
+// ---------------------------------------------------------------- batches
+// Several small graphs traversed as one: their CSRs are laid side by side
+// (node ranges aligned to 64), each graph's samples take whole 64-bit words
+// of one 256-sample traversal, and every node starts with the other graphs'
+// bits set, so "full" keeps its meaning and the level kernels are unchanged.
+// Each graph's estimator epilogue then reads its rows and words of the shared
+// snapshots.  One launch per level serves every graph of the batch.
+
+constexpr int64_t kBatchNodeLimit = 1 << 17;  // graphs at most this large are batched
+constexpr int32_t kBatchWords = 4;
+
+bool batchable(const cc_graph* g, const Resolved& r) {
+    return !g->dg.directed && !g->dg.weighted && r.mode == CC_BATCHED && r.k <= 192 && g->dg.n <= kBatchNodeLimit &&
+           g->dg.arcs < ((int64_t)1 << 30);
+}
+
+__global__ void k_union_copy(const uint32_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t n, int64_t npad,
+                             int64_t arcs, int64_t node_off, int64_t arc_off, uint32_t* __restrict__ urp,
+                             int32_t* __restrict__ ucol) {
+    const int64_t m = npad > arcs ? npad : arcs;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < npad) urp[node_off + t] = (uint32_t)(arc_off + (t < n ? (int64_t)rp[t] : arcs));
+        if (t < arcs) ucol[arc_off + t] = col[t] + (int32_t)node_off;
+    }
+}
+
+struct BatchItem {
+    const cc_graph* g = nullptr;
+    const Resolved* r = nullptr;
+    const cc_result* out = nullptr;  // device pointers
+    int32_t words = 0, word_off = 0;
+    int64_t node_off = 0, arc_off = 0, npad = 0;
+};
+
+// Assigns word offsets (jobs of two or more words on even words, so 16-byte
+// row loads stay aligned); false if the jobs do not fit in one traversal.
+bool pack_words(std::vector<BatchItem>& items) {
+    std::vector<size_t> order(items.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return items[a].words > items[b].words; });
+    int32_t next = 0;
+    for (size_t i : order) {
+        int32_t w = items[i].words;
+        if (w >= 2 && (next & 1)) next++;
+        if (next + w > kBatchWords) return false;
+        items[i].word_off = next;
+        next += w;
+    }
+    return true;
+}
+
+// Runs a batch into DEVICE outputs.  Any failure of the shared traversal
+// (capacity, disconnection, overflow) is reported as a non-OK status and the
+// caller reruns the jobs one by one, so every job gets its own status.
+cc_status run_batch(cc_context* ctx, std::vector<BatchItem>& items, Lane& L, cc_timing* timing) {
+    hipStream_t st = L.stream;
+    int64_t n_u = 0, arcs_u = 0;
+    for (auto& it : items) {
+        it.words = (it.r->k + 63) / 64;
+        it.node_off = n_u;
+        it.npad = (it.g->dg.n + 63) / 64 * 64;
+        n_u += it.npad;
+        it.arc_off = arcs_u;
+        arcs_u += it.g->dg.arcs;
+    }
+    if (!pack_words(items) || arcs_u >= ((int64_t)1 << 31)) return fail(CC_EINVAL, "batch does not fit");
+    const int32_t ngroups = (int32_t)(n_u / 64);
+    constexpr int W = kBatchWords;
+    // group tables and chunk list, built on the host
+    std::vector<uint8_t> ghub((size_t)ngroups, 0);
+    std::vector<uint64_t> preset((size_t)ngroups * W, 0);
+    std::vector<int32_t> gvalid((size_t)ngroups, 0);
+    std::vector<int32_t> chunks;
+    std::vector<int32_t> samples_u(64 * W, -1);
+    std::vector<int32_t> local;  // each job's samples as its graph's internal ids
+    for (auto& it : items) {
+        const DevGraph& g = it.g->dg;
+        uint64_t jm[W] = {0, 0, 0, 0};
+        for (int32_t i = 0; i < it.r->k; i++) jm[it.word_off + i / 64] |= 1ull << (i % 64);
+        const int32_t g0 = (int32_t)(it.node_off / 64);
+        for (int32_t q = 0; q < (int32_t)(it.npad / 64); q++) {
+            ghub[(size_t)(g0 + q)] = (int64_t)q * 64 < g.nh ? 1 : 0;
+            gvalid[(size_t)(g0 + q)] = (int32_t)std::min<int64_t>(64, std::max<int64_t>(0, g.n - (int64_t)q * 64));
+            for (int w = 0; w < W; w++) preset[(size_t)(g0 + q) * W + w] = ~jm[w];
+        }
+        const std::vector<int32_t>& ch = it.g->chunks_host;
+        for (size_t c = 0; c + 2 < ch.size(); c += 3) {
+            chunks.push_back(ch[c] + (int32_t)it.node_off);
+            chunks.push_back(ch[c + 1] + (int32_t)it.arc_off);
+            chunks.push_back(ch[c + 2] + (int32_t)it.arc_off);
+        }
+        for (int32_t i = 0; i < it.r->k; i++) {
+            const int32_t u = it.g->inv[(size_t)it.r->samples[(size_t)i]];
+            samples_u[(size_t)(64 * it.word_off + i)] = (int32_t)it.node_off + u;
+            local.push_back(u);
+        }
+    }
+    const int32_t n_chunks = (int32_t)(chunks.size() / 3);
+    size_t free_b = 0, total_b = 0;
+    CCG_HIP(hipMemGetInfo(&free_b, &total_b));
+    int32_t cap = 32;
+    for (int attempt = 0; attempt < 4; attempt++) {
+        const size_t trav_scratch = bfs_batched_scratch(n_u, 64 * W, 0);
+        const size_t hist_elems = (size_t)kHistSlotsBatched * 64 * W * cap;
+        size_t small = Carver::sz(sizeof(uint32_t) * (n_u + 1)) + Carver::sz(sizeof(int32_t) * arcs_u) +
+                       Carver::sz(ngroups) + Carver::sz(sizeof(uint64_t) * preset.size()) +
+                       Carver::sz(sizeof(int32_t) * ngroups) * 2 + Carver::sz(sizeof(int32_t) * (chunks.size() + 3)) +
+                       Carver::sz(sizeof(int32_t) * samples_u.size()) + Carver::sz(sizeof(int32_t) * local.size()) +
+                       Carver::sz(sizeof(int32_t) * n_u) + Carver::sz(sizeof(DevFlags)) +
+                       Carver::sz(sizeof(LevelCounters) * kCounterSlots) + Carver::sz(trav_scratch) +
+                       Carver::sz(sizeof(int32_t) * hist_elems);
+        for (auto& it : items)
+            small += Carver::sz(sizeof(int64_t) * it.r->k) + Carver::sz(sizeof(int32_t) * (size_t)it.r->k * it.r->k);
+        const size_t snap_bytes = Carver::sz((size_t)cap * n_u * W * 8);
+        if (snap_bytes > free_b / 3) return fail(CC_ENOMEM, "batch level masks do not fit");
+        Carver c(L.arena.get(small));
+        uint32_t* urp = c.take<uint32_t>(n_u + 1);
+        int32_t* ucol = c.take<int32_t>(arcs_u);
+        uint8_t* d_ghub = c.take<uint8_t>(ngroups);
+        uint64_t* d_preset = c.take<uint64_t>(preset.size());
+        int32_t* d_gvalid = c.take<int32_t>(ngroups);
+        int32_t* fill_level = c.take<int32_t>(ngroups);
+        int32_t* d_chunks = c.take<int32_t>(chunks.size() + 3);
+        int32_t* d_samples = c.take<int32_t>(samples_u.size());
+        int32_t* d_local = c.take<int32_t>(local.size());
+        int32_t* sidx = c.take<int32_t>(n_u);
+        DevFlags* flags = c.take<DevFlags>(1);
+        LevelCounters* cnt = c.take<LevelCounters>(kCounterSlots);
+        void* ts = c.take<char>(trav_scratch);
+        int32_t* hist = c.take<int32_t>(hist_elems);
+        std::vector<int64_t*> src_sums;
+        std::vector<int32_t*> dmats;
+        for (auto& it : items) {
+            src_sums.push_back(it.out->src_sum ? it.out->src_sum : c.take<int64_t>(it.r->k));
+            dmats.push_back(it.out->dmat ? it.out->dmat : c.take<int32_t>((size_t)it.r->k * it.r->k));
+        }
+        Carver cd(L.arenaD.get(snap_bytes + 256));
+        uint64_t* snap = cd.take<uint64_t>((size_t)cap * n_u * W);
+
+        CCG_HIP(hipMemcpyAsync(d_ghub, ghub.data(), ghub.size(), hipMemcpyHostToDevice, st));
+        CCG_HIP(hipMemcpyAsync(d_preset, preset.data(), sizeof(uint64_t) * preset.size(), hipMemcpyHostToDevice, st));
+        CCG_HIP(hipMemcpyAsync(d_gvalid, gvalid.data(), sizeof(int32_t) * gvalid.size(), hipMemcpyHostToDevice, st));
+        if (!chunks.empty())
+            CCG_HIP(hipMemcpyAsync(d_chunks, chunks.data(), sizeof(int32_t) * chunks.size(), hipMemcpyHostToDevice, st));
+        CCG_HIP(hipMemcpyAsync(d_samples, samples_u.data(), sizeof(int32_t) * samples_u.size(), hipMemcpyHostToDevice,
+                               st));
+        CCG_HIP(hipMemcpyAsync(d_local, local.data(), sizeof(int32_t) * local.size(), hipMemcpyHostToDevice, st));
+        CCG_HIP(hipEventRecord(L.ev[0], st));
+        for (auto& it : items) {
+            const DevGraph& g = it.g->dg;
+            const int64_t m = std::max<int64_t>(it.npad, g.arcs);
+            hipLaunchKernelGGL(k_union_copy, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 65536)), dim3(256), 0, st,
+                               g.rp, g.col, g.n, it.npad, g.arcs, it.node_off, it.arc_off, urp, ucol);
+        }
+        fill_u32(st, urp + n_u, (uint32_t)arcs_u, 1);
+        fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+        compute_sidx(st, d_samples, 64 * W, sidx, n_u);
+        fill_u32(st, hist, 0u, hist_elems);
+
+        BfsView gv;
+        gv.n = n_u;
+        gv.arcs = arcs_u;
+        gv.rp = gv.out_rp = urp;
+        gv.col = gv.out_col = ucol;
+        gv.nh = 0;
+        gv.hub_chunks = gv.push_chunks = n_chunks > 0 ? d_chunks : nullptr;
+        gv.n_hub_chunks = gv.n_push_chunks = n_chunks;
+        gv.ghub = d_ghub;
+        gv.preset = d_preset;
+        gv.gvalid = d_gvalid;
+        int32_t lm = 0;
+        BfsLevels lv;
+        lv.snap = snap;
+        lv.cap = cap;
+        lv.fill_level = fill_level;
+        lv.hist = hist;
+        lv.hlen = cap;
+        lv.lmax = &lm;
+        lv.hint = 0;
+        TravStats stats;
+        const int rc = bfs_batched(st, gv, d_samples, 64 * W, 0, 64 * W, lv, sidx, ts, trav_scratch, cnt, &stats,
+                                   &L.events);
+        if (rc == 1) {
+            cap = (int32_t)std::min<int64_t>((int64_t)cap * 4, n_u + 2);
+            continue;
+        }
+        CCG_HIP(hipEventRecord(L.ev[1], st));
+        if (rc != 0) return fail(CC_EDISCONNECTED, "a graph of the batch is not connected");
+        size_t es = 0;
+        for (auto& it : items) es = std::max(es, bits_epilogue_scratch(it.r->k, lm));
+        void* escr = L.arena2.get(es);
+        size_t loff = 0;
+        for (size_t j = 0; j < items.size(); j++) {
+            const BatchItem& it = items[j];
+            const cc_result* out = it.out;
+            BitsEpilogueArgs ba;
+            ba.n = it.g->dg.n;
+            ba.k = it.r->k;
+            ba.snap = snap;
+            ba.plane = (size_t)n_u * W;
+            ba.lmax = lm;
+            ba.fill_level = fill_level;
+            ba.samples = d_local + loff;
+            ba.sidx = sidx;
+            ba.orig = it.g->dg.orig;
+            ba.hist = hist;
+            ba.hist_slots = kHistSlotsBatched;
+            ba.hist_len = cap;
+            ba.eps_num = it.r->en;
+            ba.eps_den = it.r->ed;
+            ba.S_hyb = out->S_hyb;
+            ba.S_samp = out->S_samp;
+            ba.S_piv = out->S_piv;
+            ba.S_pub = out->S_pub;
+            ba.pivot = out->pivot;
+            ba.delta = out->delta;
+            ba.sampsum = out->sampsum;
+            ba.src_sum = src_sums[j];
+            ba.dmat = dmats[j];
+            ba.Dout = out->D;
+            ba.node_off = it.node_off;
+            ba.word_off = it.word_off;
+            ba.row_words = W;
+            ba.bit_base = 64 * it.word_off;
+            ba.hist_rows = 64 * W;
+            run_bits_epilogue(st, ba, escr, es, flags);
+            if (out->samples)
+                CCG_HIP(hipMemcpyAsync(out->samples, it.r->samples.data(), sizeof(int32_t) * it.r->k,
+                                       hipMemcpyHostToDevice, st));
+            loff += (size_t)it.r->k;
+        }
+        CCG_HIP(hipEventRecord(L.ev[2], st));
+        DevFlags hf;
+        CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        record_timing(timing, L, stats, 0);
+        return finish_flags(hf);
+    }
+    return fail(CC_EDEVICE, "batch traversal did not settle");
+}
+
+// A batch with host outputs; on any failure of the shared run every job is
+// rerun alone.  statuses[j] receives each job's result.
+void batch_to_host(cc_context* ctx, const std::vector<const cc_graph*>& graphs, const std::vector<const Resolved*>& rs,
+                   const std::vector<const cc_result*>& hosts, Lane& L, std::vector<cc_status>& statuses) {
+    const size_t nj = graphs.size();
+    statuses.assign(nj, CC_OK);
+    bool ok = nj > 1;
+    std::vector<std::unique_ptr<Staging>> stg;
+    std::vector<BatchItem> items(nj);
+    for (size_t j = 0; j < nj && ok; j++) {
+        stg.push_back(std::make_unique<Staging>());
+        if (stg.back()->build(hosts[j], graphs[j]->dg.n, rs[j]->k) != CC_OK) ok = false;
+        items[j].g = graphs[j];
+        items[j].r = rs[j];
+        items[j].out = &stg.back()->dev;
+    }
+    if (ok) {
+        cc_timing t{};
+        ok = run_batch(ctx, items, L, &t) == CC_OK;
+        if (ok) {
+            for (auto& sgp : stg) sgp->copy_back(L.stream);
+            CCG_HIP(hipStreamSynchronize(L.stream));
+            return;
+        }
+    }
+    stg.clear();
+    for (size_t j = 0; j < nj; j++) {
+        cc_timing t{};
+        statuses[j] = estimate_to_host(ctx, graphs[j], *rs[j], hosts[j], L, &t);
+    }
 }
 
 }  // namespace
@@ -1151,6 +1434,69 @@ extern "C" cc_status cc_estimate(cc_context* ctx, const cc_graph* g, const cc_pa
         if (st == CC_OK) ctx->last = t;
         return st;
     });
+}
+
+extern "C" cc_status cc_estimate_batch(cc_context* ctx, int32_t count, const cc_graph* const* graphs,
+                                       const cc_params* params, cc_result* outs, cc_status* statuses) {
+    if (!ctx || count < 1 || !graphs || !params || !outs) return fail(CC_EINVAL, "cc_estimate_batch: null argument");
+    std::vector<Resolved> rs((size_t)count);
+    std::vector<cc_status> st((size_t)count, CC_OK);
+    for (int32_t j = 0; j < count; j++) {
+        if (!graphs[j]) return fail(CC_EINVAL, "cc_estimate_batch: null graph");
+        const cc_status s = resolve_params(graphs[j], &params[j], rs[(size_t)j]);
+        if (s != CC_OK) return s;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const cc_status overall = guarded(ctx, [&]() -> cc_status {
+        // greedy packing in the given order: batchable jobs fill batches of at
+        // most kBatchWords words; the others run alone
+        std::vector<size_t> open;
+        int32_t open_words = 0;
+        auto flush = [&]() {
+            if (open.empty()) return;
+            std::vector<const cc_graph*> gs;
+            std::vector<const Resolved*> rp;
+            std::vector<const cc_result*> hs;
+            for (size_t j : open) {
+                gs.push_back(graphs[j]);
+                rp.push_back(&rs[j]);
+                hs.push_back(&outs[j]);
+            }
+            std::vector<cc_status> sts;
+            batch_to_host(ctx, gs, rp, hs, ctx->lane, sts);
+            for (size_t q = 0; q < open.size(); q++) st[open[q]] = sts[q];
+            open.clear();
+            open_words = 0;
+        };
+        for (int32_t j = 0; j < count; j++) {
+            const Resolved& r = rs[(size_t)j];
+            if (!batchable(graphs[j], r)) {
+                cc_timing t{};
+                st[(size_t)j] = estimate_to_host(ctx, graphs[j], r, &outs[j], ctx->lane, &t);
+                continue;
+            }
+            const int32_t w = (r.k + 63) / 64;
+            std::vector<BatchItem> trial;
+            for (size_t q : open) {
+                BatchItem it;
+                it.words = (rs[q].k + 63) / 64;
+                trial.push_back(it);
+            }
+            BatchItem me;
+            me.words = w;
+            trial.push_back(me);
+            if (open_words + w > kBatchWords || !pack_words(trial)) flush();
+            open.push_back((size_t)j);
+            open_words += w;
+        }
+        flush();
+        for (int32_t j = 0; j < count; j++)
+            if (st[(size_t)j] != CC_OK) return st[(size_t)j];
+        return CC_OK;
+    });
+    if (statuses)
+        for (int32_t j = 0; j < count; j++) statuses[j] = st[(size_t)j];
+    return overall;
 }
 
 extern "C" cc_status cc_last_timing(const cc_context* ctx, cc_timing* t) {
@@ -1294,8 +1640,18 @@ void finish_job(cc_context* ctx, cc_job* j, cc_status s, const std::string& err)
 
 void worker_main(cc_context* ctx, Lane* L) {
     (void)hipSetDevice(ctx->device);
+    auto resolved_of = [](const cc_job* j) {
+        Resolved r;
+        r.k = j->p.k;
+        r.mode = j->p.mode & ~CC_GRAPH;
+        r.graph = (j->p.mode & CC_GRAPH) != 0;
+        r.en = j->p.eps_num;
+        r.ed = j->p.eps_den;
+        r.samples = j->samples;
+        return r;
+    };
     for (;;) {
-        cc_job* j = nullptr;
+        std::vector<cc_job*> js;
         {
             std::unique_lock<std::mutex> lk(ctx->qmu);
             for (;;) {
@@ -1308,44 +1664,87 @@ void worker_main(cc_context* ctx, Lane* L) {
                     if (ctx->in_use + (int64_t)(*it)->need <= ctx->budget || ctx->inflight == 0) break;
                 }
                 if (it != ctx->queue.end()) {
-                    j = *it;
+                    cc_job* j = *it;
                     ctx->queue.erase(it);
                     ctx->in_use += (int64_t)j->need;
                     ctx->inflight += 1;
+                    js.push_back(j);
+                    // small jobs waiting behind it join the same traversal
+                    const Resolved r0 = resolved_of(j);
+                    if (batchable(j->g, r0)) {
+                        int32_t words = (r0.k + 63) / 64;
+                        for (auto q = ctx->queue.begin(); q != ctx->queue.end() && words < kBatchWords;) {
+                            cc_job* o = *q;
+                            const Resolved ro = resolved_of(o);
+                            const int32_t w = (ro.k + 63) / 64;
+                            bool fits = batchable(o->g, ro) && words + w <= kBatchWords &&
+                                        ctx->in_use + (int64_t)o->need <= ctx->budget;
+                            if (fits) {
+                                std::vector<BatchItem> trial(js.size() + 1);
+                                for (size_t t = 0; t < js.size(); t++) trial[t].words = (js[t]->p.k + 63) / 64;
+                                trial.back().words = w;
+                                fits = pack_words(trial);
+                            }
+                            if (fits) {
+                                q = ctx->queue.erase(q);
+                                ctx->in_use += (int64_t)o->need;
+                                js.push_back(o);
+                                words += w;
+                            } else {
+                                ++q;
+                            }
+                        }
+                    }
                     break;
                 }
                 ctx->qcv.wait(lk);
             }
         }
-        j->state = 1;
-        j->t_admit = std::chrono::steady_clock::now();
-        Resolved r;
-        r.k = j->p.k;
-        r.mode = j->p.mode & ~CC_GRAPH;
-        r.graph = (j->p.mode & CC_GRAPH) != 0;
-        r.en = j->p.eps_num;
-        r.ed = j->p.eps_den;
-        r.samples = j->samples;
-        cc_status s;
-        std::string err;
+        const auto now = std::chrono::steady_clock::now();
+        for (cc_job* j : js) {
+            j->state = 1;
+            j->t_admit = now;
+        }
+        std::vector<Resolved> rs;
+        for (cc_job* j : js) rs.push_back(resolved_of(j));
+        std::vector<cc_status> sts(js.size(), CC_OK);
+        std::vector<std::string> errs(js.size());
         try {
-            cc_timing t{};
-            s = estimate_to_host(ctx, j->g, r, &j->out, *L, &t);
-            if (s != CC_OK) err = g_last_error;
+            if (js.size() == 1) {
+                cc_timing t{};
+                sts[0] = estimate_to_host(ctx, js[0]->g, rs[0], &js[0]->out, *L, &t);
+                if (sts[0] != CC_OK) errs[0] = g_last_error;
+            } else {
+                std::vector<const cc_graph*> gs;
+                std::vector<const Resolved*> rp;
+                std::vector<const cc_result*> hs;
+                for (size_t q = 0; q < js.size(); q++) {
+                    gs.push_back(js[q]->g);
+                    rp.push_back(&rs[q]);
+                    hs.push_back(&js[q]->out);
+                }
+                batch_to_host(ctx, gs, rp, hs, *L, sts);
+                for (size_t q = 0; q < js.size(); q++)
+                    if (sts[q] != CC_OK) errs[q] = g_last_error;
+            }
         } catch (const std::bad_alloc&) {
-            s = CC_ENOMEM;
-            err = "device allocation failed";
+            for (size_t q = 0; q < js.size(); q++) {
+                sts[q] = CC_ENOMEM;
+                errs[q] = "device allocation failed";
+            }
         } catch (const HipError& e) {
-            s = CC_EDEVICE;
-            err = e.where + ": " + hipGetErrorString(e.err);
+            for (size_t q = 0; q < js.size(); q++) {
+                sts[q] = CC_EDEVICE;
+                errs[q] = e.where + ": " + hipGetErrorString(e.err);
+            }
         }
         {
             std::lock_guard<std::mutex> lk(ctx->qmu);
-            ctx->in_use -= (int64_t)j->need;
+            for (cc_job* j : js) ctx->in_use -= (int64_t)j->need;
             ctx->inflight -= 1;
         }
         ctx->qcv.notify_all();
-        finish_job(ctx, j, s, err);
+        for (size_t q = 0; q < js.size(); q++) finish_job(ctx, js[q], sts[q], errs[q]);
     }
 }
 

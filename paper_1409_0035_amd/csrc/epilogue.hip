@@ -124,7 +124,7 @@ __global__ void k_dmat(const DT* __restrict__ D, const DT* __restrict__ Dr, cons
 // One block per sample: sums the histogram copies, reverse inclusive scan
 // into T[i][t] for t = 0..maxd+1 (T[i][maxd+1] = 0), then S(c_i).
 __global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ hist, int32_t nslots, int32_t k,
-                                                   int64_t hlen, int64_t maxd, const int32_t* __restrict__ dmat,
+                                                   int32_t hrows, int64_t hlen, int64_t maxd, const int32_t* __restrict__ dmat,
                                                    int32_t* __restrict__ Tcnt, int64_t* __restrict__ Tsum,
                                                    int64_t* __restrict__ src_sum) {
     __shared__ int64_t wc[kBlock / 64], ws[kBlock / 64];
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ h
         const int64_t d = top - threadIdx.x;
         int64_t c = 0;
         if (d >= 0 && d < hlen)
-            for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * k + i) * hlen + d];
+            for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * hrows + i) * hlen + d];
         int64_t s = c * (d >= 0 ? d : 0);
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ h
 constexpr int64_t kChunk = 4096;
 
 __global__ __launch_bounds__(kBlock) void k_chunk_sums(const int32_t* __restrict__ hist, int32_t nslots, int32_t k,
-                                                       int64_t hlen, int64_t* __restrict__ csum_c,
+                                                       int32_t hrows, int64_t hlen, int64_t* __restrict__ csum_c,
                                                        int64_t* __restrict__ csum_s, int64_t nchunks) {
     __shared__ int64_t wc[kBlock / 64], ws[kBlock / 64];
     const int64_t c = blockIdx.x;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(const int32_t* __restrict
     int64_t cc = 0, cs = 0;
     for (int64_t d = c * kChunk + threadIdx.x; d < (c + 1) * kChunk && d < hlen; d += kBlock) {
         int64_t h = 0;
-        for (int32_t s = 0; s < nslots; s++) h += hist[((int64_t)s * k + i) * hlen + d];
+        for (int32_t s = 0; s < nslots; s++) h += hist[((int64_t)s * hrows + i) * hlen + d];
         cc += h;
         cs += h * d;
     }
@@ -237,7 +237,7 @@ __global__ void k_chunk_carry(int64_t* csum_c, int64_t* csum_s, int32_t k, int64
 }
 
 __global__ __launch_bounds__(kBlock) void k_chunk_suffix(const int32_t* __restrict__ hist, int32_t nslots, int32_t k,
-                                                         int64_t hlen, int64_t maxd, const int64_t* __restrict__ carry_c,
+                                                         int32_t hrows, int64_t hlen, int64_t maxd, const int64_t* __restrict__ carry_c,
                                                          const int64_t* __restrict__ carry_s, int64_t nchunks,
                                                          int32_t* __restrict__ Tcnt, int64_t* __restrict__ Tsum) {
     __shared__ int64_t wc[kBlock / 64], ws[kBlock / 64];
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_suffix(const int32_t* __restri
         const int64_t d = top - threadIdx.x;
         int64_t c = 0;
         if (d >= lo && d < hlen)
-            for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * k + i) * hlen + d];
+            for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * hrows + i) * hlen + d];
         int64_t sm = c * (d >= 0 ? d : 0);
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -393,7 +393,7 @@ __global__ void k_to_i32(const DT* __restrict__ D, const DT* __restrict__ Dr, co
 
 __global__ void k_sidx(const int32_t* __restrict__ samples, int32_t k, int32_t* __restrict__ sidx) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k) sidx[samples[i]] = i;
+    if (i < k && samples[i] >= 0) sidx[samples[i]] = i;  // negative: a bit position no sample uses
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
@@ -444,7 +444,7 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
     const int64_t kk = (int64_t)k * k;
     hipLaunchKernelGGL((k_dmat<DT, RT, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, (const DT*)a.D,
                        (const DT*)a.Dr, a.samples, k, a.dmat, dmat_c, flags);
-    run_suffix(st, hist, nslots, k, hlen, maxd, a.dmat, Tcnt, Tsum, a.src_sum, chunks);
+    run_suffix(st, hist, nslots, k, k, hlen, maxd, a.dmat, Tcnt, Tsum, a.src_sum, chunks);
     hipLaunchKernelGGL((k_estimate<DT, RT, MT>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, (const DT*)a.D,
                        (const DT*)a.Dr, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,
                        a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
@@ -476,19 +476,23 @@ void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* si
     hipLaunchKernelGGL(k_sidx, dim3((k + 255) / 256), dim3(256), 0, st, samples, k, sidx);
 }
 
-void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int64_t hlen, int64_t maxd,
+void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int32_t hist_rows, int64_t hlen,
+                int64_t maxd,
                 const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum, int64_t* chunk_scratch) {
     const int64_t nchunks = (maxd + 1 + kChunk - 1) / kChunk;
     if (nchunks <= 1 || chunk_scratch == nullptr) {
-        hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd, dmat, Tcnt, Tsum,
+        hipLaunchKernelGGL(k_suffix, dim3(k), dim3(kBlock), 0, st, hist, nslots, k, hist_rows, hlen, maxd, dmat, Tcnt,
+                           Tsum,
                            src_sum);
     } else {
         int64_t* cc = chunk_scratch;
         int64_t* cs = chunk_scratch + (int64_t)k * nchunks;
-        hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)nchunks, k), dim3(kBlock), 0, st, hist, nslots, k, hlen, cc, cs,
+        hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)nchunks, k), dim3(kBlock), 0, st, hist, nslots, k, hist_rows,
+                           hlen, cc, cs,
                            nchunks);
         hipLaunchKernelGGL(k_chunk_carry, dim3((k + 63) / 64), dim3(64), 0, st, cc, cs, k, nchunks);
-        hipLaunchKernelGGL(k_chunk_suffix, dim3((unsigned)nchunks, k), dim3(kBlock), 0, st, hist, nslots, k, hlen, maxd,
+        hipLaunchKernelGGL(k_chunk_suffix, dim3((unsigned)nchunks, k), dim3(kBlock), 0, st, hist, nslots, k, hist_rows,
+                           hlen, maxd,
                            cc, cs, nchunks, Tcnt, Tsum);
         hipLaunchKernelGGL(k_src_sum, dim3(k), dim3(64), 0, st, Tsum, maxd + 2, dmat, k, src_sum);
     }

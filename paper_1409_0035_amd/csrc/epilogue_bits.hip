@@ -23,11 +23,29 @@ __device__ __forceinline__ uint64_t full_word(int w, uint64_t lastmask) {
     return w == W - 1 ? lastmask : ~0ull;
 }
 
+// One graph's part of the snapshot rows: the rows of nodes noff.. and, in
+// each row of rs words, the W words from wo on (a single graph: noff = 0,
+// wo = 0, rs = W; a batch of graphs shares one set of rows).
+struct SnapView {
+    const uint64_t* snap;
+    size_t plane;  // words per level
+    int32_t rs;    // words per row
+    int32_t wo;    // first word of this graph's samples
+    int64_t noff;  // first row of this graph's nodes
+    const int32_t* fill_level;  // per 64 rows: last level written
+    __device__ __forceinline__ const uint64_t* row(int32_t L, int64_t v) const {
+        return snap + (size_t)L * plane + (size_t)(noff + v) * rs + wo;
+    }
+    __device__ __forceinline__ int32_t fill(int64_t v) const { return fill_level[(noff + v) >> 6]; }
+};
+
+// Mask of node v at level L: this graph's words, the last one cut to its
+// samples (a batch keeps other graphs' bits set in every row).
 template <int W>
-__device__ __forceinline__ void mask_at(const uint64_t* __restrict__ snap, size_t plane, int32_t L, int32_t fl,
-                                        int64_t v, uint64_t lastmask, uint64_t s[W]) {
+__device__ __forceinline__ void mask_at(const SnapView& sv, int32_t L, int32_t fl, int64_t v, uint64_t lastmask,
+                                        uint64_t s[W]) {
     if (L <= fl) {
-        const uint64_t* row = snap + (size_t)L * plane + v * W;
+        const uint64_t* row = sv.row(L, v);
 #pragma unroll
         for (int p = 0; p < (W + 1) / 2; p++) {
             if (2 * p + 1 < W) {
@@ -38,6 +56,7 @@ __device__ __forceinline__ void mask_at(const uint64_t* __restrict__ snap, size_
                 s[2 * p] = row[2 * p];
             }
         }
+        s[W - 1] &= lastmask;
     } else {
 #pragma unroll
         for (int w = 0; w < W; w++) s[w] = full_word<W>(w, lastmask);
@@ -46,25 +65,23 @@ __device__ __forceinline__ void mask_at(const uint64_t* __restrict__ snap, size_
 
 // first level at which bit i is in the mask of node v
 template <int W>
-__device__ __forceinline__ int32_t level_of(const uint64_t* __restrict__ snap, size_t plane, int32_t lmax,
-                                            int32_t fl, int64_t v, int32_t i) {
+__device__ __forceinline__ int32_t level_of(const SnapView& sv, int32_t lmax, int32_t fl, int64_t v, int32_t i) {
     for (int32_t L = 0; L <= lmax; L++) {
         if (L > fl) return L;
-        const uint64_t x = snap[(size_t)L * plane + v * W + (i >> 6)];
+        const uint64_t x = sv.row(L, v)[i >> 6];
         if ((x >> (i & 63)) & 1ull) return L;
     }
     return -1;  // never reached
 }
 
 template <int W, typename MT>
-__global__ void k_dmat_bits(const uint64_t* __restrict__ snap, size_t plane, int32_t lmax,
-                            const int32_t* __restrict__ fill_level, const int32_t* __restrict__ samples, int32_t k,
+__global__ void k_dmat_bits(SnapView sv, int32_t lmax, const int32_t* __restrict__ samples, int32_t k,
                             int32_t* __restrict__ dmat, MT* __restrict__ dmat_c, DevFlags* flags) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)k * k) return;
     const int32_t i = (int32_t)(t / k), j = (int32_t)(t % k);
     const int64_t cj = samples[j];
-    const int32_t d = level_of<W>(snap, plane, lmax, fill_level[cj >> 6], cj, i);
+    const int32_t d = level_of<W>(sv, lmax, sv.fill(cj), cj, i);
     if (d < 0) flags->disconnected = 1;
     dmat[t] = d;
     dmat_c[t] = (MT)(d < 0 ? 0 : d);
@@ -88,20 +105,20 @@ __global__ void k_lmask(const MT* __restrict__ dmat_c, int32_t k, int32_t lmax, 
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_estimate_bits(
-    const uint64_t* __restrict__ snap, size_t plane, int32_t lmax, const int32_t* __restrict__ fill_level, int64_t n,
-    int32_t k, uint64_t lastmask, const int32_t* __restrict__ sidx, const int32_t* __restrict__ orig,
+    SnapView sv, int32_t lmax, int64_t n, int32_t k, uint64_t lastmask, const int32_t* __restrict__ sidx,
+    int32_t bit_base, const int32_t* __restrict__ orig,
     const uint64_t* __restrict__ lmask, const int32_t* __restrict__ Tcnt, const int64_t* __restrict__ Tsum,
     int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed, double* S_hyb, double* S_samp,
     int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out, int64_t* sampsum_out, DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     bool any_ovf = false, any_unreached = false;
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
-        const int32_t fl = fill_level[v >> 6];
+        const int32_t fl = sv.fill(v);
         int32_t delta = -1, p = 0, last = 0;
         int64_t sum = 0;
         for (int32_t L = 0; L <= lmax; L++) {
             uint64_t s[W];
-            mask_at<W>(snap, plane, L, fl, v, lastmask, s);
+            mask_at<W>(sv, L, fl, v, lastmask, s);
             int32_t c = 0;
 #pragma unroll
             for (int w = 0; w < W; w++) c += __popcll(s[w]);
@@ -115,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
             last = c;
         }
         const bool unreached = last != k;
-        const int32_t j = sidx[v];
+        const int32_t j = sidx[sv.noff + v] >= 0 ? sidx[sv.noff + v] - bit_base : -1;
         double hyb, samp;
         int64_t piv, pub;
         bool ovf = false;
@@ -139,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
             int64_t lcsum = 0;
             for (int32_t L = 0; L < lmax; L++) {
                 uint64_t s[W];
-                mask_at<W>(snap, plane, L, fl, v, lastmask, s);
+                mask_at<W>(sv, L, fl, v, lastmask, s);
 #pragma unroll
                 for (int w = 0; w < W; w++) lcsum += __popcll(lm[w] & ~s[w]);
             }
@@ -179,15 +196,14 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
 // Distances from the masks: thread per (node, sample).  out_internal (DT,
 // node-major, columns src_base..) or out_i32 at the caller's node ids.
 template <int W, typename DT>
-__global__ void k_materialize(const uint64_t* __restrict__ snap, size_t plane, int32_t lmax,
-                              const int32_t* __restrict__ fill_level, int64_t n, int32_t kg, int32_t src_base,
-                              int32_t k, DT* __restrict__ out_internal, const int32_t* __restrict__ orig,
+__global__ void k_materialize(SnapView sv, int32_t lmax, int64_t n, int32_t kg, int32_t src_base, int32_t k,
+                              DT* __restrict__ out_internal, const int32_t* __restrict__ orig,
                               int32_t* __restrict__ out_i32, DevFlags* flags) {
     const int64_t count = n * kg;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = t / kg;
         const int32_t i = (int32_t)(t % kg);
-        const int32_t d = level_of<W>(snap, plane, lmax, fill_level[v >> 6], v, i);
+        const int32_t d = level_of<W>(sv, lmax, sv.fill(v), v, i);
         if (d < 0) flags->disconnected = 1;
         if (out_internal) out_internal[v * k + src_base + i] = (DT)(d < 0 ? DistT<DT>::never : (uint32_t)d);
         if (out_i32) out_i32[(int64_t)orig[v] * k + src_base + i] = d;
@@ -208,9 +224,8 @@ __device__ __forceinline__ uint64_t spread8(uint32_t b) {
 // caller's node ids; 16-byte stores when the row offsets allow.
 template <int W, typename OT>
 __global__ __launch_bounds__(kBlock) void k_materialize_words(
-    const uint64_t* __restrict__ snap, size_t plane, int32_t lmax, const int32_t* __restrict__ fill_level,
-    int64_t n, int32_t kg, int32_t src_base, int32_t k, OT* __restrict__ out, const int32_t* __restrict__ orig,
-    int vec, DevFlags* flags) {
+    SnapView sv, int32_t lmax, int64_t n, int32_t kg, int32_t src_base, int32_t k, OT* __restrict__ out,
+    const int32_t* __restrict__ orig, int vec, DevFlags* flags) {
     const int64_t count = n * W;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = t / W;
@@ -218,13 +233,13 @@ __global__ __launch_bounds__(kBlock) void k_materialize_words(
         const int nb = min(64, kg - w * 64);  // samples in this word
         if (nb <= 0) continue;
         const uint64_t valid = nb >= 64 ? ~0ull : ((1ull << nb) - 1);
-        const int32_t last = min(fill_level[v >> 6], lmax);
+        const int32_t last = min(sv.fill(v), lmax);
         uint64_t acc[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) acc[q] = 0;
         uint64_t miss = valid;
         for (int32_t L = 0; L <= last; L++) {
-            miss = ~snap[(size_t)L * plane + v * W + w] & valid;
+            miss = ~sv.row(L, v)[w] & valid;
             if (!miss) break;
 #pragma unroll
             for (int q = 0; q < 8; q++) acc[q] += spread8((uint32_t)(miss >> (8 * q)) & 0xFFu);
@@ -282,23 +297,25 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
     p += align256(sizeof(MT) * (size_t)k * k);
     uint64_t* lmask = (uint64_t*)p;
 
+    const SnapView sv{a.snap, a.plane, a.row_words > 0 ? a.row_words : W, a.word_off, a.node_off, a.fill_level};
+    const int32_t hrows = a.hist_rows > 0 ? a.hist_rows : k;
     const int64_t kk = (int64_t)k * k;
-    hipLaunchKernelGGL((k_dmat_bits<W, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, a.snap, a.plane,
-                       lmax, a.fill_level, a.samples, k, a.dmat, dmat_c, flags);
-    run_suffix(st, a.hist, a.hist_slots, k, a.hist_len, lmax, a.dmat, Tcnt, Tsum, a.src_sum, nullptr);
+    hipLaunchKernelGGL((k_dmat_bits<W, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, sv, lmax, a.samples,
+                       k, a.dmat, dmat_c, flags);
+    run_suffix(st, a.hist + (int64_t)a.bit_base * a.hist_len, a.hist_slots, k, hrows, a.hist_len, lmax, a.dmat, Tcnt,
+               Tsum, a.src_sum, nullptr);
     hipLaunchKernelGGL((k_lmask<W, MT>), dim3(k), dim3(64), 0, st, dmat_c, k, lmax, lmask);
-    hipLaunchKernelGGL((k_estimate_bits<W>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, a.snap, a.plane, lmax,
-                       a.fill_level, n, k, lastmask, a.sidx, a.orig, lmask, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,
-                       a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
+    hipLaunchKernelGGL((k_estimate_bits<W>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, sv, lmax, n, k, lastmask,
+                       a.sidx, a.bit_base, a.orig, lmask, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb,
+                       a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
     CCG_HIP(hipGetLastError());
     if (a.Dout) {
         if (lmax < 255) {
             hipLaunchKernelGGL((k_materialize_words<W, int32_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
-                               a.snap, a.plane, lmax, a.fill_level, n, k, 0, k, a.Dout, a.orig, (int)(k % 4 == 0),
-                               flags);
+                               sv, lmax, n, k, 0, k, a.Dout, a.orig, (int)(k % 4 == 0), flags);
         } else {
-            hipLaunchKernelGGL((k_materialize<W, uint8_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, a.snap,
-                               a.plane, lmax, a.fill_level, n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
+            hipLaunchKernelGGL((k_materialize<W, uint8_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, sv, lmax,
+                               n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
         }
     }
 }
@@ -313,17 +330,17 @@ void bits_mt(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags*
 template <int W, typename DT>
 void materialize_t(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
                    int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DevFlags* flags) {
+    const SnapView sv{snap, plane, W, 0, 0, fill_level};
     if constexpr (sizeof(DT) == 1) {
         if (lmax < 255) {
             const int vec = (k % 16 == 0) && (src_base % 16 == 0);
             hipLaunchKernelGGL((k_materialize_words<W, uint8_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
-                               snap, plane, lmax, fill_level, n, kg, src_base, k, (uint8_t*)D,
-                               (const int32_t*)nullptr, vec, flags);
+                               sv, lmax, n, kg, src_base, k, (uint8_t*)D, (const int32_t*)nullptr, vec, flags);
             return;
         }
     }
-    hipLaunchKernelGGL((k_materialize<W, DT>), dim3(grid_for(n * kg, 65536)), dim3(256), 0, st, snap, plane, lmax,
-                       fill_level, n, kg, src_base, k, (DT*)D, (const int32_t*)nullptr, (int32_t*)nullptr, flags);
+    hipLaunchKernelGGL((k_materialize<W, DT>), dim3(grid_for(n * kg, 65536)), dim3(256), 0, st, sv, lmax, n, kg,
+                       src_base, k, (DT*)D, (const int32_t*)nullptr, (int32_t*)nullptr, flags);
 }
 
 template <int W>

@@ -231,6 +231,14 @@ struct BfsView {
     int32_t n_hub_chunks = 0;
     const int32_t* push_chunks = nullptr;  // the same over out_rp/out_col
     int32_t n_push_chunks = 0;
+    // Several graphs in one traversal (a batch): node ranges aligned to 64, so
+    // hub nodes are whole groups flagged here instead of a prefix of the ids,
+    // and every node starts with the bits of the other graphs' samples set
+    // (preset[g*W..], for the first gvalid[g] nodes of group g; the rest of a
+    // group are padding and start full).  All three null for one graph.
+    const uint8_t* ghub = nullptr;
+    const uint64_t* preset = nullptr;
+    const int32_t* gvalid = nullptr;
     int32_t alpha = 4;  // a level pushes iff its frontier's out-arcs * alpha < what the last pull scanned
     int32_t level_blocks = 2048;    // merge launch grid cap
     int32_t scatter_blocks = 4096;  // scatter launch grid cap
@@ -414,7 +422,8 @@ void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t s
 void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* sidx, int64_t n);
 
 // Tail tables and exact sample sums from a histogram with `nslots` copies.
-void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int64_t hlen, int64_t maxd,
+void run_suffix(hipStream_t st, const int32_t* hist, int32_t nslots, int32_t k, int32_t hist_rows, int64_t hlen,
+                int64_t maxd,
                 const int32_t* dmat, int32_t* Tcnt, int64_t* Tsum, int64_t* src_sum, int64_t* chunk_scratch);
 size_t suffix_chunk_scratch(int32_t k, int64_t maxd);
 
@@ -443,6 +452,12 @@ struct BitsEpilogueArgs {
     int64_t* src_sum = nullptr;  // required
     int32_t* dmat = nullptr;     // required
     int32_t* Dout = nullptr;     // optional int32 distances, caller's node order
+    // this graph's part of a batch's shared rows (defaults: the whole rows)
+    int64_t node_off = 0;   // first row of this graph's nodes
+    int32_t word_off = 0;   // first word of its samples in a row
+    int32_t row_words = 0;  // words per row (0: the graph's own W)
+    int32_t bit_base = 0;   // its first sample's index in sidx and in the histogram rows
+    int32_t hist_rows = 0;  // histogram rows per slot (0: k)
 };
 size_t bits_epilogue_scratch(int32_t k, int32_t lmax);
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
