@@ -11,6 +11,9 @@ What it computes (Cohen, Delling, Pajor & Werneck 2014):
   * the pivot c(v) and Delta(v) (Sec. 2), the sample average Eq. (5), the
     pivot estimate, the pivoting upper bound (Sec. 1), and the hybrid
     estimate Eq. (6), by an explicit walk over all nodes per estimated node;
+  * the estimated squared error of the hybrid estimate (Sec. 4.1) and the
+    adaptive estimate that picks, per node, the eps of a list with the
+    smallest estimated error (Sec. 4, eps list of Sec. 8);
   * exact S(v) for every node (Eq. (1)) by one search per node.
 
 Pins (closed forms, special cases, worked examples, brute force) live in
@@ -50,7 +53,8 @@ class NodeOut(ctypes.Structure):
                 ("S_hyb", ctypes.c_double), ("L_num", ctypes.c_int64), ("LC_num", ctypes.c_int64),
                 ("HC_num", ctypes.c_int64), ("H_num", ctypes.c_int64), ("LC_sum", ctypes.c_int64),
                 ("HC_sum", ctypes.c_int64), ("H_sum", ctypes.c_int64), ("N", ctypes.c_int64),
-                ("overflow", ctypes.c_int32), ("sampled", ctypes.c_int32)]
+                ("overflow", ctypes.c_int32), ("sampled", ctypes.c_int32), ("LC_sumsq", ctypes.c_int64),
+                ("HC_sqerr", ctypes.c_int64), ("S_err", ctypes.c_double)]
 
 
 def _load():
@@ -73,7 +77,10 @@ def _load():
     lib.orc_node_estimates.restype = ctypes.c_int
     lib.orc_node_estimates.argtypes = [i64, i32, i64, P, P, P, i64, i64, i64, ctypes.POINTER(NodeOut)]
     lib.orc_estimate_all.restype = ctypes.c_int
-    lib.orc_estimate_all.argtypes = [i64, i32, P, P, i64, i64, i32, P, P, P, P, P, P, P]
+    lib.orc_estimate_all.argtypes = [i64, i32, P, P, i64, i64, i32, P, P, P, P, P, P, P, P, P, P, i32, P, P]
+    lib.orc_node_adaptive.restype = ctypes.c_int
+    lib.orc_node_adaptive.argtypes = [i64, i32, i64, P, P, P, i64, P, P, i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
     lib.orc_exact_sums.restype = ctypes.c_int
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
     _lib = lib
@@ -142,7 +149,13 @@ def sample_index(n: int, samples) -> np.ndarray:
     return sidx
 
 
-def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=None) -> dict:
+# The eps values the experiments of Sec. 8 choose from per node for the
+# adaptive hybrid estimate, as exact fractions.
+ADAPTIVE_EPS = ((1, 1000), (1, 40), (1, 20), (1, 10), (1, 5), (1, 2), (99, 100))
+
+
+def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=None,
+                 adaptive_eps=ADAPTIVE_EPS) -> dict:
     """Every estimator for every node (O(n^2) hybrid walk: small graphs only).
     Also returns D, the per-sample sums S(c_i) and the sample distance matrix
     dmat[i, j] = d(c_i, c_j)."""
@@ -157,10 +170,18 @@ def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=N
     sidx = sample_index(n, samples)
     out = dict(pivot=np.empty(n, np.int32), delta=np.empty(n, np.int64), sampsum=np.empty(n, np.int64),
                S_piv=np.empty(n, np.int64), S_pub=np.empty(n, np.int64), S_samp=np.empty(n, np.float64),
-               S_hyb=np.empty(n, np.float64))
+               S_hyb=np.empty(n, np.float64), S_err=np.empty(n, np.float64), S_ad=np.empty(n, np.float64),
+               S_ad_err=np.empty(n, np.float64))
+    ad = list(adaptive_eps or ())
+    ad_n = np.array([a for a, _ in ad] or [1], dtype=np.int64)
+    ad_d = np.array([b for _, b in ad] or [1], dtype=np.int64)
     st = lib.orc_estimate_all(n, k, _p(sidx), _p(D), int(en), int(ed), int(threads),
                               _p(out["pivot"]), _p(out["delta"]), _p(out["sampsum"]), _p(out["S_piv"]),
-                              _p(out["S_pub"]), _p(out["S_samp"]), _p(out["S_hyb"]))
+                              _p(out["S_pub"]), _p(out["S_samp"]), _p(out["S_hyb"]), _p(out["S_err"]),
+                              _p(ad_n), _p(ad_d), len(ad), _p(out["S_ad"]) if ad else None,
+                              _p(out["S_ad_err"]) if ad else None)
+    if not ad:
+        del out["S_ad"], out["S_ad_err"]
     if st != 0:
         raise OracleError(f"orc_estimate_all failed ({st})")
     out["D"] = D
@@ -197,6 +218,27 @@ def node_estimates(g, samples, v: int, eps=None, reverse_graph=None, row=None) -
     if st not in (0, 4):
         raise OracleError(f"orc_node_estimates failed ({st})")
     return o
+
+
+def node_adaptive(g, samples, v: int, adaptive_eps=ADAPTIVE_EPS, reverse_graph=None):
+    """The adaptive hybrid estimate of one node (Sec. 4 / Sec. 8): the eps of
+    the list whose estimate has the smallest estimated squared error.
+    Returns (S_ad, S_ad_err, index of the chosen eps)."""
+    lib = _load()
+    samples = np.ascontiguousarray(samples, dtype=np.int32)
+    k = int(samples.shape[0])
+    row = np.ascontiguousarray(sssp(g, v, reverse_graph)[samples], dtype=np.int64)
+    p = int(lib.orc_pivot(k, _p(row)))
+    colp = sssp(g, int(samples[p]), reverse_graph)
+    sidx = sample_index(g.n, samples)
+    ad_n = np.array([a for a, _ in adaptive_eps], dtype=np.int64)
+    ad_d = np.array([b for _, b in adaptive_eps], dtype=np.int64)
+    a, e, w = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    st = lib.orc_node_adaptive(g.n, k, int(v), _p(sidx), _p(row), _p(colp), 1, _p(ad_n), _p(ad_d),
+                               len(adaptive_eps), ctypes.byref(a), ctypes.byref(e), ctypes.byref(w))
+    if st not in (0, 4):
+        raise OracleError(f"orc_node_adaptive failed ({st})")
+    return a.value, e.value, w.value
 
 
 def exact_sums(g, threads: int = 1, reverse_graph=None) -> np.ndarray:

@@ -23,6 +23,11 @@
  *                               hybrid estimate Eq. (6) by an explicit walk
  *                               over every node u of V \ {v} that places u in
  *                               L(v), HC(v) or H(v).
+ *                               It also gives the estimated squared error of
+ *                               the hybrid estimate (Sec. 4.1).
+ *   orc_node_adaptive           the adaptive choice of Sec. 4 / Sec. 8: the
+ *                               hybrid estimate for each eps of a list, the
+ *                               one with the smallest estimated error kept.
  *   orc_estimate_all            the above for every node, O(n^2): small graphs.
  *   orc_exact_sums              S(v) for every node by n searches (Eq. (1)).
  *
@@ -230,6 +235,10 @@ typedef struct {
     int64_t N;          /* numerator of S_hyb = N / LC_num */
     int32_t overflow;   /* N or (n-1)*sampsum reached 2^53 */
     int32_t sampled;    /* v is in C */
+    /* Sec. 4.1, the estimated squared error of S_hyb */
+    int64_t LC_sumsq;   /* sum over L cap C of d(v,u)^2 */
+    int64_t HC_sqerr;   /* sum over HC of (d(v,u) - d(c(v),u))^2 */
+    double S_err;       /* |L|/|L cap C| * sample variance over L cap C + |H| * HC_sqerr/|HC| */
 } orc_node_out;
 
 int32_t orc_pivot(int32_t k, const int64_t* row) {
@@ -267,6 +276,7 @@ int orc_node_estimates(int64_t n, int32_t k, int64_t v, const int32_t* sidx, con
     int64_t ss = (n - 1) * sampsum;
     out->S_samp = (double)ss / (double)k;
     int64_t Lnum = 0, LCnum = 0, HCnum = 0, Hnum = 0, LCsum = 0, HCsum = 0, Hsum = 0;
+    __int128 LCsumsq = 0, HCsqerr = 0;
     for (int64_t u = 0; u < n; u++) {
         if (u == v) continue;
         int64_t dpu = colp[u * stride];
@@ -274,9 +284,10 @@ int orc_node_estimates(int64_t n, int32_t k, int64_t v, const int32_t* sidx, con
         int32_t i = sidx[u];
         if (in_L) {
             Lnum++;
-            if (i >= 0) { LCnum++; LCsum += row[i]; }
+            if (i >= 0) { LCnum++; LCsum += row[i]; LCsumsq += (__int128)row[i] * row[i]; }
         } else if (i >= 0) {
             HCnum++; HCsum += row[i];
+            HCsqerr += (__int128)(row[i] - dpu) * (row[i] - dpu);
         } else {
             Hnum++; Hsum += dpu;
         }
@@ -285,13 +296,46 @@ int orc_node_estimates(int64_t n, int32_t k, int64_t v, const int32_t* sidx, con
     out->LC_sum = LCsum; out->HC_sum = HCsum; out->H_sum = Hsum;
     /* LCnum >= 1 always: the pivot is in L cap C when eps <= 1 */
     if (LCnum < 1) { out->S_hyb = -1.0; return ORC_EOVERFLOW; }
+    /* Sec. 4.1: the sampling part estimates the variance of the L distances by
+     * the sample variance over L cap C (sum of squares / count minus squared
+     * mean), divided by |L cap C| and scaled by |L|; the pivoting part takes
+     * the mean squared difference over HC and scales it by |H| (no HC: 0).
+     * Written with the exact integer LCnum * LCsumsq - LCsum^2 and a fixed
+     * order of double operations. */
+    __int128 varnum = (__int128)LCnum * LCsumsq - (__int128)LCsum * LCsum;
+    int err_ovf = LCsumsq > (__int128)INT64_MAX || HCsqerr > (__int128)INT64_MAX || varnum > (__int128)INT64_MAX;
+    out->LC_sumsq = (int64_t)LCsumsq;
+    out->HC_sqerr = (int64_t)HCsqerr;
+    {
+        double tL = ((double)(int64_t)varnum / (double)(LCnum * LCnum * LCnum)) * (double)Lnum;
+        double tH = HCnum > 0 ? ((double)(int64_t)HCsqerr / (double)HCnum) * (double)Hnum : 0.0;
+        out->S_err = tL + tH;
+    }
     /* S_hyb = Hsum + HCsum + Lnum * LCsum / LCnum = N / LCnum */
     __int128 N = (__int128)(Hsum + HCsum) * LCnum + (__int128)Lnum * LCsum;
-    int ovf = (N >= (__int128)LIM) || (ss >= LIM);
+    int ovf = (N >= (__int128)LIM) || (ss >= LIM) || err_ovf;
     out->N = (int64_t)N;
     out->S_hyb = (double)(int64_t)N / (double)LCnum;
     out->overflow = ovf;
     return ovf ? ORC_EOVERFLOW : ORC_OK;
+}
+
+/* Sec. 4 / Sec. 8 adaptive choice: the hybrid estimate for each eps of a
+ * list, keeping the one with the smallest estimated squared error (the first
+ * in list order on ties).  Sampled nodes: the exact S(v), error 0. */
+int orc_node_adaptive(int64_t n, int32_t k, int64_t v, const int32_t* sidx, const int64_t* row,
+                      const int64_t* colp, int64_t stride, const int64_t* eps_nums, const int64_t* eps_dens,
+                      int32_t n_eps, double* S_ad, double* S_ad_err, int32_t* which) {
+    int status = ORC_OK;
+    *which = -1;
+    for (int32_t e = 0; e < n_eps; e++) {
+        orc_node_out o;
+        int st = orc_node_estimates(n, k, v, sidx, row, colp, stride, eps_nums[e], eps_dens[e], &o);
+        if (st != ORC_OK) status = st;
+        if (o.sampled) { *S_ad = o.S_hyb; *S_ad_err = 0.0; *which = 0; return status; }
+        if (*which < 0 || o.S_err < *S_ad_err) { *S_ad = o.S_hyb; *S_ad_err = o.S_err; *which = e; }
+    }
+    return status;
 }
 
 /* All nodes of a small graph from the full distance matrix D (node-major,
@@ -300,7 +344,8 @@ int orc_node_estimates(int64_t n, int32_t k, int64_t v, const int32_t* sidx, con
 typedef struct {
     int64_t n; int32_t k; const int32_t* sidx; const int64_t* D; int64_t en, ed;
     int32_t* pivot; int64_t* delta; int64_t* sampsum; int64_t* S_piv; int64_t* S_pub;
-    double* S_samp; double* S_hyb;
+    double* S_samp; double* S_hyb; double* S_err;
+    const int64_t* ad_nums; const int64_t* ad_dens; int32_t n_ad; double* S_ad; double* S_ad_err;
     int64_t next; pthread_mutex_t lock; int status;
 } all_job;
 
@@ -325,6 +370,16 @@ static void* all_worker(void* arg) {
             if (J->S_pub) J->S_pub[v] = o.S_pub;
             if (J->S_samp) J->S_samp[v] = o.S_samp;
             if (J->S_hyb) J->S_hyb[v] = o.S_hyb;
+            if (J->S_err) J->S_err[v] = o.sampled ? 0.0 : o.S_err;
+            if (J->S_ad && J->n_ad > 0) {
+                double a = 0, ae = 0;
+                int32_t w = 0;
+                st = orc_node_adaptive(J->n, J->k, v, J->sidx, row, J->D + p, J->k, J->ad_nums, J->ad_dens, J->n_ad,
+                                       &a, &ae, &w);
+                if (st != ORC_OK) { pthread_mutex_lock(&J->lock); J->status = st; pthread_mutex_unlock(&J->lock); }
+                J->S_ad[v] = a;
+                if (J->S_ad_err) J->S_ad_err[v] = ae;
+            }
         }
     }
     return NULL;
@@ -332,11 +387,15 @@ static void* all_worker(void* arg) {
 
 int orc_estimate_all(int64_t n, int32_t k, const int32_t* sidx, const int64_t* D, int64_t eps_num,
                      int64_t eps_den, int32_t threads, int32_t* pivot, int64_t* delta, int64_t* sampsum,
-                     int64_t* S_piv, int64_t* S_pub, double* S_samp, double* S_hyb) {
+                     int64_t* S_piv, int64_t* S_pub, double* S_samp, double* S_hyb, double* S_err,
+                     const int64_t* ad_nums, const int64_t* ad_dens, int32_t n_ad, double* S_ad,
+                     double* S_ad_err) {
     all_job J;
     J.n = n; J.k = k; J.sidx = sidx; J.D = D; J.en = eps_num; J.ed = eps_den;
     J.pivot = pivot; J.delta = delta; J.sampsum = sampsum; J.S_piv = S_piv; J.S_pub = S_pub;
-    J.S_samp = S_samp; J.S_hyb = S_hyb; J.next = 0; J.status = ORC_OK;
+    J.S_samp = S_samp; J.S_hyb = S_hyb; J.S_err = S_err;
+    J.ad_nums = ad_nums; J.ad_dens = ad_dens; J.n_ad = n_ad; J.S_ad = S_ad; J.S_ad_err = S_ad_err;
+    J.next = 0; J.status = ORC_OK;
     pthread_mutex_init(&J.lock, NULL);
     if (threads <= 1) {
         all_worker(&J);

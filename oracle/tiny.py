@@ -49,7 +49,7 @@ def estimates(dist, samples, eps: Fraction):
     k = len(samples)
     C = set(samples)
     S = [sum(dist[v]) for v in range(n)]
-    out = {key: [] for key in ("pivot", "delta", "S_exact", "S_samp", "S_piv", "S_pub", "S_hyb")}
+    out = {key: [] for key in ("pivot", "delta", "S_exact", "S_samp", "S_piv", "S_pub", "S_hyb", "S_err")}
     for j in range(n):
         out["S_exact"].append(S[j])
         dists = [dist[j][c] for c in samples]
@@ -61,6 +61,7 @@ def estimates(dist, samples, eps: Fraction):
         if j in C:
             for key in ("S_samp", "S_piv", "S_pub", "S_hyb"):
                 out[key].append(Fraction(S[j]))
+            out["S_err"].append(Fraction(0))
             continue
         T = Fraction(m) / eps
         others = set(range(n)) - {j}
@@ -72,7 +73,32 @@ def estimates(dist, samples, eps: Fraction):
         s_hyb = (sum(Fraction(dist[cp][i]) for i in H) + sum(Fraction(dist[j][i]) for i in HC)
                  + Fraction(len(L), len(LC)) * sum(Fraction(dist[j][i]) for i in LC))
         out["S_hyb"].append(s_hyb)
+        # Sec. 4.1: sample variance over L cap C (population form, mean of the
+        # squared deviations from the sample mean), over |L cap C|, times |L|;
+        # plus |H| times the mean squared pivot error over HC (none: 0)
+        mean = sum(Fraction(dist[j][i]) for i in LC) / len(LC)
+        var = sum((Fraction(dist[j][i]) - mean) ** 2 for i in LC) / len(LC)
+        piv_err = (sum(Fraction(dist[j][i] - dist[cp][i]) ** 2 for i in HC) / len(HC)) if HC else Fraction(0)
+        out["S_err"].append(var / len(LC) * len(L) + piv_err * len(H))
         out["S_samp"].append(Fraction(n - 1, k) * sum(dists))
         out["S_piv"].append(Fraction(S[cp]))
         out["S_pub"].append(Fraction(S[cp] + (n - 1) * m))
     return out
+
+
+def adaptive(dist, samples, eps_list):
+    """Per node, the hybrid estimate for the eps of eps_list (Fractions) with
+    the smallest estimated squared error, the first on ties (exact
+    rationals).  Returns (S_ad list, S_ad_err list, chosen index list)."""
+    per = [estimates(dist, samples, e) for e in eps_list]
+    n = len(dist)
+    S_ad, S_err, which = [], [], []
+    for j in range(n):
+        best = 0
+        for e in range(1, len(eps_list)):
+            if per[e]["S_err"][j] < per[best]["S_err"][j]:
+                best = e
+        S_ad.append(per[best]["S_hyb"][j])
+        S_err.append(per[best]["S_err"][j])
+        which.append(best)
+    return S_ad, S_err, which

@@ -298,3 +298,94 @@ def test_splitmix_bounded_is_exact_on_small_ranges():
         assert r1.below(8) == x >> 61           # power of two: never rejects
     r = SplitMix64(7)
     assert all(r.below(1) == 0 for _ in range(100))
+
+
+# ---------------------------------------------------------------- Sec. 4 error estimates
+
+def test_error_estimate_worked_example():
+    """Sec. 4.1 on the hand-derived path example (fixture with derivation)."""
+    rows = [list(map(int, ln.split())) for ln in open(os.path.join(GOLDEN, "path9_C048_eps1_2_err.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    g = graphgen.path(9)
+    out = oracle.estimate_all(g, [0, 4, 8], eps=(1, 2))
+    for node, num, den in rows:
+        assert abs(out["S_err"][node] - num / den) <= 1e-15 * max(1.0, num / den), node
+    t = tiny.estimates(tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx), [0, 4, 8], Fraction(1, 2))
+    assert [x for x in t["S_err"]] == [Fraction(num, den) for _, num, den in rows]
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_error_and_adaptive_vs_bruteforce(seed):
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(3, 26))
+    directed = seed % 4 == 3
+    g = graphgen.gnp(n, float(rng.uniform(0.15, 0.5)), 900 + seed, directed=directed,
+                     wmax=[1, 9, 1, 4][seed % 4])
+    if g.n < 3:
+        pytest.skip("component too small")
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    rg = None
+    if directed:
+        d = tiny.round_trip(d)
+        rg = graphgen.transpose(g)
+    if any(x == tiny.INF for r in d for x in r):
+        pytest.skip("not connected")
+    k = int(rng.integers(1, g.n + 1))
+    samples = [int(x) for x in rng.permutation(g.n)[:k]]
+    eps = [(1, 1), (1, 2), (2, 7), (1, 5)][seed % 4]
+    out = oracle.estimate_all(g, samples, eps=eps, reverse_graph=rg)
+    t = tiny.estimates(d, samples, Fraction(*eps))
+    for v in range(g.n):
+        exact = t["S_err"][v]
+        assert abs(out["S_err"][v] - float(exact)) <= 1e-12 * max(1.0, float(exact)), (v, exact)
+    eps_list = [Fraction(a, b) for a, b in oracle.ADAPTIVE_EPS]
+    per = [tiny.estimates(d, samples, e) for e in eps_list]
+    S_ad, S_ad_err, which = tiny.adaptive(d, samples, eps_list)
+    for v in range(g.n):
+        # the oracle's pick must be one of the exact minimisers (exact ties may
+        # be broken differently by rounded errors) and return that eps's estimate
+        best = min(p["S_err"][v] for p in per)
+        assert S_ad_err[v] == best
+        assert abs(out["S_ad_err"][v] - float(best)) <= 1e-12 * max(1.0, float(best)), v
+        assert any(p["S_err"][v] == best and abs(out["S_ad"][v] - float(p["S_hyb"][v])) <=
+                   1e-12 * float(p["S_hyb"][v]) for p in per), v
+
+
+def test_error_special_cases():
+    # K_n: every distance 1, H and HC empty -> 0
+    g = graphgen.complete(12)
+    out = oracle.estimate_all(g, [3, 7, 1], eps=(1, 2))
+    assert (out["S_err"] == 0).all()
+    # k = n: every node sampled -> 0, adaptive = exact
+    g = graphgen.ba(40, 2, seed=3)
+    out = oracle.estimate_all(g, list(range(g.n)))
+    assert (out["S_err"] == 0).all() and (out["S_ad_err"] == 0).all()
+    assert (out["S_ad"] == oracle.exact_sums(g)).all()
+    # tiny eps: H and HC empty, L = V \ {v}: (n-1)/k times the population
+    # variance of the k sample distances
+    g = graphgen.grid(9, 7, 4)
+    samples = [0, 10, 33, 50, 62]
+    out = oracle.estimate_all(g, samples, eps=(1, 1000))
+    D = out["D"]
+    sampled = set(samples)
+    for v in range(g.n):
+        if v in sampled:
+            continue
+        want = np.var(D[v].astype(np.float64)) * (g.n - 1) / len(samples)
+        assert abs(out["S_err"][v] - want) <= 1e-9 * max(1.0, want), v
+
+
+def test_adaptive_properties():
+    g = graphgen.rmat(8, 8, seed=4)
+    samples = oracle.draw_samples(g.n, 16, 2)
+    full = oracle.estimate_all(g, samples)
+    per = [oracle.estimate_all(g, samples, eps=e, D=full["D"], adaptive_eps=()) for e in oracle.ADAPTIVE_EPS]
+    errs = np.stack([p["S_err"] for p in per])
+    hyb = np.stack([p["S_hyb"] for p in per])
+    first_min = np.argmin(errs, axis=0)   # numpy: first index among equal minima
+    idx = np.arange(g.n)
+    assert (full["S_ad_err"] == errs[first_min, idx]).all()
+    assert (full["S_ad"] == hyb[first_min, idx]).all()
+    # a one-element list is the fixed-eps estimate
+    one = oracle.estimate_all(g, samples, eps=(1, 2), D=full["D"], adaptive_eps=((1, 2),))
+    assert (one["S_ad"] == one["S_hyb"]).all() and (one["S_ad_err"] == one["S_err"]).all()
