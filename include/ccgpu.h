@@ -134,6 +134,21 @@ typedef struct {
     int32_t* samples;  /* the samples used */
     int32_t* dmat;
     int32_t* D;
+    /* Sec. 4 (n entries each; 0 / the exact sum on sampled nodes):
+     *   S_err     estimated squared error of S_hyb: |L|/|L cap C| times the sample
+     *             variance of the distances to L cap C (mean squared deviation from
+     *             their mean), plus |H| times the mean over HC of
+     *             (d(v,u) - d(c(v),u))^2 (0 when HC is empty); computed as
+     *             ((|LC| * sum_LC d^2 - (sum_LC d)^2) / |LC|^3) * |L|
+     *             + (sum_HC (d - d_p)^2 / |HC|) * |H| in that order of double operations
+     *   S_ad      adaptive estimate: for each eps in {0.001, 0.025, 0.05, 0.1, 0.2,
+     *             0.5, 0.99} (the list of Sec. 8) the hybrid estimate and its
+     *             estimated error; the estimate with the smallest error (the first
+     *             in this order on ties)
+     *   S_ad_err  its estimated squared error */
+    double* S_err;
+    double* S_ad;
+    double* S_ad_err;
 } cc_result;
 
 /* Synchronous estimate; `out` holds HOST pointers. */

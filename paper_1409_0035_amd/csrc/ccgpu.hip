@@ -682,6 +682,9 @@ cc_status finish_flags(const DevFlags& hf) {
 }
 
 void fill_epilogue_outputs(EpilogueArgs& ea, const cc_result* out, int64_t* src_sum, int32_t* dmat) {
+    ea.S_err = out->S_err;
+    ea.S_ad = out->S_ad;
+    ea.S_ad_err = out->S_ad_err;
     ea.S_hyb = out->S_hyb;
     ea.S_samp = out->S_samp;
     ea.S_piv = out->S_piv;
@@ -944,7 +947,11 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ba.src_sum = src_sum;
             ba.dmat = dmat;
             ba.Dout = out->D;
-            ba_es = bits_epilogue_scratch(k, ba.lmax);
+            ba.S_err = out->S_err;
+            ba.S_ad = out->S_ad;
+            ba.S_ad_err = out->S_ad_err;
+            const bool want_err = out->S_err || out->S_ad || out->S_ad_err;
+            ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0);
             ba_scratch = ba_es <= trav_scratch ? ts : L.arena2.get(ba_es);
             run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
         } else {
@@ -1100,6 +1107,9 @@ struct Staging {
         add(host->samples, sizeof(int32_t) * k);
         add(host->dmat, sizeof(int32_t) * (size_t)k * k);
         add(host->D, sizeof(int32_t) * (size_t)n * k);
+        add(host->S_err, sizeof(double) * n);
+        add(host->S_ad, sizeof(double) * n);
+        add(host->S_ad_err, sizeof(double) * n);
         size_t total = 0;
         for (auto& f : fields) total += Carver::sz(f.bytes);
         if (total) {
@@ -1127,6 +1137,9 @@ struct Staging {
         dev.samples = (int32_t*)dptr(host->samples);
         dev.dmat = (int32_t*)dptr(host->dmat);
         dev.D = (int32_t*)dptr(host->D);
+        dev.S_err = (double*)dptr(host->S_err);
+        dev.S_ad = (double*)dptr(host->S_ad);
+        dev.S_ad_err = (double*)dptr(host->S_ad_err);
         return CC_OK;
     }
     void copy_back(hipStream_t st) {
@@ -1336,7 +1349,10 @@ cc_status run_batch(cc_context* ctx, std::vector<BatchItem>& items, Lane& L, cc_
         CCG_HIP(hipEventRecord(L.ev[1], st));
         if (rc != 0) return fail(CC_EDISCONNECTED, "a graph of the batch is not connected");
         size_t es = 0;
-        for (auto& it : items) es = std::max(es, bits_epilogue_scratch(it.r->k, lm));
+        for (auto& it : items) {
+            const bool want_err = it.out->S_err || it.out->S_ad || it.out->S_ad_err;
+            es = std::max(es, bits_epilogue_scratch(it.r->k, lm, want_err ? it.g->dg.n : 0));
+        }
         void* escr = L.arena2.get(es);
         size_t loff = 0;
         for (size_t j = 0; j < items.size(); j++) {
@@ -1367,6 +1383,9 @@ cc_status run_batch(cc_context* ctx, std::vector<BatchItem>& items, Lane& L, cc_
             ba.src_sum = src_sums[j];
             ba.dmat = dmats[j];
             ba.Dout = out->D;
+            ba.S_err = out->S_err;
+            ba.S_ad = out->S_ad;
+            ba.S_ad_err = out->S_ad_err;
             ba.node_off = it.node_off;
             ba.word_off = it.word_off;
             ba.row_words = W;

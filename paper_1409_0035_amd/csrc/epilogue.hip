@@ -381,6 +381,120 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     if (any_unreached) flags->disconnected = 1;
 }
 
+// Sec. 4: the estimated squared error of the hybrid estimate for the call's
+// eps, and the adaptive estimate -- for each eps of a fixed list, the hybrid
+// estimate and its estimated error, the first smallest error kept.  One lane
+// per node, one pass over its distance row for all eps at once.  For one eps,
+// with L cap C = {i : dmat[p][i] * num <= Delta * den} and HC the other
+// samples:
+//   err = ((LCnum * LCsumsq - LCsum^2) / LCnum^3) * Lnum + (HCsqerr / HCnum) * Hnum
+// (second term 0 without HC), HCsqerr = sum over HC of (d(v,c_i) - d(c_p,c_i))^2,
+// in exactly this order of double operations on exact integers.
+constexpr int kErrEps = 8;  // the call's eps + up to 7 listed ones
+struct ErrEps {
+    int32_t count;  // entries used; entry 0 is the call's eps
+    int64_t num[kErrEps], den[kErrEps];
+};
+
+template <typename DT, bool RT, typename MT>
+__global__ __launch_bounds__(kBlock) void k_errest(
+    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
+    int32_t bit_base, const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
+    const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum, ErrEps E, double* S_err,
+    double* S_ad, double* S_ad_err, DevFlags* flags) {
+    const int64_t LIM = (int64_t)1 << 53;
+    bool any_ovf = false;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+        const int64_t o = orig[v];
+        const int32_t js = sidx[v];
+        if (js >= 0) {  // a sample: its exact sum, no error
+            if (S_err) S_err[o] = 0.0;
+            if (S_ad) S_ad[o] = (double)src_sum[js - bit_base];
+            if (S_ad_err) S_ad_err[o] = 0.0;
+            continue;
+        }
+        uint32_t best = 0xFFFFFFFFu;
+        int32_t p = 0;
+        int64_t sum = 0;
+        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
+            if (d < best) {
+                best = d;
+                p = i;
+            }
+            sum += d;
+        });
+        const int64_t delta = best;
+        const MT* drow = dmat_c + (int64_t)p * k;
+        int32_t lcnum[kErrEps];
+        int64_t lcsum[kErrEps];
+        uint64_t lcsq[kErrEps], hcsq[kErrEps];
+#pragma unroll
+        for (int e = 0; e < kErrEps; e++) {
+            lcnum[e] = 0;
+            lcsum[e] = 0;
+            lcsq[e] = 0;
+            hcsq[e] = 0;
+        }
+        bool big = false;
+        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
+            const int64_t dl = drow[i];
+            const uint64_t dd = (uint64_t)d * d;
+            const int64_t diff = (int64_t)d - dl;
+            const uint64_t ee = (uint64_t)(diff * diff);
+            big = big || d >= (1u << 27) || dl >= (1 << 27);  // squares summed over k <= 4096 stay below 2^63
+#pragma unroll
+            for (int e = 0; e < kErrEps; e++) {
+                if (e >= E.count) break;
+                if (dl * E.num[e] <= delta * E.den[e]) {
+                    lcnum[e] += 1;
+                    lcsum[e] += d;
+                    lcsq[e] += dd;
+                } else {
+                    hcsq[e] += ee;
+                }
+            }
+        });
+        bool ovf = big;
+        double ad = 0.0, ad_err = 0.0, err0 = 0.0;
+#pragma unroll
+        for (int e = 0; e < kErrEps; e++) {
+            if (e >= E.count) break;
+            const int64_t thr = delta * E.den[e];
+            const int64_t tix = thr / E.num[e] + 1;  // d > floor(Delta/eps)  <=>  d >= tix
+            int64_t hnum = 0, hsum = 0;
+            if (tix < tlen) {
+                hnum = Tcnt[(int64_t)p * tlen + tix];
+                hsum = Tsum[(int64_t)p * tlen + tix];
+            }
+            const int64_t lc = lcnum[e];
+            const int64_t hcnum = k - lc;
+            const int64_t hcsum = sum - lcsum[e];
+            const int64_t lnum = (n - 1) - hnum - hcnum;
+            int64_t t1 = 0, t2 = 0, N = 0, vn1 = 0, vn2 = 0, varnum = 0;
+            bool eo = __builtin_mul_overflow(hsum + hcsum, lc, &t1) || __builtin_mul_overflow(lcsum[e], lnum, &t2) ||
+                      __builtin_add_overflow(t1, t2, &N) || N >= LIM || lc < 1 || lnum < lc;
+            eo = eo || __builtin_mul_overflow(lc, (int64_t)lcsq[e], &vn1) ||
+                 __builtin_mul_overflow(lcsum[e], lcsum[e], &vn2) || __builtin_sub_overflow(vn1, vn2, &varnum);
+            ovf = ovf || eo;
+            const double est = (double)N / (double)lc;
+            const double tL = ((double)varnum / (double)(lc * lc * lc)) * (double)lnum;
+            const double tH = hcnum > 0 ? ((double)(int64_t)hcsq[e] / (double)hcnum) * (double)hnum : 0.0;
+            const double err = tL + tH;
+            if (e == 0) {
+                err0 = err;
+            } else if (e == 1 || err < ad_err) {
+                ad = est;
+                ad_err = err;
+            }
+        }
+        if (S_err) S_err[o] = err0;
+        if (S_ad) S_ad[o] = ad;
+        if (S_ad_err) S_ad_err[o] = ad_err;
+        any_ovf = any_ovf || ovf;
+    }
+    if (any_ovf) flags->overflow = 1;
+}
+
 template <typename DT, bool RT>
 __global__ void k_to_i32(const DT* __restrict__ D, const DT* __restrict__ Dr, const int32_t* __restrict__ orig,
                          int64_t n, int32_t k, int32_t* __restrict__ out) {
@@ -453,6 +567,28 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         hipLaunchKernelGGL((k_to_i32<DT, RT>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, (const DT*)a.D,
                            (const DT*)a.Dr, a.orig, n, k, a.Dout);
     }
+    if (a.S_err || a.S_ad || a.S_ad_err) {
+        ErrArgs ea;
+        ea.D = a.D;
+        ea.Dr = a.Dr;
+        ea.dk = a.dk;
+        ea.n = n;
+        ea.k = k;
+        ea.sidx = a.sidx;
+        ea.orig = a.orig;
+        ea.dmat_c = dmat_c;
+        ea.mt_bytes = (int)sizeof(MT);
+        ea.Tcnt = Tcnt;
+        ea.Tsum = Tsum;
+        ea.tlen = tlen;
+        ea.src_sum = a.src_sum;
+        ea.eps_num = a.eps_num;
+        ea.eps_den = a.eps_den;
+        ea.S_err = a.S_err;
+        ea.S_ad = a.S_ad;
+        ea.S_ad_err = a.S_ad_err;
+        run_errest(st, ea, flags);
+    }
 }
 
 template <typename DT, bool RT>
@@ -463,6 +599,52 @@ void epilogue_mt(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags*
 }
 
 }  // namespace
+
+namespace {
+
+template <typename DT, bool RT, typename MT>
+void errest_t(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
+    ErrEps E{};
+    E.count = 1;
+    E.num[0] = a.eps_num;
+    E.den[0] = a.eps_den;
+    for (int32_t e = 0; e < kAdaptiveEps && E.count < kErrEps; e++) {
+        E.num[E.count] = kAdaptiveEpsNum[e];
+        E.den[E.count] = kAdaptiveEpsDen[e];
+        E.count++;
+    }
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((a.n + kBlock - 1) / kBlock, 4096));
+    hipLaunchKernelGGL((k_errest<DT, RT, MT>), dim3((unsigned)g), dim3(kBlock), 0, st, (const DT*)a.D, (const DT*)a.Dr,
+                       a.n, a.k, a.sidx, a.bit_base, a.orig, (const MT*)a.dmat_c, a.Tcnt, a.Tsum, a.tlen, a.src_sum, E,
+                       a.S_err, a.S_ad, a.S_ad_err, flags);
+}
+
+template <typename DT, bool RT>
+void errest_m(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
+    switch (a.mt_bytes) {
+        case 1: errest_t<DT, RT, uint8_t>(st, a, flags); break;
+        case 2: errest_t<DT, RT, uint16_t>(st, a, flags); break;
+        default: errest_t<DT, RT, uint32_t>(st, a, flags); break;
+    }
+}
+
+template <typename DT>
+void errest_r(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
+    if (a.Dr) errest_m<DT, true>(st, a, flags);
+    else errest_m<DT, false>(st, a, flags);
+}
+
+}  // namespace
+
+void run_errest(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
+    if (!a.S_err && !a.S_ad && !a.S_ad_err) return;
+    switch (a.dk) {
+        case DistKind::U8: errest_r<uint8_t>(st, a, flags); break;
+        case DistKind::U16: errest_r<uint16_t>(st, a, flags); break;
+        default: errest_r<uint32_t>(st, a, flags); break;
+    }
+    CCG_HIP(hipGetLastError());
+}
 
 void fill_u32(hipStream_t st, void* p, uint32_t value, size_t count) {
     if (count == 0) return;

@@ -318,6 +318,43 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
                                n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
         }
     }
+    if (a.S_err || a.S_ad || a.S_ad_err) {
+        // Sec. 4 needs each sample's distance row: materialise it (after the
+        // tables above in the scratch), then the shared error pass
+        char* dq = (char*)lmask + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W);
+        ErrArgs ea;
+        ea.D = dq;
+        ea.n = n;
+        ea.k = k;
+        ea.sidx = a.sidx + a.node_off;
+        ea.bit_base = a.bit_base;
+        ea.orig = a.orig;
+        ea.dmat_c = dmat_c;
+        ea.mt_bytes = (int)sizeof(MT);
+        ea.Tcnt = Tcnt;
+        ea.Tsum = Tsum;
+        ea.tlen = tlen;
+        ea.src_sum = a.src_sum;
+        ea.eps_num = a.eps_num;
+        ea.eps_den = a.eps_den;
+        ea.S_err = a.S_err;
+        ea.S_ad = a.S_ad;
+        ea.S_ad_err = a.S_ad_err;
+        if (lmax < 255) {
+            ea.dk = DistKind::U8;
+            hipLaunchKernelGGL((k_materialize_words<W, uint8_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
+                               sv, lmax, n, k, 0, k, (uint8_t*)dq, (const int32_t*)nullptr, (int)(k % 16 == 0), flags);
+        } else if (lmax < 65535) {
+            ea.dk = DistKind::U16;
+            hipLaunchKernelGGL((k_materialize<W, uint16_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, sv,
+                               lmax, n, k, 0, k, (uint16_t*)dq, (const int32_t*)nullptr, (int32_t*)nullptr, flags);
+        } else {
+            ea.dk = DistKind::U32;
+            hipLaunchKernelGGL((k_materialize<W, uint32_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, sv,
+                               lmax, n, k, 0, k, (uint32_t*)dq, (const int32_t*)nullptr, (int32_t*)nullptr, flags);
+        }
+        run_errest(st, ea, flags);
+    }
 }
 
 template <int W>
@@ -355,11 +392,13 @@ void materialize_w(hipStream_t st, const uint64_t* snap, size_t plane, int32_t l
 
 }  // namespace
 
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax) {
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows) {
     const int64_t tlen = (int64_t)lmax + 2;
     const int W = (k + 63) / 64;
+    const size_t db = lmax < 255 ? 1 : (lmax < 65535 ? 2 : 4);
     return align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
-           align256(sizeof(uint32_t) * (size_t)k * k) + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W) + 1024;
+           align256(sizeof(uint32_t) * (size_t)k * k) + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W) +
+           align256((size_t)err_rows * k * db) + 1024;
 }
 
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size,

@@ -416,6 +416,9 @@ struct EpilogueArgs {
     int64_t* src_sum = nullptr;  // required (workspace if caller does not want it)
     int32_t* dmat = nullptr;     // required (workspace if caller does not want it)
     int32_t* Dout = nullptr;     // optional int32 copy of D (combined), caller's node order
+    double* S_err = nullptr;     // Sec. 4 outputs (optional)
+    double* S_ad = nullptr;
+    double* S_ad_err = nullptr;
 };
 size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done);
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
@@ -452,6 +455,9 @@ struct BitsEpilogueArgs {
     int64_t* src_sum = nullptr;  // required
     int32_t* dmat = nullptr;     // required
     int32_t* Dout = nullptr;     // optional int32 distances, caller's node order
+    double* S_err = nullptr;     // Sec. 4 outputs (optional)
+    double* S_ad = nullptr;
+    double* S_ad_err = nullptr;
     // this graph's part of a batch's shared rows (defaults: the whole rows)
     int64_t node_off = 0;   // first row of this graph's nodes
     int32_t word_off = 0;   // first word of its samples in a row
@@ -459,7 +465,36 @@ struct BitsEpilogueArgs {
     int32_t bit_base = 0;   // its first sample's index in sidx and in the histogram rows
     int32_t hist_rows = 0;  // histogram rows per slot (0: k)
 };
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax);
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows = 0);
+
+// The eps values the experiments (Sec. 8) choose from per node for the
+// adaptive hybrid estimate: 0.001, 0.025, 0.05, 0.1, 0.2, 0.5, 0.99.
+constexpr int32_t kAdaptiveEps = 7;
+constexpr int64_t kAdaptiveEpsNum[kAdaptiveEps] = {1, 1, 1, 1, 1, 1, 99};
+constexpr int64_t kAdaptiveEpsDen[kAdaptiveEps] = {1000, 40, 20, 10, 5, 2, 100};
+
+// Inputs of the error-estimate pass (Sec. 4) over distance rows.
+struct ErrArgs {
+    const void* D = nullptr;    // node-major rows, dk bytes per entry
+    const void* Dr = nullptr;   // reverse rows (round trip) or null
+    DistKind dk = DistKind::U8;
+    int64_t n = 0;
+    int32_t k = 0;
+    const int32_t* sidx = nullptr;  // per row: sample index + bit_base, or -1
+    int32_t bit_base = 0;
+    const int32_t* orig = nullptr;
+    const void* dmat_c = nullptr;   // k x k sample distances, mt_bytes each
+    int mt_bytes = 1;
+    const int32_t* Tcnt = nullptr;
+    const int64_t* Tsum = nullptr;
+    int64_t tlen = 0;
+    const int64_t* src_sum = nullptr;
+    int64_t eps_num = 1, eps_den = 1;
+    double* S_err = nullptr;
+    double* S_ad = nullptr;
+    double* S_ad_err = nullptr;
+};
+void run_errest(hipStream_t st, const ErrArgs& a, DevFlags* flags);
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
 
 void fill_u32(hipStream_t st, void* p, uint32_t value, size_t count);

@@ -82,9 +82,24 @@ def test_fullsize_sampled(ctx, name):
     rng = np.random.default_rng(seed)
     deg = np.diff(g.row_ptr)
     nodes = list(rng.integers(0, n, size=4)) + [int(np.argmax(deg)), n - 1, int(samples[0]), int(samples[k - 1])]
+    # Sec. 4 outputs: the oracle's two extra Dijkstra runs per node on the 4.2M-node
+    # grid would double this test's time; the weighted path is covered at smaller
+    # sizes in test_gpu_errest.py
+    if name != "grid2048w":
+        gh = ctx.upload(g)
+        try:
+            errs = cc.cc_estimate(ctx.handle, gh, k, seed=seed, outputs=("S_err", "S_ad", "S_ad_err"))
+        finally:
+            ctx.release(gh)
+    else:
+        errs = None
     for v in nodes:
         _say(f"  node {v}")
         o = oracle.node_estimates(g, samples, int(v), reverse_graph=rg)
+        if errs is not None:
+            assert errs["S_err"][v] == (0.0 if o.sampled else o.S_err), v
+            a, ae, _ = oracle.node_adaptive(g, samples, int(v), reverse_graph=rg)
+            assert errs["S_ad"][v] == a and errs["S_ad_err"][v] == ae, v
         assert res["pivot"][v] == o.pivot, v
         assert res["delta"][v] == o.delta, v
         assert res["sampsum"][v] == o.sampsum, v
