@@ -365,22 +365,37 @@ __device__ __forceinline__ void hub_chunk(const int32_t* __restrict__ col, const
     uint64_t acc[W];
 #pragma unroll
     for (int w = 0; w < W; w++) acc[w] = 0;
-    uint32_t t = b + lane;
-    for (; t + 64 < e; t += 128) {
-        const int64_t u0 = col[t], u1 = col[t + 64];
+    // the bits the hub can still gain this level
+    uint64_t miss[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) miss[w] = full_word<W>(w, lastmask) & ~sh[w];
+    // The trip count is the same for every lane (loads predicated), so the
+    // wave-wide check below always sees every lane.
+    for (uint32_t base = b; base < e; base += 128) {
+        const uint32_t t0 = base + lane, t1 = t0 + 64;
         uint64_t a0[W], a1[W];
-        load_mask<W>(Sprev, u0, need, a0);
-        load_mask<W>(Sprev, u1, need, a1);
+        if (t0 < e) {
+            load_mask<W>(Sprev, col[t0], need, a0);
+            scanned += 1;
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; w++) a0[w] = 0;
+        }
+        if (t1 < e) {
+            load_mask<W>(Sprev, col[t1], need, a1);
+            scanned += 1;
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; w++) a1[w] = 0;
+        }
 #pragma unroll
         for (int w = 0; w < W; w++) acc[w] |= a0[w] | a1[w];
-        scanned += 2;
-    }
-    if (t < e) {
-        uint64_t a0[W];
-        load_mask<W>(Sprev, col[t], need, a0);
+        // stop once the chunk has found every bit the hub misses: the rest of
+        // its arcs cannot add any (exact early exit)
+        bool done = true;
 #pragma unroll
-        for (int w = 0; w < W; w++) acc[w] |= a0[w];
-        scanned += 1;
+        for (int w = 0; w < W; w++) done = done && (miss[w] & ~wave_or64_dpp(acc[w])) == 0;
+        if (done) break;
     }
 #pragma unroll
     for (int w = 0; w < W; w++) {
