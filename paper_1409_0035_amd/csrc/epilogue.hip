@@ -108,6 +108,201 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DT* __restrict__ D, con
     }
 }
 
+// ---- row-cooperative variants: G lanes per node, lane j of a node holding
+// the j-th 16 bytes of its row (and of the reverse row), so a wave's loads are
+// consecutive bytes and each row is read once.  For rows of 16 * G bytes,
+// G in {1, 2, 4, 8, 16}.
+
+template <typename DT, bool RT>
+struct RowPiece {
+    static constexpr int PER = 16 / (int)sizeof(DT);
+    uint32_t d[PER];
+    bool unreached = false;
+    __device__ __forceinline__ void load(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t v, int32_t k,
+                                         int sub) {
+        const uint4 a = ((const uint4*)(D + v * k))[sub];
+        uint4 b = make_uint4(0, 0, 0, 0);
+        if (RT) b = ((const uint4*)(Dr + v * k))[sub];
+        const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
+        const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
+        constexpr uint32_t mask = sizeof(DT) == 4 ? 0xFFFFFFFFu : ((1u << (8 * sizeof(DT))) - 1);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+#pragma unroll
+            for (int e = 0; e < 4 / (int)sizeof(DT); e++) {
+                const int sh = e * 8 * (int)sizeof(DT);
+                const uint32_t x = (wa[q] >> sh) & mask;
+                uint32_t y = 0;
+                if (RT) y = (wb[q] >> sh) & mask;
+                unreached = unreached || x == DistT<DT>::never || (RT && y == DistT<DT>::never);
+                d[q * (4 / (int)sizeof(DT)) + e] = x + y;
+            }
+        }
+    }
+};
+
+template <int G>
+__device__ __forceinline__ int64_t group_sum64(int64_t x) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// histogram over non-sampled nodes (as k_reduce)
+template <typename DT, bool RT, int G>
+__global__ __launch_bounds__(kBlock) void k_reduce_rows(const DT* __restrict__ D, const DT* __restrict__ Dr,
+                                                        int64_t n, int32_t k, const int32_t* __restrict__ sidx,
+                                                        int64_t hlen, int32_t* __restrict__ hist, int use_lds,
+                                                        DevFlags* flags) {
+    extern __shared__ int32_t lds_hist[];  // [k][hlen] when use_lds
+    if (use_lds) {
+        for (int64_t t = threadIdx.x; t < (int64_t)k * hlen; t += kBlock) lds_hist[t] = 0;
+        __syncthreads();
+    }
+    constexpr int PER = RowPiece<DT, RT>::PER;
+    const int sub = lane_id() & (G - 1);
+    const int64_t per_block = kBlock / G;
+    bool bad = false;
+    for (int64_t v0 = (int64_t)blockIdx.x * per_block; v0 < n; v0 += (int64_t)gridDim.x * per_block) {
+        const int64_t v = v0 + threadIdx.x / G;
+        if (v >= n || sidx[v] >= 0) continue;
+        RowPiece<DT, RT> r;
+        r.load(D, Dr, v, k, sub);
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            const int64_t i = (int64_t)sub * PER + e;
+            const uint32_t d = r.d[e];
+            if ((int64_t)d >= hlen || r.unreached) {
+                bad = true;
+            } else if (use_lds) {
+                atomicAdd(&lds_hist[i * hlen + d], 1);
+            } else {
+                atomicAdd(&hist[i * hlen + d], 1);
+            }
+        }
+    }
+    if (bad) flags->disconnected = 1;
+    if (use_lds) {
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < (int64_t)k * hlen; t += kBlock) {
+            const int32_t c = lds_hist[t];
+            if (c) atomicAdd(&hist[t], c);
+        }
+    }
+}
+
+// the estimators (as k_estimate)
+template <typename DT, bool RT, typename MT, int G>
+__global__ __launch_bounds__(kBlock) void k_estimate_rows(
+    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
+    const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
+    const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed,
+    double* S_hyb, double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out,
+    int64_t* sampsum_out, DevFlags* flags) {
+    constexpr int PER = RowPiece<DT, RT>::PER;
+    const int64_t LIM = (int64_t)1 << 53;
+    const int sub = lane_id() & (G - 1);
+    const int64_t per_block = kBlock / G;
+    bool any_ovf = false, any_unreached = false;
+    // every lane runs the same number of iterations (the group shuffles need
+    // all lanes); nodes past the end are masked, not skipped
+    const int64_t steps = (n + per_block - 1) / per_block;
+    for (int64_t s0 = blockIdx.x; s0 < steps; s0 += gridDim.x) {
+        const int64_t v = s0 * per_block + threadIdx.x / G;
+        const bool valid = v < n;
+        RowPiece<DT, RT> r;
+        if (valid) {
+            r.load(D, Dr, v, k, sub);
+        } else {
+#pragma unroll
+            for (int e = 0; e < PER; e++) r.d[e] = 0xFFFFFFFFu;
+        }
+        // argmin (lowest index among equal minima) and sum
+        uint32_t best = 0xFFFFFFFFu;
+        int32_t bi = 0;
+        int64_t sum = 0;
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            if (r.d[e] < best) {
+                best = r.d[e];
+                bi = sub * PER + e;
+            }
+            sum += valid ? r.d[e] : 0;
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            const uint32_t ob = (uint32_t)__shfl_xor((int)best, off);
+            const int32_t oi = __shfl_xor(bi, off);
+            if (ob < best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        sum = group_sum64<G>(sum);
+        const int p = bi;
+        const int64_t delta = best;
+        const int32_t j = valid ? sidx[v] : 0;
+        // the L cap C split against the pivot's row of the sample distances
+        const int64_t thr = delta * ed;
+        const MT* drow = dmat_c + (int64_t)p * k;
+        int64_t lcsum = 0, lcnum = 0;
+        if (valid && j < 0) {
+#pragma unroll
+            for (int e = 0; e < PER; e++) {
+                if ((int64_t)drow[sub * PER + e] * en <= thr) {
+                    lcsum += r.d[e];
+                    lcnum += 1;
+                }
+            }
+        }
+        lcsum = group_sum64<G>(lcsum);
+        lcnum = group_sum64<G>(lcnum);
+        bool unreached = r.unreached;
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) unreached = unreached || __shfl_xor((int)unreached, off);
+        if (!valid || sub != 0) continue;
+        double hyb, samp;
+        int64_t piv, pub;
+        bool ovf = false;
+        if (j >= 0) {
+            const int64_t S = src_sum[j];
+            hyb = samp = (double)S;
+            piv = pub = S;
+            ovf = S >= LIM;
+        } else {
+            const int64_t tix = thr / en + 1;  // d > floor(Delta/eps)  <=>  d >= tix
+            int64_t hnum = 0, hsum = 0;
+            if (tix < tlen) {
+                hnum = Tcnt[(int64_t)p * tlen + tix];
+                hsum = Tsum[(int64_t)p * tlen + tix];
+            }
+            const int64_t hcsum = sum - lcsum;
+            const int64_t lnum = (n - 1) - hnum - (int64_t)(k - lcnum);
+            const int64_t a = hsum + hcsum;
+            int64_t t1 = 0, t2 = 0, N = 0, ss = 0;
+            ovf = __builtin_mul_overflow(a, lcnum, &t1) || __builtin_mul_overflow(lcsum, lnum, &t2) ||
+                  __builtin_add_overflow(t1, t2, &N) || N >= LIM || lcnum < 1 || lnum < lcnum;
+            hyb = (double)N / (double)lcnum;
+            ovf = ovf || __builtin_mul_overflow(n - 1, sum, &ss) || ss >= LIM;
+            samp = (double)ss / (double)k;
+            piv = src_sum[p];
+            pub = piv + (n - 1) * delta;
+        }
+        const int64_t o = orig[v];
+        if (S_hyb) S_hyb[o] = hyb;
+        if (S_samp) S_samp[o] = samp;
+        if (S_piv) S_piv[o] = piv;
+        if (S_pub) S_pub[o] = pub;
+        if (pivot_out) pivot_out[o] = p;
+        if (delta_out) delta_out[o] = (int32_t)delta;
+        if (sampsum_out) sampsum_out[o] = sum;
+        any_ovf = any_ovf || ovf;
+        any_unreached = any_unreached || unreached;
+    }
+    if (any_ovf) flags->overflow = 1;
+    if (any_unreached) flags->disconnected = 1;
+}
+
 template <typename DT, bool RT, typename MT>
 __global__ void k_dmat(const DT* __restrict__ D, const DT* __restrict__ Dr, const int32_t* __restrict__ samples,
                        int32_t k, int32_t* __restrict__ dmat_out, MT* __restrict__ dmat_c, DevFlags* flags) {
@@ -524,6 +719,16 @@ inline unsigned grid_for(int64_t items, int64_t cap) {
     return (unsigned)g;
 }
 
+// lanes per node of the row-cooperative kernels (16 bytes each), or 0 when the
+// row is not 16 * G bytes for G in {1, 2, 4, 8, 16}
+template <typename DT>
+int row_lanes(int32_t k) {
+    const int64_t bytes = (int64_t)k * (int64_t)sizeof(DT);
+    if (bytes % 16 != 0) return 0;
+    const int64_t g = bytes / 16;
+    return (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ? (int)g : 0;
+}
+
 template <typename DT, bool RT, typename MT>
 void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* flags) {
     const int64_t n = a.n;
@@ -550,18 +755,49 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         fill_u32(st, hist, 0u, (size_t)(k * hlen));
         const size_t lds = sizeof(int32_t) * (size_t)k * hlen;
         const int use_lds = lds <= 48 * 1024 ? 1 : 0;
-        hipLaunchKernelGGL((k_reduce<DT, RT>), dim3(grid_for(n, use_lds ? 1024 : 8192)), dim3(kBlock),
-                           use_lds ? lds : 0, st, (const DT*)a.D, (const DT*)a.Dr, n, k, a.sidx, hlen, hist, use_lds,
-                           flags);
+        const int G = row_lanes<DT>(k);
+        const unsigned rb = grid_for(n, use_lds ? 1024 : 8192);
+        const size_t lb = use_lds ? lds : 0;
+        const DT* Dp = (const DT*)a.D;
+        const DT* Drp = (const DT*)a.Dr;
+        switch (G) {
+            case 1: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 1>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
+            case 2: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 2>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
+            case 4: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 4>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
+            case 8: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 8>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
+            case 16: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 16>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
+            default:
+                hipLaunchKernelGGL((k_reduce<DT, RT>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist,
+                                   use_lds, flags);
+        }
         CCG_HIP(hipGetLastError());
     }
     const int64_t kk = (int64_t)k * k;
     hipLaunchKernelGGL((k_dmat<DT, RT, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, (const DT*)a.D,
                        (const DT*)a.Dr, a.samples, k, a.dmat, dmat_c, flags);
     run_suffix(st, hist, nslots, k, k, hlen, maxd, a.dmat, Tcnt, Tsum, a.src_sum, chunks);
-    hipLaunchKernelGGL((k_estimate<DT, RT, MT>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, (const DT*)a.D,
-                       (const DT*)a.Dr, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,
-                       a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
+    {
+        const DT* Dp = (const DT*)a.D;
+        const DT* Drp = (const DT*)a.Dr;
+        const int G = row_lanes<DT>(k);
+        const unsigned eb = grid_for(n * (G > 0 ? G : 1), 8192);
+#define CCG_EST_ROWS(GG)                                                                                            \
+    hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG>), dim3(eb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx,       \
+                       a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb, a.S_samp, a.S_piv, \
+                       a.S_pub, a.pivot, a.delta, a.sampsum, flags)
+        switch (G) {
+            case 1: CCG_EST_ROWS(1); break;
+            case 2: CCG_EST_ROWS(2); break;
+            case 4: CCG_EST_ROWS(4); break;
+            case 8: CCG_EST_ROWS(8); break;
+            case 16: CCG_EST_ROWS(16); break;
+            default:
+                hipLaunchKernelGGL((k_estimate<DT, RT, MT>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, Dp, Drp, n, k,
+                                   a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb,
+                                   a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
+        }
+#undef CCG_EST_ROWS
+    }
     CCG_HIP(hipGetLastError());
     if (a.Dout) {
         hipLaunchKernelGGL((k_to_i32<DT, RT>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, (const DT*)a.D,
