@@ -456,6 +456,31 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
         if (!w)
             std::stable_sort(orig.begin(), orig.end(),
                              [&](int32_t a, int32_t b) { return deg[(size_t)a] > deg[(size_t)b]; });
+        if (!w) {
+            // Locality for the hub pulls: after the hubs (a prefix by degree;
+            // for digraphs by in+out degree, which keeps every node whose in-
+            // or out-degree passes the hub threshold inside the prefix), nodes
+            // go by coarse degree class (so 64-node groups stay even) and then
+            // by their first hub (out-)neighbour, so that the neighbours a
+            // hub's chunk gathers sit close together in id order.
+            int64_t H = 0;
+            while (H < n && deg[(size_t)orig[(size_t)H]] > (int64_t)kHubDegree) H++;
+            std::vector<int64_t> rank((size_t)n);
+            for (int64_t i = 0; i < n; i++) rank[(size_t)orig[(size_t)i]] = i;
+            std::vector<int64_t> first_hub((size_t)n, H);
+            for (int64_t i = H; i < n; i++) {
+                const int64_t v = orig[(size_t)i];
+                int64_t f = H;
+                for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) f = std::min(f, rank[(size_t)col_idx[e]]);
+                first_hub[(size_t)v] = f;
+            }
+            auto cls = [&](int64_t v) { return 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(deg[(size_t)v], 1)); };
+            std::stable_sort(orig.begin() + H, orig.end(), [&](int32_t a, int32_t b) {
+                const int ca = cls(a), cb = cls(b);
+                if (ca != cb) return ca > cb;
+                return first_hub[(size_t)a] < first_hub[(size_t)b];
+            });
+        }
         g->inv.assign((size_t)n, 0);
         for (int64_t i = 0; i < n; i++) g->inv[(size_t)orig[(size_t)i]] = (int32_t)i;
         // ---- relabelled out-arcs
@@ -472,6 +497,8 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
                 col[q] = g->inv[(size_t)col_idx[e]];
                 if (w) ww[q] = w[e];
             }
+            // rows in id order: a chunk's lanes then read neighbouring masks
+            if (!w) std::sort(col.begin() + rp[(size_t)i], col.begin() + rp[(size_t)i + 1]);
         }
         std::vector<uint32_t> trp;
         std::vector<int32_t> tcol, tw;
