@@ -388,6 +388,24 @@ namespace {
 constexpr uint32_t kHubDegree = 32;    // in-degree above which a node's arcs are scanned in chunks
 constexpr uint32_t kHubChunk = 1024;   // arcs per chunk
 
+// Runs f over [lo, hi) split into contiguous ranges on the host's threads
+// (one range for small inputs).
+void parallel_ranges(int64_t lo, int64_t hi, const std::function<void(int64_t, int64_t)>& f) {
+    const int64_t count = hi - lo;
+    const int64_t hw = std::max<int64_t>(1, std::min<int64_t>(std::thread::hardware_concurrency(), 16));
+    const int64_t parts = count < 65536 ? 1 : hw;
+    if (parts <= 1) {
+        if (count > 0) f(lo, hi);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t p = 0; p < parts; p++) {
+        const int64_t a = lo + count * p / parts, b = lo + count * (p + 1) / parts;
+        th.emplace_back([&f, a, b] { f(a, b); });
+    }
+    for (auto& t : th) t.join();
+}
+
 std::vector<int32_t> hub_chunk_list(const std::vector<uint32_t>& rp, int64_t nh) {
     std::vector<int32_t> c;
     for (int64_t h = 0; h < nh; h++)
@@ -468,12 +486,14 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             std::vector<int64_t> rank((size_t)n);
             for (int64_t i = 0; i < n; i++) rank[(size_t)orig[(size_t)i]] = i;
             std::vector<int64_t> first_hub((size_t)n, H);
-            for (int64_t i = H; i < n; i++) {
-                const int64_t v = orig[(size_t)i];
-                int64_t f = H;
-                for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) f = std::min(f, rank[(size_t)col_idx[e]]);
-                first_hub[(size_t)v] = f;
-            }
+            parallel_ranges(H, n, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; i++) {
+                    const int64_t v = orig[(size_t)i];
+                    int64_t f = H;
+                    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) f = std::min(f, rank[(size_t)col_idx[e]]);
+                    first_hub[(size_t)v] = f;
+                }
+            });
             auto cls = [&](int64_t v) { return 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(deg[(size_t)v], 1)); };
             std::stable_sort(orig.begin() + H, orig.end(), [&](int32_t a, int32_t b) {
                 const int ca = cls(a), cb = cls(b);
@@ -490,16 +510,18 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             const int64_t v = orig[(size_t)i];
             rp[(size_t)i + 1] = rp[(size_t)i] + (uint32_t)(row_ptr[v + 1] - row_ptr[v]);
         }
-        for (int64_t i = 0; i < n; i++) {
-            const int64_t v = orig[(size_t)i];
-            uint32_t q = rp[(size_t)i];
-            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++, q++) {
-                col[q] = g->inv[(size_t)col_idx[e]];
-                if (w) ww[q] = w[e];
+        parallel_ranges(0, n, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; i++) {
+                const int64_t v = orig[(size_t)i];
+                uint32_t q = rp[(size_t)i];
+                for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++, q++) {
+                    col[q] = g->inv[(size_t)col_idx[e]];
+                    if (w) ww[q] = w[e];
+                }
+                // rows in id order: a chunk's lanes then read neighbouring masks
+                if (!w) std::sort(col.begin() + rp[(size_t)i], col.begin() + rp[(size_t)i + 1]);
             }
-            // rows in id order: a chunk's lanes then read neighbouring masks
-            if (!w) std::sort(col.begin() + rp[(size_t)i], col.begin() + rp[(size_t)i + 1]);
-        }
+        });
         std::vector<uint32_t> trp;
         std::vector<int32_t> tcol, tw;
         if (directed) transpose_host(n, rp, col, ww, trp, tcol, tw);
