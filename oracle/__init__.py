@@ -11,9 +11,10 @@ What it computes (Cohen, Delling, Pajor & Werneck 2014):
   * the pivot c(v) and Delta(v) (Sec. 2), the sample average Eq. (5), the
     pivot estimate, the pivoting upper bound (Sec. 1), and the hybrid
     estimate Eq. (6), by an explicit walk over all nodes per estimated node;
-  * the estimated squared error of the hybrid estimate (Sec. 4.1) and the
+  * the estimated squared error of the hybrid estimate (Sec. 4.1), the
     adaptive estimate that picks, per node, the eps of a list with the
-    smallest estimated error (Sec. 4, eps list of Sec. 8);
+    smallest estimated error (Sec. 4, eps list of Sec. 8), and the threshold
+    sweep of Algorithm 2 (Sec. 4.2);
   * exact S(v) for every node (Eq. (1)) by one search per node.
 
 Pins (closed forms, special cases, worked examples, brute force) live in
@@ -77,7 +78,10 @@ def _load():
     lib.orc_node_estimates.restype = ctypes.c_int
     lib.orc_node_estimates.argtypes = [i64, i32, i64, P, P, P, i64, i64, i64, ctypes.POINTER(NodeOut)]
     lib.orc_estimate_all.restype = ctypes.c_int
-    lib.orc_estimate_all.argtypes = [i64, i32, P, P, i64, i64, i32, P, P, P, P, P, P, P, P, P, P, i32, P, P]
+    lib.orc_estimate_all.argtypes = [i64, i32, P, P, i64, i64, i32, P, P, P, P, P, P, P, P, P, P, i32, P, P, P, P]
+    lib.orc_node_sweep.restype = ctypes.c_int
+    lib.orc_node_sweep.argtypes = [i64, i32, i64, P, P, P, i64, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
     lib.orc_node_adaptive.restype = ctypes.c_int
     lib.orc_node_adaptive.argtypes = [i64, i32, i64, P, P, P, i64, P, P, i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
@@ -155,7 +159,7 @@ ADAPTIVE_EPS = ((1, 1000), (1, 40), (1, 20), (1, 10), (1, 5), (1, 2), (99, 100))
 
 
 def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=None,
-                 adaptive_eps=ADAPTIVE_EPS) -> dict:
+                 adaptive_eps=ADAPTIVE_EPS, sweep: bool = False) -> dict:
     """Every estimator for every node (O(n^2) hybrid walk: small graphs only).
     Also returns D, the per-sample sums S(c_i) and the sample distance matrix
     dmat[i, j] = d(c_i, c_j)."""
@@ -171,7 +175,8 @@ def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=N
     out = dict(pivot=np.empty(n, np.int32), delta=np.empty(n, np.int64), sampsum=np.empty(n, np.int64),
                S_piv=np.empty(n, np.int64), S_pub=np.empty(n, np.int64), S_samp=np.empty(n, np.float64),
                S_hyb=np.empty(n, np.float64), S_err=np.empty(n, np.float64), S_ad=np.empty(n, np.float64),
-               S_ad_err=np.empty(n, np.float64))
+               S_ad_err=np.empty(n, np.float64), S_sweep=np.empty(n, np.float64),
+               S_sweep_err=np.empty(n, np.float64))
     ad = list(adaptive_eps or ())
     ad_n = np.array([a for a, _ in ad] or [1], dtype=np.int64)
     ad_d = np.array([b for _, b in ad] or [1], dtype=np.int64)
@@ -179,7 +184,10 @@ def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=N
                               _p(out["pivot"]), _p(out["delta"]), _p(out["sampsum"]), _p(out["S_piv"]),
                               _p(out["S_pub"]), _p(out["S_samp"]), _p(out["S_hyb"]), _p(out["S_err"]),
                               _p(ad_n), _p(ad_d), len(ad), _p(out["S_ad"]) if ad else None,
-                              _p(out["S_ad_err"]) if ad else None)
+                              _p(out["S_ad_err"]) if ad else None, _p(out["S_sweep"]) if sweep else None,
+                              _p(out["S_sweep_err"]) if sweep else None)
+    if not sweep:
+        del out["S_sweep"], out["S_sweep_err"]
     if not ad:
         del out["S_ad"], out["S_ad_err"]
     if st != 0:
@@ -239,6 +247,23 @@ def node_adaptive(g, samples, v: int, adaptive_eps=ADAPTIVE_EPS, reverse_graph=N
     if st not in (0, 4):
         raise OracleError(f"orc_node_adaptive failed ({st})")
     return a.value, e.value, w.value
+
+
+def node_sweep(g, samples, v: int, reverse_graph=None):
+    """The threshold-sweep estimate of one node (Algorithm 2 / Sec. 4.2) and
+    its estimated squared error, with two searches (from v and its pivot)."""
+    lib = _load()
+    samples = np.ascontiguousarray(samples, dtype=np.int32)
+    k = int(samples.shape[0])
+    row = np.ascontiguousarray(sssp(g, v, reverse_graph)[samples], dtype=np.int64)
+    p = int(lib.orc_pivot(k, _p(row)))
+    colp = sssp(g, int(samples[p]), reverse_graph)
+    sidx = sample_index(g.n, samples)
+    a, e = ctypes.c_double(), ctypes.c_double()
+    st = lib.orc_node_sweep(g.n, k, int(v), _p(sidx), _p(row), _p(colp), 1, ctypes.byref(a), ctypes.byref(e))
+    if st not in (0, 4):
+        raise OracleError(f"orc_node_sweep failed ({st})")
+    return a.value, e.value
 
 
 def exact_sums(g, threads: int = 1, reverse_graph=None) -> np.ndarray:

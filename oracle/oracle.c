@@ -28,6 +28,9 @@
  *   orc_node_adaptive           the adaptive choice of Sec. 4 / Sec. 8: the
  *                               hybrid estimate for each eps of a list, the
  *                               one with the smallest estimated error kept.
+ *   orc_node_sweep              Algorithm 2 / Sec. 4.2: the threshold sweep over
+ *                               the pivot's distances to the samples, the
+ *                               candidate with the smallest estimated error.
  *   orc_estimate_all            the above for every node, O(n^2): small graphs.
  *   orc_exact_sums              S(v) for every node by n searches (Eq. (1)).
  *
@@ -338,6 +341,70 @@ int orc_node_adaptive(int64_t n, int32_t k, int64_t v, const int32_t* sidx, cons
     return status;
 }
 
+/* Sec. 4.2 / Algorithm 2, the threshold sweep: candidates are pure pivoting
+ * (S(c(v)), with the mean squared pivot error over all k samples times the
+ * n-1-k other unsampled nodes) and, for every distinct distance T from the
+ * pivot to a sample, the estimate with the partition of V \ {v} into
+ * L = {d(c(v),u) <= T}, HC and H as in Eq. (6) and its error as in Sec. 4.1.
+ * The candidate with the smallest error is kept (a later candidate only when
+ * strictly smaller, candidates in increasing T after pure pivoting).  Each
+ * threshold is evaluated by a literal walk over the nodes. */
+int orc_node_sweep(int64_t n, int32_t k, int64_t v, const int32_t* sidx, const int64_t* row, const int64_t* colp,
+                   int64_t stride, double* S_out, double* err_out) {
+    const int64_t LIM = (int64_t)1 << 53;
+    int32_t p = orc_pivot(k, row);
+    int64_t Sp = 0;
+    for (int64_t u = 0; u < n; u++) Sp += colp[u * stride];
+    if (sidx[v] >= 0) { *S_out = (double)Sp; *err_out = 0.0; return Sp >= LIM ? ORC_EOVERFLOW : ORC_OK; }
+    /* d(c_p, c_i) for every sample i, from the pivot's column */
+    int64_t* dp = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+    for (int64_t u = 0; u < n; u++) if (sidx[u] >= 0) dp[sidx[u]] = colp[u * stride];
+    /* pure pivoting */
+    __int128 sq_all = 0;
+    for (int32_t i = 0; i < k; i++) sq_all += (__int128)(row[i] - dp[i]) * (row[i] - dp[i]);
+    int ovf = Sp >= LIM || sq_all > (__int128)INT64_MAX;
+    double best_S = (double)Sp;
+    double best_err = ((double)(int64_t)sq_all / (double)k) * (double)(n - 1 - k);
+    /* thresholds: the distinct values of dp, ascending */
+    int64_t T = -1;
+    for (;;) {
+        int64_t next = -1;
+        for (int32_t i = 0; i < k; i++)
+            if (dp[i] > T && (next < 0 || dp[i] < next)) next = dp[i];
+        if (next < 0) break;
+        T = next;
+        int64_t Lnum = 0, LCnum = 0, HCnum = 0, Hnum = 0, LCsum = 0, HCsum = 0, Hsum = 0;
+        __int128 LCsumsq = 0, HCsqerr = 0;
+        for (int64_t u = 0; u < n; u++) {
+            if (u == v) continue;
+            int64_t dpu = colp[u * stride];
+            int32_t i = sidx[u];
+            if (dpu <= T) {
+                Lnum++;
+                if (i >= 0) { LCnum++; LCsum += row[i]; LCsumsq += (__int128)row[i] * row[i]; }
+            } else if (i >= 0) {
+                HCnum++; HCsum += row[i];
+                HCsqerr += (__int128)(row[i] - dpu) * (row[i] - dpu);
+            } else {
+                Hnum++; Hsum += dpu;
+            }
+        }
+        if (LCnum < 1) continue; /* cannot happen: the pivot sample is at distance 0 */
+        __int128 N = (__int128)(Hsum + HCsum) * LCnum + (__int128)Lnum * LCsum;
+        __int128 varnum = (__int128)LCnum * LCsumsq - (__int128)LCsum * LCsum;
+        ovf = ovf || N >= (__int128)LIM || varnum > (__int128)INT64_MAX || HCsqerr > (__int128)INT64_MAX;
+        double est = (double)(int64_t)N / (double)LCnum;
+        double tL = ((double)(int64_t)varnum / (double)(LCnum * LCnum * LCnum)) * (double)Lnum;
+        double tH = HCnum > 0 ? ((double)(int64_t)HCsqerr / (double)HCnum) * (double)Hnum : 0.0;
+        double err = tL + tH;
+        if (err < best_err) { best_err = err; best_S = est; }
+    }
+    free(dp);
+    *S_out = best_S;
+    *err_out = best_err;
+    return ovf ? ORC_EOVERFLOW : ORC_OK;
+}
+
 /* All nodes of a small graph from the full distance matrix D (node-major,
  * n x k).  Output arrays have n entries; any may be NULL. Multithreaded over
  * nodes when threads > 1. */
@@ -346,6 +413,7 @@ typedef struct {
     int32_t* pivot; int64_t* delta; int64_t* sampsum; int64_t* S_piv; int64_t* S_pub;
     double* S_samp; double* S_hyb; double* S_err;
     const int64_t* ad_nums; const int64_t* ad_dens; int32_t n_ad; double* S_ad; double* S_ad_err;
+    double* S_sweep; double* S_sweep_err;
     int64_t next; pthread_mutex_t lock; int status;
 } all_job;
 
@@ -380,6 +448,13 @@ static void* all_worker(void* arg) {
                 J->S_ad[v] = a;
                 if (J->S_ad_err) J->S_ad_err[v] = ae;
             }
+            if (J->S_sweep) {
+                double a = 0, ae = 0;
+                st = orc_node_sweep(J->n, J->k, v, J->sidx, row, J->D + p, J->k, &a, &ae);
+                if (st != ORC_OK) { pthread_mutex_lock(&J->lock); J->status = st; pthread_mutex_unlock(&J->lock); }
+                J->S_sweep[v] = a;
+                if (J->S_sweep_err) J->S_sweep_err[v] = ae;
+            }
         }
     }
     return NULL;
@@ -389,12 +464,13 @@ int orc_estimate_all(int64_t n, int32_t k, const int32_t* sidx, const int64_t* D
                      int64_t eps_den, int32_t threads, int32_t* pivot, int64_t* delta, int64_t* sampsum,
                      int64_t* S_piv, int64_t* S_pub, double* S_samp, double* S_hyb, double* S_err,
                      const int64_t* ad_nums, const int64_t* ad_dens, int32_t n_ad, double* S_ad,
-                     double* S_ad_err) {
+                     double* S_ad_err, double* S_sweep, double* S_sweep_err) {
     all_job J;
     J.n = n; J.k = k; J.sidx = sidx; J.D = D; J.en = eps_num; J.ed = eps_den;
     J.pivot = pivot; J.delta = delta; J.sampsum = sampsum; J.S_piv = S_piv; J.S_pub = S_pub;
     J.S_samp = S_samp; J.S_hyb = S_hyb; J.S_err = S_err;
     J.ad_nums = ad_nums; J.ad_dens = ad_dens; J.n_ad = n_ad; J.S_ad = S_ad; J.S_ad_err = S_ad_err;
+    J.S_sweep = S_sweep; J.S_sweep_err = S_sweep_err;
     J.next = 0; J.status = ORC_OK;
     pthread_mutex_init(&J.lock, NULL);
     if (threads <= 1) {

@@ -102,3 +102,51 @@ def adaptive(dist, samples, eps_list):
         S_err.append(per[best]["S_err"][j])
         which.append(best)
     return S_ad, S_err, which
+
+
+def sweep_candidates(dist, samples, j):
+    """The candidates of Algorithm 2 / Sec. 4.2 for an unsampled node j, in
+    the order they are compared: pure pivoting (S(c(j)), mean squared pivot
+    error over all samples times the other unsampled nodes), then, for each
+    distinct distance T from the pivot to a sample in increasing order, the
+    threshold estimate over the partition of V minus j into L, HC and H, with
+    its estimated error as in Sec. 4.1.  Exact rationals, explicit sets."""
+    n = len(dist)
+    k = len(samples)
+    C = set(samples)
+    dists = [dist[j][c] for c in samples]
+    cp = samples[dists.index(min(dists))]
+    sq_all = sum(Fraction(dist[j][c] - dist[cp][c]) ** 2 for c in samples)
+    out = [(Fraction(sum(dist[cp])), sq_all / k * (n - 1 - k))]
+    others = set(range(n)) - {j}
+    for T in sorted({dist[cp][c] for c in samples}):
+        L = {i for i in others if dist[cp][i] <= T}
+        HC = {i for i in others if i in C and dist[cp][i] > T}
+        H = {i for i in others if i not in C and dist[cp][i] > T}
+        LC = L & C
+        s_T = (sum(Fraction(dist[cp][i]) for i in H) + sum(Fraction(dist[j][i]) for i in HC)
+               + Fraction(len(L), len(LC)) * sum(Fraction(dist[j][i]) for i in LC))
+        mean = sum(Fraction(dist[j][i]) for i in LC) / len(LC)
+        var = sum((Fraction(dist[j][i]) - mean) ** 2 for i in LC) / len(LC)
+        piv = (sum(Fraction(dist[j][i] - dist[cp][i]) ** 2 for i in HC) / len(HC)) if HC else Fraction(0)
+        out.append((s_T, var / len(LC) * len(L) + piv * len(H)))
+    return out
+
+
+def sweep(dist, samples):
+    """Algorithm 2 / Sec. 4.2 with exact rationals: per node the candidate of
+    sweep_candidates with the smallest estimated error (the first on ties);
+    sampled nodes get their exact sum and error 0.  Returns (estimates,
+    errors)."""
+    C = set(samples)
+    est, errs = [], []
+    for j in range(len(dist)):
+        if j in C:
+            est.append(Fraction(sum(dist[j])))
+            errs.append(Fraction(0))
+            continue
+        cand = sweep_candidates(dist, samples, j)
+        best = min(range(len(cand)), key=lambda t: (cand[t][1], t))
+        est.append(cand[best][0])
+        errs.append(cand[best][1])
+    return est, errs

@@ -389,3 +389,91 @@ def test_adaptive_properties():
     # a one-element list is the fixed-eps estimate
     one = oracle.estimate_all(g, samples, eps=(1, 2), D=full["D"], adaptive_eps=((1, 2),))
     assert (one["S_ad"] == one["S_hyb"]).all() and (one["S_ad_err"] == one["S_err"]).all()
+
+
+# ---------------------------------------------------------------- Algorithm 2 threshold sweep
+
+def test_sweep_worked_example():
+    """Algorithm 2 on the hand-derived path example (fixture with derivation)."""
+    rows = _read_golden("path9_C048_sweep.txt")
+    g = graphgen.path(9)
+    out = oracle.estimate_all(g, [0, 4, 8], sweep=True)
+    t_est, t_err = tiny.sweep(tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx), [0, 4, 8])
+    for node, en, ed, rn, rd in rows:
+        assert out["S_sweep"][node] == en / ed, node
+        assert abs(out["S_sweep_err"][node] - rn / rd) <= 1e-15 * max(1.0, rn / rd), node
+        assert t_est[node] == Fraction(int(en), int(ed)) and t_err[node] == Fraction(int(rn), int(rd)), node
+    for node in range(g.n):  # the single-node entry point agrees
+        a, e = oracle.node_sweep(g, [0, 4, 8], node)
+        assert a == out["S_sweep"][node] and e == out["S_sweep_err"][node]
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_sweep_vs_bruteforce(seed):
+    """Against explicit-set exact arithmetic on small graphs of every kind
+    (distance ties included): the chosen error is the exact minimum over the
+    candidates and the estimate is that of a candidate attaining it."""
+    rng = np.random.default_rng(1700 + seed)
+    n = int(rng.integers(3, 24))
+    directed = seed % 4 == 3
+    g = graphgen.gnp(n, float(rng.uniform(0.15, 0.5)), 1700 + seed, directed=directed,
+                     wmax=[1, 9, 1, 5][seed % 4])
+    if g.n < 3:
+        pytest.skip("component too small")
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    rg = None
+    if directed:
+        d = tiny.round_trip(d)
+        rg = graphgen.transpose(g)
+    if any(x == tiny.INF for r in d for x in r):
+        pytest.skip("not connected")
+    k = int(rng.integers(1, g.n + 1))
+    samples = [int(x) for x in rng.permutation(g.n)[:k]]
+    out = oracle.estimate_all(g, samples, reverse_graph=rg, sweep=True)
+    S = [sum(r) for r in d]
+    for v in range(g.n):
+        if v in samples:
+            assert out["S_sweep"][v] == S[v] and out["S_sweep_err"][v] == 0.0
+            continue
+        cand = tiny.sweep_candidates(d, samples, v)
+        best = min(e for _, e in cand)
+        assert abs(out["S_sweep_err"][v] - float(best)) <= 1e-12 * max(1.0, float(best)), v
+        assert any(e == best and abs(out["S_sweep"][v] - float(s)) <= 1e-12 * float(s) for s, e in cand), v
+
+
+def test_sweep_single_sample_is_pivoting():
+    """k = 1: the threshold T = 0 puts only the sample in L and nothing in HC,
+    so its error is 0 and its estimate sums d(c,u) over u != v plus d(v,c),
+    which is S(c) on an undirected graph: the sweep returns S_piv, error 0."""
+    for g in (graphgen.ba(60, 2, seed=5), graphgen.grid(8, 6, 4), graphgen.grid(7, 7, 8, 0.1, 1, 50, seed=3)):
+        for s in (0, g.n // 2):
+            out = oracle.estimate_all(g, [s], sweep=True)
+            un = np.arange(g.n) != s
+            assert (out["S_sweep"][un] == out["S_piv"][un].astype(np.float64)).all()
+            assert (out["S_sweep_err"][un] == 0).all()
+
+
+def test_sweep_special_cases():
+    # K_n: T = 0 leaves HC with no pivot error and |L| = 1: the exact n - 1
+    g = graphgen.complete(10)
+    out = oracle.estimate_all(g, [2, 5, 9], sweep=True)
+    assert (out["S_sweep"] == 9.0).all() and (out["S_sweep_err"] == 0).all()
+    # k = n: every node sampled -> exact, error 0
+    g = graphgen.ba(40, 2, seed=3)
+    out = oracle.estimate_all(g, list(range(g.n)), sweep=True)
+    assert (out["S_sweep"] == oracle.exact_sums(g)).all() and (out["S_sweep_err"] == 0).all()
+
+
+def test_sweep_never_worse_than_pivoting():
+    """Pure pivoting is a candidate: the chosen error never exceeds its error,
+    (sum_i (d(v,c_i) - d(c,c_i))^2 / k) * (n-1-k), evaluated here from D."""
+    g = graphgen.rmat(8, 8, seed=6)
+    samples = oracle.draw_samples(g.n, 20, 4)
+    out = oracle.estimate_all(g, samples, sweep=True)
+    D, dmat, piv = out["D"].astype(np.int64), out["dmat"].astype(np.int64), out["pivot"]
+    k, n = len(samples), g.n
+    pure = ((D - dmat[piv]) ** 2).sum(axis=1) / k * (n - 1 - k)
+    un = np.ones(n, bool)
+    un[samples] = False
+    assert (out["S_sweep_err"][un] <= pure[un] * (1 + 1e-12)).all()
+    assert (out["S_sweep_err"] >= 0).all()
