@@ -145,10 +145,22 @@ typedef struct {
      *             0.5, 0.99} (the list of Sec. 8) the hybrid estimate and its
      *             estimated error; the estimate with the smallest error (the first
      *             in this order on ties)
-     *   S_ad_err  its estimated squared error */
+     *   S_ad_err  its estimated squared error
+     * Algorithm 2 / Sec. 4.2, adaptive error minimisation (n entries each; the
+     * exact sum and 0 on sampled nodes):
+     *   S_sweep      for an unsampled v with pivot c: the candidates are pure
+     *                pivoting (S(c), error (sum_i (d(v,c_i) - d(c,c_i))^2 / k) *
+     *                (n-1-k)) and, for every distinct distance T from c to a sample,
+     *                increasing, the estimate with L = {u != v : d(c,u) <= T}, HC the
+     *                samples beyond T, H the other nodes beyond T (v itself is in
+     *                none of them), Eq. (6)'s form, and its Sec. 4.1 error; the
+     *                candidate with the smallest error (the first on ties)
+     *   S_sweep_err  its estimated squared error */
     double* S_err;
     double* S_ad;
     double* S_ad_err;
+    double* S_sweep;
+    double* S_sweep_err;
 } cc_result;
 
 /* Synchronous estimate; `out` holds HOST pointers. */

@@ -45,7 +45,7 @@ class cc_params(ctypes.Structure):
 
 
 _RESULT_FIELDS = ["S_hyb", "S_samp", "S_piv", "S_pub", "pivot", "delta", "sampsum", "src_sum", "samples",
-                  "dmat", "D", "S_err", "S_ad", "S_ad_err"]
+                  "dmat", "D", "S_err", "S_ad", "S_ad_err", "S_sweep", "S_sweep_err"]
 
 
 class cc_result(ctypes.Structure):
@@ -76,6 +76,7 @@ _FIELD_SPEC = {
     "pivot": (np.int32, "n"), "delta": (np.int32, "n"), "sampsum": (np.int64, "n"), "src_sum": (np.int64, "k"),
     "samples": (np.int32, "k"), "dmat": (np.int32, "kk"), "D": (np.int32, "nk"),
     "S_err": (np.float64, "n"), "S_ad": (np.float64, "n"), "S_ad_err": (np.float64, "n"),
+    "S_sweep": (np.float64, "n"), "S_sweep_err": (np.float64, "n"),
 }
 
 _lib = None

@@ -734,6 +734,8 @@ void fill_epilogue_outputs(EpilogueArgs& ea, const cc_result* out, int64_t* src_
     ea.S_err = out->S_err;
     ea.S_ad = out->S_ad;
     ea.S_ad_err = out->S_ad_err;
+    ea.S_sweep = out->S_sweep;
+    ea.S_sweep_err = out->S_sweep_err;
     ea.S_hyb = out->S_hyb;
     ea.S_samp = out->S_samp;
     ea.S_piv = out->S_piv;
@@ -842,7 +844,10 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                                          (uint64_t)(uintptr_t)out->S_pub, (uint64_t)(uintptr_t)out->pivot,
                                          (uint64_t)(uintptr_t)out->delta, (uint64_t)(uintptr_t)out->sampsum,
                                          (uint64_t)(uintptr_t)out->src_sum, (uint64_t)(uintptr_t)out->dmat,
-                                         (uint64_t)(uintptr_t)out->D, (uint64_t)gr->tune.alpha,
+                                         (uint64_t)(uintptr_t)out->D, (uint64_t)(uintptr_t)out->S_err,
+                                         (uint64_t)(uintptr_t)out->S_ad, (uint64_t)(uintptr_t)out->S_ad_err,
+                                         (uint64_t)(uintptr_t)out->S_sweep, (uint64_t)(uintptr_t)out->S_sweep_err,
+                                         (uint64_t)gr->tune.alpha,
                                          (uint64_t)gr->tune.level_blocks, (uint64_t)gr->tune.scatter_blocks};
         };
         if (want_graph) {
@@ -999,8 +1004,11 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ba.S_err = out->S_err;
             ba.S_ad = out->S_ad;
             ba.S_ad_err = out->S_ad_err;
-            const bool want_err = out->S_err || out->S_ad || out->S_ad_err;
-            ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0);
+            ba.S_sweep = out->S_sweep;
+            ba.S_sweep_err = out->S_sweep_err;
+            const bool want_sweep = out->S_sweep || out->S_sweep_err;
+            const bool want_err = out->S_err || out->S_ad || out->S_ad_err || want_sweep;
+            ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0, want_sweep);
             ba_scratch = ba_es <= trav_scratch ? ts : L.arena2.get(ba_es);
             run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
         } else {
@@ -1017,7 +1025,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ea.eps_num = r.en;
             ea.eps_den = r.ed;
             fill_epilogue_outputs(ea, out, src_sum, dmat);
-            const size_t es = epilogue_scratch(n, k, ea.maxd, false);
+            const size_t es = epilogue_scratch(n, k, ea.maxd, false, out->S_sweep || out->S_sweep_err);
             run_epilogue(st, ea, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
         }
         if (out->samples)
@@ -1159,6 +1167,8 @@ struct Staging {
         add(host->S_err, sizeof(double) * n);
         add(host->S_ad, sizeof(double) * n);
         add(host->S_ad_err, sizeof(double) * n);
+        add(host->S_sweep, sizeof(double) * n);
+        add(host->S_sweep_err, sizeof(double) * n);
         size_t total = 0;
         for (auto& f : fields) total += Carver::sz(f.bytes);
         if (total) {
@@ -1189,6 +1199,8 @@ struct Staging {
         dev.S_err = (double*)dptr(host->S_err);
         dev.S_ad = (double*)dptr(host->S_ad);
         dev.S_ad_err = (double*)dptr(host->S_ad_err);
+        dev.S_sweep = (double*)dptr(host->S_sweep);
+        dev.S_sweep_err = (double*)dptr(host->S_sweep_err);
         return CC_OK;
     }
     void copy_back(hipStream_t st) {
@@ -1399,8 +1411,9 @@ cc_status run_batch(cc_context* ctx, std::vector<BatchItem>& items, Lane& L, cc_
         if (rc != 0) return fail(CC_EDISCONNECTED, "a graph of the batch is not connected");
         size_t es = 0;
         for (auto& it : items) {
-            const bool want_err = it.out->S_err || it.out->S_ad || it.out->S_ad_err;
-            es = std::max(es, bits_epilogue_scratch(it.r->k, lm, want_err ? it.g->dg.n : 0));
+            const bool want_sweep = it.out->S_sweep || it.out->S_sweep_err;
+            const bool want_err = it.out->S_err || it.out->S_ad || it.out->S_ad_err || want_sweep;
+            es = std::max(es, bits_epilogue_scratch(it.r->k, lm, want_err ? it.g->dg.n : 0, want_sweep));
         }
         void* escr = L.arena2.get(es);
         size_t loff = 0;
@@ -1435,6 +1448,8 @@ cc_status run_batch(cc_context* ctx, std::vector<BatchItem>& items, Lane& L, cc_
             ba.S_err = out->S_err;
             ba.S_ad = out->S_ad;
             ba.S_ad_err = out->S_ad_err;
+            ba.S_sweep = out->S_sweep;
+            ba.S_sweep_err = out->S_sweep_err;
             ba.node_off = it.node_off;
             ba.word_off = it.word_off;
             ba.row_words = W;

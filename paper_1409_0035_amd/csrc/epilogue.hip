@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_errest(
             const uint64_t dd = (uint64_t)d * d;
             const int64_t diff = (int64_t)d - dl;
             const uint64_t ee = (uint64_t)(diff * diff);
-            big = big || d >= (1u << 27) || dl >= (1 << 27);  // squares summed over k <= 4096 stay below 2^63
+            big = big || d >= (1u << 25) || dl >= (1 << 25);  // squares summed over k <= 4096 stay below 2^62
 #pragma unroll
             for (int e = 0; e < kErrEps; e++) {
                 if (e >= E.count) break;
@@ -688,6 +688,196 @@ __global__ __launch_bounds__(kBlock) void k_errest(
         any_ovf = any_ovf || ovf;
     }
     if (any_ovf) flags->overflow = 1;
+}
+
+// Algorithm 2 / Sec. 4.2 (threshold sweep), step 1: each sample's row of the
+// sample distance matrix in increasing order -- perm[p][j] is the sample of
+// rank j by distance from c_p (index order among equal distances), ds[p][j]
+// that distance.  One block per sample; bitonic sort of the keys
+// (distance << 12 | index) in LDS, k2 = the power of two >= k (<= 4096).
+template <typename MT>
+__global__ __launch_bounds__(kBlock) void k_sort_rows(const MT* __restrict__ dmat_c, int32_t k, int32_t k2,
+                                                      uint16_t* __restrict__ perm, MT* __restrict__ ds) {
+    extern __shared__ uint64_t skey[];
+    const int64_t p = blockIdx.x;
+    for (int32_t i = threadIdx.x; i < k2; i += kBlock)
+        skey[i] = i < k ? ((uint64_t)dmat_c[p * k + i] << 12) | (uint64_t)i : ~0ull;
+    __syncthreads();
+    for (int32_t size = 2; size <= k2; size <<= 1) {
+        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int32_t t = threadIdx.x; t < k2 / 2; t += kBlock) {
+                const int32_t lo = 2 * t - (t & (stride - 1));  // pairs (lo, lo + stride), bit `stride` of lo clear
+                const int32_t hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t a = skey[lo], b = skey[hi];
+                if ((a > b) == up) {
+                    skey[lo] = b;
+                    skey[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int32_t j = threadIdx.x; j < k; j += kBlock) {
+        const uint64_t x = skey[j];
+        perm[p * k + j] = (uint16_t)(x & 0xFFF);
+        ds[p * k + j] = (MT)(x >> 12);
+    }
+}
+
+// Step 2, one wavefront per node v outside C.  Candidates, compared in this
+// order: pure pivoting, S(c_p) with error (sum_i (d(v,c_i) - d(c_p,c_i))^2 / k)
+// * (n-1-k); then, for every distinct distance T from the pivot c_p to a
+// sample, increasing, the estimate of the threshold T over V \ {v}:
+//   L = {u : d(c_p,u) <= T}, HC = samples beyond T, H = other nodes beyond T,
+//   N = (sum_H d(c_p,u) + sum_HC d(v,u)) * |L cap C| + |L| * sum_{L cap C} d(v,u),
+//   estimate N / |L cap C|, error as in Sec. 4.1 with these sets.
+// |H| and sum_H come from the tail tables at T + 1, less v itself when
+// Delta > T (v lies beyond T from its pivot but is no term of its own sum);
+// |L| = n-1-|H|-|HC|.  The smallest error wins, the first candidate on ties.
+// Lane l walks the sorted ranks [l*P, l*P + P): a first pass sums its ranks,
+// a wave scan gives each lane the sums of the ranks before it, a second pass
+// evaluates the candidates at the last rank of each distinct distance; a wave
+// reduction picks (error, rank).
+template <typename DT, bool RT, typename MT>
+__global__ __launch_bounds__(kBlock) void k_sweep(
+    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
+    int32_t bit_base, const int32_t* __restrict__ orig, const uint16_t* __restrict__ perm, const MT* __restrict__ ds,
+    const int32_t* __restrict__ Tcnt, const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum,
+    double* S_sweep, double* S_sweep_err, DevFlags* flags) {
+    const int64_t LIM = (int64_t)1 << 53;
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    const int32_t P = (k + 63) / 64;
+    const int32_t j0 = lane * P < k ? lane * P : k;
+    const int32_t j1 = j0 + P < k ? j0 + P : k;
+    bool ovf = false;
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); v < n; v += nwaves) {
+        const int64_t o = orig[v];
+        const int32_t js = sidx[v];
+        if (js >= 0) {  // a sample: its exact sum, no error
+            if (lane == 0) {
+                if (S_sweep) S_sweep[o] = (double)src_sum[js - bit_base];
+                if (S_sweep_err) S_sweep_err[o] = 0.0;
+            }
+            continue;
+        }
+        const int64_t row = v * k;
+        // pivot (lowest index among the nearest samples), Delta, row sum
+        uint32_t best = 0xFFFFFFFFu;
+        int32_t bi = k;
+        int64_t sum = 0;
+        for (int32_t i = lane; i < k; i += 64) {
+            const uint32_t d = dist_at<DT, RT>(D, Dr, row + i);
+            if (d < best) {
+                best = d;
+                bi = i;
+            }
+            sum += d;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t ob = __shfl_xor(best, off);
+            const int32_t oi = __shfl_xor(bi, off);
+            if (ob < best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        sum = wave_sum64(sum);
+        const int32_t p = bi;
+        const int64_t delta = best;
+        const uint16_t* pr = perm + (int64_t)p * k;
+        const MT* dr = ds + (int64_t)p * k;
+        // pass 1: this lane's sums over its ranks
+        int64_t a1 = 0;
+        uint64_t a2 = 0, ae = 0;
+        bool big = false;
+        for (int32_t j = j0; j < j1; j++) {
+            const uint32_t d = dist_at<DT, RT>(D, Dr, row + pr[j]);
+            const int64_t dl = dr[j];
+            big = big || d >= (1u << 25) || dl >= (1 << 25);  // squares summed over k <= 4096 stay below 2^62
+            const int64_t df = (int64_t)d - dl;
+            a1 += d;
+            a2 += (uint64_t)d * d;
+            ae += (uint64_t)(df * df);
+        }
+        int64_t s1 = a1;
+        uint64_t s2 = a2, se = ae;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y1 = __shfl_up(s1, off);
+            const uint64_t y2 = __shfl_up(s2, off), ye = __shfl_up(se, off);
+            if (lane >= off) {
+                s1 += y1;
+                s2 += y2;
+                se += ye;
+            }
+        }
+        const uint64_t sq_all = __shfl(se, 63);
+        int64_t c1 = s1 - a1;  // sums over the ranks before this lane's
+        uint64_t c2 = s2 - a2, ce = se - ae;
+        // pass 2: the candidates whose threshold is a distance of this lane's ranks
+        double lerr = __builtin_inf(), lest = 0.0;
+        int32_t lpos = k;
+        bool eo = false;
+        for (int32_t j = j0; j < j1; j++) {
+            const uint32_t d = dist_at<DT, RT>(D, Dr, row + pr[j]);
+            const int64_t dl = dr[j];
+            const int64_t df = (int64_t)d - dl;
+            c1 += d;
+            c2 += (uint64_t)d * d;
+            ce += (uint64_t)(df * df);
+            if (j + 1 < k && (int64_t)dr[j + 1] == dl) continue;  // not the last rank at this distance
+            const int64_t lc = j + 1;
+            const int64_t hcnum = k - lc;
+            const int64_t hcsum = sum - c1;
+            const uint64_t hcsq = sq_all - ce;
+            int64_t hnum = 0, hsum = 0;
+            if (dl + 1 < tlen) {
+                hnum = Tcnt[(int64_t)p * tlen + dl + 1];
+                hsum = Tsum[(int64_t)p * tlen + dl + 1];
+            }
+            if (dl < delta) {  // v itself is beyond T
+                hnum -= 1;
+                hsum -= delta;
+            }
+            const int64_t lnum = (n - 1) - hnum - hcnum;
+            int64_t t1 = 0, t2 = 0, N = 0, vn1 = 0, vn2 = 0, varnum = 0;
+            bool e = __builtin_mul_overflow(hsum + hcsum, lc, &t1) || __builtin_mul_overflow(c1, lnum, &t2) ||
+                     __builtin_add_overflow(t1, t2, &N) || N >= LIM || lnum < lc || hnum < 0;
+            e = e || __builtin_mul_overflow(lc, (int64_t)c2, &vn1) || __builtin_mul_overflow(c1, c1, &vn2) ||
+                __builtin_sub_overflow(vn1, vn2, &varnum);
+            eo = eo || e;
+            const double est = (double)N / (double)lc;
+            const double tL = ((double)varnum / (double)(lc * lc * lc)) * (double)lnum;
+            const double tH = hcnum > 0 ? ((double)(int64_t)hcsq / (double)hcnum) * (double)hnum : 0.0;
+            const double err = tL + tH;
+            if (err < lerr) {
+                lerr = err;
+                lest = est;
+                lpos = j;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double oe = __shfl_xor(lerr, off), os = __shfl_xor(lest, off);
+            const int32_t op = __shfl_xor(lpos, off);
+            if (oe < lerr || (oe == lerr && op < lpos)) {
+                lerr = oe;
+                lest = os;
+                lpos = op;
+            }
+        }
+        const double pure = ((double)(int64_t)sq_all / (double)k) * (double)(n - 1 - k);
+        if (lane == 0) {
+            const bool thr = lerr < pure;
+            if (S_sweep) S_sweep[o] = thr ? lest : (double)src_sum[p];
+            if (S_sweep_err) S_sweep_err[o] = thr ? lerr : pure;
+        }
+        ovf = ovf || big || eo || src_sum[p] >= LIM;
+    }
+    if (ovf) flags->overflow = 1;
 }
 
 template <typename DT, bool RT>
@@ -803,7 +993,7 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         hipLaunchKernelGGL((k_to_i32<DT, RT>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, (const DT*)a.D,
                            (const DT*)a.Dr, a.orig, n, k, a.Dout);
     }
-    if (a.S_err || a.S_ad || a.S_ad_err) {
+    if (a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err) {
         ErrArgs ea;
         ea.D = a.D;
         ea.Dr = a.Dr;
@@ -823,6 +1013,10 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         ea.S_err = a.S_err;
         ea.S_ad = a.S_ad;
         ea.S_ad_err = a.S_ad_err;
+        ea.S_sweep = a.S_sweep;
+        ea.S_sweep_err = a.S_sweep_err;
+        // after the tables above and the histogram this pass may have counted
+        ea.sweep_scratch = p + (a.hist_done ? 0 : align256(sizeof(int32_t) * k * (maxd + 1)));
         run_errest(st, ea, flags);
     }
 }
@@ -849,10 +1043,26 @@ void errest_t(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
         E.den[E.count] = kAdaptiveEpsDen[e];
         E.count++;
     }
-    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((a.n + kBlock - 1) / kBlock, 4096));
-    hipLaunchKernelGGL((k_errest<DT, RT, MT>), dim3((unsigned)g), dim3(kBlock), 0, st, (const DT*)a.D, (const DT*)a.Dr,
-                       a.n, a.k, a.sidx, a.bit_base, a.orig, (const MT*)a.dmat_c, a.Tcnt, a.Tsum, a.tlen, a.src_sum, E,
-                       a.S_err, a.S_ad, a.S_ad_err, flags);
+    if (a.S_err || a.S_ad || a.S_ad_err) {
+        const int64_t g = std::max<int64_t>(1, std::min<int64_t>((a.n + kBlock - 1) / kBlock, 4096));
+        hipLaunchKernelGGL((k_errest<DT, RT, MT>), dim3((unsigned)g), dim3(kBlock), 0, st, (const DT*)a.D,
+                           (const DT*)a.Dr, a.n, a.k, a.sidx, a.bit_base, a.orig, (const MT*)a.dmat_c, a.Tcnt, a.Tsum,
+                           a.tlen, a.src_sum, E, a.S_err, a.S_ad, a.S_ad_err, flags);
+    }
+    if (a.S_sweep || a.S_sweep_err) {
+        if (!a.sweep_scratch) throw HipError{hipErrorInvalidValue, "threshold sweep scratch"};
+        const int32_t k = a.k;
+        int32_t k2 = 1;
+        while (k2 < k) k2 <<= 1;
+        uint16_t* perm = (uint16_t*)a.sweep_scratch;
+        MT* ds = (MT*)((char*)a.sweep_scratch + align256(sizeof(uint16_t) * (size_t)k * k));
+        hipLaunchKernelGGL((k_sort_rows<MT>), dim3((unsigned)k), dim3(kBlock), sizeof(uint64_t) * (size_t)k2, st,
+                           (const MT*)a.dmat_c, k, k2, perm, ds);
+        const int64_t g = std::max<int64_t>(1, std::min<int64_t>((a.n + 3) / 4, 16384));
+        hipLaunchKernelGGL((k_sweep<DT, RT, MT>), dim3((unsigned)g), dim3(kBlock), 0, st, (const DT*)a.D,
+                           (const DT*)a.Dr, a.n, k, a.sidx, a.bit_base, a.orig, (const uint16_t*)perm, (const MT*)ds,
+                           a.Tcnt, a.Tsum, a.tlen, a.src_sum, a.S_sweep, a.S_sweep_err, flags);
+    }
 }
 
 template <typename DT, bool RT>
@@ -872,8 +1082,12 @@ void errest_r(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
 
 }  // namespace
 
+size_t sweep_scratch_bytes(int32_t k) {
+    return align256(sizeof(uint16_t) * (size_t)k * k) + align256(sizeof(uint32_t) * (size_t)k * k);
+}
+
 void run_errest(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
-    if (!a.S_err && !a.S_ad && !a.S_ad_err) return;
+    if (!a.S_err && !a.S_ad && !a.S_ad_err && !a.S_sweep && !a.S_sweep_err) return;
     switch (a.dk) {
         case DistKind::U8: errest_r<uint8_t>(st, a, flags); break;
         case DistKind::U16: errest_r<uint16_t>(st, a, flags); break;
@@ -922,17 +1136,18 @@ size_t suffix_chunk_scratch(int32_t k, int64_t maxd) {
     return sizeof(int64_t) * 2 * (size_t)k * (size_t)nchunks + 256;
 }
 
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done) {
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool sweep) {
     const int64_t tlen = maxd + 2;
     size_t s = align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
                align256(sizeof(uint32_t) * (size_t)k * k) + align256(suffix_chunk_scratch(k, maxd)) + 1024;
     if (!hist_done) s += align256(sizeof(int32_t) * k * (maxd + 1));
+    if (sweep) s += sweep_scratch_bytes(k);
     (void)n;
     return s;
 }
 
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags) {
-    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done))
+    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done, a.S_sweep || a.S_sweep_err))
         throw HipError{hipErrorOutOfMemory, "epilogue scratch"};
     const bool rt = a.Dr != nullptr;
     switch (a.dk) {

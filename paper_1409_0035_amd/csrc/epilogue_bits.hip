@@ -318,9 +318,10 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
                                n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
         }
     }
-    if (a.S_err || a.S_ad || a.S_ad_err) {
-        // Sec. 4 needs each sample's distance row: materialise it (after the
-        // tables above in the scratch), then the shared error pass
+    if (a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err) {
+        // Sec. 4 and the threshold sweep need each node's distance row:
+        // materialise it (after the tables above in the scratch), then the
+        // shared error pass; the sweep's tables follow the rows
         char* dq = (char*)lmask + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W);
         ErrArgs ea;
         ea.D = dq;
@@ -340,6 +341,10 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
         ea.S_err = a.S_err;
         ea.S_ad = a.S_ad;
         ea.S_ad_err = a.S_ad_err;
+        ea.S_sweep = a.S_sweep;
+        ea.S_sweep_err = a.S_sweep_err;
+        const size_t db = lmax < 255 ? 1 : (lmax < 65535 ? 2 : 4);
+        ea.sweep_scratch = dq + align256((size_t)n * k * db);
         if (lmax < 255) {
             ea.dk = DistKind::U8;
             hipLaunchKernelGGL((k_materialize_words<W, uint8_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
@@ -392,18 +397,20 @@ void materialize_w(hipStream_t st, const uint64_t* snap, size_t plane, int32_t l
 
 }  // namespace
 
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows) {
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows, bool sweep) {
     const int64_t tlen = (int64_t)lmax + 2;
     const int W = (k + 63) / 64;
     const size_t db = lmax < 255 ? 1 : (lmax < 65535 ? 2 : 4);
     return align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
            align256(sizeof(uint32_t) * (size_t)k * k) + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W) +
-           align256((size_t)err_rows * k * db) + 1024;
+           align256((size_t)err_rows * k * db) + (sweep ? sweep_scratch_bytes(k) : 0) + 1024;
 }
 
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size,
                        DevFlags* flags) {
-    if (scratch_size < bits_epilogue_scratch(a.k, a.lmax)) throw HipError{hipErrorOutOfMemory, "bits epilogue scratch"};
+    const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
+    if (scratch_size < bits_epilogue_scratch(a.k, a.lmax, want_err ? a.n : 0, a.S_sweep || a.S_sweep_err))
+        throw HipError{hipErrorOutOfMemory, "bits epilogue scratch"};
     switch ((a.k + 63) / 64) {
         case 1: bits_mt<1>(st, a, scratch, flags); break;
         case 2: bits_mt<2>(st, a, scratch, flags); break;

@@ -419,8 +419,13 @@ struct EpilogueArgs {
     double* S_err = nullptr;     // Sec. 4 outputs (optional)
     double* S_ad = nullptr;
     double* S_ad_err = nullptr;
+    double* S_sweep = nullptr;   // Algorithm 2 / Sec. 4.2 outputs (optional)
+    double* S_sweep_err = nullptr;
 };
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done);
+// bytes of the threshold-sweep tables (each sample's sorted row of the sample
+// distance matrix), added to an epilogue's scratch when the sweep is wanted
+size_t sweep_scratch_bytes(int32_t k);
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool sweep = false);
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
 void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* sidx, int64_t n);
 
@@ -458,6 +463,8 @@ struct BitsEpilogueArgs {
     double* S_err = nullptr;     // Sec. 4 outputs (optional)
     double* S_ad = nullptr;
     double* S_ad_err = nullptr;
+    double* S_sweep = nullptr;   // Algorithm 2 / Sec. 4.2 outputs (optional)
+    double* S_sweep_err = nullptr;
     // this graph's part of a batch's shared rows (defaults: the whole rows)
     int64_t node_off = 0;   // first row of this graph's nodes
     int32_t word_off = 0;   // first word of its samples in a row
@@ -465,7 +472,7 @@ struct BitsEpilogueArgs {
     int32_t bit_base = 0;   // its first sample's index in sidx and in the histogram rows
     int32_t hist_rows = 0;  // histogram rows per slot (0: k)
 };
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows = 0);
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows = 0, bool sweep = false);
 
 // The eps values the experiments (Sec. 8) choose from per node for the
 // adaptive hybrid estimate: 0.001, 0.025, 0.05, 0.1, 0.2, 0.5, 0.99.
@@ -473,7 +480,8 @@ constexpr int32_t kAdaptiveEps = 7;
 constexpr int64_t kAdaptiveEpsNum[kAdaptiveEps] = {1, 1, 1, 1, 1, 1, 99};
 constexpr int64_t kAdaptiveEpsDen[kAdaptiveEps] = {1000, 40, 20, 10, 5, 2, 100};
 
-// Inputs of the error-estimate pass (Sec. 4) over distance rows.
+// Inputs of the error-estimate pass (Sec. 4) and the threshold sweep
+// (Algorithm 2) over distance rows.
 struct ErrArgs {
     const void* D = nullptr;    // node-major rows, dk bytes per entry
     const void* Dr = nullptr;   // reverse rows (round trip) or null
@@ -493,6 +501,9 @@ struct ErrArgs {
     double* S_err = nullptr;
     double* S_ad = nullptr;
     double* S_ad_err = nullptr;
+    double* S_sweep = nullptr;       // threshold sweep (Algorithm 2)
+    double* S_sweep_err = nullptr;
+    void* sweep_scratch = nullptr;   // sweep_scratch_bytes(k), when the sweep is wanted
 };
 void run_errest(hipStream_t st, const ErrArgs& a, DevFlags* flags);
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);

@@ -88,7 +88,8 @@ def test_fullsize_sampled(ctx, name):
     if name != "grid2048w":
         gh = ctx.upload(g)
         try:
-            errs = cc.cc_estimate(ctx.handle, gh, k, seed=seed, outputs=("S_err", "S_ad", "S_ad_err"))
+            errs = cc.cc_estimate(ctx.handle, gh, k, seed=seed,
+                                  outputs=("S_err", "S_ad", "S_ad_err", "S_sweep", "S_sweep_err"))
         finally:
             ctx.release(gh)
     else:
@@ -100,6 +101,8 @@ def test_fullsize_sampled(ctx, name):
             assert errs["S_err"][v] == (0.0 if o.sampled else o.S_err), v
             a, ae, _ = oracle.node_adaptive(g, samples, int(v), reverse_graph=rg)
             assert errs["S_ad"][v] == a and errs["S_ad_err"][v] == ae, v
+            a, ae = oracle.node_sweep(g, samples, int(v), reverse_graph=rg)
+            assert errs["S_sweep"][v] == a and errs["S_sweep_err"][v] == ae, v
         assert res["pivot"][v] == o.pivot, v
         assert res["delta"][v] == o.delta, v
         assert res["sampsum"][v] == o.sampsum, v

@@ -21,8 +21,12 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _outputs(torch, n):
-    return {f: torch.empty(n, dtype=getattr(torch, dt), device="cuda") for f, dt in FIELDS.items()}
+ERR_FIELDS = {"S_err": "float64", "S_ad": "float64", "S_ad_err": "float64", "S_sweep": "float64",
+              "S_sweep_err": "float64"}
+
+
+def _outputs(torch, n, fields=FIELDS):
+    return {f: torch.empty(n, dtype=getattr(torch, dt), device="cuda") for f, dt in fields.items()}
 
 
 @pytest.mark.parametrize("make,k", [(lambda: graphgen.ba(5000, 4, seed=3), 64),
@@ -70,4 +74,34 @@ def test_host_outputs_accept_graph_flag():
         with pytest.raises(cc.CCError) as e:
             cc.cc_estimate(ctx.handle, gh, 40, mode=cc.CC_PLAIN | cc.CC_GRAPH, seed=4)
         assert e.value.status == cc.CC_EINVAL
+        ctx.release(gh)
+
+
+def test_replays_with_error_outputs():
+    """Calls that alternate between two output sets -- with and without the
+    Sec. 4 and threshold-sweep outputs -- replay their own captures: each
+    set is keyed separately and every replay matches an eager estimate."""
+    import torch
+    g = graphgen.rmat(12, 16, seed=6)
+    k = 96
+    both = {**FIELDS, **ERR_FIELDS}
+    with cc.Context(0) as ctx:
+        gh = ctx.upload(g)
+        s = torch.cuda.Stream()
+        plain_out, err_out = _outputs(torch, g.n), _outputs(torch, g.n, both)
+        ref_plain, ref_err = _outputs(torch, g.n), _outputs(torch, g.n, both)
+        replays = 0
+        for it, (seed, which) in enumerate([(1, 0), (1, 1), (1, 0), (1, 1), (2, 1), (2, 0), (2, 1)]):
+            out, ref, fields = (plain_out, ref_plain, FIELDS) if which == 0 else (err_out, ref_err, both)
+            _say(f"  call {it} seed {seed} {'errors' if which else 'plain'}")
+            for t in out.values():
+                t.fill_(-1)
+            cc.cc_estimate_device(ctx.handle, gh, k, out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=seed, stream=s)
+            replays += cc.cc_last_timing(ctx.handle)["launches"] == 1
+            cc.cc_estimate_device(ctx.handle, gh, k, ref, mode=cc.CC_BATCHED, seed=seed, stream=s)
+            s.synchronize()
+            for f in fields:
+                assert torch.equal(out[f], ref[f]), (it, seed, f)
+        _say(f"  replays: {replays}")
+        assert replays >= 3
         ctx.release(gh)
