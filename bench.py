@@ -186,6 +186,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, launch one float32 copy kernel of MIB MiB (read MIB, write MIB) so "
                          "that counter passes can scale FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--outputs", choices=("hybrid", "errors", "sweep"), default="hybrid",
+                    help="what each step computes besides the Sec. 2 estimates: nothing (default), the Sec. 4 "
+                         "error estimates and adaptive estimate, or the threshold sweep of Algorithm 2")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by sample "
@@ -218,6 +221,9 @@ def main():
         "delta": torch.empty(g.n, dtype=torch.int32, device=dev),
         "sampsum": torch.empty(g.n, dtype=torch.int64, device=dev),
     }
+    extra = {"hybrid": (), "errors": ("S_err", "S_ad", "S_ad_err"), "sweep": ("S_sweep", "S_sweep_err")}
+    for f in extra[args.outputs]:
+        out[f] = torch.empty(g.n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
     tuning = cc.cc_graph_get_tuning(gh)
@@ -292,7 +298,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64 bitmask / int32 dist / int64 sums",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {g.name} n={g.n} m={m} k={k} batched", "n": g.n, "m": m,
-                   "k": k, "eps": f"1/{int(round(math.sqrt(k)))}", "graph_replay": use_graph},
+                   "k": k, "eps": f"1/{int(round(math.sqrt(k)))}", "graph_replay": use_graph,
+                   "outputs": args.outputs},
         "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
         "plain": plain,
         "speedup_vs_plain": None if plain is None else round(gteps / plain["gteps"], 2),

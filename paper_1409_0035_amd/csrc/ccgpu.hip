@@ -1006,9 +1006,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ba.S_ad_err = out->S_ad_err;
             ba.S_sweep = out->S_sweep;
             ba.S_sweep_err = out->S_sweep_err;
-            const bool want_sweep = out->S_sweep || out->S_sweep_err;
-            const bool want_err = out->S_err || out->S_ad || out->S_ad_err || want_sweep;
-            ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0, want_sweep);
+            const bool want_err = out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err;
+            ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0, want_err);
             ba_scratch = ba_es <= trav_scratch ? ts : L.arena2.get(ba_es);
             run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
         } else {
@@ -1025,7 +1024,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ea.eps_num = r.en;
             ea.eps_den = r.ed;
             fill_epilogue_outputs(ea, out, src_sum, dmat);
-            const size_t es = epilogue_scratch(n, k, ea.maxd, false, out->S_sweep || out->S_sweep_err);
+            const size_t es = epilogue_scratch(
+                n, k, ea.maxd, false, out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err);
             run_epilogue(st, ea, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
         }
         if (out->samples)
@@ -1411,9 +1411,9 @@ cc_status run_batch(cc_context* ctx, std::vector<BatchItem>& items, Lane& L, cc_
         if (rc != 0) return fail(CC_EDISCONNECTED, "a graph of the batch is not connected");
         size_t es = 0;
         for (auto& it : items) {
-            const bool want_sweep = it.out->S_sweep || it.out->S_sweep_err;
-            const bool want_err = it.out->S_err || it.out->S_ad || it.out->S_ad_err || want_sweep;
-            es = std::max(es, bits_epilogue_scratch(it.r->k, lm, want_err ? it.g->dg.n : 0, want_sweep));
+            const bool want_err =
+                it.out->S_err || it.out->S_ad || it.out->S_ad_err || it.out->S_sweep || it.out->S_sweep_err;
+            es = std::max(es, bits_epilogue_scratch(it.r->k, lm, want_err ? it.g->dg.n : 0, want_err));
         }
         void* escr = L.arena2.get(es);
         size_t loff = 0;

@@ -576,128 +576,17 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     if (any_unreached) flags->disconnected = 1;
 }
 
-// Sec. 4: the estimated squared error of the hybrid estimate for the call's
-// eps, and the adaptive estimate -- for each eps of a fixed list, the hybrid
-// estimate and its estimated error, the first smallest error kept.  One lane
-// per node, one pass over its distance row for all eps at once.  For one eps,
-// with L cap C = {i : dmat[p][i] * num <= Delta * den} and HC the other
-// samples:
-//   err = ((LCnum * LCsumsq - LCsum^2) / LCnum^3) * Lnum + (HCsqerr / HCnum) * Hnum
-// (second term 0 without HC), HCsqerr = sum over HC of (d(v,c_i) - d(c_p,c_i))^2,
-// in exactly this order of double operations on exact integers.
-constexpr int kErrEps = 8;  // the call's eps + up to 7 listed ones
-struct ErrEps {
-    int32_t count;  // entries used; entry 0 is the call's eps
-    int64_t num[kErrEps], den[kErrEps];
-};
-
-template <typename DT, bool RT, typename MT>
-__global__ __launch_bounds__(kBlock) void k_errest(
-    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
-    int32_t bit_base, const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
-    const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum, ErrEps E, double* S_err,
-    double* S_ad, double* S_ad_err, DevFlags* flags) {
-    const int64_t LIM = (int64_t)1 << 53;
-    bool any_ovf = false;
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
-        const int64_t o = orig[v];
-        const int32_t js = sidx[v];
-        if (js >= 0) {  // a sample: its exact sum, no error
-            if (S_err) S_err[o] = 0.0;
-            if (S_ad) S_ad[o] = (double)src_sum[js - bit_base];
-            if (S_ad_err) S_ad_err[o] = 0.0;
-            continue;
-        }
-        uint32_t best = 0xFFFFFFFFu;
-        int32_t p = 0;
-        int64_t sum = 0;
-        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
-            if (d < best) {
-                best = d;
-                p = i;
-            }
-            sum += d;
-        });
-        const int64_t delta = best;
-        const MT* drow = dmat_c + (int64_t)p * k;
-        int32_t lcnum[kErrEps];
-        int64_t lcsum[kErrEps];
-        uint64_t lcsq[kErrEps], hcsq[kErrEps];
-#pragma unroll
-        for (int e = 0; e < kErrEps; e++) {
-            lcnum[e] = 0;
-            lcsum[e] = 0;
-            lcsq[e] = 0;
-            hcsq[e] = 0;
-        }
-        bool big = false;
-        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
-            const int64_t dl = drow[i];
-            const uint64_t dd = (uint64_t)d * d;
-            const int64_t diff = (int64_t)d - dl;
-            const uint64_t ee = (uint64_t)(diff * diff);
-            big = big || d >= (1u << 25) || dl >= (1 << 25);  // squares summed over k <= 4096 stay below 2^62
-#pragma unroll
-            for (int e = 0; e < kErrEps; e++) {
-                if (e >= E.count) break;
-                if (dl * E.num[e] <= delta * E.den[e]) {
-                    lcnum[e] += 1;
-                    lcsum[e] += d;
-                    lcsq[e] += dd;
-                } else {
-                    hcsq[e] += ee;
-                }
-            }
-        });
-        bool ovf = big;
-        double ad = 0.0, ad_err = 0.0, err0 = 0.0;
-#pragma unroll
-        for (int e = 0; e < kErrEps; e++) {
-            if (e >= E.count) break;
-            const int64_t thr = delta * E.den[e];
-            const int64_t tix = thr / E.num[e] + 1;  // d > floor(Delta/eps)  <=>  d >= tix
-            int64_t hnum = 0, hsum = 0;
-            if (tix < tlen) {
-                hnum = Tcnt[(int64_t)p * tlen + tix];
-                hsum = Tsum[(int64_t)p * tlen + tix];
-            }
-            const int64_t lc = lcnum[e];
-            const int64_t hcnum = k - lc;
-            const int64_t hcsum = sum - lcsum[e];
-            const int64_t lnum = (n - 1) - hnum - hcnum;
-            int64_t t1 = 0, t2 = 0, N = 0, vn1 = 0, vn2 = 0, varnum = 0;
-            bool eo = __builtin_mul_overflow(hsum + hcsum, lc, &t1) || __builtin_mul_overflow(lcsum[e], lnum, &t2) ||
-                      __builtin_add_overflow(t1, t2, &N) || N >= LIM || lc < 1 || lnum < lc;
-            eo = eo || __builtin_mul_overflow(lc, (int64_t)lcsq[e], &vn1) ||
-                 __builtin_mul_overflow(lcsum[e], lcsum[e], &vn2) || __builtin_sub_overflow(vn1, vn2, &varnum);
-            ovf = ovf || eo;
-            const double est = (double)N / (double)lc;
-            const double tL = ((double)varnum / (double)(lc * lc * lc)) * (double)lnum;
-            const double tH = hcnum > 0 ? ((double)(int64_t)hcsq[e] / (double)hcnum) * (double)hnum : 0.0;
-            const double err = tL + tH;
-            if (e == 0) {
-                err0 = err;
-            } else if (e == 1 || err < ad_err) {
-                ad = est;
-                ad_err = err;
-            }
-        }
-        if (S_err) S_err[o] = err0;
-        if (S_ad) S_ad[o] = ad;
-        if (S_ad_err) S_ad_err[o] = ad_err;
-        any_ovf = any_ovf || ovf;
-    }
-    if (any_ovf) flags->overflow = 1;
-}
-
-// Algorithm 2 / Sec. 4.2 (threshold sweep), step 1: each sample's row of the
-// sample distance matrix in increasing order -- perm[p][j] is the sample of
-// rank j by distance from c_p (index order among equal distances), ds[p][j]
-// that distance.  One block per sample; bitonic sort of the keys
-// (distance << 12 | index) in LDS, k2 = the power of two >= k (<= 4096).
+// Sec. 4 / Algorithm 2 (Sec. 4.2), step 1: each sample's row of the sample
+// distance matrix in increasing order -- perm[p][j] is the sample of rank j
+// by distance from c_p (index order among equal distances), ds[p][j] that
+// distance (32-bit whatever the width of dmat_c); rows of kp = k rounded up
+// to 8 entries, padded with index 0 and distance ~0.  One block per sample;
+// bitonic sort of the keys (distance << 12 | index) in LDS, k2 = the power of
+// two >= k (<= 4096).
 template <typename MT>
 __global__ __launch_bounds__(kBlock) void k_sort_rows(const MT* __restrict__ dmat_c, int32_t k, int32_t k2,
-                                                      uint16_t* __restrict__ perm, MT* __restrict__ ds) {
+                                                      int32_t kp, uint32_t* __restrict__ perm,
+                                                      uint32_t* __restrict__ ds) {
     extern __shared__ uint64_t skey[];
     const int64_t p = blockIdx.x;
     for (int32_t i = threadIdx.x; i < k2; i += kBlock)
@@ -718,166 +607,384 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(const MT* __restrict__ dma
             __syncthreads();
         }
     }
-    for (int32_t j = threadIdx.x; j < k; j += kBlock) {
-        const uint64_t x = skey[j];
-        perm[p * k + j] = (uint16_t)(x & 0xFFF);
-        ds[p * k + j] = (MT)(x >> 12);
+    for (int32_t j = threadIdx.x; j < kp; j += kBlock) {
+        const uint64_t x = j < k ? skey[j] : ~0ull;
+        perm[p * kp + j] = j < k ? (uint32_t)(x & 0xFFF) : 0u;
+        ds[p * kp + j] = j < k ? (uint32_t)(x >> 12) : ~0u;
     }
 }
 
-// Step 2, one wavefront per node v outside C.  Candidates, compared in this
-// order: pure pivoting, S(c_p) with error (sum_i (d(v,c_i) - d(c_p,c_i))^2 / k)
-// * (n-1-k); then, for every distinct distance T from the pivot c_p to a
-// sample, increasing, the estimate of the threshold T over V \ {v}:
-//   L = {u : d(c_p,u) <= T}, HC = samples beyond T, H = other nodes beyond T,
-//   N = (sum_H d(c_p,u) + sum_HC d(v,u)) * |L cap C| + |L| * sum_{L cap C} d(v,u),
-//   estimate N / |L cap C|, error as in Sec. 4.1 with these sets.
-// |H| and sum_H come from the tail tables at T + 1, less v itself when
-// Delta > T (v lies beyond T from its pivot but is no term of its own sum);
-// |L| = n-1-|H|-|HC|.  The smallest error wins, the first candidate on ties.
-// Lane l walks the sorted ranks [l*P, l*P + P): a first pass sums its ranks,
-// a wave scan gives each lane the sums of the ranks before it, a second pass
-// evaluates the candidates at the last rank of each distinct distance; a wave
-// reduction picks (error, rank).
-template <typename DT, bool RT, typename MT>
-__global__ __launch_bounds__(kBlock) void k_sweep(
-    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
-    int32_t bit_base, const int32_t* __restrict__ orig, const uint16_t* __restrict__ perm, const MT* __restrict__ ds,
-    const int32_t* __restrict__ Tcnt, const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum,
-    double* S_sweep, double* S_sweep_err, DevFlags* flags) {
+// Sec. 4 and Algorithm 2 (Sec. 4.2): every candidate estimate has Eq. (6)'s
+// form with L cap C a prefix of the samples ranked by distance from the
+// node's pivot c_p (k_sort_rows), so all of them come from prefix sums along
+// those ranks.  With LC the first lc ranks, HC the others and H, |H| the
+// nodes outside C beyond the candidate's threshold:
+//   N   = (sum_H d(c_p,u) + sum_HC d(v,c_i)) * lc + |L| * sum_LC d(v,c_i), estimate N / lc
+//   err = ((lc * sum_LC d^2 - (sum_LC d)^2) / lc^3) * |L| + (sum_HC (d - d_p)^2 / |HC|) * |H|
+// (second term 0 without HC), |L| = n-1-|H|-|HC|, in exactly this order of
+// double operations on exact integers (d = d(v,c_i), d_p = d(c_p,c_i)).
+//   * hybrid, eps = num/den (the call's, then each of the adaptive list): LC =
+//     {i : d_p <= floor(Delta*den/num)}, H beyond that threshold (tail tables);
+//     S_err is the call's error, S_ad the first smallest error over the list.
+//   * threshold sweep: pure pivoting, S(c_p) with error (sum_i (d - d_p)^2 / k)
+//     * (n-1-k), then for every distinct d_p = T, increasing, LC = the ranks at
+//     distance <= T and H the nodes outside C beyond T other than v itself
+//     (beyond T when Delta > T); the smallest error wins, the first on ties.
+// The ranks, and so the candidate thresholds, depend on the pivot alone:
+// nodes are grouped by pivot and a wavefront takes up to 64 nodes of one
+// pivot, one per lane, walking the ranks in step (uniform loads of the sorted
+// row, uniform tail lookups, every lane evaluating its own node's candidate
+// at each distinct distance).  Each lane's distance row is staged in LDS when
+// 64 rows fit.
+constexpr int kErrEps = 8;             // the call's eps + up to 7 listed ones
+constexpr int kErrBucketBlocks = 512;  // blocks of the bucketing kernels
+struct ErrEps {
+    int32_t count;  // entries used; entry 0 is the call's eps
+    int64_t num[kErrEps], den[kErrEps];
+};
+
+__device__ __forceinline__ void prefix_candidate(int64_t n, int32_t k, int64_t lc, int64_t lcsum, uint64_t lcsq,
+                                                 int64_t hcsum, uint64_t hcsq, int64_t hnum, int64_t hsum,
+                                                 double& est, double& err, bool& eo) {
     const int64_t LIM = (int64_t)1 << 53;
-    const int lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    const int32_t P = (k + 63) / 64;
-    const int32_t j0 = lane * P < k ? lane * P : k;
-    const int32_t j1 = j0 + P < k ? j0 + P : k;
-    bool ovf = false;
-    for (int64_t v = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); v < n; v += nwaves) {
-        const int64_t o = orig[v];
+    const int64_t hcnum = k - lc;
+    const int64_t lnum = (n - 1) - hnum - hcnum;
+    int64_t t1 = 0, t2 = 0, N = 0, vn1 = 0, vn2 = 0, varnum = 0;
+    bool e = __builtin_mul_overflow(hsum + hcsum, lc, &t1) || __builtin_mul_overflow(lcsum, lnum, &t2) ||
+             __builtin_add_overflow(t1, t2, &N) || N >= LIM || lc < 1 || lnum < lc || hnum < 0;
+    e = e || __builtin_mul_overflow(lc, (int64_t)lcsq, &vn1) || __builtin_mul_overflow(lcsum, lcsum, &vn2) ||
+        __builtin_sub_overflow(vn1, vn2, &varnum);
+    eo = eo || e;
+    est = (double)N / (double)lc;
+    const double tL = ((double)varnum / (double)(lc * lc * lc)) * (double)lnum;
+    const double tH = hcnum > 0 ? ((double)(int64_t)hcsq / (double)hcnum) * (double)hnum : 0.0;
+    err = tL + tH;
+}
+
+// Per node: the pivot of an unsampled node (lowest index among the nearest
+// samples), its row sum and its total squared pivot error
+// sum_i (d(v,c_i) - d(c_p,c_i))^2; sampled nodes get their outputs here (the
+// exact sum, error 0) and pivot -1.  Each block counts its nodes per pivot in
+// LDS, keeps its counts (bcnt[block][p]) and adds them to the totals: one
+// global atomic per (block, pivot) instead of one per node on a few hot
+// pivots.
+template <typename DT, bool RT, typename MT>
+__global__ __launch_bounds__(kBlock) void k_err_pivot(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n,
+                                                      int32_t k, const int32_t* __restrict__ sidx, int32_t bit_base,
+                                                      const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c,
+                                                      const int64_t* __restrict__ src_sum, int32_t* __restrict__ piv,
+                                                      int64_t* __restrict__ vsum, uint64_t* __restrict__ vsq,
+                                                      int32_t* __restrict__ cnt, int32_t* __restrict__ bcnt,
+                                                      double* S_err, double* S_ad, double* S_ad_err, double* S_sweep,
+                                                      double* S_sweep_err, DevFlags* flags) {
+    extern __shared__ int32_t lcnt[];
+    bool big = false;
+    for (int32_t p = threadIdx.x; p < k; p += kBlock) lcnt[p] = 0;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
         const int32_t js = sidx[v];
-        if (js >= 0) {  // a sample: its exact sum, no error
-            if (lane == 0) {
-                if (S_sweep) S_sweep[o] = (double)src_sum[js - bit_base];
-                if (S_sweep_err) S_sweep_err[o] = 0.0;
-            }
+        if (js >= 0) {
+            const int64_t o = orig[v];
+            const double ex = (double)src_sum[js - bit_base];
+            if (S_err) S_err[o] = 0.0;
+            if (S_ad) S_ad[o] = ex;
+            if (S_ad_err) S_ad_err[o] = 0.0;
+            if (S_sweep) S_sweep[o] = ex;
+            if (S_sweep_err) S_sweep_err[o] = 0.0;
+            piv[v] = -1;
             continue;
         }
-        const int64_t row = v * k;
-        // pivot (lowest index among the nearest samples), Delta, row sum
         uint32_t best = 0xFFFFFFFFu;
-        int32_t bi = k;
+        int32_t p = 0;
         int64_t sum = 0;
-        for (int32_t i = lane; i < k; i += 64) {
-            const uint32_t d = dist_at<DT, RT>(D, Dr, row + i);
+        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
             if (d < best) {
                 best = d;
-                bi = i;
+                p = i;
             }
             sum += d;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint32_t ob = __shfl_xor(best, off);
-            const int32_t oi = __shfl_xor(bi, off);
-            if (ob < best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        sum = wave_sum64(sum);
-        const int32_t p = bi;
-        const int64_t delta = best;
-        const uint16_t* pr = perm + (int64_t)p * k;
-        const MT* dr = ds + (int64_t)p * k;
-        // pass 1: this lane's sums over its ranks
-        int64_t a1 = 0;
-        uint64_t a2 = 0, ae = 0;
-        bool big = false;
-        for (int32_t j = j0; j < j1; j++) {
-            const uint32_t d = dist_at<DT, RT>(D, Dr, row + pr[j]);
-            const int64_t dl = dr[j];
+        });
+        const MT* drow = dmat_c + (int64_t)p * k;
+        uint64_t sq = 0;
+        for_row<DT, RT>(D, Dr, v, k, [&](int32_t i, uint32_t d) {
+            const int64_t dl = drow[i];
             big = big || d >= (1u << 25) || dl >= (1 << 25);  // squares summed over k <= 4096 stay below 2^62
             const int64_t df = (int64_t)d - dl;
-            a1 += d;
-            a2 += (uint64_t)d * d;
-            ae += (uint64_t)(df * df);
-        }
-        int64_t s1 = a1;
-        uint64_t s2 = a2, se = ae;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int64_t y1 = __shfl_up(s1, off);
-            const uint64_t y2 = __shfl_up(s2, off), ye = __shfl_up(se, off);
-            if (lane >= off) {
-                s1 += y1;
-                s2 += y2;
-                se += ye;
-            }
-        }
-        const uint64_t sq_all = __shfl(se, 63);
-        int64_t c1 = s1 - a1;  // sums over the ranks before this lane's
-        uint64_t c2 = s2 - a2, ce = se - ae;
-        // pass 2: the candidates whose threshold is a distance of this lane's ranks
-        double lerr = __builtin_inf(), lest = 0.0;
-        int32_t lpos = k;
-        bool eo = false;
-        for (int32_t j = j0; j < j1; j++) {
-            const uint32_t d = dist_at<DT, RT>(D, Dr, row + pr[j]);
-            const int64_t dl = dr[j];
-            const int64_t df = (int64_t)d - dl;
-            c1 += d;
-            c2 += (uint64_t)d * d;
-            ce += (uint64_t)(df * df);
-            if (j + 1 < k && (int64_t)dr[j + 1] == dl) continue;  // not the last rank at this distance
-            const int64_t lc = j + 1;
-            const int64_t hcnum = k - lc;
-            const int64_t hcsum = sum - c1;
-            const uint64_t hcsq = sq_all - ce;
-            int64_t hnum = 0, hsum = 0;
-            if (dl + 1 < tlen) {
-                hnum = Tcnt[(int64_t)p * tlen + dl + 1];
-                hsum = Tsum[(int64_t)p * tlen + dl + 1];
-            }
-            if (dl < delta) {  // v itself is beyond T
-                hnum -= 1;
-                hsum -= delta;
-            }
-            const int64_t lnum = (n - 1) - hnum - hcnum;
-            int64_t t1 = 0, t2 = 0, N = 0, vn1 = 0, vn2 = 0, varnum = 0;
-            bool e = __builtin_mul_overflow(hsum + hcsum, lc, &t1) || __builtin_mul_overflow(c1, lnum, &t2) ||
-                     __builtin_add_overflow(t1, t2, &N) || N >= LIM || lnum < lc || hnum < 0;
-            e = e || __builtin_mul_overflow(lc, (int64_t)c2, &vn1) || __builtin_mul_overflow(c1, c1, &vn2) ||
-                __builtin_sub_overflow(vn1, vn2, &varnum);
-            eo = eo || e;
-            const double est = (double)N / (double)lc;
-            const double tL = ((double)varnum / (double)(lc * lc * lc)) * (double)lnum;
-            const double tH = hcnum > 0 ? ((double)(int64_t)hcsq / (double)hcnum) * (double)hnum : 0.0;
-            const double err = tL + tH;
-            if (err < lerr) {
-                lerr = err;
-                lest = est;
-                lpos = j;
-            }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double oe = __shfl_xor(lerr, off), os = __shfl_xor(lest, off);
-            const int32_t op = __shfl_xor(lpos, off);
-            if (oe < lerr || (oe == lerr && op < lpos)) {
-                lerr = oe;
-                lest = os;
-                lpos = op;
-            }
-        }
-        const double pure = ((double)(int64_t)sq_all / (double)k) * (double)(n - 1 - k);
-        if (lane == 0) {
-            const bool thr = lerr < pure;
-            if (S_sweep) S_sweep[o] = thr ? lest : (double)src_sum[p];
-            if (S_sweep_err) S_sweep_err[o] = thr ? lerr : pure;
-        }
-        ovf = ovf || big || eo || src_sum[p] >= LIM;
+            sq += (uint64_t)(df * df);
+        });
+        piv[v] = p;
+        vsum[v] = sum;
+        vsq[v] = sq;
+        atomicAdd(&lcnt[p], 1);
     }
-    if (ovf) flags->overflow = 1;
+    if (big) flags->overflow = 1;
+    __syncthreads();
+    for (int32_t p = threadIdx.x; p < k; p += kBlock) {
+        const int32_t c = lcnt[p];
+        bcnt[(int64_t)blockIdx.x * k + p] = c;
+        if (c) atomicAdd(&cnt[p], c);
+    }
+}
+
+// One block: exclusive prefix sums of the per-pivot counts (node offsets) and
+// of ceil(count / 64) (wavefront tasks), each with its total at entry k.
+__global__ __launch_bounds__(kBlock) void k_err_buckets(const int32_t* __restrict__ cnt, int32_t k,
+                                                        int32_t* __restrict__ start, int32_t* __restrict__ tstart) {
+    __shared__ int32_t wa[kBlock / 64], wb[kBlock / 64];
+    const int32_t per = (k + kBlock - 1) / kBlock;
+    const int32_t lo = threadIdx.x * per;
+    int32_t sa = 0, sb = 0;
+    for (int32_t i = lo; i < lo + per && i < k; i++) {
+        sa += cnt[i];
+        sb += (cnt[i] + 63) / 64;
+    }
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    int32_t ia = sa, ib = sb;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t ya = __shfl_up(ia, off), yb = __shfl_up(ib, off);
+        if (lane >= off) {
+            ia += ya;
+            ib += yb;
+        }
+    }
+    if (lane == 63) {
+        wa[wave] = ia;
+        wb[wave] = ib;
+    }
+    __syncthreads();
+    int32_t ba = 0, bb = 0;
+    for (int w = 0; w < wave; w++) {
+        ba += wa[w];
+        bb += wb[w];
+    }
+    int32_t ra = ba + ia - sa, rb = bb + ib - sb;  // exclusive
+    for (int32_t i = lo; i < lo + per && i < k; i++) {
+        start[i] = ra;
+        tstart[i] = rb;
+        ra += cnt[i];
+        rb += (cnt[i] + 63) / 64;
+    }
+    if (threadIdx.x == kBlock - 1) {
+        start[k] = ra;
+        tstart[k] = rb;
+    }
+}
+
+// Places the nodes in their pivot's bucket: the same blocks over the same
+// nodes as k_err_pivot reserve their share of each bucket with one atomic per
+// pivot, then hand out slots from LDS (order within a bucket is arbitrary).
+__global__ __launch_bounds__(kBlock) void k_err_fill(const int32_t* __restrict__ piv, int64_t n, int32_t k,
+                                                     const int32_t* __restrict__ start,
+                                                     const int32_t* __restrict__ bcnt, int32_t* __restrict__ fill,
+                                                     int32_t* __restrict__ order) {
+    extern __shared__ int32_t lpos[];
+    for (int32_t p = threadIdx.x; p < k; p += kBlock) {
+        const int32_t c = bcnt[(int64_t)blockIdx.x * k + p];
+        lpos[p] = c ? start[p] + atomicAdd(&fill[p], c) : 0;
+    }
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+        const int32_t p = piv[v];
+        if (p >= 0) order[atomicAdd(&lpos[p], 1)] = (int32_t)v;
+    }
+}
+
+// One wavefront (block of 64) per task: up to 64 unsampled nodes of one
+// pivot.  AT: the prefix accumulators' type (32-bit when every square and
+// its sum over k <= 4096 ranks fits, as for distances below 2^9).
+template <typename DT, bool RT, bool STAGED, typename AT>
+__global__ __launch_bounds__(64) void k_errsweep(
+    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, int32_t kp,
+    const int32_t* __restrict__ orig, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ ds,
+    const int64_t* __restrict__ vsum, const uint64_t* __restrict__ vsq, const int32_t* __restrict__ cnt,
+    const int32_t* __restrict__ start, const int32_t* __restrict__ tstart, const int32_t* __restrict__ order,
+    int32_t stride, const int32_t* __restrict__ Tcnt, const int64_t* __restrict__ Tsum, int64_t tlen,
+    const int64_t* __restrict__ src_sum, ErrEps E, double* S_err, double* S_ad, double* S_ad_err, double* S_sweep,
+    double* S_sweep_err, DevFlags* flags) {
+    extern __shared__ uint32_t stage_words[];
+    const int32_t task = blockIdx.x;
+    if (task >= tstart[k]) return;
+    // the pivot whose tasks include this one: the last p with tstart[p] <= task
+    int32_t lo = 0, hi = k - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (tstart[mid] <= task) lo = mid;
+        else hi = mid - 1;
+    }
+    const int32_t p = __builtin_amdgcn_readfirstlane(lo);
+    const int lane = threadIdx.x;
+    const int32_t first = start[p] + (task - tstart[p]) * 64;
+    const bool active = first + lane < start[p] + cnt[p];
+    const int64_t v = active ? order[first + lane] : 0;
+    const int64_t row = v * k;
+    const bool want_eps = S_err || S_ad || S_ad_err;
+    const bool want_sw = S_sweep || S_sweep_err;
+    const DT* srow = nullptr;
+    const DT* srow_r = nullptr;
+    if (STAGED) {
+        // this lane's row (and reverse row) into its LDS slot
+        uint8_t* slot = (uint8_t*)stage_words + (size_t)lane * stride;
+        const int32_t bytes = k * (int32_t)sizeof(DT);
+        if (active) {
+            const uint8_t* g = (const uint8_t*)(D + row);
+            const uint8_t* gr = RT ? (const uint8_t*)(Dr + row) : nullptr;
+            if (bytes % 16 == 0) {
+                for (int32_t b = 0; b < bytes; b += 16) {
+                    const uint4 x = *(const uint4*)(g + b);
+                    uint32_t* w = (uint32_t*)(slot + b);
+                    w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+                    if (RT) {
+                        const uint4 y = *(const uint4*)(gr + b);
+                        uint32_t* wr = (uint32_t*)(slot + bytes + b);
+                        wr[0] = y.x; wr[1] = y.y; wr[2] = y.z; wr[3] = y.w;
+                    }
+                }
+            } else {
+                for (int32_t i = 0; i < k; i++) {
+                    ((DT*)slot)[i] = D[row + i];
+                    if (RT) ((DT*)(slot + bytes))[i] = Dr[row + i];
+                }
+            }
+        }
+        srow = (const DT*)slot;
+        srow_r = (const DT*)(slot + bytes);
+    }
+    // every lane reads its own slot (or row 0 of D when inactive): in bounds
+    // without a branch; inactive lanes then see 0
+    auto dist = [&](int32_t i) -> uint32_t {
+        uint32_t a;
+        if (STAGED) {
+            a = (uint32_t)srow[i];
+            if (RT) a += (uint32_t)srow_r[i];
+        } else {
+            a = dist_at<DT, RT>(D, Dr, row + i);
+        }
+        return active ? a : 0u;
+    };
+    const uint32_t* pr = perm + (int64_t)p * kp;
+    const uint32_t* dr = ds + (int64_t)p * kp;
+    const int32_t* tc = Tcnt + (int64_t)p * tlen;
+    const int64_t* ts = Tsum + (int64_t)p * tlen;
+    // the sorted row in groups of kRun ranks: uniform loads first, then the
+    // lanes' row reads, then the arithmetic
+    constexpr int kRun = 8;
+    uint32_t ri[kRun], rd[kRun];
+    int64_t rl[kRun];
+    auto load_run = [&](int32_t j0) {  // rows are padded to a multiple of kRun
+#pragma unroll
+        for (int t = 0; t < kRun; t++) {
+            ri[t] = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)pr[j0 + t]);
+            rl[t] = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)dr[j0 + t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kRun; t++) rd[t] = dist((int32_t)ri[t]);
+    };
+    // the row sum and the total squared pivot error, from the pivot pass
+    const int64_t sum = active ? vsum[v] : 0;
+    const uint64_t sq_all = active ? vsq[v] : 0;
+    const int64_t delta = dist(p);
+    // the hybrid thresholds floor(Delta/eps), their tails, and the prefix
+    // state at each one's candidate rank
+    int64_t thr[kErrEps], ehn[kErrEps], ehs[kErrEps], elc[kErrEps], ec1[kErrEps];
+    uint64_t ec2[kErrEps], ece[kErrEps];
+#pragma unroll
+    for (int e = 0; e < kErrEps; e++) {
+        thr[e] = -1;
+        ehn[e] = ehs[e] = elc[e] = ec1[e] = 0;
+        ec2[e] = ece[e] = 0;
+        if (want_eps && e < E.count) {
+            thr[e] = delta * E.den[e] / E.num[e];
+            if (thr[e] + 1 < tlen) {
+                ehn[e] = tc[thr[e] + 1];
+                ehs[e] = ts[thr[e] + 1];
+            }
+        }
+    }
+    // prefix sums along the ranks; candidates at each distinct distance
+    using UAT = typename std::make_unsigned<AT>::type;
+    AT c1 = 0;
+    UAT c2 = 0, ce = 0;
+    double berr = __builtin_inf(), best_est = 0.0;
+    bool eo = false;
+    for (int32_t j0 = 0; j0 < k; j0 += kRun) {
+        load_run(j0);
+        const int64_t after =
+            j0 + kRun < k ? (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)dr[j0 + kRun]) : INT64_MAX;
+#pragma unroll
+        for (int t = 0; t < kRun; t++) {
+            const int32_t j = j0 + t;
+            if (j >= k) break;  // uniform
+            const int64_t dl = rl[t];
+            const int64_t nx = j + 1 < k ? (t + 1 < kRun ? rl[t + 1] : after) : INT64_MAX;
+            const uint32_t d = rd[t];
+            const AT df = (AT)d - (AT)dl;
+            c1 += (AT)d;
+            c2 += (UAT)d * (UAT)d;
+            ce += (UAT)(df * df);
+            if (nx == dl) continue;  // not the last rank at this distance (uniform)
+            const int64_t lc = j + 1;
+            if (want_sw) {
+                int64_t hn = 0, hs = 0;
+                if (dl + 1 < tlen) {
+                    hn = tc[dl + 1];
+                    hs = ts[dl + 1];
+                }
+                if (dl < delta) {  // v itself is beyond T
+                    hn -= 1;
+                    hs -= delta;
+                }
+                double est, err;
+                prefix_candidate(n, k, lc, (int64_t)c1, (uint64_t)c2, sum - (int64_t)c1, sq_all - (uint64_t)ce, hn,
+                                 hs, est, err, eo);
+                if (err < berr) {
+                    berr = err;
+                    best_est = est;
+                }
+            }
+            if (want_eps) {
+#pragma unroll
+                for (int e = 0; e < kErrEps; e++) {
+                    if (dl <= thr[e] && thr[e] < nx) {
+                        elc[e] = lc;
+                        ec1[e] = (int64_t)c1;
+                        ec2[e] = (uint64_t)c2;
+                        ece[e] = (uint64_t)ce;
+                    }
+                }
+            }
+        }
+    }
+    if (!active) return;
+    const int64_t o = orig[v];
+    if (want_eps) {
+        double err0 = 0.0, ad = 0.0, ad_err = 0.0;
+#pragma unroll
+        for (int e = 0; e < kErrEps; e++) {
+            if (e < E.count) {
+                double est, err;
+                prefix_candidate(n, k, elc[e], ec1[e], ec2[e], sum - ec1[e], sq_all - ece[e], ehn[e], ehs[e], est,
+                                 err, eo);
+                if (e == 0) {
+                    err0 = err;
+                } else if (e == 1 || err < ad_err) {
+                    ad = est;
+                    ad_err = err;
+                }
+            }
+        }
+        if (S_err) S_err[o] = err0;
+        if (S_ad) S_ad[o] = ad;
+        if (S_ad_err) S_ad_err[o] = ad_err;
+    }
+    if (want_sw) {
+        const double pure = ((double)(int64_t)sq_all / (double)k) * (double)(n - 1 - k);
+        const bool thr_wins = berr < pure;
+        if (S_sweep) S_sweep[o] = thr_wins ? best_est : (double)src_sum[p];
+        if (S_sweep_err) S_sweep_err[o] = thr_wins ? berr : pure;
+        eo = eo || src_sum[p] >= ((int64_t)1 << 53);
+    }
+    if (eo) flags->overflow = 1;
 }
 
 template <typename DT, bool RT>
@@ -1032,6 +1139,16 @@ void epilogue_mt(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags*
 
 namespace {
 
+// LDS bytes per lane for a staged row (and reverse row): a multiple of 4
+// with an odd number of words, so that lanes reading the same offset of their
+// rows hit different banks
+inline int32_t stage_stride(int32_t k, int dt_bytes, bool rt) {
+    int32_t b = k * dt_bytes * (rt ? 2 : 1);
+    b = (b + 3) & ~3;
+    if ((b / 4) % 2 == 0) b += 4;
+    return b;
+}
+
 template <typename DT, bool RT, typename MT>
 void errest_t(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
     ErrEps E{};
@@ -1043,26 +1160,56 @@ void errest_t(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
         E.den[E.count] = kAdaptiveEpsDen[e];
         E.count++;
     }
-    if (a.S_err || a.S_ad || a.S_ad_err) {
-        const int64_t g = std::max<int64_t>(1, std::min<int64_t>((a.n + kBlock - 1) / kBlock, 4096));
-        hipLaunchKernelGGL((k_errest<DT, RT, MT>), dim3((unsigned)g), dim3(kBlock), 0, st, (const DT*)a.D,
-                           (const DT*)a.Dr, a.n, a.k, a.sidx, a.bit_base, a.orig, (const MT*)a.dmat_c, a.Tcnt, a.Tsum,
-                           a.tlen, a.src_sum, E, a.S_err, a.S_ad, a.S_ad_err, flags);
-    }
-    if (a.S_sweep || a.S_sweep_err) {
-        if (!a.sweep_scratch) throw HipError{hipErrorInvalidValue, "threshold sweep scratch"};
-        const int32_t k = a.k;
-        int32_t k2 = 1;
-        while (k2 < k) k2 <<= 1;
-        uint16_t* perm = (uint16_t*)a.sweep_scratch;
-        MT* ds = (MT*)((char*)a.sweep_scratch + align256(sizeof(uint16_t) * (size_t)k * k));
-        hipLaunchKernelGGL((k_sort_rows<MT>), dim3((unsigned)k), dim3(kBlock), sizeof(uint64_t) * (size_t)k2, st,
-                           (const MT*)a.dmat_c, k, k2, perm, ds);
-        const int64_t g = std::max<int64_t>(1, std::min<int64_t>((a.n + 3) / 4, 16384));
-        hipLaunchKernelGGL((k_sweep<DT, RT, MT>), dim3((unsigned)g), dim3(kBlock), 0, st, (const DT*)a.D,
-                           (const DT*)a.Dr, a.n, k, a.sidx, a.bit_base, a.orig, (const uint16_t*)perm, (const MT*)ds,
-                           a.Tcnt, a.Tsum, a.tlen, a.src_sum, a.S_sweep, a.S_sweep_err, flags);
-    }
+    if (!a.sweep_scratch) throw HipError{hipErrorInvalidValue, "error-estimate scratch"};
+    const int32_t k = a.k;
+    const int64_t n = a.n;
+    char* q = (char*)a.sweep_scratch;
+    const int32_t kp = (k + 7) & ~7;
+    uint32_t* perm = (uint32_t*)q;
+    q += align256(sizeof(uint32_t) * (size_t)k * kp);
+    uint32_t* ds = (uint32_t*)q;
+    q += align256(sizeof(uint32_t) * (size_t)k * kp);
+    int32_t* piv = (int32_t*)q;
+    q += align256(sizeof(int32_t) * (size_t)n);
+    int64_t* vsum = (int64_t*)q;
+    q += align256(sizeof(int64_t) * (size_t)n);
+    uint64_t* vsq = (uint64_t*)q;
+    q += align256(sizeof(uint64_t) * (size_t)n);
+    int32_t* bcnt = (int32_t*)q;  // per block of the bucketing kernels: its count per pivot
+    q += align256(sizeof(int32_t) * (size_t)kErrBucketBlocks * k);
+    int32_t* order = (int32_t*)q;
+    q += align256(sizeof(int32_t) * (size_t)n);
+    int32_t* cnt = (int32_t*)q;  // cnt, fill: k each; start, tstart: k + 1 each
+    int32_t* fill = cnt + k;
+    int32_t* start = fill + k;
+    int32_t* tstart = start + (k + 1);
+    int32_t k2 = 1;
+    while (k2 < k) k2 <<= 1;
+    hipLaunchKernelGGL((k_sort_rows<MT>), dim3((unsigned)k), dim3(kBlock), sizeof(uint64_t) * (size_t)k2, st,
+                       (const MT*)a.dmat_c, k, k2, kp, perm, ds);
+    fill_u32(st, cnt, 0u, (size_t)2 * k);
+    const unsigned bb = grid_for(n, kErrBucketBlocks);
+    hipLaunchKernelGGL((k_err_pivot<DT, RT, MT>), dim3(bb), dim3(kBlock), sizeof(int32_t) * (size_t)k, st,
+                       (const DT*)a.D, (const DT*)a.Dr, n, k, a.sidx, a.bit_base, a.orig, (const MT*)a.dmat_c,
+                       a.src_sum, piv, vsum, vsq, cnt, bcnt, a.S_err, a.S_ad, a.S_ad_err, a.S_sweep, a.S_sweep_err,
+                       flags);
+    hipLaunchKernelGGL(k_err_buckets, dim3(1), dim3(kBlock), 0, st, (const int32_t*)cnt, k, start, tstart);
+    hipLaunchKernelGGL(k_err_fill, dim3(bb), dim3(kBlock), sizeof(int32_t) * (size_t)k, st, (const int32_t*)piv, n, k,
+                       (const int32_t*)start, (const int32_t*)bcnt, fill, order);
+    // tasks: at most one partial wavefront per pivot beyond n / 64 full ones
+    const unsigned tasks = (unsigned)((n + 63) / 64 + k);
+    const int32_t stride = stage_stride(k, (int)sizeof(DT), RT);
+    const size_t lds = (size_t)64 * stride;
+    using AT = typename std::conditional<sizeof(DT) == 1, int32_t, int64_t>::type;  // d < 2^9: squares fit 32 bits
+#define CCG_ERRSWEEP(STG, LDSB)                                                                                        \
+    hipLaunchKernelGGL((k_errsweep<DT, RT, STG, AT>), dim3(tasks), dim3(64), LDSB, st, (const DT*)a.D, (const DT*)a.Dr, \
+                       n, k, kp, a.orig, (const uint32_t*)perm, (const uint32_t*)ds, (const int64_t*)vsum,             \
+                       (const uint64_t*)vsq, (const int32_t*)cnt,                                                     \
+                       (const int32_t*)start, (const int32_t*)tstart, (const int32_t*)order, stride, a.Tcnt, a.Tsum,  \
+                       a.tlen, a.src_sum, E, a.S_err, a.S_ad, a.S_ad_err, a.S_sweep, a.S_sweep_err, flags)
+    if (lds <= 32 * 1024) CCG_ERRSWEEP(true, lds);
+    else CCG_ERRSWEEP(false, 0);
+#undef CCG_ERRSWEEP
 }
 
 template <typename DT, bool RT>
@@ -1082,8 +1229,11 @@ void errest_r(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
 
 }  // namespace
 
-size_t sweep_scratch_bytes(int32_t k) {
-    return align256(sizeof(uint16_t) * (size_t)k * k) + align256(sizeof(uint32_t) * (size_t)k * k);
+size_t sweep_scratch_bytes(int64_t n, int32_t k) {
+    const size_t kp = ((size_t)k + 7) & ~(size_t)7;
+    return 2 * align256(sizeof(uint32_t) * (size_t)k * kp) + 2 * align256(sizeof(int32_t) * (size_t)n) +
+           2 * align256(sizeof(int64_t) * (size_t)n) + align256(sizeof(int32_t) * (size_t)kErrBucketBlocks * k) +
+           align256(sizeof(int32_t) * (4 * (size_t)k + 2));
 }
 
 void run_errest(hipStream_t st, const ErrArgs& a, DevFlags* flags) {
@@ -1136,18 +1286,18 @@ size_t suffix_chunk_scratch(int32_t k, int64_t maxd) {
     return sizeof(int64_t) * 2 * (size_t)k * (size_t)nchunks + 256;
 }
 
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool sweep) {
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err) {
     const int64_t tlen = maxd + 2;
     size_t s = align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
                align256(sizeof(uint32_t) * (size_t)k * k) + align256(suffix_chunk_scratch(k, maxd)) + 1024;
     if (!hist_done) s += align256(sizeof(int32_t) * k * (maxd + 1));
-    if (sweep) s += sweep_scratch_bytes(k);
-    (void)n;
+    if (err) s += sweep_scratch_bytes(n, k);
     return s;
 }
 
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags) {
-    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done, a.S_sweep || a.S_sweep_err))
+    const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
+    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done, want_err))
         throw HipError{hipErrorOutOfMemory, "epilogue scratch"};
     const bool rt = a.Dr != nullptr;
     switch (a.dk) {

@@ -397,19 +397,19 @@ void materialize_w(hipStream_t st, const uint64_t* snap, size_t plane, int32_t l
 
 }  // namespace
 
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows, bool sweep) {
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows, bool err) {
     const int64_t tlen = (int64_t)lmax + 2;
     const int W = (k + 63) / 64;
     const size_t db = lmax < 255 ? 1 : (lmax < 65535 ? 2 : 4);
     return align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
            align256(sizeof(uint32_t) * (size_t)k * k) + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W) +
-           align256((size_t)err_rows * k * db) + (sweep ? sweep_scratch_bytes(k) : 0) + 1024;
+           align256((size_t)err_rows * k * db) + (err ? sweep_scratch_bytes(err_rows, k) : 0) + 1024;
 }
 
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size,
                        DevFlags* flags) {
     const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
-    if (scratch_size < bits_epilogue_scratch(a.k, a.lmax, want_err ? a.n : 0, a.S_sweep || a.S_sweep_err))
+    if (scratch_size < bits_epilogue_scratch(a.k, a.lmax, want_err ? a.n : 0, want_err))
         throw HipError{hipErrorOutOfMemory, "bits epilogue scratch"};
     switch ((a.k + 63) / 64) {
         case 1: bits_mt<1>(st, a, scratch, flags); break;

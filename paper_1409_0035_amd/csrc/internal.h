@@ -422,10 +422,11 @@ struct EpilogueArgs {
     double* S_sweep = nullptr;   // Algorithm 2 / Sec. 4.2 outputs (optional)
     double* S_sweep_err = nullptr;
 };
-// bytes of the threshold-sweep tables (each sample's sorted row of the sample
-// distance matrix), added to an epilogue's scratch when the sweep is wanted
-size_t sweep_scratch_bytes(int32_t k);
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool sweep = false);
+// bytes of the error-estimate pass's tables (Sec. 4, Algorithm 2): each
+// sample's sorted row of the sample distance matrix and the nodes grouped by
+// pivot; added to an epilogue's scratch when any of its outputs is wanted
+size_t sweep_scratch_bytes(int64_t n, int32_t k);
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err = false);
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
 void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* sidx, int64_t n);
 
@@ -472,7 +473,7 @@ struct BitsEpilogueArgs {
     int32_t bit_base = 0;   // its first sample's index in sidx and in the histogram rows
     int32_t hist_rows = 0;  // histogram rows per slot (0: k)
 };
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows = 0, bool sweep = false);
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows = 0, bool err = false);
 
 // The eps values the experiments (Sec. 8) choose from per node for the
 // adaptive hybrid estimate: 0.001, 0.025, 0.05, 0.1, 0.2, 0.5, 0.99.
@@ -503,7 +504,7 @@ struct ErrArgs {
     double* S_ad_err = nullptr;
     double* S_sweep = nullptr;       // threshold sweep (Algorithm 2)
     double* S_sweep_err = nullptr;
-    void* sweep_scratch = nullptr;   // sweep_scratch_bytes(k), when the sweep is wanted
+    void* sweep_scratch = nullptr;   // sweep_scratch_bytes(n, k): the pass's tables
 };
 void run_errest(hipStream_t st, const ErrArgs& a, DevFlags* flags);
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
