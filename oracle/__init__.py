@@ -15,6 +15,8 @@ What it computes (Cohen, Delling, Pajor & Werneck 2014):
     adaptive estimate that picks, per node, the eps of a list with the
     smallest estimated error (Sec. 4, eps list of Sec. 8), and the threshold
     sweep of Algorithm 2 (Sec. 4.2);
+  * the outbound / inbound reachability sampling of Sec. 6.2 (Algorithm 4)
+    from its definition;
   * exact S(v) for every node (Eq. (1)) by one search per node.
 
 Pins (closed forms, special cases, worked examples, brute force) live in
@@ -87,6 +89,8 @@ def _load():
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
     lib.orc_exact_sums.restype = ctypes.c_int
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
+    lib.orc_reach_all.restype = ctypes.c_int
+    lib.orc_reach_all.argtypes = [i64, P, P, P, P, i32, i32, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -279,3 +283,35 @@ def exact_sums(g, threads: int = 1, reverse_graph=None) -> np.ndarray:
     if st != 0:
         raise OracleError(f"orc_exact_sums failed ({st})")
     return S
+
+
+def rank_of(order) -> np.ndarray:
+    """rank[u] = position of u in the order (a permutation of the nodes)."""
+    order = np.asarray(order, dtype=np.int64)
+    rank = np.empty(order.shape[0], dtype=np.int32)
+    rank[order] = np.arange(order.shape[0], dtype=np.int32)
+    return rank
+
+
+def reach_all(g, order, k: int, inbound: bool = False, threads: int = 1, reverse_graph=None) -> dict:
+    """Sec. 6.2 / Algorithm 4 from its definition: for every node the bottom-k
+    sample (first k in `order`) of the nodes it reaches (outbound) or that
+    reach it (inbound, searching the transpose), with count, distsum, T and
+    the estimates B (average distance) and R (reachability)."""
+    lib = _load()
+    h = g
+    if inbound:
+        if reverse_graph is None:
+            from graphgen import transpose
+            reverse_graph = transpose(g)
+        h = reverse_graph
+    n = g.n
+    rank = rank_of(order)
+    out = dict(count=np.empty(n, np.int32), distsum=np.empty(n, np.int64), T=np.empty(n, np.int64),
+               B=np.empty(n, np.float64), R=np.empty(n, np.float64))
+    st = lib.orc_reach_all(n, _p(_c(h.row_ptr, np.int64)), _p(_c(h.col_idx, np.int32)), _p(_c(h.w, np.int32)),
+                           _p(rank), int(k), int(threads), _p(out["count"]), _p(out["distsum"]), _p(out["T"]),
+                           _p(out["B"]), _p(out["R"]))
+    if st != 0:
+        raise OracleError(f"orc_reach_all failed ({st})")
+    return out

@@ -33,6 +33,13 @@
  *                               candidate with the smallest estimated error.
  *   orc_estimate_all            the above for every node, O(n^2): small graphs.
  *   orc_exact_sums              S(v) for every node by n searches (Eq. (1)).
+ *   orc_reach_all               Sec. 6.2 / Algorithm 4 from its definition:
+ *                               for every node v, one full search from v, then
+ *                               the k reached nodes u != v first in a random
+ *                               order of V (bottom-k sample of the reachability
+ *                               set), their distance sum, the position of the
+ *                               k-th among V \ {v}, and the average-distance and
+ *                               reachability estimates.
  *
  * Readings of the paper used here (all listed with reasons in the design notes):
  *   - pivot ties go to the lowest sample index (Alg. 2 updates the pivot only
@@ -51,6 +58,7 @@
 #include <string.h>
 
 #define ORC_OK 0
+#define ORC_EINVAL 1
 #define ORC_EUNREACHED 2
 #define ORC_ENOMEM 3
 #define ORC_EOVERFLOW 4
@@ -533,4 +541,77 @@ int orc_exact_sums(int64_t n, const int64_t* rp, const int32_t* col, const int32
     }
     pthread_mutex_destroy(&J.lock);
     return J.status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 6.2 / Algorithm 4, outbound (search on G) or inbound (search on the
+ * transpose, passed as rp/col): the bottom-k sample of each node's
+ * reachability set under the rank order rank[u] (0-based position of u in a
+ * uniformly random order of V), taken from its definition.  For every node v:
+ *   count   = min(k, |R(v)|), R(v) = the nodes u != v reached from v;
+ *   distsum = the sum of d over the count members of R(v) first in rank order;
+ *   T       = when count = k, the number of nodes other than v whose rank is
+ *             at most that of the k-th member (its 1-based position among
+ *             V \ {v}); 0 otherwise;
+ *   B       = distsum / count (0 when count = 0), the average-distance
+ *             estimate;
+ *   R       = count when count < k, else 1 + (k-1)(n-2) / (T-1), the
+ *             reachability estimate (1 when k = 1, whose numerator is 0). */
+typedef struct {
+    int64_t n; const int64_t* rp; const int32_t* col; const int32_t* w; const int32_t* rank; int32_t k;
+    int32_t* count; int64_t* distsum; int64_t* T; double* B; double* R; int64_t next; pthread_mutex_t lock;
+} reach_job;
+
+static void* reach_worker(void* arg) {
+    reach_job* J = (reach_job*)arg;
+    const int64_t n = J->n;
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t* by_rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);  /* node at each rank */
+    for (int64_t u = 0; u < n; u++) by_rank[J->rank[u]] = (int32_t)u;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t v = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (v >= n) break;
+        sssp(n, J->rp, J->col, J->w, (int32_t)v, d);
+        int32_t cnt = 0;
+        int64_t sum = 0, T = 0, kth = -1;
+        /* walk V in rank order, keep the first k reached nodes other than v */
+        for (int64_t r = 0; r < n && cnt < J->k; r++) {
+            int32_t u = by_rank[r];
+            if (u == v || d[u] < 0) continue;
+            cnt++;
+            sum += d[u];
+            if (cnt == J->k) kth = r;
+        }
+        if (kth >= 0) T = (kth + 1) - (J->rank[v] < kth ? 1 : 0);
+        J->count[v] = cnt;
+        J->distsum[v] = sum;
+        J->T[v] = T;
+        J->B[v] = cnt > 0 ? (double)sum / (double)cnt : 0.0;
+        if (cnt < J->k) J->R[v] = (double)cnt;
+        else if (J->k == 1) J->R[v] = 1.0;
+        else J->R[v] = 1.0 + (double)((int64_t)(J->k - 1) * (n - 2)) / (double)(T - 1);
+    }
+    free(d); free(by_rank);
+    return NULL;
+}
+
+int orc_reach_all(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* w, const int32_t* rank,
+                  int32_t k, int32_t threads, int32_t* count, int64_t* distsum, int64_t* T, double* B, double* R) {
+    if (k < 1) return ORC_EINVAL;
+    reach_job J;
+    J.n = n; J.rp = rp; J.col = col; J.w = w; J.rank = rank; J.k = k;
+    J.count = count; J.distsum = distsum; J.T = T; J.B = B; J.R = R; J.next = 0;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads <= 1) {
+        reach_worker(&J);
+    } else {
+        pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+        for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, reach_worker, &J);
+        for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
+    pthread_mutex_destroy(&J.lock);
+    return ORC_OK;
 }

@@ -150,3 +150,86 @@ def sweep(dist, samples):
         est.append(cand[best][0])
         errs.append(cand[best][1])
     return est, errs
+
+
+def reach_definition(dist, order, k):
+    """Sec. 6.2 from the definitions, exact rationals: for each node v the
+    first k nodes u != v in `order` with dist[v][u] finite (dist[v][u] is the
+    distance the estimate averages: from v for outbound, to v for inbound --
+    pass the transposed matrix), and
+    (count, distsum, T, B, R) with T the 1-based position of the k-th among
+    V minus v, B = distsum/count (0 if none), R = count if count < k else
+    1 + (k-1)(n-2)/(T-1)."""
+    n = len(dist)
+    pos = {u: i for i, u in enumerate(order)}
+    out = []
+    for v in range(n):
+        reach = sorted((u for u in range(n) if u != v and dist[v][u] != INF), key=lambda u: pos[u])
+        chosen = reach[:k]
+        cnt = len(chosen)
+        ds = sum(dist[v][u] for u in chosen)
+        T = 0
+        if cnt == k:
+            T = sum(1 for u in range(n) if u != v and pos[u] <= pos[chosen[-1]])
+        B = Fraction(ds, cnt) if cnt else Fraction(0)
+        R = Fraction(cnt) if cnt < k else (Fraction(1) if k == 1 else 1 + Fraction((k - 1) * (n - 2), T - 1))
+        out.append((cnt, ds, T, B, R))
+    return out
+
+
+def reach_algorithm4(n, arcs, order, k, corrected=False):
+    """Algorithm 4 on a tiny graph given as a list of (tail, head, length)
+    arcs: sources u in `order`; from each, a Dijkstra on the transposed graph
+    (outbound: it reaches the nodes v that reach u, at distance d(v,u)); every
+    scanned v != u counts u, adds d(v,u) while its count is at most k, and
+    records T when its count reaches k (the number of processed sources, less
+    one if v itself was processed earlier).  Pass reversed arcs for inbound.
+    The search stops expanding at a node x when
+      * as printed (corrected=False): x's count is already k;
+      * corrected: x's count plus one if x was processed before u is at least
+        k + 1 -- then every node reaching x has k members ranked before u
+        other than itself, so u is in none of their samples.  The printed
+        rule also stops when x's k members include a node w that reaches x,
+        and w, which cannot count itself, loses u.
+    Returns the same tuples as reach_definition."""
+    import heapq
+    radj = [[] for _ in range(n)]
+    for a, b, w in arcs:
+        radj[b].append((a, w))
+    mark = [False] * n
+    count = [0] * n
+    T = [0] * n
+    distsum = [0] * n
+    for t, u in enumerate(order, start=1):
+        mark[u] = True
+        best = {u: 0}
+        heap = [(0, u)]
+        done = set()
+        while heap:
+            d, v = heapq.heappop(heap)
+            if v in done or d > best[v]:
+                continue
+            done.add(v)
+            if corrected:
+                if count[v] + (1 if (mark[v] and v != u) else 0) >= k + 1:
+                    continue  # pruned: not expanded
+            elif count[v] >= k:
+                continue  # pruned: not expanded
+            if v != u:
+                count[v] += 1
+                if count[v] <= k:
+                    distsum[v] += d
+                if count[v] == k:
+                    T[v] = t - 1 if mark[v] else t
+            for x, w in radj[v]:
+                nd = d + w
+                if x not in best or nd < best[x]:
+                    best[x] = nd
+                    heapq.heappush(heap, (nd, x))
+    out = []
+    for v in range(n):
+        cnt = min(count[v], k)
+        B = Fraction(distsum[v], cnt) if cnt else Fraction(0)
+        R = Fraction(cnt) if cnt < k else (Fraction(1) if k == 1 else 1 + Fraction((k - 1) * (n - 2), T[v] - 1))
+        out.append((cnt, distsum[v], T[v] if cnt == k else 0, B, R))
+    return out

@@ -477,3 +477,94 @@ def test_sweep_never_worse_than_pivoting():
     un[samples] = False
     assert (out["S_sweep_err"][un] <= pure[un] * (1 + 1e-12)).all()
     assert (out["S_sweep_err"] >= 0).all()
+
+
+# ---------------------------------------------------------------- Sec. 6.2 / Algorithm 4
+
+DIGRAPH6 = [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (5, 3)]
+ORDER6 = [3, 0, 5, 1, 4, 2]
+
+
+def _reach_tuple_ok(got, j, want):
+    # B is one correctly rounded division of exact integers; R adds 1 to a
+    # rounded quotient, so it is within one rounding of the exact value
+    cnt, ds, T, B, R = want
+    return (got["count"][j] == cnt and got["distsum"][j] == ds and got["T"][j] == T
+            and got["B"][j] == float(B) and abs(got["R"][j] - float(R)) <= 4e-16 * float(R))
+
+
+def test_reach_worked_example():
+    """Algorithm 4 on the hand-derived 6-node digraph (fixture with derivation),
+    outbound and inbound, from the definition and from the literal algorithm."""
+    rows = _read_golden("digraph6_reach_k2.txt")
+    g = graphgen.csr_from_arcs(6, [a for a, _ in DIGRAPH6], [b for _, b in DIGRAPH6], symmetrize=False,
+                               directed=True)
+    out = oracle.reach_all(g, ORDER6, 2)
+    inn = oracle.reach_all(g, ORDER6, 2, inbound=True)
+    arcs = [(a, b, 1) for a, b in DIGRAPH6]
+    alg_out = tiny.reach_algorithm4(6, arcs, ORDER6, 2, corrected=True)
+    alg_in = tiny.reach_algorithm4(6, [(b, a, w) for a, b, w in arcs], ORDER6, 2, corrected=True)
+    for d, v, cnt, ds, T, bn, bd, rn, rd in rows:
+        want = (cnt, ds, T, Fraction(int(bn), int(bd)), Fraction(int(rn), int(rd)))
+        got, alg = (out, alg_out) if d == 0 else (inn, alg_in)
+        assert _reach_tuple_ok(got, v, want), (d, v)
+        assert alg[v] == want, (d, v, alg[v])
+    # the printed pruning rule loses node 1 from outbound node 0's sample
+    printed = tiny.reach_algorithm4(6, arcs, ORDER6, 2)
+    assert printed[0][:2] == (1, 3) and out["count"][0] == 2
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_reach_definition_vs_algorithm4(seed):
+    """The definition-level oracle equals the pruned sequential searches of
+    Algorithm 4 (with the corrected pruning rule) and an exact-rational
+    restatement of the definition on random digraphs, weighted or not, not
+    strongly connected."""
+    rng = np.random.default_rng(2400 + seed)
+    n = int(rng.integers(2, 30))
+    wmax = [1, 7, 1, 3][seed % 4]
+    g = graphgen.gnp(n, float(rng.uniform(0.03, 0.3)), 2400 + seed, directed=True, wmax=wmax, connect=False)
+    order = [int(x) for x in oracle.draw_samples(g.n, g.n, 50 + seed)]
+    k = int(rng.integers(1, g.n + 2))
+    arcs = []
+    for a in range(g.n):
+        for e in range(g.row_ptr[a], g.row_ptr[a + 1]):
+            arcs.append((a, int(g.col_idx[e]), 1 if g.w is None else int(g.w[e])))
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    dT = [[d[u][v] for u in range(g.n)] for v in range(g.n)]
+    for inbound, dist, arcs_dir in ((False, d, arcs), (True, dT, [(b, a, w) for a, b, w in arcs])):
+        got = oracle.reach_all(g, order, k, inbound=inbound)
+        defn = tiny.reach_definition(dist, order, k)
+        alg = tiny.reach_algorithm4(g.n, arcs_dir, order, k, corrected=True)
+        assert defn == alg
+        for v in range(g.n):
+            assert _reach_tuple_ok(got, v, defn[v]), (inbound, v, defn[v])
+
+
+def test_reach_closed_forms():
+    # directed cycle: every node reaches the other n-1 at distances 1..n-1
+    n = 9
+    g = graphgen.csr_from_arcs(n, list(range(n)), [(i + 1) % n for i in range(n)], symmetrize=False, directed=True)
+    order = [int(x) for x in oracle.draw_samples(n, n, 3)]
+    big = oracle.reach_all(g, order, n + 3)
+    assert (big["count"] == n - 1).all() and (big["distsum"] == n * (n - 1) // 2).all()
+    assert (big["B"] == n / 2).all() and (big["R"] == n - 1).all() and (big["T"] == 0).all()
+    # k = n-1 on a node reaching everything: the k-th is the last other node, T = n-1, R exact
+    full = oracle.reach_all(g, order, n - 1)
+    assert (full["T"] == n - 1).all() and (full["R"] == n - 1).all()
+    # path 0 -> 1 -> ... -> n-1: outbound reach of v is v+1..n-1, inbound 0..v-1
+    g = graphgen.csr_from_arcs(n, list(range(n - 1)), list(range(1, n)), symmetrize=False, directed=True)
+    o = oracle.reach_all(g, order, n)
+    i = oracle.reach_all(g, order, n, inbound=True)
+    for v in range(n):
+        a, b = n - 1 - v, v
+        assert o["count"][v] == a and o["distsum"][v] == a * (a + 1) // 2
+        assert i["count"][v] == b and i["distsum"][v] == b * (b + 1) // 2
+    # complete digraph: the k-th member is the k-th other node in the order, T = k, R = n-1 exactly
+    n = 12
+    src = [a for a in range(n) for b in range(n) if a != b]
+    dst = [b for a in range(n) for b in range(n) if a != b]
+    g = graphgen.csr_from_arcs(n, src, dst, symmetrize=False, directed=True)
+    for k in (2, 5, 11):
+        r = oracle.reach_all(g, [int(x) for x in oracle.draw_samples(n, n, k)], k)
+        assert (r["T"] == k).all() and (r["R"] == n - 1).all() and (r["B"] == 1.0).all()
