@@ -167,6 +167,61 @@ def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
     }
 
 
+def reach_bench(args, graphgen, cc, torch):
+    """Sec. 6.2 / Algorithm 4 for every node: K timed estimates after W
+    warm-up ones on a resident graph; value = nodes estimated per second."""
+    import oracle
+    spec = graphgen.WORKLOADS[args.workload]
+    t0 = time.time()
+    g = graphgen.workload(args.workload)
+    k, seed = spec["k"], spec["sample_seed"]
+    log(f"workload {args.workload}: n={g.n} arcs={g.arcs} k={k} (generated in {time.time() - t0:.1f}s)")
+    ctx = cc.Context(0)
+    gh = ctx.upload(g)
+    outs = ("count", "distsum", "T", "B", "R")
+    for _ in range(args.warmup):
+        cc.cc_reach_estimate(ctx.handle, gh, k, inbound=args.inbound, seed=seed, outputs=outs)
+    torch.cuda.synchronize()
+    ms, tims = [], []
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        res = cc.cc_reach_estimate(ctx.handle, gh, k, inbound=args.inbound, seed=seed, outputs=outs)
+        ms.append((time.perf_counter() - a) * 1e3)
+        tims.append(cc.cc_last_timing(ctx.handle))
+    torch.cuda.synchronize()
+    mean_ms = float(np.mean(ms))
+    t = tims[-1]
+    full = int((res["count"] == k).sum())
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample of nodes (one search each), scaled to nodes per second
+        order = cc.cc_draw_samples(g.n, g.n, seed)
+        rg = graphgen.transpose(g) if args.inbound else None
+        rng = np.random.default_rng(0)
+        nodes, done, t_cpu, threads = [], 0, 0.0, os.cpu_count() or 1
+        while t_cpu < 15.0 and done < g.n:
+            batch = rng.integers(0, g.n, size=max(threads, 16)).astype(np.int32)
+            a = time.perf_counter()
+            oracle.reach_all(g, order, k, inbound=args.inbound, threads=threads, reverse_graph=rg, nodes=batch)
+            t_cpu += time.perf_counter() - a
+            done += len(batch)
+        cpu = {"value": round(done / t_cpu, 3), "unit": "nodes/s", "cores": threads, "kind": "oracle",
+               "sample": f"{done} random nodes, one search each, {t_cpu:.1f} s"}
+        log(f"cpu baseline: {cpu}")
+    line = {
+        "metric": "reachability sampling (Sec. 6.2, Algorithm 4), nodes estimated per second",
+        "value": round(g.n / (mean_ms / 1e3), 1), "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mean_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64 bitmask / u16 levels / int64 sums", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {g.name} n={g.n} arcs={g.arcs} k={k} "
+                               f"{'inbound' if args.inbound else 'outbound'}", "n": g.n, "arcs": g.arcs, "k": k},
+        "device_ms": round(t["total_ms"], 3), "levels": t["levels"], "launches": t["launches"],
+        "full_samples": full, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +244,10 @@ def main():
     ap.add_argument("--outputs", choices=("hybrid", "errors", "sweep"), default="hybrid",
                     help="what each step computes besides the Sec. 2 estimates: nothing (default), the Sec. 4 "
                          "error estimates and adaptive estimate, or the threshold sweep of Algorithm 2")
+    ap.add_argument("--reach", action="store_true",
+                    help="time the outbound reachability sampling of Sec. 6.2 (Algorithm 4) on the workload "
+                         "(default rmat20dir) instead of the hybrid estimate, and print its own JSON line")
+    ap.add_argument("--inbound", action="store_true", help="with --reach: inbound instead of outbound")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by sample "
@@ -199,6 +258,11 @@ def main():
 
     import graphgen
     import paper_1409_0035_amd as cc
+
+    if args.reach:
+        if args.workload == "rmat20":
+            args.workload = "rmat20dir"
+        return reach_bench(args, graphgen, cc, torch)
 
     spec = graphgen.WORKLOADS[args.workload]
     t0 = time.time()

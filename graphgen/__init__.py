@@ -275,6 +275,9 @@ WORKLOADS = {
     "grid2048w": dict(make=lambda: grid(2048, 2048, 8, 0.10, 1, 1000, seed=3), k=64, sample_seed=3),
     # directed R-MAT scale 22, largest strongly connected component; 128 samples, round-trip distances
     "rmat22dir": dict(make=lambda: rmat(22, 16, seed=4, directed=True), k=128, sample_seed=4),
+    # directed R-MAT scale 20, the whole graph (not strongly connected); reachability
+    # sampling (Sec. 6.2) with k = 100 as in the paper's directed experiments
+    "rmat20dir": dict(make=lambda: rmat(20, 16, seed=6, directed=True, component=False), k=100, sample_seed=6),
 }
 
 

@@ -237,6 +237,47 @@ cc_status cc_graph_set_tuning(cc_graph* g, const cc_tuning* t);
 cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64_t seed, int32_t reps, cc_tuning* best,
                       double* best_ms);
 
+/* ---- reachability sampling on general digraphs (Sec. 6.2, Algorithm 4) --
+ *
+ * For every node v: R(v) = the nodes u != v that v reaches (outbound) or that
+ * reach v (inbound), with d the distance from v (outbound) or to v (inbound).
+ * Under a rank order of the nodes (a uniformly random permutation), the
+ * sample of v is the k members of R(v) ranked first (a uniform sample of size
+ * min(k, |R(v)|) from R(v), as the bottom-k sample of Sec. 6.2).  Outputs,
+ * per node at the caller's ids:
+ *   count    min(k, |R(v)|)
+ *   distsum  sum of d over the sample
+ *   T        when count = k: the number of nodes other than v ranked no later
+ *            than the k-th member of the sample; 0 otherwise
+ *   B        distsum / count (0 when count = 0): the average-distance estimate
+ *            of Algorithm 4's final step
+ *   R        count when count < k, else 1 + (k-1)(n-2) / (T-1) (1 when k = 1):
+ *            the reachability estimate of Algorithm 4's final step
+ * The searches from the ranked sources stop at a node that holds k + 1
+ * members ranked before the source, counting the node itself when it ranks
+ * before it: this loses no member of any sample.  (Algorithm 4 as printed
+ * stops at k members, which can lose a member: a node x whose k members
+ * include v itself stops the search that v needed.)  Graphs with unit arc
+ * lengths (undirected graphs give R(v) = the rest of v's component). */
+typedef struct {
+    int32_t k;             /* sample size, k >= 1 */
+    int32_t inbound;       /* 0: outbound (distances from v), 1: inbound (distances to v) */
+    uint64_t seed;         /* rank order = cc_draw_samples(n, n, seed) when order is NULL */
+    const int32_t* order;  /* optional HOST array of n node ids: the rank order, first to last */
+} cc_reach_params;
+typedef struct {
+    int32_t* count;
+    int64_t* distsum;
+    int64_t* T;
+    double* B;
+    double* R;
+} cc_reach_result;
+/* Synchronous; `out` holds HOST pointers (n entries each; any may be NULL).
+ * CC_EINVAL: k < 1, inbound not 0 or 1, order not a permutation, or a graph
+ * with arc lengths; CC_EOVERFLOW: a search deeper than 65535 levels; CC_ENOMEM.
+ * Device state: about 128 + 36 bytes per node, allocated and freed per call. */
+cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const cc_reach_params* p, cc_reach_result* out);
+
 /* ---- serving: continuous batching over resident graphs ---------------- */
 
 /* Submit a job; `out` holds HOST pointers that must stay valid until the job

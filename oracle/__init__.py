@@ -90,7 +90,7 @@ def _load():
     lib.orc_exact_sums.restype = ctypes.c_int
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
     lib.orc_reach_all.restype = ctypes.c_int
-    lib.orc_reach_all.argtypes = [i64, P, P, P, P, i32, i32, P, P, P, P, P]
+    lib.orc_reach_all.argtypes = [i64, P, P, P, P, i32, P, i64, i32, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -293,11 +293,12 @@ def rank_of(order) -> np.ndarray:
     return rank
 
 
-def reach_all(g, order, k: int, inbound: bool = False, threads: int = 1, reverse_graph=None) -> dict:
-    """Sec. 6.2 / Algorithm 4 from its definition: for every node the bottom-k
-    sample (first k in `order`) of the nodes it reaches (outbound) or that
-    reach it (inbound, searching the transpose), with count, distsum, T and
-    the estimates B (average distance) and R (reachability)."""
+def reach_all(g, order, k: int, inbound: bool = False, threads: int = 1, reverse_graph=None, nodes=None) -> dict:
+    """Sec. 6.2 / Algorithm 4 from its definition: for every node (or for the
+    listed nodes, one search each, outputs in list order) the bottom-k sample
+    (first k in `order`) of the nodes it reaches (outbound) or that reach it
+    (inbound, searching the transpose), with count, distsum, T and the
+    estimates B (average distance) and R (reachability)."""
     lib = _load()
     h = g
     if inbound:
@@ -307,11 +308,13 @@ def reach_all(g, order, k: int, inbound: bool = False, threads: int = 1, reverse
         h = reverse_graph
     n = g.n
     rank = rank_of(order)
-    out = dict(count=np.empty(n, np.int32), distsum=np.empty(n, np.int64), T=np.empty(n, np.int64),
-               B=np.empty(n, np.float64), R=np.empty(n, np.float64))
+    sel = None if nodes is None else np.ascontiguousarray(nodes, dtype=np.int32)
+    m = n if sel is None else sel.shape[0]
+    out = dict(count=np.empty(m, np.int32), distsum=np.empty(m, np.int64), T=np.empty(m, np.int64),
+               B=np.empty(m, np.float64), R=np.empty(m, np.float64))
     st = lib.orc_reach_all(n, _p(_c(h.row_ptr, np.int64)), _p(_c(h.col_idx, np.int32)), _p(_c(h.w, np.int32)),
-                           _p(rank), int(k), int(threads), _p(out["count"]), _p(out["distsum"]), _p(out["T"]),
-                           _p(out["B"]), _p(out["R"]))
+                           _p(rank), int(k), _p(sel), int(m), int(threads), _p(out["count"]), _p(out["distsum"]),
+                           _p(out["T"]), _p(out["B"]), _p(out["R"]))
     if st != 0:
         raise OracleError(f"orc_reach_all failed ({st})")
     return out

@@ -559,6 +559,7 @@ int orc_exact_sums(int64_t n, const int64_t* rp, const int32_t* col, const int32
  *             reachability estimate (1 when k = 1, whose numerator is 0). */
 typedef struct {
     int64_t n; const int64_t* rp; const int32_t* col; const int32_t* w; const int32_t* rank; int32_t k;
+    const int32_t* nodes; int64_t nnodes;  /* the nodes to compute (NULL: all, outputs indexed by node) */
     int32_t* count; int64_t* distsum; int64_t* T; double* B; double* R; int64_t next; pthread_mutex_t lock;
 } reach_job;
 
@@ -570,9 +571,10 @@ static void* reach_worker(void* arg) {
     for (int64_t u = 0; u < n; u++) by_rank[J->rank[u]] = (int32_t)u;
     for (;;) {
         pthread_mutex_lock(&J->lock);
-        int64_t v = J->next++;
+        int64_t slot = J->next++;
         pthread_mutex_unlock(&J->lock);
-        if (v >= n) break;
+        if (slot >= (J->nodes ? J->nnodes : n)) break;
+        int64_t v = J->nodes ? J->nodes[slot] : slot;
         sssp(n, J->rp, J->col, J->w, (int32_t)v, d);
         int32_t cnt = 0;
         int64_t sum = 0, T = 0, kth = -1;
@@ -585,23 +587,24 @@ static void* reach_worker(void* arg) {
             if (cnt == J->k) kth = r;
         }
         if (kth >= 0) T = (kth + 1) - (J->rank[v] < kth ? 1 : 0);
-        J->count[v] = cnt;
-        J->distsum[v] = sum;
-        J->T[v] = T;
-        J->B[v] = cnt > 0 ? (double)sum / (double)cnt : 0.0;
-        if (cnt < J->k) J->R[v] = (double)cnt;
-        else if (J->k == 1) J->R[v] = 1.0;
-        else J->R[v] = 1.0 + (double)((int64_t)(J->k - 1) * (n - 2)) / (double)(T - 1);
+        J->count[slot] = cnt;
+        J->distsum[slot] = sum;
+        J->T[slot] = T;
+        J->B[slot] = cnt > 0 ? (double)sum / (double)cnt : 0.0;
+        if (cnt < J->k) J->R[slot] = (double)cnt;
+        else if (J->k == 1) J->R[slot] = 1.0;
+        else J->R[slot] = 1.0 + (double)((int64_t)(J->k - 1) * (n - 2)) / (double)(T - 1);
     }
     free(d); free(by_rank);
     return NULL;
 }
 
 int orc_reach_all(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* w, const int32_t* rank,
-                  int32_t k, int32_t threads, int32_t* count, int64_t* distsum, int64_t* T, double* B, double* R) {
+                  int32_t k, const int32_t* nodes, int64_t nnodes, int32_t threads, int32_t* count,
+                  int64_t* distsum, int64_t* T, double* B, double* R) {
     if (k < 1) return ORC_EINVAL;
     reach_job J;
-    J.n = n; J.rp = rp; J.col = col; J.w = w; J.rank = rank; J.k = k;
+    J.n = n; J.rp = rp; J.col = col; J.w = w; J.rank = rank; J.k = k; J.nodes = nodes; J.nnodes = nnodes;
     J.count = count; J.distsum = distsum; J.T = T; J.B = B; J.R = R; J.next = 0;
     pthread_mutex_init(&J.lock, NULL);
     if (threads <= 1) {

@@ -30,8 +30,20 @@ EXPORTED = [
     "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_release", "cc_graph_info",
     "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
     "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
-    "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune", "cc_estimate_batch",
+    "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune", "cc_estimate_batch", "cc_reach_estimate",
 ]
+
+
+class cc_reach_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("inbound", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("order", ctypes.c_void_p)]
+
+
+REACH_FIELDS = {"count": np.int32, "distsum": np.int64, "T": np.int64, "B": np.float64, "R": np.float64}
+
+
+class cc_reach_result(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in REACH_FIELDS]
 
 
 class cc_config(ctypes.Structure):
@@ -125,6 +137,7 @@ def load_library():
         "cc_graph_get_tuning": (i32, [P, ctypes.POINTER(cc_tuning)]),
         "cc_graph_set_tuning": (i32, [P, ctypes.POINTER(cc_tuning)]),
         "cc_autotune": (i32, [P, P, i32, u64, i32, ctypes.POINTER(cc_tuning), ctypes.POINTER(ctypes.c_double)]),
+        "cc_reach_estimate": (i32, [P, P, ctypes.POINTER(cc_reach_params), ctypes.POINTER(cc_reach_result)]),
         "cc_status_str": (ctypes.c_char_p, [i32]),
         "cc_last_error": (ctypes.c_char_p, []),
     }
@@ -248,6 +261,27 @@ def cc_estimate(ctx, g, k: int, mode: int = CC_BATCHED, seed: int = 0, samples=N
         arrays["dmat"] = arrays["dmat"].reshape(k, k)
     if "D" in arrays:
         arrays["D"] = arrays["D"].reshape(n, k)
+    del keep
+    return arrays
+
+
+def cc_reach_estimate(ctx, g, k: int, inbound: bool = False, seed: int = 0, order=None,
+                      outputs=tuple(REACH_FIELDS)) -> dict:
+    """Outbound (or inbound) reachability sampling of Sec. 6.2 / Algorithm 4
+    for every node, into host numpy arrays (one per requested field)."""
+    n, _, _ = cc_graph_info(g)
+    keep = None
+    if order is not None:
+        keep = np.ascontiguousarray(order, dtype=np.int32)
+        if keep.shape[0] != n:
+            raise ValueError("order must list every node once")
+    p = cc_reach_params(int(k), 1 if inbound else 0, int(seed), None if keep is None else keep.ctypes.data)
+    res = cc_reach_result()
+    arrays = {}
+    for f in outputs:
+        arrays[f] = np.empty(n, dtype=REACH_FIELDS[f])
+        setattr(res, f, arrays[f].ctypes.data)
+    _check(load_library().cc_reach_estimate(ctx, g, ctypes.byref(p), ctypes.byref(res)))
     del keep
     return arrays
 

@@ -1519,6 +1519,78 @@ extern "C" cc_status cc_estimate(cc_context* ctx, const cc_graph* g, const cc_pa
     });
 }
 
+extern "C" cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const cc_reach_params* p,
+                                       cc_reach_result* out) {
+    if (!ctx || !g || !p || !out) return fail(CC_EINVAL, "cc_reach_estimate: null argument");
+    const int64_t n = g->dg.n;
+    if (p->k < 1) return fail(CC_EINVAL, "cc_reach_estimate: need k >= 1");
+    if (p->inbound != 0 && p->inbound != 1) return fail(CC_EINVAL, "cc_reach_estimate: inbound must be 0 or 1");
+    if (g->dg.weighted) return fail(CC_EINVAL, "cc_reach_estimate: graphs with unit arc lengths only");
+    // rank order in internal ids
+    std::vector<int32_t> order((size_t)n);
+    if (p->order) {
+        std::vector<char> hit((size_t)n, 0);
+        for (int64_t r = 0; r < n; r++) {
+            const int32_t u = p->order[r];
+            if (u < 0 || u >= n || hit[(size_t)u]) return fail(CC_EINVAL, "cc_reach_estimate: order is not a permutation");
+            hit[(size_t)u] = 1;
+            order[(size_t)r] = u;
+        }
+    } else {
+        // the same draws as cc_draw_samples(n, n, seed), on a dense array
+        SplitMix64 rng{p->seed};
+        std::vector<int32_t> a((size_t)n);
+        for (int64_t i = 0; i < n; i++) a[(size_t)i] = (int32_t)i;
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t j = i + (int64_t)rng.below((uint64_t)(n - i));
+            std::swap(a[(size_t)i], a[(size_t)j]);
+            order[(size_t)i] = a[(size_t)i];
+        }
+    }
+    for (int64_t r = 0; r < n; r++) order[(size_t)r] = g->inv[(size_t)order[(size_t)r]];
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return guarded(ctx, [&]() -> cc_status {
+        Lane& L = ctx->lane;
+        hipStream_t st = L.stream;
+        CCG_HIP(hipEventRecord(L.ev[0], st));
+        // device outputs, then the traversal state
+        const size_t outb = (sizeof(int32_t) + 4 * sizeof(int64_t)) * (size_t)n + 1024;
+        char* ob = (char*)L.arena2.get(outb);
+        ReachArgs a;
+        a.n = n;
+        a.k = p->k;
+        a.rp = p->inbound ? g->dg.rp : g->dg.rrp;
+        a.col = p->inbound ? g->dg.col : g->dg.rcol;
+        a.order = order.data();
+        a.orig = g->dg.orig;
+        a.count = (int32_t*)ob;
+        a.distsum = (int64_t*)(ob + ((sizeof(int32_t) * (size_t)n + 255) & ~size_t(255)));
+        a.T = a.distsum + n;
+        a.B = (double*)(a.T + n);
+        a.R = a.B + n;
+        const size_t need = reach_scratch_bytes(n);
+        ReachStats rs;
+        run_reach(st, a, L.arena.get(need), need, &rs);
+        if (out->count) CCG_HIP(hipMemcpyAsync(out->count, a.count, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        if (out->distsum)
+            CCG_HIP(hipMemcpyAsync(out->distsum, a.distsum, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
+        if (out->T) CCG_HIP(hipMemcpyAsync(out->T, a.T, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
+        if (out->B) CCG_HIP(hipMemcpyAsync(out->B, a.B, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        if (out->R) CCG_HIP(hipMemcpyAsync(out->R, a.R, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipEventRecord(L.ev[1], st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (rs.overflow) return fail(CC_EOVERFLOW, "cc_reach_estimate: a search deeper than 65535 levels");
+        cc_timing t{};
+        float ms = 0.f;
+        CCG_HIP(hipEventElapsedTime(&ms, L.ev[0], L.ev[1]));
+        t.total_ms = t.traverse_ms = ms;
+        t.levels = rs.levels;
+        t.launches = rs.cycles * 3;
+        ctx->last = t;
+        return CC_OK;
+    });
+}
+
 extern "C" cc_status cc_estimate_batch(cc_context* ctx, int32_t count, const cc_graph* const* graphs,
                                        const cc_params* params, cc_result* outs, cc_status* statuses) {
     if (!ctx || count < 1 || !graphs || !params || !outs) return fail(CC_EINVAL, "cc_estimate_batch: null argument");

@@ -511,4 +511,32 @@ void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch,
 
 void fill_u32(hipStream_t st, void* p, uint32_t value, size_t count);
 
+// Outbound / inbound reachability sampling (Sec. 6.2, Algorithm 4).
+constexpr int kReachWords = 4;  // 256 sources of consecutive ranks per batch
+struct ReachArgs {
+    int64_t n = 0;
+    int32_t k = 0;
+    const uint32_t* rp = nullptr;  // propagation arcs: outbound the in-arcs, inbound the out-arcs
+    const int32_t* col = nullptr;
+    const int32_t* order = nullptr;  // host: internal ids in rank order (a permutation)
+    const int32_t* orig = nullptr;   // device: internal id -> caller's id
+    // device outputs at the caller's ids (each may be null)
+    int32_t* count = nullptr;
+    int64_t* distsum = nullptr;
+    int64_t* T = nullptr;
+    double* B = nullptr;
+    double* R = nullptr;
+    int32_t push_blocks = 512;
+    int32_t merge_blocks = 128;
+    int32_t account_blocks = 64;
+};
+struct ReachStats {
+    int64_t cycles = 0;   // push/merge/account/init cycles enqueued
+    int64_t batches = 0;
+    int64_t levels = 0;   // BFS levels run over all batches
+    bool overflow = false;  // some level above 65535: the result is not valid
+};
+size_t reach_scratch_bytes(int64_t n);
+void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats);
+
 }  // namespace ccg

@@ -1,0 +1,523 @@
+// Outbound / inbound reachability sampling (Sec. 6.2, Algorithm 4) on graphs
+// with unit arc lengths.
+//
+// For every node v the estimate needs the bottom-k sample of its reachability
+// set R(v) (the nodes u != v that v reaches, outbound, or that reach v,
+// inbound) under a uniformly random rank order of the nodes: the k members of
+// R(v) ranked first, their distance sum, and the position T of the k-th among
+// V \ {v}.  As in Algorithm 4, sources are taken in rank order and each one's
+// search runs on the transposed direction (outbound: from u to the nodes that
+// reach u), adding u to the sample of every node it meets; a node that holds
+// enough lower-ranked members stops the search.
+//
+// Batched here: 64W sources of consecutive ranks advance together as one
+// bit-parallel BFS (bit b = the b-th source of the batch, so bit order is rank
+// order).  The stopping rule is the exact one (see the design notes): a node x
+// stops source u when x holds at least k + 1 members ranked before u,
+// counting x itself when it ranks before u -- then every node reaching x has k
+// such members other than itself and none of them needs u.  Inside a batch x
+// counts only the bits it has already seen, so it may stop later than the
+// sequential searches would, never earlier.  Nodes that hold more than k such
+// members from earlier batches take no part.
+//
+// A source that already holds more than k members of its own can pass its
+// bit to nobody, so it is skipped: a batch takes the next 64W sources in rank
+// order that can still pass their bit (bit order stays rank order, and every
+// source skipped between them would have reached no node).
+//
+// Batches run as a state machine over three kernels that the host enqueues in
+// cycles without reading anything back: push (frontier nodes OR their
+// allowed bits into their neighbours' pending words), merge (new bits, their
+// BFS level, the bits each node passes on next), account (after the last
+// level: each touched node takes the first bits it still needs, in rank order,
+// and adds their levels; then its last block picks and starts the next
+// batch).  The control block says which kernel has work; the others return at
+// once.
+#include "internal.h"
+
+namespace ccg {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+enum : int32_t { kLevel = 1, kAccount = 2, kFinished = 3 };
+
+struct ReachCtl {
+    int32_t phase;
+    int32_t batch;
+    int64_t t0;      // rank of the batch's first source
+    int64_t tnext;   // first rank not yet looked at for sources
+    int32_t nsrc;    // sources in the batch
+    int32_t level;   // BFS level of the bits the next merge records
+    int32_t gl;      // global level stamp (first touch of a node per level)
+    int32_t fsel;    // current frontier buffer
+    int32_t nf;      // frontier size
+    int32_t nfn;     // next frontier size
+    int32_t nc;      // candidates of this level
+    int32_t nt;      // nodes touched in this batch
+    uint32_t ticket;
+    int32_t overflow;  // a recorded level above 65535
+    int32_t pad;
+    int64_t levels;  // levels run, all batches
+};
+
+struct ReachView {
+    int64_t n;
+    int32_t k;
+    const uint32_t* rp;   // propagation arcs: from a node to the nodes its bits move to
+    const int32_t* col;
+    const int32_t* rank;         // internal id -> rank
+    const int32_t* src_by_rank;  // rank -> internal id
+    int32_t* src_rank;           // [64W] rank of each bit's source in the current batch
+    int32_t* sbit;               // [n] the node's bit when it is a source of the current batch, else -1
+    int32_t* cnt;       // members counted so far (exact up to k)
+    int64_t* dsum;      // distance sum of the first min(k, cnt) members
+    int64_t* tk;        // T once the k-th member is found
+    uint64_t* seen;     // [n][W] bits of this batch at the node
+    uint64_t* nx;       // [n][W] pending bits of this level
+    uint64_t* fr;       // [n][W] bits the node passes on next level
+    uint16_t* lev;      // [n][64W] level at which each bit arrived (open nodes)
+    int32_t* stamp;     // batch that last touched the node
+    int32_t* lmark;     // level stamp that last queued the node
+    int32_t* flist;     // [2][n] frontier lists
+    int32_t* cand;      // [n] nodes with pending bits this level
+    int32_t* touched;   // [n] nodes touched in this batch
+};
+
+// Members ranked before the current batch that x holds, plus one when x
+// itself ranks before the batch (every node ranked before it was a source of
+// an earlier batch or was skipped).
+__device__ __forceinline__ int64_t held_before(const ReachView& V, int64_t x, int64_t t0) {
+    return (int64_t)V.cnt[x] + (V.rank[x] < t0 ? 1 : 0);
+}
+
+// The q lowest set bits of the W-word set s (all of them when s has fewer).
+template <int W>
+__device__ __forceinline__ void first_bits(const uint64_t (&s)[W], int64_t q, uint64_t (&out)[W]) {
+#pragma unroll
+    for (int j = 0; j < W; j++) {
+        const uint64_t x = s[j];
+        const int pc = __popcll(x);
+        if (q <= 0) {
+            out[j] = 0;
+        } else if (q >= pc) {
+            out[j] = x;
+            q -= pc;
+        } else {
+            // position of the q-th set bit: halve the window while the low half holds fewer than q
+            uint64_t y = x;
+            int pos = 0;
+            int r = (int)q;
+#pragma unroll
+            for (int sh = 32; sh >= 1; sh >>= 1) {
+                const int c = __popcll(y & ((1ull << sh) - 1));
+                if (c < r) {
+                    r -= c;
+                    y >>= sh;
+                    pos += sh;
+                }
+            }
+            out[j] = x & (pos == 63 ? ~0ull : ((2ull << pos) - 1));
+            q = 0;
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_rch_push(ReachCtl* ctl, ReachView V) {
+    if (ctl->phase != kLevel) return;
+    const int32_t nf = ctl->nf;
+    const int32_t* F = V.flist + (int64_t)ctl->fsel * V.n;
+    const int32_t gl = ctl->gl;
+    const int64_t t0 = ctl->t0;
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t e = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); e < nf; e += nwaves) {
+        const int64_t v = F[e];
+        uint64_t f[W];
+#pragma unroll
+        for (int j = 0; j < W; j++) f[j] = V.fr[v * W + j];
+        const uint32_t a0 = V.rp[v], a1 = V.rp[v + 1];
+        for (uint32_t a = a0 + lane; a < a1; a += 64) {
+            const int64_t w = V.col[a];
+            if (held_before(V, w, t0) > V.k) continue;  // holds more than k earlier members: takes no part
+            uint64_t any = 0;
+#pragma unroll
+            for (int j = 0; j < W; j++) {
+                const uint64_t b = f[j] & ~V.seen[w * W + j];
+                if (b) atomicOr((unsigned long long*)&V.nx[w * W + j], (unsigned long long)b);
+                any |= b;
+            }
+            bool first = false;
+            if (any && V.lmark[w] != gl) first = atomicExch(&V.lmark[w], gl) != gl;
+            const int idx = wave_append(&ctl->nc, first);
+            if (first) V.cand[idx] = (int32_t)w;
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_rch_merge(ReachCtl* ctl, ReachView V) {
+    if (ctl->phase != kLevel) return;
+    const int32_t nc = ctl->nc;
+    const int32_t level = ctl->level;
+    const int32_t batch = ctl->batch;
+    const int64_t t0 = ctl->t0;
+    int32_t* Fn = V.flist + (int64_t)(ctl->fsel ^ 1) * V.n;
+    bool ovf = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nc; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t w = V.cand[i];
+        uint64_t nw[W], s[W];
+        uint64_t any = 0;
+#pragma unroll
+        for (int j = 0; j < W; j++) {
+            const uint64_t p = V.nx[w * W + j];
+            V.nx[w * W + j] = 0;
+            const uint64_t old = V.seen[w * W + j];
+            nw[j] = p & ~old;
+            s[j] = old | nw[j];
+            V.seen[w * W + j] = s[j];
+            any |= nw[j];
+        }
+        bool touch = false, pass = false;
+        if (V.stamp[w] != batch) {  // each candidate appears once per level
+            V.stamp[w] = batch;
+            touch = true;
+        }
+        if (any) {
+            const int64_t held = held_before(V, w, t0);
+            if (V.cnt[w] < V.k) {  // still collecting members: remember when each bit arrived
+                if (level > 65535) ovf = true;
+#pragma unroll
+                for (int j = 0; j < W; j++) {
+                    uint64_t x = nw[j];
+                    while (x) {
+                        const int b = __ffsll((unsigned long long)x) - 1;
+                        x &= x - 1;
+                        V.lev[w * (64 * W) + j * 64 + b] = (uint16_t)level;
+                    }
+                }
+            }
+            // bit b moves on while the members ranked before it number at most k
+            uint64_t keep[W];
+            first_bits<W>(s, (int64_t)V.k - held + 1, keep);
+            uint64_t fa = 0;
+#pragma unroll
+            for (int j = 0; j < W; j++) {
+                const uint64_t f = nw[j] & keep[j];
+                V.fr[w * W + j] = f;
+                fa |= f;
+            }
+            pass = fa != 0;
+        }
+        const int ti = wave_append(&ctl->nt, touch);
+        if (touch) V.touched[ti] = (int32_t)w;
+        const int fi = wave_append(&ctl->nfn, pass);
+        if (pass) Fn[fi] = (int32_t)w;
+    }
+    if (ovf) ctl->overflow = 1;
+    __syncthreads();
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        ctl->ticket = 0;
+        const int32_t nn = atomicAdd(&ctl->nfn, 0);
+        ctl->nf = nn;
+        ctl->nfn = 0;
+        ctl->nc = 0;
+        ctl->fsel ^= 1;
+        ctl->level = level + 1;
+        ctl->gl = ctl->gl + 1;
+        ctl->levels = ctl->levels + 1;
+        if (nn == 0) ctl->phase = kAccount;
+        __threadfence();
+    }
+}
+
+// The last block of account starts the next batch: it scans ranks from tnext
+// for up to 64W sources that can still pass their bit, in rank order.
+template <int W>
+__device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
+    __shared__ int32_t wcount[kBlock / 64];
+    __shared__ int32_t got;
+    __shared__ int64_t scan, first_rank, last_rank;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int32_t batch = ctl->batch;
+    int32_t* F = V.flist + (int64_t)ctl->fsel * V.n;
+    if (threadIdx.x == 0) {
+        got = 0;
+        scan = ctl->tnext;
+    }
+    __syncthreads();
+    constexpr int kPer = 4;  // ranks per thread and window
+    while (got < 64 * W && scan < V.n) {
+        // 4 x 256 ranks per window, loads in flight together; thread t takes
+        // ranks scan + t*4 .. +3, so the window stays in rank order
+        int64_t s[kPer];
+        bool take[kPer];
+        int32_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const int64_t r = scan + (int64_t)threadIdx.x * kPer + q;
+            s[q] = r < V.n ? V.src_by_rank[r] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            take[q] = s[q] >= 0 && V.cnt[s[q]] <= V.k;
+            mine += take[q] ? 1 : 0;
+        }
+        // exclusive prefix of `mine` over the block
+        int32_t incl = mine;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wcount[wave] = incl;
+        __syncthreads();
+        int32_t b = got + incl - mine;
+        for (int w = 0; w < wave; w++) b += wcount[w];
+        int32_t total = got;
+        for (int w = 0; w < kBlock / 64; w++) total += wcount[w];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            if (!take[q]) continue;
+            if (b < 64 * W) {
+                const int64_t r = scan + (int64_t)threadIdx.x * kPer + q;
+                const int64_t x = s[q];
+                const uint64_t bit = 1ull << (b & 63);
+                if (b == 0) first_rank = r;
+                if (b == 64 * W - 1) last_rank = r;
+                V.src_rank[b] = (int32_t)r;
+                V.sbit[x] = b;
+                V.seen[x * W + (b >> 6)] = bit;
+                V.stamp[x] = batch;
+                V.fr[x * W + (b >> 6)] = bit;
+                V.touched[b] = (int32_t)x;
+                F[b] = (int32_t)x;
+            }
+            b++;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (total >= 64 * W) {  // the batch is full: continue after its last source
+                scan = last_rank + 1;
+                got = 64 * W;
+            } else {
+                scan += (int64_t)kBlock * kPer;
+                got = total;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int32_t S = got;
+        ctl->tnext = scan < V.n ? scan : V.n;
+        ctl->nsrc = S;
+        ctl->nt = S;
+        ctl->nf = S;
+        ctl->nfn = 0;
+        ctl->nc = 0;
+        ctl->level = 1;
+        ctl->t0 = S > 0 ? first_rank : V.n;
+        ctl->phase = S > 0 ? kLevel : kFinished;
+        __threadfence();
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_rch_account(ReachCtl* ctl, ReachView V) {
+    if (ctl->phase != kAccount) return;
+    const int32_t nt = ctl->nt;
+    const int32_t k = V.k;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nt; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t w = V.touched[i];
+        uint64_t s[W];
+#pragma unroll
+        for (int j = 0; j < W; j++) {
+            s[j] = V.seen[w * W + j];
+            V.seen[w * W + j] = 0;
+            V.fr[w * W + j] = 0;
+        }
+        const int64_t r = V.rank[w];
+        const int32_t own = V.sbit[w];
+        if (own >= 0) {  // its own bit counts nothing for itself
+            s[own >> 6] &= ~(1ull << (own & 63));
+            V.sbit[w] = -1;
+        }
+        int32_t pc = 0;
+#pragma unroll
+        for (int j = 0; j < W; j++) pc += __popcll(s[j]);
+        const int32_t c = V.cnt[w];
+        if (c < k) {  // members in rank order until it holds k
+            const int32_t need = k - c;
+            int32_t taken = 0;
+            int64_t sum = 0;
+#pragma unroll
+            for (int j = 0; j < W; j++) {
+                uint64_t x = s[j];
+                while (x && taken < need) {
+                    const int b = __ffsll((unsigned long long)x) - 1;
+                    x &= x - 1;
+                    sum += V.lev[w * (64 * W) + j * 64 + b];
+                    taken++;
+                    if (taken == need) {
+                        const int64_t rk = V.src_rank[j * 64 + b];
+                        V.tk[w] = (rk + 1) - (r < rk ? 1 : 0);
+                    }
+                }
+            }
+            V.dsum[w] += sum;
+        }
+        V.cnt[w] = c + pc;
+    }
+    __syncthreads();
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        if (threadIdx.x == 0) {
+            ctl->ticket = 0;
+            ctl->batch = ctl->batch + 1;
+        }
+        __syncthreads();
+        start_batch<W>(ctl, V);
+    }
+}
+
+__global__ void k_rch_out(ReachView V, const int32_t* __restrict__ orig, int32_t* count, int64_t* distsum,
+                          int64_t* T, double* B, double* R) {
+    const int64_t n = V.n;
+    const int32_t k = V.k;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = orig[v];
+        const int32_t c = V.cnt[v] < k ? V.cnt[v] : k;
+        const int64_t ds = V.dsum[v];
+        const int64_t t = c == k ? V.tk[v] : 0;
+        if (count) count[o] = c;
+        if (distsum) distsum[o] = ds;
+        if (T) T[o] = t;
+        if (B) B[o] = c > 0 ? (double)ds / (double)c : 0.0;
+        if (R) {
+            double r;
+            if (c < k) r = (double)c;
+            else if (k == 1) r = 1.0;
+            else r = 1.0 + (double)((int64_t)(k - 1) * (n - 2)) / (double)(t - 1);
+            R[o] = r;
+        }
+    }
+}
+
+__global__ void k_rch_set_phase(ReachCtl* ctl, int32_t phase) { ctl->phase = phase; }
+
+__global__ void k_rch_rank(const int32_t* __restrict__ order_internal, int64_t n, int32_t* __restrict__ rank) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        rank[order_internal[r]] = (int32_t)r;
+}
+
+}  // namespace
+
+size_t reach_scratch_bytes(int64_t n) {
+    constexpr int W = kReachWords;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    return al(sizeof(ReachCtl)) + 2 * al(sizeof(int32_t) * n) /* rank, src_by_rank */ +
+           al(sizeof(int32_t) * n) + 2 * al(sizeof(int64_t) * n) /* cnt, dsum, tk */ +
+           3 * al(sizeof(uint64_t) * n * W) + al(sizeof(uint16_t) * n * 64 * W) + 2 * al(sizeof(int32_t) * n) +
+           2 * al(sizeof(int32_t) * n) + 2 * al(sizeof(int32_t) * n) + al(sizeof(int32_t) * n) /* sbit */ +
+           al(sizeof(int32_t) * 64 * W) + 1024;
+}
+
+void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats) {
+    constexpr int W = kReachWords;
+    const int64_t n = a.n;
+    if (scratch_size < reach_scratch_bytes(n)) throw HipError{hipErrorOutOfMemory, "reach scratch"};
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    char* p = (char*)scratch;
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += al(bytes);
+        return (void*)q;
+    };
+    ReachCtl* ctl = (ReachCtl*)take(sizeof(ReachCtl));
+    ReachView V{};
+    V.n = n;
+    V.k = a.k;
+    V.rp = a.rp;
+    V.col = a.col;
+    int32_t* rank = (int32_t*)take(sizeof(int32_t) * n);
+    int32_t* sbr = (int32_t*)take(sizeof(int32_t) * n);
+    V.rank = rank;
+    V.src_by_rank = sbr;
+    V.cnt = (int32_t*)take(sizeof(int32_t) * n);
+    V.dsum = (int64_t*)take(sizeof(int64_t) * n);
+    V.tk = (int64_t*)take(sizeof(int64_t) * n);
+    V.seen = (uint64_t*)take(sizeof(uint64_t) * n * W);
+    V.nx = (uint64_t*)take(sizeof(uint64_t) * n * W);
+    V.fr = (uint64_t*)take(sizeof(uint64_t) * n * W);
+    V.lev = (uint16_t*)take(sizeof(uint16_t) * n * 64 * W);
+    V.stamp = (int32_t*)take(sizeof(int32_t) * n);
+    V.lmark = (int32_t*)take(sizeof(int32_t) * n);
+    V.sbit = (int32_t*)take(sizeof(int32_t) * n);
+    V.src_rank = (int32_t*)take(sizeof(int32_t) * 64 * W);
+    V.flist = (int32_t*)take(sizeof(int32_t) * 2 * n);
+    V.cand = (int32_t*)take(sizeof(int32_t) * n);
+    V.touched = (int32_t*)take(sizeof(int32_t) * n);
+
+    CCG_HIP(hipMemcpyAsync(sbr, a.order, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    const unsigned gn = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_rch_rank, dim3(gn), dim3(256), 0, st, (const int32_t*)sbr, n, rank);
+    fill_u32(st, V.cnt, 0u, (size_t)n);
+    fill_u32(st, V.dsum, 0u, (size_t)n * 2);
+    fill_u32(st, V.tk, 0u, (size_t)n * 2);
+    fill_u32(st, V.seen, 0u, (size_t)n * W * 2);
+    fill_u32(st, V.nx, 0u, (size_t)n * W * 2);
+    fill_u32(st, V.fr, 0u, (size_t)n * W * 2);
+    fill_u32(st, V.stamp, 0xFFFFFFFFu, (size_t)n);
+    fill_u32(st, V.lmark, 0xFFFFFFFFu, (size_t)n);
+    fill_u32(st, V.sbit, 0xFFFFFFFFu, (size_t)n);
+    fill_u32(st, ctl, 0u, sizeof(ReachCtl) / 4);
+    // start in the account phase with nothing touched: its last block picks the first batch
+    hipLaunchKernelGGL(k_rch_set_phase, dim3(1), dim3(1), 0, st, ctl, (int32_t)kAccount);
+    CCG_HIP(hipGetLastError());
+
+    const unsigned gp = (unsigned)a.push_blocks, gm = (unsigned)a.merge_blocks, ga = (unsigned)a.account_blocks;
+    const int64_t nbatches = (n + 64 * W - 1) / (64 * W) + 1;
+    const int64_t max_cycles = nbatches * (n + 2);
+    int64_t cycles = 0;
+    int32_t chunk = 16;
+    ReachCtl hc{};
+    for (;;) {
+        for (int32_t c = 0; c < chunk; c++) {
+            hipLaunchKernelGGL((k_rch_push<W>), dim3(gp), dim3(kBlock), 0, st, ctl, V);
+            hipLaunchKernelGGL((k_rch_merge<W>), dim3(gm), dim3(kBlock), 0, st, ctl, V);
+            hipLaunchKernelGGL((k_rch_account<W>), dim3(ga), dim3(kBlock), 0, st, ctl, V);
+        }
+        CCG_HIP(hipGetLastError());
+        cycles += chunk;
+        CCG_HIP(hipMemcpyAsync(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (hc.phase == kFinished) break;
+        if (cycles > max_cycles) throw HipError{hipErrorLaunchTimeOut, "reachability sampling did not finish"};
+        if (chunk < 256) chunk *= 2;
+    }
+    hipLaunchKernelGGL(k_rch_out, dim3(gn), dim3(256), 0, st, V, a.orig, a.count, a.distsum, a.T, a.B, a.R);
+    CCG_HIP(hipGetLastError());
+    if (stats) {
+        stats->cycles = cycles;
+        stats->batches = hc.batch;
+        stats->levels = hc.levels;
+        stats->overflow = hc.overflow != 0;
+    }
+}
+
+}  // namespace ccg
