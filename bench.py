@@ -57,19 +57,20 @@ def source_digest() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str, tuning: dict):
+def measured_traffic(workload: str, tuning: dict, path: str | None = None):
     """HBM bytes per launch of the scatter kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes, each scaled by the same counter on a copy
     of known size; None once the kernel source has changed since, or when
     the run's launch knobs differ from the profiled ones."""
-    path = os.path.join(ROOT, "profiles", f"{SCATTER_KERNEL}_{workload}_pmc.md")
+    if path is None:
+        path = os.path.join(ROOT, "profiles", f"{SCATTER_KERNEL}_{workload}_pmc.md")
     if not os.path.exists(path):
         return None
     vals = {}
     with open(path) as f:
         for line in f:
-            if line.startswith("- ") and ":" in line:
-                key, _, val = line[2:].partition(":")
+            if line.startswith("- ") and ": " in line:  # keys may hold a colon ("sha256[:16]")
+                key, _, val = line[2:].partition(": ")
                 vals[key.strip()] = val.strip().strip("`")
     if vals.get("bfs_batched.hip sha256[:16]") != source_digest():
         return None
