@@ -32,7 +32,7 @@ import subprocess
 
 import numpy as np
 
-from .sampler import draw_samples  # noqa: F401  (re-export)
+from .sampler import draw_samples, draw_weighted  # noqa: F401  (re-export)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -89,6 +89,8 @@ def _load():
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
     lib.orc_exact_sums.restype = ctypes.c_int
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
+    lib.orc_beta_all.restype = ctypes.c_int
+    lib.orc_beta_all.argtypes = [i64, i32, P, P, P, i64, i32, P, i64, i64, i32, P, P]
     lib.orc_reach_all.restype = ctypes.c_int
     lib.orc_reach_all.argtypes = [i64, P, P, P, P, i32, P, i64, i32, P, P, P, P, P]
     _lib = lib
@@ -317,4 +319,35 @@ def reach_all(g, order, k: int, inbound: bool = False, threads: int = 1, reverse
                            _p(out["T"]), _p(out["B"]), _p(out["R"]))
     if st != 0:
         raise OracleError(f"orc_reach_all failed ({st})")
+    return out
+
+
+def estimate_weighted(g, beta, k: int, seed: int, eps=None, threads: int = 1, reverse_graph=None, D=None,
+                      sample=None) -> dict:
+    """Sec. 5: the node-weighted hybrid estimate of S_beta(v) = sum_u beta(u)
+    d(v,u) for every node (O(n^2) walk: small graphs) from the sample of
+    draw_weighted (or `sample` = (ids, light flags, R, m)), with its variance
+    estimate; also the sample, tau = R/m and the adjusted weights."""
+    lib = _load()
+    beta = np.ascontiguousarray(beta, dtype=np.uint32)
+    ids, light, R, m = sample if sample is not None else draw_weighted([int(b) for b in beta], k, seed)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    kk = int(ids.shape[0])
+    if eps is None:
+        r = int(round(math.sqrt(kk)))
+        eps = (1, max(r, 1))
+    if D is None:
+        D = sample_distances(g, ids, threads=threads, reverse_graph=reverse_graph)
+    D = np.ascontiguousarray(D, dtype=np.int64)
+    sidx = sample_index(g.n, ids)
+    lf = np.ascontiguousarray(light, dtype=np.uint8)
+    out = dict(S_beta=np.empty(g.n, np.float64), S_beta_var=np.empty(g.n, np.float64))
+    st = lib.orc_beta_all(g.n, kk, _p(sidx), _p(lf), _p(beta), int(R), int(m), _p(D), int(eps[0]), int(eps[1]),
+                          int(threads), _p(out["S_beta"]), _p(out["S_beta_var"]))
+    if st not in (0, 4):
+        raise OracleError(f"orc_beta_all failed ({st})")
+    tau = R / m
+    out.update(samples=ids, light=np.asarray(light, bool), R=int(R), m=int(m), tau=float(tau),
+               adjusted=np.array([tau if lt else float(beta[v]) for v, lt in zip(ids, light)]), D=D,
+               status=st)
     return out

@@ -33,6 +33,11 @@
  *                               candidate with the smallest estimated error.
  *   orc_estimate_all            the above for every node, O(n^2): small graphs.
  *   orc_exact_sums              S(v) for every node by n searches (Eq. (1)).
+ *   orc_beta_all                Sec. 5 / Algorithm 3: the node-weighted hybrid
+ *                               estimate of S_beta(v) = sum_u beta(u) d(v,u) and its
+ *                               variance estimate, by the literal walk over
+ *                               V \ {v} with beta-weighted terms and adjusted
+ *                               weights on L cap C.
  *   orc_reach_all               Sec. 6.2 / Algorithm 4 from its definition:
  *                               for every node v, one full search from v, then
  *                               the k reached nodes u != v first in a random
@@ -617,4 +622,89 @@ int orc_reach_all(int64_t n, const int64_t* rp, const int32_t* col, const int32_
     }
     pthread_mutex_destroy(&J.lock);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 5 / Algorithm 3: the node-weighted hybrid estimate.  The sample C has
+ * adjusted weights beta^(c) = max(tau, beta(c)), tau = R/m: the light samples
+ * (light[i] = 1) weigh tau, the heavy ones their own weight.  For v not in C,
+ * with the pivot, Delta and the sets L, HC, H of Eq. (6) (u != v, L decided
+ * by d(c(v),u) * num <= Delta * den):
+ *   S_beta^(v) = sum_H beta(u) d(c(v),u) + sum_HC beta(u) d(v,u) + sum_{L cap C} beta^(u) d(v,u)
+ * evaluated exactly as N / m, N = (sum_H + sum_HC + sum_{heavy L cap C}) * m
+ * + R * sum_{light L cap C} d(v,u), one division; and the variance estimate
+ * of the L term, sum over light L cap C of d^2 (tau - beta(u)) tau, as
+ * t * (t * A - B) with t = R/m, A = sum d^2, B = sum beta(u) d^2 over the light
+ * members of L cap C.  For v in C: the exact sum_u beta(u) d(v,u), variance 0.
+ * D[u*k + i] = d(c_i, u) (symmetric distances). */
+typedef struct {
+    int64_t n; int32_t k; const int32_t* sidx; const uint8_t* light; const uint32_t* beta; int64_t R; int32_t m;
+    const int64_t* D; int64_t num, den; double* S; double* var; int64_t next; pthread_mutex_t lock; int status;
+} beta_job;
+
+static void* beta_worker(void* arg) {
+    beta_job* J = (beta_job*)arg;
+    const int64_t n = J->n, k = J->k;
+    const __int128 LIM = (__int128)1 << 53;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t v = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (v >= n) break;
+        const int64_t* row = J->D + v * k;
+        int ovf = 0;
+        if (J->sidx[v] >= 0) {
+            int32_t i = J->sidx[v];
+            __int128 s = 0;
+            for (int64_t u = 0; u < n; u++) s += (__int128)J->beta[u] * J->D[u * k + i];
+            ovf = s >= LIM;
+            J->S[v] = (double)(int64_t)s;
+            J->var[v] = 0.0;
+        } else {
+            int32_t p = orc_pivot((int32_t)k, row);
+            int64_t delta = row[p];
+            __int128 H = 0, HC = 0, Lb = 0, Ls = 0, A = 0, B = 0;
+            for (int64_t u = 0; u < n; u++) {
+                if (u == v) continue;
+                int64_t dpu = J->D[u * k + p];
+                int32_t j = J->sidx[u];
+                if ((__int128)dpu * J->num <= (__int128)delta * J->den) {  /* u in L */
+                    if (j < 0) continue;  /* only the sampled members of L are counted */
+                    int64_t d = row[j];
+                    if (J->light[j]) { Ls += d; A += (__int128)d * d; B += (__int128)J->beta[u] * d * d; }
+                    else Lb += (__int128)J->beta[u] * d;
+                } else if (j >= 0) {
+                    HC += (__int128)J->beta[u] * row[j];
+                } else {
+                    H += (__int128)J->beta[u] * dpu;
+                }
+            }
+            __int128 N = (H + HC + Lb) * J->m + Ls * J->R;
+            ovf = N >= LIM || A > (__int128)INT64_MAX || B > (__int128)INT64_MAX;
+            J->S[v] = (double)(int64_t)N / (double)J->m;
+            double t = (double)J->R / (double)J->m;
+            J->var[v] = t * (t * (double)(int64_t)A - (double)(int64_t)B);
+        }
+        if (ovf) { pthread_mutex_lock(&J->lock); J->status = ORC_EOVERFLOW; pthread_mutex_unlock(&J->lock); }
+    }
+    return NULL;
+}
+
+int orc_beta_all(int64_t n, int32_t k, const int32_t* sidx, const uint8_t* light, const uint32_t* beta, int64_t R,
+                 int32_t m, const int64_t* D, int64_t num, int64_t den, int32_t threads, double* S, double* var) {
+    if (k < 1 || m < 1 || num < 1 || den < 1) return ORC_EINVAL;
+    beta_job J;
+    J.n = n; J.k = k; J.sidx = sidx; J.light = light; J.beta = beta; J.R = R; J.m = m; J.D = D;
+    J.num = num; J.den = den; J.S = S; J.var = var; J.next = 0; J.status = ORC_OK;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads <= 1) {
+        beta_worker(&J);
+    } else {
+        pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+        for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, beta_worker, &J);
+        for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
+    pthread_mutex_destroy(&J.lock);
+    return J.status;
 }

@@ -62,3 +62,79 @@ def draw_samples(n: int, k: int, seed: int) -> list[int]:
         moved[j] = a_i
         out.append(a_j)
     return out
+
+
+def draw_weighted(beta, k: int, seed: int):
+    """Node-weighted sample of Sec. 5: exactly k nodes (all nodes with
+    beta > 0 when there are at most k of them), node v included with
+    probability min(1, beta(v)/tau), where tau solves
+    sum_v min(1, beta(v)/tau) = k (VarOpt's threshold).  Integer weights,
+    exact integer arithmetic throughout:
+
+    * threshold: nodes with beta > 0, heaviest first (ties by id); the number
+      L of heavy nodes is the first L with beta_(L+1) * (k - L) < R_L, R_L the
+      weight of all but the L heaviest; tau = R_L / (k - L) = R / m;
+    * the heavy nodes are taken; the light ones get masses beta(v) * m, out of
+      Q = R per unit, summing to m * Q, and pass in a random order (the full
+      Fisher-Yates permutation of draw_samples(n, n, seed)) through ordered
+      pivotal sampling (Deville & Tille's splitting method): the current
+      pivot with mass a meets the next node with mass b; if a + b <= Q, one
+      of the two gets a + b (the pivot with probability a/(a+b)) and the
+      other is dropped; else one of the two is taken with mass Q (the pivot
+      with probability (Q-b)/(2Q-a-b)) and the other keeps a + b - Q; a
+      pivot that reaches Q is taken;
+    * each decision with probability num/den draws x = next() from the same
+      generator (after the permutation's draws) and is "yes" iff
+      x * den < num * 2^64.
+    Returns (sample ids in increasing order, per-sample light flags, R, m);
+    when every positive node is taken, R = 0, m = 1 and none is light."""
+    n = len(beta)
+    pos = [v for v in range(n) if beta[v] > 0]
+    if len(pos) <= k:
+        return sorted(pos), [False] * len(pos), 0, 1
+    heavy_first = sorted(pos, key=lambda v: (-beta[v], v))
+    R = sum(beta[v] for v in pos)
+    L = 0
+    while not (beta[heavy_first[L]] * (k - L) < R):
+        R -= beta[heavy_first[L]]
+        L += 1
+    m = k - L
+    heavy = set(heavy_first[:L])
+    rng = SplitMix64(seed)
+    perm = list(range(n))
+    for i in range(n):  # the same draws as draw_samples(n, n, seed)
+        j = i + rng.below(n - i)
+        perm[i], perm[j] = perm[j], perm[i]
+    Q = R
+
+    def yes(num, den):
+        return rng.next() * den < (num << 64)
+
+    taken = set(heavy)
+    cur, ca = None, 0
+    for v in perm:
+        if beta[v] == 0 or v in heavy:
+            continue
+        b = beta[v] * m
+        if cur is None:
+            cur, ca = v, b
+            continue
+        s = ca + b
+        if s <= Q:
+            if not yes(ca, s):
+                cur = v
+            ca = s
+            if ca == Q:
+                taken.add(cur)
+                cur, ca = None, 0
+        else:
+            if yes(Q - b, 2 * Q - s):
+                taken.add(cur)
+                cur = v
+            else:
+                taken.add(v)
+            ca = s - Q
+    assert cur is None, "pivotal sampling left a fractional mass"
+    sample = sorted(taken)
+    assert len(sample) == k
+    return sample, [v not in heavy for v in sample], R, m

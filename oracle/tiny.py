@@ -233,3 +233,36 @@ def reach_algorithm4(n, arcs, order, k, corrected=False):
         R = Fraction(cnt) if cnt < k else (Fraction(1) if k == 1 else 1 + Fraction((k - 1) * (n - 2), T[v] - 1))
         out.append((cnt, distsum[v], T[v] if cnt == k else 0, B, R))
     return out
+
+
+def weighted_estimates(dist, beta, samples, light, tau, eps):
+    """Sec. 5 / Algorithm 3 with exact rationals and explicit sets: for v
+    not in C, with the pivot, Delta and L, HC, H of Eq. (6) over V minus v,
+    S^ = sum_H beta d(c,u) + sum_HC beta d(v,u) + sum_{L cap C} beta^ d(v,u)
+    (beta^ = tau for light samples, beta for heavy ones) and the variance
+    estimate sum over light L cap C of d^2 (tau - beta) tau; sampled nodes
+    their exact weighted sum and 0.  tau and eps are Fractions."""
+    n = len(dist)
+    C = list(samples)
+    Cset = set(C)
+    adj = {c: (tau if lt else Fraction(beta[c])) for c, lt in zip(C, light)}
+    lightset = {c for c, lt in zip(C, light) if lt}
+    est, var = [], []
+    for v in range(n):
+        if v in Cset:
+            est.append(Fraction(sum(beta[u] * dist[v][u] for u in range(n))))
+            var.append(Fraction(0))
+            continue
+        dists = [dist[v][c] for c in C]
+        cp = C[dists.index(min(dists))]
+        delta = dist[v][cp]
+        others = [u for u in range(n) if u != v]
+        L = {u for u in others if dist[cp][u] <= Fraction(delta) / eps}
+        HC = {u for u in others if u in Cset and u not in L}
+        H = {u for u in others if u not in Cset and u not in L}
+        s = (sum(Fraction(beta[u] * dist[cp][u]) for u in H) + sum(Fraction(beta[u] * dist[v][u]) for u in HC)
+             + sum(adj[u] * dist[v][u] for u in L & Cset))
+        w = sum(Fraction(dist[v][u]) ** 2 * (tau - beta[u]) * tau for u in L & lightset)
+        est.append(s)
+        var.append(w)
+    return est, var

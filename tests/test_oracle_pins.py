@@ -568,3 +568,119 @@ def test_reach_closed_forms():
     for k in (2, 5, 11):
         r = oracle.reach_all(g, [int(x) for x in oracle.draw_samples(n, n, k)], k)
         assert (r["T"] == k).all() and (r["R"] == n - 1).all() and (r["B"] == 1.0).all()
+
+
+# ---------------------------------------------------------------- Sec. 5 node-weighted centrality
+
+def test_weighted_worked_example():
+    rows = _read_golden("path7_beta_C135.txt")
+    g = graphgen.path(7)
+    beta = [1, 2, 1, 3, 1, 1, 2]
+    out = oracle.estimate_weighted(g, beta, 3, 0, eps=(1, 2), sample=([1, 3, 5], [True, False, True], 5, 2))
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx)
+    est, var = tiny.weighted_estimates(d, beta, [1, 3, 5], [True, False, True], Fraction(5, 2), Fraction(1, 2))
+    for v, en, ed, vn, vd in rows:
+        assert out["S_beta"][v] == en / ed and abs(out["S_beta_var"][v] - vn / vd) <= 1e-15 * max(1, vn / vd)
+        assert est[v] == Fraction(int(en), int(ed)) and var[v] == Fraction(int(vn), int(vd))
+
+
+def _exact_weighted(d, beta):
+    n = len(d)
+    return [sum(beta[u] * d[v][u] for u in range(n)) for v in range(n)]
+
+
+def test_weighted_sampler_threshold_and_size():
+    rng = np.random.default_rng(31)
+    for trial in range(40):
+        n = int(rng.integers(2, 60))
+        beta = [int(x) for x in rng.integers(0, [2, 10, 1000, 5][trial % 4], size=n)]
+        if trial % 5 == 0:
+            beta[int(rng.integers(0, n))] = 10 ** 6  # one very heavy node
+        pos = [v for v in range(n) if beta[v] > 0]
+        k = int(rng.integers(1, n + 1))
+        ids, light, R, m = oracle.draw_weighted(beta, k, 100 + trial)
+        assert ids == sorted(set(ids)) and all(beta[v] > 0 for v in ids)
+        if len(pos) <= k:
+            assert ids == pos and R == 0 and m == 1 and not any(light)
+            continue
+        assert len(ids) == k
+        tau = Fraction(R, m)
+        # tau is VarOpt's threshold: sum of min(1, beta/tau) over the nodes is k
+        assert sum(min(Fraction(1), Fraction(beta[v]) / tau) for v in pos) == k
+        # every node at or above the threshold is taken, as heavy
+        heavy = {v for v in pos if beta[v] >= tau}
+        assert heavy <= set(ids)
+        assert {v for v, lt in zip(ids, light) if not lt} == heavy
+
+
+def test_weighted_sampler_inclusion_frequencies():
+    """Inclusion frequency of each node over many seeds is min(1, beta/tau)
+    (within 5 standard deviations); 0/1 weights sample uniformly among the
+    ones; pairs are never positively correlated beyond noise."""
+    beta = [3, 1, 4, 1, 5, 9, 2, 6, 5, 3, 5, 8, 9, 7, 9, 3, 0, 0, 20]
+    k, T = 6, 4000
+    _, _, R, m = oracle.draw_weighted(beta, k, 0)
+    tau = R / m
+    hits = np.zeros(len(beta))
+    pair = np.zeros((len(beta), len(beta)))
+    for sd in range(T):
+        ids, _, _, _ = oracle.draw_weighted(beta, k, sd)
+        x = np.zeros(len(beta))
+        x[ids] = 1
+        hits += x
+        pair += np.outer(x, x)
+    for v, b in enumerate(beta):
+        p = min(1.0, b / tau)
+        sd = math.sqrt(max(p * (1 - p), 1e-12) / T)
+        assert abs(hits[v] / T - p) <= 5 * sd + 1e-12, (v, b, hits[v] / T, p)
+    light = [v for v, b in enumerate(beta) if 0 < b < tau]
+    for i in light:
+        for j in light:
+            if i < j:
+                pi, pj = min(1, beta[i] / tau), min(1, beta[j] / tau)
+                assert pair[i, j] / T <= pi * pj + 5 * math.sqrt(pi * pj / T), (i, j)
+    ones = [0, 1, 1, 0, 1, 1, 1, 0, 1, 1]
+    h = np.zeros(len(ones))
+    for sd in range(2000):
+        ids, light_, R1, m1 = oracle.draw_weighted(ones, 3, sd)
+        assert all(ones[v] for v in ids) and all(light_) and Fraction(R1, m1) == Fraction(7, 3)
+        h[ids] += 1
+    p = 3 / 7
+    for v in range(len(ones)):
+        want = p if ones[v] else 0.0
+        assert abs(h[v] / 2000 - want) <= 5 * math.sqrt(p * (1 - p) / 2000)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_weighted_vs_bruteforce(seed):
+    rng = np.random.default_rng(3100 + seed)
+    n = int(rng.integers(3, 26))
+    directed = seed % 4 == 3
+    g = graphgen.gnp(n, float(rng.uniform(0.15, 0.5)), 3100 + seed, directed=directed, wmax=[1, 9, 1, 4][seed % 4])
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    rg = None
+    if directed:
+        d = tiny.round_trip(d)
+        rg = graphgen.transpose(g)
+    beta = [int(x) for x in rng.integers(0, [3, 20, 1000, 2][seed % 4], size=g.n)]
+    beta[0] = max(beta[0], 1)
+    k = int(rng.integers(1, g.n + 1))
+    eps = [(1, 1), (1, 2), (2, 7), (1, 5)][seed % 4]
+    out = oracle.estimate_weighted(g, beta, k, 77 + seed, eps=eps, reverse_graph=rg)
+    tau = Fraction(out["R"], out["m"])
+    est, var = tiny.weighted_estimates(d, beta, list(out["samples"]), list(out["light"]), tau, Fraction(*eps))
+    for v in range(g.n):
+        assert out["S_beta"][v] == float(est[v]), v  # one correctly rounded division of exact integers
+        assert abs(out["S_beta_var"][v] - float(var[v])) <= 1e-12 * max(1.0, abs(float(var[v]))), v
+
+
+def test_weighted_exact_when_every_positive_node_is_sampled():
+    g = graphgen.grid(7, 6, 8)
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx)
+    rng = np.random.default_rng(5)
+    beta = [int(x) if x > 2 else 0 for x in rng.integers(0, 9, size=g.n)]
+    k = sum(1 for b in beta if b > 0)
+    out = oracle.estimate_weighted(g, beta, k, 1)
+    assert out["R"] == 0 and not out["light"].any()
+    assert (out["S_beta"] == np.array(_exact_weighted(d, beta), dtype=np.float64)).all()
+    assert (out["S_beta_var"] == 0).all()
