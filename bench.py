@@ -168,6 +168,41 @@ def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
     }
 
 
+def beta_bench(args, graphgen, cc, torch):
+    """Sec. 5 for every node: K timed node-weighted estimates (weighted sample
+    drawn on the host, k traversals, distance rows, beta-weighted tables and
+    estimate) after W warm-up ones; value = k * m / t as for the headline."""
+    spec = graphgen.WORKLOADS[args.workload]
+    g = graphgen.workload(args.workload)
+    k, seed = spec["k"], spec["sample_seed"]
+    beta = graphgen.node_weights(g.n, seed)
+    log(f"workload {args.workload}: n={g.n} m={g.m} k={k}, {int((beta > 0).sum())} nodes of positive weight")
+    ctx = cc.Context(0)
+    gh = ctx.upload(g)
+    for _ in range(args.warmup):
+        cc.cc_estimate_weighted(ctx.handle, gh, beta, k, seed=seed)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        res = cc.cc_estimate_weighted(ctx.handle, gh, beta, k, seed=seed)
+        ms.append((time.perf_counter() - a) * 1e3)
+    mean_ms = float(np.mean(ms))
+    edges = k * g.m * (2 if g.directed else 1)
+    line = {
+        "metric": "node-weighted hybrid estimate (Sec. 5), GTEPS of the k-source traversal plus weighted epilogue",
+        "value": round(edges / (mean_ms / 1e3) / 1e9, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mean_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64 bitmask / int32 dist / int64 weighted sums", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {g.name} n={g.n} m={g.m} k={k} node weights 1+floor(10 U^-0.7), "
+                               "20% zero", "n": g.n, "m": g.m, "k": k, "sample_size": res["sample_size"],
+                   "tau": res["tau"]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def reach_bench(args, graphgen, cc, torch):
     """Sec. 6.2 / Algorithm 4 for every node: K timed estimates after W
     warm-up ones on a resident graph; value = nodes estimated per second."""
@@ -249,6 +284,9 @@ def main():
                     help="time the outbound reachability sampling of Sec. 6.2 (Algorithm 4) on the workload "
                          "(default rmat20dir) instead of the hybrid estimate, and print its own JSON line")
     ap.add_argument("--inbound", action="store_true", help="with --reach: inbound instead of outbound")
+    ap.add_argument("--beta", action="store_true",
+                    help="time the node-weighted hybrid estimate of Sec. 5 (heavy-tailed integer node weights, "
+                         "20%% zeros) on the workload and print its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by sample "
@@ -264,6 +302,8 @@ def main():
         if args.workload == "rmat20":
             args.workload = "rmat20dir"
         return reach_bench(args, graphgen, cc, torch)
+    if args.beta:
+        return beta_bench(args, graphgen, cc, torch)
 
     spec = graphgen.WORKLOADS[args.workload]
     t0 = time.time()

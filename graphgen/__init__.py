@@ -266,6 +266,18 @@ def gnp(n: int, p: float, seed: int, directed: bool = False, wmax: int = 1,
 # ---------------------------------------------------------------------------
 # named workloads (sizes and structure of the paper's instance families)
 
+def node_weights(n: int, seed: int, zero_frac: float = 0.2, cap: int = 1 << 20) -> np.ndarray:
+    """Integer node weights for the node-weighted estimate (Sec. 5): a
+    fraction zero_frac of the nodes weigh 0, the others 1 + floor(10 * U^-0.7)
+    (heavy-tailed, U uniform in (0, 1]), capped at `cap` (numpy PCG64)."""
+    rng = np.random.default_rng(seed)
+    u = 1.0 - rng.random(n)
+    w = 1 + np.floor(10.0 * u ** -0.7)
+    w = np.minimum(w, cap).astype(np.uint32)
+    w[rng.random(n) < zero_frac] = 0
+    return w
+
+
 WORKLOADS = {
     # Barabasi-Albert, 10,000 nodes, 4 edges per new node (~40k edges); 64 samples
     "ba10k": dict(make=lambda: ba(10_000, 4, seed=1), k=64, sample_seed=1),

@@ -237,6 +237,64 @@ cc_status cc_graph_set_tuning(cc_graph* g, const cc_tuning* t);
 cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64_t seed, int32_t reps, cc_tuning* best,
                       double* best_ms);
 
+/* ---- node-weighted centrality (Sec. 5, Algorithm 3) --------------------
+ *
+ * S_beta(v) = sum_u beta(u) d(v,u) for integer node weights beta >= 0.
+ *
+ * Sample (cc_draw_weighted): exactly k nodes (every node with beta > 0 when
+ * there are at most k), node v taken with probability min(1, beta(v)/tau),
+ * where tau solves sum_v min(1, beta(v)/tau) = k -- VarOpt's threshold -- with
+ * exact integers:
+ *   - the nodes with beta > 0 heaviest first (ties by id); the number L of
+ *     heavy nodes is the first L with beta_(L+1) * (k-L) < R_L, R_L the weight
+ *     of all but the L heaviest; tau = R / m with R = R_L, m = k - L; the heavy
+ *     nodes are taken, with their own weight as adjusted weight;
+ *   - the light nodes, masses beta(v) * m out of Q = R, pass in the order of
+ *     cc_draw_samples(n, n, seed) through ordered pivotal (splitting)
+ *     sampling: the pivot with mass a meets the next node with mass b; if
+ *     a + b <= Q one of them gets a + b (the pivot with probability a/(a+b)),
+ *     the other is dropped; else one is taken (the pivot with probability
+ *     (Q-b)/(2Q-a-b)) and the other keeps a + b - Q; a pivot at Q is taken.
+ *     Each decision of probability num/den draws x, the next output of the
+ *     same generator after the permutation's draws, and is "yes" iff
+ *     x * den < num * 2^64.  Taken light nodes have adjusted weight tau.
+ *   This keeps the inclusion probabilities and the sample size exact with no
+ *   positive covariances between inclusions (as VarOpt requires); it stands in
+ *   for VarOpt's stream procedure, whose floating-point threshold updates
+ *   would make the sample depend on rounding.
+ * Estimate (Algorithm 3): the traversal of cc_estimate from this sample, then
+ * for v outside C, with the pivot, Delta and L, HC, H of Eq. (6),
+ *   S_beta^(v) = sum_H beta d(c(v),u) + sum_HC beta d(v,u) + sum_{L cap C} adjusted * d(v,u)
+ * computed as N / m with N = (sum_H + sum_HC + sum_{heavy L cap C}) * m
+ * + R * sum_{light L cap C} d (exact integers, one division), and the variance
+ * estimate of the L term, sum over light L cap C of d^2 (tau - beta) tau, as
+ * t * (t * A - B), t = R/m, A = sum d^2, B = sum beta d^2.  Sampled nodes: the
+ * exact sum, variance 0. */
+typedef struct {
+    int32_t k;                 /* sample size (fewer when fewer nodes have beta > 0) */
+    int32_t mode;              /* CC_BATCHED or CC_PLAIN, as in cc_params */
+    uint64_t seed;
+    int32_t eps_num, eps_den;  /* 0/0: eps = 1/round(sqrt(sample size)) */
+    const uint32_t* beta;      /* HOST, n node weights at the caller's ids; some > 0 */
+} cc_weighted_params;
+typedef struct {
+    double* S_beta;        /* n */
+    double* S_beta_var;    /* n */
+    int32_t* samples;      /* k: the sample in increasing id order, -1 past its size */
+    double* adjusted;      /* k: adjusted weights (tau or the node's weight) */
+    double* tau;           /* 1: R / m (0 when every positive node is sampled) */
+    int32_t* sample_size;  /* 1 */
+} cc_weighted_result;
+/* Host only: the sample above.  ids and light hold k entries; *count is the
+ * sample size, *R and *m give tau = R/m.  CC_EINVAL without a node of positive
+ * weight or when the total weight reaches 2^62. */
+cc_status cc_draw_weighted(int64_t n, const uint32_t* beta, int32_t k, uint64_t seed, int32_t* ids, uint8_t* light,
+                           int64_t* R, int32_t* m, int32_t* count);
+/* Synchronous; `out` holds HOST pointers (any may be NULL).  CC_EOVERFLOW when
+ * an exact numerator reaches 2^53 or a weighted sum leaves int64. */
+cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, const cc_weighted_params* p,
+                               cc_weighted_result* out);
+
 /* ---- reachability sampling on general digraphs (Sec. 6.2, Algorithm 4) --
  *
  * For every node v: R(v) = the nodes u != v that v reaches (outbound) or that

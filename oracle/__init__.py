@@ -90,7 +90,7 @@ def _load():
     lib.orc_exact_sums.restype = ctypes.c_int
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
     lib.orc_beta_all.restype = ctypes.c_int
-    lib.orc_beta_all.argtypes = [i64, i32, P, P, P, i64, i32, P, i64, i64, i32, P, P]
+    lib.orc_beta_all.argtypes = [i64, i32, P, P, P, i64, i32, P, i64, i64, P, i64, i32, P, P]
     lib.orc_reach_all.restype = ctypes.c_int
     lib.orc_reach_all.argtypes = [i64, P, P, P, P, i32, P, i64, i32, P, P, P, P, P]
     _lib = lib
@@ -323,11 +323,12 @@ def reach_all(g, order, k: int, inbound: bool = False, threads: int = 1, reverse
 
 
 def estimate_weighted(g, beta, k: int, seed: int, eps=None, threads: int = 1, reverse_graph=None, D=None,
-                      sample=None) -> dict:
+                      sample=None, nodes=None) -> dict:
     """Sec. 5: the node-weighted hybrid estimate of S_beta(v) = sum_u beta(u)
-    d(v,u) for every node (O(n^2) walk: small graphs) from the sample of
-    draw_weighted (or `sample` = (ids, light flags, R, m)), with its variance
-    estimate; also the sample, tau = R/m and the adjusted weights."""
+    d(v,u) for every node (O(n^2) walk: small graphs) or for the listed nodes
+    (outputs in list order), from the sample of draw_weighted (or `sample` =
+    (ids, light flags, R, m)), with its variance estimate; also the sample,
+    tau = R/m and the adjusted weights."""
     lib = _load()
     beta = np.ascontiguousarray(beta, dtype=np.uint32)
     ids, light, R, m = sample if sample is not None else draw_weighted([int(b) for b in beta], k, seed)
@@ -341,9 +342,11 @@ def estimate_weighted(g, beta, k: int, seed: int, eps=None, threads: int = 1, re
     D = np.ascontiguousarray(D, dtype=np.int64)
     sidx = sample_index(g.n, ids)
     lf = np.ascontiguousarray(light, dtype=np.uint8)
-    out = dict(S_beta=np.empty(g.n, np.float64), S_beta_var=np.empty(g.n, np.float64))
+    sel = None if nodes is None else np.ascontiguousarray(nodes, dtype=np.int32)
+    cnt = g.n if sel is None else sel.shape[0]
+    out = dict(S_beta=np.empty(cnt, np.float64), S_beta_var=np.empty(cnt, np.float64))
     st = lib.orc_beta_all(g.n, kk, _p(sidx), _p(lf), _p(beta), int(R), int(m), _p(D), int(eps[0]), int(eps[1]),
-                          int(threads), _p(out["S_beta"]), _p(out["S_beta_var"]))
+                          _p(sel), int(cnt), int(threads), _p(out["S_beta"]), _p(out["S_beta_var"]))
     if st not in (0, 4):
         raise OracleError(f"orc_beta_all failed ({st})")
     tau = R / m

@@ -639,7 +639,8 @@ int orc_reach_all(int64_t n, const int64_t* rp, const int32_t* col, const int32_
  * D[u*k + i] = d(c_i, u) (symmetric distances). */
 typedef struct {
     int64_t n; int32_t k; const int32_t* sidx; const uint8_t* light; const uint32_t* beta; int64_t R; int32_t m;
-    const int64_t* D; int64_t num, den; double* S; double* var; int64_t next; pthread_mutex_t lock; int status;
+    const int64_t* D; int64_t num, den; const int32_t* nodes; int64_t nnodes;  /* NULL: all nodes */
+    double* S; double* var; int64_t next; pthread_mutex_t lock; int status;
 } beta_job;
 
 static void* beta_worker(void* arg) {
@@ -648,9 +649,10 @@ static void* beta_worker(void* arg) {
     const __int128 LIM = (__int128)1 << 53;
     for (;;) {
         pthread_mutex_lock(&J->lock);
-        int64_t v = J->next++;
+        int64_t slot = J->next++;
         pthread_mutex_unlock(&J->lock);
-        if (v >= n) break;
+        if (slot >= (J->nodes ? J->nnodes : n)) break;
+        int64_t v = J->nodes ? J->nodes[slot] : slot;
         const int64_t* row = J->D + v * k;
         int ovf = 0;
         if (J->sidx[v] >= 0) {
@@ -658,8 +660,8 @@ static void* beta_worker(void* arg) {
             __int128 s = 0;
             for (int64_t u = 0; u < n; u++) s += (__int128)J->beta[u] * J->D[u * k + i];
             ovf = s >= LIM;
-            J->S[v] = (double)(int64_t)s;
-            J->var[v] = 0.0;
+            J->S[slot] = (double)(int64_t)s;
+            J->var[slot] = 0.0;
         } else {
             int32_t p = orc_pivot((int32_t)k, row);
             int64_t delta = row[p];
@@ -681,9 +683,9 @@ static void* beta_worker(void* arg) {
             }
             __int128 N = (H + HC + Lb) * J->m + Ls * J->R;
             ovf = N >= LIM || A > (__int128)INT64_MAX || B > (__int128)INT64_MAX;
-            J->S[v] = (double)(int64_t)N / (double)J->m;
+            J->S[slot] = (double)(int64_t)N / (double)J->m;
             double t = (double)J->R / (double)J->m;
-            J->var[v] = t * (t * (double)(int64_t)A - (double)(int64_t)B);
+            J->var[slot] = t * (t * (double)(int64_t)A - (double)(int64_t)B);
         }
         if (ovf) { pthread_mutex_lock(&J->lock); J->status = ORC_EOVERFLOW; pthread_mutex_unlock(&J->lock); }
     }
@@ -691,10 +693,12 @@ static void* beta_worker(void* arg) {
 }
 
 int orc_beta_all(int64_t n, int32_t k, const int32_t* sidx, const uint8_t* light, const uint32_t* beta, int64_t R,
-                 int32_t m, const int64_t* D, int64_t num, int64_t den, int32_t threads, double* S, double* var) {
+                 int32_t m, const int64_t* D, int64_t num, int64_t den, const int32_t* nodes, int64_t nnodes,
+                 int32_t threads, double* S, double* var) {
     if (k < 1 || m < 1 || num < 1 || den < 1) return ORC_EINVAL;
     beta_job J;
     J.n = n; J.k = k; J.sidx = sidx; J.light = light; J.beta = beta; J.R = R; J.m = m; J.D = D;
+    J.nodes = nodes; J.nnodes = nnodes;
     J.num = num; J.den = den; J.S = S; J.var = var; J.next = 0; J.status = ORC_OK;
     pthread_mutex_init(&J.lock, NULL);
     if (threads <= 1) {

@@ -31,6 +31,7 @@ EXPORTED = [
     "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
     "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
     "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune", "cc_estimate_batch", "cc_reach_estimate",
+    "cc_draw_weighted", "cc_estimate_weighted",
 ]
 
 
@@ -44,6 +45,16 @@ REACH_FIELDS = {"count": np.int32, "distsum": np.int64, "T": np.int64, "B": np.f
 
 class cc_reach_result(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in REACH_FIELDS]
+
+
+class cc_weighted_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("mode", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("eps_num", ctypes.c_int32), ("eps_den", ctypes.c_int32), ("beta", ctypes.c_void_p)]
+
+
+class cc_weighted_result(ctypes.Structure):
+    _fields_ = [("S_beta", ctypes.c_void_p), ("S_beta_var", ctypes.c_void_p), ("samples", ctypes.c_void_p),
+                ("adjusted", ctypes.c_void_p), ("tau", ctypes.c_void_p), ("sample_size", ctypes.c_void_p)]
 
 
 class cc_config(ctypes.Structure):
@@ -138,6 +149,9 @@ def load_library():
         "cc_graph_set_tuning": (i32, [P, ctypes.POINTER(cc_tuning)]),
         "cc_autotune": (i32, [P, P, i32, u64, i32, ctypes.POINTER(cc_tuning), ctypes.POINTER(ctypes.c_double)]),
         "cc_reach_estimate": (i32, [P, P, ctypes.POINTER(cc_reach_params), ctypes.POINTER(cc_reach_result)]),
+        "cc_draw_weighted": (i32, [i64, P, i32, u64, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32)]),
+        "cc_estimate_weighted": (i32, [P, P, ctypes.POINTER(cc_weighted_params), ctypes.POINTER(cc_weighted_result)]),
         "cc_status_str": (ctypes.c_char_p, [i32]),
         "cc_last_error": (ctypes.c_char_p, []),
     }
@@ -263,6 +277,41 @@ def cc_estimate(ctx, g, k: int, mode: int = CC_BATCHED, seed: int = 0, samples=N
         arrays["D"] = arrays["D"].reshape(n, k)
     del keep
     return arrays
+
+
+def cc_draw_weighted(beta, k: int, seed: int):
+    """The node-weighted sample of Sec. 5: (ids in increasing order, light
+    flags, R, m) with tau = R/m."""
+    beta = np.ascontiguousarray(beta, dtype=np.uint32)
+    ids = np.empty(k, dtype=np.int32)
+    light = np.empty(k, dtype=np.uint8)
+    R, m, c = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().cc_draw_weighted(int(beta.shape[0]), _ptr(beta), int(k), int(seed), _ptr(ids), _ptr(light),
+                                           ctypes.byref(R), ctypes.byref(m), ctypes.byref(c)))
+    return ids[:c.value].copy(), light[:c.value].astype(bool), int(R.value), int(m.value)
+
+
+def cc_estimate_weighted(ctx, g, beta, k: int, seed: int = 0, mode: int = CC_BATCHED, eps=None) -> dict:
+    """Node-weighted hybrid estimate (Sec. 5 / Algorithm 3) for every node,
+    with its variance estimate, the sample, adjusted weights and tau."""
+    n, _, _ = cc_graph_info(g)
+    beta = np.ascontiguousarray(beta, dtype=np.uint32)
+    if beta.shape[0] != n:
+        raise ValueError("one weight per node")
+    en, ed = (0, 0) if eps is None else (int(eps[0]), int(eps[1]))
+    p = cc_weighted_params(int(k), int(mode), int(seed), en, ed, beta.ctypes.data)
+    out = dict(S_beta=np.empty(n, np.float64), S_beta_var=np.empty(n, np.float64),
+               samples=np.empty(k, np.int32), adjusted=np.empty(k, np.float64), tau=np.zeros(1, np.float64),
+               sample_size=np.zeros(1, np.int32))
+    res = cc_weighted_result(*(out[f].ctypes.data for f in ("S_beta", "S_beta_var", "samples", "adjusted", "tau",
+                                                            "sample_size")))
+    _check(load_library().cc_estimate_weighted(ctx, g, ctypes.byref(p), ctypes.byref(res)))
+    c = int(out["sample_size"][0])
+    out["samples"] = out["samples"][:c]
+    out["adjusted"] = out["adjusted"][:c]
+    out["tau"] = float(out["tau"][0])
+    out["sample_size"] = c
+    return out
 
 
 def cc_reach_estimate(ctx, g, k: int, inbound: bool = False, seed: int = 0, order=None,

@@ -101,6 +101,104 @@ extern "C" cc_status cc_draw_samples(int64_t n, int32_t k, uint64_t seed, int32_
     return CC_OK;
 }
 
+// Node-weighted sample (Sec. 5): VarOpt's threshold in exact integers, heavy
+// nodes taken, light ones by ordered pivotal sampling over a random order.
+extern "C" cc_status cc_draw_weighted(int64_t n, const uint32_t* beta, int32_t k, uint64_t seed, int32_t* ids,
+                                      uint8_t* light, int64_t* R_out, int32_t* m_out, int32_t* count) {
+    if (!beta || !ids || !light || !R_out || !m_out || !count || k < 1 || n < 1 || n > INT32_MAX)
+        return fail(CC_EINVAL, "cc_draw_weighted: bad argument");
+    std::vector<int32_t> pos;
+    int64_t total = 0;
+    for (int64_t v = 0; v < n; v++) {
+        if (beta[v] == 0) continue;
+        pos.push_back((int32_t)v);
+        total += beta[v];
+        if (total >= ((int64_t)1 << 62)) return fail(CC_EINVAL, "cc_draw_weighted: total weight reaches 2^62");
+    }
+    if (pos.empty()) return fail(CC_EINVAL, "cc_draw_weighted: no node of positive weight");
+    if ((int64_t)pos.size() <= k) {  // every positive node, at its own weight
+        for (size_t i = 0; i < pos.size(); i++) {
+            ids[i] = pos[i];
+            light[i] = 0;
+        }
+        *R_out = 0;
+        *m_out = 1;
+        *count = (int32_t)pos.size();
+        return CC_OK;
+    }
+    // VarOpt's threshold: the heavy nodes are the first L in weight order
+    // only the k heaviest can be heavy: order those (weight down, id up)
+    std::vector<int32_t> heavy_first = pos;
+    std::partial_sort(heavy_first.begin(), heavy_first.begin() + k, heavy_first.end(), [&](int32_t a, int32_t b) {
+        return beta[a] != beta[b] ? beta[a] > beta[b] : a < b;
+    });
+    int64_t R = total;
+    int32_t L = 0;
+    while (!((int64_t)beta[heavy_first[(size_t)L]] * (int64_t)(k - L) < R)) {
+        R -= beta[heavy_first[(size_t)L]];
+        L++;
+    }
+    const int64_t m = k - L;
+    std::vector<char> is_heavy((size_t)n, 0), taken((size_t)n, 0);
+    for (int32_t i = 0; i < L; i++) is_heavy[(size_t)heavy_first[(size_t)i]] = taken[(size_t)heavy_first[(size_t)i]] = 1;
+    // the random order: cc_draw_samples(n, n, seed)'s permutation; its generator continues for the decisions
+    SplitMix64 rng{seed};
+    std::vector<int32_t> perm((size_t)n);
+    for (int64_t i = 0; i < n; i++) perm[(size_t)i] = (int32_t)i;
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t j = i + (int64_t)rng.below((uint64_t)(n - i));
+        std::swap(perm[(size_t)i], perm[(size_t)j]);
+    }
+    const uint64_t Q = (uint64_t)R;
+    auto yes = [&](uint64_t num, uint64_t den) {
+        return (unsigned __int128)rng.next() * den < ((unsigned __int128)num << 64);
+    };
+    int64_t cur = -1;
+    uint64_t ca = 0;
+    for (int64_t r = 0; r < n; r++) {
+        const int32_t v = perm[(size_t)r];
+        if (beta[v] == 0 || is_heavy[(size_t)v]) continue;
+        const uint64_t b = (uint64_t)beta[v] * (uint64_t)m;
+        if (cur < 0) {
+            cur = v;
+            ca = b;
+            continue;
+        }
+        const uint64_t sum = ca + b;
+        if (sum <= Q) {  // one of the two gets the sum, the other is dropped
+            if (!yes(ca, sum)) cur = v;
+            ca = sum;
+            if (ca == Q) {
+                taken[(size_t)cur] = 1;
+                cur = -1;
+                ca = 0;
+            }
+        } else {  // one of the two is taken, the other keeps sum - Q
+            if (yes(Q - b, 2 * Q - sum)) {
+                taken[(size_t)cur] = 1;
+                cur = v;
+            } else {
+                taken[(size_t)v] = 1;
+            }
+            ca = sum - Q;
+        }
+    }
+    if (cur >= 0) return fail(CC_EINVAL, "cc_draw_weighted: pivotal sampling left a fractional mass");
+    int32_t c = 0;
+    for (int64_t v = 0; v < n; v++) {
+        if (!taken[(size_t)v]) continue;
+        if (c >= k) return fail(CC_EINVAL, "cc_draw_weighted: sample larger than k");
+        ids[c] = (int32_t)v;
+        light[c] = is_heavy[(size_t)v] ? 0 : 1;
+        c++;
+    }
+    if (c != k) return fail(CC_EINVAL, "cc_draw_weighted: sample smaller than k");
+    *R_out = R;
+    *m_out = (int32_t)m;
+    *count = c;
+    return CC_OK;
+}
+
 // ---------------------------------------------------------------- device arena
 
 namespace {
@@ -153,6 +251,7 @@ struct Lane {
     Arena arena;      // per-job small buffers and traversal state
     Arena arenaD;     // distance matrices / level masks
     Arena arena2;     // epilogue tables (sized once the largest distance is known)
+    Arena arenaW;     // node-weighted estimate: its distance rows and per-node arrays
     LevelCounters* cnt_host = nullptr;  // pinned
     hipEvent_t ev[4] = {};
     EventPool events;  // per-launch timing inside the traversals
@@ -1516,6 +1615,104 @@ extern "C" cc_status cc_estimate(cc_context* ctx, const cc_graph* g, const cc_pa
         cc_status st = estimate_to_host(ctx, g, r, out, ctx->lane, &t);
         if (st == CC_OK) ctx->last = t;
         return st;
+    });
+}
+
+extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, const cc_weighted_params* p,
+                                          cc_weighted_result* out) {
+    if (!ctx || !g || !p || !out || !p->beta) return fail(CC_EINVAL, "cc_estimate_weighted: null argument");
+    const int64_t n = g->dg.n;
+    if (p->k < 1) return fail(CC_EINVAL, "cc_estimate_weighted: need k >= 1");
+    std::vector<int32_t> ids((size_t)p->k);
+    std::vector<uint8_t> light((size_t)p->k);
+    int64_t R = 0;
+    int32_t m = 1, kk = 0;
+    cc_status s = cc_draw_weighted(n, p->beta, p->k, p->seed, ids.data(), light.data(), &R, &m, &kk);
+    if (s != CC_OK) return s;
+    ids.resize((size_t)kk);
+    light.resize((size_t)kk);
+    cc_params pp{};
+    pp.k = kk;
+    pp.mode = p->mode;
+    pp.seed = 0;
+    pp.samples = ids.data();
+    pp.eps_num = p->eps_num;
+    pp.eps_den = p->eps_den;
+    Resolved r;
+    s = resolve_params(g, &pp, r);
+    if (s != CC_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return guarded(ctx, [&]() -> cc_status {
+        Lane& L = ctx->lane;
+        hipStream_t st = L.stream;
+        auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+        // device block: D, dmat, beta, sidx, samples, light, S, var, flags, small scratch
+        const size_t bytes = al(sizeof(int32_t) * (size_t)n * kk) + al(sizeof(int32_t) * (size_t)kk * kk) +
+                             al(sizeof(uint32_t) * n) + al(sizeof(int32_t) * n) + al(sizeof(int32_t) * kk) + al(kk) +
+                             2 * al(sizeof(double) * n) + al(sizeof(DevFlags)) + 256;
+        char* q = (char*)L.arenaW.get(bytes);
+        auto take = [&](size_t b) {
+            char* x = q;
+            q += al(b);
+            return (void*)x;
+        };
+        int32_t* D = (int32_t*)take(sizeof(int32_t) * (size_t)n * kk);
+        int32_t* dmat = (int32_t*)take(sizeof(int32_t) * (size_t)kk * kk);
+        uint32_t* beta_d = (uint32_t*)take(sizeof(uint32_t) * n);
+        int32_t* sidx = (int32_t*)take(sizeof(int32_t) * n);
+        int32_t* samples_d = (int32_t*)take(sizeof(int32_t) * kk);
+        uint8_t* light_d = (uint8_t*)take(kk);
+        double* S = (double*)take(sizeof(double) * n);
+        double* var = (double*)take(sizeof(double) * n);
+        DevFlags* flags = (DevFlags*)take(sizeof(DevFlags));
+        void* small = take(256);
+        // the traversal and distance rows of cc_estimate, from this sample
+        cc_result res{};
+        res.D = D;
+        res.dmat = dmat;
+        cc_timing t{};
+        const cc_status js = run_job(ctx, g, r, &res, L, &t);
+        if (js != CC_OK) return js;
+        CCG_HIP(hipMemcpyAsync(beta_d, p->beta, sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
+        CCG_HIP(hipMemcpyAsync(samples_d, ids.data(), sizeof(int32_t) * kk, hipMemcpyHostToDevice, st));
+        CCG_HIP(hipMemcpyAsync(light_d, light.data(), (size_t)kk, hipMemcpyHostToDevice, st));
+        compute_sidx(st, samples_d, kk, sidx, n);
+        fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+        BetaArgs ba;
+        ba.n = n;
+        ba.k = kk;
+        ba.D = D;
+        ba.dmat = dmat;
+        ba.sidx = sidx;
+        ba.samples = samples_d;
+        ba.beta = beta_d;
+        ba.light = light_d;
+        ba.R = R;
+        ba.m = m;
+        ba.eps_num = r.en;
+        ba.eps_den = r.ed;
+        ba.S = S;
+        ba.var = var;
+        ba.small_scratch = small;
+        ba.get_scratch = [&](size_t need) { return L.arena2.get(need); };
+        run_beta_epilogue(st, ba, flags);
+        DevFlags hf;
+        CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+        if (out->S_beta) CCG_HIP(hipMemcpyAsync(out->S_beta, S, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        if (out->S_beta_var)
+            CCG_HIP(hipMemcpyAsync(out->S_beta_var, var, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (hf.overflow) return fail(CC_EOVERFLOW, "cc_estimate_weighted: a weighted sum leaves the exact range");
+        const double tau = (double)R / (double)m;
+        for (int32_t i = 0; i < p->k; i++) {
+            if (out->samples) out->samples[i] = i < kk ? ids[(size_t)i] : -1;
+            if (out->adjusted) out->adjusted[i] = i < kk ? (light[(size_t)i] ? tau : (double)p->beta[ids[(size_t)i]]) : 0.0;
+        }
+        if (out->tau) *out->tau = tau;
+        if (out->sample_size) *out->sample_size = kk;
+        t.epilogue_ms = 0;
+        ctx->last = t;
+        return CC_OK;
     });
 }
 

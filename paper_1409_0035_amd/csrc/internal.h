@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -510,6 +511,27 @@ void run_errest(hipStream_t st, const ErrArgs& a, DevFlags* flags);
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
 
 void fill_u32(hipStream_t st, void* p, uint32_t value, size_t count);
+
+// Node-weighted hybrid estimate (Sec. 5, Algorithm 3) from int32 distance
+// rows at the caller's ids.
+struct BetaArgs {
+    int64_t n = 0;
+    int32_t k = 0;
+    const int32_t* D = nullptr;        // [n][k] d(c_i, v)
+    const int32_t* dmat = nullptr;     // [k][k] d(c_i, c_j)
+    const int32_t* sidx = nullptr;     // [n] sample index or -1
+    const int32_t* samples = nullptr;  // [k] caller ids
+    const uint32_t* beta = nullptr;    // [n] node weights
+    const uint8_t* light = nullptr;    // [k] 1: adjusted weight tau
+    int64_t R = 0;                     // tau = R / m
+    int32_t m = 1;
+    int64_t eps_num = 1, eps_den = 1;
+    double* S = nullptr;
+    double* var = nullptr;
+    void* small_scratch = nullptr;     // 256 bytes
+    std::function<void*(size_t)> get_scratch;  // device buffer of at least the given size
+};
+void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags);
 
 // Outbound / inbound reachability sampling (Sec. 6.2, Algorithm 4).
 constexpr int kReachWords = 4;  // 256 sources of consecutive ranks per batch

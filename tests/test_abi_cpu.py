@@ -37,6 +37,32 @@ def test_sampler_matches_oracle(n, k, seed):
     assert (a == b).all()
 
 
+@pytest.mark.parametrize("case", range(12))
+def test_weighted_sampler_matches_oracle(case):
+    """The library's node-weighted sample (host code) equals the oracle's
+    independent implementation: same ids, light flags and tau."""
+    rng = np.random.default_rng(500 + case)
+    n = int(rng.integers(1, [40, 400, 5000][case % 3]))
+    hi = [2, 10, 1000, 2 ** 20][case % 4]
+    beta = rng.integers(0, hi, size=n).astype(np.uint32)
+    if case % 5 == 0:
+        beta[int(rng.integers(0, n))] = 3_000_000
+    if not beta.any():
+        beta[0] = 1
+    k = int(rng.integers(1, max(2, min(n, 300))))
+    a = cc.cc_draw_weighted(beta, k, 900 + case)
+    b = oracle.draw_weighted([int(x) for x in beta], k, 900 + case)
+    assert list(a[0]) == list(b[0]) and list(a[1]) == list(b[1]) and a[2:] == b[2:]
+
+
+def test_weighted_sampler_rejects_bad_arguments():
+    with pytest.raises(cc.CCError) as e:
+        cc.cc_draw_weighted(np.zeros(10, np.uint32), 3, 1)
+    assert e.value.status == cc.CC_EINVAL
+    with pytest.raises(cc.CCError):
+        cc.cc_draw_weighted(np.ones(10, np.uint32), 0, 1)
+
+
 def test_sampler_rejects_bad_arguments():
     with pytest.raises(cc.CCError) as e:
         cc.cc_draw_samples(5, 6, 1)
