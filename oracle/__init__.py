@@ -45,7 +45,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC])
+                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -91,6 +91,8 @@ def _load():
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
     lib.orc_beta_all.restype = ctypes.c_int
     lib.orc_beta_all.argtypes = [i64, i32, P, P, P, i64, i32, P, i64, i64, P, i64, i32, P, P]
+    lib.orc_reach_beta.restype = ctypes.c_int
+    lib.orc_reach_beta.argtypes = [i64, P, P, P, P, P, P, i64, i32, P, i64, i32, P, P, P, P]
     lib.orc_reach_all.restype = ctypes.c_int
     lib.orc_reach_all.argtypes = [i64, P, P, P, P, i32, P, i64, i32, P, P, P, P, P]
     _lib = lib
@@ -353,4 +355,52 @@ def estimate_weighted(g, beta, k: int, seed: int, eps=None, threads: int = 1, re
     out.update(samples=ids, light=np.asarray(light, bool), R=int(R), m=int(m), tau=float(tau),
                adjusted=np.array([tau if lt else float(beta[v]) for v, lt in zip(ids, light)]), D=D,
                status=st)
+    return out
+
+
+def priority_numerators(n: int, seed: int) -> np.ndarray:
+    """U(u) in [1, 2^53] for the priority ranks of Sec. 6.2 / Algorithm 5:
+    (x >> 11) + 1 for the u-th output x of SplitMix64(seed), u = 0..n-1."""
+    from .sampler import SplitMix64
+    rng = SplitMix64(seed)
+    return np.array([(rng.next() >> 11) + 1 for _ in range(n)], dtype=np.uint64)
+
+
+def priority_order(beta, U) -> np.ndarray:
+    """The nodes with beta > 0 by increasing rank U/beta (exact), ties by id."""
+    from functools import cmp_to_key
+    pos = [u for u in range(len(beta)) if beta[u] > 0]
+
+    def cmp(a, b):
+        x, y = int(U[a]) * int(beta[b]), int(U[b]) * int(beta[a])
+        return -1 if x < y or (x == y and a < b) else (1 if (x, a) != (y, b) else 0)
+    return np.array(sorted(pos, key=cmp_to_key(cmp)), dtype=np.int32)
+
+
+def reach_weighted(g, beta, k: int, seed: int, inbound: bool = False, threads: int = 1, reverse_graph=None,
+                   nodes=None, U=None) -> dict:
+    """Sec. 6.2 / Algorithm 5 from its definition: per node the k members of
+    its reachability set with beta > 0 first in priority-rank order, count,
+    the k-th member (-1 if fewer), and the estimates S (weighted distance sum)
+    and R (weighted reach)."""
+    lib = _load()
+    h = g
+    if inbound:
+        if reverse_graph is None:
+            from graphgen import transpose
+            reverse_graph = transpose(g)
+        h = reverse_graph
+    beta = np.ascontiguousarray(beta, dtype=np.uint32)
+    U = priority_numerators(g.n, seed) if U is None else np.ascontiguousarray(U, dtype=np.uint64)
+    by_rank = priority_order(beta, U)
+    sel = None if nodes is None else np.ascontiguousarray(nodes, dtype=np.int32)
+    m = g.n if sel is None else sel.shape[0]
+    out = dict(count=np.empty(m, np.int32), kth=np.empty(m, np.int32), S=np.empty(m, np.float64),
+               R=np.empty(m, np.float64))
+    st = lib.orc_reach_beta(g.n, _p(_c(h.row_ptr, np.int64)), _p(_c(h.col_idx, np.int32)), _p(_c(h.w, np.int32)),
+                            _p(beta), _p(U), _p(by_rank), int(by_rank.shape[0]), int(k), _p(sel), int(m), int(threads),
+                            _p(out["count"]), _p(out["kth"]), _p(out["S"]), _p(out["R"]))
+    if st != 0:
+        raise OracleError(f"orc_reach_beta failed ({st})")
+    out["order"] = by_rank
     return out

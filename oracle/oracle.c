@@ -38,6 +38,8 @@
  *                               variance estimate, by the literal walk over
  *                               V \ {v} with beta-weighted terms and adjusted
  *                               weights on L cap C.
+ *   orc_reach_beta              Sec. 6.2 / Algorithm 5: node-weighted reachability
+ *                               sampling with priority ranks, from its definition.
  *   orc_reach_all               Sec. 6.2 / Algorithm 4 from its definition:
  *                               for every node v, one full search from v, then
  *                               the k reached nodes u != v first in a random
@@ -57,6 +59,7 @@
  *     N = (sum_H + sum_HC)*|L cap C| + |L|*sum_{L cap C}, rounded once to
  *     double (N is checked to be below 2^53 so the conversion is exact).
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -711,4 +714,92 @@ int orc_beta_all(int64_t n, int32_t k, const int32_t* sidx, const uint8_t* light
     }
     pthread_mutex_destroy(&J.lock);
     return J.status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 6.2 / Algorithm 5, node-weighted reachability sampling.  Nodes with
+ * beta > 0 have priority ranks r(u) = U(u) / (2^53 beta(u)), U(u) in
+ * [1, 2^53] (compared exactly: r(a) < r(b) iff U(a) beta(b) < U(b) beta(a),
+ * ties by id).  For every node v, the sample is the k members of R(v) (nodes
+ * u != v with beta > 0 reached from v; the caller passes the transpose for
+ * inbound) first in rank order.  With c = the sample size:
+ *   c < k : S = sum beta(u) d, R = sum beta(u) over the sample (exact);
+ *   c = k : T = r(k-th member), tau = 1/T = 2^53 beta_k / U_k; each of the
+ *           first k-1 members weighs max(beta(u), tau) (priority sampling):
+ *           heavy (beta(u) U_k >= 2^53 beta_k) its own weight, light tau;
+ *           S = (double)sum_heavy beta d + tau * (double)sum_light d,
+ *           R = (double)sum_heavy beta + tau * (double)(number light),
+ *           tau computed as ldexp(beta_k, 53) / U_k.
+ * Outputs count, the k-th member (-1 if none), S and R. */
+typedef struct {
+    int64_t n; const int64_t* rp; const int32_t* col; const int32_t* w; const uint32_t* beta; const uint64_t* U;
+    const int32_t* by_rank; int64_t npos; const int32_t* pos_of; int32_t k; const int32_t* nodes; int64_t nnodes;
+    int32_t* count; int32_t* kth; double* S; double* R; int64_t next; pthread_mutex_t lock;
+} rbeta_job;
+
+static void* rbeta_worker(void* arg) {
+    rbeta_job* J = (rbeta_job*)arg;
+    const int64_t n = J->n;
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t* mem = (int32_t*)malloc(sizeof(int32_t) * (size_t)(J->k > 0 ? J->k : 1));
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t slot = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (slot >= (J->nodes ? J->nnodes : n)) break;
+        int64_t v = J->nodes ? J->nodes[slot] : slot;
+        sssp(n, J->rp, J->col, J->w, (int32_t)v, d);
+        int32_t c = 0;
+        for (int64_t r = 0; r < J->npos && c < J->k; r++) {
+            int32_t u = J->by_rank[r];
+            if (u == v || d[u] < 0) continue;
+            mem[c++] = u;
+        }
+        J->count[slot] = c;
+        if (c < J->k) {
+            int64_t s = 0, rr = 0;
+            for (int32_t j = 0; j < c; j++) { s += (int64_t)J->beta[mem[j]] * d[mem[j]]; rr += J->beta[mem[j]]; }
+            J->kth[slot] = -1;
+            J->S[slot] = (double)s;
+            J->R[slot] = (double)rr;
+        } else {
+            int32_t q = mem[J->k - 1];
+            uint64_t Uk = J->U[q];
+            uint64_t bk = J->beta[q];
+            double tau = ldexp((double)bk, 53) / (double)Uk;
+            int64_t hs = 0, hr = 0, ls = 0, lc = 0;
+            for (int32_t j = 0; j < J->k - 1; j++) {
+                int32_t u = mem[j];
+                unsigned __int128 lhs = (unsigned __int128)J->beta[u] * Uk;
+                unsigned __int128 rhs = (unsigned __int128)bk << 53;
+                if (lhs >= rhs) { hs += (int64_t)J->beta[u] * d[u]; hr += J->beta[u]; }
+                else { ls += d[u]; lc += 1; }
+            }
+            J->kth[slot] = q;
+            J->S[slot] = (double)hs + tau * (double)ls;
+            J->R[slot] = (double)hr + tau * (double)lc;
+        }
+    }
+    free(d); free(mem);
+    return NULL;
+}
+
+int orc_reach_beta(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* w, const uint32_t* beta,
+                   const uint64_t* U, const int32_t* by_rank, int64_t npos, int32_t k, const int32_t* nodes,
+                   int64_t nnodes, int32_t threads, int32_t* count, int32_t* kth, double* S, double* R) {
+    if (k < 1) return ORC_EINVAL;
+    rbeta_job J;
+    J.n = n; J.rp = rp; J.col = col; J.w = w; J.beta = beta; J.U = U; J.by_rank = by_rank; J.npos = npos;
+    J.k = k; J.nodes = nodes; J.nnodes = nnodes; J.count = count; J.kth = kth; J.S = S; J.R = R; J.next = 0;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads <= 1) {
+        rbeta_worker(&J);
+    } else {
+        pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+        for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, rbeta_worker, &J);
+        for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
+    pthread_mutex_destroy(&J.lock);
+    return ORC_OK;
 }

@@ -266,3 +266,62 @@ def weighted_estimates(dist, beta, samples, light, tau, eps):
         est.append(s)
         var.append(w)
     return est, var
+
+
+def reach_weighted_definition(dist, beta, U, k):
+    """Sec. 6.2 / Algorithm 5 with exact rationals: ranks r(u) = U(u) /
+    (2^53 beta(u)) for beta(u) > 0 (ties by id); per node v the k members of
+    R(v) (u != v, beta(u) > 0, dist[v][u] finite) of lowest rank; fewer than
+    k: exact S = sum beta d, R = sum beta; else with T the k-th member's rank,
+    each of the first k-1 members weighs max(beta, 1/T) (priority sampling).
+    Returns (count, kth member or -1, S, R) per node, S and R as Fractions."""
+    n = len(dist)
+    rank = {u: (Fraction(int(U[u]), (1 << 53) * int(beta[u])), u) for u in range(n) if beta[u] > 0}
+    out = []
+    for v in range(n):
+        mem = sorted((u for u in rank if u != v and dist[v][u] != INF), key=lambda u: rank[u])[:k]
+        if len(mem) < k:
+            out.append((len(mem), -1, Fraction(sum(beta[u] * dist[v][u] for u in mem)),
+                        Fraction(sum(beta[u] for u in mem))))
+            continue
+        tau = 1 / rank[mem[-1]][0]
+        wts = [max(Fraction(int(beta[u])), tau) for u in mem[:-1]]
+        out.append((k, mem[-1], sum(w * dist[v][u] for w, u in zip(wts, mem[:-1])), sum(wts)))
+    return out
+
+
+def reach_weighted_algorithm5(n, arcs, beta, U, k):
+    """Algorithm 5's searches run literally on a tiny graph (arcs (tail, head,
+    length); pass reversed arcs for inbound): sources with beta > 0 in rank
+    order, a Dijkstra from each on the transpose counting the source at every
+    scanned node v != u, stopping (as for Algorithm 4) at a node holding k + 1
+    members ranked before the source, counting itself when it ranks before
+    it.  Returns each node's members in order (the first k)."""
+    import heapq
+    radj = [[] for _ in range(n)]
+    for a, b, w in arcs:
+        radj[b].append((a, w))
+    order = sorted((u for u in range(n) if beta[u] > 0),
+                   key=lambda u: (Fraction(int(U[u]), (1 << 53) * int(beta[u])), u))
+    processed = set()
+    members = [[] for _ in range(n)]
+    for u in order:
+        best = {u: 0}
+        heap = [(0, u)]
+        done = set()
+        while heap:
+            d, v = heapq.heappop(heap)
+            if v in done or d > best[v]:
+                continue
+            done.add(v)
+            if len(members[v]) + (1 if (v in processed and v != u) else 0) >= k + 1:
+                continue
+            if v != u:
+                members[v].append((u, d))
+            for x, w in radj[v]:
+                nd = d + w
+                if x not in best or nd < best[x]:
+                    best[x] = nd
+                    heapq.heappush(heap, (nd, x))
+        processed.add(u)
+    return [m[:k] for m in members]

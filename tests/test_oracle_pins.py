@@ -684,3 +684,85 @@ def test_weighted_exact_when_every_positive_node_is_sampled():
     assert out["R"] == 0 and not out["light"].any()
     assert (out["S_beta"] == np.array(_exact_weighted(d, beta), dtype=np.float64)).all()
     assert (out["S_beta_var"] == 0).all()
+
+
+# ---------------------------------------------------------------- Sec. 6.2 / Algorithm 5
+
+def _reach_beta_ok(got, j, want):
+    cnt, kth, S, R = want
+    return (got["count"][j] == cnt and got["kth"][j] == kth
+            and abs(got["S"][j] - float(S)) <= 1e-12 * max(1.0, float(S))
+            and abs(got["R"][j] - float(R)) <= 1e-12 * max(1.0, float(R)))
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_reach_weighted_vs_definition_and_algorithm5(seed):
+    """The oracle equals an exact-rational restatement of the definition, and
+    the sequential pruned searches of Algorithm 5 find the same members."""
+    rng = np.random.default_rng(4200 + seed)
+    n = int(rng.integers(2, 28))
+    g = graphgen.gnp(n, float(rng.uniform(0.03, 0.3)), 4200 + seed, directed=True, wmax=[1, 6][seed % 2],
+                     connect=False)
+    beta = rng.integers(0, [3, 50, 1000, 2][seed % 4], size=g.n).astype(np.uint32)
+    beta[0] = max(int(beta[0]), 1)
+    k = int(rng.integers(1, g.n + 2))
+    U = oracle.priority_numerators(g.n, 60 + seed)
+    arcs = []
+    for a in range(g.n):
+        for e in range(g.row_ptr[a], g.row_ptr[a + 1]):
+            arcs.append((a, int(g.col_idx[e]), 1 if g.w is None else int(g.w[e])))
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    dT = [[d[u][v] for u in range(g.n)] for v in range(g.n)]
+    for inbound, dist, arcs_dir in ((False, d, arcs), (True, dT, [(b, a, w) for a, b, w in arcs])):
+        got = oracle.reach_weighted(g, beta, k, 60 + seed, inbound=inbound)
+        defn = tiny.reach_weighted_definition(dist, beta, U, k)
+        alg = tiny.reach_weighted_algorithm5(g.n, arcs_dir, beta, U, k)
+        for v in range(g.n):
+            assert _reach_beta_ok(got, v, defn[v]), (inbound, v, defn[v])
+            mem = sorted((u for u in range(g.n) if beta[u] > 0 and u != v and dist[v][u] != tiny.INF),
+                         key=lambda u: (Fraction(int(U[u]), int(beta[u])), u))[:k]
+            assert [u for u, _ in alg[v]] == mem and all(dd == dist[v][u] for u, dd in alg[v]), (inbound, v)
+
+
+def test_reach_weighted_unbiased():
+    """Priority sampling is unbiased: over many rank draws the mean estimates
+    approach the exact weighted reach and weighted distance sum (4 standard
+    errors); the printed S = sum beta d / T would be off for unequal weights."""
+    g = graphgen.gnp(14, 0.25, 7, directed=True, wmax=3, connect=False)
+    rng = np.random.default_rng(8)
+    beta = rng.integers(1, 30, size=g.n).astype(np.uint32)
+    beta[3] = 200  # one heavy node
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx, g.w)
+    k, T = 4, 3000
+    S = np.zeros((T, g.n))
+    R = np.zeros((T, g.n))
+    for t in range(T):
+        o = oracle.reach_weighted(g, beta, k, 1000 + t)
+        S[t], R[t] = o["S"], o["R"]
+    for v in range(g.n):
+        reach = [u for u in range(g.n) if u != v and d[v][u] != tiny.INF]
+        exR = sum(int(beta[u]) for u in reach)
+        exS = sum(int(beta[u]) * d[v][u] for u in reach)
+        for est, ex in ((R[:, v], exR), (S[:, v], exS)):
+            se = est.std() / math.sqrt(T) + 1e-9
+            assert abs(est.mean() - ex) <= 4 * se + 1e-9 * max(1, ex), (v, est.mean(), ex)
+
+
+def test_reach_weighted_unit_weights_and_small_sets():
+    # beta = 1: R = (k-1)/T and S = (sum of the first k-1 distances)/T, Algorithm 5's own final step
+    g = graphgen.csr_from_arcs(9, list(range(9)), [(i + 1) % 9 for i in range(9)], symmetrize=False, directed=True)
+    beta = np.ones(9, np.uint32)
+    U = oracle.priority_numerators(9, 5)
+    o = oracle.reach_weighted(g, beta, 3, 5)
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx)
+    order = list(oracle.priority_order(beta, U))
+    for v in range(9):
+        mem = [u for u in order if u != v][:3]
+        Tk = Fraction(int(U[mem[-1]]), 1 << 53)
+        assert abs(o["R"][v] - float(2 / Tk)) <= 1e-12 * float(2 / Tk)
+        s = sum(d[v][u] for u in mem[:2])
+        assert abs(o["S"][v] - float(s / Tk)) <= 1e-12 * float(s / Tk)
+    # fewer than k members: exact weighted sums
+    o = oracle.reach_weighted(g, beta, 20, 5)
+    assert (o["count"] == 8).all() and (o["R"] == 8).all() and (o["S"] == 36).all() and (o["kth"] == -1).all()
+
