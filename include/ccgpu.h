@@ -336,6 +336,41 @@ typedef struct {
  * Device state: about 128 + 36 bytes per node, allocated and freed per call. */
 cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const cc_reach_params* p, cc_reach_result* out);
 
+/* Node-weighted reachability sampling (Sec. 6.2, Algorithm 5): the nodes u
+ * with beta(u) > 0 get priority ranks r(u) = U(u) / (2^53 beta(u)), U(u) =
+ * (x >> 11) + 1 for the u-th output x of SplitMix64(seed) (u = 0..n-1),
+ * compared exactly (ties by id); the sample of v is the k members of R(v) of
+ * positive weight first in rank order, found by the same stopping searches.
+ * Outputs per node:
+ *   count  min(k, number of such members)
+ *   kth    the k-th member (-1 when fewer)
+ *   S, R   fewer than k members: the exact sum of beta(u) d and of beta(u)
+ *          over them; else priority sampling's estimates of the weighted
+ *          distance sum and the weighted reach: each of the first k-1 members
+ *          weighs max(beta(u), 1/T), T = r(k-th member), 1/T computed as
+ *          ldexp(beta_k, 53) / U_k; S = (double)(sum of beta d over the
+ *          heavy ones) + (1/T) * (double)(sum of d over the light ones),
+ *          R = (double)(sum of beta over the heavy) + (1/T) * (number light).
+ *          (Algorithm 5's last step, S = (sum of beta d) / T, agrees for unit
+ *          weights and is biased otherwise.)
+ * Graphs with unit arc lengths; k <= 4096. */
+typedef struct {
+    int32_t k;
+    int32_t inbound;        /* 0: outbound, 1: inbound */
+    uint64_t seed;
+    const uint32_t* beta;   /* HOST, n node weights; some > 0 */
+} cc_reach_weighted_params;
+typedef struct {
+    int32_t* count;
+    int32_t* kth;
+    double* S;
+    double* R;
+} cc_reach_weighted_result;
+/* Synchronous; `out` holds HOST pointers (n entries each; any may be NULL).
+ * Device state: about 6(k-1) + 170 bytes per node. */
+cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const cc_reach_weighted_params* p,
+                            cc_reach_weighted_result* out);
+
 /* ---- serving: continuous batching over resident graphs ---------------- */
 
 /* Submit a job; `out` holds HOST pointers that must stay valid until the job

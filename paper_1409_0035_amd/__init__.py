@@ -31,7 +31,7 @@ EXPORTED = [
     "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
     "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
     "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune", "cc_estimate_batch", "cc_reach_estimate",
-    "cc_draw_weighted", "cc_estimate_weighted",
+    "cc_draw_weighted", "cc_estimate_weighted", "cc_reach_weighted",
 ]
 
 
@@ -55,6 +55,16 @@ class cc_weighted_params(ctypes.Structure):
 class cc_weighted_result(ctypes.Structure):
     _fields_ = [("S_beta", ctypes.c_void_p), ("S_beta_var", ctypes.c_void_p), ("samples", ctypes.c_void_p),
                 ("adjusted", ctypes.c_void_p), ("tau", ctypes.c_void_p), ("sample_size", ctypes.c_void_p)]
+
+
+class cc_reach_weighted_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("inbound", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("beta", ctypes.c_void_p)]
+
+
+class cc_reach_weighted_result(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_void_p), ("kth", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("R", ctypes.c_void_p)]
 
 
 class cc_config(ctypes.Structure):
@@ -152,6 +162,8 @@ def load_library():
         "cc_draw_weighted": (i32, [i64, P, i32, u64, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32)]),
         "cc_estimate_weighted": (i32, [P, P, ctypes.POINTER(cc_weighted_params), ctypes.POINTER(cc_weighted_result)]),
+        "cc_reach_weighted": (i32, [P, P, ctypes.POINTER(cc_reach_weighted_params),
+                                    ctypes.POINTER(cc_reach_weighted_result)]),
         "cc_status_str": (ctypes.c_char_p, [i32]),
         "cc_last_error": (ctypes.c_char_p, []),
     }
@@ -311,6 +323,21 @@ def cc_estimate_weighted(ctx, g, beta, k: int, seed: int = 0, mode: int = CC_BAT
     out["adjusted"] = out["adjusted"][:c]
     out["tau"] = float(out["tau"][0])
     out["sample_size"] = c
+    return out
+
+
+def cc_reach_weighted(ctx, g, beta, k: int, inbound: bool = False, seed: int = 0) -> dict:
+    """Node-weighted reachability sampling of Sec. 6.2 / Algorithm 5 for
+    every node: count, the k-th member, and the estimates S and R."""
+    n, _, _ = cc_graph_info(g)
+    beta = np.ascontiguousarray(beta, dtype=np.uint32)
+    if beta.shape[0] != n:
+        raise ValueError("one weight per node")
+    p = cc_reach_weighted_params(int(k), 1 if inbound else 0, int(seed), beta.ctypes.data)
+    out = dict(count=np.empty(n, np.int32), kth=np.empty(n, np.int32), S=np.empty(n, np.float64),
+               R=np.empty(n, np.float64))
+    res = cc_reach_weighted_result(*(out[f].ctypes.data for f in ("count", "kth", "S", "R")))
+    _check(load_library().cc_reach_weighted(ctx, g, ctypes.byref(p), ctypes.byref(res)))
     return out
 
 

@@ -551,6 +551,14 @@ struct ReachArgs {
     int32_t push_blocks = 512;
     int32_t merge_blocks = 128;
     int32_t account_blocks = 64;
+    // node-weighted sampling (Algorithm 5): order lists only the nsrc nodes of
+    // positive weight; beta and U (priority-rank numerators) per internal id, on
+    // the device; outputs count, kth (the k-th member), S_w and R
+    int64_t nsrc = 0;
+    const uint32_t* beta = nullptr;
+    const uint64_t* U = nullptr;
+    int32_t* kth = nullptr;
+    double* S_w = nullptr;
 };
 struct ReachStats {
     int64_t cycles = 0;   // push/merge/account/init cycles enqueued
@@ -558,7 +566,7 @@ struct ReachStats {
     int64_t levels = 0;   // BFS levels run over all batches
     bool overflow = false;  // some level above 65535: the result is not valid
 };
-size_t reach_scratch_bytes(int64_t n);
+size_t reach_scratch_bytes(int64_t n, int32_t k_weighted = 0);
 void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats);
 
 }  // namespace ccg

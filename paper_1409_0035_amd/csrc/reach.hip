@@ -64,6 +64,7 @@ struct ReachCtl {
 
 struct ReachView {
     int64_t n;
+    int64_t nsrc;  // ranked sources (n, or the nodes of positive weight)
     int32_t k;
     const uint32_t* rp;   // propagation arcs: from a node to the nodes its bits move to
     const int32_t* col;
@@ -83,6 +84,10 @@ struct ReachView {
     int32_t* flist;     // [2][n] frontier lists
     int32_t* cand;      // [n] nodes with pending bits this level
     int32_t* touched;   // [n] nodes touched in this batch
+    // node-weighted sampling (Algorithm 5): the first k-1 members of each
+    // node's sample and their distances (null for Algorithm 4)
+    int32_t* mem_id;    // [n][k-1]
+    uint16_t* mem_d;    // [n][k-1]
 };
 
 // Members ranked before the current batch that x holds, plus one when x
@@ -256,7 +261,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
     }
     __syncthreads();
     constexpr int kPer = 4;  // ranks per thread and window
-    while (got < 64 * W && scan < V.n) {
+    while (got < 64 * W && scan < V.nsrc) {
         // 4 x 256 ranks per window, loads in flight together; thread t takes
         // ranks scan + t*4 .. +3, so the window stays in rank order
         int64_t s[kPer];
@@ -265,7 +270,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             const int64_t r = scan + (int64_t)threadIdx.x * kPer + q;
-            s[q] = r < V.n ? V.src_by_rank[r] : -1;
+            s[q] = r < V.nsrc ? V.src_by_rank[r] : -1;
         }
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
@@ -318,7 +323,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
     }
     if (threadIdx.x == 0) {
         const int32_t S = got;
-        ctl->tnext = scan < V.n ? scan : V.n;
+        ctl->tnext = scan < V.nsrc ? scan : V.nsrc;
         ctl->nsrc = S;
         ctl->nt = S;
         ctl->nf = S;
@@ -365,12 +370,21 @@ __global__ __launch_bounds__(kBlock) void k_rch_account(ReachCtl* ctl, ReachView
                 while (x && taken < need) {
                     const int b = __ffsll((unsigned long long)x) - 1;
                     x &= x - 1;
-                    sum += V.lev[w * (64 * W) + j * 64 + b];
-                    taken++;
-                    if (taken == need) {
-                        const int64_t rk = V.src_rank[j * 64 + b];
-                        V.tk[w] = (rk + 1) - (r < rk ? 1 : 0);
+                    const uint16_t lv = V.lev[w * (64 * W) + j * 64 + b];
+                    sum += lv;
+                    const int64_t rk = V.src_rank[j * 64 + b];
+                    if (V.mem_id) {  // Algorithm 5: keep the member, or the k-th's id
+                        const int32_t slot = c + taken;
+                        const int32_t src = V.src_by_rank[rk];
+                        if (slot < k - 1) {
+                            V.mem_id[w * (k - 1) + slot] = src;
+                            V.mem_d[w * (k - 1) + slot] = lv;
+                        } else {
+                            V.tk[w] = src;
+                        }
                     }
+                    taken++;
+                    if (taken == need && !V.mem_id) V.tk[w] = (rk + 1) - (r < rk ? 1 : 0);
                 }
             }
             V.dsum[w] += sum;
@@ -418,6 +432,55 @@ __global__ void k_rch_out(ReachView V, const int32_t* __restrict__ orig, int32_t
     }
 }
 
+// Algorithm 5's estimates from the kept members: fewer than k, their exact
+// weighted sums; else priority sampling's weights max(beta, 1/T) for the
+// first k-1 members, T the rank U_k / (2^53 beta_k) of the k-th.
+__global__ void k_rch_out_beta(ReachView V, const int32_t* __restrict__ orig, const uint32_t* __restrict__ beta,
+                               const uint64_t* __restrict__ U, int32_t* count, int32_t* kth, double* S, double* R) {
+    const int64_t n = V.n;
+    const int32_t k = V.k;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = orig[v];
+        const int32_t c = V.cnt[v] < k ? V.cnt[v] : k;
+        const int32_t* mi = V.mem_id + v * (k - 1);
+        const uint16_t* md = V.mem_d + v * (k - 1);
+        double s, r;
+        int32_t q = -1;
+        if (c < k) {
+            int64_t ss = 0, rr = 0;
+            for (int32_t j = 0; j < c; j++) {
+                const int64_t b = beta[mi[j]];
+                ss += b * md[j];
+                rr += b;
+            }
+            s = (double)ss;
+            r = (double)rr;
+        } else {
+            q = (int32_t)V.tk[v];
+            const uint64_t Uk = U[q];
+            const uint64_t bk = beta[q];
+            const double tau = ldexp((double)bk, 53) / (double)Uk;
+            int64_t hs = 0, hr = 0, ls = 0, lc = 0;
+            for (int32_t j = 0; j < k - 1; j++) {
+                const uint64_t b = beta[mi[j]];
+                if ((unsigned __int128)b * Uk >= ((unsigned __int128)bk << 53)) {  // heavy: its own weight
+                    hs += (int64_t)b * md[j];
+                    hr += (int64_t)b;
+                } else {
+                    ls += md[j];
+                    lc += 1;
+                }
+            }
+            s = (double)hs + tau * (double)ls;
+            r = (double)hr + tau * (double)lc;
+        }
+        if (count) count[o] = c;
+        if (kth) kth[o] = q >= 0 ? orig[q] : -1;
+        if (S) S[o] = s;
+        if (R) R[o] = r;
+    }
+}
+
 __global__ void k_rch_set_phase(ReachCtl* ctl, int32_t phase) { ctl->phase = phase; }
 
 __global__ void k_rch_rank(const int32_t* __restrict__ order_internal, int64_t n, int32_t* __restrict__ rank) {
@@ -427,20 +490,24 @@ __global__ void k_rch_rank(const int32_t* __restrict__ order_internal, int64_t n
 
 }  // namespace
 
-size_t reach_scratch_bytes(int64_t n) {
+size_t reach_scratch_bytes(int64_t n, int32_t k_weighted) {
     constexpr int W = kReachWords;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     return al(sizeof(ReachCtl)) + 2 * al(sizeof(int32_t) * n) /* rank, src_by_rank */ +
            al(sizeof(int32_t) * n) + 2 * al(sizeof(int64_t) * n) /* cnt, dsum, tk */ +
            3 * al(sizeof(uint64_t) * n * W) + al(sizeof(uint16_t) * n * 64 * W) + 2 * al(sizeof(int32_t) * n) +
            2 * al(sizeof(int32_t) * n) + 2 * al(sizeof(int32_t) * n) + al(sizeof(int32_t) * n) /* sbit */ +
-           al(sizeof(int32_t) * 64 * W) + 1024;
+           al(sizeof(int32_t) * 64 * W) + 1024 +
+           (k_weighted > 0 ? al(sizeof(int32_t) * n * std::max(1, k_weighted - 1)) +
+                                 al(sizeof(uint16_t) * n * std::max(1, k_weighted - 1))
+                           : 0);
 }
 
 void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats) {
     constexpr int W = kReachWords;
     const int64_t n = a.n;
-    if (scratch_size < reach_scratch_bytes(n)) throw HipError{hipErrorOutOfMemory, "reach scratch"};
+    const bool weighted = a.beta != nullptr;
+    if (scratch_size < reach_scratch_bytes(n, weighted ? a.k : 0)) throw HipError{hipErrorOutOfMemory, "reach scratch"};
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     char* p = (char*)scratch;
     auto take = [&](size_t bytes) {
@@ -451,6 +518,7 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
     ReachCtl* ctl = (ReachCtl*)take(sizeof(ReachCtl));
     ReachView V{};
     V.n = n;
+    V.nsrc = a.nsrc > 0 ? a.nsrc : n;
     V.k = a.k;
     V.rp = a.rp;
     V.col = a.col;
@@ -469,13 +537,18 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
     V.lmark = (int32_t*)take(sizeof(int32_t) * n);
     V.sbit = (int32_t*)take(sizeof(int32_t) * n);
     V.src_rank = (int32_t*)take(sizeof(int32_t) * 64 * W);
+    if (weighted) {
+        V.mem_id = (int32_t*)take(sizeof(int32_t) * n * std::max(1, a.k - 1));
+        V.mem_d = (uint16_t*)take(sizeof(uint16_t) * n * std::max(1, a.k - 1));
+    }
     V.flist = (int32_t*)take(sizeof(int32_t) * 2 * n);
     V.cand = (int32_t*)take(sizeof(int32_t) * n);
     V.touched = (int32_t*)take(sizeof(int32_t) * n);
 
-    CCG_HIP(hipMemcpyAsync(sbr, a.order, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    CCG_HIP(hipMemcpyAsync(sbr, a.order, sizeof(int32_t) * V.nsrc, hipMemcpyHostToDevice, st));
     const unsigned gn = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
-    hipLaunchKernelGGL(k_rch_rank, dim3(gn), dim3(256), 0, st, (const int32_t*)sbr, n, rank);
+    fill_u32(st, rank, 0x7FFFFFFFu, (size_t)n);  // nodes that are never sources rank after all
+    hipLaunchKernelGGL(k_rch_rank, dim3(gn), dim3(256), 0, st, (const int32_t*)sbr, V.nsrc, rank);
     fill_u32(st, V.cnt, 0u, (size_t)n);
     fill_u32(st, V.dsum, 0u, (size_t)n * 2);
     fill_u32(st, V.tk, 0u, (size_t)n * 2);
@@ -491,7 +564,7 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
     CCG_HIP(hipGetLastError());
 
     const unsigned gp = (unsigned)a.push_blocks, gm = (unsigned)a.merge_blocks, ga = (unsigned)a.account_blocks;
-    const int64_t nbatches = (n + 64 * W - 1) / (64 * W) + 1;
+    const int64_t nbatches = (V.nsrc + 64 * W - 1) / (64 * W) + 1;
     const int64_t max_cycles = nbatches * (n + 2);
     int64_t cycles = 0;
     int32_t chunk = 16;
@@ -510,7 +583,11 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
         if (cycles > max_cycles) throw HipError{hipErrorLaunchTimeOut, "reachability sampling did not finish"};
         if (chunk < 256) chunk *= 2;
     }
-    hipLaunchKernelGGL(k_rch_out, dim3(gn), dim3(256), 0, st, V, a.orig, a.count, a.distsum, a.T, a.B, a.R);
+    if (weighted)
+        hipLaunchKernelGGL(k_rch_out_beta, dim3(gn), dim3(256), 0, st, V, a.orig, a.beta, a.U, a.count, a.kth, a.S_w,
+                           a.R);
+    else
+        hipLaunchKernelGGL(k_rch_out, dim3(gn), dim3(256), 0, st, V, a.orig, a.count, a.distsum, a.T, a.B, a.R);
     CCG_HIP(hipGetLastError());
     if (stats) {
         stats->cycles = cycles;

@@ -140,3 +140,59 @@ def test_fullsize_sampled_nodes(ctx):
         for j, v in enumerate(nodes):
             for f in FIELDS:
                 assert r[f][v] == ref[f][j], (ib, int(v), f)
+
+
+# ---------------------------------------------------------------- Algorithm 5 (node weights)
+
+WFIELDS = ("count", "kth", "S", "R")
+
+WCASES = [
+    ("gnp-dir", lambda: graphgen.gnp(300, 0.01, 5, directed=True, connect=False), (1, 2, 9, 60)),
+    ("rmat-dir-s12", lambda: graphgen.rmat(12, 8, seed=3, directed=True, component=False), (1, 16, 100)),
+    ("ba-undirected", lambda: graphgen.ba(3000, 3, seed=6), (5, 64)),
+    ("path-dir", lambda: graphgen.csr_from_arcs(500, list(range(499)), list(range(1, 500)), symmetrize=False,
+                                                directed=True), (3, 600)),
+]
+
+
+@pytest.mark.parametrize("name,make,ks", WCASES, ids=[c[0] for c in WCASES])
+def test_reach_weighted_matches_oracle(ctx, name, make, ks):
+    g = make()
+    rg = graphgen.transpose(g)
+    beta = graphgen.node_weights(g.n, 17, zero_frac=0.3)
+    gh = ctx.upload(g)
+    try:
+        for k in ks:
+            for inbound in (False, True):
+                seed = 31 + k
+                _say(f"  {name}: n={g.n} k={k} inbound={inbound}")
+                got = cc.cc_reach_weighted(ctx.handle, gh, beta, k, inbound=inbound, seed=seed)
+                ref = oracle.reach_weighted(g, beta, k, seed, inbound=inbound, threads=8, reverse_graph=rg)
+                for f in WFIELDS:
+                    assert np.array_equal(got[f], ref[f]), f"{name} k={k} inbound={inbound}: {f}"
+    finally:
+        ctx.release(gh)
+
+
+def test_reach_weighted_fullsize_sampled_nodes(ctx):
+    spec = graphgen.WORKLOADS["rmat20dir"]
+    k, seed = spec["k"], spec["sample_seed"]
+    g = graphgen.workload("rmat20dir")
+    beta = graphgen.node_weights(g.n, seed)
+    gh = ctx.upload(g)
+    try:
+        got = cc.cc_reach_weighted(ctx.handle, gh, beta, k, seed=seed)
+        t = cc.cc_last_timing(ctx.handle)
+        _say(f"  weighted outbound: {t['total_ms']:.1f} ms, {t['levels']} levels")
+        with pytest.raises(cc.CCError) as e:
+            cc.cc_reach_weighted(ctx.handle, gh, np.zeros(g.n, np.uint32), k)
+        assert e.value.status == cc.CC_EINVAL
+    finally:
+        ctx.release(gh)
+    rng = np.random.default_rng(seed)
+    deg = np.diff(g.row_ptr)
+    nodes = np.unique(np.concatenate([rng.integers(0, g.n, size=8), [int(np.argmax(deg)), 0]])).astype(np.int32)
+    ref = oracle.reach_weighted(g, beta, k, seed, threads=8, nodes=nodes)
+    for j, v in enumerate(nodes):
+        for f in WFIELDS:
+            assert got[f][v] == ref[f][j], (int(v), f)
