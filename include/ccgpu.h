@@ -284,6 +284,10 @@ typedef struct {
     double* adjusted;      /* k: adjusted weights (tau or the node's weight) */
     double* tau;           /* 1: R / m (0 when every positive node is sampled) */
     int32_t* sample_size;  /* 1 */
+    double* S_beta_err;    /* n: the error estimate of Sec. 4.1 with beta masses (Sec. 5): S_beta_var
+                              plus beta(H) times the beta-weighted mean over HC of
+                              (d(v,u) - d(c(v),u))^2 (0 when HC has no weight), in that order of
+                              double operations: var + (sum / weight(HC)) * weight(H); 0 on samples */
 } cc_weighted_result;
 /* Host only: the sample above.  ids and light hold k entries; *count is the
  * sample size, *R and *m give tau = R/m.  CC_EINVAL without a node of positive

@@ -90,7 +90,7 @@ def _load():
     lib.orc_exact_sums.restype = ctypes.c_int
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
     lib.orc_beta_all.restype = ctypes.c_int
-    lib.orc_beta_all.argtypes = [i64, i32, P, P, P, i64, i32, P, i64, i64, P, i64, i32, P, P]
+    lib.orc_beta_all.argtypes = [i64, i32, P, P, P, i64, i32, P, i64, i64, P, i64, i32, P, P, P]
     lib.orc_reach_beta.restype = ctypes.c_int
     lib.orc_reach_beta.argtypes = [i64, P, P, P, P, P, P, i64, i32, P, i64, i32, P, P, P, P]
     lib.orc_reach_all.restype = ctypes.c_int
@@ -346,9 +346,11 @@ def estimate_weighted(g, beta, k: int, seed: int, eps=None, threads: int = 1, re
     lf = np.ascontiguousarray(light, dtype=np.uint8)
     sel = None if nodes is None else np.ascontiguousarray(nodes, dtype=np.int32)
     cnt = g.n if sel is None else sel.shape[0]
-    out = dict(S_beta=np.empty(cnt, np.float64), S_beta_var=np.empty(cnt, np.float64))
+    out = dict(S_beta=np.empty(cnt, np.float64), S_beta_var=np.empty(cnt, np.float64),
+               S_beta_err=np.empty(cnt, np.float64))
     st = lib.orc_beta_all(g.n, kk, _p(sidx), _p(lf), _p(beta), int(R), int(m), _p(D), int(eps[0]), int(eps[1]),
-                          _p(sel), int(cnt), int(threads), _p(out["S_beta"]), _p(out["S_beta_var"]))
+                          _p(sel), int(cnt), int(threads), _p(out["S_beta"]), _p(out["S_beta_var"]),
+                          _p(out["S_beta_err"]))
     if st not in (0, 4):
         raise OracleError(f"orc_beta_all failed ({st})")
     tau = R / m

@@ -643,7 +643,7 @@ int orc_reach_all(int64_t n, const int64_t* rp, const int32_t* col, const int32_
 typedef struct {
     int64_t n; int32_t k; const int32_t* sidx; const uint8_t* light; const uint32_t* beta; int64_t R; int32_t m;
     const int64_t* D; int64_t num, den; const int32_t* nodes; int64_t nnodes;  /* NULL: all nodes */
-    double* S; double* var; int64_t next; pthread_mutex_t lock; int status;
+    double* S; double* var; double* err; int64_t next; pthread_mutex_t lock; int status;
 } beta_job;
 
 static void* beta_worker(void* arg) {
@@ -665,10 +665,11 @@ static void* beta_worker(void* arg) {
             ovf = s >= LIM;
             J->S[slot] = (double)(int64_t)s;
             J->var[slot] = 0.0;
+            if (J->err) J->err[slot] = 0.0;
         } else {
             int32_t p = orc_pivot((int32_t)k, row);
             int64_t delta = row[p];
-            __int128 H = 0, HC = 0, Lb = 0, Ls = 0, A = 0, B = 0;
+            __int128 H = 0, HC = 0, Lb = 0, Ls = 0, A = 0, B = 0, Hb = 0, HCb = 0, HCsq = 0;
             for (int64_t u = 0; u < n; u++) {
                 if (u == v) continue;
                 int64_t dpu = J->D[u * k + p];
@@ -680,8 +681,11 @@ static void* beta_worker(void* arg) {
                     else Lb += (__int128)J->beta[u] * d;
                 } else if (j >= 0) {
                     HC += (__int128)J->beta[u] * row[j];
+                    HCb += J->beta[u];
+                    HCsq += (__int128)J->beta[u] * (row[j] - dpu) * (row[j] - dpu);
                 } else {
                     H += (__int128)J->beta[u] * dpu;
+                    Hb += J->beta[u];
                 }
             }
             __int128 N = (H + HC + Lb) * J->m + Ls * J->R;
@@ -689,6 +693,12 @@ static void* beta_worker(void* arg) {
             J->S[slot] = (double)(int64_t)N / (double)J->m;
             double t = (double)J->R / (double)J->m;
             J->var[slot] = t * (t * (double)(int64_t)A - (double)(int64_t)B);
+            /* Sec. 4.1 with beta masses (Sec. 5): the L term's variance plus beta(H) times the
+             * beta-weighted mean over HC of (d(v,u) - d(c(v),u))^2 (0 without HC weight) */
+            ovf = ovf || HCsq > (__int128)INT64_MAX;
+            if (J->err)
+                J->err[slot] = J->var[slot] +
+                               (HCb > 0 ? ((double)(int64_t)HCsq / (double)(int64_t)HCb) * (double)(int64_t)Hb : 0.0);
         }
         if (ovf) { pthread_mutex_lock(&J->lock); J->status = ORC_EOVERFLOW; pthread_mutex_unlock(&J->lock); }
     }
@@ -697,12 +707,12 @@ static void* beta_worker(void* arg) {
 
 int orc_beta_all(int64_t n, int32_t k, const int32_t* sidx, const uint8_t* light, const uint32_t* beta, int64_t R,
                  int32_t m, const int64_t* D, int64_t num, int64_t den, const int32_t* nodes, int64_t nnodes,
-                 int32_t threads, double* S, double* var) {
+                 int32_t threads, double* S, double* var, double* err) {
     if (k < 1 || m < 1 || num < 1 || den < 1) return ORC_EINVAL;
     beta_job J;
     J.n = n; J.k = k; J.sidx = sidx; J.light = light; J.beta = beta; J.R = R; J.m = m; J.D = D;
     J.nodes = nodes; J.nnodes = nnodes;
-    J.num = num; J.den = den; J.S = S; J.var = var; J.next = 0; J.status = ORC_OK;
+    J.num = num; J.den = den; J.S = S; J.var = var; J.err = err; J.next = 0; J.status = ORC_OK;
     pthread_mutex_init(&J.lock, NULL);
     if (threads <= 1) {
         beta_worker(&J);

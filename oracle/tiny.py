@@ -268,6 +268,32 @@ def weighted_estimates(dist, beta, samples, light, tau, eps):
     return est, var
 
 
+def weighted_errors(dist, beta, samples, light, tau, eps):
+    """Sec. 5's error estimate: Sec. 4.1 with beta masses -- the variance
+    estimate of the L term plus beta(H) times the beta-weighted mean over HC
+    of (d(v,u) - d(c(v),u))^2 (0 without HC weight); sampled nodes 0."""
+    n = len(dist)
+    C = list(samples)
+    Cset = set(C)
+    _, var = weighted_estimates(dist, beta, samples, light, tau, eps)
+    out = []
+    for v in range(n):
+        if v in Cset:
+            out.append(Fraction(0))
+            continue
+        dists = [dist[v][c] for c in C]
+        cp = C[dists.index(min(dists))]
+        delta = dist[v][cp]
+        others = [u for u in range(n) if u != v]
+        far = [u for u in others if dist[cp][u] > Fraction(delta) / eps]
+        HC = [u for u in far if u in Cset]
+        Hb = sum(beta[u] for u in far if u not in Cset)
+        HCb = sum(beta[u] for u in HC)
+        sq = (sum(beta[u] * Fraction(dist[v][u] - dist[cp][u]) ** 2 for u in HC) / HCb) if HCb else Fraction(0)
+        out.append(var[v] + sq * Hb)
+    return out
+
+
 def reach_weighted_definition(dist, beta, U, k):
     """Sec. 6.2 / Algorithm 5 with exact rationals: ranks r(u) = U(u) /
     (2^53 beta(u)) for beta(u) > 0 (ties by id); per node v the k members of

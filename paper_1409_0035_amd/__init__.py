@@ -54,7 +54,8 @@ class cc_weighted_params(ctypes.Structure):
 
 class cc_weighted_result(ctypes.Structure):
     _fields_ = [("S_beta", ctypes.c_void_p), ("S_beta_var", ctypes.c_void_p), ("samples", ctypes.c_void_p),
-                ("adjusted", ctypes.c_void_p), ("tau", ctypes.c_void_p), ("sample_size", ctypes.c_void_p)]
+                ("adjusted", ctypes.c_void_p), ("tau", ctypes.c_void_p), ("sample_size", ctypes.c_void_p),
+                ("S_beta_err", ctypes.c_void_p)]
 
 
 class cc_reach_weighted_params(ctypes.Structure):
@@ -314,9 +315,9 @@ def cc_estimate_weighted(ctx, g, beta, k: int, seed: int = 0, mode: int = CC_BAT
     p = cc_weighted_params(int(k), int(mode), int(seed), en, ed, beta.ctypes.data)
     out = dict(S_beta=np.empty(n, np.float64), S_beta_var=np.empty(n, np.float64),
                samples=np.empty(k, np.int32), adjusted=np.empty(k, np.float64), tau=np.zeros(1, np.float64),
-               sample_size=np.zeros(1, np.int32))
+               sample_size=np.zeros(1, np.int32), S_beta_err=np.empty(n, np.float64))
     res = cc_weighted_result(*(out[f].ctypes.data for f in ("S_beta", "S_beta_var", "samples", "adjusted", "tau",
-                                                            "sample_size")))
+                                                            "sample_size", "S_beta_err")))
     _check(load_library().cc_estimate_weighted(ctx, g, ctypes.byref(p), ctypes.byref(res)))
     c = int(out["sample_size"][0])
     out["samples"] = out["samples"][:c]

@@ -1649,7 +1649,7 @@ extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, co
         // device block: D, dmat, beta, sidx, samples, light, S, var, flags, small scratch
         const size_t bytes = al(sizeof(int32_t) * (size_t)n * kk) + al(sizeof(int32_t) * (size_t)kk * kk) +
                              al(sizeof(uint32_t) * n) + al(sizeof(int32_t) * n) + al(sizeof(int32_t) * kk) + al(kk) +
-                             2 * al(sizeof(double) * n) + al(sizeof(DevFlags)) + 256;
+                             3 * al(sizeof(double) * n) + al(sizeof(DevFlags)) + 256;
         char* q = (char*)L.arenaW.get(bytes);
         auto take = [&](size_t b) {
             char* x = q;
@@ -1664,6 +1664,7 @@ extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, co
         uint8_t* light_d = (uint8_t*)take(kk);
         double* S = (double*)take(sizeof(double) * n);
         double* var = (double*)take(sizeof(double) * n);
+        double* err = (double*)take(sizeof(double) * n);
         DevFlags* flags = (DevFlags*)take(sizeof(DevFlags));
         void* small = take(256);
         // the traversal and distance rows of cc_estimate, from this sample
@@ -1693,6 +1694,7 @@ extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, co
         ba.eps_den = r.ed;
         ba.S = S;
         ba.var = var;
+        ba.err = err;
         ba.small_scratch = small;
         ba.get_scratch = [&](size_t need) { return L.arena2.get(need); };
         run_beta_epilogue(st, ba, flags);
@@ -1701,6 +1703,8 @@ extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, co
         if (out->S_beta) CCG_HIP(hipMemcpyAsync(out->S_beta, S, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         if (out->S_beta_var)
             CCG_HIP(hipMemcpyAsync(out->S_beta_var, var, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        if (out->S_beta_err)
+            CCG_HIP(hipMemcpyAsync(out->S_beta_err, err, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         CCG_HIP(hipStreamSynchronize(st));
         if (hf.overflow) return fail(CC_EOVERFLOW, "cc_estimate_weighted: a weighted sum leaves the exact range");
         const double tau = (double)R / (double)m;

@@ -16,8 +16,11 @@
 //   k_beta_maxd      largest distance (the tables' length)
 //   k_beta_hist      hw[i][d] = sum of beta(u) over u outside C with d(c_i,u) = d,
 //                    per block in LDS when the table fits
-//   k_beta_suffix    WT[i][t] = sum_{d >= t} d * hw[i][d]; exact S_beta(c_i) =
-//                    WT[i][0] + sum_j beta(c_j) d(c_i, c_j)
+//   k_beta_suffix    WT[i][t] = sum_{d >= t} d * hw[i][d] and WC[i][t] = sum_{d >= t}
+//                    hw[i][d]; exact S_beta(c_i) = WT[i][0] + sum_j beta(c_j) d(c_i, c_j)
+// The error estimate (Sec. 4.1 with beta masses, Sec. 5) adds to the variance
+// estimate beta(H) (from WC) times the beta-weighted mean over HC of
+// (d(v,c_i) - d(c(v),c_i))^2, 0 when HC has no weight.
 //   k_beta_estimate  one lane per node: pivot, Delta, the split of the samples,
 //                    the estimate and the variance estimate
 #include "internal.h"
@@ -76,34 +79,52 @@ __global__ __launch_bounds__(kBlock) void k_beta_suffix(const unsigned long long
                                                         int64_t hlen, const int32_t* __restrict__ dmat,
                                                         const int32_t* __restrict__ samples,
                                                         const uint32_t* __restrict__ beta, int64_t* __restrict__ WT,
-                                                        int64_t* __restrict__ Sx, DevFlags* flags) {
-    __shared__ int64_t ws[kBlock / 64];
+                                                        int64_t* __restrict__ WC, int64_t* __restrict__ Sx,
+                                                        DevFlags* flags) {
+    __shared__ int64_t ws[kBlock / 64], wc[kBlock / 64];
     const int32_t i = blockIdx.x;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     int64_t* wt = WT + (int64_t)i * hlen;
-    int64_t carry = 0;
+    int64_t* wcn = WC + (int64_t)i * hlen;
+    int64_t carry = 0, carry_c = 0;
     bool ovf = false;
     for (int64_t top = hlen - 1; top >= 0; top -= kBlock) {
         const int64_t d = top - threadIdx.x;
-        int64_t s = 0;
+        int64_t s = 0, c = 0;
         if (d >= 0) {
             const unsigned long long h = hw[(int64_t)i * hlen + d];
             unsigned long long prod = 0;
             const bool o = __builtin_mul_overflow(h, (unsigned long long)d, &prod);
             ovf = ovf || o || prod > (unsigned long long)INT64_MAX;
             s = (int64_t)prod;
+            c = (int64_t)h;
         }
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const int64_t y = __shfl_up(s, off);
-            if (lane >= off) s += y;
+            const int64_t y = __shfl_up(s, off), z = __shfl_up(c, off);
+            if (lane >= off) {
+                s += y;
+                c += z;
+            }
         }
-        if (lane == 63) ws[wave] = s;
+        if (lane == 63) {
+            ws[wave] = s;
+            wc[wave] = c;
+        }
         __syncthreads();
-        int64_t pre = carry;
-        for (int w = 0; w < wave; w++) pre += ws[w];
-        if (d >= 0) wt[d] = pre + s;
-        for (int w = 0; w < kBlock / 64; w++) carry += ws[w];
+        int64_t pre = carry, pre_c = carry_c;
+        for (int w = 0; w < wave; w++) {
+            pre += ws[w];
+            pre_c += wc[w];
+        }
+        if (d >= 0) {
+            wt[d] = pre + s;
+            wcn[d] = pre_c + c;
+        }
+        for (int w = 0; w < kBlock / 64; w++) {
+            carry += ws[w];
+            carry_c += wc[w];
+        }
         __syncthreads();
     }
     // the samples' own part: sum_j beta(c_j) d(c_i, c_j)
@@ -125,7 +146,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
     const int32_t* __restrict__ D, int64_t n, int32_t k, const int32_t* __restrict__ dmat,
     const int32_t* __restrict__ sidx, const int32_t* __restrict__ samples, const uint32_t* __restrict__ beta,
     const uint8_t* __restrict__ light, int64_t R, int32_t m, int64_t num, int64_t den, const int64_t* __restrict__ WT,
-    int64_t hlen, const int64_t* __restrict__ Sx, double* S, double* var, DevFlags* flags) {
+    const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, double* S, double* var, double* err,
+    DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     bool ovf = false;
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
@@ -135,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
             ovf = ovf || x >= LIM;
             if (S) S[v] = (double)x;
             if (var) var[v] = 0.0;
+            if (err) err[v] = 0.0;
             continue;
         }
         const int32_t* row = D + v * k;
@@ -148,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
         }
         const int64_t delta = best;
         const int32_t* drow = dmat + (int64_t)p * k;
-        int64_t HC = 0, Lb = 0, Ls = 0, A = 0, B = 0;
+        int64_t HC = 0, Lb = 0, Ls = 0, A = 0, B = 0, HCb = 0, HCsq = 0;
         bool e = false;
         for (int32_t i = 0; i < k; i++) {
             const int64_t d = row[i];
@@ -164,21 +187,26 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
                     e = e || __builtin_mul_overflow(b, d, &t) || __builtin_add_overflow(Lb, t, &Lb);
                 }
             } else {  // HC
-                e = e || __builtin_mul_overflow(b, d, &t) || __builtin_add_overflow(HC, t, &HC);
+                const int64_t df = d - drow[i];
+                int64_t q = 0;
+                HCb += b;
+                e = e || __builtin_mul_overflow(b, d, &t) || __builtin_add_overflow(HC, t, &HC) ||
+                    __builtin_mul_overflow(df * df, b, &q) || __builtin_add_overflow(HCsq, q, &HCsq);
             }
         }
         const int64_t thr = delta * den / num;  // H: nodes outside C at distance > floor(Delta/eps)
         const int64_t H = thr + 1 < hlen ? WT[(int64_t)p * hlen + thr + 1] : 0;
+        const int64_t Hb = thr + 1 < hlen ? WC[(int64_t)p * hlen + thr + 1] : 0;
         int64_t s1 = 0, s2 = 0, s3 = 0, N = 0;
         e = e || __builtin_add_overflow(H, HC, &s1) || __builtin_add_overflow(s1, Lb, &s1) ||
             __builtin_mul_overflow(s1, (int64_t)m, &s2) || __builtin_mul_overflow(Ls, R, &s3) ||
             __builtin_add_overflow(s2, s3, &N) || N >= LIM;
         ovf = ovf || e;
         if (S) S[v] = (double)N / (double)m;
-        if (var) {
-            const double tt = (double)R / (double)m;
-            var[v] = tt * (tt * (double)A - (double)B);
-        }
+        const double tt = (double)R / (double)m;
+        const double vv = tt * (tt * (double)A - (double)B);
+        if (var) var[v] = vv;
+        if (err) err[v] = vv + (HCb > 0 ? ((double)HCsq / (double)HCb) * (double)Hb : 0.0);
     }
     if (ovf) flags->overflow = 1;
 }
@@ -191,7 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
     const int32_t* __restrict__ D, int64_t n, int32_t k, const int32_t* __restrict__ dmat,
     const int32_t* __restrict__ sidx, const int32_t* __restrict__ samples, const uint32_t* __restrict__ beta,
     const uint8_t* __restrict__ light, int64_t R, int32_t m, int64_t num, int64_t den, const int64_t* __restrict__ WT,
-    int64_t hlen, const int64_t* __restrict__ Sx, double* S, double* var, DevFlags* flags) {
+    const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, double* S, double* var, double* err,
+    DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     const int g = threadIdx.x & (G - 1);
     const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
@@ -205,6 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
                 ovf = ovf || x >= LIM;
                 if (S) S[v] = (double)x;
                 if (var) var[v] = 0.0;
+                if (err) err[v] = 0.0;
             }
             continue;
         }
@@ -231,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
         const int32_t p = bi;
         const int64_t delta = best;
         const int32_t* drow = dmat + (int64_t)p * k;
-        int64_t HC = 0, Lb = 0, Ls = 0, A = 0, B = 0;
+        int64_t HC = 0, Lb = 0, Ls = 0, A = 0, B = 0, HCb = 0, HCsq = 0;
         bool e = false;
         for (int32_t c = g; c < pieces; c += G) {
             const int4 x = row[c];
@@ -252,7 +282,11 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
                         e = e || __builtin_mul_overflow(b, d, &t) || __builtin_add_overflow(Lb, t, &Lb);
                     }
                 } else {
-                    e = e || __builtin_mul_overflow(b, d, &t) || __builtin_add_overflow(HC, t, &HC);
+                    const int64_t df = d - drow[i];
+                    int64_t qq = 0;
+                    HCb += b;
+                    e = e || __builtin_mul_overflow(b, d, &t) || __builtin_add_overflow(HC, t, &HC) ||
+                        __builtin_mul_overflow(df * df, b, &qq) || __builtin_add_overflow(HCsq, qq, &HCsq);
                 }
             }
         }
@@ -262,22 +296,25 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
         for (int off = G / 2; off > 0; off >>= 1) {
             const int64_t a1 = __shfl_xor(HC, off, G), a2 = __shfl_xor(Lb, off, G), a3 = __shfl_xor(Ls, off, G);
             const int64_t a4 = __shfl_xor(A, off, G), a5 = __shfl_xor(B, off, G);
+            const int64_t a6 = __shfl_xor(HCb, off, G), a7 = __shfl_xor(HCsq, off, G);
             e = e || __builtin_add_overflow(HC, a1, &HC) || __builtin_add_overflow(Lb, a2, &Lb) ||
                 __builtin_add_overflow(Ls, a3, &Ls) || __builtin_add_overflow(A, a4, &A) ||
-                __builtin_add_overflow(B, a5, &B);
+                __builtin_add_overflow(B, a5, &B) || __builtin_add_overflow(HCb, a6, &HCb) ||
+                __builtin_add_overflow(HCsq, a7, &HCsq);
         }
         if (g == 0) {
             const int64_t thr = delta * den / num;
             const int64_t H = thr + 1 < hlen ? WT[(int64_t)p * hlen + thr + 1] : 0;
+            const int64_t Hb = thr + 1 < hlen ? WC[(int64_t)p * hlen + thr + 1] : 0;
             int64_t s1 = 0, s2 = 0, s3 = 0, N = 0;
             e = e || __builtin_add_overflow(H, HC, &s1) || __builtin_add_overflow(s1, Lb, &s1) ||
                 __builtin_mul_overflow(s1, (int64_t)m, &s2) || __builtin_mul_overflow(Ls, R, &s3) ||
                 __builtin_add_overflow(s2, s3, &N) || N >= LIM;
             if (S) S[v] = (double)N / (double)m;
-            if (var) {
-                const double tt = (double)R / (double)m;
-                var[v] = tt * (tt * (double)A - (double)B);
-            }
+            const double tt = (double)R / (double)m;
+            const double vv = tt * (tt * (double)A - (double)B);
+            if (var) var[v] = vv;
+            if (err) err[v] = vv + (HCb > 0 ? ((double)HCsq / (double)HCb) * (double)Hb : 0.0);
         }
         ovf = ovf || e;
     }
@@ -300,12 +337,14 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     CCG_HIP(hipMemcpyAsync(&maxd, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     CCG_HIP(hipStreamSynchronize(st));
     const int64_t hlen = (int64_t)maxd + 2;
-    const size_t need = al(sizeof(uint64_t) * (size_t)k * hlen) * 2 + al(sizeof(int64_t) * (size_t)k);
+    const size_t need = al(sizeof(uint64_t) * (size_t)k * hlen) * 3 + al(sizeof(int64_t) * (size_t)k);
     void* scr = a.get_scratch(need);
     char* q = (char*)scr;
     unsigned long long* hw = (unsigned long long*)q;
     q += al(sizeof(uint64_t) * (size_t)k * hlen);
     int64_t* WT = (int64_t*)q;
+    q += al(sizeof(uint64_t) * (size_t)k * hlen);
+    int64_t* WC = (int64_t*)q;
     q += al(sizeof(uint64_t) * (size_t)k * hlen);
     int64_t* Sx = (int64_t*)q;
     fill_u32(st, hw, 0u, (size_t)k * hlen * 2);
@@ -315,22 +354,22 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     hipLaunchKernelGGL(k_beta_hist, dim3(hb), dim3(kBlock), use_lds ? lds : 0, st, a.D, n, k, a.sidx, a.beta, hlen, hw,
                        use_lds);
     hipLaunchKernelGGL(k_beta_suffix, dim3((unsigned)k), dim3(kBlock), 0, st, (const unsigned long long*)hw, k, hlen,
-                       a.dmat, a.samples, a.beta, WT, Sx, flags);
+                       a.dmat, a.samples, a.beta, WT, WC, Sx, flags);
     const int32_t pieces = k % 4 == 0 ? k / 4 : 0;
     const int G = pieces >= 16 ? 16 : (pieces >= 8 ? 8 : (pieces >= 4 ? 4 : 0));
     const unsigned eb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n * (G ? G : 1) + kBlock - 1) / kBlock, 16384));
 #define CCG_BETA_ROWS(GG)                                                                                            \
     hipLaunchKernelGGL((k_beta_estimate_rows<GG>), dim3(eb), dim3(kBlock), 0, st, a.D, n, k, a.dmat, a.sidx,          \
-                       a.samples, a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT, hlen,           \
-                       (const int64_t*)Sx, a.S, a.var, flags)
+                       a.samples, a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT,                 \
+                       (const int64_t*)WC, hlen, (const int64_t*)Sx, a.S, a.var, a.err, flags)
     switch (G) {
         case 16: CCG_BETA_ROWS(16); break;
         case 8: CCG_BETA_ROWS(8); break;
         case 4: CCG_BETA_ROWS(4); break;
         default:
             hipLaunchKernelGGL(k_beta_estimate, dim3(eb), dim3(kBlock), 0, st, a.D, n, k, a.dmat, a.sidx, a.samples,
-                               a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT, hlen,
-                               (const int64_t*)Sx, a.S, a.var, flags);
+                               a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT,
+                               (const int64_t*)WC, hlen, (const int64_t*)Sx, a.S, a.var, a.err, flags);
     }
 #undef CCG_BETA_ROWS
     CCG_HIP(hipGetLastError());

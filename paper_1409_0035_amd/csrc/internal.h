@@ -528,6 +528,7 @@ struct BetaArgs {
     int64_t eps_num = 1, eps_den = 1;
     double* S = nullptr;
     double* var = nullptr;
+    double* err = nullptr;             // Sec. 4.1's error estimate with beta masses (optional)
     void* small_scratch = nullptr;     // 256 bytes
     std::function<void*(size_t)> get_scratch;  // device buffer of at least the given size
 };

@@ -1,6 +1,6 @@
 """GPU parity for the node-weighted estimate of Sec. 5 (Algorithm 3): the
-sample, tau and adjusted weights equal the oracle's; S_beta and its variance
-estimate are bit-identical (both sides: the same exact integers, one
+sample, tau and adjusted weights equal the oracle's; S_beta, its variance
+estimate and its error estimate are bit-identical (both sides: the same exact integers, one
 division for the estimate and the same order of double operations for the
 variance; the bar is a relative error of 1e-12)."""
 import sys
@@ -31,7 +31,7 @@ def _check(got, ref):
     assert (got["samples"] == ref["samples"]).all()
     assert got["tau"] == ref["tau"]
     assert (got["adjusted"] == ref["adjusted"]).all()
-    for f in ("S_beta", "S_beta_var"):
+    for f in ("S_beta", "S_beta_var", "S_beta_err"):
         a, b = got[f], ref[f]
         assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1.0)), f
         assert (a == b).all(), f + " (not bit-identical)"
@@ -116,3 +116,4 @@ def test_weighted_fullsize_sampled_nodes(ctx):
     for j, v in enumerate(nodes):
         assert got["S_beta"][v] == ref["S_beta"][j], int(v)
         assert got["S_beta_var"][v] == ref["S_beta_var"][j], int(v)
+        assert got["S_beta_err"][v] == ref["S_beta_err"][j], int(v)

@@ -669,9 +669,11 @@ def test_weighted_vs_bruteforce(seed):
     out = oracle.estimate_weighted(g, beta, k, 77 + seed, eps=eps, reverse_graph=rg)
     tau = Fraction(out["R"], out["m"])
     est, var = tiny.weighted_estimates(d, beta, list(out["samples"]), list(out["light"]), tau, Fraction(*eps))
+    err = tiny.weighted_errors(d, beta, list(out["samples"]), list(out["light"]), tau, Fraction(*eps))
     for v in range(g.n):
         assert out["S_beta"][v] == float(est[v]), v  # one correctly rounded division of exact integers
         assert abs(out["S_beta_var"][v] - float(var[v])) <= 1e-12 * max(1.0, abs(float(var[v]))), v
+        assert abs(out["S_beta_err"][v] - float(err[v])) <= 1e-12 * max(1.0, abs(float(err[v]))), v
 
 
 def test_weighted_exact_when_every_positive_node_is_sampled():
@@ -766,3 +768,28 @@ def test_reach_weighted_unit_weights_and_small_sets():
     o = oracle.reach_weighted(g, beta, 20, 5)
     assert (o["count"] == 8).all() and (o["R"] == 8).all() and (o["S"] == 36).all() and (o["kth"] == -1).all()
 
+
+
+def test_weighted_error_reduces_to_unit_weights():
+    """With every weight 1 the H term of the weighted error estimate is the
+    one of Sec. 4.1: |H| times the mean squared pivot error over HC."""
+    g = graphgen.grid(8, 7, 8)
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx)
+    beta = [1] * g.n
+    samples = [3, 17, 30, 44, 51]
+    out = oracle.estimate_weighted(g, beta, 5, 0, eps=(1, 2), sample=(samples, [True] * 5, g.n, 5))
+    _, var = tiny.weighted_estimates(d, beta, samples, [True] * 5, Fraction(g.n, 5), Fraction(1, 2))
+    ref = oracle.estimate_all(g, samples, eps=(1, 2))
+    for v in range(g.n):
+        if v in samples:
+            continue
+        # the unweighted S_err is the L variance term (ratio form) plus the same H term
+        hterm = float(out["S_beta_err"][v] - out["S_beta_var"][v])
+        row = ref["D"][v]
+        p = int(np.argmin(row))
+        thr = Fraction(int(row[p]) * 2)
+        far = [u for u in range(g.n) if u != v and d[samples[p]][u] > thr]
+        hc = [u for u in far if u in samples]
+        h = [u for u in far if u not in samples]
+        want = (sum((d[v][u] - d[samples[p]][u]) ** 2 for u in hc) / len(hc)) * len(h) if hc else 0
+        assert abs(hterm - float(want)) <= 1e-9 * max(1.0, float(want)), v
