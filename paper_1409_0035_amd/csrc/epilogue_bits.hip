@@ -114,8 +114,27 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
     bool any_ovf = false, any_unreached = false;
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
         const int32_t fl = sv.fill(v);
-        int32_t delta = -1, p = 0, last = 0;
-        int64_t sum = 0;
+        const int32_t j = sidx[sv.noff + v] >= 0 ? sidx[sv.noff + v] - bit_base : -1;
+        // One pass over the levels.  The pivot and Delta are known at the
+        // first non-empty level, and with them the pivot's L mask, so the sum
+        // over L cap C is taken in the same pass: every earlier level is empty
+        // and adds |Lmask| (each of those samples is still missing there).
+        int32_t delta = -1, p = 0, last = 0, lcnum = 0;
+        int64_t sum = 0, lcsum = 0;
+        uint64_t lm[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) lm[w] = 0;
+        auto take_lmask = [&](int32_t d, int32_t piv) {
+            int64_t t = (int64_t)d * ed / en;
+            if (t > lmax) t = lmax;
+            lcnum = 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                lm[w] = lmask[((int64_t)piv * (lmax + 1) + t) * W + w];
+                lcnum += __popcll(lm[w]);
+            }
+            lcsum = (int64_t)d * lcnum;
+        };
         for (int32_t L = 0; L <= lmax; L++) {
             uint64_t s[W];
             mask_at<W>(sv, L, fl, v, lastmask, s);
@@ -127,16 +146,28 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
 #pragma unroll
                 for (int w = W - 1; w >= 0; w--)
                     if (s[w]) p = w * 64 + __ffsll((unsigned long long)s[w]) - 1;
+                if (j < 0) take_lmask(delta, p);
             }
-            if (L < lmax) sum += k - c;
+            if (L < lmax) {
+                sum += k - c;
+                if (delta >= 0) {
+#pragma unroll
+                    for (int w = 0; w < W; w++) lcsum += __popcll(lm[w] & ~s[w]);
+                }
+            }
             last = c;
         }
         const bool unreached = last != k;
-        const int32_t j = sidx[sv.noff + v] >= 0 ? sidx[sv.noff + v] - bit_base : -1;
         double hyb, samp;
         int64_t piv, pub;
         bool ovf = false;
-        if (delta < 0) delta = 0;
+        if (delta < 0) {  // no sample reaches v: pivot 0 at Delta 0, every level empty
+            delta = 0;
+            if (j < 0) {
+                take_lmask(0, 0);
+                lcsum = (int64_t)lmax * lcnum;
+            }
+        }
         if (j >= 0) {
             const int64_t S = src_sum[j];
             hyb = samp = (double)S;
@@ -144,22 +175,6 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
             ovf = S >= LIM;
         } else {
             const int64_t thr = (int64_t)delta * ed;
-            int64_t t = thr / en;
-            if (t > lmax) t = lmax;
-            uint64_t lm[W];
-            int32_t lcnum = 0;
-#pragma unroll
-            for (int w = 0; w < W; w++) {
-                lm[w] = lmask[((int64_t)p * (lmax + 1) + t) * W + w];
-                lcnum += __popcll(lm[w]);
-            }
-            int64_t lcsum = 0;
-            for (int32_t L = 0; L < lmax; L++) {
-                uint64_t s[W];
-                mask_at<W>(sv, L, fl, v, lastmask, s);
-#pragma unroll
-                for (int w = 0; w < W; w++) lcsum += __popcll(lm[w] & ~s[w]);
-            }
             const int64_t tix = thr / en + 1;  // d > floor(Delta/eps)  <=>  d >= tix
             int64_t hnum = 0, hsum = 0;
             if (tix < tlen) {
