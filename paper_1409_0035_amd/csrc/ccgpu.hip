@@ -1792,6 +1792,7 @@ extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const
         };
         ReachArgs a;
         a.n = n;
+        a.arcs = g->dg.arcs;
         a.k = p->k;
         a.rp = p->inbound ? g->dg.rp : g->dg.rrp;
         a.col = p->inbound ? g->dg.col : g->dg.rcol;
@@ -1808,7 +1809,7 @@ extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const
         CCG_HIP(hipMemcpyAsync(Ud, U_i.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, st));
         a.beta = bd;
         a.U = Ud;
-        const size_t need = reach_scratch_bytes(n, p->k);
+        const size_t need = reach_scratch_bytes(n, a.arcs, p->k);
         ReachStats rs;
         run_reach(st, a, L.arena.get(need), need, &rs);
         if (out->count) CCG_HIP(hipMemcpyAsync(out->count, a.count, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
@@ -1868,6 +1869,7 @@ extern "C" cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const
         char* ob = (char*)L.arena2.get(outb);
         ReachArgs a;
         a.n = n;
+        a.arcs = g->dg.arcs;
         a.k = p->k;
         a.rp = p->inbound ? g->dg.rp : g->dg.rrp;
         a.col = p->inbound ? g->dg.col : g->dg.rcol;
@@ -1878,7 +1880,7 @@ extern "C" cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const
         a.T = a.distsum + n;
         a.B = (double*)(a.T + n);
         a.R = a.B + n;
-        const size_t need = reach_scratch_bytes(n);
+        const size_t need = reach_scratch_bytes(n, a.arcs);
         ReachStats rs;
         run_reach(st, a, L.arena.get(need), need, &rs);
         if (out->count) CCG_HIP(hipMemcpyAsync(out->count, a.count, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));

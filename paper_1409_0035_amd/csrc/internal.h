@@ -535,9 +535,10 @@ struct BetaArgs {
 void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags);
 
 // Outbound / inbound reachability sampling (Sec. 6.2, Algorithm 4).
-constexpr int kReachWords = 4;  // 256 sources of consecutive ranks per batch
+constexpr int kReachWords = 16;  // up to 1024 sources of consecutive ranks per batch
 struct ReachArgs {
     int64_t n = 0;
+    int64_t arcs = 0;  // propagation arcs (rp[n])
     int32_t k = 0;
     const uint32_t* rp = nullptr;  // propagation arcs: outbound the in-arcs, inbound the out-arcs
     const int32_t* col = nullptr;
@@ -567,7 +568,7 @@ struct ReachStats {
     int64_t levels = 0;   // BFS levels run over all batches
     bool overflow = false;  // some level above 65535: the result is not valid
 };
-size_t reach_scratch_bytes(int64_t n, int32_t k_weighted = 0);
+size_t reach_scratch_bytes(int64_t n, int64_t arcs, int32_t k_weighted = 0);
 void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats);
 
 }  // namespace ccg

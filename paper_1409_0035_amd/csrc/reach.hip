@@ -10,9 +10,13 @@
 // reach u), adding u to the sample of every node it meets; a node that holds
 // enough lower-ranked members stops the search.
 //
-// Batched here: 64W sources of consecutive ranks advance together as one
-// bit-parallel BFS (bit b = the b-th source of the batch, so bit order is rank
-// order).  The stopping rule is the exact one (see the design notes): a node x
+// Batched here: up to 64W sources of consecutive ranks advance together as
+// one bit-parallel BFS (bit b = the b-th source of the batch, so bit order is
+// rank order).  The first batches are smaller (256, then 512 sources): while
+// every node still collects, each extra word costs on every arc, whereas the
+// later batches touch few nodes and are bound by the fixed cost of a cycle,
+// so fewer, larger batches pay off there.  Kernels touch only the words the
+// current batch uses.  The stopping rule is the exact one (see the design notes): a node x
 // stops source u when x holds at least k + 1 members ranked before u,
 // counting x itself when it ranks before u -- then every node reaching x has k
 // such members other than itself and none of them needs u.  Inside a batch x
@@ -21,7 +25,7 @@
 // members from earlier batches take no part.
 //
 // A source that already holds more than k members of its own can pass its
-// bit to nobody, so it is skipped: a batch takes the next 64W sources in rank
+// bit to nobody, so it is skipped: a batch takes the next sources in rank
 // order that can still pass their bit (bit order stays rank order, and every
 // source skipped between them would have reached no node).
 //
@@ -40,6 +44,13 @@ namespace ccg {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int32_t kFirstBatch = 256;  // sources in the first batch; doubled per batch up to 64W
+// Frontier entries are chunks of at most kChunk propagation arcs of a node
+// (node << 32 | offset of the chunk's first arc), so a node with a huge
+// degree is spread over many waves instead of holding up the level in one.
+constexpr uint32_t kChunk = 256;
+
+__host__ __device__ inline int64_t frontier_cap(int64_t n, int64_t arcs) { return n + arcs / kChunk + 1; }
 
 enum : int32_t { kLevel = 1, kAccount = 2, kFinished = 3 };
 
@@ -58,7 +69,7 @@ struct ReachCtl {
     int32_t nt;      // nodes touched in this batch
     uint32_t ticket;
     int32_t overflow;  // a recorded level above 65535
-    int32_t pad;
+    int32_t nw;        // words the current batch uses
     int64_t levels;  // levels run, all batches
 };
 
@@ -81,7 +92,8 @@ struct ReachView {
     uint16_t* lev;      // [n][64W] level at which each bit arrived (open nodes)
     int32_t* stamp;     // batch that last touched the node
     int32_t* lmark;     // level stamp that last queued the node
-    int32_t* flist;     // [2][n] frontier lists
+    uint64_t* flist;    // [2][fcap] frontier chunk lists
+    int64_t fcap;
     int32_t* cand;      // [n] nodes with pending bits this level
     int32_t* touched;   // [n] nodes touched in this batch
     // node-weighted sampling (Algorithm 5): the first k-1 members of each
@@ -129,37 +141,88 @@ __device__ __forceinline__ void first_bits(const uint64_t (&s)[W], int64_t q, ui
     }
 }
 
+// List appends staged per wave in LDS: one global atomic per flush instead of
+// one per wave and call (hundreds of thousands of waves appending to one
+// counter serialise on it).  put() and flush() are called with every lane of
+// the wave active, so the count stays the same in all lanes.
+constexpr int kWaveStage = 512;
+
+struct WaveList {
+    int32_t* items;  // this wave's LDS segment of kWaveStage entries
+    int32_t* gcount;
+    int32_t* glist;
+    int32_t count;
+    __device__ __forceinline__ void flush() {
+        if (count == 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(gcount, count);
+        base = __shfl(base, 0);
+        for (int t = lane_id(); t < count; t += 64) glist[base + t] = items[t];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        count = 0;
+    }
+    __device__ __forceinline__ void put(bool pred, int32_t x) {
+        const uint64_t m = __ballot(pred);
+        if (!m) return;
+        const int c = (int)__popcll(m);
+        if (count + c > kWaveStage) flush();
+        if (pred) items[count + (int)__popcll(m & lanemask_lt())] = x;
+        count += c;
+    }
+};
+
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_rch_push(ReachCtl* ctl, ReachView V) {
     if (ctl->phase != kLevel) return;
     const int32_t nf = ctl->nf;
-    const int32_t* F = V.flist + (int64_t)ctl->fsel * V.n;
+    const uint64_t* F = V.flist + (int64_t)ctl->fsel * V.fcap;
     const int32_t gl = ctl->gl;
     const int64_t t0 = ctl->t0;
+    const int32_t nwa = ctl->nw;
     const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    __shared__ int32_t stage[kBlock / 64][kWaveStage];
+    WaveList cand{stage[wave], &ctl->nc, V.cand, 0};
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t e = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); e < nf; e += nwaves) {
-        const int64_t v = F[e];
+    for (int64_t e = (int64_t)blockIdx.x * (kBlock / 64) + wave; e < nf; e += nwaves) {
+        const uint64_t ent = F[e];
+        const int64_t v = (int64_t)(ent >> 32);
         uint64_t f[W];
 #pragma unroll
-        for (int j = 0; j < W; j++) f[j] = V.fr[v * W + j];
-        const uint32_t a0 = V.rp[v], a1 = V.rp[v + 1];
-        for (uint32_t a = a0 + lane; a < a1; a += 64) {
-            const int64_t w = V.col[a];
-            if (held_before(V, w, t0) > V.k) continue;  // holds more than k earlier members: takes no part
-            uint64_t any = 0;
-#pragma unroll
-            for (int j = 0; j < W; j++) {
-                const uint64_t b = f[j] & ~V.seen[w * W + j];
-                if (b) atomicOr((unsigned long long*)&V.nx[w * W + j], (unsigned long long)b);
-                any |= b;
-            }
+        for (int j = 0; j < W; j++) f[j] = j < nwa ? V.fr[v * W + j] : 0ull;
+        const uint32_t a0 = V.rp[v] + (uint32_t)ent, a1 = min(V.rp[v + 1], a0 + kChunk);
+        for (uint32_t base = a0; base < a1; base += 64) {  // same trip count in every lane
+            const uint32_t a = base + lane;
+            int64_t w = 0;
             bool first = false;
-            if (any && V.lmark[w] != gl) first = atomicExch(&V.lmark[w], gl) != gl;
-            const int idx = wave_append(&ctl->nc, first);
-            if (first) V.cand[idx] = (int32_t)w;
+            if (a < a1) w = V.col[a];
+            // a node holding more than k earlier members takes no part
+            if (a < a1 && held_before(V, w, t0) <= V.k) {
+                uint64_t any = 0;
+#pragma unroll
+                for (int j = 0; j < W; j++) {
+                    if (!f[j]) continue;
+                    const uint64_t b = f[j] & ~V.seen[w * W + j];
+                    if (!b) continue;
+                    any |= b;
+                    // only bits not already pending need the atomic, so a popular
+                    // target stops taking atomics once it holds the level's bits
+                    // (a stale read only lets a redundant atomic through)
+                    const uint64_t r =
+                        b & ~__hip_atomic_load(&V.nx[w * W + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (r) atomicOr((unsigned long long*)&V.nx[w * W + j], (unsigned long long)r);
+                }
+                if (any && V.lmark[w] != gl) first = atomicExch(&V.lmark[w], gl) != gl;
+            }
+            cand.put(first, (int32_t)w);
         }
     }
+    cand.flush();
 }
 
 template <int W>
@@ -169,58 +232,83 @@ __global__ __launch_bounds__(kBlock) void k_rch_merge(ReachCtl* ctl, ReachView V
     const int32_t level = ctl->level;
     const int32_t batch = ctl->batch;
     const int64_t t0 = ctl->t0;
-    int32_t* Fn = V.flist + (int64_t)(ctl->fsel ^ 1) * V.n;
+    const int32_t nwa = ctl->nw;
+    uint64_t* Fn = V.flist + (int64_t)(ctl->fsel ^ 1) * V.fcap;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    __shared__ int32_t stage[kBlock / 64][kWaveStage];
+    WaveList tl{stage[wave], &ctl->nt, V.touched, 0};
     bool ovf = false;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nc; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t w = V.cand[i];
-        uint64_t nw[W], s[W];
-        uint64_t any = 0;
-#pragma unroll
-        for (int j = 0; j < W; j++) {
-            const uint64_t p = V.nx[w * W + j];
-            V.nx[w * W + j] = 0;
-            const uint64_t old = V.seen[w * W + j];
-            nw[j] = p & ~old;
-            s[j] = old | nw[j];
-            V.seen[w * W + j] = s[j];
-            any |= nw[j];
-        }
+    // same trip count in every lane of a block (the lists are appended to with every lane active)
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < nc; i0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = i0 + threadIdx.x;
         bool touch = false, pass = false;
-        if (V.stamp[w] != batch) {  // each candidate appears once per level
-            V.stamp[w] = batch;
-            touch = true;
-        }
-        if (any) {
-            const int64_t held = held_before(V, w, t0);
-            if (V.cnt[w] < V.k) {  // still collecting members: remember when each bit arrived
-                if (level > 65535) ovf = true;
-#pragma unroll
-                for (int j = 0; j < W; j++) {
-                    uint64_t x = nw[j];
-                    while (x) {
-                        const int b = __ffsll((unsigned long long)x) - 1;
-                        x &= x - 1;
-                        V.lev[w * (64 * W) + j * 64 + b] = (uint16_t)level;
-                    }
-                }
-            }
-            // bit b moves on while the members ranked before it number at most k
-            uint64_t keep[W];
-            first_bits<W>(s, (int64_t)V.k - held + 1, keep);
-            uint64_t fa = 0;
+        const int64_t w = i < nc ? V.cand[i] : 0;
+        if (i < nc) {
+            uint64_t nw[W], s[W];
+            uint64_t any = 0;
 #pragma unroll
             for (int j = 0; j < W; j++) {
-                const uint64_t f = nw[j] & keep[j];
-                V.fr[w * W + j] = f;
-                fa |= f;
+                nw[j] = 0;
+                s[j] = 0;
+                if (j >= nwa) continue;
+                const uint64_t p = V.nx[w * W + j];
+                const uint64_t old = V.seen[w * W + j];
+                nw[j] = p & ~old;
+                s[j] = old | nw[j];
+                if (p) V.nx[w * W + j] = 0;
+                if (nw[j]) V.seen[w * W + j] = s[j];
+                any |= nw[j];
             }
-            pass = fa != 0;
+            if (V.stamp[w] != batch) {  // each candidate appears once per level
+                V.stamp[w] = batch;
+                touch = true;
+            }
+            if (any) {
+                const int64_t held = held_before(V, w, t0);
+                if (V.cnt[w] < V.k) {  // still collecting members: remember when each bit arrived
+                    if (level > 65535) ovf = true;
+#pragma unroll
+                    for (int j = 0; j < W; j++) {
+                        uint64_t x = nw[j];
+                        while (x) {
+                            const int b = __ffsll((unsigned long long)x) - 1;
+                            x &= x - 1;
+                            V.lev[w * (64 * W) + j * 64 + b] = (uint16_t)level;
+                        }
+                    }
+                }
+                // bit b moves on while the members ranked before it number at most k
+                uint64_t keep[W];
+                first_bits<W>(s, (int64_t)V.k - held + 1, keep);
+                uint64_t fa = 0;
+#pragma unroll
+                for (int j = 0; j < W; j++) {
+                    if (j >= nwa) continue;
+                    const uint64_t f = nw[j] & keep[j];
+                    V.fr[w * W + j] = f;
+                    fa |= f;
+                }
+                pass = fa != 0;
+            }
         }
-        const int ti = wave_append(&ctl->nt, touch);
-        if (touch) V.touched[ti] = (int32_t)w;
-        const int fi = wave_append(&ctl->nfn, pass);
-        if (pass) Fn[fi] = (int32_t)w;
+        tl.put(touch, (int32_t)w);
+        // the next frontier: the node's propagation arcs in chunks (none if it has no arcs)
+        uint32_t c = 0;
+        if (pass) c = (V.rp[w + 1] - V.rp[w] + kChunk - 1) / kChunk;
+        uint32_t incl = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+            if (lane >= off) incl += y;
+        }
+        const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+        int32_t base = 0;
+        if (lane == 0 && total) base = atomicAdd(&ctl->nfn, (int32_t)total);
+        base = __shfl(base, 0);
+        for (uint32_t q = 0; q < c; q++) Fn[base + (incl - c) + q] = ((uint64_t)w << 32) | (q * kChunk);
     }
+    tl.flush();
     if (ovf) ctl->overflow = 1;
     __syncthreads();
     __shared__ bool last;
@@ -246,22 +334,23 @@ __global__ __launch_bounds__(kBlock) void k_rch_merge(ReachCtl* ctl, ReachView V
 }
 
 // The last block of account starts the next batch: it scans ranks from tnext
-// for up to 64W sources that can still pass their bit, in rank order.
+// for up to cap sources that can still pass their bit, in rank order.
 template <int W>
 __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
     __shared__ int32_t wcount[kBlock / 64];
     __shared__ int32_t got;
     __shared__ int64_t scan, first_rank, last_rank;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    const int32_t batch = ctl->batch;
-    int32_t* F = V.flist + (int64_t)ctl->fsel * V.n;
+    const int32_t batch = ctl->batch;  // 1 for the first batch
+    const int32_t cap = (int32_t)std::min<int64_t>(64 * W, (int64_t)kFirstBatch << std::min(batch - 1, 16));
+    uint64_t* F = V.flist + (int64_t)ctl->fsel * V.fcap;
     if (threadIdx.x == 0) {
         got = 0;
         scan = ctl->tnext;
     }
     __syncthreads();
     constexpr int kPer = 4;  // ranks per thread and window
-    while (got < 64 * W && scan < V.nsrc) {
+    while (got < cap && scan < V.nsrc) {
         // 4 x 256 ranks per window, loads in flight together; thread t takes
         // ranks scan + t*4 .. +3, so the window stays in rank order
         int64_t s[kPer];
@@ -293,27 +382,26 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             if (!take[q]) continue;
-            if (b < 64 * W) {
+            if (b < cap) {
                 const int64_t r = scan + (int64_t)threadIdx.x * kPer + q;
                 const int64_t x = s[q];
                 const uint64_t bit = 1ull << (b & 63);
                 if (b == 0) first_rank = r;
-                if (b == 64 * W - 1) last_rank = r;
+                if (b == cap - 1) last_rank = r;
                 V.src_rank[b] = (int32_t)r;
                 V.sbit[x] = b;
                 V.seen[x * W + (b >> 6)] = bit;
                 V.stamp[x] = batch;
                 V.fr[x * W + (b >> 6)] = bit;
                 V.touched[b] = (int32_t)x;
-                F[b] = (int32_t)x;
             }
             b++;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            if (total >= 64 * W) {  // the batch is full: continue after its last source
+            if (total >= cap) {  // the batch is full: continue after its last source
                 scan = last_rank + 1;
-                got = 64 * W;
+                got = cap;
             } else {
                 scan += (int64_t)kBlock * kPer;
                 got = total;
@@ -321,12 +409,41 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
         }
         __syncthreads();
     }
+    // the first frontier: the sources' propagation arcs in chunks, in source order
+    __shared__ int32_t nfe;
+    if (threadIdx.x == 0) nfe = 0;
+    __syncthreads();
+    const int32_t S = got;
+    for (int32_t b0 = 0; b0 < S; b0 += kBlock) {
+        const int32_t b = b0 + threadIdx.x;
+        int64_t x = 0;
+        uint32_t c = 0;
+        if (b < S) {
+            x = V.touched[b];
+            c = (V.rp[x + 1] - V.rp[x] + kChunk - 1) / kChunk;
+        }
+        uint32_t incl = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wcount[wave] = (int32_t)incl;
+        __syncthreads();
+        int32_t base = nfe;
+        for (int w = 0; w < wave; w++) base += wcount[w];
+        for (uint32_t q = 0; q < c; q++) F[base + (int32_t)(incl - c) + (int32_t)q] = ((uint64_t)x << 32) | (q * kChunk);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kBlock / 64; w++) nfe += wcount[w];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        const int32_t S = got;
         ctl->tnext = scan < V.nsrc ? scan : V.nsrc;
         ctl->nsrc = S;
+        ctl->nw = (S + 63) / 64;
         ctl->nt = S;
-        ctl->nf = S;
+        ctl->nf = nfe;
         ctl->nfn = 0;
         ctl->nc = 0;
         ctl->level = 1;
@@ -341,14 +458,17 @@ __global__ __launch_bounds__(kBlock) void k_rch_account(ReachCtl* ctl, ReachView
     if (ctl->phase != kAccount) return;
     const int32_t nt = ctl->nt;
     const int32_t k = V.k;
+    const int32_t nwa = ctl->nw;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nt; i += (int64_t)gridDim.x * kBlock) {
         const int64_t w = V.touched[i];
         uint64_t s[W];
 #pragma unroll
-        for (int j = 0; j < W; j++) {
-            s[j] = V.seen[w * W + j];
-            V.seen[w * W + j] = 0;
-            V.fr[w * W + j] = 0;
+        for (int j = 0; j < W; j++) {  // fr is a subset of seen: clear both where seen has bits
+            s[j] = j < nwa ? V.seen[w * W + j] : 0ull;
+            if (s[j]) {
+                V.seen[w * W + j] = 0;
+                V.fr[w * W + j] = 0;
+            }
         }
         const int64_t r = V.rank[w];
         const int32_t own = V.sbit[w];
@@ -490,24 +610,24 @@ __global__ void k_rch_rank(const int32_t* __restrict__ order_internal, int64_t n
 
 }  // namespace
 
-size_t reach_scratch_bytes(int64_t n, int32_t k_weighted) {
+size_t reach_scratch_bytes(int64_t n, int64_t arcs, int32_t k_weighted) {
     constexpr int W = kReachWords;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    return al(sizeof(ReachCtl)) + 2 * al(sizeof(int32_t) * n) /* rank, src_by_rank */ +
-           al(sizeof(int32_t) * n) + 2 * al(sizeof(int64_t) * n) /* cnt, dsum, tk */ +
-           3 * al(sizeof(uint64_t) * n * W) + al(sizeof(uint16_t) * n * 64 * W) + 2 * al(sizeof(int32_t) * n) +
-           2 * al(sizeof(int32_t) * n) + 2 * al(sizeof(int32_t) * n) + al(sizeof(int32_t) * n) /* sbit */ +
-           al(sizeof(int32_t) * 64 * W) + 1024 +
-           (k_weighted > 0 ? al(sizeof(int32_t) * n * std::max(1, k_weighted - 1)) +
-                                 al(sizeof(uint16_t) * n * std::max(1, k_weighted - 1))
-                           : 0);
+    const size_t i32 = al(sizeof(int32_t) * n), i64 = al(sizeof(int64_t) * n);
+    const size_t kw = (size_t)std::max(1, k_weighted - 1);
+    return al(sizeof(ReachCtl)) + 2 * i32 /* rank, src_by_rank */ + i32 + 2 * i64 /* cnt, dsum, tk */ +
+           3 * al(sizeof(uint64_t) * n * W) /* seen, nx, fr */ + al(sizeof(uint16_t) * n * 64 * W) /* lev */ +
+           3 * i32 /* stamp, lmark, sbit */ + al(sizeof(int32_t) * 64 * W) /* src_rank */ +
+           (k_weighted > 0 ? al(sizeof(int32_t) * n * kw) + al(sizeof(uint16_t) * n * kw) : 0) +
+           al(sizeof(uint64_t) * 2 * (size_t)frontier_cap(n, arcs)) /* flist */ + 2 * i32 /* cand, touched */ + 1024;
 }
 
 void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats) {
     constexpr int W = kReachWords;
     const int64_t n = a.n;
     const bool weighted = a.beta != nullptr;
-    if (scratch_size < reach_scratch_bytes(n, weighted ? a.k : 0)) throw HipError{hipErrorOutOfMemory, "reach scratch"};
+    if (scratch_size < reach_scratch_bytes(n, a.arcs, weighted ? a.k : 0))
+        throw HipError{hipErrorOutOfMemory, "reach scratch"};
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     char* p = (char*)scratch;
     auto take = [&](size_t bytes) {
@@ -541,7 +661,8 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
         V.mem_id = (int32_t*)take(sizeof(int32_t) * n * std::max(1, a.k - 1));
         V.mem_d = (uint16_t*)take(sizeof(uint16_t) * n * std::max(1, a.k - 1));
     }
-    V.flist = (int32_t*)take(sizeof(int32_t) * 2 * n);
+    V.fcap = frontier_cap(n, a.arcs);
+    V.flist = (uint64_t*)take(sizeof(uint64_t) * 2 * (size_t)V.fcap);
     V.cand = (int32_t*)take(sizeof(int32_t) * n);
     V.touched = (int32_t*)take(sizeof(int32_t) * n);
 
@@ -564,7 +685,7 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
     CCG_HIP(hipGetLastError());
 
     const unsigned gp = (unsigned)a.push_blocks, gm = (unsigned)a.merge_blocks, ga = (unsigned)a.account_blocks;
-    const int64_t nbatches = (V.nsrc + 64 * W - 1) / (64 * W) + 1;
+    const int64_t nbatches = (V.nsrc + kFirstBatch - 1) / kFirstBatch + 1;
     const int64_t max_cycles = nbatches * (n + 2);
     int64_t cycles = 0;
     int32_t chunk = 16;
