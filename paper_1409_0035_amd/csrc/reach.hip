@@ -24,10 +24,11 @@
 // sequential searches would, never earlier.  Nodes that hold more than k such
 // members from earlier batches take no part.
 //
-// A source that already holds more than k members of its own can pass its
-// bit to nobody, so it is skipped: a batch takes the next sources in rank
-// order that can still pass their bit (bit order stays rank order, and every
-// source skipped between them would have reached no node).
+// A source that already holds more than k members of its own, or that has no
+// propagation arc (outbound: no node has an arc into it), can pass its bit to
+// nobody, so it is skipped: a batch takes the next sources in rank order that
+// can still pass their bit (bit order stays rank order, and every source
+// skipped between them would have reached no node).
 //
 // Batches run as a state machine over three kernels that the host enqueues in
 // cycles without reading anything back: push (frontier nodes OR their
@@ -349,10 +350,10 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
         scan = ctl->tnext;
     }
     __syncthreads();
-    constexpr int kPer = 4;  // ranks per thread and window
+    constexpr int kPer = 16;  // ranks per thread and window
     while (got < cap && scan < V.nsrc) {
-        // 4 x 256 ranks per window, loads in flight together; thread t takes
-        // ranks scan + t*4 .. +3, so the window stays in rank order
+        // kPer x 256 ranks per window, loads in flight together; thread t takes
+        // ranks scan + t*kPer .. +kPer-1, so the window stays in rank order
         int64_t s[kPer];
         bool take[kPer];
         int32_t mine = 0;
@@ -363,7 +364,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
         }
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
-            take[q] = s[q] >= 0 && V.cnt[s[q]] <= V.k;
+            take[q] = s[q] >= 0 && V.cnt[s[q]] <= V.k && V.rp[s[q] + 1] > V.rp[s[q]];
             mine += take[q] ? 1 : 0;
         }
         // exclusive prefix of `mine` over the block
@@ -409,35 +410,36 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
         }
         __syncthreads();
     }
-    // the first frontier: the sources' propagation arcs in chunks, in source order
-    __shared__ int32_t nfe;
-    if (threadIdx.x == 0) nfe = 0;
-    __syncthreads();
+    // the first frontier: the sources' propagation arcs in chunks, in source
+    // order; thread t takes sources t*kSrc .. +kSrc-1 (64W <= kSrc * kBlock)
+    constexpr int kSrc = (64 * W + kBlock - 1) / kBlock;
     const int32_t S = got;
-    for (int32_t b0 = 0; b0 < S; b0 += kBlock) {
-        const int32_t b = b0 + threadIdx.x;
-        int64_t x = 0;
-        uint32_t c = 0;
-        if (b < S) {
-            x = V.touched[b];
-            c = (V.rp[x + 1] - V.rp[x] + kChunk - 1) / kChunk;
-        }
-        uint32_t incl = c;
+    int64_t xs[kSrc];
+    uint32_t cs[kSrc];
+    uint32_t mine_c = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
-            if (lane >= off) incl += y;
-        }
-        if (lane == 63) wcount[wave] = (int32_t)incl;
-        __syncthreads();
-        int32_t base = nfe;
-        for (int w = 0; w < wave; w++) base += wcount[w];
-        for (uint32_t q = 0; q < c; q++) F[base + (int32_t)(incl - c) + (int32_t)q] = ((uint64_t)x << 32) | (q * kChunk);
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (int w = 0; w < kBlock / 64; w++) nfe += wcount[w];
-        __syncthreads();
+    for (int q = 0; q < kSrc; q++) {
+        const int32_t b = threadIdx.x * kSrc + q;
+        xs[q] = b < S ? V.touched[b] : 0;
+        cs[q] = b < S ? (V.rp[xs[q] + 1] - V.rp[xs[q]] + kChunk - 1) / kChunk : 0;
+        mine_c += cs[q];
     }
+    uint32_t incl = mine_c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wcount[wave] = (int32_t)incl;
+    __syncthreads();
+    int32_t nfe = 0, pos = (int32_t)(incl - mine_c);
+    for (int w = 0; w < kBlock / 64; w++) {
+        if (w < wave) pos += wcount[w];
+        nfe += wcount[w];
+    }
+#pragma unroll
+    for (int q = 0; q < kSrc; q++)
+        for (uint32_t c = 0; c < cs[q]; c++) F[pos++] = ((uint64_t)xs[q] << 32) | (c * kChunk);
     if (threadIdx.x == 0) {
         ctl->tnext = scan < V.nsrc ? scan : V.nsrc;
         ctl->nsrc = S;
@@ -482,31 +484,51 @@ __global__ __launch_bounds__(kBlock) void k_rch_account(ReachCtl* ctl, ReachView
         const int32_t c = V.cnt[w];
         if (c < k) {  // members in rank order until it holds k
             const int32_t need = k - c;
+            uint64_t take[W];
+            first_bits<W>(s, need, take);
             int32_t taken = 0;
-            int64_t sum = 0;
+            int64_t sum = 0, last_rk = -1;
 #pragma unroll
             for (int j = 0; j < W; j++) {
-                uint64_t x = s[j];
-                while (x && taken < need) {
-                    const int b = __ffsll((unsigned long long)x) - 1;
-                    x &= x - 1;
-                    const uint16_t lv = V.lev[w * (64 * W) + j * 64 + b];
-                    sum += lv;
-                    const int64_t rk = V.src_rank[j * 64 + b];
-                    if (V.mem_id) {  // Algorithm 5: keep the member, or the k-th's id
-                        const int32_t slot = c + taken;
-                        const int32_t src = V.src_by_rank[rk];
-                        if (slot < k - 1) {
-                            V.mem_id[w * (k - 1) + slot] = src;
-                            V.mem_d[w * (k - 1) + slot] = lv;
-                        } else {
-                            V.tk[w] = src;
-                        }
+                uint64_t x = take[j];
+                while (x) {
+                    // up to eight members at a time, their loads in flight together
+                    int32_t bb[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        bb[u] = x ? __ffsll((unsigned long long)x) - 1 : -1;
+                        x &= x - 1;
                     }
-                    taken++;
-                    if (taken == need && !V.mem_id) V.tk[w] = (rk + 1) - (r < rk ? 1 : 0);
+                    uint16_t lv[8];
+                    int32_t rk[8], src[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        lv[u] = bb[u] >= 0 ? V.lev[w * (64 * W) + j * 64 + bb[u]] : (uint16_t)0;
+                        rk[u] = bb[u] >= 0 ? V.src_rank[j * 64 + bb[u]] : 0;
+                    }
+                    if (V.mem_id) {
+#pragma unroll
+                        for (int u = 0; u < 8; u++) src[u] = bb[u] >= 0 ? V.src_by_rank[rk[u]] : 0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        if (bb[u] < 0) continue;
+                        sum += lv[u];
+                        if (V.mem_id) {  // Algorithm 5: keep the member, or the k-th's id
+                            const int32_t slot = c + taken;
+                            if (slot < k - 1) {
+                                V.mem_id[w * (k - 1) + slot] = src[u];
+                                V.mem_d[w * (k - 1) + slot] = lv[u];
+                            } else {
+                                V.tk[w] = src[u];
+                            }
+                        }
+                        taken++;
+                        last_rk = rk[u];
+                    }
                 }
             }
+            if (taken == need && !V.mem_id) V.tk[w] = (last_rk + 1) - (r < last_rk ? 1 : 0);
             V.dsum[w] += sum;
         }
         V.cnt[w] = c + pc;
