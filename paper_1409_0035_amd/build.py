@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccgpu.so")
 SOURCES = ["ccgpu.hip", "bfs_batched.hip", "bfs_plain.hip", "sssp_weighted.hip", "epilogue.hip", "epilogue_bits.hip",
-           "reach.hip", "epilogue_beta.hip"]
+           "reach.hip", "epilogue_beta.hip", "prio.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
     "-ffp-contract=off", "-fno-fast-math",

@@ -1727,55 +1727,11 @@ extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const
     if (p->k < 1 || p->k > 4096) return fail(CC_EINVAL, "cc_reach_weighted: need 1 <= k <= 4096");
     if (p->inbound != 0 && p->inbound != 1) return fail(CC_EINVAL, "cc_reach_weighted: inbound must be 0 or 1");
     if (g->dg.weighted) return fail(CC_EINVAL, "cc_reach_weighted: graphs with unit arc lengths only");
-    // priority ranks U(u) / (2^53 beta(u)) of the nodes of positive weight, in increasing order
-    SplitMix64 rng{p->seed};
-    std::vector<uint64_t> U((size_t)n);
-    for (int64_t u = 0; u < n; u++) U[(size_t)u] = (rng.next() >> 11) + 1;
-    std::vector<int32_t> order;
-    for (int64_t u = 0; u < n; u++)
-        if (p->beta[u] > 0) order.push_back((int32_t)u);
-    if (order.empty()) return fail(CC_EINVAL, "cc_reach_weighted: no node of positive weight");
-    // U/beta rounded to double is monotone in the exact rank, so different
-    // doubles order as the exact ranks do: an LSD radix sort on the doubles'
-    // bits (positive doubles order as their bit patterns), then runs of equal
-    // doubles by the exact cross products and the id
-    {
-        const size_t m = order.size();
-        std::vector<std::pair<uint64_t, int32_t>> a(m), b(m);
-        for (size_t i = 0; i < m; i++) {
-            const int32_t u = order[i];
-            const double kd = (double)U[(size_t)u] / (double)p->beta[u];
-            uint64_t bits;
-            std::memcpy(&bits, &kd, sizeof(bits));
-            a[i] = {bits, u};
-        }
-        for (int shift = 0; shift < 64; shift += 8) {
-            size_t cnt[257] = {0};
-            for (size_t i = 0; i < m; i++) cnt[((a[i].first >> shift) & 255) + 1]++;
-            for (int d = 0; d < 256; d++) cnt[d + 1] += cnt[d];
-            for (size_t i = 0; i < m; i++) b[cnt[(a[i].first >> shift) & 255]++] = a[i];
-            a.swap(b);
-        }
-        auto exact_less = [&](int32_t x, int32_t y) {
-            const unsigned __int128 lx = (unsigned __int128)U[(size_t)x] * p->beta[y];
-            const unsigned __int128 ly = (unsigned __int128)U[(size_t)y] * p->beta[x];
-            return lx != ly ? lx < ly : x < y;
-        };
-        for (size_t i = 0; i < m; i++) order[i] = a[i].second;
-        for (size_t i = 0; i < m;) {
-            size_t j = i + 1;
-            while (j < m && a[j].first == a[i].first) j++;
-            if (j - i > 1) std::sort(order.begin() + (ptrdiff_t)i, order.begin() + (ptrdiff_t)j, exact_less);
-            i = j;
-        }
-    }
-    std::vector<uint32_t> beta_i((size_t)n);
-    std::vector<uint64_t> U_i((size_t)n);
-    for (int64_t u = 0; u < n; u++) {
-        beta_i[(size_t)g->inv[(size_t)u]] = p->beta[u];
-        U_i[(size_t)g->inv[(size_t)u]] = U[(size_t)u];
-    }
-    for (auto& x : order) x = g->inv[(size_t)x];
+    // the nodes of positive weight are the sources; their priority ranks are
+    // drawn and sorted on the device
+    int64_t m = 0;
+    for (int64_t u = 0; u < n; u++) m += p->beta[u] > 0 ? 1 : 0;
+    if (m == 0) return fail(CC_EINVAL, "cc_reach_weighted: no node of positive weight");
     std::lock_guard<std::mutex> lk(ctx->mu);
     return guarded(ctx, [&]() -> cc_status {
         Lane& L = ctx->lane;
@@ -1783,7 +1739,8 @@ extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const
         CCG_HIP(hipEventRecord(L.ev[0], st));
         auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
         const size_t outb = 2 * al(sizeof(int32_t) * (size_t)n) + 2 * al(sizeof(double) * (size_t)n) +
-                            al(sizeof(uint32_t) * (size_t)n) + al(sizeof(uint64_t) * (size_t)n) + 1024;
+                            2 * al(sizeof(uint32_t) * (size_t)n) + al(sizeof(uint64_t) * (size_t)n) +
+                            al(sizeof(int32_t) * (size_t)n) + al(priority_scratch_bytes(n)) + 1024;
         char* ob = (char*)L.arena2.get(outb);
         auto take = [&](size_t b) {
             char* x = ob;
@@ -1796,17 +1753,20 @@ extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const
         a.k = p->k;
         a.rp = p->inbound ? g->dg.rp : g->dg.rrp;
         a.col = p->inbound ? g->dg.col : g->dg.rcol;
-        a.order = order.data();
-        a.nsrc = (int64_t)order.size();
+        a.nsrc = m;
         a.orig = g->dg.orig;
         a.count = (int32_t*)take(sizeof(int32_t) * n);
         a.kth = (int32_t*)take(sizeof(int32_t) * n);
         a.S_w = (double*)take(sizeof(double) * n);
         a.R = (double*)take(sizeof(double) * n);
-        uint32_t* bd = (uint32_t*)take(sizeof(uint32_t) * n);
+        uint32_t* bc = (uint32_t*)take(sizeof(uint32_t) * n);  // caller's ids
+        uint32_t* bd = (uint32_t*)take(sizeof(uint32_t) * n);  // internal ids
         uint64_t* Ud = (uint64_t*)take(sizeof(uint64_t) * n);
-        CCG_HIP(hipMemcpyAsync(bd, beta_i.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
-        CCG_HIP(hipMemcpyAsync(Ud, U_i.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, st));
+        int32_t* by_rank = (int32_t*)take(sizeof(int32_t) * n);
+        void* ps = take(priority_scratch_bytes(n));
+        CCG_HIP(hipMemcpyAsync(bc, p->beta, sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
+        priority_order(st, n, m, p->seed, bc, g->dg.orig, bd, Ud, by_rank, ps, priority_scratch_bytes(n));
+        a.order_dev = by_rank;
         a.beta = bd;
         a.U = Ud;
         const size_t need = reach_scratch_bytes(n, a.arcs, p->k);

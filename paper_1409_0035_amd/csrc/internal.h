@@ -543,6 +543,7 @@ struct ReachArgs {
     const uint32_t* rp = nullptr;  // propagation arcs: outbound the in-arcs, inbound the out-arcs
     const int32_t* col = nullptr;
     const int32_t* order = nullptr;  // host: internal ids in rank order (a permutation)
+    const int32_t* order_dev = nullptr;  // or device: the nsrc sources in rank order
     const int32_t* orig = nullptr;   // device: internal id -> caller's id
     // device outputs at the caller's ids (each may be null)
     int32_t* count = nullptr;
@@ -569,6 +570,12 @@ struct ReachStats {
     bool overflow = false;  // some level above 65535: the result is not valid
 };
 size_t reach_scratch_bytes(int64_t n, int64_t arcs, int32_t k_weighted = 0);
+// Algorithm 5's priority ranks: beta and U at internal ids, and the m nodes of
+// positive weight (internal ids) by increasing rank U / (2^53 beta)
+size_t priority_scratch_bytes(int64_t n);
+void priority_order(hipStream_t st, int64_t n, int64_t m, uint64_t seed, const uint32_t* beta_caller,
+                    const int32_t* orig, uint32_t* beta_i, uint64_t* U_i, int32_t* by_rank, void* scratch,
+                    size_t scratch_size);
 void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats);
 
 }  // namespace ccg

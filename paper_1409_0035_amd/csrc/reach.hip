@@ -688,7 +688,10 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
     V.cand = (int32_t*)take(sizeof(int32_t) * n);
     V.touched = (int32_t*)take(sizeof(int32_t) * n);
 
-    CCG_HIP(hipMemcpyAsync(sbr, a.order, sizeof(int32_t) * V.nsrc, hipMemcpyHostToDevice, st));
+    if (a.order_dev)
+        CCG_HIP(hipMemcpyAsync(sbr, a.order_dev, sizeof(int32_t) * V.nsrc, hipMemcpyDeviceToDevice, st));
+    else
+        CCG_HIP(hipMemcpyAsync(sbr, a.order, sizeof(int32_t) * V.nsrc, hipMemcpyHostToDevice, st));
     const unsigned gn = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
     fill_u32(st, rank, 0x7FFFFFFFu, (size_t)n);  // nodes that are never sources rank after all
     hipLaunchKernelGGL(k_rch_rank, dim3(gn), dim3(256), 0, st, (const int32_t*)sbr, V.nsrc, rank);
