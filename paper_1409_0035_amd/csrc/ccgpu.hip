@@ -129,9 +129,10 @@ extern "C" cc_status cc_draw_weighted(int64_t n, const uint32_t* beta, int32_t k
     // VarOpt's threshold: the heavy nodes are the first L in weight order
     // only the k heaviest can be heavy: order those (weight down, id up)
     std::vector<int32_t> heavy_first = pos;
-    std::partial_sort(heavy_first.begin(), heavy_first.begin() + k, heavy_first.end(), [&](int32_t a, int32_t b) {
-        return beta[a] != beta[b] ? beta[a] > beta[b] : a < b;
-    });
+    auto heavier = [&](int32_t a, int32_t b) { return beta[a] != beta[b] ? beta[a] > beta[b] : a < b; };
+    // a strict total order (ids are distinct): the k first are unique
+    std::nth_element(heavy_first.begin(), heavy_first.begin() + (k - 1), heavy_first.end(), heavier);
+    std::sort(heavy_first.begin(), heavy_first.begin() + k, heavier);
     int64_t R = total;
     int32_t L = 0;
     while (!((int64_t)beta[heavy_first[(size_t)L]] * (int64_t)(k - L) < R)) {
