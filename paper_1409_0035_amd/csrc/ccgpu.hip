@@ -129,10 +129,10 @@ extern "C" cc_status cc_draw_weighted(int64_t n, const uint32_t* beta, int32_t k
     // VarOpt's threshold: the heavy nodes are the first L in weight order
     // only the k heaviest can be heavy: order those (weight down, id up)
     std::vector<int32_t> heavy_first = pos;
-    auto heavier = [&](int32_t a, int32_t b) { return beta[a] != beta[b] ? beta[a] > beta[b] : a < b; };
-    // a strict total order (ids are distinct): the k first are unique
-    std::nth_element(heavy_first.begin(), heavy_first.begin() + (k - 1), heavy_first.end(), heavier);
-    std::sort(heavy_first.begin(), heavy_first.begin() + k, heavier);
+    // a heap of the k heaviest: with heavy-tailed weights few nodes ever enter it
+    std::partial_sort(heavy_first.begin(), heavy_first.begin() + k, heavy_first.end(), [&](int32_t a, int32_t b) {
+        return beta[a] != beta[b] ? beta[a] > beta[b] : a < b;
+    });
     int64_t R = total;
     int32_t L = 0;
     while (!((int64_t)beta[heavy_first[(size_t)L]] * (int64_t)(k - L) < R)) {
@@ -257,6 +257,7 @@ struct Lane {
     hipEvent_t ev[4] = {};
     EventPool events;  // per-launch timing inside the traversals
     uint64_t gen = 0;  // arena generation
+    int64_t last_maxd = -1;  // an upper bound on the last job's largest distance (-1: unknown)
     // Captured estimates (stream capture of a whole estimate), replayed when
     // the same graph, parameters, buffers and outputs come again.
     struct Captured {
@@ -676,6 +677,7 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             g->dg.rw = g->dg.w;
         }
         g->dg.orig = (const int32_t*)up(6, orig.data(), sizeof(int32_t) * n);
+        g->dg.inv = (const int32_t*)up(9, g->inv.data(), sizeof(int32_t) * n);
         g->dg.hub_chunks_in = (const int32_t*)up(7, ch_in.data(), sizeof(int32_t) * ch_in.size());
         g->dg.n_hub_chunks_in = (int32_t)(ch_in.size() / 3);
         if (directed) {
@@ -1086,6 +1088,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ba.samples = samples_dev;
             ba.sidx = sidx;
             ba.orig = g.orig;
+            ba.inv = g.inv;
             ba.hist = hist;
             ba.hist_slots = kHistSlotsBatched;
             ba.hist_len = cap;
@@ -1107,9 +1110,12 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ba.S_sweep = out->S_sweep;
             ba.S_sweep_err = out->S_sweep_err;
             const bool want_err = out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err;
-            ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0, want_err);
+            const bool staged = out->S_hyb || out->S_samp || out->S_piv || out->S_pub || out->pivot || out->delta ||
+                                out->sampsum;
+            ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0, want_err, staged ? n : 0);
             ba_scratch = ba_es <= trav_scratch ? ts : L.arena2.get(ba_es);
             run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
+            L.last_maxd = ba.lmax;
         } else {
             EpilogueArgs ea;
             ea.n = n;
@@ -1127,6 +1133,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             const size_t es = epilogue_scratch(
                 n, k, ea.maxd, false, out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err);
             run_epilogue(st, ea, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
+            L.last_maxd = ea.maxd;
         }
         if (out->samples)
             CCG_HIP(hipMemcpyAsync(out->samples, r.samples.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
@@ -1673,6 +1680,7 @@ extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, co
         res.D = D;
         res.dmat = dmat;
         cc_timing t{};
+        L.last_maxd = -1;
         const cc_status js = run_job(ctx, g, r, &res, L, &t);
         if (js != CC_OK) return js;
         CCG_HIP(hipMemcpyAsync(beta_d, p->beta, sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
@@ -1697,6 +1705,7 @@ extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, co
         ba.var = var;
         ba.err = err;
         ba.small_scratch = small;
+        ba.maxd = L.last_maxd;  // the traversal's bound on the distances, when it knows one
         ba.get_scratch = [&](size_t need) { return L.arena2.get(need); };
         run_beta_epilogue(st, ba, flags);
         DevFlags hf;

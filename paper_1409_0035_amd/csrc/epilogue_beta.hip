@@ -13,7 +13,8 @@
 // the nodes outside C at each distance (k_beta_hist), suffix-summed with the
 // distance (k_beta_suffix), read at floor(Delta/eps) + 1.
 //
-//   k_beta_maxd      largest distance (the tables' length)
+//   k_beta_maxd      largest distance (the tables' length), when the traversal
+//                    gives no bound on it
 //   k_beta_hist      hw[i][d] = sum of beta(u) over u outside C with d(c_i,u) = d,
 //                    per block in LDS when the table fits
 //   k_beta_suffix    WT[i][t] = sum_{d >= t} d * hw[i][d] and WC[i][t] = sum_{d >= t}
@@ -62,8 +63,10 @@ __global__ __launch_bounds__(kBlock) void k_beta_hist(const int32_t* __restrict_
         const int64_t u = t / k;
         const int32_t i = (int32_t)(t - u * k);
         const uint32_t b = beta[u];
-        if (b == 0 || sidx[u] >= 0) continue;
-        const int64_t cell = (int64_t)i * hlen + D[t];
+        const int32_t d = D[t];
+        // the caller has ruled out unreached entries; the bound keeps the tables safe regardless
+        if (b == 0 || sidx[u] >= 0 || d < 0 || d >= hlen) continue;
+        const int64_t cell = (int64_t)i * hlen + d;
         if (use_lds) atomicAdd(&lh[cell], (unsigned long long)b);
         else atomicAdd(&hw[cell], (unsigned long long)b);
     }
@@ -327,16 +330,22 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     const int64_t n = a.n;
     const int32_t k = a.k;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    // largest distance: the tables' length
-    int32_t* dmax = (int32_t*)a.small_scratch;
-    fill_u32(st, dmax, 0u, 1);
+    // the tables' length: the largest distance, or a bound on it the
+    // traversal already knows (entries past the largest distance stay zero)
     const int64_t cells = n * k;
-    hipLaunchKernelGGL(k_beta_maxd, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((cells + 255) / 256, 8192))),
-                       dim3(256), 0, st, a.D, cells, dmax);
-    int32_t maxd = 0;
-    CCG_HIP(hipMemcpyAsync(&maxd, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    CCG_HIP(hipStreamSynchronize(st));
-    const int64_t hlen = (int64_t)maxd + 2;
+    int64_t maxd = a.maxd;
+    if (maxd < 0) {
+        int32_t* dmax = (int32_t*)a.small_scratch;
+        fill_u32(st, dmax, 0u, 1);
+        hipLaunchKernelGGL(k_beta_maxd,
+                           dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((cells + 255) / 256, 8192))), dim3(256),
+                           0, st, a.D, cells, dmax);
+        int32_t hm = 0;
+        CCG_HIP(hipMemcpyAsync(&hm, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        maxd = hm;
+    }
+    const int64_t hlen = maxd + 2;
     const size_t need = al(sizeof(uint64_t) * (size_t)k * hlen) * 3 + al(sizeof(int64_t) * (size_t)k);
     void* scr = a.get_scratch(need);
     char* q = (char*)scr;

@@ -109,7 +109,8 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
     int32_t bit_base, const int32_t* __restrict__ orig,
     const uint64_t* __restrict__ lmask, const int32_t* __restrict__ Tcnt, const int64_t* __restrict__ Tsum,
     int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed, double* S_hyb, double* S_samp,
-    int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out, int64_t* sampsum_out, DevFlags* flags) {
+    int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out, int64_t* sampsum_out,
+    uint4* __restrict__ stage, DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     bool any_ovf = false, any_unreached = false;
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
@@ -193,19 +194,47 @@ __global__ __launch_bounds__(kBlock) void k_estimate_bits(
             piv = src_sum[p];
             pub = piv + (n - 1) * (int64_t)delta;
         }
-        const int64_t o = orig[v];
-        if (S_hyb) S_hyb[o] = hyb;
-        if (S_samp) S_samp[o] = samp;
-        if (S_piv) S_piv[o] = piv;
-        if (S_pub) S_pub[o] = pub;
-        if (pivot_out) pivot_out[o] = p;
-        if (delta_out) delta_out[o] = delta;
-        if (sampsum_out) sampsum_out[o] = sum;
+        if (stage) {  // one 64-byte record per node, in internal order (coalesced)
+            const uint64_t hb = (uint64_t)__double_as_longlong(hyb), sb = (uint64_t)__double_as_longlong(samp);
+            uint4* r = stage + v * 4;
+            r[0] = make_uint4((uint32_t)hb, (uint32_t)(hb >> 32), (uint32_t)sb, (uint32_t)(sb >> 32));
+            r[1] = make_uint4((uint32_t)piv, (uint32_t)((uint64_t)piv >> 32), (uint32_t)pub, (uint32_t)((uint64_t)pub >> 32));
+            r[2] = make_uint4((uint32_t)sum, (uint32_t)((uint64_t)sum >> 32), (uint32_t)p, (uint32_t)delta);
+        } else {
+            const int64_t o = orig[v];
+            if (S_hyb) S_hyb[o] = hyb;
+            if (S_samp) S_samp[o] = samp;
+            if (S_piv) S_piv[o] = piv;
+            if (S_pub) S_pub[o] = pub;
+            if (pivot_out) pivot_out[o] = p;
+            if (delta_out) delta_out[o] = delta;
+            if (sampsum_out) sampsum_out[o] = sum;
+        }
         any_ovf = any_ovf || ovf;
         any_unreached = any_unreached || unreached;
     }
     if (any_ovf) flags->overflow = 1;
     if (any_unreached) flags->disconnected = 1;
+}
+
+// The staged records written out in the caller's order: thread o reads the
+// record of its internal node inv[o] (one 64-byte line) and writes each
+// requested output at o, coalesced across the wave.
+__global__ __launch_bounds__(kBlock) void k_put_outputs(int64_t n, const int32_t* __restrict__ inv,
+                                                        const uint4* __restrict__ stage, double* S_hyb, double* S_samp,
+                                                        int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out,
+                                                        int32_t* delta_out, int64_t* sampsum_out) {
+    for (int64_t o = (int64_t)blockIdx.x * kBlock + threadIdx.x; o < n; o += (int64_t)gridDim.x * kBlock) {
+        const uint4* r = stage + (int64_t)inv[o] * 4;
+        const uint4 a = r[0], b = r[1], c = r[2];
+        if (S_hyb) S_hyb[o] = __longlong_as_double((long long)(((uint64_t)a.y << 32) | a.x));
+        if (S_samp) S_samp[o] = __longlong_as_double((long long)(((uint64_t)a.w << 32) | a.z));
+        if (S_piv) S_piv[o] = (int64_t)(((uint64_t)b.y << 32) | b.x);
+        if (S_pub) S_pub[o] = (int64_t)(((uint64_t)b.w << 32) | b.z);
+        if (sampsum_out) sampsum_out[o] = (int64_t)(((uint64_t)c.y << 32) | c.x);
+        if (pivot_out) pivot_out[o] = (int32_t)c.z;
+        if (delta_out) delta_out[o] = (int32_t)c.w;
+    }
 }
 
 // Distances from the masks: thread per (node, sample).  out_internal (DT,
@@ -304,6 +333,9 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
     const int rem = k - (W - 1) * 64;
     const uint64_t lastmask = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
     char* p = (char*)scratch;
+    const bool staged = a.inv && (a.S_hyb || a.S_samp || a.S_piv || a.S_pub || a.pivot || a.delta || a.sampsum);
+    uint4* stage = staged ? (uint4*)p : nullptr;  // 64 bytes per node, first in the scratch
+    if (staged) p += align256((size_t)n * 64);
     int32_t* Tcnt = (int32_t*)p;
     p += align256(sizeof(int32_t) * k * tlen);
     int64_t* Tsum = (int64_t*)p;
@@ -322,7 +354,10 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
     hipLaunchKernelGGL((k_lmask<W, MT>), dim3(k), dim3(64), 0, st, dmat_c, k, lmax, lmask);
     hipLaunchKernelGGL((k_estimate_bits<W>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, sv, lmax, n, k, lastmask,
                        a.sidx, a.bit_base, a.orig, lmask, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb,
-                       a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
+                       a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, stage, flags);
+    if (staged)
+        hipLaunchKernelGGL(k_put_outputs, dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, n, a.inv,
+                           (const uint4*)stage, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum);
     CCG_HIP(hipGetLastError());
     if (a.Dout) {
         if (lmax < 255) {
@@ -412,19 +447,21 @@ void materialize_w(hipStream_t st, const uint64_t* snap, size_t plane, int32_t l
 
 }  // namespace
 
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows, bool err) {
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows, bool err, int64_t stage_rows) {
     const int64_t tlen = (int64_t)lmax + 2;
     const int W = (k + 63) / 64;
     const size_t db = lmax < 255 ? 1 : (lmax < 65535 ? 2 : 4);
     return align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
            align256(sizeof(uint32_t) * (size_t)k * k) + align256(sizeof(uint64_t) * (size_t)k * (lmax + 1) * W) +
-           align256((size_t)err_rows * k * db) + (err ? sweep_scratch_bytes(err_rows, k) : 0) + 1024;
+           align256((size_t)err_rows * k * db) + (err ? sweep_scratch_bytes(err_rows, k) : 0) +
+           align256((size_t)stage_rows * 64) + 1024;
 }
 
 void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, size_t scratch_size,
                        DevFlags* flags) {
     const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
-    if (scratch_size < bits_epilogue_scratch(a.k, a.lmax, want_err ? a.n : 0, want_err))
+    const bool staged = a.inv && (a.S_hyb || a.S_samp || a.S_piv || a.S_pub || a.pivot || a.delta || a.sampsum);
+    if (scratch_size < bits_epilogue_scratch(a.k, a.lmax, want_err ? a.n : 0, want_err, staged ? a.n : 0))
         throw HipError{hipErrorOutOfMemory, "bits epilogue scratch"};
     switch ((a.k + 63) / 64) {
         case 1: bits_mt<1>(st, a, scratch, flags); break;

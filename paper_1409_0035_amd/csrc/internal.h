@@ -209,6 +209,7 @@ struct DevGraph {
     const int32_t* rcol = nullptr;
     const int32_t* rw = nullptr;
     const int32_t* orig = nullptr;  // internal id -> caller's id
+    const int32_t* inv = nullptr;   // caller's id -> internal id
     uint32_t delta = 1;             // delta-stepping bucket width (weighted graphs)
     // high-degree prefix [0, nh) scanned in chunks; chunk lists per pull direction
     int64_t nh = 0;
@@ -448,6 +449,10 @@ struct BitsEpilogueArgs {
     const int32_t* samples = nullptr;  // device, internal ids
     const int32_t* sidx = nullptr;
     const int32_t* orig = nullptr;
+    // caller's id -> internal id: the per-node outputs then go through a
+    // staging area in internal order and are written out in the caller's
+    // order, coalesced (null: each written in place through orig)
+    const int32_t* inv = nullptr;
     const int32_t* hist = nullptr;
     int32_t hist_slots = 0;
     int64_t hist_len = 0;
@@ -474,7 +479,8 @@ struct BitsEpilogueArgs {
     int32_t bit_base = 0;   // its first sample's index in sidx and in the histogram rows
     int32_t hist_rows = 0;  // histogram rows per slot (0: k)
 };
-size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows = 0, bool err = false);
+// stage_rows: n when the per-node outputs are staged (inv set and some requested)
+size_t bits_epilogue_scratch(int32_t k, int32_t lmax, int64_t err_rows = 0, bool err = false, int64_t stage_rows = 0);
 
 // The eps values the experiments (Sec. 8) choose from per node for the
 // adaptive hybrid estimate: 0.001, 0.025, 0.05, 0.1, 0.2, 0.5, 0.99.
@@ -529,6 +535,7 @@ struct BetaArgs {
     double* S = nullptr;
     double* var = nullptr;
     double* err = nullptr;             // Sec. 4.1's error estimate with beta masses (optional)
+    int64_t maxd = -1;                 // an upper bound on the distances in D, or -1: found by a pass over D
     void* small_scratch = nullptr;     // 256 bytes
     std::function<void*(size_t)> get_scratch;  // device buffer of at least the given size
 };
