@@ -218,8 +218,8 @@ cc_status cc_last_timing(const cc_context* ctx, cc_timing* t);
 typedef struct {
     int32_t alpha;          /* BFS: a level pushes iff its frontier's out-arcs * alpha are fewer than the arcs
                                the last pull scanned (1..1024; default 4) */
-    int32_t level_blocks;   /* BFS: blocks of the merge launch per level (1..65535; default 2048) */
-    int32_t scatter_blocks; /* BFS: blocks of the scatter launch per level (1..65535; default 4096) */
+    int32_t level_blocks;   /* BFS: blocks of the merge launch per level (1..65535; default 1024) */
+    int32_t scatter_blocks; /* BFS: blocks of the scatter launch per level (1..65535; default 8192) */
     int32_t delta;          /* weighted: bucket width of delta-stepping (>= 1; default 2 x mean arc length) */
     int32_t round_blocks;   /* weighted: blocks per relaxation round (1..65535; default 1024) */
     int32_t local_passes;   /* weighted: block-local relaxation passes per round (0..1024; default 64) */

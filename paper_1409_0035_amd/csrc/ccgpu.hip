@@ -321,7 +321,7 @@ struct cc_graph {
     uint64_t id = 0;  // never reused: keys captured estimates
     std::vector<int32_t> chunks_host;  // hub chunk triples (undirected graphs), for batching
     mutable std::atomic<int32_t> bfs_hint{0};  // levels the last batched traversal of this graph ran
-    cc_tuning tune{4, 2048, 4096, 1, 1024, 64};  // launch shapes (cc_graph_set_tuning / cc_autotune)
+    cc_tuning tune{4, 1024, 8192, 1, 1024, 64};  // launch shapes (cc_graph_set_tuning / cc_autotune)
 };
 
 struct cc_job {
@@ -2033,8 +2033,8 @@ extern "C" cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64
                 try_knob(&cc_tuning::round_blocks, {256, 512, 2048, 4096});
             } else {
                 try_knob(&cc_tuning::alpha, {1, 2, 8, 16, 32, 64});
-                try_knob(&cc_tuning::scatter_blocks, {1024, 2048, 8192, 16384});
-                try_knob(&cc_tuning::level_blocks, {512, 1024, 4096, 8192});
+                try_knob(&cc_tuning::scatter_blocks, {2048, 4096, 8192, 16384});
+                try_knob(&cc_tuning::level_blocks, {512, 1024, 2048, 4096});
             }
         } catch (...) {
             g->tune = start;

@@ -242,8 +242,8 @@ struct BfsView {
     const uint64_t* preset = nullptr;
     const int32_t* gvalid = nullptr;
     int32_t alpha = 4;  // a level pushes iff its frontier's out-arcs * alpha < what the last pull scanned
-    int32_t level_blocks = 2048;    // merge launch grid cap
-    int32_t scatter_blocks = 4096;  // scatter launch grid cap
+    int32_t level_blocks = 1024;    // merge launch grid cap
+    int32_t scatter_blocks = 8192;  // scatter launch grid cap
 };
 
 // Traversal state the batched BFS level kernels read at entry and the last
