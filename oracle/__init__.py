@@ -20,8 +20,7 @@ What it computes (Cohen, Delling, Pajor & Werneck 2014):
   * exact S(v) for every node (Eq. (1)) by one search per node.
 
 Pins (closed forms, special cases, worked examples, brute force) live in
-``tests/test_oracle_pins.py``.  Parity status of each function: pinned, see
-the design notes.
+``tests/test_oracle_pins.py``; every function here is pinned by them.
 """
 from __future__ import annotations
 

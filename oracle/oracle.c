@@ -48,7 +48,7 @@
  *                               k-th among V \ {v}, and the average-distance and
  *                               reachability estimates.
  *
- * Readings of the paper used here (all listed with reasons in the design notes):
+ * Readings of the paper used here:
  *   - pivot ties go to the lowest sample index (Alg. 2 updates the pivot only
  *     on a strictly smaller distance while scanning samples in index order);
  *   - u is in L(v) iff d(c(v),u) <= Delta(v)/eps, compared exactly as

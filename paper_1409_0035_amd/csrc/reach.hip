@@ -16,7 +16,8 @@
 // every node still collects, each extra word costs on every arc, whereas the
 // later batches touch few nodes and are bound by the fixed cost of a cycle,
 // so fewer, larger batches pay off there.  Kernels touch only the words the
-// current batch uses.  The stopping rule is the exact one (see the design notes): a node x
+// current batch uses.  The stopping rule is the exact one, not Algorithm 4's
+// printed count-equals-k test (which loses members a node reaching x needs): a node x
 // stops source u when x holds at least k + 1 members ranked before u,
 // counting x itself when it ranks before u -- then every node reaching x has k
 // such members other than itself and none of them needs u.  Inside a batch x
