@@ -131,29 +131,30 @@ __device__ __forceinline__ uint32_t pairs_needed(const uint64_t s[W], uint64_t l
 // per field per block.
 struct WaveCounts {
     int64_t arcs = 0, farcs = 0, hub = 0;
-    int32_t n_new = 0, n_out = 0;
+    int32_t n_new = 0, n_out = 0, hub_open = 0;
 };
 
 // Returns, in thread 0, a value that depends on every counter atomic's result
 // (always 0): using it makes the thread wait until those atomics have been
 // performed, so a later atomic can announce them to other blocks.
 __device__ __forceinline__ uint32_t flush_counts(WaveCounts c, LevelCounters* slots) {
-    __shared__ int64_t red[kWaves][5];
+    __shared__ int64_t red[kWaves][6];
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int64_t a = wave_sum64(c.arcs), f = wave_sum64(c.farcs), h = wave_sum64(c.hub);
-    const int32_t nn = wave_sum32(c.n_new), no = wave_sum32(c.n_out);
+    const int32_t nn = wave_sum32(c.n_new), no = wave_sum32(c.n_out), ho = wave_sum32(c.hub_open);
     if (lane == 0) {
         red[wave][0] = a;
         red[wave][1] = f;
         red[wave][2] = nn;
         red[wave][3] = no;
         red[wave][4] = h;
+        red[wave][5] = ho;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t t[5] = {0, 0, 0, 0, 0};
+        int64_t t[6] = {0, 0, 0, 0, 0, 0};
         for (int w = 0; w < kWaves; w++)
-            for (int q = 0; q < 5; q++) t[q] += red[w][q];
+            for (int q = 0; q < 6; q++) t[q] += red[w][q];
         LevelCounters* c0 = slots + (blockIdx.x % kCounterSlots);
         uint64_t r = 0;
         if (t[0]) r |= atomicAdd((unsigned long long*)&c0->arcs, (unsigned long long)t[0]);
@@ -161,6 +162,7 @@ __device__ __forceinline__ uint32_t flush_counts(WaveCounts c, LevelCounters* sl
         if (t[2]) r |= (uint32_t)atomicAdd(&c0->n_new, (int32_t)t[2]);
         if (t[3]) r |= (uint32_t)atomicAdd(&c0->n_out, (int32_t)t[3]);
         if (t[4]) r |= atomicAdd((unsigned long long*)&c0->matched, (unsigned long long)t[4]);
+        if (t[5]) r |= (uint32_t)atomicAdd(&c0->hub_open, (int32_t)t[5]);
         return (uint32_t)(r >> 63);  // counts stay far below 2^63
     }
     return 0;
@@ -175,13 +177,15 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
     if (t < n) {
         const int64_t g = t >> 6;
         const bool pad = preset && (int32_t)(t & 63) >= gvalid[g];
+        uint64_t s0[W], z[W];
 #pragma unroll
         for (int w = 0; w < W; w++) {
-            const uint64_t s0 = preset ? (pad ? ~0ull : preset[g * W + w]) : 0ull;
-            S0[t * W + w] = s0;
-            snap0[t * W + w] = s0;
-            NX[t * W + w] = 0;
+            s0[w] = preset ? (pad ? ~0ull : preset[g * W + w]) : 0ull;
+            z[w] = 0;
         }
+        store_mask<W>(S0, t, s0);  // 16-byte stores
+        store_mask<W>(snap0, t, s0);
+        store_mask<W>(NX, t, z);
         chg[t] = -1;
     }
     if (t < ngroups) {
@@ -223,6 +227,7 @@ __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, 
     const int64_t matched = wave_sum64(__hip_atomic_load(&c->matched, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const int64_t n_new = wave_sum64(__hip_atomic_load(&c->n_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const int64_t n_out = wave_sum64(__hip_atomic_load(&c->n_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const int64_t hub_open = wave_sum64(__hip_atomic_load(&c->hub_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     *c = LevelCounters{};
     if (t != 0) return;
     BfsCtl s = *ctl;
@@ -252,6 +257,7 @@ __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, 
         s.push_atomics += matched;
     }
     s.nodes += n_out * 64;
+    s.hubs_full = hub_open == 0 ? 1 : 0;
     if (n_new > 0) s.lmax = level;
     s.frontier_arcs = farcs;
     if (n_out == 0) {
@@ -420,6 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_level(
     const BfsCtl* __restrict__ ctl) {
     if (ctl->done) return;
     const int pull = ctl->pull;
+    if (pull && ctl->hubs_full) return;  // every hub holds every bit: its chunks would find nothing
     const int32_t waves = gridDim.x * kWaves;
     const int32_t wid = blockIdx.x * kWaves + (threadIdx.x >> 6);
     WaveCounts wc;
@@ -578,6 +585,9 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
             wc.farcs += out_rp[v + 1] - out_rp[v];
         }
         wc.n_new += (int32_t)__popcll(__ballot(anynew));
+        // hub nodes that still miss a bit after this level (the next pull's hub work)
+        const uint64_t open = __ballot(valid && ishub && pairs_needed<W>(sn, lastmask) != 0);
+        if (lane == 0) wc.hub_open += (int32_t)__popcll(open);
         const bool active = __ballot(valid && !fullv) != 0;
         if (lane == 0) {
             fill_level[g] = level;

@@ -333,11 +333,31 @@ __global__ __launch_bounds__(kBlock) void k_suffix(const int32_t* __restrict__ h
         tc[maxd + 1] = 0;
         ts[maxd + 1] = 0;
     }
+    // short tables (BFS levels): the slots are summed first by all threads,
+    // kBlock / (maxd + 1) of them per distance
+    __shared__ unsigned long long hsm[kBlock];
+    const bool small = maxd + 1 <= kBlock;
+    if (small) {
+        const int32_t D = (int32_t)(maxd + 1), G = kBlock / D;
+        hsm[threadIdx.x] = 0;
+        __syncthreads();
+        const int32_t dd = (int32_t)threadIdx.x % D, g = (int32_t)threadIdx.x / D;
+        if (g < G && dd < hlen) {
+            unsigned long long c = 0;
+            for (int32_t s = g; s < nslots; s += G) c += (unsigned long long)hist[((int64_t)s * hrows + i) * hlen + dd];
+            if (c) atomicAdd(&hsm[dd], c);
+        }
+        __syncthreads();
+    }
     for (int64_t top = maxd; top >= 0; top -= kBlock) {
         const int64_t d = top - threadIdx.x;
         int64_t c = 0;
-        if (d >= 0 && d < hlen)
-            for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * hrows + i) * hlen + d];
+        if (d >= 0 && d < hlen) {
+            if (small)
+                c = (int64_t)hsm[d];
+            else
+                for (int32_t s = 0; s < nslots; s++) c += hist[((int64_t)s * hrows + i) * hlen + d];
+        }
         int64_t s = c * (d >= 0 ? d : 0);
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {

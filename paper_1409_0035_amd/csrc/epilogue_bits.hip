@@ -103,6 +103,78 @@ __global__ void k_lmask(const MT* __restrict__ dmat_c, int32_t k, int32_t lmax, 
     }
 }
 
+// Everything the estimate needs per sample, one block per sample i, for
+// searches of at most kBlock - 2 levels: row i of the sample distance matrix
+// (the level at which each sample node gains bit i), the L masks of i as a
+// pivot (Lmask[i][t] = {j : d(c_i, c_j) <= t}), the tail tables of its
+// level histogram (summed over the histogram's slots) and the exact S(c_i).
+// The same results as k_dmat_bits, k_lmask and k_suffix, in one launch.
+template <int W, typename MT>
+__global__ __launch_bounds__(kBlock) void k_sample_tables(
+    SnapView sv, int32_t lmax, const int32_t* __restrict__ samples, int32_t k, const int32_t* __restrict__ hist,
+    int32_t nslots, int32_t hrows, int64_t hlen, int32_t* __restrict__ dmat, MT* __restrict__ dmat_c,
+    uint64_t* __restrict__ lmask, int32_t* __restrict__ Tcnt, int64_t* __restrict__ Tsum, int64_t* __restrict__ src_sum,
+    DevFlags* flags) {
+    __shared__ int32_t row[64 * W];
+    __shared__ unsigned long long hsm[kBlock];
+    __shared__ long long part[kBlock / 64];
+    const int32_t i = blockIdx.x;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int32_t D = lmax + 1;  // distances 0..lmax
+    // the row, and the histogram summed over its slots (kBlock / D threads per distance)
+    long long rs = 0;
+    bool bad = false;
+    for (int32_t j = threadIdx.x; j < k; j += kBlock) {
+        const int64_t cj = samples[j];
+        const int32_t d = level_of<W>(sv, lmax, sv.fill(cj), cj, i);
+        bad = bad || d < 0;
+        dmat[(int64_t)i * k + j] = d;
+        dmat_c[(int64_t)i * k + j] = (MT)(d < 0 ? 0 : d);
+        row[j] = d < 0 ? 0 : d;
+        rs += d;
+    }
+    if (bad) flags->disconnected = 1;
+    hsm[threadIdx.x] = 0;
+    __syncthreads();
+    {
+        const int32_t G = kBlock / D, dd = (int32_t)threadIdx.x % D, g = (int32_t)threadIdx.x / D;
+        if (g < G && dd < hlen) {
+            unsigned long long c = 0;
+            for (int32_t s = g; s < nslots; s += G) c += (unsigned long long)hist[((int64_t)s * hrows + i) * hlen + dd];
+            if (c) atomicAdd(&hsm[dd], c);
+        }
+    }
+    rs = (long long)wave_sum64((int64_t)rs);
+    if (lane == 0) part[wave] = rs;
+    __syncthreads();
+    // L masks of i as a pivot: wave w takes thresholds w, w + 4, ...
+    for (int32_t t = wave; t <= lmax; t += kBlock / 64) {
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const int32_t j = w * 64 + lane;
+            const uint64_t m = __ballot(j < k && row[j] <= t);
+            if (lane == 0) lmask[((int64_t)i * (lmax + 1) + t) * W + w] = m;
+        }
+    }
+    // tail tables: T_cnt[i][t] = sum_{d >= t} h[d], T_sum[i][t] = sum_{d >= t} d h[d]
+    const int64_t tlen = (int64_t)lmax + 2;
+    if (threadIdx.x < tlen) {
+        int64_t c = 0, sm = 0;
+        for (int32_t d = (int32_t)threadIdx.x; d < D; d++) {
+            c += (int64_t)hsm[d];
+            sm += (int64_t)d * (int64_t)hsm[d];
+        }
+        Tcnt[(int64_t)i * tlen + threadIdx.x] = (int32_t)c;
+        Tsum[(int64_t)i * tlen + threadIdx.x] = sm;
+        // S(c_i) = (sum over non-sampled u of d(c_i, u)) + sum_j d(c_i, c_j)
+        if (threadIdx.x == 0) {
+            long long tot = 0;
+            for (int w = 0; w < kBlock / 64; w++) tot += part[w];
+            src_sum[i] = sm + (int64_t)tot;
+        }
+    }
+}
+
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_estimate_bits(
     SnapView sv, int32_t lmax, int64_t n, int32_t k, uint64_t lastmask, const int32_t* __restrict__ sidx,
@@ -347,11 +419,17 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
     const SnapView sv{a.snap, a.plane, a.row_words > 0 ? a.row_words : W, a.word_off, a.node_off, a.fill_level};
     const int32_t hrows = a.hist_rows > 0 ? a.hist_rows : k;
     const int64_t kk = (int64_t)k * k;
-    hipLaunchKernelGGL((k_dmat_bits<W, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, sv, lmax, a.samples,
-                       k, a.dmat, dmat_c, flags);
-    run_suffix(st, a.hist + (int64_t)a.bit_base * a.hist_len, a.hist_slots, k, hrows, a.hist_len, lmax, a.dmat, Tcnt,
-               Tsum, a.src_sum, nullptr);
-    hipLaunchKernelGGL((k_lmask<W, MT>), dim3(k), dim3(64), 0, st, dmat_c, k, lmax, lmask);
+    if (lmax + 2 <= kBlock) {  // the tail tables' lmax + 2 entries, one thread each
+        hipLaunchKernelGGL((k_sample_tables<W, MT>), dim3(k), dim3(kBlock), 0, st, sv, lmax, a.samples, k,
+                           a.hist + (int64_t)a.bit_base * a.hist_len, a.hist_slots, hrows, a.hist_len, a.dmat, dmat_c,
+                           lmask, Tcnt, Tsum, a.src_sum, flags);
+    } else {
+        hipLaunchKernelGGL((k_dmat_bits<W, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, sv, lmax,
+                           a.samples, k, a.dmat, dmat_c, flags);
+        run_suffix(st, a.hist + (int64_t)a.bit_base * a.hist_len, a.hist_slots, k, hrows, a.hist_len, lmax, a.dmat,
+                   Tcnt, Tsum, a.src_sum, nullptr);
+        hipLaunchKernelGGL((k_lmask<W, MT>), dim3(k), dim3(64), 0, st, dmat_c, k, lmax, lmask);
+    }
     hipLaunchKernelGGL((k_estimate_bits<W>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, sv, lmax, n, k, lastmask,
                        a.sidx, a.bit_base, a.orig, lmask, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb,
                        a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, stage, flags);

@@ -44,7 +44,7 @@ struct alignas(128) LevelCounters {
     int32_t n_out;          // groups (or nodes) still in play after this level
     int32_t n_new;          // nodes that received new bits / distances this level
     int32_t n_out_q;        // nodes appended to the next frontier list
-    int32_t pad;
+    int32_t hub_open;       // batched BFS: hub nodes not yet full after this level
     int64_t arcs;           // adjacency entries scanned (pull) or pushed along (push)
     int64_t frontier_arcs;  // sum of the out-degrees of the next frontier
     int64_t matched;        // scanned arcs whose tail was on the previous level
@@ -257,7 +257,7 @@ struct BfsCtl {
     int32_t levels;       // levels run
     int32_t pull_levels;  // of which pulls
     uint32_t ticket;      // blocks of the current merge launch that have finished
-    int32_t pad;
+    int32_t hubs_full;    // every hub node was full after the last level: a pull has no hub work
     int64_t frontier_arcs;  // out-arcs of the nodes that changed at the last level
     int64_t pull_arcs;      // arcs the last pull scanned (what a pull would cost now)
     int64_t arcs;           // arcs scanned or pushed along, all levels
