@@ -2018,7 +2018,7 @@ extern "C" cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64
                     t.*field = v;
                     if (check_tuning(&t) != CC_OK) continue;
                     const double m = measure(t);
-                    if (m < 0.97 * cur_ms) {  // keep the current setting unless clearly faster (timing noise)
+                    if (m < 0.95 * cur_ms) {  // keep the current setting unless clearly faster (timing noise)
                         cur_ms = m;
                         cur = t;
                     }
