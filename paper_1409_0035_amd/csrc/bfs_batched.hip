@@ -24,6 +24,16 @@
 // Two launches per level: k_scatter_level (push, or the hub pull) and
 // k_group_level (the other nodes' pull, the merge and the decision).
 //
+// Sparse hub pulls: only in-neighbours that gained bits at the previous level
+// can pass new bits on (same triangle argument), so when few nodes changed, a
+// hub chunk reads a neighbour's mask only if the neighbour's bit is set in the bitmap of
+// nodes that changed at the previous level (one bit per node, written by the
+// merge).  There are two bitmaps, by level parity, so a merge writing level
+// L's bits never races with reads of level L-1's.  (The merge's own pulls of
+// low-degree nodes gain nothing from the test: it costs what it saves.)  Groups that left the
+// work list keep older bits; reading a full neighbour adds nothing, so a
+// superset of the changed nodes is exact.
+//
 // Pull work decomposition (node ids are degree-sorted by the graph builder):
 //   * hub nodes (the leading nh ids) are scanned by k_scatter_level in fixed chunks
 //     of arcs, one wave per chunk, reduced with DPP and OR-ed atomically into
@@ -171,7 +181,7 @@ __device__ __forceinline__ uint32_t flush_counts(WaveCounts c, LevelCounters* sl
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uint64_t* S0, uint64_t* snap0,
                                                  uint64_t* NX, int32_t* chg, uint8_t* gfull, int32_t* fill_level,
-                                                 const uint64_t* __restrict__ preset,
+                                                 uint64_t* chgbits, const uint64_t* __restrict__ preset,
                                                  const int32_t* __restrict__ gvalid) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < n) {
@@ -191,6 +201,8 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
     if (t < ngroups) {
         gfull[t] = 0;
         fill_level[t] = 0;
+        chgbits[t] = 0;
+        chgbits[ngroups + t] = 0;
     }
 }
 
@@ -198,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
 // the samples form the level-0 frontier.  Samples are distinct nodes.
 template <int W>
 __global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_base, uint64_t* S0, uint64_t* snap0,
-                               int32_t* chg, const uint32_t* out_rp, LevelCounters* cnt) {
+                               int32_t* chg, uint64_t* chgbits, const uint32_t* out_rp, LevelCounters* cnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kg) return;
     const int64_t v = samples[src_base + i];
@@ -207,10 +219,12 @@ __global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_b
     atomicOr((unsigned long long*)&S0[v * W + (i >> 6)], bit);
     atomicOr((unsigned long long*)&snap0[v * W + (i >> 6)], bit);
     chg[v] = 0;
+    atomicOr((unsigned long long*)&chgbits[v >> 6], 1ull << (v & 63));
     atomicAdd((unsigned long long*)&cnt[i % kCounterSlots].frontier_arcs, (unsigned long long)(out_rp[v + 1] - out_rp[v]));
 }
 
 constexpr int32_t kModeLog = 4096;  // levels whose direction is logged for the host
+constexpr int64_t kSparseDiv = 8;   // a level is sparse when fewer than n / kSparseDiv nodes changed
 
 // One wave (lanes = counter slots): sums and clears the counter slots of the
 // level just run, records it, and decides whether and how the next level
@@ -219,7 +233,7 @@ constexpr int32_t kModeLog = 4096;  // levels whose direction is logged for the 
 // frontier.  Counters are read with device-scope atomic loads: they were
 // written by atomics of other blocks.
 __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, int32_t level, int32_t cap,
-                            int64_t arcs_total, int32_t alpha) {
+                            int64_t arcs_total, int32_t alpha, int64_t n) {
     const int t = lane_id();
     LevelCounters* c = cnt + t;
     const int64_t arcs = wave_sum64(__hip_atomic_load(&c->arcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -258,6 +272,7 @@ __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, 
     }
     s.nodes += n_out * 64;
     s.hubs_full = hub_open == 0 ? 1 : 0;
+    s.sparse = n_new * kSparseDiv < n ? 1 : 0;
     if (n_new > 0) s.lmax = level;
     s.frontier_arcs = farcs;
     if (n_out == 0) {
@@ -276,8 +291,8 @@ __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, 
 
 // level 0 (after the samples are placed): one wave
 __global__ void k_decide(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, int32_t level, int32_t cap,
-                         int64_t arcs_total, int32_t alpha) {
-    decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha);
+                         int64_t arcs_total, int32_t alpha, int64_t n) {
+    decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha, n);
 }
 
 // push along arc u->x of the mask su (u's seen mask): only bits x has not seen
@@ -359,7 +374,7 @@ __device__ __forceinline__ void push_chunk(const int32_t* __restrict__ out_col, 
 template <int W>
 __device__ __forceinline__ void hub_chunk(const int32_t* __restrict__ col, const uint64_t* __restrict__ Sprev,
                                           const int32_t* __restrict__ chunk, uint64_t* NX, uint64_t lastmask,
-                                          int64_t& scanned) {
+                                          const uint64_t* __restrict__ chgbits, bool sparse, int64_t& scanned) {
     const int lane = lane_id();
     const int64_t h = chunk[0];
     const uint32_t b = (uint32_t)chunk[1], e = (uint32_t)chunk[2];
@@ -380,16 +395,19 @@ __device__ __forceinline__ void hub_chunk(const int32_t* __restrict__ col, const
     for (uint32_t base = b; base < e; base += 128) {
         const uint32_t t0 = base + lane, t1 = t0 + 64;
         uint64_t a0[W], a1[W];
-        if (t0 < e) {
-            load_mask<W>(Sprev, col[t0], need, a0);
-            scanned += 1;
+        // a sparse level reads only the masks of neighbours that changed at the last level
+        const int64_t u0 = t0 < e ? col[t0] : -1, u1 = t1 < e ? col[t1] : -1;
+        const bool r0 = u0 >= 0 && (!sparse || ((chgbits[u0 >> 6] >> (u0 & 63)) & 1ull));
+        const bool r1 = u1 >= 0 && (!sparse || ((chgbits[u1 >> 6] >> (u1 & 63)) & 1ull));
+        scanned += r0 + r1;  // arcs whose mask was read (36 bytes each)
+        if (r0) {
+            load_mask<W>(Sprev, u0, need, a0);
         } else {
 #pragma unroll
             for (int w = 0; w < W; w++) a0[w] = 0;
         }
-        if (t1 < e) {
-            load_mask<W>(Sprev, col[t1], need, a1);
-            scanned += 1;
+        if (r1) {
+            load_mask<W>(Sprev, u1, need, a1);
         } else {
 #pragma unroll
             for (int w = 0; w < W; w++) a1[w] = 0;
@@ -423,16 +441,18 @@ __global__ __launch_bounds__(kBlock) void k_scatter_level(
     int32_t n_push_chunks, int32_t g0, int32_t ngroups, const int32_t* __restrict__ chg,
     const uint8_t* __restrict__ ghub, int64_t n,
     int32_t prev_level, const uint64_t* __restrict__ Sprev, uint64_t* NX, uint64_t lastmask, LevelCounters* cnt,
-    const BfsCtl* __restrict__ ctl) {
+    const BfsCtl* __restrict__ ctl, const uint64_t* __restrict__ chgbits) {
     if (ctl->done) return;
     const int pull = ctl->pull;
+    const bool sparse = ctl->sparse != 0;
     if (pull && ctl->hubs_full) return;  // every hub holds every bit: its chunks would find nothing
     const int32_t waves = gridDim.x * kWaves;
     const int32_t wid = blockIdx.x * kWaves + (threadIdx.x >> 6);
     WaveCounts wc;
     int64_t extra = 0;  // pull: arcs scanned; push: atomics issued
     if (pull) {
-        for (int32_t c = wid; c < n_hub_chunks; c += waves) hub_chunk<W>(col, Sprev, hub_chunks + 3 * (int64_t)c, NX, lastmask, extra);
+        for (int32_t c = wid; c < n_hub_chunks; c += waves)
+            hub_chunk<W>(col, Sprev, hub_chunks + 3 * (int64_t)c, NX, lastmask, chgbits, sparse, extra);
     } else {
         const int64_t items = (int64_t)n_push_chunks + (ngroups - g0);
         for (int64_t t = wid; t < items; t += waves) {
@@ -455,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
     int64_t n, int64_t nh, uint64_t* __restrict__ NX, uint64_t lastmask, int32_t level,
     const int32_t* __restrict__ sidx, int32_t* __restrict__ hist, int64_t hlen, int64_t k, int32_t src_base,
     LevelCounters* __restrict__ cnt, BfsCtl* ctl, int32_t* mode_log, int32_t cap, int64_t arcs_total, int32_t alpha,
-    const uint8_t* __restrict__ ghub) {
+    const uint8_t* __restrict__ ghub, uint64_t* __restrict__ chg_out) {
     if (ctl->done) return;
     const int pull = ctl->pull;
     __shared__ uint64_t lds_acc[kWaves][64][W];
@@ -584,7 +604,11 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
             chg[v] = level;
             wc.farcs += out_rp[v + 1] - out_rp[v];
         }
-        wc.n_new += (int32_t)__popcll(__ballot(anynew));
+        const uint64_t changed = __ballot(anynew);
+        if (lane == 0) {
+            wc.n_new += (int32_t)__popcll(changed);
+            chg_out[g] = changed;
+        }
         // hub nodes that still miss a bit after this level (the next pull's hub work)
         const uint64_t open = __ballot(valid && ishub && pairs_needed<W>(sn, lastmask) != 0);
         if (lane == 0) wc.hub_open += (int32_t)__popcll(open);
@@ -629,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
     __shared__ uint32_t last;
     if (threadIdx.x == 0) last = atomicAdd(&ctl->ticket, 1u + token) == gridDim.x - 1;
     __syncthreads();
-    if (last && threadIdx.x < 64) decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha);
+    if (last && threadIdx.x < 64) decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha, n);
 }
 
 __global__ void k_zero_counters(LevelCounters* c) {
@@ -660,18 +684,20 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     BfsCtl* ctl = (BfsCtl*)p;
     p += align256(sizeof(BfsCtl));
     int32_t* mode_log = (int32_t*)p;
+    p += align256(sizeof(int32_t) * kModeLog);
+    uint64_t* chgbits = (uint64_t*)p;  // [2][ngroups]: nodes that changed, by level parity
 
     const size_t plane = (size_t)n * W;
     const int rem = kg - (W - 1) * 64;
     const uint64_t lastmask = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
     const int64_t nmax = std::max<int64_t>(n, ngroups);
     hipLaunchKernelGGL((k_init<W>), dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, ngroups,
-                       S0, out.snap, NX, chg, gfull, out.fill_level, gv.preset, gv.gvalid);
+                       S0, out.snap, NX, chg, gfull, out.fill_level, chgbits, gv.preset, gv.gvalid);
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
     hipLaunchKernelGGL((k_init_samples<W>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, src_base, S0,
-                       out.snap, chg, gv.out_rp, cnt_dev);
+                       out.snap, chg, chgbits, gv.out_rp, cnt_dev);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev, ctl, mode_log, 0, out.cap, gv.arcs,
-                       gv.alpha);
+                       gv.alpha, n);
     stats->launches += 4;
 
     const unsigned gb = (unsigned)std::max<int64_t>(
@@ -698,12 +724,13 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
             if (timed) CCG_HIP(hipEventRecord(evp->at(2 + 2 * (size_t)L), st));
             hipLaunchKernelGGL((k_scatter_level<W>), dim3(sb), dim3(kBlock), 0, st, gv.col, gv.hub_chunks,
                                gv.n_hub_chunks, gv.out_rp, gv.out_col, gv.push_chunks, gv.n_push_chunks, g0, ngroups,
-                               chg, gv.ghub, n, L - 1, Sp, NX, lastmask, cnt_dev, ctl);
+                               chg, gv.ghub, n, L - 1, Sp, NX, lastmask, cnt_dev, ctl,
+                               (const uint64_t*)(chgbits + (size_t)((L - 1) & 1) * ngroups));
             if (timed) CCG_HIP(hipEventRecord(evp->at(3 + 2 * (size_t)L), st));
             hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp, Sc,
                                out.snap + (size_t)L * plane, out.fill_level, gfull, chg, ngroups, n, gv.nh, NX,
                                lastmask, L, sidx, out.hist, out.hlen, (int64_t)k, src_base, cnt_dev, ctl, mode_log,
-                               out.cap, gv.arcs, gv.alpha, gv.ghub);
+                               out.cap, gv.arcs, gv.alpha, gv.ghub, chgbits + (size_t)(L & 1) * ngroups);
         }
         CCG_HIP(hipGetLastError());
         if (enqueue_only) return 0;
@@ -763,7 +790,8 @@ size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh) {
     const int W = (kg + 63) / 64;
     const int64_t ngroups = (n + 63) / 64;
     return align256(sizeof(uint64_t) * n * W) * 3 + align256(sizeof(int32_t) * n) + align256((size_t)ngroups) +
-           align256(sizeof(BfsCtl)) + align256(sizeof(int32_t) * kModeLog) + 1024;
+           align256(sizeof(BfsCtl)) + align256(sizeof(int32_t) * kModeLog) + align256(sizeof(uint64_t) * 2 * ngroups) +
+           1024;
 }
 
 int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,

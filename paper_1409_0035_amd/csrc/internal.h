@@ -258,6 +258,8 @@ struct BfsCtl {
     int32_t pull_levels;  // of which pulls
     uint32_t ticket;      // blocks of the current merge launch that have finished
     int32_t hubs_full;    // every hub node was full after the last level: a pull has no hub work
+    int32_t sparse;       // few nodes changed at the last level: pulls read only their masks
+    int32_t pad;
     int64_t frontier_arcs;  // out-arcs of the nodes that changed at the last level
     int64_t pull_arcs;      // arcs the last pull scanned (what a pull would cost now)
     int64_t arcs;           // arcs scanned or pushed along, all levels
