@@ -47,7 +47,9 @@
 // hist[i][L] = #{v not sampled : d(c_i, v) = L} by ballot transposition.
 // A group leaves the work list once all of its nodes were full (reached by
 // every sample) at the start of a level; fill_level[g] records the last level
-// whose snapshot the group wrote -- later snapshots of it are all-ones.
+// it was processed at.  Its later snapshots are written all-ones, so every
+// level's snapshot plane is complete and is the next level's working mask:
+// there is no separate working copy of the masks.
 #include "internal.h"
 
 namespace ccg {
@@ -179,7 +181,7 @@ __device__ __forceinline__ uint32_t flush_counts(WaveCounts c, LevelCounters* sl
 }
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uint64_t* S0, uint64_t* snap0,
+__global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uint64_t* snap0,
                                                  uint64_t* NX, int32_t* chg, uint8_t* gfull, int32_t* fill_level,
                                                  uint64_t* chgbits, const uint64_t* __restrict__ preset,
                                                  const int32_t* __restrict__ gvalid) {
@@ -193,8 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
             s0[w] = preset ? (pad ? ~0ull : preset[g * W + w]) : 0ull;
             z[w] = 0;
         }
-        store_mask<W>(S0, t, s0);  // 16-byte stores
-        store_mask<W>(snap0, t, s0);
+        store_mask<W>(snap0, t, s0);  // 16-byte stores
         store_mask<W>(NX, t, z);
         chg[t] = -1;
     }
@@ -209,14 +210,13 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
 // Level-0 state: bit i in c_i's mask (both the working mask and snapshot 0);
 // the samples form the level-0 frontier.  Samples are distinct nodes.
 template <int W>
-__global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_base, uint64_t* S0, uint64_t* snap0,
+__global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_base, uint64_t* snap0,
                                int32_t* chg, uint64_t* chgbits, const uint32_t* out_rp, LevelCounters* cnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kg) return;
     const int64_t v = samples[src_base + i];
     if (v < 0) return;  // a bit position no sample uses (batches)
     const unsigned long long bit = 1ull << (i & 63);
-    atomicOr((unsigned long long*)&S0[v * W + (i >> 6)], bit);
     atomicOr((unsigned long long*)&snap0[v * W + (i >> 6)], bit);
     chg[v] = 0;
     atomicOr((unsigned long long*)&chgbits[v >> 6], 1ull << (v & 63));
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_level(
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_group_level(
     const uint32_t* __restrict__ rp, const int32_t* __restrict__ col, const uint32_t* __restrict__ out_rp,
-    const uint64_t* __restrict__ Sprev, uint64_t* __restrict__ Scur, uint64_t* __restrict__ snap,
+    const uint64_t* __restrict__ Sprev, uint64_t* __restrict__ snap,
     int32_t* __restrict__ fill_level, uint8_t* __restrict__ gfull, int32_t* __restrict__ chg, int32_t ngroups,
     int64_t n, int64_t nh, uint64_t* __restrict__ NX, uint64_t lastmask, int32_t level,
     const int32_t* __restrict__ sidx, int32_t* __restrict__ hist, int64_t hlen, int64_t k, int32_t src_base,
@@ -494,7 +494,16 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
 
     const int32_t stride = gridDim.x * kWaves;
     for (int32_t g = blockIdx.x * kWaves + wave; g < ngroups; g += stride) {
-        if (gfull[g]) continue;  // every node of the group is full in every later mask
+        if (gfull[g]) {  // every node of the group is full in every later mask: write it so
+            const int64_t v = (int64_t)g * 64 + lane;
+            if (v < n) {
+                uint64_t f[W];
+#pragma unroll
+                for (int w = 0; w < W; w++) f[w] = full_word<W>(w, lastmask);
+                store_mask<W>(snap, v, f);
+            }
+            continue;
+        }
         const int64_t v = (int64_t)g * 64 + lane;
         const bool valid = v < n;
         uint64_t sv[W];
@@ -596,10 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
             sn[w] = sv[w] | nw[w];
             anynew = anynew || (nw[w] != 0);
         }
-        if (valid) {
-            store_mask<W>(Scur, v, sn);
-            store_mask<W>(snap, v, sn);
-        }
+        if (valid) store_mask<W>(snap, v, sn);
         if (anynew) {
             chg[v] = level;
             wc.farcs += out_rp[v + 1] - out_rp[v];
@@ -671,10 +677,6 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     const int64_t n = gv.n;
     const int32_t ngroups = (int32_t)((n + 63) / 64);
     char* p = (char*)scratch;
-    uint64_t* S0 = (uint64_t*)p;
-    p += align256(sizeof(uint64_t) * n * W);
-    uint64_t* S1 = (uint64_t*)p;
-    p += align256(sizeof(uint64_t) * n * W);
     uint64_t* NX = (uint64_t*)p;
     p += align256(sizeof(uint64_t) * n * W);
     int32_t* chg = (int32_t*)p;
@@ -692,9 +694,9 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     const uint64_t lastmask = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
     const int64_t nmax = std::max<int64_t>(n, ngroups);
     hipLaunchKernelGGL((k_init<W>), dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, ngroups,
-                       S0, out.snap, NX, chg, gfull, out.fill_level, chgbits, gv.preset, gv.gvalid);
+                       out.snap, NX, chg, gfull, out.fill_level, chgbits, gv.preset, gv.gvalid);
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
-    hipLaunchKernelGGL((k_init_samples<W>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, src_base, S0,
+    hipLaunchKernelGGL((k_init_samples<W>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, src_base,
                        out.snap, chg, chgbits, gv.out_rp, cnt_dev);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev, ctl, mode_log, 0, out.cap, gv.arcs,
                        gv.alpha, n);
@@ -718,8 +720,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
         const int32_t end = (int32_t)std::min<int64_t>((int64_t)level + batch, out.cap);
         if (evp) CCG_HIP(hipEventRecord(evp->at(0), st));
         for (int32_t L = level; L < end; L++) {
-            uint64_t* Sp = (L & 1) ? S0 : S1;  // level 1 reads S0
-            uint64_t* Sc = (L & 1) ? S1 : S0;
+            const uint64_t* Sp = out.snap + (size_t)(L - 1) * plane;  // the previous level's plane
             const bool timed = evp && L < kTimedLevels;
             if (timed) CCG_HIP(hipEventRecord(evp->at(2 + 2 * (size_t)L), st));
             hipLaunchKernelGGL((k_scatter_level<W>), dim3(sb), dim3(kBlock), 0, st, gv.col, gv.hub_chunks,
@@ -727,7 +728,7 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
                                chg, gv.ghub, n, L - 1, Sp, NX, lastmask, cnt_dev, ctl,
                                (const uint64_t*)(chgbits + (size_t)((L - 1) & 1) * ngroups));
             if (timed) CCG_HIP(hipEventRecord(evp->at(3 + 2 * (size_t)L), st));
-            hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp, Sc,
+            hipLaunchKernelGGL((k_group_level<W>), dim3(gb), dim3(kBlock), 0, st, gv.rp, gv.col, gv.out_rp, Sp,
                                out.snap + (size_t)L * plane, out.fill_level, gfull, chg, ngroups, n, gv.nh, NX,
                                lastmask, L, sidx, out.hist, out.hlen, (int64_t)k, src_base, cnt_dev, ctl, mode_log,
                                out.cap, gv.arcs, gv.alpha, gv.ghub, chgbits + (size_t)(L & 1) * ngroups);
@@ -781,7 +782,7 @@ BfsCtl* bfs_batched_ctl(void* scratch, int64_t n, int32_t kg) {
     const int W = (kg + 63) / 64;
     const int64_t ngroups = (n + 63) / 64;
     char* p = (char*)scratch;
-    p += align256(sizeof(uint64_t) * n * W) * 3 + align256(sizeof(int32_t) * n) + align256((size_t)ngroups);
+    p += align256(sizeof(uint64_t) * n * W) + align256(sizeof(int32_t) * n) + align256((size_t)ngroups);
     return (BfsCtl*)p;
 }
 
@@ -789,7 +790,7 @@ size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh) {
     (void)nh;
     const int W = (kg + 63) / 64;
     const int64_t ngroups = (n + 63) / 64;
-    return align256(sizeof(uint64_t) * n * W) * 3 + align256(sizeof(int32_t) * n) + align256((size_t)ngroups) +
+    return align256(sizeof(uint64_t) * n * W) + align256(sizeof(int32_t) * n) + align256((size_t)ngroups) +
            align256(sizeof(BfsCtl)) + align256(sizeof(int32_t) * kModeLog) + align256(sizeof(uint64_t) * 2 * ngroups) +
            1024;
 }

@@ -1113,7 +1113,10 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             const bool staged = out->S_hyb || out->S_samp || out->S_piv || out->S_pub || out->pivot || out->delta ||
                                 out->sampsum;
             ba_es = bits_epilogue_scratch(k, ba.lmax, want_err ? n : 0, want_err, staged ? n : 0);
-            ba_scratch = ba_es <= trav_scratch ? ts : L.arena2.get(ba_es);
+            // the traversal's scratch is free now, up to its control block,
+            // which a replay of this estimate reads back afterwards
+            const size_t ts_free = (size_t)((char*)bfs_batched_ctl(ts, n, kg0) - (char*)ts);
+            ba_scratch = ba_es <= ts_free ? ts : L.arena2.get(ba_es);
             run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
             L.last_maxd = ba.lmax;
         } else {
