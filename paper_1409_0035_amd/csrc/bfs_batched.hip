@@ -180,11 +180,16 @@ __device__ __forceinline__ uint32_t flush_counts(WaveCounts c, LevelCounters* sl
     return 0;
 }
 
+__device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, int32_t level, int32_t cap,
+                            int64_t arcs_total, int32_t alpha, int64_t n);
+
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uint64_t* snap0,
                                                  uint64_t* NX, int32_t* chg, uint8_t* gfull, int32_t* fill_level,
                                                  uint64_t* chgbits, const uint64_t* __restrict__ preset,
-                                                 const int32_t* __restrict__ gvalid) {
+                                                 const int32_t* __restrict__ gvalid, LevelCounters* cnt,
+                                                 DevFlags* zero_flags, int32_t* sidx_fill, int32_t* hist_zero,
+                                                 int64_t hist_elems) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < n) {
         const int64_t g = t >> 6;
@@ -198,6 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
         store_mask<W>(snap0, t, s0);  // 16-byte stores
         store_mask<W>(NX, t, z);
         chg[t] = -1;
+        if (sidx_fill) sidx_fill[t] = -1;
     }
     if (t < ngroups) {
         gfull[t] = 0;
@@ -205,22 +211,34 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
         chgbits[t] = 0;
         chgbits[ngroups + t] = 0;
     }
+    if (t < hist_elems) hist_zero[t] = 0;
+    if (t < kCounterSlots) cnt[t] = LevelCounters{};
+    if (zero_flags && t == 0) *zero_flags = DevFlags{};
 }
 
-// Level-0 state: bit i in c_i's mask (both the working mask and snapshot 0);
-// the samples form the level-0 frontier.  Samples are distinct nodes.
+// Level-0 state, one block: bit i in c_i's mask (the working mask is the
+// level-0 snapshot); the samples form the level-0 frontier.  Samples are
+// distinct nodes.  Then the block's first wave makes the level-0 decision.
 template <int W>
-__global__ void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_base, uint64_t* snap0,
-                               int32_t* chg, uint64_t* chgbits, const uint32_t* out_rp, LevelCounters* cnt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kg) return;
-    const int64_t v = samples[src_base + i];
-    if (v < 0) return;  // a bit position no sample uses (batches)
-    const unsigned long long bit = 1ull << (i & 63);
-    atomicOr((unsigned long long*)&snap0[v * W + (i >> 6)], bit);
-    chg[v] = 0;
-    atomicOr((unsigned long long*)&chgbits[v >> 6], 1ull << (v & 63));
-    atomicAdd((unsigned long long*)&cnt[i % kCounterSlots].frontier_arcs, (unsigned long long)(out_rp[v + 1] - out_rp[v]));
+__global__ __launch_bounds__(kBlock) void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_base,
+                                                         uint64_t* snap0, int32_t* chg, uint64_t* chgbits,
+                                                         const uint32_t* out_rp, LevelCounters* cnt,
+                                                         int32_t* sidx_fill, BfsCtl* ctl, int32_t* mode_log,
+                                                         int32_t cap, int64_t arcs_total, int32_t alpha, int64_t n) {
+    for (int i = threadIdx.x; i < kg; i += kBlock) {
+        const int64_t v = samples[src_base + i];
+        if (v < 0) continue;  // a bit position no sample uses (batches)
+        const unsigned long long bit = 1ull << (i & 63);
+        atomicOr((unsigned long long*)&snap0[v * W + (i >> 6)], bit);
+        chg[v] = 0;
+        if (sidx_fill) sidx_fill[v] = src_base + i;
+        atomicOr((unsigned long long*)&chgbits[v >> 6], 1ull << (v & 63));
+        atomicAdd((unsigned long long*)&cnt[i % kCounterSlots].frontier_arcs,
+                  (unsigned long long)(out_rp[v + 1] - out_rp[v]));
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x < 64) decide_wave(cnt, ctl, mode_log, 0, cap, arcs_total, alpha, n);
 }
 
 constexpr int32_t kModeLog = 4096;  // levels whose direction is logged for the host
@@ -289,11 +307,6 @@ __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, 
     *ctl = s;
 }
 
-// level 0 (after the samples are placed): one wave
-__global__ void k_decide(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, int32_t level, int32_t cap,
-                         int64_t arcs_total, int32_t alpha, int64_t n) {
-    decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha, n);
-}
 
 // push along arc u->x of the mask su (u's seen mask): only bits x has not seen
 // and that are not already pending in NX(x) need the atomic, so popular
@@ -662,10 +675,6 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
     if (last && threadIdx.x < 64) decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha, n);
 }
 
-__global__ void k_zero_counters(LevelCounters* c) {
-    const int t = threadIdx.x;
-    if (t < kCounterSlots) c[t] = LevelCounters{};
-}
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -692,15 +701,14 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     const size_t plane = (size_t)n * W;
     const int rem = kg - (W - 1) * 64;
     const uint64_t lastmask = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
-    const int64_t nmax = std::max<int64_t>(n, ngroups);
+    const int64_t hist_elems = out.zero_hist ? (int64_t)kHistSlotsBatched * k * out.hlen : 0;
+    const int64_t nmax = std::max<int64_t>(std::max<int64_t>(n, ngroups), std::max<int64_t>(hist_elems, kCounterSlots));
     hipLaunchKernelGGL((k_init<W>), dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, ngroups,
-                       out.snap, NX, chg, gfull, out.fill_level, chgbits, gv.preset, gv.gvalid);
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev);
-    hipLaunchKernelGGL((k_init_samples<W>), dim3((kg + 63) / 64), dim3(64), 0, st, samples_dev, kg, src_base,
-                       out.snap, chg, chgbits, gv.out_rp, cnt_dev);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kCounterSlots), 0, st, cnt_dev, ctl, mode_log, 0, out.cap, gv.arcs,
-                       gv.alpha, n);
-    stats->launches += 4;
+                       out.snap, NX, chg, gfull, out.fill_level, chgbits, gv.preset, gv.gvalid, cnt_dev,
+                       out.zero_flags, out.sidx_fill, out.hist, hist_elems);
+    hipLaunchKernelGGL((k_init_samples<W>), dim3(1), dim3(kBlock), 0, st, samples_dev, kg, src_base, out.snap, chg,
+                       chgbits, gv.out_rp, cnt_dev, out.sidx_fill, ctl, mode_log, out.cap, gv.arcs, gv.alpha, n);
+    stats->launches += 2;
 
     const unsigned gb = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((ngroups + kWaves - 1) / kWaves, std::max(1, gv.level_blocks)));

@@ -982,10 +982,11 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 // recompute as usual, which rewrites every output
             }
         }
-        fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+        // the batched traversal of a single sample group zeroes the flags and
+        // the histogram and fills sidx in its own first launches
+        if (!bits_path) fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
         CCG_HIP(hipEventRecord(L.ev[0], st));
-        compute_sidx(st, samples_dev, k, sidx, n);
-        if (hist) fill_u32(st, hist, 0u, hist_elems);
+        if (!bits_path) compute_sidx(st, samples_dev, k, sidx, n);
 
         // ---- traversal
         int rc = 0;
@@ -1042,6 +1043,11 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     lv.hlen = cap;
                     lv.lmax = &lm;
                     lv.hint = gr->bfs_hint.load(std::memory_order_relaxed);
+                    if (bits_path) {
+                        lv.zero_flags = flags;
+                        lv.sidx_fill = sidx;
+                        lv.zero_hist = true;
+                    }
                     rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, &ds, &L.events);
                     if (rc == 0) gr->bfs_hint.store(ds.bfs_levels, std::memory_order_relaxed);
                     if (rc != 0) break;
@@ -1157,9 +1163,6 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             const bool began = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
             bool captured_ok = began;
             if (began) try {
-                fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
-                compute_sidx(st, samples_dev, k, sidx, n);
-                fill_u32(st, hist, 0u, hist_elems);
                 int32_t lm = 0;
                 BfsLevels lv;
                 lv.snap = snap;
@@ -1169,6 +1172,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 lv.hlen = cap;
                 lv.lmax = &lm;
                 lv.enqueue_only = stats.bfs_levels;
+                lv.zero_flags = flags;
+                lv.sidx_fill = sidx;
+                lv.zero_hist = true;
                 TravStats ignored;
                 (void)bfs_batched(st, make_view(0), samples_dev, k, 0, k, lv, sidx, ts, trav_scratch, cnt, &ignored,
                                   nullptr);

@@ -278,6 +278,11 @@ struct BfsLevels {
     int64_t hlen = 0;
     int32_t* lmax = nullptr;      // host: largest level with new bits (max over calls)
     int32_t hint = 0;             // levels the host enqueues before its first check (0 = a few)
+    // optional, for a traversal of all of the job's samples (src_base 0, kg = k): the job's setup
+    // folded into the traversal's first two launches instead of launches of its own
+    DevFlags* zero_flags = nullptr;  // zeroed
+    int32_t* sidx_fill = nullptr;    // [n]: -1, then each sample's index
+    bool zero_hist = false;          // hist ([kHistSlotsBatched][k][hlen]) zeroed
     int32_t enqueue_only = 0;     // > 0: enqueue exactly this many levels and return at once (stream capture)
 };
 
