@@ -254,6 +254,11 @@ struct Lane {
     Arena arena2;     // epilogue tables (sized once the largest distance is known)
     Arena arenaW;     // node-weighted estimate: its distance rows and per-node arrays
     LevelCounters* cnt_host = nullptr;  // pinned
+    struct Readback {
+        BfsCtl ctl;
+        DevFlags flags;
+    };
+    Readback* rb_host = nullptr;  // pinned: a replay's control block and flags
     hipEvent_t ev[4] = {};
     EventPool events;  // per-launch timing inside the traversals
     uint64_t gen = 0;  // arena generation
@@ -292,6 +297,7 @@ struct Lane {
             own_stream = true;
         }
         CCG_HIP(hipHostMalloc((void**)&cnt_host, sizeof(LevelCounters) * kCounterSlots, hipHostMallocDefault));
+        CCG_HIP(hipHostMalloc((void**)&rb_host, sizeof(Readback), hipHostMallocDefault));
         for (auto& e : ev) CCG_HIP(hipEventCreate(&e));
     }
     void destroy() {
@@ -300,6 +306,8 @@ struct Lane {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         if (cnt_host) (void)hipHostFree(cnt_host);
+        if (rb_host) (void)hipHostFree(rb_host);
+        rb_host = nullptr;
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         cnt_host = nullptr;
         stream = nullptr;
@@ -960,11 +968,12 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 CCG_HIP(hipEventRecord(L.ev[0], st));
                 CCG_HIP(hipGraphLaunch(cap_e->exec, st));
                 CCG_HIP(hipEventRecord(L.ev[2], st));
-                BfsCtl hc;
-                DevFlags hf;
-                CCG_HIP(hipMemcpyAsync(&hc, bfs_batched_ctl(ts, n, kg0), sizeof(hc), hipMemcpyDeviceToHost, st));
-                CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+                CCG_HIP(hipMemcpyAsync(&L.rb_host->ctl, bfs_batched_ctl(ts, n, kg0), sizeof(BfsCtl),
+                                       hipMemcpyDeviceToHost, st));
+                CCG_HIP(hipMemcpyAsync(&L.rb_host->flags, flags, sizeof(DevFlags), hipMemcpyDeviceToHost, st));
                 CCG_HIP(hipStreamSynchronize(st));
+                const BfsCtl hc = L.rb_host->ctl;
+                const DevFlags hf = L.rb_host->flags;
                 if (hc.done && hc.status == 0 && hc.lmax == cap_e->lmax && hc.levels <= cap_e->levels &&
                     !hf.disconnected && !hf.overflow && !hf.bad_sample && !hf.timeout) {
                     if (timing) {
