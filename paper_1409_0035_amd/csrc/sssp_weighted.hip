@@ -101,7 +101,7 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
 // Pile appends are staged in LDS per block and reserved in the global pile
 // with one atomic per block and flush (thousands of waves appending to one
 // counter would serialise on it).
-constexpr int kStage = 2048;
+constexpr int kStage = 1024;
 
 struct Stage {
     uint64_t item[2][kStage];
