@@ -171,7 +171,8 @@ struct WArgs {
 };
 
 // One round (block-uniform control flow; every block returns normally).
-__device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S, uint32_t* smax, uint64_t* Wloc) {
+__device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S, uint32_t* smax, uint64_t* Wloc,
+                                            int32_t* wcount) {
     const uint32_t* __restrict__ rp = A.rp;
     const int32_t* __restrict__ col = A.col;
     const int32_t* __restrict__ wt = A.wt;
@@ -237,51 +238,20 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
     }
     __syncthreads();
     uint32_t lmin = kInf;
-    if (split) {
-        // far pile of epoch ep -> near pile (below hi) or far pile of epoch ep+1
-        uint64_t* fin = ep % 2 == 0 ? F0 : F1;
-        uint64_t* fout = ep % 2 == 0 ? F1 : F0;
-        int32_t* fcnt_out = &dev->fcnt[(ep + 1) % 3];
-        for (int64_t base = b0; base < b1; base += kBlock) {
-            const int64_t t = base + threadIdx.x;
-            uint64_t item = 0;
-            bool to_near = false, to_far = false;
-            if (t < b1) {
-                item = fin[t];
-                const int64_t bit = (int64_t)(item >> 32) * n + (uint32_t)item;
-                atomicAnd(&fbit[bit >> 5], ~(1u << (bit & 31)));
-                // a split round relaxes nothing, so the word is stable here
-                const uint32_t e = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t d = e >> 1;
-                if (d < hi) {
-                    if (e & 1u) {  // not yet in a near pile
-                        atomicAnd(&Dt[bit], ~1u);
-                        to_near = true;
-                    }
-                } else {
-                    const uint32_t old = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
-                    to_far = !(old & (1u << (bit & 31)));
-                    if (to_far) lmin = d < lmin ? d : lmin;
-                }
-            }
-            stage_put(S, 0, to_near, item);
-            stage_put(S, 1, to_far, item);
-            stage_maybe_flush(S, nout, ncnt_out, fout, fcnt_out, cap, &dev->overflow);
-        }
-        stage_flush(S, nout, ncnt_out, fout, fcnt_out, cap, &dev->overflow);
-        lmin = wave_min_u32(lmin);
-        if (lane_id() == 0 && lmin != kInf) atomicMin(&dev->minfar[(ep + 1) % 3], lmin);
-        return;
-    }
+    // Far appends go to the pile of the round's epoch: a split round opens
+    // epoch ep + 1, and the near rounds after it append there too.
+    const int32_t epa = split ? ep + 1 : ep;
+    uint64_t* fpile = epa % 2 == 0 ? F0 : F1;
+    int32_t* fcnt_cur = &dev->fcnt[epa % 3];
     // near round: relax every pair of the near pile; kPairLanes lanes per
     // pair, each taking every kPairLanes-th arc, so a round costs about one
     // chain of dependent atomics instead of one per arc.  Pairs a block finds
     // below the bound are then relaxed by the same block from its stage for up
     // to local_passes more passes before anything is flushed: relaxations may
     // run in any order (label correcting), and improvements travel many hops
-    // per launch instead of one.
-    uint64_t* fpile = ep % 2 == 0 ? F0 : F1;
-    int32_t* fcnt_cur = &dev->fcnt[ep % 3];
+    // per launch instead of one.  A split round relaxes the far pairs that fall
+    // below its new bound at once, the same way, instead of handing them to
+    // the next round.
     constexpr int kPairLanes = 8;
     const int sub = threadIdx.x & (kPairLanes - 1);
     auto relax_batch = [&](auto fetch, int64_t lo, int64_t hi_ix) {
@@ -344,7 +314,53 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
             }
         }
     };
-    relax_batch([&](int64_t t) { return nin[t]; }, b0, b1);
+    if (split) {
+        // far pile of epoch ep: pairs below hi not yet in a near pile are
+        // relaxed here (chunk by chunk, gathered in Wloc); the rest move to
+        // the pile of epoch ep + 1.  Other blocks relax meanwhile, so a word
+        // may only drop below what is read here; an improver that lands below
+        // hi queues the pair itself.
+        uint64_t* fin = ep % 2 == 0 ? F0 : F1;
+        for (int64_t c0 = b0; c0 < b1; c0 += kStage) {
+            const int64_t c1 = std::min<int64_t>(c0 + kStage, b1);
+            __syncthreads();  // every thread has read the last chunk's count
+            if (threadIdx.x == 0) *wcount = 0;
+            __syncthreads();
+            for (int64_t base = c0; base < c1; base += kBlock) {
+                const int64_t t = base + threadIdx.x;
+                uint64_t item = 0;
+                bool take = false, to_far = false;
+                if (t < c1) {
+                    item = fin[t];
+                    const int64_t bit = (int64_t)(item >> 32) * n + (uint32_t)item;
+                    atomicAnd(&fbit[bit >> 5], ~(1u << (bit & 31)));
+                    const uint32_t e = __hip_atomic_load(&Dt[bit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t d = e >> 1;
+                    if (d < hi) {
+                        take = (e & 1u) != 0;  // not in a near pile: relax it now
+                    } else {
+                        const uint32_t old = atomicOr(&fbit[bit >> 5], 1u << (bit & 31));
+                        to_far = !(old & (1u << (bit & 31)));
+                        if (to_far) lmin = d < lmin ? d : lmin;
+                    }
+                }
+                const uint64_t m = __ballot(take);
+                if (m) {
+                    int at = 0;
+                    if (lane_id() == 0) at = atomicAdd(wcount, (int)__popcll(m));
+                    at = __shfl(at, 0);
+                    if (take) Wloc[at + (int)__popcll(m & lanemask_lt())] = item;
+                }
+                stage_put(S, 1, to_far, item);
+                stage_maybe_flush(S, nout, ncnt_out, fpile, fcnt_cur, cap, &dev->overflow);
+            }
+            __syncthreads();
+            const int32_t cnt = *wcount;
+            relax_batch([&](int64_t t) { return Wloc[t]; }, 0, cnt);
+        }
+    } else {
+        relax_batch([&](int64_t t) { return nin[t]; }, b0, b1);
+    }
     for (int li = 0; li < A.local_passes; li++) {
         __syncthreads();
         const int32_t cnt = S.count[0];
@@ -357,14 +373,15 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
     }
     stage_flush(S, nout, ncnt_out, fpile, fcnt_cur, cap, &dev->overflow);
     lmin = wave_min_u32(lmin);
-    if (lane_id() == 0 && lmin != kInf) atomicMin(&dev->minfar[ep % 3], lmin);
+    if (lane_id() == 0 && lmin != kInf) atomicMin(&dev->minfar[epa % 3], lmin);
 }
 
 __global__ __launch_bounds__(kBlock) void k_wround(WArgs A, int32_t r) {
     __shared__ Stage S;
     __shared__ uint32_t smax[kBlock / 64];
     __shared__ uint64_t Wloc[kStage];
-    wround_body(A, r, S, smax, Wloc);
+    __shared__ int32_t wcount;
+    wround_body(A, r, S, smax, Wloc, &wcount);
 }
 
 // All rounds in one launch; rounds are separated by a grid barrier.
@@ -372,8 +389,9 @@ __global__ __launch_bounds__(kBlock) void k_wpersist(WArgs A, GridSync* gs, int3
     __shared__ Stage S;
     __shared__ uint32_t smax[kBlock / 64];
     __shared__ uint64_t Wloc[kStage];
+    __shared__ int32_t wcount;
     for (int32_t r = 1; r < rmax; r++) {
-        wround_body(A, r, S, smax, Wloc);
+        wround_body(A, r, S, smax, Wloc, &wcount);
         if (!grid_barrier(gs, gridDim.x)) return;
         if (__hip_atomic_load(&A.dev->ctl[r % 3].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     }
