@@ -9,7 +9,9 @@
 // v->u of length w, cand = Dt[j][v] + w is applied with atomicMin; an
 // improved pair goes to the next near pile if cand < hi, else to the far pile.
 // When a round leaves the near pile empty, the next round splits the far
-// pile at a raised bound hi (to the first bucket that holds a far pair).
+// pile at a raised bound hi (to the first bucket that holds a far pair): the
+// pairs below it are relaxed in that same round, the rest move to the next
+// far pile.
 // Label-correcting: a pair may be relaxed again after its distance drops,
 // and the result is the exact shortest distance when the piles run dry.
 //
@@ -29,8 +31,8 @@
 // atomic min with 2*cand clears the flag in the same operation and tells the
 // improver whether it was the one to clear it (and so must enqueue).  Both
 // act on one word, so no relaxation can miss an improvement.  The far pile
-// keeps a bit per pair; it is only drained by split rounds, which relax
-// nothing.  The last pass rewrites Dt to plain distances.
+// keeps a bit per pair; it is only drained by split rounds.  The last pass
+// rewrites Dt to plain distances.
 #include "internal.h"
 
 namespace ccg {
