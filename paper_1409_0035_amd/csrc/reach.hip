@@ -12,7 +12,7 @@
 //
 // Batched here: up to 64W sources of consecutive ranks advance together as
 // one bit-parallel BFS (bit b = the b-th source of the batch, so bit order is
-// rank order).  The first batches are smaller (256, then 512 sources): while
+// rank order).  The first batches are smaller (128, 256, then 512 sources): while
 // every node still collects, each extra word costs on every arc, whereas the
 // later batches touch few nodes and are bound by the fixed cost of a cycle,
 // so fewer, larger batches pay off there.  Kernels touch only the words the
@@ -46,7 +46,7 @@ namespace ccg {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int32_t kFirstBatch = 256;  // sources in the first batch; doubled per batch up to 64W
+constexpr int32_t kFirstBatch = 128;  // sources in the first batch; doubled per batch up to 64W
 // Frontier entries are chunks of at most kChunk propagation arcs of a node
 // (node << 32 | offset of the chunk's first arc), so a node with a huge
 // degree is spread over many waves instead of holding up the level in one.
