@@ -219,14 +219,28 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int32_t ngroups, uin
 // Level-0 state, one block: bit i in c_i's mask (the working mask is the
 // level-0 snapshot); the samples form the level-0 frontier.  Samples are
 // distinct nodes.  Then the block's first wave makes the level-0 decision.
+// With stage_ids the samples are taken from pinned host memory and stored to
+// `samples` for the later launches (the caller's numbering to samples_out).
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_init_samples(const int32_t* samples, int32_t kg, int32_t src_base,
+__global__ __launch_bounds__(kBlock) void k_init_samples(int32_t* samples, const int32_t* stage_ids,
+                                                         const int32_t* stage_caller, int32_t* samples_out,
+                                                         int32_t kg, int32_t src_base,
                                                          uint64_t* snap0, int32_t* chg, uint64_t* chgbits,
                                                          const uint32_t* out_rp, LevelCounters* cnt,
                                                          int32_t* sidx_fill, BfsCtl* ctl, int32_t* mode_log,
                                                          int32_t cap, int64_t arcs_total, int32_t alpha, int64_t n) {
     for (int i = threadIdx.x; i < kg; i += kBlock) {
-        const int64_t v = samples[src_base + i];
+        const int32_t j = src_base + i;
+        int64_t v;
+        if (stage_ids) {  // pinned host memory: system-scope loads see what the host wrote before the launch
+            const int32_t s = __hip_atomic_load(stage_ids + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            samples[j] = s;
+            if (samples_out)
+                samples_out[j] = __hip_atomic_load(stage_caller + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            v = s;
+        } else {
+            v = samples[j];
+        }
         if (v < 0) continue;  // a bit position no sample uses (batches)
         const unsigned long long bit = 1ull << (i & 63);
         atomicOr((unsigned long long*)&snap0[v * W + (i >> 6)], bit);
@@ -480,6 +494,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter_level(
     (void)flush_counts(wc, cnt);
 }
 
+// Column sums of a 64 x 64 bit matrix held one row per lane (bit j of lane
+// i's word is entry (i, j)): six butterfly stages transpose it, each swapping
+// the off-diagonal s x s blocks of every 2s x 2s diagonal block (s = 32 .. 1),
+// after which lane j holds column j; returns that column's popcount.
+__device__ inline int32_t column_count64(uint64_t x, int lane) {
+    constexpr uint64_t kLow[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                  0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+        const int s = 32 >> t;
+        const uint64_t lo = kLow[t];
+        const uint64_t p = __shfl_xor(x, s);
+        x = (lane & s) ? ((x & ~lo) | ((p & ~lo) >> s)) : ((x & lo) | ((p & lo) << s));
+    }
+    return (int32_t)__popcll(x);
+}
+
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_group_level(
     const uint32_t* __restrict__ rp, const int32_t* __restrict__ col, const uint32_t* __restrict__ out_rp,
@@ -639,17 +670,15 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
         if (active && lane == 0) wc.n_out += 1;
 
         // histogram: lane j accumulates, for word w, how many non-sampled
-        // nodes of the group gained bit w*64+j at this level
+        // nodes of the group gained bit w*64+j at this level (the column sums
+        // of the group's 64 x 64 bit matrix of new bits)
         if (do_hist) {
             const bool counted = anynew && sidx[v] < 0;
 #pragma unroll
             for (int w = 0; w < W; w++) {
                 const uint64_t x = counted ? nw[w] : 0ull;
                 if (!__ballot(x != 0)) continue;
-                for (int j = 0; j < 64; j++) {
-                    const int c = (int)__popcll(__ballot((x >> j) & 1ull));
-                    if (lane == j) hcnt[w] += c;
-                }
+                hcnt[w] += column_count64(x, lane);
             }
         }
     }
@@ -680,7 +709,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 
 template <int W>
-int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
+int bfs_batched_t(hipStream_t st, const BfsView& gv, int32_t* samples_dev, int32_t kg, int32_t src_base,
                   int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, LevelCounters* cnt_dev,
                   TravStats* stats, EventPool* evp) {
     const int64_t n = gv.n;
@@ -706,7 +735,8 @@ int bfs_batched_t(hipStream_t st, const BfsView& gv, const int32_t* samples_dev,
     hipLaunchKernelGGL((k_init<W>), dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, ngroups,
                        out.snap, NX, chg, gfull, out.fill_level, chgbits, gv.preset, gv.gvalid, cnt_dev,
                        out.zero_flags, out.sidx_fill, out.hist, hist_elems);
-    hipLaunchKernelGGL((k_init_samples<W>), dim3(1), dim3(kBlock), 0, st, samples_dev, kg, src_base, out.snap, chg,
+    hipLaunchKernelGGL((k_init_samples<W>), dim3(1), dim3(kBlock), 0, st, samples_dev, out.stage_ids,
+                       out.stage_caller, out.samples_out, kg, src_base, out.snap, chg,
                        chgbits, gv.out_rp, cnt_dev, out.sidx_fill, ctl, mode_log, out.cap, gv.arcs, gv.alpha, n);
     stats->launches += 2;
 
@@ -803,7 +833,7 @@ size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh) {
            1024;
 }
 
-int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
+int bfs_batched(hipStream_t st, const BfsView& gv, int32_t* samples_dev, int32_t kg, int32_t src_base,
                 int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, size_t scratch_size,
                 LevelCounters* cnt_dev, TravStats* stats, EventPool* evp) {
     if (scratch_size < bfs_batched_scratch(gv.n, kg, gv.nh)) throw HipError{hipErrorOutOfMemory, "bfs_batched scratch"};

@@ -246,6 +246,21 @@ struct Carver {
 };
 
 // Everything one job needs on one stream.
+// Copies a finished estimate's control block and flags into pinned host memory
+// through its device-visible address (system-scope stores), so that a replayed
+// estimate needs no copy commands after its last kernel.
+__global__ void k_status_out(const uint32_t* __restrict__ ctl, const uint32_t* __restrict__ flags,
+                             uint32_t* ctl_host, uint32_t* flags_host) {
+    constexpr int nc = (int)(sizeof(BfsCtl) / 4), nf = (int)(sizeof(DevFlags) / 4);
+    static_assert(sizeof(BfsCtl) % 4 == 0 && sizeof(DevFlags) % 4 == 0 && nc + nf <= 64, "one wave copies both");
+    const int t = threadIdx.x;
+    if (t < nc) __hip_atomic_store(ctl_host + t, ctl[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    else if (t < nc + nf)
+        __hip_atomic_store(flags_host + (t - nc), flags[t - nc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+constexpr int32_t kStagedSamples = 256;  // samples of an estimate that can be replayed from a captured graph
+
 struct Lane {
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -257,8 +272,11 @@ struct Lane {
     struct Readback {
         BfsCtl ctl;
         DevFlags flags;
+        int32_t ids[kStagedSamples];     // the samples, internal ids (read by the traversal's first launch)
+        int32_t caller[kStagedSamples];  // the same, as the caller numbers them
     };
-    Readback* rb_host = nullptr;  // pinned: a replay's control block and flags
+    Readback* rb_host = nullptr;  // pinned: a replay's control block and flags, and the staged samples
+    Readback* rb_dev = nullptr;   // its device-visible address
     hipEvent_t ev[4] = {};
     EventPool events;  // per-launch timing inside the traversals
     uint64_t gen = 0;  // arena generation
@@ -298,6 +316,7 @@ struct Lane {
         }
         CCG_HIP(hipHostMalloc((void**)&cnt_host, sizeof(LevelCounters) * kCounterSlots, hipHostMallocDefault));
         CCG_HIP(hipHostMalloc((void**)&rb_host, sizeof(Readback), hipHostMallocDefault));
+        CCG_HIP(hipHostGetDevicePointer((void**)&rb_dev, rb_host, 0));
         for (auto& e : ev) CCG_HIP(hipEventCreate(&e));
     }
     void destroy() {
@@ -308,6 +327,7 @@ struct Lane {
         if (cnt_host) (void)hipHostFree(cnt_host);
         if (rb_host) (void)hipHostFree(rb_host);
         rb_host = nullptr;
+        rb_dev = nullptr;
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         cnt_host = nullptr;
         stream = nullptr;
@@ -876,11 +896,19 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                          Carver::sz(sizeof(int32_t) * ngroups);
     const int32_t kg0 = std::min(k, 256);
     const int Wg = (kg0 + 63) / 64;
+    // free device memory, queried (once) only where a size depends on it: the
+    // weighted piles, and the level-mask budget of a search deeper than cap
+    size_t free_b = 0;
+    auto free_mem = [&]() {
+        if (free_b == 0) {
+            size_t total_b = 0;
+            CCG_HIP(hipMemGetInfo(&free_b, &total_b));
+        }
+        return free_b;
+    };
     // level masks take cap * n * W words; deep graphs whose masks would not fit
     // this budget are traversed one sample at a time instead
-    size_t free_b = 0, total_b = 0;
-    CCG_HIP(hipMemGetInfo(&free_b, &total_b));
-    const size_t mask_budget = std::min<size_t>(free_b / 3, (size_t)32 << 30);
+    auto mask_budget = [&]() { return std::min<size_t>(free_mem() / 3, (size_t)32 << 30); };
     int32_t mode = r.mode;
 
     int32_t cap = 32;              // level-mask capacity of the batched BFS
@@ -894,7 +922,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         int32_t kw = 1;
         if (g.weighted && mode != CC_PLAIN) {
             const size_t per = sssp_weighted_scratch(n, 2) - sssp_weighted_scratch(n, 1);
-            kw = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)k, (free_b / 4) / std::max<size_t>(per, 1)));
+            kw = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)k, (free_mem() / 4) / std::max<size_t>(per, 1)));
         }
         size_t trav_scratch;
         if (g.weighted)
@@ -923,7 +951,22 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         void* Dr = (!bits_path && g.directed) ? cd.take<char>(dbytes) : nullptr;
         void* Dt = need_Dt ? cd.take<char>(dbytes) : nullptr;
 
-        CCG_HIP(hipMemcpyAsync(samples_dev, samples_int.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+        // a single-group traversal takes its samples from the lane's pinned staging
+        // buffer in its first launch (replays included), others from a copy
+        const bool stage_samples = bits_path && k <= kStagedSamples;
+        if (stage_samples) {
+            CCG_HIP(hipStreamSynchronize(st));  // the lane's earlier launches are done with the buffer
+            std::memcpy(L.rb_host->ids, samples_int.data(), sizeof(int32_t) * k);
+            std::memcpy(L.rb_host->caller, r.samples.data(), sizeof(int32_t) * k);
+        } else {
+            CCG_HIP(hipMemcpyAsync(samples_dev, samples_int.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+        }
+        auto stage_into = [&](BfsLevels& lv) {
+            if (!stage_samples) return;
+            lv.stage_ids = L.rb_dev->ids;
+            lv.stage_caller = L.rb_dev->caller;
+            lv.samples_out = out->samples;
+        };
 
         // the adjacency a batched traversal uses in direction dir (0: forward
         // distances, pull over in-arcs / push over out-arcs; 1: reverse)
@@ -957,24 +1000,21 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                                          (uint64_t)(uintptr_t)out->D, (uint64_t)(uintptr_t)out->S_err,
                                          (uint64_t)(uintptr_t)out->S_ad, (uint64_t)(uintptr_t)out->S_ad_err,
                                          (uint64_t)(uintptr_t)out->S_sweep, (uint64_t)(uintptr_t)out->S_sweep_err,
-                                         (uint64_t)gr->tune.alpha,
+                                         (uint64_t)(uintptr_t)out->samples, (uint64_t)gr->tune.alpha,
                                          (uint64_t)gr->tune.level_blocks, (uint64_t)gr->tune.scatter_blocks};
         };
         if (want_graph) {
             if (Lane::Captured* cap_e = L.find_captured(graph_key())) {
-                if (out->samples)
-                    CCG_HIP(hipMemcpyAsync(out->samples, r.samples.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice,
-                                           st));
+                // the graph takes the staged samples and writes the control block and
+                // flags back itself; a readback that did not land fails the check below
+                L.rb_host->ctl.done = -1;
                 CCG_HIP(hipEventRecord(L.ev[0], st));
                 CCG_HIP(hipGraphLaunch(cap_e->exec, st));
                 CCG_HIP(hipEventRecord(L.ev[2], st));
-                CCG_HIP(hipMemcpyAsync(&L.rb_host->ctl, bfs_batched_ctl(ts, n, kg0), sizeof(BfsCtl),
-                                       hipMemcpyDeviceToHost, st));
-                CCG_HIP(hipMemcpyAsync(&L.rb_host->flags, flags, sizeof(DevFlags), hipMemcpyDeviceToHost, st));
                 CCG_HIP(hipStreamSynchronize(st));
                 const BfsCtl hc = L.rb_host->ctl;
                 const DevFlags hf = L.rb_host->flags;
-                if (hc.done && hc.status == 0 && hc.lmax == cap_e->lmax && hc.levels <= cap_e->levels &&
+                if (hc.done == 1 && hc.status == 0 && hc.lmax == cap_e->lmax && hc.levels <= cap_e->levels &&
                     !hf.disconnected && !hf.overflow && !hf.bad_sample && !hf.timeout) {
                     if (timing) {
                         *timing = cc_timing{};
@@ -1056,6 +1096,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                         lv.zero_flags = flags;
                         lv.sidx_fill = sidx;
                         lv.zero_hist = true;
+                        stage_into(lv);
                     }
                     rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, &ds, &L.events);
                     if (rc == 0) gr->bfs_hint.store(ds.bfs_levels, std::memory_order_relaxed);
@@ -1073,7 +1114,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         }
         if (rc == 1) {  // more levels than the mask buffer holds
             cap = (int32_t)std::min<int64_t>((int64_t)cap * 4, n + 2);
-            if ((size_t)cap * n * Wg * 8 > mask_budget) mode = CC_PLAIN;
+            if ((size_t)cap * n * Wg * 8 > mask_budget()) mode = CC_PLAIN;
             continue;
         }
         if (rc == 3) {  // distance type too narrow
@@ -1153,7 +1194,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             run_epilogue(st, ea, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
             L.last_maxd = ea.maxd;
         }
-        if (out->samples)
+        if (out->samples && !stage_samples)
             CCG_HIP(hipMemcpyAsync(out->samples, r.samples.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
         CCG_HIP(hipEventRecord(L.ev[2], st));
         CCG_HIP(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
@@ -1184,10 +1225,15 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 lv.zero_flags = flags;
                 lv.sidx_fill = sidx;
                 lv.zero_hist = true;
+                stage_into(lv);
                 TravStats ignored;
                 (void)bfs_batched(st, make_view(0), samples_dev, k, 0, k, lv, sidx, ts, trav_scratch, cnt, &ignored,
                                   nullptr);
                 run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
+                hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st,
+                                   (const uint32_t*)bfs_batched_ctl(ts, n, kg0), (const uint32_t*)flags,
+                                   (uint32_t*)&L.rb_dev->ctl, (uint32_t*)&L.rb_dev->flags);
+                CCG_HIP(hipGetLastError());
             } catch (const HipError&) {
                 captured_ok = false;
             }

@@ -283,6 +283,11 @@ struct BfsLevels {
     DevFlags* zero_flags = nullptr;  // zeroed
     int32_t* sidx_fill = nullptr;    // [n]: -1, then each sample's index
     bool zero_hist = false;          // hist ([kHistSlotsBatched][k][hlen]) zeroed
+    // optional, same condition: the samples are read by the first launch from pinned host memory
+    // (device-visible addresses) and stored to samples_dev there, so nothing is copied before it
+    const int32_t* stage_ids = nullptr;     // [k] internal ids, read with system-scope loads
+    const int32_t* stage_caller = nullptr;  // [k] the same samples as the caller numbers them
+    int32_t* samples_out = nullptr;         // device [k]: receives stage_caller (optional)
     int32_t enqueue_only = 0;     // > 0: enqueue exactly this many levels and return at once (stream capture)
 };
 
@@ -354,12 +359,12 @@ constexpr int kHistSlotsBatched = 32;  // spread copies of the per-level histogr
 
 
 // Batched bit-parallel BFS over one group of kg <= 256 samples (internal
-// ids samples_dev[src_base .. src_base+kg)), recording per-level seen masks in
-// `out`; with out.hist it also counts hist[slot][src_base+i][L] over
+// ids samples_dev[src_base .. src_base+kg), written by the traversal itself
+// when out.stage_ids is set), recording per-level seen masks in `out`; with out.hist it also counts hist[slot][src_base+i][L] over
 // non-sampled nodes (sidx[v] < 0).
 // Returns 0 = done, 1 = snapshot capacity too small (retry with more levels),
 // 2 = some node is unreachable from some sample.
-int bfs_batched(hipStream_t st, const BfsView& gv, const int32_t* samples_dev, int32_t kg, int32_t src_base,
+int bfs_batched(hipStream_t st, const BfsView& gv, int32_t* samples_dev, int32_t kg, int32_t src_base,
                 int32_t k, const BfsLevels& out, const int32_t* sidx, void* scratch, size_t scratch_size,
                 LevelCounters* cnt_dev, TravStats* stats, EventPool* evp);
 size_t bfs_batched_scratch(int64_t n, int32_t kg, int64_t nh);

@@ -105,3 +105,37 @@ def test_replays_with_error_outputs():
         _say(f"  replays: {replays}")
         assert replays >= 3
         ctx.release(gh)
+
+
+def test_replays_write_samples():
+    """A captured estimate takes its samples from the lane's pinned staging
+    buffer in its first launch, which also writes the `samples` output: every
+    replay's samples and estimates match an eager batched estimate, and the
+    samples match the plain path's (copied from the host) for the same seed."""
+    import torch
+    g = graphgen.rmat(12, 16, seed=9)
+    k = 128
+    fields = {**FIELDS}
+    with cc.Context(0) as ctx:
+        gh = ctx.upload(g)
+        s = torch.cuda.Stream()
+        out, ref = _outputs(torch, g.n), _outputs(torch, g.n)
+        for d in (out, ref):
+            d["samples"] = torch.empty(k, dtype=torch.int32, device="cuda")
+        plain = {"samples": torch.empty(k, dtype=torch.int32, device="cuda")}
+        replays = 0
+        for it, seed in enumerate([5, 5, 6, 6, 6, 5, 7, 7]):
+            _say(f"  call {it} seed {seed}")
+            for t in out.values():
+                t.fill_(-1)
+            cc.cc_estimate_device(ctx.handle, gh, k, out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=seed, stream=s)
+            replays += cc.cc_last_timing(ctx.handle)["launches"] == 1
+            cc.cc_estimate_device(ctx.handle, gh, k, ref, mode=cc.CC_BATCHED, seed=seed, stream=s)
+            cc.cc_estimate_device(ctx.handle, gh, k, plain, mode=cc.CC_PLAIN, seed=seed, stream=s)
+            s.synchronize()
+            assert torch.equal(out["samples"], plain["samples"]), (it, seed)
+            for f in (*fields, "samples"):
+                assert torch.equal(out[f], ref[f]), (it, seed, f)
+        _say(f"  replays: {replays}")
+        assert replays >= 4
+        ctx.release(gh)
