@@ -60,7 +60,7 @@ struct ReachCtl {
     int32_t phase;
     int32_t batch;
     int64_t t0;      // rank of the batch's first source
-    int64_t tnext;   // first rank not yet looked at for sources
+    int64_t tnext;   // first entry of the list of sources with propagation arcs not yet looked at
     int32_t nsrc;    // sources in the batch
     int32_t level;   // BFS level of the bits the next merge records
     int32_t gl;      // global level stamp (first touch of a node per level)
@@ -73,6 +73,7 @@ struct ReachCtl {
     int32_t overflow;  // a recorded level above 65535
     int32_t nw;        // words the current batch uses
     int64_t levels;  // levels run, all batches
+    int64_t nact;    // sources with propagation arcs (the list's length)
 };
 
 struct ReachView {
@@ -83,6 +84,9 @@ struct ReachView {
     const int32_t* col;
     const int32_t* rank;         // internal id -> rank
     const int32_t* src_by_rank;  // rank -> internal id
+    int32_t* act_src;            // [nsrc] the sources that have propagation arcs, in rank order
+    int32_t* act_rank;           // [nsrc] their ranks
+    int32_t* act_blk;            // per-chunk counts of such sources, then the chunks' offsets
     int32_t* src_rank;           // [64W] rank of each bit's source in the current batch
     int32_t* sbit;               // [n] the node's bit when it is a source of the current batch, else -1
     int32_t* cnt;       // members counted so far (exact up to k)
@@ -341,7 +345,7 @@ template <int W>
 __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
     __shared__ int32_t wcount[kBlock / 64];
     __shared__ int32_t got;
-    __shared__ int64_t scan, first_rank, last_rank;
+    __shared__ int64_t scan, first_rank, last_idx;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int32_t batch = ctl->batch;  // 1 for the first batch
     const int32_t cap = (int32_t)std::min<int64_t>(64 * W, (int64_t)kFirstBatch << std::min(batch - 1, 16));
@@ -352,20 +356,25 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
     }
     __syncthreads();
     constexpr int kPer = 16;  // ranks per thread and window
-    while (got < cap && scan < V.nsrc) {
-        // kPer x 256 ranks per window, loads in flight together; thread t takes
-        // ranks scan + t*kPer .. +kPer-1, so the window stays in rank order
+    // the scan runs over the sources that have propagation arcs (listed once
+    // per estimate, in rank order): a source without any passes its bit to no one
+    const int64_t nact = ctl->nact;
+    while (got < cap && scan < nact) {
+        // kPer x 256 entries per window, loads in flight together; thread t takes
+        // entries scan + t*kPer .. +kPer-1, so the window stays in rank order
         int64_t s[kPer];
+        int32_t rk[kPer];
         bool take[kPer];
         int32_t mine = 0;
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
-            const int64_t r = scan + (int64_t)threadIdx.x * kPer + q;
-            s[q] = r < V.nsrc ? V.src_by_rank[r] : -1;
+            const int64_t i = scan + (int64_t)threadIdx.x * kPer + q;
+            s[q] = i < nact ? V.act_src[i] : -1;
+            rk[q] = i < nact ? V.act_rank[i] : 0;
         }
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
-            take[q] = s[q] >= 0 && V.cnt[s[q]] <= V.k && V.rp[s[q] + 1] > V.rp[s[q]];
+            take[q] = s[q] >= 0 && V.cnt[s[q]] <= V.k;
             mine += take[q] ? 1 : 0;
         }
         // exclusive prefix of `mine` over the block
@@ -385,12 +394,11 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
         for (int q = 0; q < kPer; q++) {
             if (!take[q]) continue;
             if (b < cap) {
-                const int64_t r = scan + (int64_t)threadIdx.x * kPer + q;
                 const int64_t x = s[q];
                 const uint64_t bit = 1ull << (b & 63);
-                if (b == 0) first_rank = r;
-                if (b == cap - 1) last_rank = r;
-                V.src_rank[b] = (int32_t)r;
+                if (b == 0) first_rank = rk[q];
+                if (b == cap - 1) last_idx = scan + (int64_t)threadIdx.x * kPer + q;
+                V.src_rank[b] = rk[q];
                 V.sbit[x] = b;
                 V.seen[x * W + (b >> 6)] = bit;
                 V.stamp[x] = batch;
@@ -402,7 +410,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
         __syncthreads();
         if (threadIdx.x == 0) {
             if (total >= cap) {  // the batch is full: continue after its last source
-                scan = last_rank + 1;
+                scan = last_idx + 1;
                 got = cap;
             } else {
                 scan += (int64_t)kBlock * kPer;
@@ -442,7 +450,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
     for (int q = 0; q < kSrc; q++)
         for (uint32_t c = 0; c < cs[q]; c++) F[pos++] = ((uint64_t)xs[q] << 32) | (c * kChunk);
     if (threadIdx.x == 0) {
-        ctl->tnext = scan < V.nsrc ? scan : V.nsrc;
+        ctl->tnext = scan < nact ? scan : nact;
         ctl->nsrc = S;
         ctl->nw = (S + 63) / 64;
         ctl->nt = S;
@@ -626,6 +634,98 @@ __global__ void k_rch_out_beta(ReachView V, const int32_t* __restrict__ orig, co
 
 __global__ void k_rch_set_phase(ReachCtl* ctl, int32_t phase) { ctl->phase = phase; }
 
+// The sources that have propagation arcs, listed in rank order once per
+// estimate, so that picking a batch reads one count per candidate: per-chunk
+// counts, one block's exclusive scan of them (which also stores the list's
+// length), then each chunk writes its entries in order.
+constexpr int kActPer = 16;                                  // ranks per thread
+constexpr int64_t kActChunk = (int64_t)kBlock * kActPer;     // ranks per block
+
+__device__ __forceinline__ bool has_arcs(const ReachView& V, int64_t r, int32_t& s) {
+    if (r >= V.nsrc) return false;
+    s = V.src_by_rank[r];
+    return V.rp[s + 1] > V.rp[s];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rch_act_count(ReachView V) {
+    __shared__ int32_t total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kActChunk + (int64_t)threadIdx.x * kActPer;
+    int32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < kActPer; q++) {
+        int32_t s;
+        c += has_arcs(V, base + q, s) ? 1 : 0;
+    }
+    atomicAdd(&total, c);
+    __syncthreads();
+    if (threadIdx.x == 0) V.act_blk[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rch_act_scan(ReachCtl* ctl, ReachView V, int32_t nb) {
+    __shared__ int32_t wcount[kBlock / 64];
+    __shared__ int64_t carry;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t t0 = 0; t0 < nb; t0 += kBlock) {
+        const int32_t i = t0 + (int32_t)threadIdx.x;
+        const int32_t v = i < nb ? V.act_blk[i] : 0;
+        int32_t incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wcount[wave] = incl;
+        __syncthreads();
+        int64_t before = carry;
+        int64_t tile = 0;
+        for (int w = 0; w < kBlock / 64; w++) {
+            if (w < wave) before += wcount[w];
+            tile += wcount[w];
+        }
+        if (i < nb) V.act_blk[i] = (int32_t)(before + incl - v);
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tile;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl->nact = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rch_act_put(ReachView V) {
+    __shared__ int32_t wcount[kBlock / 64];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kActChunk + (int64_t)threadIdx.x * kActPer;
+    int32_t s[kActPer];
+    bool f[kActPer];
+    int32_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < kActPer; q++) {
+        s[q] = 0;
+        f[q] = has_arcs(V, base + q, s[q]);
+        mine += f[q] ? 1 : 0;
+    }
+    int32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wcount[wave] = incl;
+    __syncthreads();
+    int64_t pos = (int64_t)V.act_blk[blockIdx.x] + incl - mine;
+    for (int w = 0; w < wave; w++) pos += wcount[w];
+#pragma unroll
+    for (int q = 0; q < kActPer; q++) {
+        if (!f[q]) continue;
+        V.act_src[pos] = s[q];
+        V.act_rank[pos] = (int32_t)(base + q);
+        pos++;
+    }
+}
+
 __global__ void k_rch_rank(const int32_t* __restrict__ order_internal, int64_t n, int32_t* __restrict__ rank) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
         rank[order_internal[r]] = (int32_t)r;
@@ -638,7 +738,9 @@ size_t reach_scratch_bytes(int64_t n, int64_t arcs, int32_t k_weighted) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t i32 = al(sizeof(int32_t) * n), i64 = al(sizeof(int64_t) * n);
     const size_t kw = (size_t)std::max(1, k_weighted - 1);
-    return al(sizeof(ReachCtl)) + 2 * i32 /* rank, src_by_rank */ + i32 + 2 * i64 /* cnt, dsum, tk */ +
+    const size_t nb = (size_t)((n + kActChunk - 1) / kActChunk) + 1;
+    return al(sizeof(ReachCtl)) + 2 * i32 /* rank, src_by_rank */ + 2 * i32 /* act_src, act_rank */ +
+           al(sizeof(int32_t) * nb) /* act_blk */ + i32 + 2 * i64 /* cnt, dsum, tk */ +
            3 * al(sizeof(uint64_t) * n * W) /* seen, nx, fr */ + al(sizeof(uint16_t) * n * 64 * W) /* lev */ +
            3 * i32 /* stamp, lmark, sbit */ + al(sizeof(int32_t) * 64 * W) /* src_rank */ +
            (k_weighted > 0 ? al(sizeof(int32_t) * n * kw) + al(sizeof(uint16_t) * n * kw) : 0) +
@@ -669,6 +771,10 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
     int32_t* sbr = (int32_t*)take(sizeof(int32_t) * n);
     V.rank = rank;
     V.src_by_rank = sbr;
+    const int32_t nb = (int32_t)((V.nsrc + kActChunk - 1) / kActChunk);
+    V.act_src = (int32_t*)take(sizeof(int32_t) * n);
+    V.act_rank = (int32_t*)take(sizeof(int32_t) * n);
+    V.act_blk = (int32_t*)take(sizeof(int32_t) * ((size_t)((n + kActChunk - 1) / kActChunk) + 1));
     V.cnt = (int32_t*)take(sizeof(int32_t) * n);
     V.dsum = (int64_t*)take(sizeof(int64_t) * n);
     V.tk = (int64_t*)take(sizeof(int64_t) * n);
@@ -706,6 +812,11 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
     fill_u32(st, V.lmark, 0xFFFFFFFFu, (size_t)n);
     fill_u32(st, V.sbit, 0xFFFFFFFFu, (size_t)n);
     fill_u32(st, ctl, 0u, sizeof(ReachCtl) / 4);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_rch_act_count, dim3((unsigned)nb), dim3(kBlock), 0, st, V);
+        hipLaunchKernelGGL(k_rch_act_scan, dim3(1), dim3(kBlock), 0, st, ctl, V, nb);
+        hipLaunchKernelGGL(k_rch_act_put, dim3((unsigned)nb), dim3(kBlock), 0, st, V);
+    }
     // start in the account phase with nothing touched: its last block picks the first batch
     hipLaunchKernelGGL(k_rch_set_phase, dim3(1), dim3(1), 0, st, ctl, (int32_t)kAccount);
     CCG_HIP(hipGetLastError());
