@@ -360,18 +360,33 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
     // per estimate, in rank order): a source without any passes its bit to no one
     const int64_t nact = ctl->nact;
     while (got < cap && scan < nact) {
-        // kPer x 256 entries per window, loads in flight together; thread t takes
-        // entries scan + t*kPer .. +kPer-1, so the window stays in rank order
+        // kPer x 256 entries per window from `scan` rounded down to a multiple of
+        // kPer (entries before `scan` are not taken); thread t takes entries
+        // w0 + t*kPer .. +kPer-1, 16-byte loads, so the window stays in rank order
+        const int64_t w0 = scan & ~(int64_t)(kPer - 1);
+        const int64_t i0 = w0 + (int64_t)threadIdx.x * kPer;
         int64_t s[kPer];
         int32_t rk[kPer];
         bool take[kPer];
         int32_t mine = 0;
+        if (i0 + kPer <= nact) {  // the lists are 256-byte aligned and i0 is a multiple of kPer
 #pragma unroll
-        for (int q = 0; q < kPer; q++) {
-            const int64_t i = scan + (int64_t)threadIdx.x * kPer + q;
-            s[q] = i < nact ? V.act_src[i] : -1;
-            rk[q] = i < nact ? V.act_rank[i] : 0;
+            for (int c = 0; c < kPer / 4; c++) {
+                const int4 a = *(const int4*)(V.act_src + i0 + 4 * c);
+                const int4 b = *(const int4*)(V.act_rank + i0 + 4 * c);
+                s[4 * c] = a.x, s[4 * c + 1] = a.y, s[4 * c + 2] = a.z, s[4 * c + 3] = a.w;
+                rk[4 * c] = b.x, rk[4 * c + 1] = b.y, rk[4 * c + 2] = b.z, rk[4 * c + 3] = b.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                s[q] = i0 + q < nact ? V.act_src[i0 + q] : -1;
+                rk[q] = i0 + q < nact ? V.act_rank[i0 + q] : 0;
+            }
         }
+#pragma unroll
+        for (int q = 0; q < kPer; q++)
+            if (i0 + q < scan) s[q] = -1;
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             take[q] = s[q] >= 0 && V.cnt[s[q]] <= V.k;
@@ -397,7 +412,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
                 const int64_t x = s[q];
                 const uint64_t bit = 1ull << (b & 63);
                 if (b == 0) first_rank = rk[q];
-                if (b == cap - 1) last_idx = scan + (int64_t)threadIdx.x * kPer + q;
+                if (b == cap - 1) last_idx = i0 + q;
                 V.src_rank[b] = rk[q];
                 V.sbit[x] = b;
                 V.seen[x * W + (b >> 6)] = bit;
@@ -413,7 +428,7 @@ __device__ void start_batch(ReachCtl* ctl, const ReachView& V) {
                 scan = last_idx + 1;
                 got = cap;
             } else {
-                scan += (int64_t)kBlock * kPer;
+                scan = w0 + (int64_t)kBlock * kPer;
                 got = total;
             }
         }
