@@ -54,6 +54,9 @@ CASES = [
                                                 directed=True), (1, 5, 1000)),
     ("star-dir", lambda: graphgen.csr_from_arcs(1025, [0] * 1024, list(range(1, 1025)), symmetrize=False,
                                                 directed=True), (4, 300)),
+    # no source has a propagation arc (the list of sources to pick batches from is empty), or one has
+    ("no-arcs", lambda: graphgen.csr_from_arcs(50, [], [], symmetrize=False, directed=True), (1, 3)),
+    ("one-arc", lambda: graphgen.csr_from_arcs(40, [7], [3], symmetrize=False, directed=True), (1, 2)),
 ]
 
 
