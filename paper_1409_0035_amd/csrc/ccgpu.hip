@@ -81,6 +81,29 @@ struct SplitMix64 {
     }
 };
 
+// Fisher-Yates over a[0..n): the same draws and swaps, in the same order, as
+// swapping a[i] with a[i + below(n - i)] for i = 0, 1, ..., n - 1. The draws do
+// not depend on the array, so each swap target is drawn kAhead steps early and
+// its line prefetched; the generator ends in the same state.
+void shuffle(SplitMix64& rng, int32_t* a, int64_t n) {
+    constexpr int64_t kAhead = 16;
+    int64_t ring[kAhead];
+    for (int64_t i = 0; i < std::min(kAhead, n); i++) {
+        ring[i] = i + (int64_t)rng.below((uint64_t)(n - i));
+        __builtin_prefetch(a + ring[i], 1);
+    }
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t j = ring[i % kAhead];
+        const int64_t ia = i + kAhead;
+        if (ia < n) {
+            const int64_t ja = ia + (int64_t)rng.below((uint64_t)(n - ia));
+            ring[ia % kAhead] = ja;
+            __builtin_prefetch(a + ja, 1);
+        }
+        std::swap(a[i], a[j]);
+    }
+}
+
 }  // namespace
 
 extern "C" cc_status cc_draw_samples(int64_t n, int32_t k, uint64_t seed, int32_t* out) {
@@ -146,17 +169,20 @@ extern "C" cc_status cc_draw_weighted(int64_t n, const uint32_t* beta, int32_t k
     SplitMix64 rng{seed};
     std::vector<int32_t> perm((size_t)n);
     for (int64_t i = 0; i < n; i++) perm[(size_t)i] = (int32_t)i;
-    for (int64_t i = 0; i < n; i++) {
-        const int64_t j = i + (int64_t)rng.below((uint64_t)(n - i));
-        std::swap(perm[(size_t)i], perm[(size_t)j]);
-    }
+    shuffle(rng, perm.data(), n);
     const uint64_t Q = (uint64_t)R;
     auto yes = [&](uint64_t num, uint64_t den) {
         return (unsigned __int128)rng.next() * den < ((unsigned __int128)num << 64);
     };
     int64_t cur = -1;
     uint64_t ca = 0;
+    constexpr int64_t kAhead = 16;  // nodes ahead whose weight and flag are prefetched
     for (int64_t r = 0; r < n; r++) {
+        if (r + kAhead < n) {
+            const int32_t u = perm[(size_t)(r + kAhead)];
+            __builtin_prefetch(beta + u);
+            __builtin_prefetch(is_heavy.data() + u);
+        }
         const int32_t v = perm[(size_t)r];
         if (beta[v] == 0 || is_heavy[(size_t)v]) continue;
         const uint64_t b = (uint64_t)beta[v] * (uint64_t)m;
@@ -1884,15 +1910,13 @@ extern "C" cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const
     } else {
         // the same draws as cc_draw_samples(n, n, seed), on a dense array
         SplitMix64 rng{p->seed};
-        std::vector<int32_t> a((size_t)n);
-        for (int64_t i = 0; i < n; i++) a[(size_t)i] = (int32_t)i;
-        for (int64_t i = 0; i < n; i++) {
-            const int64_t j = i + (int64_t)rng.below((uint64_t)(n - i));
-            std::swap(a[(size_t)i], a[(size_t)j]);
-            order[(size_t)i] = a[(size_t)i];
-        }
+        for (int64_t i = 0; i < n; i++) order[(size_t)i] = (int32_t)i;
+        shuffle(rng, order.data(), n);
     }
-    for (int64_t r = 0; r < n; r++) order[(size_t)r] = g->inv[(size_t)order[(size_t)r]];
+    for (int64_t r = 0; r < n; r++) {
+        if (r + 16 < n) __builtin_prefetch(g->inv.data() + order[(size_t)(r + 16)]);
+        order[(size_t)r] = g->inv[(size_t)order[(size_t)r]];
+    }
     std::lock_guard<std::mutex> lk(ctx->mu);
     return guarded(ctx, [&]() -> cc_status {
         Lane& L = ctx->lane;
