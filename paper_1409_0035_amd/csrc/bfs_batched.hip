@@ -695,11 +695,21 @@ __global__ __launch_bounds__(kBlock) void k_group_level(
             if (c) atomicAdd(&hist[((int64_t)slot * k + src_base + t) * hlen + level], c);
         }
     }
-    // the last block to finish decides the next level (its counters are
-    // complete: each block takes its ticket only after its counter atomics
-    // have returned)
+    // the last block to finish decides the next level. Tickets in two steps,
+    // so that no address takes an atomic from every block: a block counts in
+    // its counter slot, the slot's last block in the control block. The
+    // counters are complete then: a block takes its slot ticket only after its
+    // counter atomics have returned, and a slot's last block takes the
+    // control block's ticket only after the slot's count is complete.
     __shared__ uint32_t last;
-    if (threadIdx.x == 0) last = atomicAdd(&ctl->ticket, 1u + token) == gridDim.x - 1;
+    if (threadIdx.x == 0) {
+        const uint32_t slot = blockIdx.x % kCounterSlots;
+        const uint32_t in_slot = (gridDim.x - slot + kCounterSlots - 1) / kCounterSlots;
+        const uint32_t used = gridDim.x < (uint32_t)kCounterSlots ? gridDim.x : (uint32_t)kCounterSlots;
+        last = 0;
+        if (atomicAdd(&cnt[slot].ticket, 1u + token) == in_slot - 1)
+            last = atomicAdd(&ctl->ticket, 1u) == used - 1;
+    }
     __syncthreads();
     if (last && threadIdx.x < 64) decide_wave(cnt, ctl, mode_log, level, cap, arcs_total, alpha, n);
 }

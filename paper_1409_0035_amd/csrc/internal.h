@@ -48,6 +48,7 @@ struct alignas(128) LevelCounters {
     int64_t arcs;           // adjacency entries scanned (pull) or pushed along (push)
     int64_t frontier_arcs;  // sum of the out-degrees of the next frontier
     int64_t matched;        // scanned arcs whose tail was on the previous level
+    uint32_t ticket;        // batched BFS: blocks of this slot that have finished the merge launch
 };
 constexpr int kCounterSlots = 64;
 
