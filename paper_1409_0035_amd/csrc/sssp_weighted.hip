@@ -374,8 +374,17 @@ __device__ __forceinline__ void wround_body(const WArgs& A, int32_t r, Stage& S,
         relax_batch([&](int64_t t) { return Wloc[t]; }, 0, cnt);
     }
     stage_flush(S, nout, ncnt_out, fpile, fcnt_cur, cap, &dev->overflow);
+    // the smallest far distance: one atomic per block, not per wave, on an
+    // address that every block of the round updates
     lmin = wave_min_u32(lmin);
-    if (lane_id() == 0 && lmin != kInf) atomicMin(&dev->minfar[epa % 3], lmin);
+    __syncthreads();  // smax is free again
+    if (lane_id() == 0) smax[threadIdx.x >> 6] = lmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = kInf;
+        for (int w = 0; w < kBlock / 64; w++) m = smax[w] < m ? smax[w] : m;
+        if (m != kInf) atomicMin(&dev->minfar[epa % 3], m);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_wround(WArgs A, int32_t r) {
