@@ -137,10 +137,12 @@ typedef struct {
     /* Sec. 4 (n entries each; 0 / the exact sum on sampled nodes):
      *   S_err     estimated squared error of S_hyb: |L|/|L cap C| times the sample
      *             variance of the distances to L cap C (mean squared deviation from
-     *             their mean), plus |H| times the mean over HC of
-     *             (d(v,u) - d(c(v),u))^2 (0 when HC is empty); computed as
+     *             their mean), plus |H| times the mean over F of
+     *             (d(v,u) - d(c(v),u))^2, where F = HC, or, when HC is empty, the
+     *             samples at the largest distance from c(v) (Sec. 4.1's "suffix" of
+     *             the farthest samples); computed as
      *             ((|LC| * sum_LC d^2 - (sum_LC d)^2) / |LC|^3) * |L|
-     *             + (sum_HC (d - d_p)^2 / |HC|) * |H| in that order of double operations
+     *             + (sum_F (d - d_p)^2 / |F|) * |H| in that order of double operations
      *   S_ad      adaptive estimate: for each eps in {0.001, 0.025, 0.05, 0.1, 0.2,
      *             0.5, 0.99} (the list of Sec. 8) the hybrid estimate and its
      *             estimated error; the estimate with the smallest error (the first
@@ -153,8 +155,9 @@ typedef struct {
      *                (n-1-k)) and, for every distinct distance T from c to a sample,
      *                increasing, the estimate with L = {u != v : d(c,u) <= T}, HC the
      *                samples beyond T, H the other nodes beyond T (v itself is in
-     *                none of them), Eq. (6)'s form, and its Sec. 4.1 error; the
-     *                candidate with the smallest error (the first on ties)
+     *                none of them), Eq. (6)'s form, and its Sec. 4.1 error (with F
+     *                as for S_err: the farthest samples when no sample lies beyond
+     *                T); the candidate with the smallest error (the first on ties)
      *   S_sweep_err  its estimated squared error */
     double* S_err;
     double* S_ad;
@@ -285,9 +288,11 @@ typedef struct {
     double* tau;           /* 1: R / m (0 when every positive node is sampled) */
     int32_t* sample_size;  /* 1 */
     double* S_beta_err;    /* n: the error estimate of Sec. 4.1 with beta masses (Sec. 5): S_beta_var
-                              plus beta(H) times the beta-weighted mean over HC of
-                              (d(v,u) - d(c(v),u))^2 (0 when HC has no weight), in that order of
-                              double operations: var + (sum / weight(HC)) * weight(H); 0 on samples */
+                              plus beta(H) times the beta-weighted mean over F of
+                              (d(v,u) - d(c(v),u))^2, F = HC, or the samples at the largest
+                              distance from c(v) when HC has no weight (0 if F weighs nothing), in
+                              that order of double operations: var + (sum / weight(F)) * weight(H);
+                              0 on samples */
 } cc_weighted_result;
 /* Host only: the sample above.  ids and light hold k entries; *count is the
  * sample size, *R and *m give tau = R/m.  CC_EINVAL without a node of positive

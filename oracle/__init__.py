@@ -86,6 +86,8 @@ def _load():
     lib.orc_node_adaptive.restype = ctypes.c_int
     lib.orc_node_adaptive.argtypes = [i64, i32, i64, P, P, P, i64, P, P, i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    lib.orc_estimate_tails.restype = ctypes.c_int
+    lib.orc_estimate_tails.argtypes = [i64, i32, P, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_exact_sums.restype = ctypes.c_int
     lib.orc_exact_sums.argtypes = [i64, P, P, P, P, P, P, i32, P]
     lib.orc_beta_all.restype = ctypes.c_int
@@ -202,6 +204,46 @@ def estimate_all(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=N
     out["D"] = D
     out["src_sum"] = D.sum(axis=0)               # S(c_i) = sum_v d(c_i, v)
     out["dmat"] = D[samples, :].T.copy()         # dmat[i, j] = D[c_j, i] = d(c_i, c_j)
+    out["samples"] = samples
+    out["eps"] = (en, ed)
+    return out
+
+
+def estimate_tails(g, samples, eps=None, D=None, threads: int = 1, reverse_graph=None,
+                   adaptive_eps=ADAPTIVE_EPS) -> dict:
+    """Every node at any size, with Algorithm 1's accounting (Sec. 3): the
+    sums over H(v) from each pivot sample's sorted distances and suffix sums,
+    the samples split by their distance from the pivot.  Gives the same values
+    as estimate_all (pinned against it), without its O(n^2) walk: pivot,
+    delta, sampsum, src_sum, dmat, S_piv, S_pub, S_samp, S_hyb, S_err, and
+    S_ad / S_ad_err over adaptive_eps."""
+    lib = _load()
+    samples = np.ascontiguousarray(samples, dtype=np.int32)
+    k = int(samples.shape[0])
+    en, ed = eps if eps is not None else default_eps(k)
+    if D is None:
+        D = sample_distances(g, samples, threads=threads, reverse_graph=reverse_graph)
+    D = np.ascontiguousarray(D, dtype=np.int64)
+    n = g.n
+    sidx = sample_index(n, samples)
+    ad = list(adaptive_eps or ())
+    nums = np.array([en] + [a for a, _ in ad], dtype=np.int64)
+    dens = np.array([ed] + [b for _, b in ad], dtype=np.int64)
+    out = dict(pivot=np.empty(n, np.int32), delta=np.empty(n, np.int64), sampsum=np.empty(n, np.int64),
+               src_sum=np.empty(k, np.int64), dmat=np.empty((k, k), np.int64), S_piv=np.empty(n, np.int64),
+               S_pub=np.empty(n, np.int64), S_samp=np.empty(n, np.float64), S_hyb=np.empty(n, np.float64),
+               S_err=np.empty(n, np.float64), S_ad=np.empty(n, np.float64), S_ad_err=np.empty(n, np.float64))
+    st = lib.orc_estimate_tails(n, k, _p(sidx), _p(D), _p(nums), _p(dens), len(nums), int(threads),
+                                *[_p(out[f]) for f in ("pivot", "delta", "sampsum", "src_sum", "dmat", "S_piv",
+                                                       "S_pub", "S_samp", "S_hyb", "S_err", "S_ad", "S_ad_err")])
+    if not ad:
+        del out["S_ad"], out["S_ad_err"]
+    if st == 3:
+        raise OracleError("out of memory")
+    if st not in (0, 4):
+        raise OracleError(f"orc_estimate_tails failed ({st})")
+    out["overflow"] = st == 4
+    out["D"] = D
     out["samples"] = samples
     out["eps"] = (en, ed)
     return out

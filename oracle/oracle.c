@@ -32,6 +32,10 @@
  *                               the pivot's distances to the samples, the
  *                               candidate with the smallest estimated error.
  *   orc_estimate_all            the above for every node, O(n^2): small graphs.
+ *   orc_estimate_tails          every node at any size with Algorithm 1's
+ *                               accounting (tail sums per pivot sample instead
+ *                               of a walk over V per node), O(nk + kn log n);
+ *                               the same values as orc_estimate_all.
  *   orc_exact_sums              S(v) for every node by n searches (Eq. (1)).
  *   orc_beta_all                Sec. 5 / Algorithm 3: the node-weighted hybrid
  *                               estimate of S_beta(v) = sum_u beta(u) d(v,u) and its
@@ -267,6 +271,27 @@ int32_t orc_pivot(int32_t k, const int64_t* row) {
     return p;
 }
 
+/* Sec. 4.1: when HC(v) is empty the mean squared pivoting error is taken
+ * over a "suffix" of the farthest samples instead; read here as the samples at
+ * the largest distance from the pivot (all of them when they tie).  Returns
+ * the sum of (d(v,u) - d(c(v),u))^2 over those samples and their number, by a
+ * walk over every node u that picks out the sampled ones. */
+static __int128 far_suffix_sqerr(int64_t n, const int32_t* sidx, const int64_t* row, const int64_t* colp,
+                                 int64_t stride, int64_t* count) {
+    int64_t far = -1;
+    for (int64_t u = 0; u < n; u++)
+        if (sidx[u] >= 0 && colp[u * stride] > far) far = colp[u * stride];
+    __int128 sq = 0;
+    *count = 0;
+    for (int64_t u = 0; u < n; u++) {
+        int32_t i = sidx[u];
+        if (i < 0 || colp[u * stride] != far) continue;
+        sq += (__int128)(row[i] - far) * (row[i] - far);
+        (*count)++;
+    }
+    return sq;
+}
+
 int orc_node_estimates(int64_t n, int32_t k, int64_t v, const int32_t* sidx, const int64_t* row,
                        const int64_t* colp, int64_t stride, int64_t eps_num, int64_t eps_den,
                        orc_node_out* out) {
@@ -318,16 +343,20 @@ int orc_node_estimates(int64_t n, int32_t k, int64_t v, const int32_t* sidx, con
     /* Sec. 4.1: the sampling part estimates the variance of the L distances by
      * the sample variance over L cap C (sum of squares / count minus squared
      * mean), divided by |L cap C| and scaled by |L|; the pivoting part takes
-     * the mean squared difference over HC and scales it by |H| (no HC: 0).
-     * Written with the exact integer LCnum * LCsumsq - LCsum^2 and a fixed
-     * order of double operations. */
+     * the mean squared difference over HC and scales it by |H|; with HC empty
+     * the mean is over the farthest samples (far_suffix_sqerr).  Written with
+     * the exact integer LCnum * LCsumsq - LCsum^2 and a fixed order of double
+     * operations. */
     __int128 varnum = (__int128)LCnum * LCsumsq - (__int128)LCsum * LCsum;
-    int err_ovf = LCsumsq > (__int128)INT64_MAX || HCsqerr > (__int128)INT64_MAX || varnum > (__int128)INT64_MAX;
+    int64_t sqcnt = HCnum;
+    __int128 sqsum = HCsqerr;
+    if (HCnum == 0) sqsum = far_suffix_sqerr(n, sidx, row, colp, stride, &sqcnt);
+    int err_ovf = LCsumsq > (__int128)INT64_MAX || sqsum > (__int128)INT64_MAX || varnum > (__int128)INT64_MAX;
     out->LC_sumsq = (int64_t)LCsumsq;
     out->HC_sqerr = (int64_t)HCsqerr;
     {
         double tL = ((double)(int64_t)varnum / (double)(LCnum * LCnum * LCnum)) * (double)Lnum;
-        double tH = HCnum > 0 ? ((double)(int64_t)HCsqerr / (double)HCnum) * (double)Hnum : 0.0;
+        double tH = ((double)(int64_t)sqsum / (double)sqcnt) * (double)Hnum;
         out->S_err = tL + tH;
     }
     /* S_hyb = Hsum + HCsum + Lnum * LCsum / LCnum = N / LCnum */
@@ -408,10 +437,13 @@ int orc_node_sweep(int64_t n, int32_t k, int64_t v, const int32_t* sidx, const i
         if (LCnum < 1) continue; /* cannot happen: the pivot sample is at distance 0 */
         __int128 N = (__int128)(Hsum + HCsum) * LCnum + (__int128)Lnum * LCsum;
         __int128 varnum = (__int128)LCnum * LCsumsq - (__int128)LCsum * LCsum;
-        ovf = ovf || N >= (__int128)LIM || varnum > (__int128)INT64_MAX || HCsqerr > (__int128)INT64_MAX;
+        int64_t sqcnt = HCnum;
+        __int128 sqsum = HCsqerr;
+        if (HCnum == 0) sqsum = far_suffix_sqerr(n, sidx, row, colp, stride, &sqcnt); /* Sec. 4.1's suffix */
+        ovf = ovf || N >= (__int128)LIM || varnum > (__int128)INT64_MAX || sqsum > (__int128)INT64_MAX;
         double est = (double)(int64_t)N / (double)LCnum;
         double tL = ((double)(int64_t)varnum / (double)(LCnum * LCnum * LCnum)) * (double)Lnum;
-        double tH = HCnum > 0 ? ((double)(int64_t)HCsqerr / (double)HCnum) * (double)Hnum : 0.0;
+        double tH = ((double)(int64_t)sqsum / (double)sqcnt) * (double)Hnum;
         double err = tL + tH;
         if (err < best_err) { best_err = err; best_S = est; }
     }
@@ -499,6 +531,189 @@ int orc_estimate_all(int64_t n, int32_t k, const int32_t* sidx, const int64_t* D
     }
     pthread_mutex_destroy(&J.lock);
     return J.status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Every node at any size, with Algorithm 1's accounting instead of a walk
+ * over V per node (Sec. 3): the sums over H(v) come from the unsampled nodes'
+ * distances to the pivot, kept per sample as a sorted list with suffix sums
+ * ("tail sums for nodes for which c_i is pivot"); the samples are split into
+ * L cap C and HC by d(c(v), c_i) against the threshold; |L| = n-1-|H|-|HC|.
+ * The estimates and errors are then those of orc_node_estimates (the same
+ * exact integers, the same order of double operations), and the adaptive
+ * choice that of orc_node_adaptive.  D is node-major n x k with
+ * D[u*k + i] = d(c_i, u); distances must be symmetric (undirected or round
+ * trip).  Outputs have n entries (src_sum k, dmat k*k); any may be NULL. */
+typedef struct {
+    int64_t n; int32_t k; const int32_t* sidx; const int64_t* D; const int32_t* piv; const int64_t* bstart;
+    const int32_t* bnodes; const int64_t* src_sum; const int64_t* dmat;
+    const int64_t* nums; const int64_t* dens; int32_t n_eps;  /* entry 0: the call's eps; 1..: the list */
+    int64_t* S_pub; double* S_samp; double* S_hyb; double* S_err; double* S_ad; double* S_ad_err;
+    int32_t next; pthread_mutex_t lock; int status;
+} tails_job;
+
+static int cmp_i64(const void* a, const void* b) {
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* number of entries of the ascending list srt[0..m) that are > T */
+static int64_t count_above(const int64_t* srt, int64_t m, int64_t T) {
+    int64_t lo = 0, hi = m;  /* first index with srt[idx] > T */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (srt[mid] > T) hi = mid; else lo = mid + 1;
+    }
+    return m - lo;
+}
+
+static void* tails_worker(void* arg) {
+    tails_job* J = (tails_job*)arg;
+    const int64_t n = J->n, k = J->k;
+    const __int128 LIM = (__int128)1 << 53;
+    int64_t* srt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t* suf = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!srt || !suf) {
+        pthread_mutex_lock(&J->lock); J->status = ORC_ENOMEM; pthread_mutex_unlock(&J->lock);
+        free(srt); free(suf); return NULL;
+    }
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int32_t p = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (p >= k) break;
+        if (J->bstart[p] == J->bstart[p + 1]) continue;  /* no unsampled node has this pivot */
+        /* the unsampled nodes' distances to c_p, ascending, with suffix sums */
+        int64_t m = 0;
+        for (int64_t u = 0; u < n; u++)
+            if (J->sidx[u] < 0) srt[m++] = J->D[u * k + p];
+        qsort(srt, (size_t)m, sizeof(int64_t), cmp_i64);
+        suf[m] = 0;
+        for (int64_t t = m - 1; t >= 0; t--) suf[t] = suf[t + 1] + srt[t];
+        const int64_t* dp = J->dmat + (int64_t)p * k;  /* d(c_p, c_i) */
+        int64_t far = 0;
+        for (int32_t i = 0; i < k; i++) if (dp[i] > far) far = dp[i];
+        for (int64_t b = J->bstart[p]; b < J->bstart[p + 1]; b++) {
+            const int64_t v = J->bnodes[b];
+            const int64_t* row = J->D + v * k;
+            const int64_t delta = row[p];
+            int ovf = 0;
+            double ad = 0, ad_err = 0;
+            for (int32_t e = 0; e < J->n_eps; e++) {
+                const int64_t num = J->nums[e], den = J->dens[e];
+                const int64_t T = delta * den / num;  /* d*num <= Delta*den  <=>  d <= T for integer d */
+                const int64_t Hnum = count_above(srt, m, T);
+                const int64_t Hsum = suf[m - Hnum];
+                int64_t LCnum = 0, HCnum = 0, LCsum = 0, HCsum = 0;
+                __int128 LCsumsq = 0, HCsqerr = 0, Fsq = 0;
+                int64_t Fnum = 0;
+                for (int32_t i = 0; i < k; i++) {
+                    const int64_t d = row[i];
+                    if (dp[i] * num <= delta * den) {
+                        LCnum++; LCsum += d; LCsumsq += (__int128)d * d;
+                    } else {
+                        HCnum++; HCsum += d; HCsqerr += (__int128)(d - dp[i]) * (d - dp[i]);
+                    }
+                    if (dp[i] == far) { Fnum++; Fsq += (__int128)(d - dp[i]) * (d - dp[i]); }
+                }
+                const int64_t Lnum = n - 1 - Hnum - (k - LCnum);
+                if (LCnum < 1 || Lnum < LCnum) { ovf = 1; continue; }
+                __int128 N = (__int128)(Hsum + HCsum) * LCnum + (__int128)Lnum * LCsum;
+                __int128 varnum = (__int128)LCnum * LCsumsq - (__int128)LCsum * LCsum;
+                int64_t sqcnt = HCnum;
+                __int128 sqsum = HCsqerr;
+                if (HCnum == 0) { sqcnt = Fnum; sqsum = Fsq; }  /* Sec. 4.1's suffix of the farthest samples */
+                ovf = ovf || N >= LIM || varnum > (__int128)INT64_MAX || sqsum > (__int128)INT64_MAX ||
+                      LCsumsq > (__int128)INT64_MAX;
+                const double est = (double)(int64_t)N / (double)LCnum;
+                const double tL = ((double)(int64_t)varnum / (double)(LCnum * LCnum * LCnum)) * (double)Lnum;
+                const double tH = ((double)(int64_t)sqsum / (double)sqcnt) * (double)Hnum;
+                const double err = tL + tH;
+                if (e == 0) {
+                    if (J->S_hyb) J->S_hyb[v] = est;
+                    if (J->S_err) J->S_err[v] = err;
+                } else if (e == 1 || err < ad_err) {
+                    ad = est; ad_err = err;
+                }
+            }
+            if (J->S_ad && J->n_eps > 1) J->S_ad[v] = ad;
+            if (J->S_ad_err && J->n_eps > 1) J->S_ad_err[v] = ad_err;
+            if (ovf) { pthread_mutex_lock(&J->lock); J->status = ORC_EOVERFLOW; pthread_mutex_unlock(&J->lock); }
+        }
+    }
+    free(srt); free(suf);
+    return NULL;
+}
+
+int orc_estimate_tails(int64_t n, int32_t k, const int32_t* sidx, const int64_t* D, const int64_t* nums,
+                       const int64_t* dens, int32_t n_eps, int32_t threads, int32_t* pivot, int64_t* delta,
+                       int64_t* sampsum, int64_t* src_sum, int64_t* dmat, int64_t* S_piv, int64_t* S_pub,
+                       double* S_samp, double* S_hyb, double* S_err, double* S_ad, double* S_ad_err) {
+    const __int128 LIM = (__int128)1 << 53;
+    int status = ORC_OK;
+    /* S(c_i) = sum over every node of d(c_i, u); the sample distance matrix */
+    for (int32_t i = 0; i < k; i++) src_sum[i] = 0;
+    for (int64_t u = 0; u < n; u++) {
+        const int64_t* row = D + u * k;
+        for (int32_t i = 0; i < k; i++) src_sum[i] += row[i];
+        if (sidx[u] >= 0)
+            for (int32_t i = 0; i < k; i++) dmat[(int64_t)i * k + sidx[u]] = row[i];
+    }
+    /* per node: pivot (lowest index on ties), Delta, sampsum, and the
+     * estimates that need nothing else; sampled nodes get their exact sum */
+    int64_t* bstart = (int64_t*)calloc((size_t)k + 2, sizeof(int64_t));
+    int32_t* bnodes = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!bstart || !bnodes) { free(bstart); free(bnodes); return ORC_ENOMEM; }
+    for (int64_t v = 0; v < n; v++) {
+        const int64_t* row = D + v * k;
+        int32_t p = orc_pivot(k, row);
+        int64_t ss = 0;
+        for (int32_t i = 0; i < k; i++) ss += row[i];
+        pivot[v] = p; delta[v] = row[p]; sampsum[v] = ss;
+        const int64_t Sp = src_sum[p];
+        if (sidx[v] >= 0) {
+            S_piv[v] = S_pub[v] = Sp;
+            S_samp[v] = (double)Sp;
+            if (S_hyb) S_hyb[v] = (double)Sp;
+            if (S_err) S_err[v] = 0.0;
+            if (S_ad) S_ad[v] = (double)Sp;
+            if (S_ad_err) S_ad_err[v] = 0.0;
+            if (Sp >= LIM) status = ORC_EOVERFLOW;
+            continue;
+        }
+        S_piv[v] = Sp;
+        S_pub[v] = Sp + (n - 1) * row[p];
+        const __int128 x = (__int128)(n - 1) * ss;
+        if (x >= LIM) status = ORC_EOVERFLOW;
+        S_samp[v] = (double)(int64_t)x / (double)k;
+        bstart[p + 1]++;
+    }
+    for (int32_t p = 0; p < k; p++) bstart[p + 1] += bstart[p];
+    {
+        int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k + 1));
+        if (!fill) { free(bstart); free(bnodes); return ORC_ENOMEM; }
+        memcpy(fill, bstart, sizeof(int64_t) * (size_t)(k + 1));
+        for (int64_t v = 0; v < n; v++)
+            if (sidx[v] < 0) bnodes[fill[pivot[v]]++] = (int32_t)v;
+        free(fill);
+    }
+    tails_job J;
+    J.n = n; J.k = k; J.sidx = sidx; J.D = D; J.piv = pivot; J.bstart = bstart; J.bnodes = bnodes;
+    J.src_sum = src_sum; J.dmat = dmat; J.nums = nums; J.dens = dens; J.n_eps = n_eps;
+    J.S_pub = S_pub; J.S_samp = S_samp; J.S_hyb = S_hyb; J.S_err = S_err; J.S_ad = S_ad; J.S_ad_err = S_ad_err;
+    J.next = 0; J.status = ORC_OK;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads <= 1) {
+        tails_worker(&J);
+    } else {
+        pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+        for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, tails_worker, &J);
+        for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
+    pthread_mutex_destroy(&J.lock);
+    free(bstart); free(bnodes);
+    return J.status != ORC_OK ? J.status : status;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -694,7 +909,20 @@ static void* beta_worker(void* arg) {
             double t = (double)J->R / (double)J->m;
             J->var[slot] = t * (t * (double)(int64_t)A - (double)(int64_t)B);
             /* Sec. 4.1 with beta masses (Sec. 5): the L term's variance plus beta(H) times the
-             * beta-weighted mean over HC of (d(v,u) - d(c(v),u))^2 (0 without HC weight) */
+             * beta-weighted mean over HC of (d(v,u) - d(c(v),u))^2; without HC weight the mean is
+             * over the samples at the largest distance from the pivot (Sec. 4.1's suffix of the
+             * farthest samples), 0 if they weigh nothing either */
+            if (HCb == 0) {
+                int64_t far = -1;
+                for (int64_t u = 0; u < n; u++)
+                    if (J->sidx[u] >= 0 && J->D[u * k + p] > far) far = J->D[u * k + p];
+                for (int64_t u = 0; u < n; u++) {
+                    int32_t j = J->sidx[u];
+                    if (j < 0 || J->D[u * k + p] != far) continue;
+                    HCb += J->beta[u];
+                    HCsq += (__int128)J->beta[u] * (row[j] - far) * (row[j] - far);
+                }
+            }
             ovf = ovf || HCsq > (__int128)INT64_MAX;
             if (J->err)
                 J->err[slot] = J->var[slot] +

@@ -41,6 +41,18 @@ def round_trip(d):
     return [[d[a][b] + d[b][a] for b in range(n)] for a in range(n)]
 
 
+def pivot_sq_err(dist, samples, j, cp, HC):
+    """Sec. 4.1's estimate of the mean squared pivoting error of node j with
+    pivot cp: the mean of (d(j,u) - d(cp,u))^2 over HC, and when HC is empty
+    over the "suffix" of the farthest samples, read as the samples at the
+    largest distance from the pivot (Fraction)."""
+    if HC:
+        return sum(Fraction(dist[j][i] - dist[cp][i]) ** 2 for i in HC) / len(HC)
+    far = max(dist[cp][c] for c in samples)
+    F = [c for c in samples if dist[cp][c] == far]
+    return sum(Fraction(dist[j][i] - dist[cp][i]) ** 2 for i in F) / len(F)
+
+
 def estimates(dist, samples, eps: Fraction):
     """dist: full n x n metric (list of lists); samples: ordered list C.
     Returns dict of per-node lists: pivot, delta, S_exact, S_samp, S_piv, S_pub, S_hyb
@@ -75,10 +87,11 @@ def estimates(dist, samples, eps: Fraction):
         out["S_hyb"].append(s_hyb)
         # Sec. 4.1: sample variance over L cap C (population form, mean of the
         # squared deviations from the sample mean), over |L cap C|, times |L|;
-        # plus |H| times the mean squared pivot error over HC (none: 0)
+        # plus |H| times the mean squared pivot error over HC (no HC: over the
+        # farthest samples)
         mean = sum(Fraction(dist[j][i]) for i in LC) / len(LC)
         var = sum((Fraction(dist[j][i]) - mean) ** 2 for i in LC) / len(LC)
-        piv_err = (sum(Fraction(dist[j][i] - dist[cp][i]) ** 2 for i in HC) / len(HC)) if HC else Fraction(0)
+        piv_err = pivot_sq_err(dist, samples, j, cp, HC)
         out["S_err"].append(var / len(LC) * len(L) + piv_err * len(H))
         out["S_samp"].append(Fraction(n - 1, k) * sum(dists))
         out["S_piv"].append(Fraction(S[cp]))
@@ -128,7 +141,7 @@ def sweep_candidates(dist, samples, j):
                + Fraction(len(L), len(LC)) * sum(Fraction(dist[j][i]) for i in LC))
         mean = sum(Fraction(dist[j][i]) for i in LC) / len(LC)
         var = sum((Fraction(dist[j][i]) - mean) ** 2 for i in LC) / len(LC)
-        piv = (sum(Fraction(dist[j][i] - dist[cp][i]) ** 2 for i in HC) / len(HC)) if HC else Fraction(0)
+        piv = pivot_sq_err(dist, samples, j, cp, HC)
         out.append((s_T, var / len(LC) * len(L) + piv * len(H)))
     return out
 
@@ -271,7 +284,9 @@ def weighted_estimates(dist, beta, samples, light, tau, eps):
 def weighted_errors(dist, beta, samples, light, tau, eps):
     """Sec. 5's error estimate: Sec. 4.1 with beta masses -- the variance
     estimate of the L term plus beta(H) times the beta-weighted mean over HC
-    of (d(v,u) - d(c(v),u))^2 (0 without HC weight); sampled nodes 0."""
+    of (d(v,u) - d(c(v),u))^2; without HC weight the mean is taken over the
+    samples at the largest distance from the pivot (Sec. 4.1's suffix of the
+    farthest samples; 0 if they weigh nothing either); sampled nodes 0."""
     n = len(dist)
     C = list(samples)
     Cset = set(C)
@@ -289,6 +304,10 @@ def weighted_errors(dist, beta, samples, light, tau, eps):
         HC = [u for u in far if u in Cset]
         Hb = sum(beta[u] for u in far if u not in Cset)
         HCb = sum(beta[u] for u in HC)
+        if not HCb:
+            top = max(dist[cp][c] for c in C)
+            HC = [c for c in C if dist[cp][c] == top]
+            HCb = sum(beta[u] for u in HC)
         sq = (sum(beta[u] * Fraction(dist[v][u] - dist[cp][u]) ** 2 for u in HC) / HCb) if HCb else Fraction(0)
         out.append(var[v] + sq * Hb)
     return out

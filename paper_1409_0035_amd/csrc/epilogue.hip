@@ -640,9 +640,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(const MT* __restrict__ dma
 // those ranks.  With LC the first lc ranks, HC the others and H, |H| the
 // nodes outside C beyond the candidate's threshold:
 //   N   = (sum_H d(c_p,u) + sum_HC d(v,c_i)) * lc + |L| * sum_LC d(v,c_i), estimate N / lc
-//   err = ((lc * sum_LC d^2 - (sum_LC d)^2) / lc^3) * |L| + (sum_HC (d - d_p)^2 / |HC|) * |H|
-// (second term 0 without HC), |L| = n-1-|H|-|HC|, in exactly this order of
-// double operations on exact integers (d = d(v,c_i), d_p = d(c_p,c_i)).
+//   err = ((lc * sum_LC d^2 - (sum_LC d)^2) / lc^3) * |L| + (sum_F (d - d_p)^2 / |F|) * |H|
+// with F = HC, or, when HC is empty, F = the samples at the largest distance
+// from c_p (Sec. 4.1's "suffix" of the farthest samples: the last ranks), and
+// |L| = n-1-|H|-|HC|, in exactly this order of double operations on exact
+// integers (d = d(v,c_i), d_p = d(c_p,c_i)).
 //   * hybrid, eps = num/den (the call's, then each of the adaptive list): LC =
 //     {i : d_p <= floor(Delta*den/num)}, H beyond that threshold (tail tables);
 //     S_err is the call's error, S_ad the first smallest error over the list.
@@ -664,8 +666,8 @@ struct ErrEps {
 };
 
 __device__ __forceinline__ void prefix_candidate(int64_t n, int32_t k, int64_t lc, int64_t lcsum, uint64_t lcsq,
-                                                 int64_t hcsum, uint64_t hcsq, int64_t hnum, int64_t hsum,
-                                                 double& est, double& err, bool& eo) {
+                                                 int64_t hcsum, uint64_t fsq, int64_t fnum, int64_t hnum,
+                                                 int64_t hsum, double& est, double& err, bool& eo) {
     const int64_t LIM = (int64_t)1 << 53;
     const int64_t hcnum = k - lc;
     const int64_t lnum = (n - 1) - hnum - hcnum;
@@ -677,7 +679,7 @@ __device__ __forceinline__ void prefix_candidate(int64_t n, int32_t k, int64_t l
     eo = eo || e;
     est = (double)N / (double)lc;
     const double tL = ((double)varnum / (double)(lc * lc * lc)) * (double)lnum;
-    const double tH = hcnum > 0 ? ((double)(int64_t)hcsq / (double)hcnum) * (double)hnum : 0.0;
+    const double tH = ((double)(int64_t)fsq / (double)fnum) * (double)hnum;
     err = tL + tH;
 }
 
@@ -925,6 +927,11 @@ __global__ __launch_bounds__(64) void k_errsweep(
     using UAT = typename std::make_unsigned<AT>::type;
     AT c1 = 0;
     UAT c2 = 0, ce = 0;
+    // the prefix state at the previous distinct distance, and the squared
+    // pivot errors of the last ranks (the farthest samples) with their count
+    UAT ce_last = 0;
+    int64_t lc_last = 0, suf_cnt = 1;
+    uint64_t suf_sq = 0;
     double berr = __builtin_inf(), best_est = 0.0;
     bool eo = false;
     for (int32_t j0 = 0; j0 < k; j0 += kRun) {
@@ -944,6 +951,10 @@ __global__ __launch_bounds__(64) void k_errsweep(
             ce += (UAT)(df * df);
             if (nx == dl) continue;  // not the last rank at this distance (uniform)
             const int64_t lc = j + 1;
+            if (lc == k) {  // the farthest distance: its ranks are the suffix
+                suf_sq = (uint64_t)(UAT)(ce - ce_last);
+                suf_cnt = lc - lc_last;
+            }
             if (want_sw) {
                 int64_t hn = 0, hs = 0;
                 if (dl + 1 < tlen) {
@@ -955,8 +966,9 @@ __global__ __launch_bounds__(64) void k_errsweep(
                     hs -= delta;
                 }
                 double est, err;
-                prefix_candidate(n, k, lc, (int64_t)c1, (uint64_t)c2, sum - (int64_t)c1, sq_all - (uint64_t)ce, hn,
-                                 hs, est, err, eo);
+                const bool hc = lc < k;
+                prefix_candidate(n, k, lc, (int64_t)c1, (uint64_t)c2, sum - (int64_t)c1,
+                                 hc ? sq_all - (uint64_t)ce : suf_sq, hc ? k - lc : suf_cnt, hn, hs, est, err, eo);
                 if (err < berr) {
                     berr = err;
                     best_est = est;
@@ -973,6 +985,8 @@ __global__ __launch_bounds__(64) void k_errsweep(
                     }
                 }
             }
+            ce_last = ce;
+            lc_last = lc;
         }
     }
     if (!active) return;
@@ -983,8 +997,9 @@ __global__ __launch_bounds__(64) void k_errsweep(
         for (int e = 0; e < kErrEps; e++) {
             if (e < E.count) {
                 double est, err;
-                prefix_candidate(n, k, elc[e], ec1[e], ec2[e], sum - ec1[e], sq_all - ece[e], ehn[e], ehs[e], est,
-                                 err, eo);
+                const bool hc = elc[e] < k;
+                prefix_candidate(n, k, elc[e], ec1[e], ec2[e], sum - ec1[e], hc ? sq_all - ece[e] : suf_sq,
+                                 hc ? k - elc[e] : suf_cnt, ehn[e], ehs[e], est, err, eo);
                 if (e == 0) {
                     err0 = err;
                 } else if (e == 1 || err < ad_err) {

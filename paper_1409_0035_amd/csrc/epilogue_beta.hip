@@ -21,7 +21,9 @@
 //                    hw[i][d]; exact S_beta(c_i) = WT[i][0] + sum_j beta(c_j) d(c_i, c_j)
 // The error estimate (Sec. 4.1 with beta masses, Sec. 5) adds to the variance
 // estimate beta(H) (from WC) times the beta-weighted mean over HC of
-// (d(v,c_i) - d(c(v),c_i))^2, 0 when HC has no weight.
+// (d(v,c_i) - d(c(v),c_i))^2.  When HC has no weight the mean is over the
+// samples at the largest distance from the pivot (Sec. 4.1's suffix of the
+// farthest samples), and 0 if those weigh nothing either.
 //   k_beta_estimate  one lane per node: pivot, Delta, the split of the samples,
 //                    the estimate and the variance estimate
 #include "internal.h"
@@ -197,6 +199,17 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
                     __builtin_mul_overflow(df * df, b, &q) || __builtin_add_overflow(HCsq, q, &HCsq);
             }
         }
+        if (err && HCb == 0) {  // the farthest samples stand in for HC
+            int32_t far = -1;
+            for (int32_t i = 0; i < k; i++) far = max(far, drow[i]);
+            for (int32_t i = 0; i < k; i++) {
+                if (drow[i] != far) continue;
+                const int64_t b = beta[samples[i]], df = (int64_t)row[i] - far;
+                int64_t q = 0;
+                HCb += b;
+                e = e || __builtin_mul_overflow(df * df, b, &q) || __builtin_add_overflow(HCsq, q, &HCsq);
+            }
+        }
         const int64_t thr = delta * den / num;  // H: nodes outside C at distance > floor(Delta/eps)
         const int64_t H = thr + 1 < hlen ? WT[(int64_t)p * hlen + thr + 1] : 0;
         const int64_t Hb = thr + 1 < hlen ? WC[(int64_t)p * hlen + thr + 1] : 0;
@@ -304,6 +317,31 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
                 __builtin_add_overflow(Ls, a3, &Ls) || __builtin_add_overflow(A, a4, &A) ||
                 __builtin_add_overflow(B, a5, &B) || __builtin_add_overflow(HCb, a6, &HCb) ||
                 __builtin_add_overflow(HCsq, a7, &HCsq);
+        }
+        if (err && HCb == 0) {  // the farthest samples stand in for HC (HCb is the group's total)
+            int32_t far = -1;
+            for (int32_t c = g; c < pieces; c += G)
+                far = max(far, max(max(drow[4 * c], drow[4 * c + 1]), max(drow[4 * c + 2], drow[4 * c + 3])));
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) far = max(far, __shfl_xor(far, off, G));
+            for (int32_t c = g; c < pieces; c += G) {
+                const int4 x = row[c];
+                const int32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int32_t i = 4 * c + q;
+                    if (drow[i] != far) continue;
+                    const int64_t b = beta[samples[i]], df = (int64_t)w[q] - far;
+                    int64_t qq = 0;
+                    HCb += b;
+                    e = e || __builtin_mul_overflow(df * df, b, &qq) || __builtin_add_overflow(HCsq, qq, &HCsq);
+                }
+            }
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                const int64_t a6 = __shfl_xor(HCb, off, G), a7 = __shfl_xor(HCsq, off, G);
+                e = e || __builtin_add_overflow(HCb, a6, &HCb) || __builtin_add_overflow(HCsq, a7, &HCsq);
+            }
         }
         if (g == 0) {
             const int64_t thr = delta * den / num;

@@ -97,9 +97,12 @@ def same_result(a: dict, b: dict) -> bool:
 
 
 def serve(jobs, graphs, load: float = 0.8, seed: int = 5, max_inflight: int = 8, mem_budget_bytes: int = 0,
-          check: bool = True) -> dict:
+          check: bool = True, reference=None) -> dict:
     """Run a job list against pre-built graphs.  `jobs[i]["graph"]` indexes
-    `graphs`.  Returns a summary dict (latencies in ms)."""
+    `graphs`.  Returns a summary dict (latencies in ms).  With check, every
+    served result (in the paced run and in the burst) must equal the job run
+    alone; `reference`, if given, is a function i -> dict of expected arrays
+    (the fields of OUTPUTS) that every result must equal as well."""
     ctx = cc.Context(0, mem_budget_bytes=mem_budget_bytes, max_inflight=max_inflight)
     try:
         t0 = time.perf_counter()
@@ -118,6 +121,13 @@ def serve(jobs, graphs, load: float = 0.8, seed: int = 5, max_inflight: int = 8,
         if check:
             mismatches = [i for i in range(len(jobs))
                           if not (same_result(alone[i], mixed[i]) and same_result(alone[i], burst[i]))]
+        if reference is not None:
+            for i in range(len(jobs)):
+                want = reference(i)
+                if not all(np.array_equal(r[f], np.asarray(want[f]).astype(r[f].dtype))
+                           for r in (alone[i], mixed[i], burst[i]) for f in OUTPUTS):
+                    mismatches.append(i)
+            mismatches = sorted(set(mismatches))
         total = [t for _, t in lat]
         queue = [q for q, _ in lat]
         teps = sum(edges_traversed(graphs[j["graph"]], j["k"]) for j in jobs)

@@ -51,7 +51,7 @@ def test_batch_matches_single_runs(ctx):
             _same(res[j], alone, f"job {j}")
         # and against the oracle for two of them
         for j in (1, 3):
-            samples = cc.cc_draw_samples(graphs[j].n, ks[j], 10 + j)
+            samples = oracle.draw_samples(graphs[j].n, ks[j], 10 + j)
             ref = oracle.estimate_all(graphs[j], samples, eps=eps[j], threads=8)
             assert np.array_equal(res[j]["D"], ref["D"])
             assert np.array_equal(res[j]["S_hyb"], ref["S_hyb"])

@@ -54,7 +54,7 @@ CASES = [
 @pytest.mark.parametrize("name,make,k,mode,eps", CASES, ids=[c[0] for c in CASES])
 def test_error_estimates_match_oracle(ctx, name, make, k, mode, eps):
     g = make()
-    samples = cc.cc_draw_samples(g.n, k, 7)
+    samples = oracle.draw_samples(g.n, k, 7)
     rg = graphgen.transpose(g) if g.directed else None
     _say(f"  {name}: n={g.n} k={k}")
     ref = oracle.estimate_all(g, samples, eps=eps, threads=8, reverse_graph=rg, sweep=True)
@@ -75,7 +75,7 @@ def test_error_estimates_in_a_batch(ctx):
                                         outputs=ERR)
         assert sts == [cc.CC_OK] * 3
         for j, g in enumerate(graphs):
-            ref = oracle.estimate_all(g, cc.cc_draw_samples(g.n, ks[j], 20 + j), threads=8, sweep=True)
+            ref = oracle.estimate_all(g, oracle.draw_samples(g.n, ks[j], 20 + j), threads=8, sweep=True)
             _check(res[j], ref)
     finally:
         for h in hs:
@@ -86,7 +86,7 @@ def test_sweep_only_outputs(ctx):
     """The sweep alone (no other Sec. 4 output) on the snapshot and the row
     paths."""
     for g, k in ((graphgen.rmat(11, 16, seed=13), 150), (graphgen.grid(30, 30, 8, 0.1, 1, 100, seed=14), 40)):
-        samples = cc.cc_draw_samples(g.n, k, 3)
+        samples = oracle.draw_samples(g.n, k, 3)
         ref = oracle.estimate_all(g, samples, threads=8, sweep=True)
         gh = ctx.upload(g)
         try:

@@ -55,7 +55,7 @@ def check_all(res, ref, samples, with_D=True):
 
 
 def parity(ctx, g, k, seed, eps=None, modes=(cc.CC_BATCHED, cc.CC_PLAIN)):
-    samples = cc.cc_draw_samples(g.n, k, seed)
+    samples = oracle.draw_samples(g.n, k, seed)
     rg = graphgen.transpose(g) if g.directed else None
     ref = oracle.estimate_all(g, samples, eps=eps, threads=8, reverse_graph=rg)
     out = {}

@@ -71,7 +71,7 @@ def test_reach_matches_oracle(ctx, name, make, ks):
                 seed = 11 + k
                 _say(f"  {name}: n={g.n} arcs={g.arcs} k={k} inbound={inbound}")
                 got = cc.cc_reach_estimate(ctx.handle, gh, k, inbound=inbound, seed=seed)
-                order = cc.cc_draw_samples(g.n, g.n, seed)
+                order = oracle.draw_samples(g.n, g.n, seed)
                 ref = oracle.reach_all(g, order, k, inbound=inbound, threads=8, reverse_graph=rg)
                 _same(got, ref, f"{name} k={k} inbound={inbound}")
     finally:
@@ -83,7 +83,7 @@ def test_explicit_order_equals_seeded(ctx):
     gh = ctx.upload(g)
     try:
         a = cc.cc_reach_estimate(ctx.handle, gh, 32, seed=77)
-        b = cc.cc_reach_estimate(ctx.handle, gh, 32, order=cc.cc_draw_samples(g.n, g.n, 77))
+        b = cc.cc_reach_estimate(ctx.handle, gh, 32, order=oracle.draw_samples(g.n, g.n, 77))
         _same(a, b, "order")
         # another order gives another sample, same reach counts where the sample is not full
         c = cc.cc_reach_estimate(ctx.handle, gh, 32, seed=78)
@@ -126,7 +126,7 @@ def test_fullsize_sampled_nodes(ctx):
         _say(f"  inbound estimate: {t['total_ms']:.1f} ms, {t['levels']} levels, {t['launches']} launches")
     finally:
         ctx.release(gh)
-    order = cc.cc_draw_samples(g.n, g.n, seed)
+    order = oracle.draw_samples(g.n, g.n, seed)
     rng = np.random.default_rng(seed)
     deg = np.diff(g.row_ptr)
     nodes = np.unique(np.concatenate([rng.integers(0, g.n, size=6), [int(np.argmax(deg)), 0, g.n - 1],

@@ -1,7 +1,8 @@
 """Serving on the GPU: jobs submitted while others run are admitted as slots
 and memory free up, overlap on the device, and return exactly what the same
-job returns when run alone (every output bit-identical, which is within the
-1e-12 relative tolerance of the estimates)."""
+job returns when run alone and what the oracle computes for it from its own
+draw of the samples (every output bit-identical, which is within the 1e-12
+relative tolerance of the estimates)."""
 import sys
 import time
 
@@ -9,6 +10,7 @@ import numpy as np
 import pytest
 
 import graphgen
+import oracle
 import paper_1409_0035_amd as cc
 from paper_1409_0035_amd import serve
 
@@ -44,6 +46,21 @@ def _check_same(a, b, what):
         assert np.array_equal(a[f], b[f]), f"{what}: {f}"
 
 
+def _oracle_ref(g, k, seed):
+    """Every output of a job from the oracle: its own draw of the samples,
+    all k searches, every node by Algorithm 1's accounting."""
+    samples = np.asarray(oracle.draw_samples(g.n, k, seed), dtype=np.int32)
+    rg = graphgen.transpose(g) if g.directed else None
+    ref = oracle.estimate_tails(g, samples, threads=8, reverse_graph=rg, adaptive_eps=())
+    return ref
+
+
+def _check_oracle(res, ref, what):
+    for f in res:
+        want = ref[f]
+        assert np.array_equal(res[f], np.asarray(want).astype(res[f].dtype).reshape(res[f].shape)), f"{what}: {f}"
+
+
 def test_alone_vs_mix():
     jobs, graphs = _mix()
     # a budget well below the sum of the jobs' needs forces admission waits;
@@ -52,9 +69,12 @@ def test_alone_vs_mix():
         hs = [ctx.upload(g) for g in graphs]
         alone = []
         for j in jobs:
-            _say(f"  alone job {j['job']} n={graphs[j['graph']].n} k={j['k']} mode={j['mode']}")
+            g = graphs[j["graph"]]
+            _say(f"  alone job {j['job']} n={g.n} k={j['k']} mode={j['mode']}")
             alone.append(cc.cc_estimate(ctx.handle, hs[j["graph"]], j["k"], mode=j["mode"],
                                         seed=j["sample_seed"], outputs=ALL))
+            # the job alone equals the oracle; the served ones must equal it
+            _check_oracle(alone[-1], _oracle_ref(g, j["k"], j["sample_seed"]), f"job {j['job']} vs oracle")
         for rep in range(2):
             _say(f"  mix, burst {rep}")
             sub = [cc.cc_submit(ctx.handle, hs[j["graph"]], j["k"], mode=j["mode"], seed=j["sample_seed"],
@@ -110,7 +130,15 @@ def test_graph_release_while_jobs_queued():
 
 def test_serving_driver_small_mix():
     jobs, graphs = serve.build_mix(32, seed=7, n_lo=1e3, n_hi=5e4, threads=8)
-    out = serve.serve(jobs, graphs, load=0.8, seed=7, max_inflight=8)
+    refs = {}
+
+    def reference(i):  # what the oracle computes for job i
+        if i not in refs:
+            j = jobs[i]
+            refs[i] = _oracle_ref(graphs[j["graph"]], j["k"], j["sample_seed"])
+        return refs[i]
+
+    out = serve.serve(jobs, graphs, load=0.8, seed=7, max_inflight=8, reference=reference)
     _say(f"  serving summary: {out}")
     assert out["mismatches"] == []
     assert out["jobs"] == 32

@@ -57,7 +57,7 @@ def test_weighted_knobs_do_not_change_results(ctx):
     g = graphgen.grid(70, 60, 8, 0.1, 1, 1000, seed=5)
     gh = ctx.upload(g)
     try:
-        samples = cc.cc_draw_samples(g.n, 48, 6)
+        samples = oracle.draw_samples(g.n, 48, 6)
         ref = cc.cc_estimate(ctx.handle, gh, 48, seed=6, outputs=ALL)
         orc = oracle.estimate_all(g, samples, threads=8)
         assert np.array_equal(ref["D"], orc["D"])
@@ -99,10 +99,32 @@ def test_autotune_keeps_results(ctx, make, k):
         assert cc.cc_graph_get_tuning(gh) == best
         _same(ref, cc.cc_estimate(ctx.handle, gh, k, seed=1, outputs=ALL), "autotuned")
         # another sample set under the tuned setting still matches the oracle
-        samples = cc.cc_draw_samples(g.n, k, 2)
+        samples = oracle.draw_samples(g.n, k, 2)
         got = cc.cc_estimate(ctx.handle, gh, k, seed=2, outputs=("D", "pivot", "S_hyb"))
         orc = oracle.estimate_all(g, samples, threads=8)
         assert np.array_equal(got["D"], orc["D"]) and np.array_equal(got["pivot"], orc["pivot"])
         assert np.array_equal(got["S_hyb"], orc["S_hyb"])
     finally:
         ctx.release(gh)
+
+
+@pytest.mark.parametrize("level_blocks", [1024, 100, 65])
+def test_merge_grid_not_a_multiple_of_64(ctx, level_blocks):
+    """R-MAT scale 16 (46,754 nodes, 731 64-node groups): the merge launch
+    takes min(ceil(731 / 4), level_blocks) = 183, 100 or 65 blocks, more than
+    the 64 counter slots and not a multiple of 64, so the slots of the level
+    decision's two-step ticket hold different numbers of blocks.  Every output
+    against the oracle, for every node."""
+    g = graphgen.rmat(16, 16, seed=21)
+    k = 192
+    gh = ctx.upload(g)
+    try:
+        cc.cc_graph_set_tuning(gh, level_blocks=level_blocks)
+        got = cc.cc_estimate(ctx.handle, gh, k, seed=4, outputs=ALL)
+    finally:
+        ctx.release(gh)
+    samples = np.asarray(oracle.draw_samples(g.n, k, 4), dtype=np.int32)
+    ref = oracle.estimate_tails(g, samples, threads=8, adaptive_eps=())
+    assert np.array_equal(got["samples"], samples)
+    for f in ALL:
+        assert np.array_equal(got[f], np.asarray(ref[f]).astype(got[f].dtype).reshape(got[f].shape)), f

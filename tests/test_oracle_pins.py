@@ -254,6 +254,37 @@ def test_node_estimates_match_all_nodes():
             assert o.LC_num >= 1
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_tails_form_equals_definition_walk(seed):
+    """Algorithm 1's accounting (tail sums per pivot, estimate_tails) gives
+    exactly the values of the literal walk over V per node (estimate_all) on
+    random undirected, weighted and round-trip graphs, several eps."""
+    rng = np.random.default_rng(1300 + seed)
+    n = int(rng.integers(2, 160))
+    directed = seed % 4 == 3
+    g = graphgen.gnp(n, float(rng.uniform(0.02, 0.2)), 1300 + seed, directed=directed,
+                     wmax=[1, 1, 30, 1][seed % 4])
+    rg = graphgen.transpose(g) if directed else None
+    k = int(rng.integers(1, g.n + 1))
+    samples = oracle.draw_samples(g.n, k, seed)
+    eps = [(1, 1), (1, 3), (2, 5), None][seed % 4]
+    a = oracle.estimate_all(g, samples, eps=eps, reverse_graph=rg)
+    b = oracle.estimate_tails(g, samples, eps=eps, D=a["D"], threads=1 + seed % 3)
+    for f in ("pivot", "delta", "sampsum", "src_sum", "dmat", "S_piv", "S_pub", "S_samp", "S_hyb", "S_err",
+              "S_ad", "S_ad_err"):
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_tails_form_worked_examples():
+    """The hand-derived fixtures through the tails form as well."""
+    rows = _read_golden("path7_C01_eps1_suffix.txt")
+    out = oracle.estimate_tails(graphgen.path(7), [0, 1], eps=(1, 1))
+    for node, hn, hd, en, ed, *_ in rows:
+        assert out["S_hyb"][node] == hn / hd and out["S_err"][node] == en / ed, node
+    out = oracle.estimate_tails(graphgen.path(9), [0, 4, 8], eps=(1, 2))
+    assert list(out["S_hyb"]) == [36, 33, 32, 18, 20, 18, 80 / 3, 33, 36]
+
+
 def test_sum_invariant_per_sample():
     """S(c_i) = sum over non-sampled u of d(c_i,u) + sum_j dmat[i][j]."""
     g = graphgen.grid(20, 20, 8, 0.1, 1, 50, seed=5)
@@ -443,14 +474,39 @@ def test_sweep_vs_bruteforce(seed):
 
 def test_sweep_single_sample_is_pivoting():
     """k = 1: the threshold T = 0 puts only the sample in L and nothing in HC,
-    so its error is 0 and its estimate sums d(c,u) over u != v plus d(v,c),
-    which is S(c) on an undirected graph: the sweep returns S_piv, error 0."""
+    and its estimate sums d(c,u) over u != v plus d(v,c), which is S(c) on an
+    undirected graph.  With HC empty, Sec. 4.1 averages the pivot error over
+    the farthest samples, here the pivot itself: Delta^2 per node of H, which
+    is the n - 2 other nodes, the same as pure pivoting's Delta^2 (n - 1 - k).
+    The tie keeps pure pivoting: S_piv with error Delta^2 (n - 2)."""
     for g in (graphgen.ba(60, 2, seed=5), graphgen.grid(8, 6, 4), graphgen.grid(7, 7, 8, 0.1, 1, 50, seed=3)):
         for s in (0, g.n // 2):
             out = oracle.estimate_all(g, [s], sweep=True)
             un = np.arange(g.n) != s
             assert (out["S_sweep"][un] == out["S_piv"][un].astype(np.float64)).all()
-            assert (out["S_sweep_err"][un] == 0).all()
+            want = out["delta"][un].astype(np.float64) ** 2 * (g.n - 2)
+            assert (out["S_sweep_err"][un] == want).all()
+
+
+def test_empty_hc_suffix_worked_example():
+    """Sec. 4.1's fallback for an empty HC, on a hand-derived fixture where
+    HC is empty and H is not (the samples sit at one end of a path): S_hyb,
+    S_err and the threshold sweep of Algorithm 2, node by node."""
+    rows = _read_golden("path7_C01_eps1_suffix.txt")
+    g = graphgen.path(7)
+    out = oracle.estimate_all(g, [0, 1], eps=(1, 1), sweep=True)
+    d = tiny.floyd_warshall(g.n, g.row_ptr, g.col_idx)
+    t = tiny.estimates(d, [0, 1], Fraction(1, 1))
+    sw, swe = tiny.sweep(d, [0, 1])
+    for node, hn, hd, en, ed, sn, sd, sen, sed in rows:
+        assert out["S_hyb"][node] == hn / hd and t["S_hyb"][node] == Fraction(hn, hd), node
+        assert out["S_err"][node] == en / ed and t["S_err"][node] == Fraction(en, ed), node
+        assert out["S_sweep"][node] == sn / sd and sw[node] == Fraction(sn, sd), node
+        assert out["S_sweep_err"][node] == sen / sed and swe[node] == Fraction(sen, sed), node
+    # the node-level oracle agrees at every node
+    for v in range(2, 7):
+        o = oracle.node_estimates(g, [0, 1], v, eps=(1, 1))
+        assert o.S_err == out["S_err"][v]
 
 
 def test_sweep_special_cases():
