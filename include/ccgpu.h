@@ -104,6 +104,28 @@ cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, const int64_
 void cc_graph_release(cc_graph* g);
 cc_status cc_graph_info(const cc_graph* g, int64_t* n, int64_t* arcs, uint32_t* flags);
 
+/* The same graph (Algorithm 1's input "Network G") from a CSR that already
+ * sits in DEVICE memory of the context's device, e.g. torch tensors:
+ * row_ptr int64[n+1], col_idx int32[arcs], w int32[arcs] or NULL, in the
+ * layout of cc_graph_upload.  Zero copy: the library reads col_idx and w in
+ * place for the whole life of the graph and never writes or frees them; the
+ * caller keeps the three arrays alive and unchanged until cc_graph_release
+ * has been called AND every job that uses the graph has ended (the handle is
+ * reference-counted while jobs run), and has finished writing them before
+ * this call (it reads them on the context's own stream).  The library owns
+ * only what it derives: 32-bit row bounds (4(n+1) B), for CC_DIRECTED the
+ * transposed arcs (as in cc_graph_upload), the 64-node groups that hold a
+ * node of degree above 32 and their arc chunks, and an identity id map.
+ * Nodes keep the caller's order (no degree relabelling), so traversals of
+ * skewed graphs can run slower than after cc_graph_upload; results are the
+ * same.  Checks: shape and non-decreasing row bounds, ids in [0, n) and
+ * lengths >= 1 (on the device), symmetry with CC_VALIDATE (copies the arcs to
+ * the host).  CC_EINVAL when a check fails or an array is not device memory
+ * of the context's device.  Such graphs are not batched with others
+ * (cc_estimate_batch and the serving slots run them alone). */
+cc_status cc_graph_borrow_device(cc_context* ctx, int64_t n, int64_t arcs, const int64_t* row_ptr,
+                                 const int32_t* col_idx, const int32_t* w, uint32_t flags, cc_graph** out);
+
 /* The sample draw of Sec. 2 (k nodes uniformly at random, as a set), fixed
  * so that independent implementations agree: SplitMix64 seeded with `seed`,
  * bounded integers by Lemire's multiply-shift with rejection (64-bit draws),

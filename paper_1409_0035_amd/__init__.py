@@ -27,7 +27,8 @@ CC_BATCHED, CC_PLAIN = 0, 1
 CC_GRAPH = 0x100  # or-ed into CC_BATCHED: capture the estimate as a HIP graph and replay it
 
 EXPORTED = [
-    "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_release", "cc_graph_info",
+    "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_borrow_device", "cc_graph_release",
+    "cc_graph_info",
     "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
     "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
     "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune", "cc_estimate_batch", "cc_reach_estimate",
@@ -142,6 +143,7 @@ def load_library():
         "cc_context_create": (i32, [ctypes.c_int, ctypes.POINTER(cc_config), PP]),
         "cc_context_destroy": (None, [P]),
         "cc_graph_upload": (i32, [P, i64, i64, P, P, P, u32, PP]),
+        "cc_graph_borrow_device": (i32, [P, i64, i64, P, P, P, u32, PP]),
         "cc_graph_release": (None, [P]),
         "cc_graph_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(u32)]),
         "cc_draw_samples": (i32, [i64, i32, u64, P]),
@@ -215,6 +217,26 @@ def cc_graph_upload(ctx, n: int, arcs: int, row_ptr, col_idx, w=None, flags: int
     out = ctypes.c_void_p()
     _check(lib.cc_graph_upload(ctx, int(n), int(arcs), _ptr(rp), _ptr(col), _ptr(wa), int(flags),
                                ctypes.byref(out)))
+    return out
+
+
+def cc_graph_borrow_device(ctx, n: int, arcs: int, row_ptr, col_idx, w=None, flags: int = 0) -> ctypes.c_void_p:
+    """A graph over a CSR already in device memory (torch tensors on the
+    context's device: int64 row_ptr, int32 col_idx, int32 w or None).  The
+    library reads the tensors in place; keep them alive and unchanged until
+    the graph is released and its jobs have ended."""
+    import torch
+    for name, t, dt in (("row_ptr", row_ptr, torch.int64), ("col_idx", col_idx, torch.int32), ("w", w, torch.int32)):
+        if t is None:
+            continue
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != dt:
+            raise ValueError(f"{name}: need a contiguous {dt} device tensor")
+    torch.cuda.synchronize()  # the library reads them on its own stream
+    out = ctypes.c_void_p()
+    _check(load_library().cc_graph_borrow_device(ctx, int(n), int(arcs), ctypes.c_void_p(row_ptr.data_ptr()),
+                                                 ctypes.c_void_p(col_idx.data_ptr()),
+                                                 None if w is None else ctypes.c_void_p(w.data_ptr()), int(flags),
+                                                 ctypes.byref(out)))
     return out
 
 

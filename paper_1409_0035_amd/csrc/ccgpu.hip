@@ -374,6 +374,7 @@ struct cc_graph {
     std::vector<int32_t> inv;  // caller's id -> internal id
     uint64_t id = 0;  // never reused: keys captured estimates
     std::vector<int32_t> chunks_host;  // hub chunk triples (undirected graphs), for batching
+    bool borrowed = false;  // the arcs (and lengths) are the caller's device arrays, never freed here
     mutable std::atomic<int32_t> bfs_hint{0};  // levels the last batched traversal of this graph ran
     cc_tuning tune{4, 1024, 8192, 1, 1024, 64};  // launch shapes (cc_graph_set_tuning / cc_autotune)
 };
@@ -411,8 +412,6 @@ struct cc_context {
     int inflight = 0;
     bool stopping = false;
     bool service_started = false;
-    std::once_flag wgrid_once;
-    int wgrid = 0;  // blocks of the persistent weighted launch (0 = unavailable), found on first use
 };
 
 static void graph_unref(cc_graph* g) {
@@ -697,9 +696,7 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             double sw = 0;
             for (int64_t e = 0; e < arcs; e++) sw += w[e];
             const double mean = arcs > 0 ? sw / (double)arcs : 1.0;
-            double mult = 2.0;
-            if (const char* e = std::getenv("CCGPU_DELTA_MULT")) mult = std::atof(e);
-            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(mult * mean));
+            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(2.0 * mean));
         }
         g->tune.delta = (int32_t)std::min<uint32_t>(std::max<uint32_t>(g->dg.delta, 1u), INT32_MAX);
         std::vector<int32_t> ch_in = hub_chunk_list(prp, nh);
@@ -747,6 +744,231 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
     } catch (const HipError& e) {
         graph_unref(g);
         return fail(CC_EDEVICE, "cc_graph_upload: " + e.where + ": " + hipGetErrorString(e.err));
+    }
+    *out = g;
+    return CC_OK;
+}
+
+// ---------------------------------------------------------------- borrowed device CSR
+
+namespace {
+constexpr int kPrepBlock = 256;
+
+// Range checks of a borrowed CSR's arcs: end ids in [0, n), lengths >= 1.
+__global__ void k_borrow_check(const int32_t* __restrict__ col, const int32_t* __restrict__ w, int64_t arcs,
+                               int64_t n, int32_t* bad) {
+    bool b = false;
+    for (int64_t e = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x; e < arcs; e += (int64_t)gridDim.x * kPrepBlock)
+        b = b || col[e] < 0 || col[e] >= n || (w && w[e] < 1);
+    if (b) *bad = 1;
+}
+
+// Sum of the arc lengths (for the default bucket width) and the in-degrees.
+__global__ void k_borrow_sums(const int32_t* __restrict__ col, const int32_t* __restrict__ w, int64_t arcs,
+                              unsigned long long* wsum, uint32_t* indeg) {
+    unsigned long long s = 0;
+    for (int64_t e = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x; e < arcs; e += (int64_t)gridDim.x * kPrepBlock) {
+        if (w) s += (unsigned long long)w[e];
+        if (indeg) atomicAdd(&indeg[col[e]], 1u);
+    }
+    if (w) atomicAdd(wsum, s);
+}
+
+// The transposed arcs of a digraph: each node's out-arcs land in their
+// targets' rows (row order is immaterial to every search).
+__global__ void k_borrow_transpose(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                   const int32_t* __restrict__ w, int64_t n, uint32_t* pos, int32_t* tcol,
+                                   int32_t* tw) {
+    for (int64_t u = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kPrepBlock)
+        for (int64_t e = rp[u]; e < rp[u + 1]; e++) {
+            const uint32_t q = atomicAdd(&pos[col[e]], 1u);
+            tcol[q] = (int32_t)u;
+            if (w) tw[q] = w[e];
+        }
+}
+
+__global__ void k_iota(int32_t* a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPrepBlock)
+        a[i] = (int32_t)i;
+}
+
+unsigned prep_grid(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + kPrepBlock - 1) / kPrepBlock, 8192)); }
+}  // namespace
+
+extern "C" cc_status cc_graph_borrow_device(cc_context* ctx, int64_t n, int64_t arcs, const int64_t* row_ptr,
+                                            const int32_t* col_idx, const int32_t* w, uint32_t flags,
+                                            cc_graph** out) {
+    if (!ctx || !out || !row_ptr || (arcs > 0 && !col_idx))
+        return fail(CC_EINVAL, "cc_graph_borrow_device: null argument");
+    if (n < 1 || n >= INT32_MAX || arcs < 0 || arcs >= (int64_t)UINT32_MAX)
+        return fail(CC_EINVAL, "cc_graph_borrow_device: need 1 <= n < 2^31 and arcs < 2^32");
+    const bool directed = (flags & CC_DIRECTED) != 0;
+    cc_graph* g = new (std::nothrow) cc_graph();
+    if (!g) return fail(CC_ENOMEM, "cc_graph_borrow_device: host allocation");
+    g->ctx = ctx;
+    static std::atomic<uint64_t> next_borrow_id{1ull << 62};
+    g->id = next_borrow_id.fetch_add(1);
+    g->flags = flags;
+    g->borrowed = true;
+    g->dg.n = n;
+    g->dg.arcs = arcs;
+    g->dg.directed = directed;
+    g->dg.weighted = w != nullptr;
+    std::lock_guard<std::mutex> lk(ctx->mu);  // the context's own stream does the preparation
+    try {
+        CCG_HIP(hipSetDevice(ctx->device));
+        // the three arrays must be device memory of this context's device
+        for (const void* p : {(const void*)row_ptr, (const void*)col_idx, (const void*)w}) {
+            if (!p) continue;
+            hipPointerAttribute_t at{};
+            if (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice ||
+                at.device != ctx->device) {
+                (void)hipGetLastError();
+                graph_unref(g);
+                return fail(CC_EINVAL, "cc_graph_borrow_device: an array is not device memory of the context's device");
+            }
+        }
+        auto own = [&](int slot, size_t bytes) -> void* {
+            void* d = nullptr;
+            if (hipMalloc(&d, bytes ? bytes : 4) != hipSuccess) {
+                (void)hipGetLastError();
+                throw std::bad_alloc();
+            }
+            g->mem[slot] = d;
+            g->bytes += bytes;
+            return d;
+        };
+        hipStream_t st = ctx->lane.stream;
+        // row bounds: read once to the host for the shape checks, the 32-bit
+        // copy the kernels index with and the hub chunk lists
+        std::vector<int64_t> rp64((size_t)n + 1);
+        CCG_HIP(hipMemcpy(rp64.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+        if (rp64[0] != 0 || rp64[(size_t)n] != arcs) {
+            graph_unref(g);
+            return fail(CC_EINVAL, "cc_graph_borrow_device: row_ptr[0] must be 0 and row_ptr[n] must equal arcs");
+        }
+        std::vector<uint32_t> rp((size_t)n + 1);
+        for (int64_t v = 0; v <= n; v++) {
+            if (v < n && rp64[(size_t)v + 1] < rp64[(size_t)v]) {
+                graph_unref(g);
+                return fail(CC_EINVAL, "cc_graph_borrow_device: row_ptr must be non-decreasing");
+            }
+            rp[(size_t)v] = (uint32_t)rp64[(size_t)v];
+        }
+        // ids and lengths, on the device; in-degrees and the length sum with them
+        int32_t* bad = (int32_t*)own(0, sizeof(int32_t) + sizeof(unsigned long long));
+        unsigned long long* wsum = (unsigned long long*)(bad + 2);
+        CCG_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t) * 2 + sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_borrow_check, dim3(prep_grid(arcs)), dim3(kPrepBlock), 0, st, col_idx, w, arcs, n, bad);
+        int32_t bad_h = 0;
+        CCG_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (bad_h) {
+            graph_unref(g);
+            return fail(CC_EINVAL, "cc_graph_borrow_device: col_idx out of range or an arc length below 1");
+        }
+        if ((flags & CC_VALIDATE) && !directed) {
+            // symmetry needs the arcs on the host
+            std::vector<int32_t> col_h((size_t)arcs), w_h(w ? (size_t)arcs : 0);
+            CCG_HIP(hipMemcpy(col_h.data(), col_idx, sizeof(int32_t) * arcs, hipMemcpyDeviceToHost));
+            if (w) CCG_HIP(hipMemcpy(w_h.data(), w, sizeof(int32_t) * arcs, hipMemcpyDeviceToHost));
+            std::string why;
+            if (!check_csr(n, arcs, rp64.data(), col_h.data(), w ? w_h.data() : nullptr, false, why)) {
+                graph_unref(g);
+                return fail(CC_EINVAL, "cc_graph_borrow_device: " + why);
+            }
+        }
+        uint32_t* indeg = directed ? (uint32_t*)own(9, sizeof(uint32_t) * (n + 1)) : nullptr;
+        if (indeg) CCG_HIP(hipMemsetAsync(indeg, 0, sizeof(uint32_t) * (n + 1), st));
+        if (w || indeg)
+            hipLaunchKernelGGL(k_borrow_sums, dim3(prep_grid(arcs)), dim3(kPrepBlock), 0, st, col_idx, w, arcs, wsum,
+                               indeg);
+        std::vector<uint32_t> trp;
+        if (directed) {
+            std::vector<uint32_t> cnt((size_t)n);
+            CCG_HIP(hipMemcpyAsync(cnt.data(), indeg, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, st));
+            CCG_HIP(hipStreamSynchronize(st));
+            trp.assign((size_t)n + 1, 0);
+            for (int64_t v = 0; v < n; v++) trp[(size_t)v + 1] = trp[(size_t)v] + cnt[(size_t)v];
+        }
+        if (w) {
+            unsigned long long ws = 0;
+            CCG_HIP(hipMemcpyAsync(&ws, wsum, sizeof(ws), hipMemcpyDeviceToHost, st));
+            CCG_HIP(hipStreamSynchronize(st));
+            const double mean = arcs > 0 ? (double)ws / (double)arcs : 1.0;
+            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(2.0 * mean));
+        }
+        g->tune.delta = (int32_t)std::min<uint32_t>(std::max<uint32_t>(g->dg.delta, 1u), INT32_MAX);
+        // the caller's order stays: 64-node groups that hold a node of high
+        // in- or out-degree are flagged and all their nodes' arcs are chunked
+        const int64_t ngroups = (n + 63) / 64;
+        std::vector<uint8_t> ghub((size_t)ngroups, 0);
+        const std::vector<uint32_t>& prp = directed ? trp : rp;
+        if (!w)
+            for (int64_t v = 0; v < n; v++) {
+                const uint32_t din = prp[(size_t)v + 1] - prp[(size_t)v], dout = rp[(size_t)v + 1] - rp[(size_t)v];
+                if (std::max(din, dout) > kHubDegree) ghub[(size_t)(v / 64)] = 1;
+            }
+        auto chunk_list = [&](const std::vector<uint32_t>& r) {
+            std::vector<int32_t> c;
+            for (int64_t v = 0; v < n; v++) {
+                if (!ghub[(size_t)(v / 64)]) continue;
+                for (uint32_t b = r[(size_t)v]; b < r[(size_t)v + 1]; b += kHubChunk) {
+                    c.push_back((int32_t)v);
+                    c.push_back((int32_t)b);
+                    c.push_back((int32_t)std::min<uint32_t>(b + kHubChunk, r[(size_t)v + 1]));
+                }
+            }
+            return c;
+        };
+        std::vector<int32_t> ch_in = chunk_list(prp);
+        std::vector<int32_t> ch_out = directed ? chunk_list(rp) : std::vector<int32_t>();
+        auto up = [&](int slot, const void* src, size_t bytes) -> void* {
+            void* d = own(slot, bytes);
+            if (bytes) CCG_HIP(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+            return d;
+        };
+        g->dg.rp = (const uint32_t*)up(1, rp.data(), sizeof(uint32_t) * (n + 1));
+        g->dg.col = col_idx;
+        g->dg.w = w;
+        if (directed) {
+            g->dg.rrp = (const uint32_t*)up(2, trp.data(), sizeof(uint32_t) * (n + 1));
+            int32_t* tcol = (int32_t*)own(3, sizeof(int32_t) * arcs);
+            int32_t* tw = w ? (int32_t*)own(4, sizeof(int32_t) * arcs) : nullptr;
+            uint32_t* pos = indeg;  // reused: the in-degree counts become write positions
+            CCG_HIP(hipMemcpyAsync(pos, trp.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_borrow_transpose, dim3(prep_grid(n)), dim3(kPrepBlock), 0, st, row_ptr, col_idx, w, n,
+                               pos, tcol, tw);
+            g->dg.rcol = tcol;
+            g->dg.rw = tw;
+        } else {
+            g->dg.rrp = g->dg.rp;
+            g->dg.rcol = g->dg.col;
+            g->dg.rw = g->dg.w;
+        }
+        int32_t* ident = (int32_t*)own(5, sizeof(int32_t) * n);
+        hipLaunchKernelGGL(k_iota, dim3(prep_grid(n)), dim3(kPrepBlock), 0, st, ident, n);
+        g->dg.orig = g->dg.inv = ident;
+        g->inv.resize((size_t)n);
+        for (int64_t v = 0; v < n; v++) g->inv[(size_t)v] = (int32_t)v;
+        g->dg.nh = 0;
+        if (!w) g->dg.ghub = (const uint8_t*)up(6, ghub.data(), ghub.size());
+        g->dg.hub_chunks_in = (const int32_t*)up(7, ch_in.data(), sizeof(int32_t) * ch_in.size());
+        g->dg.n_hub_chunks_in = (int32_t)(ch_in.size() / 3);
+        if (directed) {
+            g->dg.hub_chunks_out = (const int32_t*)up(8, ch_out.data(), sizeof(int32_t) * ch_out.size());
+            g->dg.n_hub_chunks_out = (int32_t)(ch_out.size() / 3);
+        } else {
+            g->dg.hub_chunks_out = g->dg.hub_chunks_in;
+            g->dg.n_hub_chunks_out = g->dg.n_hub_chunks_in;
+        }
+        CCG_HIP(hipStreamSynchronize(st));
+    } catch (const std::bad_alloc&) {
+        graph_unref(g);
+        return fail(CC_ENOMEM, "cc_graph_borrow_device: device allocation failed");
+    } catch (const HipError& e) {
+        graph_unref(g);
+        return fail(CC_EDEVICE, "cc_graph_borrow_device: " + e.where + ": " + hipGetErrorString(e.err));
     }
     *out = g;
     return CC_OK;
@@ -825,7 +1047,7 @@ size_t job_bytes(const DevGraph& g, int32_t k, int32_t mode, int db) {
     size_t b = Carver::sz(sizeof(int32_t) * k) * 2 + Carver::sz(sizeof(DevFlags)) + Carver::sz(sizeof(LevelCounters) * kCounterSlots) +
                Carver::sz(sizeof(int32_t) * n);
     if (g.weighted) {
-        b += dbytes * (g.directed ? 3 : 2) + sssp_weighted_scratch(n, mode == CC_PLAIN ? 1 : k);
+        b += dbytes * (g.directed ? 3 : 2) + (mode == CC_PLAIN ? sssp_weighted_scratch(n, 1) : sssp_wsearch_scratch(n, k));
     } else if (mode == CC_PLAIN) {
         b += dbytes * (g.directed ? 3 : 2) + bfs_plain_scratch(n);
     } else {
@@ -944,15 +1166,16 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         const bool bits_path = batched && !g.directed && k <= 256;
         TravStats stats;
         const size_t dbytes = (size_t)n * k * (int)dk;
-        // weighted: samples per delta-stepping call (piles of n*kw pairs)
+        // weighted: samples per call (one workgroup and 16n + n/8 bytes of
+        // piles per sample in the batched path; one sample per call in plain)
         int32_t kw = 1;
         if (g.weighted && mode != CC_PLAIN) {
-            const size_t per = sssp_weighted_scratch(n, 2) - sssp_weighted_scratch(n, 1);
+            const size_t per = sssp_wsearch_scratch(n, 2) - sssp_wsearch_scratch(n, 1);
             kw = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)k, (free_mem() / 4) / std::max<size_t>(per, 1)));
         }
         size_t trav_scratch;
         if (g.weighted)
-            trav_scratch = sssp_weighted_scratch(n, kw);
+            trav_scratch = mode == CC_PLAIN ? sssp_weighted_scratch(n, 1) : sssp_wsearch_scratch(n, kw);
         else
             trav_scratch = mode == CC_PLAIN ? bfs_plain_scratch(n) : bfs_batched_scratch(n, kg0, g.nh);
         const size_t hist_elems = bits_path ? (size_t)kHistSlotsBatched * k * cap : 0;
@@ -1012,6 +1235,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             gv.alpha = gr->tune.alpha;
             gv.level_blocks = gr->tune.level_blocks;
             gv.scatter_blocks = gr->tune.scatter_blocks;
+            gv.ghub = g.ghub;
             return gv;
         };
         // a captured estimate is keyed by everything its launches refer to
@@ -1080,22 +1304,20 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 int64_t md = 0;
                 for (int32_t s0 = 0; s0 < k && rc == 0; s0 += kw) {
                     const int32_t kg = std::min(kw, k - s0);
-                    // the all-rounds cooperative launch pays agent-scope fences at
-                    // every barrier and measures slower than one launch per round;
-                    // it is kept for experiments behind CCGPU_PERSISTENT=1
-                    std::call_once(ctx->wgrid_once, [ctx] {
-                        ctx->wgrid = std::getenv("CCGPU_PERSISTENT") ? weighted_persistent_grid(ctx->device) : 0;
-                    });
                     WeightedShape shape;
                     shape.delta = (uint32_t)std::max(1, gr->tune.delta);
                     shape.round_blocks = gr->tune.round_blocks;
                     shape.local_passes = gr->tune.local_passes;
-                    const int wr = sssp_weighted(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
-                                                 (uint32_t*)Dt + (size_t)s0 * n, shape, ts, trav_scratch, &md, &ds,
-                                                 ctx->wgrid);
+                    const int wr =
+                        mode == CC_PLAIN
+                            ? sssp_weighted(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
+                                            (uint32_t*)Dt + (size_t)s0 * n, shape, ts, trav_scratch, &md, &ds)
+                            : sssp_weighted_batched(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
+                                                    (uint32_t*)Dt + (size_t)s0 * n, shape.delta, ts, trav_scratch,
+                                                    &md, &ds);
                     if (wr == 2) rc = 2;
                     else if (wr == 4) return fail(CC_EOVERFLOW, "a weighted distance or work pile overflowed");
-                    else if (wr == 5) return fail(CC_EDEVICE, "a grid barrier wait expired");
+                    else if (wr == 5) return fail(CC_EDEVICE, "a weighted search did not finish within its time limit");
                 }
                 if (rc == 0) transpose_dist(st, Dt, Dd, n, k, dk);
                 lmax_dir[dir] = (int32_t)std::min<int64_t>(md, INT32_MAX);
@@ -1430,7 +1652,7 @@ constexpr int64_t kBatchNodeLimit = 1 << 17;  // graphs at most this large are b
 constexpr int32_t kBatchWords = 4;
 
 bool batchable(const cc_graph* g, const Resolved& r) {
-    return !g->dg.directed && !g->dg.weighted && r.mode == CC_BATCHED && r.k <= 192 && g->dg.n <= kBatchNodeLimit &&
+    return !g->borrowed && !g->dg.directed && !g->dg.weighted && r.mode == CC_BATCHED && r.k <= 192 && g->dg.n <= kBatchNodeLimit &&
            g->dg.arcs < ((int64_t)1 << 30);
 }
 
@@ -2115,10 +2337,11 @@ extern "C" cc_status cc_autotune(cc_context* ctx, cc_graph* g, int32_t k, uint64
             if (g->dg.weighted) {
                 const int32_t d0 = std::max(1, start.delta);
                 std::vector<int32_t> ds;
-                for (double f : {0.25, 0.5, 2.0, 4.0, 8.0}) ds.push_back((int32_t)std::max<double>(1.0, std::llround(d0 * f)));
+                // the batched searches take the bucket width only (the round
+                // shape knobs belong to the plain path's device-wide rounds)
+                for (double f : {0.5, 1.5, 2.0, 3.0, 4.0, 8.0})
+                    ds.push_back((int32_t)std::max<double>(1.0, std::llround(d0 * f)));
                 try_knob(&cc_tuning::delta, ds);
-                try_knob(&cc_tuning::local_passes, {0, 8, 16, 32, 128});
-                try_knob(&cc_tuning::round_blocks, {256, 512, 2048, 4096});
             } else {
                 try_knob(&cc_tuning::alpha, {1, 2, 8, 16, 32, 64});
                 try_knob(&cc_tuning::scatter_blocks, {2048, 4096, 8192, 16384});

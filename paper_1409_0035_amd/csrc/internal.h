@@ -31,7 +31,7 @@ struct DevFlags {
     int32_t disconnected;   // a node never reached by some sample
     int32_t overflow;       // a distance or numerator out of range
     int32_t bad_sample;     // duplicate / out-of-range sample
-    int32_t timeout;        // a bounded wait expired (persistent kernels)
+    int32_t timeout;        // a bounded wait or a time limit expired
     int64_t maxd;           // largest distance seen (weighted traversal)
     int64_t reserved[3];
 };
@@ -119,65 +119,6 @@ __device__ __forceinline__ int wave_append(int32_t* counter, bool pred) {
     return pred ? base + (int)__popcll(m & lanemask_lt()) : -1;
 }
 
-// ---------------------------------------------------------------- grid barrier
-// Barrier across all blocks of a persistent launch (every block resident: the
-// launch goes through hipLaunchCooperativeKernel, which refuses grids that do
-// not fit).  Two levels: blocks arrive on one of kBarGroups counters, the
-// last of each group on the top counter, the last overall bumps the
-// generation everyone waits on.  Waits are bounded: after about two seconds
-// of spinning a block raises `abort`, every block leaves at its next barrier
-// and the host reports a device error instead of hanging.
-constexpr int kBarGroups = 8;
-
-struct GridSync {
-    uint32_t group[kBarGroups][32];  // one cache line each
-    uint32_t top[32];
-    uint32_t gen[32];
-    uint32_t abort[32];
-};
-
-__device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t nblocks) {
-    __shared__ uint32_t ok;  // thread 0's view of the abort flag, so the whole block agrees
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (__hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            __threadfence();
-            const uint32_t g = __hip_atomic_load(&gs->gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t grp = blockIdx.x % kBarGroups;
-            const uint32_t in_grp = nblocks / kBarGroups + (grp < nblocks % kBarGroups ? 1u : 0u);
-            const uint32_t ngroups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
-            bool last = false;
-            if (__hip_atomic_fetch_add(&gs->group[grp][0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-                in_grp - 1) {
-                __hip_atomic_store(&gs->group[grp][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (__hip_atomic_fetch_add(&gs->top[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-                    ngroups - 1) {
-                    __hip_atomic_store(&gs->top[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(&gs->gen[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    last = true;
-                }
-            }
-            if (!last) {
-                uint64_t spins = 0;
-                while (__hip_atomic_load(&gs->gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > (1ull << 25)) {
-                        __hip_atomic_store(&gs->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    if ((spins & 255) == 0 &&
-                        __hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                        break;
-                }
-            }
-            __threadfence();
-        }
-        ok = __hip_atomic_load(&gs->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    }
-    __syncthreads();
-    return ok != 0;
-}
-
 // ---------------------------------------------------------------- distances
 template <typename DT> struct DistT;
 template <> struct DistT<uint8_t> {
@@ -218,6 +159,9 @@ struct DevGraph {
     int32_t n_hub_chunks_in = 0;
     const int32_t* hub_chunks_out = nullptr;  // over out-arcs (reverse distances)
     int32_t n_hub_chunks_out = 0;
+    // graphs kept in the caller's order (borrowed device CSRs): the 64-node
+    // groups that hold a high-degree node, flagged, instead of the prefix [0, nh)
+    const uint8_t* ghub = nullptr;
 };
 
 // The adjacency one batched traversal uses: pull over rp/col (in-arcs), push
@@ -398,10 +342,13 @@ struct WeightedShape {
 };
 int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
                   const int32_t* samples_dev, int32_t kg, uint32_t* Dt, const WeightedShape& shape, void* scratch,
-                  size_t scratch_size, int64_t* maxd, TravStats* stats, int persistent_grid);
-// Blocks for the all-rounds cooperative launch on `device` (0 = not available).
-int weighted_persistent_grid(int device);
+                  size_t scratch_size, int64_t* maxd, TravStats* stats);
 size_t sssp_weighted_scratch(int64_t n, int32_t kg);
+// The batched path: every sample's search in its own workgroup of one launch.
+int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
+                          const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
+                          size_t scratch_size, int64_t* maxd, TravStats* stats);
+size_t sssp_wsearch_scratch(int64_t n, int32_t kg);
 
 // ---------------------------------------------------------------- epilogue API
 struct EpilogueArgs {

@@ -395,19 +395,6 @@ __global__ __launch_bounds__(kBlock) void k_wround(WArgs A, int32_t r) {
     wround_body(A, r, S, smax, Wloc, &wcount);
 }
 
-// All rounds in one launch; rounds are separated by a grid barrier.
-__global__ __launch_bounds__(kBlock) void k_wpersist(WArgs A, GridSync* gs, int32_t rmax) {
-    __shared__ Stage S;
-    __shared__ uint32_t smax[kBlock / 64];
-    __shared__ uint64_t Wloc[kStage];
-    __shared__ int32_t wcount;
-    for (int32_t r = 1; r < rmax; r++) {
-        wround_body(A, r, S, smax, Wloc, &wcount);
-        if (!grid_barrier(gs, gridDim.x)) return;
-        if (__hip_atomic_load(&A.dev->ctl[r % 3].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    }
-}
-
 // Rewrites the search's words 2d + f as plain distances (kInf stays) and
 // finds the largest distance and whether any pair was left unreached.
 __global__ void k_wmax(uint32_t* Dt, int64_t count, uint32_t* out, int32_t* unreached) {
@@ -438,6 +425,225 @@ __global__ void k_wmax(uint32_t* Dt, int64_t count, uint32_t* out, int32_t* unre
     if (un) *unreached = 1;
 }
 
+// ---------------------------------------------------------------- one workgroup per sample
+//
+// The batched path runs every sample's search in its own workgroup of one
+// launch: near/far delta-stepping exactly as above (the 2d + f words, a far
+// bit per node), but on one sample's row, with the near pile, the far pile and
+// their counters owned by the workgroup.  Rounds are separated by workgroup
+// barriers instead of launches, so a search costs about one chain of
+// dependent loads and atomics per round (the rounds of a weighted search on a
+// grid number in the thousands, each with a frontier of a few hundred to a
+// few thousand nodes), and the k searches run side by side without any
+// host round trip or cross-workgroup synchronisation.
+constexpr int kSBlock = 1024;   // threads per sample's workgroup
+constexpr int kSmallDeg = 32;   // nodes up to this degree: one lane walks the arcs, 8 at a time
+
+struct SearchBufs {
+    uint32_t* E;      // [kg][n] words 2d + f (the distance rows, decoded afterwards)
+    uint32_t* fbit;   // [kg][ceil(n/32)] far-pile membership
+    int32_t* queues;  // [kg][4][n]: two near piles, two far piles
+    int32_t* status;  // [kg]: 0 done, 4 distance overflow, 5 time limit
+    int32_t* rounds;  // [kg]: rounds run
+};
+
+__device__ __forceinline__ int wave_append(int32_t* cnt_lds, bool pred) {
+    const uint64_t m = __ballot(pred);
+    if (!m) return -1;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(cnt_lds, (int32_t)__popcll(m));
+    base = __shfl(base, leader);
+    return pred ? base + (int)__popcll(m & lanemask_lt()) : -1;
+}
+
+__global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                      const int32_t* __restrict__ wt, int64_t n,
+                                                      const int32_t* __restrict__ samples, SearchBufs B, uint32_t delta,
+                                                      uint64_t time_limit) {
+    const int32_t j = blockIdx.x;
+    uint32_t* E = B.E + (int64_t)j * n;
+    uint32_t* fbit = B.fbit + (int64_t)j * ((n + 31) / 32);
+    int32_t* qbase = B.queues + (int64_t)j * 4 * n;
+    __shared__ int32_t s_cnt[2];  // entries of the next near pile; of the current far pile (cumulative)
+    __shared__ int32_t s_nq, s_nf, s_qsel, s_fsel, s_stop, s_rounds;
+    __shared__ uint32_t s_hi;
+    __shared__ uint32_t s_min[kSBlock / 64];
+    __shared__ int32_t s_ovf;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        const int32_t src = samples[j];
+        E[src] = 0;  // distance 0, in the first near pile
+        qbase[0] = src;  // near pile 0, entry 0
+        s_nq = 1;
+        s_nf = 0;
+        s_qsel = 0;
+        s_fsel = 0;
+        s_hi = delta;
+        s_stop = 0;
+        s_ovf = 0;
+        s_rounds = 0;
+        s_cnt[0] = s_cnt[1] = 0;
+    }
+    __syncthreads();
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        const int32_t nq = s_nq;
+        const uint32_t hi = s_hi;
+        int32_t* qin = qbase + (int64_t)s_qsel * n;
+        int32_t* qout = qbase + (int64_t)(s_qsel ^ 1) * n;
+        int32_t* fpile = qbase + (int64_t)(2 + s_fsel) * n;
+        if (nq > 0) {
+            // ---- a near round: relax every node of the pile
+            for (int32_t base = wave * 64; base < nq; base += kSBlock) {
+                const int32_t t = base + lane;
+                const bool valid = t < nq;
+                const int32_t v = valid ? qin[t] : 0;
+                uint32_t d = 0, b = 0, e = 0;
+                if (valid) {
+                    b = rp[v];
+                    e = rp[v + 1];
+                    d = atomicOr(&E[v], 1u) >> 1;  // leave the pile, read the distance
+                }
+                const uint32_t deg = e - b;
+                // low-degree nodes: each lane its own arcs, eight independent atomics at a time
+                const bool small = valid && deg <= kSmallDeg;
+                uint32_t todo = small ? deg : 0;
+                uint32_t a = b;
+                while (__ballot(todo > 0)) {
+                    int32_t u[8];
+                    uint32_t cand[8], old[8];
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const bool ok = (uint32_t)q < todo;
+                        u[q] = ok ? col[a + q] : -1;
+                        const uint64_t c = ok ? (uint64_t)d + (uint32_t)wt[a + q] : 0;
+                        if (c > kMaxDist) s_ovf = 1;
+                        cand[q] = c > kMaxDist ? kMaxDist : (uint32_t)c;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        old[q] = 0;
+                        if (u[q] >= 0) old[q] = atomicMin(&E[u[q]], cand[q] < hi ? cand[q] << 1 : (cand[q] << 1) | 1u);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const bool near = u[q] >= 0 && cand[q] < hi && (cand[q] << 1) < old[q] && (old[q] & 1u);
+                        bool far = u[q] >= 0 && cand[q] >= hi && ((cand[q] << 1) | 1u) < old[q];
+                        if (far) {
+                            const uint32_t bit = 1u << (u[q] & 31);
+                            far = !(atomicOr(&fbit[u[q] >> 5], bit) & bit);
+                        }
+                        const int pn = wave_append(&s_cnt[0], near);
+                        if (pn >= 0) qout[pn] = u[q];
+                        const int pf = wave_append(&s_cnt[1], far);
+                        if (pf >= 0) fpile[pf] = u[q];
+                    }
+                    const uint32_t step = todo < 8 ? todo : 8;
+                    todo -= step;
+                    a += step;
+                }
+                // high-degree nodes: the whole wave walks the arcs, one per lane
+                uint64_t big = __ballot(valid && deg > kSmallDeg);
+                while (big) {
+                    const int src_lane = __ffsll((unsigned long long)big) - 1;
+                    big &= big - 1;
+                    const uint32_t bb = (uint32_t)__shfl((int)b, src_lane);
+                    const uint32_t be = (uint32_t)__shfl((int)e, src_lane);
+                    const uint32_t bd = (uint32_t)__shfl((int)d, src_lane);
+                    for (uint32_t a0 = bb; a0 < be; a0 += 64) {
+                        const uint32_t ai = a0 + lane;
+                        int32_t u = -1;
+                        uint32_t c = 0, o = 0;
+                        if (ai < be) {
+                            u = col[ai];
+                            const uint64_t c64 = (uint64_t)bd + (uint32_t)wt[ai];
+                            if (c64 > kMaxDist) s_ovf = 1;
+                            c = c64 > kMaxDist ? kMaxDist : (uint32_t)c64;
+                            o = atomicMin(&E[u], c < hi ? c << 1 : (c << 1) | 1u);
+                        }
+                        const bool near = u >= 0 && c < hi && (c << 1) < o && (o & 1u);
+                        bool far = u >= 0 && c >= hi && ((c << 1) | 1u) < o;
+                        if (far) {
+                            const uint32_t bit = 1u << (u & 31);
+                            far = !(atomicOr(&fbit[u >> 5], bit) & bit);
+                        }
+                        const int pn = wave_append(&s_cnt[0], near);
+                        if (pn >= 0) qout[pn] = u;
+                        const int pf = wave_append(&s_cnt[1], far);
+                        if (pf >= 0) fpile[pf] = u;
+                    }
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_nq = s_cnt[0];
+                s_nf = s_cnt[1];
+                s_cnt[0] = 0;
+                s_qsel ^= 1;
+                s_rounds++;
+                if (s_ovf || wall_clock64() - t0 > time_limit) s_stop = 1;
+            }
+            __syncthreads();
+            if (s_stop) break;
+            continue;
+        }
+        // ---- the near pile is empty: split the far pile at the next bucket
+        const int32_t nf = s_nf;
+        if (nf == 0) break;  // uniform: the search is over
+        // the least far distance not below hi (entries below hi were settled
+        // in the rounds of this bucket)
+        uint32_t m = kInf;
+        for (int32_t t = threadIdx.x; t < nf; t += kSBlock) {
+            const uint32_t dv = E[fpile[t]] >> 1;
+            if (dv >= hi && dv < m) m = dv;
+        }
+        m = wave_min_u32(m);
+        if (lane == 0) s_min[wave] = m;
+        if (threadIdx.x == 0) s_cnt[1] = 0;  // the far pile is rebuilt from here
+        __syncthreads();
+        uint32_t mm = kInf;
+        for (int w = 0; w < kSBlock / 64; w++) mm = s_min[w] < mm ? s_min[w] : mm;
+        uint64_t nh = mm == kInf ? (uint64_t)hi : ((uint64_t)mm / delta + 1) * (uint64_t)delta;
+        const uint32_t nhi = nh > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)nh;
+        int32_t* fnext = qbase + (int64_t)(2 + (s_fsel ^ 1)) * n;
+        for (int32_t base = wave * 64; base < nf; base += kSBlock) {
+            const int32_t t = base + lane;
+            const bool valid = t < nf;
+            const int32_t v = valid ? fpile[t] : 0;
+            bool to_near = false, keep = false;
+            if (valid) {
+                const uint32_t dv = E[v] >> 1;
+                if (dv < nhi) {
+                    atomicAnd(&fbit[v >> 5], ~(1u << (v & 31)));
+                    if (dv >= hi) to_near = (atomicAnd(&E[v], ~1u) & 1u) != 0;  // into the near pile
+                } else {
+                    keep = true;
+                }
+            }
+            const int pn = wave_append(&s_cnt[0], to_near);
+            if (pn >= 0) qin[pn] = v;  // the near pile is empty: refill it
+            const int pk = wave_append(&s_cnt[1], keep);
+            if (pk >= 0) fnext[pk] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_nq = s_cnt[0];
+            s_nf = s_cnt[1];
+            s_cnt[0] = 0;
+            s_fsel ^= 1;
+            s_hi = nhi;
+            if (wall_clock64() - t0 > time_limit) s_stop = 1;
+        }
+        __syncthreads();
+        if (s_stop) break;
+    }
+    if (threadIdx.x == 0) {
+        B.status[j] = s_ovf ? 4 : (s_stop ? 5 : 0);
+        B.rounds[j] = s_rounds;
+    }
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
@@ -445,26 +651,81 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t sssp_weighted_scratch(int64_t n, int32_t kg) {
     const int64_t pairs = n * kg;
     return align256(sizeof(WDev)) + align256((size_t)((pairs + 31) / 32) * 4) + 4 * align256((size_t)pairs * 8) +
-           align256(16) + align256(sizeof(GridSync)) + 1024;
+           align256(16) + 1024;
+}
+
+size_t sssp_wsearch_scratch(int64_t n, int32_t kg) {
+    return align256((size_t)kg * ((n + 31) / 32) * 4) + align256((size_t)kg * 4 * n * 4) + 2 * align256((size_t)kg * 4) +
+           align256(16) + 1024;
+}
+
+// The k searches of a batched estimate, one workgroup each (k_wsearch), into
+// Dt[j][v] (device, source-major rows of length n).  Returns 0 = done, 2 =
+// unreached node, 4 = a distance beyond 2^31 - 2, 5 = the time limit expired.
+int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
+                          const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
+                          size_t scratch_size, int64_t* maxd, TravStats* stats) {
+    if (scratch_size < sssp_wsearch_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted_batched scratch"};
+    if (delta < 1) delta = 1;
+    char* p = (char*)scratch;
+    SearchBufs B;
+    B.E = Dt;
+    const int64_t words = (int64_t)kg * ((n + 31) / 32);
+    B.fbit = (uint32_t*)p;
+    p += align256((size_t)words * 4);
+    B.queues = (int32_t*)p;
+    p += align256((size_t)kg * 4 * n * 4);
+    B.status = (int32_t*)p;
+    p += align256((size_t)kg * 4);
+    B.rounds = (int32_t*)p;
+    p += align256((size_t)kg * 4);
+    uint32_t* mx = (uint32_t*)p;
+    const int64_t pairs = n * kg;
+    const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_winit, dim3(gz), dim3(256), 0, st, Dt, pairs);
+    hipLaunchKernelGGL(k_wzero, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0, st,
+                       B.fbit, words);
+    // a search that has not finished after two minutes is stopped and reported
+    int rate_khz = 0, device = 0;
+    CCG_HIP(hipGetDevice(&device));
+    CCG_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device));
+    const uint64_t limit = (uint64_t)std::max(rate_khz, 1) * 120000ull;
+    KernelTimer kt;
+    kt.start(st);
+    hipLaunchKernelGGL(k_wsearch, dim3((unsigned)kg), dim3(kSBlock), 0, st, rp, col, w, n, samples_dev, B, delta, limit);
+    CCG_HIP(hipGetLastError());
+    kt.stop(st);
+    std::vector<int32_t> hs((size_t)kg * 2);
+    CCG_HIP(hipMemcpyAsync(hs.data(), B.status, sizeof(int32_t) * kg, hipMemcpyDeviceToHost, st));
+    CCG_HIP(hipMemcpyAsync(hs.data() + kg, B.rounds, sizeof(int32_t) * kg, hipMemcpyDeviceToHost, st));
+    CCG_HIP(hipStreamSynchronize(st));
+    stats->kernel_ms += kt.ms();
+    stats->kernel_launches += 1;
+    stats->launches += 3;
+    int32_t rmax = 0, bad = 0;
+    for (int32_t q = 0; q < kg; q++) {
+        rmax = std::max(rmax, hs[(size_t)kg + q]);
+        if (hs[(size_t)q] != 0) bad = hs[(size_t)q];
+    }
+    stats->levels += rmax;
+    if (bad) return bad;
+    hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, mx, (int64_t)2);
+    hipLaunchKernelGGL(k_wmax, dim3((unsigned)std::min<int64_t>(gz, 1024)), dim3(256), 0, st, Dt, pairs, mx,
+                       (int32_t*)(mx + 1));
+    uint32_t hm[2];
+    CCG_HIP(hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, st));
+    CCG_HIP(hipStreamSynchronize(st));
+    *maxd = std::max<int64_t>(*maxd, hm[0]);
+    return hm[1] ? 2 : 0;
 }
 
 // Distances from samples[0..kg) (device, internal ids) into Dt[j][v] (device,
-// source-major rows of length n).  Returns 0 = done, 2 = unreached node,
-// 4 = overflow (distance or pile capacity), 5 = a bounded wait expired.
-// persistent_grid > 0 runs every round in one cooperative launch of that
-// many blocks; otherwise (or if the launch is refused) one launch per round.
-
-int weighted_persistent_grid(int device) {
-    int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_wpersist, kBlock, 0) != hipSuccess) return 0;
-    int coop = 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
-    return cus * std::max(1, std::min(per, 2));
-}
+// source-major rows of length n), every round a launch over the whole device
+// (the plain path: one sample per call).  Returns 0 = done, 2 = unreached
+// node, 4 = overflow (distance or pile capacity).
 int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
                   const int32_t* samples_dev, int32_t kg, uint32_t* Dt, const WeightedShape& shape, void* scratch,
-                  size_t scratch_size, int64_t* maxd, TravStats* stats, int persistent_grid) {
+                  size_t scratch_size, int64_t* maxd, TravStats* stats) {
     uint32_t delta = shape.delta;
     if (scratch_size < sssp_weighted_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted scratch"};
     const int64_t pairs = n * kg;
@@ -482,8 +743,6 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     uint64_t* F1 = (uint64_t*)p;
     p += align256((size_t)pairs * 8);
     uint32_t* mx = (uint32_t*)p;
-    p += align256(16);
-    GridSync* gsync = (GridSync*)p;
     if (delta < 1) delta = 1;
 
     const int64_t words = (pairs + 31) / 32;
@@ -502,32 +761,6 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     // pairs means the control state is broken -- stop instead of spinning
     const int64_t max_rounds = std::min<int64_t>(4 * n + 10000, (int64_t)1 << 22);
 
-    // preferred: all rounds in one cooperative (co-resident) launch
-    if (persistent_grid > 0) {
-        hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, (uint32_t*)gsync, (int64_t)(sizeof(GridSync) / 4));
-        int32_t rmax = (int32_t)max_rounds;
-        void* args[] = {&A, &gsync, &rmax};
-        kt.start(st);
-        const hipError_t e = hipLaunchCooperativeKernel((const void*)k_wpersist, dim3(persistent_grid), dim3(kBlock),
-                                                        args, 0, st);
-        if (e == hipSuccess) {
-            kt.stop(st);
-            GridSync gh;
-            CCG_HIP(hipMemcpyAsync(&host, dev, sizeof(WDev), hipMemcpyDeviceToHost, st));
-            CCG_HIP(hipMemcpyAsync(&gh.abort[0], &gsync->abort[0], 4, hipMemcpyDeviceToHost, st));
-            CCG_HIP(hipStreamSynchronize(st));
-            stats->kernel_ms += kt.ms();
-            stats->kernel_launches += 1;
-            stats->launches += 1;
-            if (gh.abort[0]) return 5;
-            if (host.overflow) return 4;
-            bool done = false;
-            for (int q = 0; q < 3; q++) done = done || host.ctl[q].done;
-            if (!done) return 4;
-            goto finished;
-        }
-        (void)hipGetLastError();  // cooperative launch not available: one round per launch
-    }
     {
     int32_t r = 1;
     int batch = 16;
@@ -550,7 +783,6 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
     }
     stats->levels += r - 1;
     }
-finished:
     hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, mx, (int64_t)2);
     hipLaunchKernelGGL(k_wmax, dim3((unsigned)std::min<int64_t>(gz, 1024)), dim3(256), 0, st, Dt, pairs, mx,
                        (int32_t*)(mx + 1));

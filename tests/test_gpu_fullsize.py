@@ -123,7 +123,9 @@ def test_timed_path_replays(ctx):
         out = {f: torch.empty(g.n, dtype=dt[f], device=dev) for f in BENCH_OUT}
         stream = torch.cuda.current_stream()
         replays = 0
-        for seed in (2, 12, 2, 12):
+        # the first call of a seed may capture (a capture is kept for the deepest
+        # level its search reached); the calls after it replay
+        for seed in (2, 2, 2, 12, 12, 12):
             ref = _reference(name, seed)
             for f in out.values():
                 f.fill_(-1)
@@ -134,6 +136,6 @@ def test_timed_path_replays(ctx):
             got = {f: t.cpu().numpy() for f, t in out.items()}
             _say(f"  seed {seed}: checking every node")
             _check(got, ref, BENCH_OUT, f"replay seed {seed}")
-        assert replays >= 3, "the estimates were not replayed from the captured graph"
+        assert replays >= 4, "the estimates were not replayed from the captured graph"
     finally:
         ctx.release(gh)
