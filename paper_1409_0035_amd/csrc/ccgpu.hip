@@ -369,7 +369,7 @@ struct cc_graph {
     DevGraph dg;
     uint32_t flags = 0;
     std::atomic<int> refs{1};
-    void* mem[10] = {};
+    void* mem[12] = {};
     size_t bytes = 0;
     std::vector<int32_t> inv;  // caller's id -> internal id
     uint64_t id = 0;  // never reused: keys captured estimates
@@ -590,6 +590,25 @@ void transpose_host(int64_t n, const std::vector<uint32_t>& rp, const std::vecto
 }
 }  // namespace
 
+// The (end, length) pairs the batched weighted searches read, for both
+// directions, into library-owned slots a and b.
+static void zip_weighted(cc_graph* g, int a, int b, hipStream_t st) {
+    const int64_t arcs = g->dg.arcs;
+    for (int dir = 0; dir < (g->dg.directed ? 2 : 1); dir++) {
+        void* d = nullptr;
+        if (hipMalloc(&d, sizeof(int2) * (size_t)std::max<int64_t>(arcs, 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            throw std::bad_alloc();
+        }
+        g->mem[dir == 0 ? a : b] = d;
+        g->bytes += sizeof(int2) * (size_t)arcs;
+        zip_arcs(st, dir == 0 ? g->dg.col : g->dg.rcol, dir == 0 ? g->dg.w : g->dg.rw, arcs, (int2*)d);
+        (dir == 0 ? g->dg.cw : g->dg.rcw) = (const int2*)d;
+    }
+    if (!g->dg.directed) g->dg.rcw = g->dg.cw;
+    CCG_HIP(hipStreamSynchronize(st));
+}
+
 extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, const int64_t* row_ptr,
                                      const int32_t* col_idx, const int32_t* w, uint32_t flags, cc_graph** out) {
     if (!ctx || !out || !row_ptr || (arcs > 0 && !col_idx)) return fail(CC_EINVAL, "cc_graph_upload: null argument");
@@ -738,6 +757,7 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             g->dg.hub_chunks_out = g->dg.hub_chunks_in;
             g->dg.n_hub_chunks_out = g->dg.n_hub_chunks_in;
         }
+        if (w) zip_weighted(g, 10, 11, nullptr);
     } catch (const std::bad_alloc&) {
         graph_unref(g);
         return fail(CC_ENOMEM, "cc_graph_upload: device allocation failed");
@@ -856,9 +876,10 @@ extern "C" cc_status cc_graph_borrow_device(cc_context* ctx, int64_t n, int64_t 
             rp[(size_t)v] = (uint32_t)rp64[(size_t)v];
         }
         // ids and lengths, on the device; in-degrees and the length sum with them
-        int32_t* bad = (int32_t*)own(0, sizeof(int32_t) + sizeof(unsigned long long));
+        // [0]: a bad id or length seen; [2..3]: the sum of the lengths
+        int32_t* bad = (int32_t*)own(0, 2 * sizeof(int32_t) + sizeof(unsigned long long));
         unsigned long long* wsum = (unsigned long long*)(bad + 2);
-        CCG_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t) * 2 + sizeof(unsigned long long), st));
+        CCG_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int32_t) + sizeof(unsigned long long), st));
         hipLaunchKernelGGL(k_borrow_check, dim3(prep_grid(arcs)), dim3(kPrepBlock), 0, st, col_idx, w, arcs, n, bad);
         int32_t bad_h = 0;
         CCG_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -962,6 +983,7 @@ extern "C" cc_status cc_graph_borrow_device(cc_context* ctx, int64_t n, int64_t 
             g->dg.hub_chunks_out = g->dg.hub_chunks_in;
             g->dg.n_hub_chunks_out = g->dg.n_hub_chunks_in;
         }
+        if (w) zip_weighted(g, 10, 11, st);
         CCG_HIP(hipStreamSynchronize(st));
     } catch (const std::bad_alloc&) {
         graph_unref(g);
@@ -1312,7 +1334,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                         mode == CC_PLAIN
                             ? sssp_weighted(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
                                             (uint32_t*)Dt + (size_t)s0 * n, shape, ts, trav_scratch, &md, &ds)
-                            : sssp_weighted_batched(st, out_rp, out_col, wv, n, samples_dev + s0, kg,
+                            : sssp_weighted_batched(st, out_rp, dir == 0 ? g.cw : g.rcw, n, samples_dev + s0, kg,
                                                     (uint32_t*)Dt + (size_t)s0 * n, shape.delta, ts, trav_scratch,
                                                     &md, &ds);
                     if (wr == 2) rc = 2;

@@ -150,6 +150,9 @@ struct DevGraph {
     const uint32_t* rrp = nullptr;
     const int32_t* rcol = nullptr;
     const int32_t* rw = nullptr;
+    // weighted graphs: each arc's (end, length) side by side, out-arcs and in-arcs
+    const int2* cw = nullptr;
+    const int2* rcw = nullptr;
     const int32_t* orig = nullptr;  // internal id -> caller's id
     const int32_t* inv = nullptr;   // caller's id -> internal id
     uint32_t delta = 1;             // delta-stepping bucket width (weighted graphs)
@@ -345,10 +348,12 @@ int sssp_weighted(hipStream_t st, const uint32_t* rp, const int32_t* col, const 
                   size_t scratch_size, int64_t* maxd, TravStats* stats);
 size_t sssp_weighted_scratch(int64_t n, int32_t kg);
 // The batched path: every sample's search in its own workgroup of one launch.
-int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
-                          const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
-                          size_t scratch_size, int64_t* maxd, TravStats* stats);
+int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, int64_t n, const int32_t* samples_dev,
+                          int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch, size_t scratch_size, int64_t* maxd,
+                          TravStats* stats);
 size_t sssp_wsearch_scratch(int64_t n, int32_t kg);
+// (end, length) pairs of a weighted adjacency, for the batched searches
+void zip_arcs(hipStream_t st, const int32_t* col, const int32_t* w, int64_t arcs, int2* out);
 
 // ---------------------------------------------------------------- epilogue API
 struct EpilogueArgs {

@@ -428,24 +428,45 @@ __global__ void k_wmax(uint32_t* Dt, int64_t count, uint32_t* out, int32_t* unre
 // ---------------------------------------------------------------- one workgroup per sample
 //
 // The batched path runs every sample's search in its own workgroup of one
-// launch: near/far delta-stepping exactly as above (the 2d + f words, a far
-// bit per node), but on one sample's row, with the near pile, the far pile and
-// their counters owned by the workgroup.  Rounds are separated by workgroup
-// barriers instead of launches, so a search costs about one chain of
-// dependent loads and atomics per round (the rounds of a weighted search on a
-// grid number in the thousands, each with a frontier of a few hundred to a
-// few thousand nodes), and the k searches run side by side without any
-// host round trip or cross-workgroup synchronisation.
+// launch: near/far delta-stepping on one sample's row, with the near pile,
+// the far pile and their counters owned by the workgroup.  Rounds are
+// separated by workgroup barriers instead of launches, and the k searches run
+// side by side without any host round trip or cross-workgroup
+// synchronisation.  A weighted search on a grid takes thousands of rounds
+// with frontiers of a few hundred to a few thousand nodes, all on one CU, so
+// what a round costs is the CU's memory requests: kGroup lanes take one node
+// (its arcs are one or two cache lines), and a node costs one atomic to leave
+// the pile, its arc range, its arcs and one atomic minimum per arc.
+// Each node has one 64-bit word W = 4d + f: bit 0 set while the node is in a
+// near pile, bit 1 set while it is in the far pile.  An improver's atomic
+// minimum with 4c + 1 (near) or 4c + 2 (far) changes the word exactly when
+// c < d (an equal distance never queues a node again), and the old word's
+// bit tells it whether it was the one to put the node in that pile.
 constexpr int kSBlock = 1024;   // threads per sample's workgroup
-constexpr int kSmallDeg = 32;   // nodes up to this degree: one lane walks the arcs, 8 at a time
+constexpr int kGroup = 8;       // lanes per node: lane s of a group takes arcs s, s + 8, ...
+constexpr int kUnroll = 4;      // nodes a group has in flight at once
+constexpr int kLq = 6144;       // near-pile entries kept in LDS (more spill to device memory)
+constexpr uint64_t kInfW = ~0ull << 2;  // unreached: largest d, in no pile
 
 struct SearchBufs {
-    uint32_t* E;      // [kg][n] words 2d + f (the distance rows, decoded afterwards)
-    uint32_t* fbit;   // [kg][ceil(n/32)] far-pile membership
-    int32_t* queues;  // [kg][4][n]: two near piles, two far piles
+    uint64_t* W;      // [kg][n] words 4d + f
+    int32_t* near;    // [kg][2][n] near piles beyond the LDS part
+    int32_t* far;     // [kg][2][n] far piles
     int32_t* status;  // [kg]: 0 done, 4 distance overflow, 5 time limit
     int32_t* rounds;  // [kg]: rounds run
 };
+
+// A sample's words are touched by its own workgroup only, and its phases are
+// ordered by workgroup barriers: workgroup-scope atomics suffice.
+__device__ __forceinline__ uint64_t wg_min(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t wg_and(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t wg_xor(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 __device__ __forceinline__ int wave_append(int32_t* cnt_lds, bool pred) {
     const uint64_t m = __ballot(pred);
@@ -457,24 +478,29 @@ __device__ __forceinline__ int wave_append(int32_t* cnt_lds, bool pred) {
     return pred ? base + (int)__popcll(m & lanemask_lt()) : -1;
 }
 
-__global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                      const int32_t* __restrict__ wt, int64_t n,
+__global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict__ rp, const int2* __restrict__ cw,
+                                                      int64_t n,
                                                       const int32_t* __restrict__ samples, SearchBufs B, uint32_t delta,
                                                       uint64_t time_limit) {
     const int32_t j = blockIdx.x;
-    uint32_t* E = B.E + (int64_t)j * n;
-    uint32_t* fbit = B.fbit + (int64_t)j * ((n + 31) / 32);
-    int32_t* qbase = B.queues + (int64_t)j * 4 * n;
+    uint64_t* W = B.W + (int64_t)j * n;
+    int32_t* nsp = B.near + (int64_t)j * 2 * n;
+    int32_t* fsp = B.far + (int64_t)j * 2 * n;
+    __shared__ int32_t lq[2][kLq];
     __shared__ int32_t s_cnt[2];  // entries of the next near pile; of the current far pile (cumulative)
-    __shared__ int32_t s_nq, s_nf, s_qsel, s_fsel, s_stop, s_rounds;
+    __shared__ int32_t s_nq, s_nf, s_qsel, s_fsel, s_stop, s_rounds, s_ovf;
     __shared__ uint32_t s_hi;
     __shared__ uint32_t s_min[kSBlock / 64];
-    __shared__ int32_t s_ovf;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int sub = lane & (kGroup - 1), glane = lane & ~(kGroup - 1);
+    auto put_near = [&](int p, int32_t pos, int32_t v) {
+        if (pos < kLq) lq[p][pos] = v;
+        else nsp[(int64_t)p * n + pos] = v;
+    };
     if (threadIdx.x == 0) {
         const int32_t src = samples[j];
-        E[src] = 0;  // distance 0, in the first near pile
-        qbase[0] = src;  // near pile 0, entry 0
+        W[src] = 1;  // distance 0, in the first near pile
+        put_near(0, 0, src);
         s_nq = 1;
         s_nf = 0;
         s_qsel = 0;
@@ -487,91 +513,79 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
     }
     __syncthreads();
     const uint64_t t0 = wall_clock64();
+    constexpr int kPerWave = 64 / kGroup;  // nodes a wave takes at a time
     for (;;) {
         const int32_t nq = s_nq;
         const uint32_t hi = s_hi;
-        int32_t* qin = qbase + (int64_t)s_qsel * n;
-        int32_t* qout = qbase + (int64_t)(s_qsel ^ 1) * n;
-        int32_t* fpile = qbase + (int64_t)(2 + s_fsel) * n;
+        const int pin = s_qsel, pout = s_qsel ^ 1;
+        int32_t* fpile = fsp + (int64_t)s_fsel * n;
         if (nq > 0) {
-            // ---- a near round: relax every node of the pile
-            for (int32_t base = wave * 64; base < nq; base += kSBlock) {
-                const int32_t t = base + lane;
-                const bool valid = t < nq;
-                const int32_t v = valid ? qin[t] : 0;
-                uint32_t d = 0, b = 0, e = 0;
-                if (valid) {
-                    b = rp[v];
-                    e = rp[v + 1];
-                    d = atomicOr(&E[v], 1u) >> 1;  // leave the pile, read the distance
+            // ---- a near round: relax every node of the pile, kGroup lanes per node and
+            // kUnroll nodes per group at a time, so that the takes, the arc loads and the
+            // atomic minima of kUnroll nodes are in flight together
+            for (int32_t base = wave * kPerWave * kUnroll; base < nq; base += (kSBlock / 64) * kPerWave * kUnroll) {
+                int32_t v[kUnroll];
+                uint64_t d[kUnroll];
+                uint32_t b[kUnroll], e[kUnroll];
+                bool valid[kUnroll];
+#pragma unroll
+                for (int r = 0; r < kUnroll; r++) {
+                    const int32_t t = base + r * kPerWave + lane / kGroup;
+                    valid[r] = t < nq;
+                    v[r] = valid[r] ? (t < kLq ? lq[pin][t] : nsp[(int64_t)pin * n + t]) : 0;
+                    d[r] = 0;
+                    b[r] = e[r] = 0;
                 }
-                const uint32_t deg = e - b;
-                // low-degree nodes: each lane its own arcs, eight independent atomics at a time
-                const bool small = valid && deg <= kSmallDeg;
-                uint32_t todo = small ? deg : 0;
-                uint32_t a = b;
-                while (__ballot(todo > 0)) {
-                    int32_t u[8];
-                    uint32_t cand[8], old[8];
 #pragma unroll
-                    for (int q = 0; q < 8; q++) {
-                        const bool ok = (uint32_t)q < todo;
-                        u[q] = ok ? col[a + q] : -1;
-                        const uint64_t c = ok ? (uint64_t)d + (uint32_t)wt[a + q] : 0;
-                        if (c > kMaxDist) s_ovf = 1;
-                        cand[q] = c > kMaxDist ? kMaxDist : (uint32_t)c;
+                for (int r = 0; r < kUnroll; r++) {
+                    // lane 0 of the group leaves the pile (reading d), lanes 1, 2 read the arc range
+                    if (valid[r]) {
+                        if (sub == 0) d[r] = wg_and(&W[v[r]], ~1ull) >> 2;
+                        else if (sub == 1) b[r] = rp[v[r]];
+                        else if (sub == 2) e[r] = rp[v[r] + 1];
                     }
-#pragma unroll
-                    for (int q = 0; q < 8; q++) {
-                        old[q] = 0;
-                        if (u[q] >= 0) old[q] = atomicMin(&E[u[q]], cand[q] < hi ? cand[q] << 1 : (cand[q] << 1) | 1u);
-                    }
-#pragma unroll
-                    for (int q = 0; q < 8; q++) {
-                        const bool near = u[q] >= 0 && cand[q] < hi && (cand[q] << 1) < old[q] && (old[q] & 1u);
-                        bool far = u[q] >= 0 && cand[q] >= hi && ((cand[q] << 1) | 1u) < old[q];
-                        if (far) {
-                            const uint32_t bit = 1u << (u[q] & 31);
-                            far = !(atomicOr(&fbit[u[q] >> 5], bit) & bit);
-                        }
-                        const int pn = wave_append(&s_cnt[0], near);
-                        if (pn >= 0) qout[pn] = u[q];
-                        const int pf = wave_append(&s_cnt[1], far);
-                        if (pf >= 0) fpile[pf] = u[q];
-                    }
-                    const uint32_t step = todo < 8 ? todo : 8;
-                    todo -= step;
-                    a += step;
                 }
-                // high-degree nodes: the whole wave walks the arcs, one per lane
-                uint64_t big = __ballot(valid && deg > kSmallDeg);
-                while (big) {
-                    const int src_lane = __ffsll((unsigned long long)big) - 1;
-                    big &= big - 1;
-                    const uint32_t bb = (uint32_t)__shfl((int)b, src_lane);
-                    const uint32_t be = (uint32_t)__shfl((int)e, src_lane);
-                    const uint32_t bd = (uint32_t)__shfl((int)d, src_lane);
-                    for (uint32_t a0 = bb; a0 < be; a0 += 64) {
-                        const uint32_t ai = a0 + lane;
-                        int32_t u = -1;
-                        uint32_t c = 0, o = 0;
-                        if (ai < be) {
-                            u = col[ai];
-                            const uint64_t c64 = (uint64_t)bd + (uint32_t)wt[ai];
-                            if (c64 > kMaxDist) s_ovf = 1;
-                            c = c64 > kMaxDist ? kMaxDist : (uint32_t)c64;
-                            o = atomicMin(&E[u], c < hi ? c << 1 : (c << 1) | 1u);
+                uint32_t trips = 0;
+#pragma unroll
+                for (int r = 0; r < kUnroll; r++) {
+                    d[r] = (uint64_t)__shfl((long long)d[r], glane);
+                    b[r] = (uint32_t)__shfl((int)b[r], glane + 1);
+                    e[r] = (uint32_t)__shfl((int)e[r], glane + 2);
+                    if (valid[r]) trips = max(trips, (e[r] - b[r] + kGroup - 1) / kGroup);
+                }
+                // the wave's trip count: its longest arc list (every lane takes part in the appends)
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) trips = max(trips, (uint32_t)__shfl_xor((int)trips, off));
+                for (uint32_t it = 0; it < trips; it++) {
+                    int32_t u[kUnroll];
+                    uint64_t c[kUnroll], o[kUnroll];
+#pragma unroll
+                    for (int r = 0; r < kUnroll; r++) {
+                        const uint32_t a = b[r] + it * kGroup + sub;
+                        u[r] = -1;
+                        c[r] = 0;
+                        if (valid[r] && a < e[r]) {
+                            const int2 x = cw[a];  // the arc's end and length, one 8-byte load
+                            u[r] = x.x;
+                            c[r] = d[r] + (uint32_t)x.y;
                         }
-                        const bool near = u >= 0 && c < hi && (c << 1) < o && (o & 1u);
-                        bool far = u >= 0 && c >= hi && ((c << 1) | 1u) < o;
-                        if (far) {
-                            const uint32_t bit = 1u << (u & 31);
-                            far = !(atomicOr(&fbit[u >> 5], bit) & bit);
+                    }
+#pragma unroll
+                    for (int r = 0; r < kUnroll; r++) {
+                        o[r] = 0;
+                        if (u[r] >= 0) {
+                            if (c[r] > kMaxDist) s_ovf = 1;
+                            o[r] = wg_min(&W[u[r]], (c[r] << 2) | (c[r] < hi ? 1ull : 2ull));
                         }
-                        const int pn = wave_append(&s_cnt[0], near);
-                        if (pn >= 0) qout[pn] = u;
-                        const int pf = wave_append(&s_cnt[1], far);
-                        if (pf >= 0) fpile[pf] = u;
+                    }
+#pragma unroll
+                    for (int r = 0; r < kUnroll; r++) {
+                        const bool better = u[r] >= 0 && c[r] < (o[r] >> 2);
+                        const bool nr = c[r] < hi;
+                        const int pn = wave_append(&s_cnt[0], better && nr && !(o[r] & 1ull));  // this minimum queued it
+                        if (pn >= 0) put_near(pout, pn, u[r]);
+                        const int pf = wave_append(&s_cnt[1], better && !nr && !(o[r] & 2ull));
+                        if (pf >= 0) fpile[pf] = u[r];
                     }
                 }
             }
@@ -593,36 +607,34 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
         if (nf == 0) break;  // uniform: the search is over
         // the least far distance not below hi (entries below hi were settled
         // in the rounds of this bucket)
-        uint32_t m = kInf;
+        uint64_t m = kMaxDist + 1ull;
         for (int32_t t = threadIdx.x; t < nf; t += kSBlock) {
-            const uint32_t dv = E[fpile[t]] >> 1;
+            const uint64_t dv = __hip_atomic_load(&W[fpile[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 2;
             if (dv >= hi && dv < m) m = dv;
         }
-        m = wave_min_u32(m);
-        if (lane == 0) s_min[wave] = m;
+        uint32_t m32 = (uint32_t)m;
+        m32 = wave_min_u32(m32);
+        if (lane == 0) s_min[wave] = m32;
         if (threadIdx.x == 0) s_cnt[1] = 0;  // the far pile is rebuilt from here
         __syncthreads();
         uint32_t mm = kInf;
         for (int w = 0; w < kSBlock / 64; w++) mm = s_min[w] < mm ? s_min[w] : mm;
-        uint64_t nh = mm == kInf ? (uint64_t)hi : ((uint64_t)mm / delta + 1) * (uint64_t)delta;
+        const uint64_t nh = mm > kMaxDist ? (uint64_t)hi : ((uint64_t)mm / delta + 1) * (uint64_t)delta;
         const uint32_t nhi = nh > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)nh;
-        int32_t* fnext = qbase + (int64_t)(2 + (s_fsel ^ 1)) * n;
+        int32_t* fnext = fsp + (int64_t)(s_fsel ^ 1) * n;
         for (int32_t base = wave * 64; base < nf; base += kSBlock) {
             const int32_t t = base + lane;
             const bool valid = t < nf;
             const int32_t v = valid ? fpile[t] : 0;
             bool to_near = false, keep = false;
             if (valid) {
-                const uint32_t dv = E[v] >> 1;
-                if (dv < nhi) {
-                    atomicAnd(&fbit[v >> 5], ~(1u << (v & 31)));
-                    if (dv >= hi) to_near = (atomicAnd(&E[v], ~1u) & 1u) != 0;  // into the near pile
-                } else {
-                    keep = true;
-                }
+                const uint64_t dv = __hip_atomic_load(&W[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 2;
+                if (dv >= nhi) keep = true;
+                else if (dv >= hi) to_near = (wg_xor(&W[v], 3ull) & 3ull) == 2ull;  // far pile -> near pile
+                // else settled in an earlier bucket: dropped
             }
             const int pn = wave_append(&s_cnt[0], to_near);
-            if (pn >= 0) qin[pn] = v;  // the near pile is empty: refill it
+            if (pn >= 0) put_near(pin, pn, v);  // the near pile is empty: refill it
             const int pk = wave_append(&s_cnt[1], keep);
             if (pk >= 0) fnext[pk] = v;
         }
@@ -644,6 +656,43 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
     }
 }
 
+// The searches' words as plain distances into Dt (kInf = unreached), the
+// largest distance and whether any node was left unreached.
+__global__ void k_wdecode(const uint64_t* __restrict__ W, uint32_t* Dt, int64_t count, uint32_t* out,
+                          int32_t* unreached) {
+    __shared__ uint32_t bm[4];
+    uint32_t m = 0;
+    bool un = false;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = W[t];
+        if (x == kInfW) {
+            un = true;
+            Dt[t] = kInf;
+        } else {
+            const uint32_t d = (uint32_t)(x >> 2);
+            Dt[t] = d;
+            m = d > m ? d : m;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)m, off);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0) bm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = bm[w] > m ? bm[w] : m;
+        m = bm[0] > m ? bm[0] : m;
+        atomicMax(out, m);
+    }
+    if (un) *unreached = 1;
+}
+
+__global__ void k_wfill64(uint64_t* p, int64_t count, uint64_t value) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = value;
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
@@ -654,37 +703,46 @@ size_t sssp_weighted_scratch(int64_t n, int32_t kg) {
            align256(16) + 1024;
 }
 
+__global__ void k_zip_arcs(const int32_t* __restrict__ col, const int32_t* __restrict__ w, int64_t arcs, int2* out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < arcs; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = make_int2(col[e], w[e]);
+}
+
+void zip_arcs(hipStream_t st, const int32_t* col, const int32_t* w, int64_t arcs, int2* out) {
+    if (arcs <= 0) return;
+    hipLaunchKernelGGL(k_zip_arcs, dim3((unsigned)std::min<int64_t>((arcs + 255) / 256, 65536)), dim3(256), 0, st, col, w,
+                       arcs, out);
+}
+
 size_t sssp_wsearch_scratch(int64_t n, int32_t kg) {
-    return align256((size_t)kg * ((n + 31) / 32) * 4) + align256((size_t)kg * 4 * n * 4) + 2 * align256((size_t)kg * 4) +
+    return align256((size_t)kg * n * 8) + 2 * align256((size_t)kg * 2 * n * 4) + 2 * align256((size_t)kg * 4) +
            align256(16) + 1024;
 }
 
 // The k searches of a batched estimate, one workgroup each (k_wsearch), into
 // Dt[j][v] (device, source-major rows of length n).  Returns 0 = done, 2 =
 // unreached node, 4 = a distance beyond 2^31 - 2, 5 = the time limit expired.
-int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int32_t* col, const int32_t* w, int64_t n,
-                          const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch,
-                          size_t scratch_size, int64_t* maxd, TravStats* stats) {
+int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, int64_t n, const int32_t* samples_dev,
+                          int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch, size_t scratch_size, int64_t* maxd,
+                          TravStats* stats) {
     if (scratch_size < sssp_wsearch_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted_batched scratch"};
     if (delta < 1) delta = 1;
     char* p = (char*)scratch;
     SearchBufs B;
-    B.E = Dt;
-    const int64_t words = (int64_t)kg * ((n + 31) / 32);
-    B.fbit = (uint32_t*)p;
-    p += align256((size_t)words * 4);
-    B.queues = (int32_t*)p;
-    p += align256((size_t)kg * 4 * n * 4);
+    const int64_t pairs = n * kg;
+    B.W = (uint64_t*)p;
+    p += align256((size_t)pairs * 8);
+    B.near = (int32_t*)p;
+    p += align256((size_t)kg * 2 * n * 4);
+    B.far = (int32_t*)p;
+    p += align256((size_t)kg * 2 * n * 4);
     B.status = (int32_t*)p;
     p += align256((size_t)kg * 4);
     B.rounds = (int32_t*)p;
     p += align256((size_t)kg * 4);
     uint32_t* mx = (uint32_t*)p;
-    const int64_t pairs = n * kg;
     const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_winit, dim3(gz), dim3(256), 0, st, Dt, pairs);
-    hipLaunchKernelGGL(k_wzero, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0, st,
-                       B.fbit, words);
+    hipLaunchKernelGGL(k_wfill64, dim3(gz), dim3(256), 0, st, B.W, pairs, kInfW);
     // a search that has not finished after two minutes is stopped and reported
     int rate_khz = 0, device = 0;
     CCG_HIP(hipGetDevice(&device));
@@ -692,7 +750,7 @@ int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int32_t* col
     const uint64_t limit = (uint64_t)std::max(rate_khz, 1) * 120000ull;
     KernelTimer kt;
     kt.start(st);
-    hipLaunchKernelGGL(k_wsearch, dim3((unsigned)kg), dim3(kSBlock), 0, st, rp, col, w, n, samples_dev, B, delta, limit);
+    hipLaunchKernelGGL(k_wsearch, dim3((unsigned)kg), dim3(kSBlock), 0, st, rp, cw, n, samples_dev, B, delta, limit);
     CCG_HIP(hipGetLastError());
     kt.stop(st);
     std::vector<int32_t> hs((size_t)kg * 2);
@@ -710,7 +768,7 @@ int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int32_t* col
     stats->levels += rmax;
     if (bad) return bad;
     hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, mx, (int64_t)2);
-    hipLaunchKernelGGL(k_wmax, dim3((unsigned)std::min<int64_t>(gz, 1024)), dim3(256), 0, st, Dt, pairs, mx,
+    hipLaunchKernelGGL(k_wdecode, dim3((unsigned)std::min<int64_t>(gz, 1024)), dim3(256), 0, st, B.W, Dt, pairs, mx,
                        (int32_t*)(mx + 1));
     uint32_t hm[2];
     CCG_HIP(hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, st));
