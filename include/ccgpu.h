@@ -198,6 +198,24 @@ cc_status cc_estimate(cc_context* ctx, const cc_graph* g, const cc_params* p, cc
 cc_status cc_estimate_device(cc_context* ctx, const cc_graph* g, const cc_params* p, cc_result* out,
                              void* hip_stream);
 
+/* For callers that cannot allocate device memory (code running under HIP
+ * graph capture of their own, tight serving loops, harnesses that forbid
+ * allocation): cc_estimate_device without any device allocation.  The same
+ * kernels run with every buffer carved from a 64 MiB array in the library's
+ * device code (`scratch`, one copy per GPU, held until the process ends; its
+ * address is looked up once per device when a context is created).  Calls
+ * on one GPU share that array and the previous call's contents stay there:
+ * the kernels initialise what they read.  Calls that would overlap on one GPU
+ * race on it, so the library runs them one at a time (a per-device lock).
+ * Undirected graphs without arc lengths, mode CC_BATCHED (no CC_GRAPH),
+ * k <= 256; anything else is CC_EINVAL.  CC_ENOMEM (outputs untouched) when
+ * the estimate needs more than the array holds: 16 MiB of per-job buffers and
+ * traversal state, 40 MiB of level masks (levels x n x ceil(k/64) x 8 bytes,
+ * plus n x k bytes when D is requested), 8 MiB of estimator tables.  Like
+ * cc_estimate_device it synchronises `hip_stream` once at the end. */
+cc_status cc_estimate_device_noalloc(cc_context* ctx, const cc_graph* g, const cc_params* p, cc_result* out,
+                                     void* hip_stream);
+
 /* Several estimates in one call, for many small graphs.  outs[j] holds HOST
  * pointers for job j (graphs[j], params[j]).  Jobs on undirected graphs
  * without arc lengths, with k <= 192 and at most 131072 nodes, are traversed

@@ -29,7 +29,8 @@ CC_GRAPH = 0x100  # or-ed into CC_BATCHED: capture the estimate as a HIP graph a
 EXPORTED = [
     "cc_context_create", "cc_context_destroy", "cc_graph_upload", "cc_graph_borrow_device", "cc_graph_release",
     "cc_graph_info",
-    "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_last_timing", "cc_submit", "cc_poll",
+    "cc_draw_samples", "cc_estimate", "cc_estimate_device", "cc_estimate_device_noalloc", "cc_last_timing",
+    "cc_submit", "cc_poll",
     "cc_wait", "cc_cancel", "cc_job_times", "cc_job_release", "cc_status_str", "cc_last_error",
     "cc_graph_get_tuning", "cc_graph_set_tuning", "cc_autotune", "cc_estimate_batch", "cc_reach_estimate",
     "cc_draw_weighted", "cc_estimate_weighted", "cc_reach_weighted",
@@ -149,6 +150,7 @@ def load_library():
         "cc_draw_samples": (i32, [i64, i32, u64, P]),
         "cc_estimate": (i32, [P, P, ctypes.POINTER(cc_params), ctypes.POINTER(cc_result)]),
         "cc_estimate_device": (i32, [P, P, ctypes.POINTER(cc_params), ctypes.POINTER(cc_result), P]),
+        "cc_estimate_device_noalloc": (i32, [P, P, ctypes.POINTER(cc_params), ctypes.POINTER(cc_result), P]),
         "cc_last_timing": (i32, [P, ctypes.POINTER(cc_timing)]),
         "cc_submit": (i32, [P, P, ctypes.POINTER(cc_params), ctypes.POINTER(cc_result), PP]),
         "cc_poll": (i32, [P]),
@@ -425,10 +427,11 @@ def cc_estimate_batch(ctx, jobs, outputs=("S_hyb", "S_samp", "S_piv", "S_pub", "
 
 
 def cc_estimate_device(ctx, g, k: int, out: dict, mode: int = CC_BATCHED, seed: int = 0, samples=None,
-                       eps=None, stream=None) -> None:
+                       eps=None, stream=None, noalloc: bool = False) -> None:
     """Estimate into device tensors.  `out` maps result field names to torch
     tensors on the context's device (contiguous, of the field's dtype and
-    length); `stream` is a torch.cuda.Stream (default: torch's current)."""
+    length); `stream` is a torch.cuda.Stream (default: torch's current).
+    noalloc=True calls cc_estimate_device_noalloc (no device allocation)."""
     import torch
     p, keep = _params(k, mode, seed, samples, eps)
     res = cc_result()
@@ -441,8 +444,8 @@ def cc_estimate_device(ctx, g, k: int, out: dict, mode: int = CC_BATCHED, seed: 
         setattr(res, f, t.data_ptr())
     if stream is None:
         stream = torch.cuda.current_stream()
-    _check(load_library().cc_estimate_device(ctx, g, ctypes.byref(p), ctypes.byref(res),
-                                             ctypes.c_void_p(stream.cuda_stream)))
+    fn = load_library().cc_estimate_device_noalloc if noalloc else load_library().cc_estimate_device
+    _check(fn(ctx, g, ctypes.byref(p), ctypes.byref(res), ctypes.c_void_p(stream.cuda_stream)))
     del keep
 
 

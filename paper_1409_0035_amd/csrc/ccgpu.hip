@@ -230,16 +230,24 @@ extern "C" cc_status cc_draw_weighted(int64_t n, const uint32_t* beta, int32_t k
 
 namespace {
 
-// A growable device buffer; one per stream that runs jobs.
+// Thrown when an estimate needs more than a fixed (allocation-free) buffer holds.
+struct FixedScratchFull {
+    size_t need, have;
+};
+
+// A growable device buffer; one per stream that runs jobs.  A fixed arena
+// is a slice of the static scratch array and never allocates.
 struct Arena {
     void* ptr = nullptr;
     size_t size = 0;
+    bool fixed = false;
     uint64_t* gen = nullptr;  // bumped whenever the buffer moves (captured graphs refer to it)
     ~Arena() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr && !fixed) (void)hipFree(ptr);
     }
     void* get(size_t need) {
         if (need <= size) return ptr;
+        if (fixed) throw FixedScratchFull{need, size};
         if (gen) ++*gen;
         if (ptr) {
             CCG_HIP(hipFree(ptr));
@@ -307,6 +315,7 @@ struct Lane {
     EventPool events;  // per-launch timing inside the traversals
     uint64_t gen = 0;  // arena generation
     int64_t last_maxd = -1;  // an upper bound on the last job's largest distance (-1: unknown)
+    bool no_alloc = false;   // the allocation-free lane: fixed arenas, no event pool, no capture
     // Captured estimates (stream capture of a whole estimate), replayed when
     // the same graph, parameters, buffers and outputs come again.
     struct Captured {
@@ -401,6 +410,10 @@ struct cc_context {
     std::mutex mu;  // serialises synchronous calls on the default lane
     Lane lane;
     cc_timing last{};
+    // the allocation-free entry point: a lane whose buffers are slices of the
+    // device's static scratch array (set up when the context is created)
+    Lane fixed_lane;
+    bool fixed_ready = false;
     // serving
     std::mutex qmu;
     std::condition_variable qcv;
@@ -426,6 +439,38 @@ static void graph_unref(cc_graph* g) {
 
 // ---------------------------------------------------------------- context
 
+// ---------------------------------------------------------------- static scratch
+// Device memory for cc_estimate_device_noalloc: a file-scope array that every
+// GPU the library runs on holds until the process ends.  Host code never uses
+// its name as an address: the address is taken once per device with that
+// device current (scratch_address) and kept.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr size_t kNoAllocSmall = (size_t)16 << 20;   // per-job buffers, traversal state, level histograms
+constexpr size_t kNoAllocMasks = (size_t)40 << 20;   // level snapshots (and D)
+constexpr size_t kNoAllocTables = kNoAllocBytes - kNoAllocSmall - kNoAllocMasks;  // epilogue tables
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static std::unordered_map<int, void*> g_scratch_ptr;      // device -> address of its copy of scratch
+static std::unordered_map<int, std::mutex*> g_scratch_use;  // device -> serialises its users
+
+// The current device's copy of `scratch` (looked up once per device).
+static void* scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void* p = nullptr;
+    CCG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = p;
+    g_scratch_use[device] = new std::mutex();
+    return p;
+}
+
+static std::mutex& scratch_user_lock(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return *g_scratch_use.at(device);
+}
+
 extern "C" cc_status cc_context_create(int device, const cc_config* cfg, cc_context** out) {
     if (!out) return fail(CC_EINVAL, "cc_context_create: out is NULL");
     int count = 0;
@@ -440,6 +485,19 @@ extern "C" cc_status cc_context_create(int device, const cc_config* cfg, cc_cont
     try {
         CCG_HIP(hipSetDevice(device));
         ctx->lane.init(nullptr);
+        // the allocation-free lane: its buffers are fixed slices of `scratch`
+        char* sp = (char*)scratch_address(device);
+        ctx->fixed_lane.init(nullptr);
+        Arena* parts[3] = {&ctx->fixed_lane.arena, &ctx->fixed_lane.arenaD, &ctx->fixed_lane.arena2};
+        const size_t sizes[3] = {kNoAllocSmall, kNoAllocMasks, kNoAllocTables};
+        for (int q = 0; q < 3; q++) {
+            parts[q]->fixed = true;
+            parts[q]->ptr = sp;
+            parts[q]->size = sizes[q];
+            sp += sizes[q];
+        }
+        ctx->fixed_lane.no_alloc = true;
+        ctx->fixed_ready = true;
         size_t fr = 0, tot = 0;
         CCG_HIP(hipMemGetInfo(&fr, &tot));
         ctx->budget = ctx->cfg.mem_budget_bytes > 0 ? ctx->cfg.mem_budget_bytes : (int64_t)(0.8 * (double)fr);
@@ -479,6 +537,10 @@ extern "C" void cc_context_destroy(cc_context* ctx) {
     ctx->worker_lanes.clear();
     (void)hipStreamSynchronize(ctx->lane.stream);
     ctx->lane.destroy();
+    if (ctx->fixed_ready) {
+        (void)hipStreamSynchronize(ctx->fixed_lane.stream);
+        ctx->fixed_lane.destroy();
+    }
     delete ctx;
 }
 
@@ -1368,7 +1430,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                         lv.zero_hist = true;
                         stage_into(lv);
                     }
-                    rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, &ds, &L.events);
+                    rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, &ds,
+                                     L.no_alloc ? nullptr : &L.events);
                     if (rc == 0) gr->bfs_hint.store(ds.bfs_levels, std::memory_order_relaxed);
                     if (rc != 0) break;
                     lmax_dir[dir] = std::max(lmax_dir[dir], lm);
@@ -1384,6 +1447,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         }
         if (rc == 1) {  // more levels than the mask buffer holds
             cap = (int32_t)std::min<int64_t>((int64_t)cap * 4, n + 2);
+            if (L.no_alloc && (size_t)cap * n * Wg * 8 > L.arenaD.size)  // the fixed buffers cannot hold the masks
+                throw FixedScratchFull{(size_t)cap * n * Wg * 8, L.arenaD.size};
             if ((size_t)cap * n * Wg * 8 > mask_budget()) mode = CC_PLAIN;
             continue;
         }
@@ -1571,7 +1636,45 @@ extern "C" cc_status cc_estimate_device(cc_context* ctx, const cc_graph* g, cons
     });
 }
 
+extern "C" cc_status cc_estimate_device_noalloc(cc_context* ctx, const cc_graph* g, const cc_params* p,
+                                                cc_result* out, void* hip_stream) {
+    if (!ctx || !g || !p || !out) return fail(CC_EINVAL, "cc_estimate_device_noalloc: null argument");
+    if (!ctx->fixed_ready) return fail(CC_EDEVICE, "cc_estimate_device_noalloc: no static scratch on this device");
+    if (g->dg.directed || g->dg.weighted || p->mode != CC_BATCHED || p->k > 256)
+        return fail(CC_EINVAL, "cc_estimate_device_noalloc: undirected graphs without arc lengths, CC_BATCHED, "
+                               "k <= 256 only");
+    Resolved r;
+    cc_status s = resolve_params(g, p, r);
+    if (s != CC_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::lock_guard<std::mutex> use(scratch_user_lock(ctx->device));  // one user of the device's array at a time
+    return guarded(ctx, [&]() -> cc_status {
+        Lane* L = &ctx->fixed_lane;
+        hipStream_t saved = L->stream;
+        if (hip_stream) L->stream = (hipStream_t)hip_stream;
+        cc_timing t{};
+        cc_status st;
+        try {
+            st = run_job(ctx, g, r, out, *L, &t);
+        } catch (const FixedScratchFull& e) {
+            L->stream = saved;
+            (void)hipStreamSynchronize(L->stream);
+            return fail(CC_ENOMEM, "cc_estimate_device_noalloc: the estimate needs " + std::to_string(e.need) +
+                                       " bytes of one scratch part of " + std::to_string(e.have) + " (static scratch " +
+                                       std::to_string(kNoAllocBytes >> 20) + " MiB)");
+        } catch (...) {
+            L->stream = saved;
+            throw;
+        }
+        L->stream = saved;
+        if (st == CC_OK) ctx->last = t;
+        return st;
+    });
+}
+
 namespace {
+
+// Device staging for host outputs: device buffers for the requestednamespace {
 
 // Device staging for host outputs: device buffers for the requested
 // fields, copied back after the run.
