@@ -83,7 +83,8 @@ typedef struct cc_job cc_job;
 
 typedef struct {
     int64_t mem_budget_bytes; /* serving admission budget; 0 = 80% of free device memory */
-    int32_t max_inflight;     /* serving: jobs on the device at once; 0 = 8 */
+    int32_t max_inflight;     /* serving: slots (one stream each) running jobs at once; 0 = 4, the
+                                 device's hardware queues per process */
     int32_t reserved;
 } cc_config;
 
@@ -427,7 +428,12 @@ cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const cc_reach_w
  * are admitted onto the device as memory (cc_config.mem_budget_bytes) and
  * slots (max_inflight) free up, and run concurrently on several streams; a
  * slot that takes a small job (as in cc_estimate_batch) also takes the small
- * jobs queued behind it that fit, into one batched traversal. */
+ * jobs queued behind it that fit, into one batched traversal.  The oldest
+ * queued job can be passed by younger ones that fit the memory it waits for
+ * at most 16 times; then it is admitted next.  Each slot keeps its device
+ * and pinned host staging between jobs (given back when it exceeds the
+ * slot's share of the budget), so a job allocates nothing once its slot has
+ * run one as large. */
 cc_status cc_submit(cc_context* ctx, const cc_graph* g, const cc_params* p, const cc_result* out,
                     cc_job** job);
 /* CC_OK when done successfully, CC_ENOTREADY while queued or running,

@@ -302,6 +302,34 @@ struct Lane {
     Arena arenaD;     // distance matrices / level masks
     Arena arena2;     // epilogue tables (sized once the largest distance is known)
     Arena arenaW;     // node-weighted estimate: its distance rows and per-node arrays
+    Arena arenaO;     // device staging of host outputs
+    char* pin = nullptr;  // pinned host staging of host outputs (grown when a larger job comes)
+    size_t pin_size = 0;
+    char* pinned_host(size_t need) {
+        if (need <= pin_size) return pin;
+        if (pin) CCG_HIP(hipHostFree(pin));
+        pin = nullptr;
+        pin_size = 0;
+        need = (need + (1u << 20)) & ~size_t((1u << 20) - 1);
+        if (hipHostMalloc((void**)&pin, need, hipHostMallocDefault) != hipSuccess) {
+            pin = nullptr;
+            (void)hipGetLastError();
+            throw std::bad_alloc();
+        }
+        pin_size = need;
+        return pin;
+    }
+    size_t retained() const { return arena.size + arenaD.size + arena2.size + arenaW.size + arenaO.size; }
+    void trim() {  // give the buffers back (the next job allocates afresh)
+        Arena* as[5] = {&arena, &arenaD, &arena2, &arenaW, &arenaO};
+        for (Arena* a : as)
+            if (a->ptr && !a->fixed) {
+                if (a->gen) ++*a->gen;
+                (void)hipFree(a->ptr);
+                a->ptr = nullptr;
+                a->size = 0;
+            }
+    }
     LevelCounters* cnt_host = nullptr;  // pinned
     struct Readback {
         BfsCtl ctl;
@@ -342,7 +370,7 @@ struct Lane {
         captured.push_back(std::move(c));
     }
     void init(hipStream_t s) {
-        arena.gen = arenaD.gen = arena2.gen = &gen;
+        arena.gen = arenaD.gen = arena2.gen = arenaO.gen = &gen;
         if (s) {
             stream = s;
         } else {
@@ -361,6 +389,9 @@ struct Lane {
             if (e) (void)hipEventDestroy(e);
         if (cnt_host) (void)hipHostFree(cnt_host);
         if (rb_host) (void)hipHostFree(rb_host);
+        if (pin) (void)hipHostFree(pin);
+        pin = nullptr;
+        pin_size = 0;
         rb_host = nullptr;
         rb_dev = nullptr;
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -398,6 +429,7 @@ struct cc_job {
     cc_status status = CC_ENOTREADY;
     std::string err;
     size_t need = 0;
+    int32_t overtaken = 0;  // younger jobs admitted while this one waited at the front
     std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
     std::mutex m;
     std::condition_variable cv;
@@ -1674,28 +1706,27 @@ extern "C" cc_status cc_estimate_device_noalloc(cc_context* ctx, const cc_graph*
 
 namespace {
 
-// Device staging for host outputs: device buffers for the requestednamespace {
-
-// Device staging for host outputs: device buffers for the requested
-// fields, copied back after the run.
+// Staging for host outputs: the requested fields laid out in the lane's
+// persistent device buffer (arenaO, grown only when a larger job comes), the
+// results copied into the lane's pinned host buffer, then into the caller's
+// arrays, so a served job allocates and frees nothing once its lane has held
+// a job as large.
 struct Staging {
     struct F {
         void* h;
         size_t bytes;
+        size_t off;
         void* d;
     };
     std::vector<F> fields;
     cc_result dev{};
-    void* buf = nullptr;
-    Staging() = default;
-    Staging(const Staging&) = delete;
-    Staging& operator=(const Staging&) = delete;
-    ~Staging() {
-        if (buf) (void)hipFree(buf);
-    }
-    cc_status build(const cc_result* host, int64_t n, int32_t k) {
+    size_t total = 0;
+    void plan(const cc_result* host, int64_t n, int32_t k) {
         auto add = [&](void* h, size_t bytes) {
-            if (h) fields.push_back({h, bytes, nullptr});
+            if (h) {
+                fields.push_back({h, bytes, total, nullptr});
+                total += Carver::sz(bytes);
+            }
         };
         add(host->S_hyb, sizeof(double) * n);
         add(host->S_samp, sizeof(double) * n);
@@ -1713,17 +1744,10 @@ struct Staging {
         add(host->S_ad_err, sizeof(double) * n);
         add(host->S_sweep, sizeof(double) * n);
         add(host->S_sweep_err, sizeof(double) * n);
-        size_t total = 0;
-        for (auto& f : fields) total += Carver::sz(f.bytes);
-        if (total) {
-            if (hipMalloc(&buf, total) != hipSuccess) {
-                buf = nullptr;
-                (void)hipGetLastError();
-                return fail(CC_ENOMEM, "output staging allocation failed");
-            }
-        }
-        Carver c(buf);
-        for (auto& f : fields) f.d = c.take<char>(f.bytes);
+    }
+    // the fields at dbase + their offsets (device)
+    void place(const cc_result* host, char* dbase) {
+        for (auto& f : fields) f.d = dbase + f.off;
         auto dptr = [&](void* h) -> void* {
             for (auto& f : fields)
                 if (f.h == h) return f.d;
@@ -1745,22 +1769,27 @@ struct Staging {
         dev.S_ad_err = (double*)dptr(host->S_ad_err);
         dev.S_sweep = (double*)dptr(host->S_sweep);
         dev.S_sweep_err = (double*)dptr(host->S_sweep_err);
-        return CC_OK;
     }
-    void copy_back(hipStream_t st) {
-        for (auto& f : fields) CCG_HIP(hipMemcpyAsync(f.h, f.d, f.bytes, hipMemcpyDeviceToHost, st));
+    void to_pinned(hipStream_t st, char* pbase) const {
+        for (const auto& f : fields)
+            CCG_HIP(hipMemcpyAsync(pbase + f.off, f.d, f.bytes, hipMemcpyDeviceToHost, st));
+    }
+    void deliver(const char* pbase) const {
+        for (const auto& f : fields) std::memcpy(f.h, pbase + f.off, f.bytes);
     }
 };
 
 cc_status estimate_to_host(cc_context* ctx, const cc_graph* g, const Resolved& r, const cc_result* host, Lane& L,
                            cc_timing* t) {
     Staging sg;
-    cc_status s = sg.build(host, g->dg.n, r.k);
-    if (s != CC_OK) return s;
-    s = run_job(ctx, g, r, &sg.dev, L, t);
-    if (s == CC_OK) {
-        sg.copy_back(L.stream);
+    sg.plan(host, g->dg.n, r.k);
+    sg.place(host, sg.total ? (char*)L.arenaO.get(sg.total) : nullptr);
+    cc_status s = run_job(ctx, g, r, &sg.dev, L, t);
+    if (s == CC_OK && sg.total) {
+        char* hp = L.pinned_host(sg.total);
+        sg.to_pinned(L.stream, hp);
         CCG_HIP(hipStreamSynchronize(L.stream));
+        sg.deliver(hp);
     }
     return s;
 }
@@ -1774,6 +1803,7 @@ cc_status estimate_to_host(cc_context* ctx, const cc_graph* g, const Resolved& r
 // snapshots.  One launch per level serves every graph of the batch.
 
 constexpr int64_t kBatchNodeLimit = 1 << 17;  // graphs at most this large are batched
+constexpr int32_t kMaxOvertakes = 16;          // younger jobs that may pass a waiting oldest job
 constexpr int32_t kBatchWords = 4;
 
 bool batchable(const cc_graph* g, const Resolved& r) {
@@ -2022,25 +2052,41 @@ void batch_to_host(cc_context* ctx, const std::vector<const cc_graph*>& graphs, 
     const size_t nj = graphs.size();
     statuses.assign(nj, CC_OK);
     bool ok = nj > 1;
-    std::vector<std::unique_ptr<Staging>> stg;
+    std::vector<Staging> stg(nj);
     std::vector<BatchItem> items(nj);
-    for (size_t j = 0; j < nj && ok; j++) {
-        stg.push_back(std::make_unique<Staging>());
-        if (stg.back()->build(hosts[j], graphs[j]->dg.n, rs[j]->k) != CC_OK) ok = false;
-        items[j].g = graphs[j];
-        items[j].r = rs[j];
-        items[j].out = &stg.back()->dev;
+    size_t total = 0;
+    for (size_t j = 0; j < nj; j++) {
+        stg[j].plan(hosts[j], graphs[j]->dg.n, rs[j]->k);
+        total += stg[j].total;
     }
     if (ok) {
+        char* dbase = total ? (char*)L.arenaO.get(total) : nullptr;
+        size_t off = 0;
+        for (size_t j = 0; j < nj; j++) {
+            stg[j].place(hosts[j], dbase ? dbase + off : nullptr);
+            off += stg[j].total;
+            items[j].g = graphs[j];
+            items[j].r = rs[j];
+            items[j].out = &stg[j].dev;
+        }
         cc_timing t{};
         ok = run_batch(ctx, items, L, &t) == CC_OK;
         if (ok) {
-            for (auto& sgp : stg) sgp->copy_back(L.stream);
+            char* hp = total ? L.pinned_host(total) : nullptr;
+            off = 0;
+            for (size_t j = 0; j < nj; j++) {
+                if (stg[j].total) stg[j].to_pinned(L.stream, hp + off);
+                off += stg[j].total;
+            }
             CCG_HIP(hipStreamSynchronize(L.stream));
+            off = 0;
+            for (size_t j = 0; j < nj; j++) {
+                if (stg[j].total) stg[j].deliver(hp + off);
+                off += stg[j].total;
+            }
             return;
         }
     }
-    stg.clear();
     for (size_t j = 0; j < nj; j++) {
         cc_timing t{};
         statuses[j] = estimate_to_host(ctx, graphs[j], *rs[j], hosts[j], L, &t);
@@ -2530,14 +2576,21 @@ void worker_main(cc_context* ctx, Lane* L) {
             for (;;) {
                 if (ctx->stopping) return;
                 // admit the oldest job that fits the memory budget (continuous
-                // batching: a small job may overtake a large one that waits for
-                // memory, but never a job of the same or smaller size)
+                // batching: a job that fits may overtake an older one that waits
+                // for memory, but at most kMaxOvertakes times; after that the
+                // oldest job goes next, as soon as memory frees up)
                 auto it = ctx->queue.begin();
+                const bool front_first = it != ctx->queue.end() && (*it)->overtaken >= kMaxOvertakes;
                 for (; it != ctx->queue.end(); ++it) {
                     if (ctx->in_use + (int64_t)(*it)->need <= ctx->budget || ctx->inflight == 0) break;
+                    if (front_first) {
+                        it = ctx->queue.end();
+                        break;
+                    }
                 }
                 if (it != ctx->queue.end()) {
                     cc_job* j = *it;
+                    if (it != ctx->queue.begin()) ctx->queue.front()->overtaken++;
                     ctx->queue.erase(it);
                     ctx->in_use += (int64_t)j->need;
                     ctx->inflight += 1;
@@ -2546,7 +2599,7 @@ void worker_main(cc_context* ctx, Lane* L) {
                     const Resolved r0 = resolved_of(j);
                     if (batchable(j->g, r0)) {
                         int32_t words = (r0.k + 63) / 64;
-                        for (auto q = ctx->queue.begin(); q != ctx->queue.end() && words < kBatchWords;) {
+                        for (auto q = ctx->queue.begin(); q != ctx->queue.end() && words < kBatchWords && !front_first;) {
                             cc_job* o = *q;
                             const Resolved ro = resolved_of(o);
                             const int32_t w = (ro.k + 63) / 64;
@@ -2611,6 +2664,14 @@ void worker_main(cc_context* ctx, Lane* L) {
                 errs[q] = e.where + ": " + hipGetErrorString(e.err);
             }
         }
+        // a lane keeps its buffers for the next job; beyond its share of the
+        // budget it gives them back, so that retained memory cannot crowd out
+        // jobs the budget admits
+        const int slots = (int)ctx->worker_lanes.size();
+        if (slots > 0 && (int64_t)L->retained() > ctx->budget / slots) {
+            (void)hipStreamSynchronize(L->stream);
+            L->trim();
+        }
         {
             std::lock_guard<std::mutex> lk(ctx->qmu);
             for (cc_job* j : js) ctx->in_use -= (int64_t)j->need;
@@ -2623,7 +2684,9 @@ void worker_main(cc_context* ctx, Lane* L) {
 
 void start_service(cc_context* ctx) {
     if (ctx->service_started) return;
-    const int slots = ctx->cfg.max_inflight > 0 ? ctx->cfg.max_inflight : 8;
+    // one stream per slot; the default matches the device's hardware queues
+    // per process (4), beyond which streams share queues and only add waiting
+    const int slots = ctx->cfg.max_inflight > 0 ? ctx->cfg.max_inflight : 4;
     for (int i = 0; i < slots; i++) {
         auto L = std::make_unique<Lane>();
         L->init(nullptr);
