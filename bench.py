@@ -2,16 +2,21 @@
 
 One step = one full estimate (sample draw, all k traversals, every estimator
 of Sec. 2 for every node, outputs left in device memory) on a resident graph.
-Default workload: undirected R-MAT scale 20 (a,b,c,d = .57,.19,.19,.05, edge
-factor 16, duplicates and self-loops removed, largest connected component),
-k = 256 samples, batched 64-samples-per-word BFS.
+Headline workload: directed R-MAT scale 22 (a,b,c,d = .57,.19,.19,.05, 16 arcs
+per node, duplicates and self-loops removed, largest strongly connected
+component), k = 128 samples, round-trip distances (a forward and a reverse
+batched 64-samples-per-word BFS per sample group).
 
-Prints ONE JSON line.  `value` = GTEPS of the batched path = k * m / t with m
-the undirected edge count (each edge once) and t the wall time of one step.
-Also reported: the plain one-sample-at-a-time GPU path, per-step latency
-percentiles, the roofline of the dominant kernel (the batched traversal
-kernel: algorithmic bytes / its HIP-event-timed duration), and the CPU oracle
-timed on a bounded sample of the same workload.
+Prints ONE JSON line.  `value` = GTEPS of the batched path = 2 k arcs / t for
+the round trip (k m / t for undirected graphs, m the edges counted once) with
+t the wall time of one step.  Also reported: the plain one-sample-at-a-time
+GPU path, per-step latency percentiles, the roofline of the dominant kernel
+(algorithmic bytes / its HIP-event-timed duration), and the CPU oracle timed
+on a bounded sample of the same workload.  Under "configs" the same figures
+for the other workloads (Barabasi-Albert 10k with k = 64, with the oracle's
+exact all-pairs time and the estimators' error; R-MAT scale 20 with k = 256;
+the weighted 2048 x 2048 grid with k = 64) and the 512-job serving mix at
+0.5, 0.8 and 1.0 of its burst capacity.
 """
 from __future__ import annotations
 
@@ -107,65 +112,86 @@ def scatter_roofline(timings, W: int, workload: str, tuning: dict) -> dict:
             "pull_levels_gbs": round(pull_arcs * bytes_per_arc(W) / (pull_ms / 1e3) / 1e9, 1) if pull_ms > 0 else None}
 
 
-def cpu_baseline(g, k, seed, rg=None, budget_s=20.0):
-    """The CPU oracle, as it stands, on a bounded sample of the same workload:
-    a prefix of the k sources' searches (all host threads, over sources) and
-    the literal Eq. (6) walk for a set of random nodes (all host threads, over
-    nodes), each grown until it has taken about half of `budget_s`, then
-    extrapolated to k sources and all n nodes, as GTEPS."""
-    import concurrent.futures as cf
-    import ctypes
-
+def cpu_baseline(g, k, seed, rg=None, budget_s=24.0, exact_all_pairs=False):
+    """The CPU oracle, as it stands, on a bounded sample of the same workload,
+    on the host's cores.  Its two stages are timed apart and extrapolated to
+    the whole estimate: the k searches (BFS / Dijkstra, both directions for a
+    digraph) on all host threads and on one, for a prefix of the sources; and
+    the estimator for every node by the oracle's Algorithm 1 accounting
+    (estimate_tails, O(nk + kn log n)) over that prefix's distance columns,
+    scaled to k columns.  With exact_all_pairs, also one search from every
+    node (the exact S of Eq. (1)), on all threads and on one; the exact sums
+    are returned for the estimator-error report."""
     import oracle
 
-    threads = min(os.cpu_count() or 1, 16)
-    samples = oracle.draw_samples(g.n, k, seed)
-    half = budget_s / 2
-    # searches: one batch of `threads` sources to size the rest
+    threads = os.cpu_count() or 1
+    samples = np.asarray(oracle.draw_samples(g.n, k, seed), dtype=np.int32)
+    m = g.m if not g.directed else 2 * g.arcs
+    # all threads: a prefix of the sources grown to about a third of the budget
     ks = min(k, threads)
     t0 = time.perf_counter()
     oracle.sample_distances(g, samples[:ks], threads=threads, reverse_graph=rg)
     t_batch = time.perf_counter() - t0
-    ks = min(k, max(ks, int(ks * half / max(t_batch, 1e-3))))
+    ks = min(k, max(ks, int(ks * (budget_s / 3) / max(t_batch, 1e-3)) // threads * threads))
     t0 = time.perf_counter()
     D = oracle.sample_distances(g, samples[:ks], threads=threads, reverse_graph=rg)
-    t_search = time.perf_counter() - t0
-    per_source = t_search / ks  # wall time per source with all threads busy
-
-    lib = oracle._load()
-    sidx = oracle.sample_index(g.n, samples[:ks])
-    Dc = np.ascontiguousarray(D)
-
-    def one_node(v):
-        row = np.ascontiguousarray(Dc[v])
-        p = int(lib.orc_pivot(ks, oracle._p(row)))
-        o = oracle.NodeOut()
-        col = Dc[:, p:]
-        lib.orc_node_estimates(g.n, ks, int(v), oracle._p(sidx), oracle._p(row),
-                               ctypes.c_void_p(col.ctypes.data), ks, 1, 10, ctypes.byref(o))
-        return o.S_hyb
-
-    rng = np.random.default_rng(seed)
-    nodes_done, t_walk = 0, 0.0
-    with cf.ThreadPoolExecutor(threads) as ex:
-        batch = min(threads, g.n)
-        while t_walk < half and nodes_done < g.n:
-            nodes = rng.integers(0, g.n, size=batch)
-            t1 = time.perf_counter()
-            list(ex.map(one_node, nodes))
-            dt = time.perf_counter() - t1
-            t_walk += dt
-            nodes_done += batch
-            batch = min(g.n - nodes_done, max(batch, int(batch * (half - t_walk) / max(dt, 1e-3))))
-    per_node = t_walk / nodes_done  # wall time per node with all threads busy
-    t_total = k * per_source + g.n * per_node
-    m = g.m if not g.directed else 2 * g.arcs
-    return {
-        "value": k * m / t_total / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
-        "sample": (f"{ks} of {k} sources' searches ({t_search:.1f} s) + literal Eq.6 walk for {nodes_done} "
-                   f"random nodes ({t_walk:.1f} s), {threads} threads; extrapolated to k={k} sources and "
-                   f"n={g.n} nodes: {t_total:.1f} s per estimate"),
+    t_search_T = (time.perf_counter() - t0) / ks
+    # one thread: one or two sources
+    k1 = 1 if t_search_T * threads > 2.0 else 2
+    t0 = time.perf_counter()
+    oracle.sample_distances(g, samples[:k1], threads=1, reverse_graph=rg)
+    t_search_1 = (time.perf_counter() - t0) / k1
+    # the estimator over the prefix's columns, on all threads and on one
+    t0 = time.perf_counter()
+    oracle.estimate_tails(g, samples[:ks], D=D, threads=threads, adaptive_eps=())
+    t_est_T = (time.perf_counter() - t0) * k / ks
+    t0 = time.perf_counter()
+    oracle.estimate_tails(g, samples[:ks], D=D, threads=1, adaptive_eps=())
+    t_est_1 = (time.perf_counter() - t0) * k / ks
+    del D
+    total_T = k * t_search_T + t_est_T
+    total_1 = k * t_search_1 + t_est_1
+    out = {
+        "value": round(k * m / total_T / 1e9, 5), "unit": "GTEPS", "cores": threads, "kind": "oracle",
+        "sample": (f"searches from {ks} of the {k} sources on {threads} threads and {k1} on one thread, and the "
+                   f"oracle's Algorithm 1 estimator for all {g.n} nodes over those {ks} columns; extrapolated to "
+                   f"{k} sources: {total_T:.2f} s per estimate on {threads} threads, {total_1:.1f} s on one"),
+        "per_estimate_s": {"threads": threads, "searches": round(k * t_search_T, 3), "estimator": round(t_est_T, 3),
+                           "total": round(total_T, 3)},
+        "single_thread": {"value": round(k * m / total_1 / 1e9, 5), "searches_s": round(k * t_search_1, 3),
+                          "estimator_s": round(t_est_1, 3), "total_s": round(total_1, 3)},
     }
+    exact = None
+    if exact_all_pairs:
+        t0 = time.perf_counter()
+        exact = oracle.exact_sums(g, threads=threads, reverse_graph=rg)
+        tT = time.perf_counter() - t0
+        t1 = None
+        if tT * threads < 30.0:
+            t0 = time.perf_counter()
+            oracle.exact_sums(g, threads=1, reverse_graph=rg)
+            t1 = time.perf_counter() - t0
+        out["exact_all_pairs_s"] = {"threads": round(tT, 3), "single_thread": None if t1 is None else round(t1, 3)}
+    return out, exact
+
+
+def estimator_error(ctx, gh, g, k, seed, exact, cc):
+    """Average relative error |S^ - S| / S of each estimator against the exact
+    S (Eq. (1)), over every node and over 1000 random query nodes (as the
+    paper's experiments report it), from the library's outputs."""
+    res = cc.cc_estimate(ctx.handle, gh, k, seed=seed,
+                         outputs=("S_hyb", "S_samp", "S_piv", "S_pub", "S_ad", "S_sweep"))
+    res["S_hyb_eps_1/10"] = cc.cc_estimate(ctx.handle, gh, k, seed=seed, eps=(1, 10), outputs=("S_hyb",))["S_hyb"]
+    S = exact.astype(np.float64)
+    q = np.random.default_rng(1000 + seed).choice(g.n, size=min(1000, g.n), replace=False)
+    names = {"S_samp": "sampling", "S_piv": "pivoting", "S_pub": "pivoting upper bound",
+             "S_hyb": f"hybrid eps=1/{int(round(math.sqrt(k)))}", "S_hyb_eps_1/10": "hybrid eps=1/10",
+             "S_ad": "adaptive eps (Sec. 4)", "S_sweep": "threshold sweep (Algorithm 2)"}
+    out = {}
+    for f, label in names.items():
+        e = np.abs(res[f].astype(np.float64) - S) / S
+        out[label] = {"all_nodes": round(float(e.mean()), 5), "1000_queries": round(float(e[q].mean()), 5)}
+    return out
 
 
 def beta_bench(args, graphgen, cc, torch):
@@ -292,18 +318,178 @@ def reach_bench(args, graphgen, cc, torch):
     ctx.close()
 
 
+def wsearch_roofline(timings, workload: str) -> dict:
+    """Per-launch algorithmic bytes / average launch duration of the weighted
+    searches' kernel (one launch of one workgroup per sample): 16 B per arc
+    relaxed (its 8-byte end and length, and the far end's 8-byte word) and
+    16 B per node taken from a near pile (its word and its two row bounds),
+    counted on the device, over the HIP-event time of the launch."""
+    launches = sum(t["kernel_launches"] for t in timings)
+    ms = sum(t["kernel_ms"] for t in timings)
+    byts = sum(16 * (t["arcs_scanned"] + t["nodes_visited"]) for t in timings)
+    if launches == 0 or ms <= 0:
+        return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": "k_wsearch"}
+    per = byts / launches
+    achieved = per / (ms / launches / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic_kernel("k_wsearch", workload,
+                                                                                         "sssp_weighted.hip"),
+            "kernel": "k_wsearch", "algorithmic_bytes_per_launch": int(per),
+            "avg_launch_us": round(ms / launches * 1e3, 1), "launches_per_step": launches / len(timings),
+            "bytes_per_relaxation": 16}
+
+
+def measured_traffic_kernel(kernel: str, workload: str, source: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    passes (profiles/<kernel>_<workload>_pmc.md), None once `source` has
+    changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    with open(os.path.join(ROOT, "paper_1409_0035_amd", "csrc", source), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                key, _, val = line[2:].partition(": ")
+                vals[key.strip()] = val.strip().strip("`")
+    if vals.get(f"{source} sha256[:16]") != digest:
+        return None
+    try:
+        return float(vals["scaled HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_config(name, cc, graphgen, torch, steps, warmup, plain_steps, autotune=True, fixed_tuning=None,
+               outputs="hybrid", keep=False):
+    """One workload: K timed estimates into device memory after W warm-up ones
+    (replays of the captured estimate where that applies), the dominant
+    kernel's roofline from extra eager steps, and the plain one-source-at-a-
+    time path.  Returns the summary (and, with keep, the context and graph)."""
+    spec = graphgen.WORKLOADS[name]
+    t0 = time.time()
+    g = graphgen.workload(name)
+    k, seed = spec["k"], spec["sample_seed"]
+    edges = k * g.m * (2 if g.directed else 1)  # round trip: forward + reverse searches
+    log(f"workload {name}: n={g.n} m={g.m} arcs={g.arcs} k={k} (generated in {time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    ctx = cc.Context(0)
+    gh = ctx.upload(g)
+    out = {f: torch.empty(g.n, dtype=dt, device=dev) for f, dt in
+           (("S_hyb", torch.float64), ("S_samp", torch.float64), ("S_piv", torch.int64), ("S_pub", torch.int64),
+            ("pivot", torch.int32), ("delta", torch.int32), ("sampsum", torch.int64))}
+    extra = {"hybrid": (), "errors": ("S_err", "S_ad", "S_ad_err"), "sweep": ("S_sweep", "S_sweep_err")}
+    for f in extra[outputs]:
+        out[f] = torch.empty(g.n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    tuning = cc.cc_graph_get_tuning(gh)
+    if fixed_tuning:
+        tuning = cc.cc_graph_set_tuning(gh, **fixed_tuning)
+    elif autotune:
+        t0 = time.time()
+        tuning, tuned_ms = cc.cc_autotune(ctx.handle, gh, k, seed=seed, reps=3 if g.w is None else 1)
+        log(f"  autotune: {tuning} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
+
+    def step(mode):
+        cc.cc_estimate_device(ctx.handle, gh, k, out, mode=mode, seed=seed, stream=stream)
+
+    use_graph = not g.directed and g.w is None and k <= 256
+    main_mode = cc.CC_BATCHED | (cc.CC_GRAPH if use_graph else 0)
+    for _ in range(warmup):
+        step(main_mode)
+    torch.cuda.synchronize()
+    lat, timings = [], []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        step(main_mode)
+        lat.append((time.perf_counter() - a) * 1e3)
+        timings.append(cc.cc_last_timing(ctx.handle))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / steps
+    gteps = edges / (ms_per_step / 1e3) / 1e9
+    replayed = sum(1 for t in timings if t["launches"] == 1)
+    log(f"  batched{' (graph replays: %d)' % replayed if use_graph else ''}: {ms_per_step:.3f} ms/step, "
+        f"{gteps:.1f} GTEPS")
+    if use_graph:  # replays carry no per-launch timing: take it from eager steps
+        timings = []
+        for _ in range(max(3, min(steps, 10))):
+            step(cc.CC_BATCHED)
+            timings.append(cc.cc_last_timing(ctx.handle))
+    tm = timings[-1]
+    if g.w is None:
+        W = (min(k, 256) + 63) // 64
+        roofline = scatter_roofline(timings, W, name, tuning)
+    else:
+        roofline = wsearch_roofline(timings, name)
+    log(f"  roofline: {roofline}")
+    plain = None
+    if plain_steps > 0:
+        a = time.perf_counter()
+        step(cc.CC_PLAIN)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - a
+        reps = 1 if first > 2.0 else plain_steps
+        a = time.perf_counter()
+        for _ in range(reps):
+            step(cc.CC_PLAIN)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - a) * 1e3 / reps
+        plain = {"ms_per_step": round(pms, 3), "gteps": round(edges / (pms / 1e3) / 1e9, 3), "steps": reps}
+        log(f"  plain: {pms:.3f} ms/step, {plain['gteps']} GTEPS")
+    summary = {
+        "workload": f"{name}: {g.name} n={g.n} m={g.m} arcs={g.arcs} k={k}", "n": g.n, "m": g.m, "arcs": g.arcs,
+        "k": k, "eps": f"1/{int(round(math.sqrt(k)))}", "round_trip": bool(g.directed), "weighted": g.w is not None,
+        "steps": steps, "ms_per_step": round(ms_per_step, 4), "gteps": round(gteps, 3),
+        "teps_edges_per_step": edges, "graph_replay": use_graph and replayed > 0,
+        "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
+        "plain": plain, "speedup_vs_plain": None if plain is None else round(gteps / plain["gteps"], 2),
+        "breakdown_ms": {"traverse": round(tm["traverse_ms"], 4), "epilogue": round(tm["epilogue_ms"], 4),
+                         "level_kernels": round(float(np.median([t["kernel_ms"] for t in timings])), 4)},
+        "levels": tm["levels"], "tuning": tuning, "roofline": roofline,
+    }
+    if keep:
+        return summary, ctx, gh, g
+    ctx.close()
+    return summary
+
+
+def serving_config(args, graphgen):
+    """The serving mix: 512 Poisson-arriving BA / R-MAT jobs (n log-uniform in
+    [1e3, 1e6], k in {16, 64, 256}) against resident graphs, at offered loads
+    of 0.5, 0.8 and 1.0 times the measured burst capacity."""
+    from paper_1409_0035_amd import serve
+    t0 = time.time()
+    jobs, graphs = serve.build_mix(args.serve_jobs, seed=5, n_lo=1e3, n_hi=1e6,
+                                   threads=min(os.cpu_count() or 1, 16))
+    log(f"serving mix: {len(jobs)} graphs generated in {time.time() - t0:.1f}s")
+    res = serve.serve(jobs, graphs, load=[0.5, 0.8, 1.0], seed=5)
+    res["workload"] = (f"serving mix: {len(jobs)} Poisson-arriving BA (4 edges per node) / R-MAT (edge factor 16) "
+                       f"jobs, n log-uniform in [1e3, 1e6], k in {{16, 64, 256}}, eps = 1/round(sqrt(k))")
+    res["alone_p99_ratio_at_0.8"] = round(res["loads"][1]["latency_ms"]["p99"] / res["service_alone_ms"]["p99"], 3)
+    log(f"serving: {json.dumps(res)}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--workload", default="rmat22dir",
+                    help="the headline workload (default: directed R-MAT scale 22, round trip, k = 128)")
+    ap.add_argument("--only", action="store_true",
+                    help="time the headline workload only (no other configurations, no serving mix)")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="time eager estimates instead of replays of the captured estimate (CC_GRAPH, used by "
-                         "default where it applies; the roofline then comes from extra eager steps)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=512)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of running the library's autotuner first")
     ap.add_argument("--tuning", default="",
@@ -333,133 +519,74 @@ def main():
     import paper_1409_0035_amd as cc
 
     if args.reach:
-        if args.workload == "rmat20":
+        if args.workload == "rmat22dir":
             args.workload = "rmat20dir"
         if args.beta:
             return reach_weighted_bench(args, graphgen, cc, torch)
         return reach_bench(args, graphgen, cc, torch)
     if args.beta:
+        if args.workload == "rmat22dir":
+            args.workload = "rmat20"
         return beta_bench(args, graphgen, cc, torch)
 
+    fixed = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.tuning.split(",") if kv} or None
+    plain_steps = 0 if args.no_plain else args.plain_steps
+    # ---- the headline workload
+    head, hctx, hgh, hg = run_config(args.workload, cc, graphgen, torch, args.steps, args.warmup, plain_steps,
+                                     autotune=not args.no_autotune, fixed_tuning=fixed, outputs=args.outputs,
+                                     keep=True)
     spec = graphgen.WORKLOADS[args.workload]
-    t0 = time.time()
-    g = graphgen.workload(args.workload)
-    k, seed = spec["k"], spec["sample_seed"]
-    rg = graphgen.transpose(g) if g.directed else None
-    m = g.m
-    teps_edges = k * m * (2 if g.directed else 1)  # round trip: forward + reverse searches
-    log(f"workload {args.workload}: n={g.n} m={m} arcs={g.arcs} k={k} (generated in {time.time() - t0:.1f}s)")
-
-    dev = torch.device("cuda:0")
-    ctx = cc.Context(0)
-    gh = ctx.upload(g)
-    out = {
-        "S_hyb": torch.empty(g.n, dtype=torch.float64, device=dev),
-        "S_samp": torch.empty(g.n, dtype=torch.float64, device=dev),
-        "S_piv": torch.empty(g.n, dtype=torch.int64, device=dev),
-        "S_pub": torch.empty(g.n, dtype=torch.int64, device=dev),
-        "pivot": torch.empty(g.n, dtype=torch.int32, device=dev),
-        "delta": torch.empty(g.n, dtype=torch.int32, device=dev),
-        "sampsum": torch.empty(g.n, dtype=torch.int64, device=dev),
-    }
-    extra = {"hybrid": (), "errors": ("S_err", "S_ad", "S_ad_err"), "sweep": ("S_sweep", "S_sweep_err")}
-    for f in extra[args.outputs]:
-        out[f] = torch.empty(g.n, dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
-
-    tuning = cc.cc_graph_get_tuning(gh)
-    if args.tuning:
-        fixed = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.tuning.split(",") if kv}
-        tuning = cc.cc_graph_set_tuning(gh, **fixed)
-        log(f"tuning fixed: {tuning}")
-    elif not args.no_autotune:
-        t0 = time.time()
-        tuning, tuned_ms = cc.cc_autotune(ctx.handle, gh, k, seed=seed, reps=3)
-        log(f"autotune: {tuning} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
-
-    def step(mode):
-        cc.cc_estimate_device(ctx.handle, gh, k, out, mode=mode, seed=seed, stream=stream)
-
-    use_graph = not args.no_graph and not g.directed and g.w is None and k <= 256
-    main_mode = cc.CC_BATCHED | (cc.CC_GRAPH if use_graph else 0)
-    for i in range(args.warmup):
-        step(main_mode)
-    log(f"warmup done ({args.warmup} steps)")
-    torch.cuda.synchronize()
-    lat, kern_ms, timings = [], [], []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        a = time.perf_counter()
-        step(main_mode)
-        lat.append((time.perf_counter() - a) * 1e3)
-        tm = cc.cc_last_timing(ctx.handle)
-        timings.append(tm)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms_per_step = wall * 1e3 / args.steps
-    gteps = teps_edges / (ms_per_step / 1e3) / 1e9
-    replayed = sum(1 for t in timings if t["launches"] == 1)
-    log(f"batched{' (graph replays: %d)' % replayed if use_graph else ''}: {ms_per_step:.3f} ms/step, "
-        f"{gteps:.1f} GTEPS")
-    if use_graph:  # replays carry no per-launch timing: take it from eager steps
-        timings = []
-        for i in range(max(3, min(args.steps, 10))):
-            step(cc.CC_BATCHED)
-            timings.append(cc.cc_last_timing(ctx.handle))
-
-    # roofline of the dominant kernel (the per-level scatter kernel), timed
-    # live with HIP events on the stream it is launched on
-    tm = timings[-1]
-    W = (min(k, 256) + 63) // 64
-    roofline = scatter_roofline(timings, W, args.workload, tuning)
-    level_ms = float(np.median([t["kernel_ms"] for t in timings]))
-    log(f"roofline: {roofline}")
-
-    plain = None
-    if not args.no_plain and args.plain_steps > 0:
-        step(cc.CC_PLAIN)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(args.plain_steps):
-            step(cc.CC_PLAIN)
-        torch.cuda.synchronize()
-        pms = (time.perf_counter() - a) * 1e3 / args.plain_steps
-        plain = {"ms_per_step": round(pms, 3), "gteps": round(teps_edges / (pms / 1e3) / 1e9, 3)}
-        log(f"plain: {pms:.3f} ms/step, {plain['gteps']} GTEPS")
-
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(g, k, seed, rg)
-        log(f"cpu baseline: {cpu['value']:.4f} GTEPS")
+        rg = graphgen.transpose(hg) if hg.directed else None
+        cpu, _ = cpu_baseline(hg, spec["k"], spec["sample_seed"], rg)
+        log(f"cpu baseline: {cpu}")
+    hctx.close()
+    del hg
+    # ---- the other configurations
+    configs = {}
+    if not args.only:
+        for name, steps in (("ba10k", 50), ("rmat20", 20), ("grid2048w", 5)):
+            if name == args.workload:
+                continue
+            keep = name == "ba10k"
+            r = run_config(name, cc, graphgen, torch, steps, 3 if name != "grid2048w" else 1, plain_steps,
+                           keep=keep)
+            if keep:
+                r, bctx, bgh, bg = r
+                if not args.no_cpu_baseline:
+                    spec1 = graphgen.WORKLOADS[name]
+                    c1, exact = cpu_baseline(bg, spec1["k"], spec1["sample_seed"], budget_s=6.0,
+                                             exact_all_pairs=True)
+                    r["cpu_oracle"] = c1
+                    r["estimator_error"] = estimator_error(bctx, bgh, bg, spec1["k"], spec1["sample_seed"], exact, cc)
+                    log(f"  estimator error: {r['estimator_error']}")
+                bctx.close()
+            configs[name] = r
+        if not args.no_serving:
+            configs["serving"] = serving_config(args, graphgen)
 
     line = {
-        "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64 bitmask / int32 dist / int64 sums",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {g.name} n={g.n} m={m} k={k} batched", "n": g.n, "m": m,
-                   "k": k, "eps": f"1/{int(round(math.sqrt(k)))}", "graph_replay": use_graph,
-                   "outputs": args.outputs},
-        "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
-        "plain": plain,
-        "speedup_vs_plain": None if plain is None else round(gteps / plain["gteps"], 2),
-        "breakdown_ms": {"traverse": round(tm["traverse_ms"], 4), "epilogue": round(tm["epilogue_ms"], 4),
-                         "level_kernels": round(level_ms, 4),
-                         "scatter_kernel": round(float(np.median([t["scatter_ms"] for t in timings])), 4)},
-        "tuning": tuning,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+        "metric": METRIC, "value": head["gteps"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64 bitmask / int32 dist / int64 sums", "data": "synthetic",
+        "config": {"workload": head["workload"] + (" round trip" if head["round_trip"] else "") + " batched",
+                   "n": head["n"], "m": head["m"], "arcs": head["arcs"], "k": head["k"], "eps": head["eps"],
+                   "graph_replay": head["graph_replay"], "outputs": args.outputs},
+        "latency_ms": head["latency_ms"], "plain": head["plain"], "speedup_vs_plain": head["speedup_vs_plain"],
+        "breakdown_ms": head["breakdown_ms"], "tuning": head["tuning"],
+        "roofline": head["roofline"], "cpu_baseline": cpu, "configs": configs,
     }
     print(json.dumps(line), flush=True)
     if args.copy_calibration > 0:
+        dev = torch.device("cuda:0")
         x = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         torch.cuda.synchronize()
         torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration} MiB read + written by one elementwise kernel")
-    ctx.close()
 
 
 if __name__ == "__main__":

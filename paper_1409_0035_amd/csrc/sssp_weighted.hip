@@ -454,6 +454,7 @@ struct SearchBufs {
     int32_t* far;     // [kg][2][n] far piles
     int32_t* status;  // [kg]: 0 done, 4 distance overflow, 5 time limit
     int32_t* rounds;  // [kg]: rounds run
+    int64_t* work;    // [kg][2]: nodes taken from near piles, arcs relaxed
 };
 
 // A sample's words are touched by its own workgroup only, and its phases are
@@ -489,6 +490,7 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
     __shared__ int32_t lq[2][kLq];
     __shared__ int32_t s_cnt[2];  // entries of the next near pile; of the current far pile (cumulative)
     __shared__ int32_t s_nq, s_nf, s_qsel, s_fsel, s_stop, s_rounds, s_ovf;
+    __shared__ unsigned long long s_taken, s_relaxed;
     __shared__ uint32_t s_hi;
     __shared__ uint32_t s_min[kSBlock / 64];
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -510,10 +512,12 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
         s_ovf = 0;
         s_rounds = 0;
         s_cnt[0] = s_cnt[1] = 0;
+        s_taken = s_relaxed = 0;
     }
     __syncthreads();
     const uint64_t t0 = wall_clock64();
     constexpr int kPerWave = 64 / kGroup;  // nodes a wave takes at a time
+    uint64_t my_taken = 0, my_relaxed = 0;  // work counters (the roofline's bytes)
     for (;;) {
         const int32_t nq = s_nq;
         const uint32_t hi = s_hi;
@@ -540,7 +544,10 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
                 for (int r = 0; r < kUnroll; r++) {
                     // lane 0 of the group leaves the pile (reading d), lanes 1, 2 read the arc range
                     if (valid[r]) {
-                        if (sub == 0) d[r] = wg_and(&W[v[r]], ~1ull) >> 2;
+                        if (sub == 0) {
+                            d[r] = wg_and(&W[v[r]], ~1ull) >> 2;
+                            my_taken++;
+                        }
                         else if (sub == 1) b[r] = rp[v[r]];
                         else if (sub == 2) e[r] = rp[v[r] + 1];
                     }
@@ -574,6 +581,7 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
                     for (int r = 0; r < kUnroll; r++) {
                         o[r] = 0;
                         if (u[r] >= 0) {
+                            my_relaxed++;
                             if (c[r] > kMaxDist) s_ovf = 1;
                             o[r] = wg_min(&W[u[r]], (c[r] << 2) | (c[r] < hi ? 1ull : 2ull));
                         }
@@ -650,9 +658,14 @@ __global__ __launch_bounds__(kSBlock) void k_wsearch(const uint32_t* __restrict_
         __syncthreads();
         if (s_stop) break;
     }
+    atomicAdd(&s_taken, (unsigned long long)my_taken);
+    atomicAdd(&s_relaxed, (unsigned long long)my_relaxed);
+    __syncthreads();
     if (threadIdx.x == 0) {
         B.status[j] = s_ovf ? 4 : (s_stop ? 5 : 0);
         B.rounds[j] = s_rounds;
+        B.work[2 * j] = (int64_t)s_taken;
+        B.work[2 * j + 1] = (int64_t)s_relaxed;
     }
 }
 
@@ -716,7 +729,7 @@ void zip_arcs(hipStream_t st, const int32_t* col, const int32_t* w, int64_t arcs
 
 size_t sssp_wsearch_scratch(int64_t n, int32_t kg) {
     return align256((size_t)kg * n * 8) + 2 * align256((size_t)kg * 2 * n * 4) + 2 * align256((size_t)kg * 4) +
-           align256(16) + 1024;
+           align256((size_t)kg * 16) + align256(16) + 1024;
 }
 
 // The k searches of a batched estimate, one workgroup each (k_wsearch), into
@@ -740,6 +753,8 @@ int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, in
     p += align256((size_t)kg * 4);
     B.rounds = (int32_t*)p;
     p += align256((size_t)kg * 4);
+    B.work = (int64_t*)p;
+    p += align256((size_t)kg * 16);
     uint32_t* mx = (uint32_t*)p;
     const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
     hipLaunchKernelGGL(k_wfill64, dim3(gz), dim3(256), 0, st, B.W, pairs, kInfW);
@@ -754,9 +769,15 @@ int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, in
     CCG_HIP(hipGetLastError());
     kt.stop(st);
     std::vector<int32_t> hs((size_t)kg * 2);
+    std::vector<int64_t> hw((size_t)kg * 2);
     CCG_HIP(hipMemcpyAsync(hs.data(), B.status, sizeof(int32_t) * kg, hipMemcpyDeviceToHost, st));
     CCG_HIP(hipMemcpyAsync(hs.data() + kg, B.rounds, sizeof(int32_t) * kg, hipMemcpyDeviceToHost, st));
+    CCG_HIP(hipMemcpyAsync(hw.data(), B.work, sizeof(int64_t) * kg * 2, hipMemcpyDeviceToHost, st));
     CCG_HIP(hipStreamSynchronize(st));
+    for (int32_t q = 0; q < kg; q++) {
+        stats->nodes_visited += hw[(size_t)2 * q];
+        stats->arcs_scanned += hw[(size_t)2 * q + 1];
+    }
     stats->kernel_ms += kt.ms();
     stats->kernel_launches += 1;
     stats->launches += 3;
