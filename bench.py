@@ -318,32 +318,39 @@ def reach_bench(args, graphgen, cc, torch):
     ctx.close()
 
 
-def wsearch_roofline(timings, workload: str) -> dict:
+def wsearch_roofline(timings, workload: str, n: int, arcs: int, k: int, tuning: dict) -> dict:
     """Per-launch algorithmic bytes / average launch duration of the weighted
-    searches' kernel (one launch of one workgroup per sample): 16 B per arc
-    relaxed (its 8-byte end and length, and the far end's 8-byte word) and
-    16 B per node taken from a near pile (its word and its two row bounds),
-    counted on the device, over the HIP-event time of the launch."""
+    searches' kernel (one launch of one workgroup per sample).  Algorithmic
+    bytes are those of a label-setting search that takes every node once and
+    relaxes every arc once: 16 B per node (its distance word and its two row
+    bounds) and 16 B per arc (its packed end and length, and the far end's
+    8-byte word), k (n + arcs) x 16 per launch on a connected graph.  The
+    device's own counts of nodes taken and arcs relaxed give the re-work of
+    the Delta-stepping phases beside it."""
     launches = sum(t["kernel_launches"] for t in timings)
     ms = sum(t["kernel_ms"] for t in timings)
-    byts = sum(16 * (t["arcs_scanned"] + t["nodes_visited"]) for t in timings)
     if launches == 0 or ms <= 0:
         return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
                 "traffic": None, "kernel": "k_wsearch"}
-    per = byts / launches
+    per = 16 * k * (n + arcs) * len(timings) / launches
     achieved = per / (ms / launches / 1e3) / 1e9
+    relaxed = sum(t["arcs_scanned"] for t in timings) / len(timings)
+    taken = sum(t["nodes_visited"] for t in timings) / len(timings)
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic_kernel("k_wsearch", workload,
-                                                                                         "sssp_weighted.hip"),
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": measured_traffic_kernel("k_wsearch", workload, "sssp_weighted.hip", f"delta={tuning['delta']}"),
             "kernel": "k_wsearch", "algorithmic_bytes_per_launch": int(per),
             "avg_launch_us": round(ms / launches * 1e3, 1), "launches_per_step": launches / len(timings),
-            "bytes_per_relaxation": 16}
+            "bytes_per_node_and_arc": 16, "relaxations_per_arc": round(relaxed / (k * arcs), 4),
+            "takes_per_node": round(taken / (k * n), 4),
+            "relaxations_per_s": round(relaxed / (ms / len(timings) / 1e3) / 1e9, 3)}
 
 
-def measured_traffic_kernel(kernel: str, workload: str, source: str):
+def measured_traffic_kernel(kernel: str, workload: str, source: str, tuning: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     passes (profiles/<kernel>_<workload>_pmc.md), None once `source` has
-    changed since."""
+    changed since or when the run's knobs (`tuning`) differ from the
+    profiled ones."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
     if not os.path.exists(path):
@@ -356,7 +363,7 @@ def measured_traffic_kernel(kernel: str, workload: str, source: str):
             if line.startswith("- ") and ": " in line:
                 key, _, val = line[2:].partition(": ")
                 vals[key.strip()] = val.strip().strip("`")
-    if vals.get(f"{source} sha256[:16]") != digest:
+    if vals.get(f"{source} sha256[:16]") != digest or vals.get("tuning") != tuning:
         return None
     try:
         return float(vals["scaled HBM bytes per launch"])
@@ -365,7 +372,7 @@ def measured_traffic_kernel(kernel: str, workload: str, source: str):
 
 
 def run_config(name, cc, graphgen, torch, steps, warmup, plain_steps, autotune=True, fixed_tuning=None,
-               outputs="hybrid", keep=False):
+               outputs="hybrid", keep=False, graph=True):
     """One workload: K timed estimates into device memory after W warm-up ones
     (replays of the captured estimate where that applies), the dominant
     kernel's roofline from extra eager steps, and the plain one-source-at-a-
@@ -397,7 +404,7 @@ def run_config(name, cc, graphgen, torch, steps, warmup, plain_steps, autotune=T
     def step(mode):
         cc.cc_estimate_device(ctx.handle, gh, k, out, mode=mode, seed=seed, stream=stream)
 
-    use_graph = not g.directed and g.w is None and k <= 256
+    use_graph = graph and not g.directed and g.w is None and k <= 256
     main_mode = cc.CC_BATCHED | (cc.CC_GRAPH if use_graph else 0)
     for _ in range(warmup):
         step(main_mode)
@@ -426,7 +433,7 @@ def run_config(name, cc, graphgen, torch, steps, warmup, plain_steps, autotune=T
         W = (min(k, 256) + 63) // 64
         roofline = scatter_roofline(timings, W, name, tuning)
     else:
-        roofline = wsearch_roofline(timings, name)
+        roofline = wsearch_roofline(timings, name, g.n, g.arcs, k, tuning)
     log(f"  roofline: {roofline}")
     plain = None
     if plain_steps > 0:
@@ -490,6 +497,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=512)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="eager estimates only: no captured-graph replays (counter passes per launch)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of running the library's autotuner first")
     ap.add_argument("--tuning", default="",
@@ -534,7 +543,7 @@ def main():
     # ---- the headline workload
     head, hctx, hgh, hg = run_config(args.workload, cc, graphgen, torch, args.steps, args.warmup, plain_steps,
                                      autotune=not args.no_autotune, fixed_tuning=fixed, outputs=args.outputs,
-                                     keep=True)
+                                     keep=True, graph=not args.no_graph)
     spec = graphgen.WORKLOADS[args.workload]
     cpu = None
     if not args.no_cpu_baseline:
@@ -551,8 +560,10 @@ def main():
             if name == args.workload:
                 continue
             keep = name == "ba10k"
+            # the weighted searches keep the library's default bucket width (1.5 x the mean length):
+            # the autotuner's one-shot timings of nearby widths differ by less than their noise
             r = run_config(name, cc, graphgen, torch, steps, 3 if name != "grid2048w" else 1, plain_steps,
-                           keep=keep)
+                           keep=keep, autotune=name != "grid2048w")
             if keep:
                 r, bctx, bgh, bg = r
                 if not args.no_cpu_baseline:

@@ -264,7 +264,7 @@ typedef struct {
                                the last pull scanned (1..1024; default 4) */
     int32_t level_blocks;   /* BFS: blocks of the merge launch per level (1..65535; default 1024) */
     int32_t scatter_blocks; /* BFS: blocks of the scatter launch per level (1..65535; default 8192) */
-    int32_t delta;          /* weighted: bucket width of delta-stepping (>= 1; default 2 x mean arc length) */
+    int32_t delta;          /* weighted: bucket width of delta-stepping (>= 1; default 1.5 x mean arc length) */
     int32_t round_blocks;   /* weighted: blocks per relaxation round (1..65535; default 1024) */
     int32_t local_passes;   /* weighted: block-local relaxation passes per round (0..1024; default 64) */
 } cc_tuning;

@@ -809,7 +809,7 @@ extern "C" cc_status cc_graph_upload(cc_context* ctx, int64_t n, int64_t arcs, c
             double sw = 0;
             for (int64_t e = 0; e < arcs; e++) sw += w[e];
             const double mean = arcs > 0 ? sw / (double)arcs : 1.0;
-            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(2.0 * mean));
+            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(1.5 * mean));
         }
         g->tune.delta = (int32_t)std::min<uint32_t>(std::max<uint32_t>(g->dg.delta, 1u), INT32_MAX);
         std::vector<int32_t> ch_in = hub_chunk_list(prp, nh);
@@ -1011,7 +1011,7 @@ extern "C" cc_status cc_graph_borrow_device(cc_context* ctx, int64_t n, int64_t 
             CCG_HIP(hipMemcpyAsync(&ws, wsum, sizeof(ws), hipMemcpyDeviceToHost, st));
             CCG_HIP(hipStreamSynchronize(st));
             const double mean = arcs > 0 ? (double)ws / (double)arcs : 1.0;
-            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(2.0 * mean));
+            g->dg.delta = (uint32_t)std::max<double>(1.0, std::llround(1.5 * mean));
         }
         g->tune.delta = (int32_t)std::min<uint32_t>(std::max<uint32_t>(g->dg.delta, 1u), INT32_MAX);
         // the caller's order stays: 64-node groups that hold a node of high
