@@ -104,11 +104,18 @@ def scatter_roofline(timings, W: int, workload: str, tuning: dict) -> dict:
     achieved = per_launch / (avg_ms / 1e3) / 1e9
     pull_ms = sum(t["pull_scatter_ms"] for t in timings)
     pull_arcs = sum(t["hub_arcs"] for t in timings)
+    traffic = measured_traffic(workload, tuning)
+    level_ms = sum(t["kernel_ms"] for t in timings)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, tuning),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": SCATTER_KERNEL, "algorithmic_bytes_per_launch": int(per_launch),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": launches / len(timings),
             "bytes_per_arc": bytes_per_arc(W),
+            # the counters' bytes over the same launch time, beside the algorithmic figure
+            "traffic_gbs": None if traffic is None else round(traffic / (avg_ms / 1e3) / 1e9, 1),
+            "traffic_frac": None if traffic is None else round(traffic / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            # the scatter launches' share of the level batches (the rest: the merge launches and gaps)
+            "share_of_level_kernels": round(ms / level_ms, 3) if level_ms > 0 else None,
             "pull_levels_gbs": round(pull_arcs * bytes_per_arc(W) / (pull_ms / 1e3) / 1e9, 1) if pull_ms > 0 else None}
 
 
