@@ -202,6 +202,24 @@ def grid(rows: int, cols: int, nbr: int = 8, pdel: float = 0.0, wlo: int = 1, wh
     return largest_component(g) if component and pdel > 0 else g
 
 
+def with_lengths(g: Graph, wlo: int, whi: int, seed: int) -> Graph:
+    """The same arcs with integer lengths uniform in [wlo, whi] (numpy
+    PCG64); an undirected graph gets one length per edge, on both of its arcs."""
+    rng = np.random.default_rng(seed)
+    if g.directed:
+        w = rng.integers(wlo, whi + 1, size=g.arcs).astype(np.int32)
+        out = Graph(n=g.n, row_ptr=g.row_ptr.copy(), col_idx=g.col_idx.copy(), w=w, directed=True,
+                    name=f"{g.name}-w{wlo}_{whi}-s{seed}")
+    else:
+        src = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.row_ptr))
+        keep = src < g.col_idx
+        s, d = src[keep], g.col_idx[keep]
+        w = rng.integers(wlo, whi + 1, size=s.shape[0]).astype(np.int32)
+        out = csr_from_arcs(g.n, s, d, w, symmetrize=True, directed=False, name=f"{g.name}-w{wlo}_{whi}-s{seed}")
+    out.meta.update(g.meta)
+    return out
+
+
 def path(n: int) -> Graph:
     i = np.arange(n - 1, dtype=np.int32)
     return csr_from_arcs(n, i, i + 1, name=f"path{n}")
@@ -290,6 +308,9 @@ WORKLOADS = {
     # directed R-MAT scale 20, the whole graph (not strongly connected); reachability
     # sampling (Sec. 6.2) with k = 100 as in the paper's directed experiments
     "rmat20dir": dict(make=lambda: rmat(20, 16, seed=6, directed=True, component=False), k=100, sample_seed=6),
+    # the same digraph with arc lengths uniform in [1, 1000] (the listing's Dijkstra searches)
+    "rmat20dirw": dict(make=lambda: with_lengths(rmat(20, 16, seed=6, directed=True, component=False), 1, 1000, 7),
+                       k=100, sample_seed=7),
 }
 
 

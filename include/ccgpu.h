@@ -365,8 +365,12 @@ cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, const cc_weig
  * members ranked before the source, counting the node itself when it ranks
  * before it: this loses no member of any sample.  (Algorithm 4 as printed
  * stops at k members, which can lose a member: a node x whose k members
- * include v itself stops the search that v needed.)  Graphs with unit arc
- * lengths (undirected graphs give R(v) = the rest of v's component). */
+ * include v itself stops the search that v needed.)  Undirected graphs give
+ * R(v) = the rest of v's component.  Unit arc lengths run batches of up to
+ * 1024 sources as one bit-parallel BFS; with arc lengths (the listing's
+ * Dijkstra) d is the shortest-path length and batches of up to 256 sources
+ * run one delta-stepping search each (bucket width: the graph's tuning
+ * knob `delta`), pruned by the same rule against the earlier batches. */
 typedef struct {
     int32_t k;             /* sample size, k >= 1 */
     int32_t inbound;       /* 0: outbound (distances from v), 1: inbound (distances to v) */
@@ -381,9 +385,13 @@ typedef struct {
     double* R;
 } cc_reach_result;
 /* Synchronous; `out` holds HOST pointers (n entries each; any may be NULL).
- * CC_EINVAL: k < 1, inbound not 0 or 1, order not a permutation, or a graph
- * with arc lengths; CC_EOVERFLOW: a search deeper than 65535 levels; CC_ENOMEM.
- * Device state: about 128 + 36 bytes per node, allocated and freed per call. */
+ * CC_EINVAL: k < 1, inbound not 0 or 1, or order not a permutation;
+ * CC_EOVERFLOW: a search deeper than 65535 levels (unit lengths) or a
+ * distance above 2^31 - 2 (arc lengths); CC_EDEVICE: an arc-length search
+ * that ran past its two-minute limit; CC_ENOMEM.  Device state: about
+ * 128 + 36 bytes per node (unit lengths), or 24 bytes per node and source of
+ * a batch plus about 40 per node (arc lengths; the batch shrinks to fit a
+ * quarter of the free memory), held in the context's arena. */
 cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const cc_reach_params* p, cc_reach_result* out);
 
 /* Node-weighted reachability sampling (Sec. 6.2, Algorithm 5): the nodes u
@@ -403,7 +411,9 @@ cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const cc_reach_p
  *          R = (double)(sum of beta over the heavy) + (1/T) * (number light).
  *          (Algorithm 5's last step, S = (sum of beta d) / T, agrees for unit
  *          weights and is biased otherwise.)
- * Graphs with unit arc lengths; k <= 4096. */
+ * Unit arc lengths or arc lengths (shortest-path lengths, searched as for
+ * cc_reach_estimate); k <= 4096.  CC_EOVERFLOW when a weighted distance sum
+ * leaves int64 (arc lengths) or a search is deeper than 65535 levels. */
 typedef struct {
     int32_t k;
     int32_t inbound;        /* 0: outbound, 1: inbound */
@@ -417,7 +427,8 @@ typedef struct {
     double* R;
 } cc_reach_weighted_result;
 /* Synchronous; `out` holds HOST pointers (n entries each; any may be NULL).
- * Device state: about 6(k-1) + 170 bytes per node. */
+ * Device state: about 6(k-1) + 170 bytes per node (unit lengths), 8(k-1)
+ * more than cc_reach_estimate's with arc lengths. */
 cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const cc_reach_weighted_params* p,
                             cc_reach_weighted_result* out);
 

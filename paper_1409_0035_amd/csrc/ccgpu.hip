@@ -2213,13 +2213,30 @@ extern "C" cc_status cc_estimate_weighted(cc_context* ctx, const cc_graph* g, co
     });
 }
 
+// Scratch of a reachability run.  With arc lengths the searches take the
+// propagation arcs as (end, length) pairs and run up to 256 sources per batch,
+// fewer when a quarter of the free memory cannot hold their rows and piles.
+static size_t reach_scratch_for(const cc_graph* g, ReachArgs& a, int32_t inbound, int32_t k_weighted) {
+    if (!g->dg.weighted) return reach_scratch_bytes(a.n, a.arcs, k_weighted);
+    a.cw = inbound ? g->dg.cw : g->dg.rcw;
+    a.delta = (uint32_t)std::max(1, g->tune.delta);
+    const size_t base = reach_len_scratch_bytes(a.n, 1, k_weighted);
+    const size_t per = reach_len_scratch_bytes(a.n, 2, k_weighted) - base;
+    size_t free_b = 0, total_b = 0;
+    CCG_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t budget = free_b / 4;
+    int32_t S = 256;
+    while (S > 1 && base + per * (size_t)(S - 1) > budget) S /= 2;
+    a.len_sources = S;
+    return reach_len_scratch_bytes(a.n, S, k_weighted);
+}
+
 extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const cc_reach_weighted_params* p,
                                        cc_reach_weighted_result* out) {
     if (!ctx || !g || !p || !out || !p->beta) return fail(CC_EINVAL, "cc_reach_weighted: null argument");
     const int64_t n = g->dg.n;
     if (p->k < 1 || p->k > 4096) return fail(CC_EINVAL, "cc_reach_weighted: need 1 <= k <= 4096");
     if (p->inbound != 0 && p->inbound != 1) return fail(CC_EINVAL, "cc_reach_weighted: inbound must be 0 or 1");
-    if (g->dg.weighted) return fail(CC_EINVAL, "cc_reach_weighted: graphs with unit arc lengths only");
     // the nodes of positive weight are the sources; their priority ranks are
     // drawn and sorted on the device
     int64_t m = 0;
@@ -2262,7 +2279,7 @@ extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const
         a.order_dev = by_rank;
         a.beta = bd;
         a.U = Ud;
-        const size_t need = reach_scratch_bytes(n, a.arcs, p->k);
+        const size_t need = reach_scratch_for(g, a, p->inbound, p->k);
         ReachStats rs;
         run_reach(st, a, L.arena.get(need), need, &rs);
         if (out->count) CCG_HIP(hipMemcpyAsync(out->count, a.count, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
@@ -2271,13 +2288,17 @@ extern "C" cc_status cc_reach_weighted(cc_context* ctx, const cc_graph* g, const
         if (out->R) CCG_HIP(hipMemcpyAsync(out->R, a.R, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         CCG_HIP(hipEventRecord(L.ev[1], st));
         CCG_HIP(hipStreamSynchronize(st));
-        if (rs.overflow) return fail(CC_EOVERFLOW, "cc_reach_weighted: a search deeper than 65535 levels");
+        if (rs.timeout) return fail(CC_EDEVICE, "cc_reach_weighted: a search did not finish within its time limit");
+        if (rs.overflow)
+            return fail(CC_EOVERFLOW, g->dg.weighted ? "cc_reach_weighted: a distance or weighted sum out of range"
+                                                     : "cc_reach_weighted: a search deeper than 65535 levels");
         cc_timing t{};
         float ms = 0.f;
         CCG_HIP(hipEventElapsedTime(&ms, L.ev[0], L.ev[1]));
         t.total_ms = t.traverse_ms = ms;
         t.levels = rs.levels;
-        t.launches = rs.cycles * 3;
+        t.launches = rs.cycles * (g->dg.weighted ? 2 : 3);
+        t.arcs_scanned = rs.relaxed;
         ctx->last = t;
         return CC_OK;
     });
@@ -2289,7 +2310,6 @@ extern "C" cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const
     const int64_t n = g->dg.n;
     if (p->k < 1) return fail(CC_EINVAL, "cc_reach_estimate: need k >= 1");
     if (p->inbound != 0 && p->inbound != 1) return fail(CC_EINVAL, "cc_reach_estimate: inbound must be 0 or 1");
-    if (g->dg.weighted) return fail(CC_EINVAL, "cc_reach_estimate: graphs with unit arc lengths only");
     // rank order in internal ids
     std::vector<int32_t> order((size_t)n);
     if (p->order) {
@@ -2331,7 +2351,7 @@ extern "C" cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const
         a.T = a.distsum + n;
         a.B = (double*)(a.T + n);
         a.R = a.B + n;
-        const size_t need = reach_scratch_bytes(n, a.arcs);
+        const size_t need = reach_scratch_for(g, a, p->inbound, 0);
         ReachStats rs;
         run_reach(st, a, L.arena.get(need), need, &rs);
         if (out->count) CCG_HIP(hipMemcpyAsync(out->count, a.count, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
@@ -2342,13 +2362,17 @@ extern "C" cc_status cc_reach_estimate(cc_context* ctx, const cc_graph* g, const
         if (out->R) CCG_HIP(hipMemcpyAsync(out->R, a.R, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         CCG_HIP(hipEventRecord(L.ev[1], st));
         CCG_HIP(hipStreamSynchronize(st));
-        if (rs.overflow) return fail(CC_EOVERFLOW, "cc_reach_estimate: a search deeper than 65535 levels");
+        if (rs.timeout) return fail(CC_EDEVICE, "cc_reach_estimate: a search did not finish within its time limit");
+        if (rs.overflow)
+            return fail(CC_EOVERFLOW, g->dg.weighted ? "cc_reach_estimate: a distance out of range"
+                                                     : "cc_reach_estimate: a search deeper than 65535 levels");
         cc_timing t{};
         float ms = 0.f;
         CCG_HIP(hipEventElapsedTime(&ms, L.ev[0], L.ev[1]));
         t.total_ms = t.traverse_ms = ms;
         t.levels = rs.levels;
-        t.launches = rs.cycles * 3;
+        t.launches = rs.cycles * (g->dg.weighted ? 2 : 3);
+        t.arcs_scanned = rs.relaxed;
         ctx->last = t;
         return CC_OK;
     });

@@ -534,14 +534,25 @@ struct ReachArgs {
     const uint64_t* U = nullptr;
     int32_t* kth = nullptr;
     double* S_w = nullptr;
+    // graphs with arc lengths: the propagation arcs as (end, length) pairs,
+    // the delta-stepping bucket width, and the sources searched per batch
+    // (one workgroup each); cw set selects run_reach_lengths
+    const int2* cw = nullptr;
+    uint32_t delta = 1;
+    int32_t len_sources = 0;
 };
 struct ReachStats {
     int64_t cycles = 0;   // push/merge/account/init cycles enqueued
     int64_t batches = 0;
-    int64_t levels = 0;   // BFS levels run over all batches
-    bool overflow = false;  // some level above 65535: the result is not valid
+    int64_t levels = 0;   // BFS levels (arc lengths: delta-stepping phases) run over all batches
+    bool overflow = false;  // some level above 65535 (arc lengths: a distance or sum out of range)
+    bool timeout = false;   // arc lengths: a search ran past its time limit
+    int64_t relaxed = 0;    // arc lengths: arcs relaxed by all searches
 };
 size_t reach_scratch_bytes(int64_t n, int64_t arcs, int32_t k_weighted = 0);
+// Sources per batch and scratch of the arc-length searches (24 bytes per node
+// and source, plus per-node state)
+size_t reach_len_scratch_bytes(int64_t n, int32_t sources, int32_t k_weighted);
 // Algorithm 5's priority ranks: beta and U at internal ids, and the m nodes of
 // positive weight (internal ids) by increasing rank U / (2^53 beta)
 size_t priority_scratch_bytes(int64_t n);

@@ -601,22 +601,29 @@ __global__ void k_rch_out(ReachView V, const int32_t* __restrict__ orig, int32_t
 // Algorithm 5's estimates from the kept members: fewer than k, their exact
 // weighted sums; else priority sampling's weights max(beta, 1/T) for the
 // first k-1 members, T the rank U_k / (2^53 beta_k) of the k-th.
-__global__ void k_rch_out_beta(ReachView V, const int32_t* __restrict__ orig, const uint32_t* __restrict__ beta,
-                               const uint64_t* __restrict__ U, int32_t* count, int32_t* kth, double* S, double* R) {
+// Member distances are u16 levels (unit lengths) or u32 distances (arc
+// lengths); with arc lengths a weighted sum that leaves int64 sets *ovf.
+template <typename DT>
+__global__ void k_rch_out_beta(ReachView V, const DT* __restrict__ mem_d, const int32_t* __restrict__ orig,
+                               const uint32_t* __restrict__ beta, const uint64_t* __restrict__ U, int32_t* count,
+                               int32_t* kth, double* S, double* R, int32_t* ovf) {
     const int64_t n = V.n;
     const int32_t k = V.k;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t o = orig[v];
         const int32_t c = V.cnt[v] < k ? V.cnt[v] : k;
         const int32_t* mi = V.mem_id + v * (k - 1);
-        const uint16_t* md = V.mem_d + v * (k - 1);
+        const DT* md = mem_d + v * (k - 1);
+        bool bad = false;
         double s, r;
         int32_t q = -1;
         if (c < k) {
             int64_t ss = 0, rr = 0;
             for (int32_t j = 0; j < c; j++) {
                 const int64_t b = beta[mi[j]];
-                ss += b * md[j];
+                int64_t t;
+                bad |= __builtin_mul_overflow(b, (int64_t)md[j], &t);
+                bad |= __builtin_add_overflow(ss, t, &ss);
                 rr += b;
             }
             s = (double)ss;
@@ -630,7 +637,9 @@ __global__ void k_rch_out_beta(ReachView V, const int32_t* __restrict__ orig, co
             for (int32_t j = 0; j < k - 1; j++) {
                 const uint64_t b = beta[mi[j]];
                 if ((unsigned __int128)b * Uk >= ((unsigned __int128)bk << 53)) {  // heavy: its own weight
-                    hs += (int64_t)b * md[j];
+                    int64_t t;
+                    bad |= __builtin_mul_overflow((int64_t)b, (int64_t)md[j], &t);
+                    bad |= __builtin_add_overflow(hs, t, &hs);
                     hr += (int64_t)b;
                 } else {
                     ls += md[j];
@@ -640,6 +649,7 @@ __global__ void k_rch_out_beta(ReachView V, const int32_t* __restrict__ orig, co
             s = (double)hs + tau * (double)ls;
             r = (double)hr + tau * (double)lc;
         }
+        if (bad) *ovf = 1;
         if (count) count[o] = c;
         if (kth) kth[o] = q >= 0 ? orig[q] : -1;
         if (S) S[o] = s;
@@ -746,6 +756,413 @@ __global__ void k_rch_rank(const int32_t* __restrict__ order_internal, int64_t n
         rank[order_internal[r]] = (int32_t)r;
 }
 
+
+// ---- Algorithms 4 and 5 on graphs with arc lengths -------------------------
+//
+// The listing runs a pruned Dijkstra from each source in rank order.  Here a
+// batch of sources of consecutive ranks (those that can still pass their
+// membership on, as above) searches at once, one workgroup per source: the
+// near/far delta-stepping of the estimate's weighted searches on the
+// source's own row of 64-bit words 4d + flags (bit 0: in a near pile, bit 1:
+// in the far pile).  A search does not enter a node that holds more than k
+// members ranked before the batch (counting the node itself when it ranks
+// before it): every node that reaches such a node through it has k members
+// ranked before every source of the batch, so it needs none of them, and
+// the shortest path from a source to a node that needs it never passes such
+// a node.  Inside a batch a node counts only the earlier batches' members,
+// so a search may run on where the sequential searches would stop, never the
+// other way.  A node entered by a source for the first time joins the
+// batch's touched list once (a batch stamp per node).
+// Then one thread per touched node reads the batch's words at the node in
+// rank order, takes the first sources it still needs (its own aside), adds
+// their distances (or keeps them, Algorithm 5) and clears the words; the
+// last block picks the next batch.
+constexpr int kLBlock = 1024;  // threads per source's workgroup
+constexpr int kLGroup = 8;     // lanes per node
+constexpr int kLUnroll = 4;    // nodes a lane group has in flight
+constexpr int kLLq = 4096;     // near-pile entries kept in LDS
+constexpr int32_t kLFirstBatch = 128;
+constexpr uint64_t kLInfW = ~0ull << 2;
+constexpr uint64_t kLMaxDist = 0x7FFFFFFEull;
+enum : int32_t { kLSearch = 1, kLFinished = 3 };
+
+struct LenCtl {
+    ReachCtl rc;          // phase, batch, t0, tnext, nsrc, nt, ticket, overflow, levels, nact
+    int32_t timeout;      // a search ran past its time limit
+    int32_t pad;
+    uint64_t relaxed;     // arcs relaxed, all searches
+};
+
+struct LenView {
+    int64_t n;
+    int32_t k;
+    int32_t smax;                // sources per batch at most (workgroups per search launch)
+    const uint32_t* rp;          // propagation arcs
+    const int2* cw;              // their (end, length) pairs
+    const int32_t* rank;         // internal id -> rank (INT32_MAX: never a source)
+    const int32_t* act_src;      // sources with propagation arcs, in rank order
+    const int32_t* act_rank;
+    int32_t* cnt;                // members counted so far (exact up to k)
+    int64_t* dsum;
+    int64_t* tk;
+    uint64_t* W;                 // [smax][n] words, all 4d + flags = kLInfW between batches
+    int32_t* near;               // [smax][2][n]
+    int32_t* far;                // [smax][2][n]
+    int32_t* bsrc;               // [smax] the batch's sources in rank order
+    int32_t* brank;              // [smax] their ranks
+    int32_t* sbit;               // [n] index of the node in the batch when it is one of its sources, else -1
+    int32_t* stamp;              // [n] batch that last touched the node
+    int32_t* touched;            // [n] nodes touched in this batch
+    int32_t* mem_id;             // Algorithm 5: [n][k-1] the first k-1 members
+    uint32_t* mem_d;             // and their distances
+    uint32_t delta;
+    uint64_t time_limit;         // wall-clock ticks per search
+};
+
+__device__ __forceinline__ uint64_t rl_min(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t rl_and(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t rl_xor(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// First touch of node u by a search of this batch: the node joins the list.
+__device__ __forceinline__ void rl_touch(LenCtl* lc, const LenView& V, int32_t batch, bool first, int32_t u) {
+    bool ins = false;
+    if (first) ins = atomicExch(&V.stamp[u], batch) != batch;
+    const int pos = wave_append(&lc->rc.nt, ins);
+    if (pos >= 0) V.touched[pos] = u;
+}
+
+__global__ __launch_bounds__(kLBlock) void k_rl_search(LenCtl* lc, LenView V) {
+    ReachCtl* ctl = &lc->rc;
+    if (ctl->phase != kLSearch) return;
+    const int32_t j = blockIdx.x;
+    if (j >= ctl->nsrc) return;
+    const int64_t n = V.n;
+    const int64_t t0 = ctl->t0;
+    const int32_t batch = ctl->batch;
+    const int64_t k = V.k;
+    const uint32_t delta = V.delta;
+    uint64_t* W = V.W + (int64_t)j * n;
+    int32_t* nsp = V.near + (int64_t)j * 2 * n;
+    int32_t* fsp = V.far + (int64_t)j * 2 * n;
+    __shared__ int32_t lq[2][kLLq];
+    __shared__ int32_t s_cnt[2];  // entries of the next near pile; of the far pile being built
+    __shared__ int32_t s_nq, s_nf, s_qsel, s_fsel, s_stop, s_ovf, s_phases;
+    __shared__ uint32_t s_hi;
+    __shared__ uint32_t s_min[kLBlock / 64];
+    __shared__ unsigned long long s_relaxed;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int sub = lane & (kLGroup - 1), glane = lane & ~(kLGroup - 1);
+    auto put_near = [&](int p, int32_t pos, int32_t v) {
+        if (pos < kLLq) lq[p][pos] = v;
+        else nsp[(int64_t)p * n + pos] = v;
+    };
+    if (threadIdx.x == 0) {
+        const int32_t src = V.bsrc[j];
+        W[src] = 1;  // distance 0, in the first near pile
+        put_near(0, 0, src);
+        s_nq = 1;
+        s_nf = 0;
+        s_qsel = 0;
+        s_fsel = 0;
+        s_hi = delta;
+        s_stop = 0;
+        s_ovf = 0;
+        s_phases = 0;
+        s_cnt[0] = s_cnt[1] = 0;
+        s_relaxed = 0;
+    }
+    if (wave == 0) rl_touch(lc, V, batch, lane == 0, V.bsrc[j]);  // its word is cleared by the account
+    __syncthreads();
+    const uint64_t c0 = wall_clock64();
+    constexpr int kPerWave = 64 / kLGroup;
+    uint64_t my_relaxed = 0;
+    for (;;) {
+        const int32_t nq = s_nq;
+        const uint32_t hi = s_hi;
+        const int pin = s_qsel, pout = s_qsel ^ 1;
+        int32_t* fpile = fsp + (int64_t)s_fsel * n;
+        if (nq > 0) {
+            for (int32_t base = wave * kPerWave * kLUnroll; base < nq; base += (kLBlock / 64) * kPerWave * kLUnroll) {
+                int32_t v[kLUnroll];
+                uint64_t d[kLUnroll];
+                uint32_t b[kLUnroll], e[kLUnroll];
+                bool valid[kLUnroll];
+#pragma unroll
+                for (int r = 0; r < kLUnroll; r++) {
+                    const int32_t t = base + r * kPerWave + lane / kLGroup;
+                    valid[r] = t < nq;
+                    v[r] = valid[r] ? (t < kLLq ? lq[pin][t] : nsp[(int64_t)pin * n + t]) : 0;
+                    d[r] = 0;
+                    b[r] = e[r] = 0;
+                }
+#pragma unroll
+                for (int r = 0; r < kLUnroll; r++) {
+                    if (valid[r]) {
+                        if (sub == 0) d[r] = rl_and(&W[v[r]], ~1ull) >> 2;  // leaves the near pile
+                        else if (sub == 1) b[r] = V.rp[v[r]];
+                        else if (sub == 2) e[r] = V.rp[v[r] + 1];
+                    }
+                }
+                uint32_t trips = 0;
+#pragma unroll
+                for (int r = 0; r < kLUnroll; r++) {
+                    d[r] = (uint64_t)__shfl((long long)d[r], glane);
+                    b[r] = (uint32_t)__shfl((int)b[r], glane + 1);
+                    e[r] = (uint32_t)__shfl((int)e[r], glane + 2);
+                    if (valid[r]) trips = max(trips, (e[r] - b[r] + kLGroup - 1) / kLGroup);
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) trips = max(trips, (uint32_t)__shfl_xor((int)trips, off));
+                for (uint32_t it = 0; it < trips; it++) {
+                    int32_t u[kLUnroll];
+                    uint64_t c[kLUnroll], o[kLUnroll];
+#pragma unroll
+                    for (int r = 0; r < kLUnroll; r++) {
+                        const uint32_t a = b[r] + it * kLGroup + sub;
+                        u[r] = -1;
+                        c[r] = 0;
+                        if (valid[r] && a < e[r]) {
+                            const int2 x = V.cw[a];
+                            u[r] = x.x;
+                            c[r] = d[r] + (uint32_t)x.y;
+                        }
+                    }
+                    // a node holding more than k members ranked before the batch takes no part
+#pragma unroll
+                    for (int r = 0; r < kLUnroll; r++)
+                        if (u[r] >= 0 && (int64_t)V.cnt[u[r]] + (V.rank[u[r]] < t0 ? 1 : 0) > k) u[r] = -1;
+#pragma unroll
+                    for (int r = 0; r < kLUnroll; r++) {
+                        o[r] = 0;
+                        if (u[r] >= 0) {
+                            my_relaxed++;
+                            if (c[r] > kLMaxDist) s_ovf = 1;
+                            o[r] = rl_min(&W[u[r]], (c[r] << 2) | (c[r] < hi ? 1ull : 2ull));
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < kLUnroll; r++) {
+                        const bool better = u[r] >= 0 && c[r] < (o[r] >> 2);
+                        const bool nr = c[r] < hi;
+                        const int pn = wave_append(&s_cnt[0], better && nr && !(o[r] & 1ull));
+                        if (pn >= 0) put_near(pout, pn, u[r]);
+                        const int pf = wave_append(&s_cnt[1], better && !nr && !(o[r] & 2ull));
+                        if (pf >= 0) fpile[pf] = u[r];
+                        rl_touch(lc, V, batch, better && o[r] == kLInfW, u[r]);
+                    }
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_nq = s_cnt[0];
+                s_nf = s_cnt[1];
+                s_cnt[0] = 0;
+                s_qsel ^= 1;
+                s_phases++;
+                if (s_ovf || wall_clock64() - c0 > V.time_limit) s_stop = 1;
+            }
+            __syncthreads();
+            if (s_stop) break;
+            continue;
+        }
+        // the near pile is empty: the next bucket from the far pile
+        const int32_t nf = s_nf;
+        if (nf == 0) break;
+        uint64_t m = kLMaxDist + 1ull;
+        for (int32_t t = threadIdx.x; t < nf; t += kLBlock) {
+            const uint64_t dv = __hip_atomic_load(&W[fpile[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 2;
+            if (dv >= hi && dv < m) m = dv;
+        }
+        uint32_t m32 = (uint32_t)m;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t y = (uint32_t)__shfl_xor((int)m32, off);
+            m32 = y < m32 ? y : m32;
+        }
+        if (lane == 0) s_min[wave] = m32;
+        if (threadIdx.x == 0) s_cnt[1] = 0;
+        __syncthreads();
+        uint32_t mm = 0xFFFFFFFFu;
+        for (int w = 0; w < kLBlock / 64; w++) mm = s_min[w] < mm ? s_min[w] : mm;
+        const uint64_t nh = mm > kLMaxDist ? (uint64_t)hi : ((uint64_t)mm / delta + 1) * (uint64_t)delta;
+        const uint32_t nhi = nh > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)nh;
+        int32_t* fnext = fsp + (int64_t)(s_fsel ^ 1) * n;
+        for (int32_t base = wave * 64; base < nf; base += kLBlock) {
+            const int32_t t = base + lane;
+            const bool ok = t < nf;
+            const int32_t v = ok ? fpile[t] : 0;
+            bool to_near = false, keep = false;
+            if (ok) {
+                const uint64_t dv = __hip_atomic_load(&W[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 2;
+                if (dv >= nhi) keep = true;
+                else if (dv >= hi) to_near = (rl_xor(&W[v], 3ull) & 3ull) == 2ull;  // far pile -> near pile
+            }
+            const int pn = wave_append(&s_cnt[0], to_near);
+            if (pn >= 0) put_near(pin, pn, v);
+            const int pk = wave_append(&s_cnt[1], keep);
+            if (pk >= 0) fnext[pk] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_nq = s_cnt[0];
+            s_nf = s_cnt[1];
+            s_cnt[0] = 0;
+            s_fsel ^= 1;
+            s_hi = nhi;
+            if (wall_clock64() - c0 > V.time_limit) s_stop = 1;
+        }
+        __syncthreads();
+        if (s_stop) break;
+    }
+    atomicAdd(&s_relaxed, (unsigned long long)my_relaxed);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&lc->relaxed, s_relaxed);
+        atomicAdd((unsigned long long*)&ctl->levels, (unsigned long long)s_phases);
+        if (s_ovf) atomicOr(&ctl->overflow, 1);
+        else if (s_stop) atomicOr(&lc->timeout, 1);
+    }
+}
+
+// The last block of the account picks the next batch: up to cap sources of
+// the list of sources with propagation arcs, from tnext on, that hold at most
+// k members (the others can pass their membership to nobody), in rank order.
+__device__ void rl_start_batch(LenCtl* lc, const LenView& V) {
+    ReachCtl* ctl = &lc->rc;
+    __shared__ int32_t wcount[kBlock / 64];
+    __shared__ int32_t got;
+    __shared__ int64_t scan, next_scan;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int32_t batch = ctl->batch;  // 1 for the first batch
+    const int32_t cap = (int32_t)std::min<int64_t>(V.smax, (int64_t)kLFirstBatch << std::min(batch - 1, 16));
+    const int64_t nact = ctl->nact;
+    if (threadIdx.x == 0) {
+        got = 0;
+        scan = ctl->tnext;
+    }
+    __syncthreads();
+    while (got < cap && scan < nact) {
+        const int64_t i = scan + threadIdx.x;
+        int32_t s = -1, rk = 0;
+        bool take = false;
+        if (i < nact) {
+            s = V.act_src[i];
+            rk = V.act_rank[i];
+            take = V.cnt[s] <= V.k;
+        }
+        const uint64_t m = __ballot(take);
+        if (lane == 0) wcount[wave] = (int32_t)__popcll(m);
+        if (threadIdx.x == 0) next_scan = scan + kBlock;
+        __syncthreads();
+        int32_t pos = got + (int32_t)__popcll(m & lanemask_lt());
+        int32_t total = 0;
+        for (int w = 0; w < kBlock / 64; w++) {
+            if (w < wave) pos += wcount[w];
+            total += wcount[w];
+        }
+        if (take && pos < cap) {
+            V.bsrc[pos] = s;
+            V.brank[pos] = rk;
+            V.sbit[s] = pos;
+        }
+        if (take && pos == cap - 1) next_scan = i + 1;  // the batch is full: go on after its last source
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            got = got + total < cap ? got + total : cap;
+            scan = next_scan;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctl->tnext = scan < nact ? scan : nact;
+        ctl->nsrc = got;
+        ctl->nt = 0;
+        ctl->t0 = got > 0 ? V.brank[0] : V.n;
+        ctl->phase = got > 0 ? kLSearch : kLFinished;
+        __threadfence();
+    }
+}
+
+// Runs after every search launch: the batch that launch searched (none
+// before the first) is accounted, then the next one is picked.
+__global__ __launch_bounds__(kBlock) void k_rl_account(LenCtl* lc, LenView V) {
+    ReachCtl* ctl = &lc->rc;
+    if (ctl->phase != kLSearch) return;
+    const int32_t nt = ctl->nt;
+    const int32_t S = ctl->nsrc;
+    const int32_t k = V.k;
+    const int64_t n = V.n;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nt; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t y = V.touched[i];
+        const int32_t own = V.sbit[y];
+        if (own >= 0) V.sbit[y] = -1;  // its own search counts nothing for itself
+        const int32_t c = V.cnt[y];
+        const int64_t r = V.rank[y];
+        int32_t pc = 0, taken = 0;
+        int64_t sum = 0, last_rk = -1;
+        for (int32_t j0 = 0; j0 < S; j0 += 8) {
+            uint64_t x[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) x[q] = j0 + q < S ? V.W[(int64_t)(j0 + q) * n + y] : kLInfW;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                if (x[q] == kLInfW) continue;
+                const int32_t jj = j0 + q;
+                V.W[(int64_t)jj * n + y] = kLInfW;
+                if (jj == own) continue;
+                pc++;
+                if (c + taken < k) {  // the members it still needs, in rank order
+                    const uint32_t dd = (uint32_t)(x[q] >> 2);
+                    sum += dd;
+                    if (V.mem_id) {  // Algorithm 5: keep the member, or the k-th's id
+                        const int32_t slot = c + taken;
+                        if (slot < k - 1) {
+                            V.mem_id[y * (k - 1) + slot] = V.bsrc[jj];
+                            V.mem_d[y * (k - 1) + slot] = dd;
+                        } else {
+                            V.tk[y] = V.bsrc[jj];
+                        }
+                    }
+                    taken++;
+                    last_rk = V.brank[jj];
+                }
+            }
+        }
+        if (c < k) {
+            if (c + taken == k && !V.mem_id) V.tk[y] = (last_rk + 1) - (r < last_rk ? 1 : 0);
+            V.dsum[y] += sum;
+        }
+        V.cnt[y] = c + pc;
+    }
+    __syncthreads();
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        if (threadIdx.x == 0) {
+            ctl->ticket = 0;
+            ctl->batch = ctl->batch + 1;
+        }
+        __syncthreads();
+        rl_start_batch(lc, V);
+    }
+}
+
+__global__ void k_rl_fill64(uint64_t* p, int64_t count, uint64_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 }  // namespace
 
 size_t reach_scratch_bytes(int64_t n, int64_t arcs, int32_t k_weighted) {
@@ -762,7 +1179,157 @@ size_t reach_scratch_bytes(int64_t n, int64_t arcs, int32_t k_weighted) {
            al(sizeof(uint64_t) * 2 * (size_t)frontier_cap(n, arcs)) /* flist */ + 2 * i32 /* cand, touched */ + 1024;
 }
 
+size_t reach_len_scratch_bytes(int64_t n, int32_t sources, int32_t k_weighted) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t i32 = al(sizeof(int32_t) * n), i64 = al(sizeof(int64_t) * n);
+    const size_t kw = (size_t)std::max(1, k_weighted - 1);
+    const size_t nb = (size_t)((n + kActChunk - 1) / kActChunk) + 1;
+    const size_t S = (size_t)std::max(1, sources);
+    return al(sizeof(LenCtl)) + 4 * i32 /* rank, src_by_rank, act_src, act_rank */ + al(sizeof(int32_t) * nb) +
+           i32 + 2 * i64 /* cnt, dsum, tk */ + al(sizeof(uint64_t) * S * n) /* W */ +
+           2 * al(sizeof(int32_t) * S * 2 * n) /* near, far */ + 2 * al(sizeof(int32_t) * S) /* bsrc, brank */ +
+           3 * i32 /* sbit, stamp, touched */ +
+           (k_weighted > 0 ? al(sizeof(int32_t) * n * kw) + al(sizeof(uint32_t) * n * kw) : 0) + 1024;
+}
+
+// Algorithms 4 and 5 with arc lengths (the kernels above): batches of
+// searches, one workgroup per source, then the account, enqueued in cycles
+// that read nothing back until a chunk of them has run.
+static void run_reach_lengths(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size,
+                              ReachStats* stats) {
+    const int64_t n = a.n;
+    const bool weighted = a.beta != nullptr;
+    const int32_t S = std::max(1, a.len_sources);
+    if (scratch_size < reach_len_scratch_bytes(n, S, weighted ? a.k : 0))
+        throw HipError{hipErrorOutOfMemory, "reach (arc lengths) scratch"};
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    char* p = (char*)scratch;
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += al(bytes);
+        return (void*)q;
+    };
+    LenCtl* lc = (LenCtl*)take(sizeof(LenCtl));
+    LenView V{};
+    V.n = n;
+    V.k = a.k;
+    V.smax = S;
+    V.rp = a.rp;
+    V.cw = a.cw;
+    V.delta = std::max<uint32_t>(1, a.delta);
+    int32_t* rank = (int32_t*)take(sizeof(int32_t) * n);
+    int32_t* sbr = (int32_t*)take(sizeof(int32_t) * n);
+    int32_t* act_src = (int32_t*)take(sizeof(int32_t) * n);
+    int32_t* act_rank = (int32_t*)take(sizeof(int32_t) * n);
+    int32_t* act_blk = (int32_t*)take(sizeof(int32_t) * ((size_t)((n + kActChunk - 1) / kActChunk) + 1));
+    V.rank = rank;
+    V.act_src = act_src;
+    V.act_rank = act_rank;
+    V.cnt = (int32_t*)take(sizeof(int32_t) * n);
+    V.dsum = (int64_t*)take(sizeof(int64_t) * n);
+    V.tk = (int64_t*)take(sizeof(int64_t) * n);
+    V.W = (uint64_t*)take(sizeof(uint64_t) * (size_t)S * n);
+    V.near = (int32_t*)take(sizeof(int32_t) * (size_t)S * 2 * n);
+    V.far = (int32_t*)take(sizeof(int32_t) * (size_t)S * 2 * n);
+    V.bsrc = (int32_t*)take(sizeof(int32_t) * S);
+    V.brank = (int32_t*)take(sizeof(int32_t) * S);
+    V.sbit = (int32_t*)take(sizeof(int32_t) * n);
+    V.stamp = (int32_t*)take(sizeof(int32_t) * n);
+    V.touched = (int32_t*)take(sizeof(int32_t) * n);
+    if (weighted) {
+        V.mem_id = (int32_t*)take(sizeof(int32_t) * n * std::max(1, a.k - 1));
+        V.mem_d = (uint32_t*)take(sizeof(uint32_t) * n * std::max(1, a.k - 1));
+    }
+    int rate_khz = 0, device = 0;
+    CCG_HIP(hipGetDevice(&device));
+    CCG_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device));
+    V.time_limit = (uint64_t)std::max(rate_khz, 1) * 120000ull;  // two minutes per search
+
+    // the rank order and the list of sources with propagation arcs, as in the unit-length path
+    ReachView R{};
+    R.n = n;
+    R.nsrc = a.nsrc > 0 ? a.nsrc : n;
+    R.k = a.k;
+    R.rp = a.rp;
+    R.rank = rank;
+    R.src_by_rank = sbr;
+    R.act_src = act_src;
+    R.act_rank = act_rank;
+    R.act_blk = act_blk;
+    R.cnt = V.cnt;
+    R.dsum = V.dsum;
+    R.tk = V.tk;
+    R.mem_id = V.mem_id;
+    if (a.order_dev)
+        CCG_HIP(hipMemcpyAsync(sbr, a.order_dev, sizeof(int32_t) * R.nsrc, hipMemcpyDeviceToDevice, st));
+    else
+        CCG_HIP(hipMemcpyAsync(sbr, a.order, sizeof(int32_t) * R.nsrc, hipMemcpyHostToDevice, st));
+    const unsigned gn = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+    fill_u32(st, rank, 0x7FFFFFFFu, (size_t)n);
+    hipLaunchKernelGGL(k_rch_rank, dim3(gn), dim3(256), 0, st, (const int32_t*)sbr, R.nsrc, rank);
+    fill_u32(st, V.cnt, 0u, (size_t)n);
+    fill_u32(st, V.dsum, 0u, (size_t)n * 2);
+    fill_u32(st, V.tk, 0u, (size_t)n * 2);
+    fill_u32(st, V.sbit, 0xFFFFFFFFu, (size_t)n);
+    fill_u32(st, V.stamp, 0xFFFFFFFFu, (size_t)n);
+    fill_u32(st, lc, 0u, sizeof(LenCtl) / 4);
+    const int64_t words = (int64_t)S * n;
+    hipLaunchKernelGGL(k_rl_fill64, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 255) / 256, 65536))),
+                       dim3(256), 0, st, V.W, words, kLInfW);
+    const int32_t nb = (int32_t)((R.nsrc + kActChunk - 1) / kActChunk);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_rch_act_count, dim3((unsigned)nb), dim3(kBlock), 0, st, R);
+        hipLaunchKernelGGL(k_rch_act_scan, dim3(1), dim3(kBlock), 0, st, &lc->rc, R, nb);
+        hipLaunchKernelGGL(k_rch_act_put, dim3((unsigned)nb), dim3(kBlock), 0, st, R);
+    }
+    // start with an empty batch: the first search launch finds nothing to do and
+    // the account after it picks the first batch
+    hipLaunchKernelGGL(k_rch_set_phase, dim3(1), dim3(1), 0, st, &lc->rc, (int32_t)kLSearch);
+    CCG_HIP(hipGetLastError());
+
+    const unsigned ga = (unsigned)std::max(1, a.account_blocks);
+    const int64_t max_cycles = R.nsrc + 4;  // every batch but the last takes at least one source
+    int64_t cycles = 0;
+    int32_t chunk = 4;
+    LenCtl hc{};
+    for (;;) {
+        for (int32_t c = 0; c < chunk; c++) {
+            hipLaunchKernelGGL(k_rl_search, dim3((unsigned)S), dim3(kLBlock), 0, st, lc, V);
+            hipLaunchKernelGGL(k_rl_account, dim3(ga), dim3(kBlock), 0, st, lc, V);
+        }
+        CCG_HIP(hipGetLastError());
+        cycles += chunk;
+        CCG_HIP(hipMemcpyAsync(&hc, lc, sizeof(hc), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+        if (hc.rc.phase == kLFinished || hc.rc.overflow || hc.timeout) break;
+        if (cycles > max_cycles) throw HipError{hipErrorLaunchTimeOut, "reachability sampling did not finish"};
+        if (chunk < 64) chunk *= 2;
+    }
+    if (!hc.rc.overflow && !hc.timeout) {
+        if (weighted)
+            hipLaunchKernelGGL(k_rch_out_beta<uint32_t>, dim3(gn), dim3(256), 0, st, R, (const uint32_t*)V.mem_d,
+                               a.orig, a.beta, a.U, a.count, a.kth, a.S_w, a.R, &lc->rc.overflow);
+        else
+            hipLaunchKernelGGL(k_rch_out, dim3(gn), dim3(256), 0, st, R, a.orig, a.count, a.distsum, a.T, a.B, a.R);
+        CCG_HIP(hipGetLastError());
+        CCG_HIP(hipMemcpyAsync(&hc, lc, sizeof(hc), hipMemcpyDeviceToHost, st));
+        CCG_HIP(hipStreamSynchronize(st));
+    }
+    if (stats) {
+        stats->cycles = cycles;
+        stats->batches = hc.rc.batch;
+        stats->levels = hc.rc.levels;
+        stats->overflow = hc.rc.overflow != 0;
+        stats->timeout = hc.timeout != 0;
+        stats->relaxed = (int64_t)hc.relaxed;
+    }
+}
+
 void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch_size, ReachStats* stats) {
+    if (a.cw) {
+        run_reach_lengths(st, a, scratch, scratch_size, stats);
+        return;
+    }
     constexpr int W = kReachWords;
     const int64_t n = a.n;
     const bool weighted = a.beta != nullptr;
@@ -857,8 +1424,8 @@ void run_reach(hipStream_t st, const ReachArgs& a, void* scratch, size_t scratch
         if (chunk < 256) chunk *= 2;
     }
     if (weighted)
-        hipLaunchKernelGGL(k_rch_out_beta, dim3(gn), dim3(256), 0, st, V, a.orig, a.beta, a.U, a.count, a.kth, a.S_w,
-                           a.R);
+        hipLaunchKernelGGL(k_rch_out_beta<uint16_t>, dim3(gn), dim3(256), 0, st, V, (const uint16_t*)V.mem_d, a.orig,
+                           a.beta, a.U, a.count, a.kth, a.S_w, a.R, &ctl->overflow);
     else
         hipLaunchKernelGGL(k_rch_out, dim3(gn), dim3(256), 0, st, V, a.orig, a.count, a.distsum, a.T, a.B, a.R);
     CCG_HIP(hipGetLastError());
