@@ -334,6 +334,8 @@ struct Lane {
     struct Readback {
         BfsCtl ctl;
         DevFlags flags;
+        BfsCtl ctl_fwd;  // a round-trip replay: the forward search's control block
+        DevFlags flags_fwd;
         int32_t ids[kStagedSamples];     // the samples, internal ids (read by the traversal's first launch)
         int32_t caller[kStagedSamples];  // the same, as the caller numbers them
     };
@@ -350,6 +352,7 @@ struct Lane {
         std::vector<uint64_t> key;
         hipGraphExec_t exec = nullptr;
         int32_t lmax = 0, levels = 0;
+        int32_t lmax_fwd = -1, levels_fwd = 0;  // round trip: the forward search (the reverse one above)
     };
     std::vector<Captured> captured;  // most recently used last
     static constexpr size_t kMaxCaptured = 8;
@@ -1280,6 +1283,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
     for (int attempt = 0; attempt < 16; attempt++) {
         const bool batched = mode == CC_BATCHED && !g.weighted;
         const bool bits_path = batched && !g.directed && k <= 256;
+        // a round trip of one sample group: both searches and the D-based epilogue can be captured
+        const bool rt_single = batched && g.directed && k <= kStagedSamples;
         TravStats stats;
         const size_t dbytes = (size_t)n * k * (int)dk;
         // weighted: samples per call (one workgroup and 16n + n/8 bytes of
@@ -1318,7 +1323,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
 
         // a single-group traversal takes its samples from the lane's pinned staging
         // buffer in its first launch (replays included), others from a copy
-        const bool stage_samples = bits_path && k <= kStagedSamples;
+        const bool stage_samples = (bits_path || rt_single) && k <= kStagedSamples;
         if (stage_samples) {
             CCG_HIP(hipStreamSynchronize(st));  // the lane's earlier launches are done with the buffer
             std::memcpy(L.rb_host->ids, samples_int.data(), sizeof(int32_t) * k);
@@ -1355,7 +1360,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             return gv;
         };
         // a captured estimate is keyed by everything its launches refer to
-        const bool want_graph = r.graph && bits_path;
+        const bool want_graph = r.graph && (bits_path || rt_single);
         auto graph_key = [&]() {
             return std::vector<uint64_t>{gr->id, (uint64_t)k, (uint64_t)r.en, (uint64_t)r.ed, (uint64_t)cap,
                                          (uint64_t)(uintptr_t)st, L.gen, (uint64_t)(uintptr_t)out->S_hyb,
@@ -1374,14 +1379,23 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 // the graph takes the staged samples and writes the control block and
                 // flags back itself; a readback that did not land fails the check below
                 L.rb_host->ctl.done = -1;
+                L.rb_host->ctl_fwd.done = -1;
                 CCG_HIP(hipEventRecord(L.ev[0], st));
                 CCG_HIP(hipGraphLaunch(cap_e->exec, st));
                 CCG_HIP(hipEventRecord(L.ev[2], st));
                 CCG_HIP(hipStreamSynchronize(st));
                 const BfsCtl hc = L.rb_host->ctl;
                 const DevFlags hf = L.rb_host->flags;
-                if (hc.done == 1 && hc.status == 0 && hc.lmax == cap_e->lmax && hc.levels <= cap_e->levels &&
-                    !hf.disconnected && !hf.overflow && !hf.bad_sample && !hf.timeout) {
+                // a round trip: the forward search must also have ended where the captured one did
+                bool fwd_ok = true;
+                if (cap_e->lmax_fwd >= 0) {
+                    const BfsCtl hc0 = L.rb_host->ctl_fwd;
+                    fwd_ok = hc0.done == 1 && hc0.status == 0 && hc0.lmax == cap_e->lmax_fwd &&
+                             hc0.levels <= cap_e->levels_fwd;
+                }
+                if (fwd_ok && hc.done == 1 && hc.status == 0 && hc.lmax == cap_e->lmax &&
+                    hc.levels <= cap_e->levels && !hf.disconnected && !hf.overflow && !hf.bad_sample &&
+                    !hf.timeout) {
                     if (timing) {
                         *timing = cc_timing{};
                         timing->total_ms = timing->traverse_ms = elapsed(L.ev[0], L.ev[2]);
@@ -1399,13 +1413,14 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         }
         // the batched traversal of a single sample group zeroes the flags and
         // the histogram and fills sidx in its own first launches
-        if (!bits_path) fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+        if (!bits_path && !rt_single) fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
         CCG_HIP(hipEventRecord(L.ev[0], st));
-        if (!bits_path) compute_sidx(st, samples_dev, k, sidx, n);
+        if (!bits_path && !rt_single) compute_sidx(st, samples_dev, k, sidx, n);
 
         // ---- traversal
         int rc = 0;
         int32_t lmax_dir[2] = {0, 0};
+        int32_t levels_dir[2] = {0, 0};  // levels each direction's batched traversal ran
         for (int dir = 0; dir < (g.directed ? 2 : 1) && rc == 0; dir++) {
             // forward distances d(c_i -> v): push over out-arcs, pull over in-arcs;
             // reverse distances d(v -> c_i): the same on the transposed graph
@@ -1456,10 +1471,11 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     lv.hlen = cap;
                     lv.lmax = &lm;
                     lv.hint = gr->bfs_hint.load(std::memory_order_relaxed);
-                    if (bits_path) {
+                    if (bits_path || (rt_single && dir == 0)) {
+                        // the job's setup in the first traversal's launches
                         lv.zero_flags = flags;
                         lv.sidx_fill = sidx;
-                        lv.zero_hist = true;
+                        lv.zero_hist = bits_path;
                         stage_into(lv);
                     }
                     rc = bfs_batched(st, gv, samples_dev, kg, s0, k, lv, sidx, ts, trav_scratch, cnt, &ds,
@@ -1467,6 +1483,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     if (rc == 0) gr->bfs_hint.store(ds.bfs_levels, std::memory_order_relaxed);
                     if (rc != 0) break;
                     lmax_dir[dir] = std::max(lmax_dir[dir], lm);
+                    levels_dir[dir] = std::max(levels_dir[dir], ds.bfs_levels);
                     if (!bits_path) {
                         if ((int64_t)lm > DistT<uint8_t>::max_level && dk == DistKind::U8) { rc = 3; break; }
                         if ((int64_t)lm > DistT<uint16_t>::max_level && dk == DistKind::U16) { rc = 3; break; }
@@ -1501,6 +1518,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         BitsEpilogueArgs ba;
         void* ba_scratch = nullptr;
         size_t ba_es = 0;
+        EpilogueArgs ea;
+        void* ea_scratch = nullptr;
+        size_t ea_es = 0;
         if (bits_path) {
             ba.n = n;
             ba.k = k;
@@ -1543,7 +1563,6 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
             L.last_maxd = ba.lmax;
         } else {
-            EpilogueArgs ea;
             ea.n = n;
             ea.k = k;
             ea.dk = dk;
@@ -1556,9 +1575,14 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ea.eps_num = r.en;
             ea.eps_den = r.ed;
             fill_epilogue_outputs(ea, out, src_sum, dmat);
-            const size_t es = epilogue_scratch(
-                n, k, ea.maxd, false, out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err);
-            run_epilogue(st, ea, es <= trav_scratch ? ts : L.arena2.get(es), es, flags);
+            ea_es = epilogue_scratch(n, k, ea.maxd, false,
+                                     out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err);
+            // a round trip that may be replayed keeps the traversal's control block
+            // intact: a replay reads it back after the epilogue
+            const size_t ts_free =
+                rt_single ? (size_t)((char*)bfs_batched_ctl(ts, n, kg0) - (char*)ts) : trav_scratch;
+            ea_scratch = ea_es <= ts_free ? ts : L.arena2.get(ea_es);
+            run_epilogue(st, ea, ea_scratch, ea_es, flags);
             L.last_maxd = ea.maxd;
         }
         if (out->samples && !stage_samples)
@@ -1574,31 +1598,48 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             // the epilogue for its deepest level) for replay; nothing runs now
             Lane::Captured cap_e;
             cap_e.key = graph_key();
-            cap_e.lmax = ba.lmax;
-            cap_e.levels = stats.bfs_levels;
+            cap_e.lmax = bits_path ? ba.lmax : lmax_dir[1];
+            cap_e.levels = bits_path ? stats.bfs_levels : levels_dir[1];
+            if (rt_single) {
+                cap_e.lmax_fwd = lmax_dir[0];
+                cap_e.levels_fwd = levels_dir[0];
+            }
             hipGraph_t graph = nullptr;
             const bool began = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
             bool captured_ok = began;
             if (began) try {
-                int32_t lm = 0;
-                BfsLevels lv;
-                lv.snap = snap;
-                lv.cap = cap;
-                lv.fill_level = fill_level;
-                lv.hist = hist;
-                lv.hlen = cap;
-                lv.lmax = &lm;
-                lv.enqueue_only = stats.bfs_levels;
-                lv.zero_flags = flags;
-                lv.sidx_fill = sidx;
-                lv.zero_hist = true;
-                stage_into(lv);
-                TravStats ignored;
-                (void)bfs_batched(st, make_view(0), samples_dev, k, 0, k, lv, sidx, ts, trav_scratch, cnt, &ignored,
-                                  nullptr);
-                run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
-                hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st,
-                                   (const uint32_t*)bfs_batched_ctl(ts, n, kg0), (const uint32_t*)flags,
+                const uint32_t* ctl_dev = (const uint32_t*)bfs_batched_ctl(ts, n, kg0);
+                for (int dir = 0; dir < (rt_single ? 2 : 1); dir++) {
+                    int32_t lm = 0;
+                    BfsLevels lv;
+                    lv.snap = snap;
+                    lv.cap = cap;
+                    lv.fill_level = fill_level;
+                    lv.hist = hist;
+                    lv.hlen = cap;
+                    lv.lmax = &lm;
+                    lv.enqueue_only = bits_path ? stats.bfs_levels : levels_dir[dir];
+                    if (dir == 0) {
+                        lv.zero_flags = flags;
+                        lv.sidx_fill = sidx;
+                        lv.zero_hist = bits_path;
+                        stage_into(lv);
+                    }
+                    TravStats ignored;
+                    (void)bfs_batched(st, make_view(dir), samples_dev, k, 0, k, lv, sidx, ts, trav_scratch, cnt,
+                                      &ignored, nullptr);
+                    if (rt_single) {
+                        materialize_distances(st, snap, (size_t)n * ((k + 63) / 64), lmax_dir[dir], fill_level, n, k,
+                                              0, k, dir == 0 ? D : Dr, dk, flags);
+                        if (dir == 0)  // the forward search's control block, before the reverse one reuses it
+                            hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st, ctl_dev,
+                                               (const uint32_t*)flags, (uint32_t*)&L.rb_dev->ctl_fwd,
+                                               (uint32_t*)&L.rb_dev->flags_fwd);
+                    }
+                }
+                if (bits_path) run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);
+                else run_epilogue(st, ea, ea_scratch, ea_es, flags);
+                hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st, ctl_dev, (const uint32_t*)flags,
                                    (uint32_t*)&L.rb_dev->ctl, (uint32_t*)&L.rb_dev->flags);
                 CCG_HIP(hipGetLastError());
             } catch (const HipError&) {

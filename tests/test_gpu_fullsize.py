@@ -101,6 +101,26 @@ def test_fullsize_every_node(ctx, name):
         _say(f"  sweep at node {v}")
         a, ae = oracle.node_sweep(g, ref["samples"], v, reverse_graph=rg)
         assert sweep["S_sweep"][v] == a and sweep["S_sweep_err"][v] == ae, v
+    if name == "rmat22dir":
+        # the benchmark's path on the round trip: CC_GRAPH replays into device tensors
+        import torch
+        dt = {"S_hyb": torch.float64, "S_samp": torch.float64, "S_piv": torch.int64, "S_pub": torch.int64,
+              "pivot": torch.int32, "delta": torch.int32, "sampsum": torch.int64}
+        gh = ctx.upload(g)
+        try:
+            out = {f: torch.empty(g.n, dtype=dt[f], device="cuda") for f in BENCH_OUT}
+            replays = 0
+            for call in range(3):
+                for t in out.values():
+                    t.fill_(-1)
+                cc.cc_estimate_device(ctx.handle, gh, k, out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=seed)
+                replays += cc.cc_last_timing(ctx.handle)["launches"] == 1
+                torch.cuda.synchronize()
+                _say(f"  round-trip call {call}: checking every node")
+                _check({f: t.cpu().numpy() for f, t in out.items()}, ref, BENCH_OUT, f"{name} replay {call}")
+            assert replays >= 2, "the round trip was not replayed from the captured graph"
+        finally:
+            ctx.release(gh)
     if name != "rmat20":  # the replay test reuses rmat20's reference
         _REF.pop((name, seed), None)
         _REF.pop(("g", name), None)

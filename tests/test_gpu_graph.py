@@ -30,7 +30,10 @@ def _outputs(torch, n, fields=FIELDS):
 
 
 @pytest.mark.parametrize("make,k", [(lambda: graphgen.ba(5000, 4, seed=3), 64),
-                                    (lambda: graphgen.rmat(12, 16, seed=5), 200)])
+                                    (lambda: graphgen.rmat(12, 16, seed=5), 200),
+                                    (lambda: graphgen.rmat(12, 16, seed=6, directed=True), 128),
+                                    (lambda: graphgen.rmat(11, 8, seed=7, directed=True), 40)],
+                         ids=["ba5000-k64", "rmat12-k200", "rmat12dir-k128-round-trip", "rmat11dir-k40-round-trip"])
 def test_replays_match_eager(make, k):
     import torch
     g = make()
@@ -138,4 +141,37 @@ def test_replays_write_samples():
                 assert torch.equal(out[f], ref[f]), (it, seed, f)
         _say(f"  replays: {replays}")
         assert replays >= 4
+        ctx.release(gh)
+
+
+@pytest.mark.parametrize("k", [40, 128, 256])
+def test_round_trip_replays_match_oracle(k):
+    """Round-trip estimates (Sec. 6.1) replayed from a captured graph: both
+    searches, the distances and the D-based epilogue, with the Sec. 4
+    outputs, against the oracle's every-node accounting for each seed."""
+    import torch
+    import oracle
+    g = graphgen.rmat(11, 16, seed=6, directed=True)
+    rg = graphgen.transpose(g)
+    fields = {**FIELDS, "S_err": "float64", "S_ad": "float64", "S_ad_err": "float64"}
+    refs = {}
+    with cc.Context(0) as ctx:
+        gh = ctx.upload(g)
+        out = _outputs(torch, g.n, fields)
+        replays = 0
+        for it, seed in enumerate([4, 4, 4, 9, 9, 4]):
+            if seed not in refs:
+                samples = np.asarray(oracle.draw_samples(g.n, k, seed), dtype=np.int32)
+                refs[seed] = oracle.estimate_tails(g, samples, threads=8, reverse_graph=rg)
+            for t in out.values():
+                t.fill_(-1)
+            cc.cc_estimate_device(ctx.handle, gh, k, out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=seed)
+            replays += cc.cc_last_timing(ctx.handle)["launches"] == 1
+            torch.cuda.synchronize()
+            ref = refs[seed]
+            for f in fields:
+                got = out[f].cpu().numpy()
+                assert np.array_equal(got, np.asarray(ref[f]).astype(got.dtype)), (it, seed, f)
+        _say(f"  k={k}: {replays} replays")
+        assert replays >= 3
         ctx.release(gh)
