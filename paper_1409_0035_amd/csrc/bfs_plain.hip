@@ -25,16 +25,65 @@ __global__ __launch_bounds__(kBlock) void k_plain_init(int64_t n, DT* dist, uint
     if (v < (n + 31) / 32) vis[v] = 0;
 }
 
+// The search's state between launches, so that the host enqueues levels
+// without reading anything back: the frontier of the level that runs next
+// (queue buffer, size, out-arcs), the arcs and nodes reached so far, the
+// direction, and whether the search is over.
+struct PlainCtl {
+    int32_t done;
+    int32_t pull;
+    uint32_t level;     // the level the next push or pull finds
+    int32_t qsel;       // frontier buffer of the next level
+    int32_t nf;         // frontier size
+    int32_t overflow;   // a level beyond what the distance type holds
+    int64_t mf;         // the frontier's out-arcs
+    int64_t explored;   // out-arcs of every node found so far
+    int64_t visited;    // nodes found so far
+    int64_t arcs;       // arcs scanned, this source
+    int64_t nodes;      // frontier / unvisited nodes processed, this source
+};
+// What one source's search left: levels run, nodes found, whether it ended
+// inside the levels enqueued for it, overflow.
+struct PlainRec {
+    int32_t done;
+    int32_t overflow;
+    uint32_t levels;
+    int32_t pad;
+    int64_t visited;
+    int64_t arcs;
+    int64_t nodes;
+};
+
+// push while the frontier's out-arcs are at most the unexplored arcs / 14, then
+// pull until the frontier holds fewer than n / 24 nodes
+__device__ __forceinline__ int32_t plain_direction(const PlainCtl& c, int64_t n, int64_t arcs) {
+    const int64_t mu = arcs - c.explored;
+    if (!c.pull && c.mf > mu / 14) return 1;
+    if (c.pull && (int64_t)c.nf < n / 24) return 0;
+    return c.pull;
+}
+
 template <typename DT>
 __global__ void k_plain_source(int32_t s, DT* dist, uint32_t* vis, int32_t* q, const uint32_t* rp,
-                               LevelCounters* cnt) {
+                               LevelCounters* cnt, PlainCtl* ctl, int64_t n, int64_t arcs) {
     if (threadIdx.x == 0) {
         dist[s] = 0;
         vis[s >> 5] |= 1u << (s & 31);
         q[0] = s;
-        cnt->n_out = 1;
-        cnt->n_new = 1;
-        cnt->frontier_arcs = rp[s + 1] - rp[s];
+        cnt->n_out = 0;
+        cnt->n_new = 0;
+        cnt->arcs = 0;
+        cnt->frontier_arcs = 0;
+        cnt->matched = 0;
+        PlainCtl c{};
+        c.level = 1;
+        c.nf = 1;
+        c.mf = rp[s + 1] - rp[s];
+        c.explored = c.mf;
+        c.visited = 1;
+        c.pull = 0;
+        c.pull = plain_direction(c, n, arcs);
+        *ctl = c;
     }
 }
 
@@ -57,42 +106,48 @@ __device__ __forceinline__ void claim(int32_t w, uint32_t* vis, DT* dist, uint32
 }
 
 // top-down: one lane per low-degree frontier node, the whole wave per
-// high-degree one
+// high-degree one; the grid strides over the frontier
 template <typename DT>
 __global__ __launch_bounds__(kBlock) void k_plain_push(const uint32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ col,
-                                                       const int32_t* __restrict__ q_in, int32_t n_in,
-                                                       int32_t* __restrict__ q_out, uint32_t* vis, DT* dist,
-                                                       uint32_t level, LevelCounters* cnt) {
+                                                       const int32_t* __restrict__ col, int32_t* q0, int32_t* q1,
+                                                       uint32_t* vis, DT* dist, const PlainCtl* ctl,
+                                                       LevelCounters* cnt) {
+    if (ctl->done || ctl->pull) return;
+    const uint32_t level = ctl->level;
+    const int32_t n_in = ctl->nf;
+    const int32_t* q_in = ctl->qsel ? q1 : q0;
+    int32_t* q_out = ctl->qsel ? q0 : q1;
     const int lane = lane_id();
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = idx < n_in;
-    const int32_t u = valid ? q_in[idx] : 0;
-    uint32_t beg = 0, end = 0;
-    if (valid) {
-        beg = rp[u];
-        end = rp[u + 1];
-    }
-    const bool big = valid && (end - beg > kSmallDeg);
     int64_t farcs = 0, scanned = 0;
     int32_t nnew = 0;
-    if (valid && !big) {
-        for (uint32_t e = beg; e < end; ++e) {
-            ++scanned;
-            claim<DT>(col[e], vis, dist, level, rp, q_out, cnt, farcs, nnew);
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_in; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t idx = base + threadIdx.x;
+        const bool valid = idx < n_in;
+        const int32_t u = valid ? q_in[idx] : 0;
+        uint32_t beg = 0, end = 0;
+        if (valid) {
+            beg = rp[u];
+            end = rp[u + 1];
         }
-    }
-    uint64_t bm = __ballot(big);
-    while (bm) {
-        const int s = __ffsll((unsigned long long)bm) - 1;
-        bm &= bm - 1;
-        const uint32_t b = (uint32_t)readlane32((int)beg, s);
-        const uint32_t en = (uint32_t)readlane32((int)end, s);
-        for (uint32_t e0 = b; e0 < en; e0 += 64) {
-            const uint32_t e = e0 + lane;
-            if (e < en) {
+        const bool big = valid && (end - beg > kSmallDeg);
+        if (valid && !big) {
+            for (uint32_t e = beg; e < end; ++e) {
                 ++scanned;
                 claim<DT>(col[e], vis, dist, level, rp, q_out, cnt, farcs, nnew);
+            }
+        }
+        uint64_t bm = __ballot(big);
+        while (bm) {
+            const int s = __ffsll((unsigned long long)bm) - 1;
+            bm &= bm - 1;
+            const uint32_t b = (uint32_t)readlane32((int)beg, s);
+            const uint32_t en = (uint32_t)readlane32((int)end, s);
+            for (uint32_t e0 = b; e0 < en; e0 += 64) {
+                const uint32_t e = e0 + lane;
+                if (e < en) {
+                    ++scanned;
+                    claim<DT>(col[e], vis, dist, level, rp, q_out, cnt, farcs, nnew);
+                }
             }
         }
     }
@@ -111,8 +166,11 @@ template <typename DT>
 __global__ __launch_bounds__(kBlock) void k_plain_pull(const uint32_t* __restrict__ in_rp,
                                                        const int32_t* __restrict__ in_col,
                                                        const uint32_t* __restrict__ out_rp, int64_t n,
-                                                       uint32_t* vis, DT* dist, uint32_t level,
-                                                       int32_t* __restrict__ q_out, LevelCounters* cnt) {
+                                                       uint32_t* vis, DT* dist, int32_t* q0, int32_t* q1,
+                                                       const PlainCtl* ctl, LevelCounters* cnt) {
+    if (ctl->done || !ctl->pull) return;
+    const uint32_t level = ctl->level;
+    int32_t* q_out = ctl->qsel ? q0 : q1;
     const int lane = lane_id();
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     bool found = false;
@@ -145,14 +203,47 @@ __global__ __launch_bounds__(kBlock) void k_plain_pull(const uint32_t* __restric
     }
 }
 
-__global__ void k_zero_counters_plain(LevelCounters* c) {
-    if (threadIdx.x == 0) {
-        c->n_out = 0;
-        c->n_new = 0;
-        c->arcs = 0;
-        c->frontier_arcs = 0;
-        c->matched = 0;
+// After each level: the next frontier becomes current, the search ends when
+// it is empty, and the next level's direction is decided.
+__global__ void k_plain_post(PlainCtl* ctl, LevelCounters* cnt, int64_t n, int64_t arcs, uint32_t max_level) {
+    if (threadIdx.x != 0 || ctl->done) return;
+    PlainCtl c = *ctl;
+    c.nodes += c.pull ? n - c.visited : c.nf;
+    c.arcs += cnt->arcs;
+    c.nf = cnt->n_out;
+    c.mf = cnt->frontier_arcs;
+    c.explored += c.mf;
+    c.visited += c.nf;
+    cnt->n_out = 0;
+    cnt->n_new = 0;
+    cnt->arcs = 0;
+    cnt->frontier_arcs = 0;
+    if (c.nf == 0) {
+        c.done = 1;
+    } else {
+        c.qsel ^= 1;
+        c.level += 1;
+        if (c.level > max_level) {
+            c.overflow = 1;
+            c.done = 1;
+        } else {
+            c.pull = plain_direction(c, n, arcs);
+        }
     }
+    *ctl = c;
+}
+
+__global__ void k_plain_record(const PlainCtl* ctl, PlainRec* rec) {
+    if (threadIdx.x != 0) return;
+    const PlainCtl c = *ctl;
+    PlainRec r{};
+    r.done = c.done;
+    r.overflow = c.overflow;
+    r.levels = c.level;
+    r.visited = c.visited;
+    r.arcs = c.arcs;
+    r.nodes = c.nodes;
+    *rec = r;
 }
 
 template <typename DT>
@@ -177,97 +268,114 @@ __global__ __launch_bounds__(256) void k_transpose(const DT* __restrict__ Dt, DT
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// One source: its initialisation and `levels` levels (push, pull, post), the
+// levels past its end returning at once, then its record.
+template <typename DT>
+void enqueue_source(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
+                    const int32_t* in_col, int64_t n, int64_t arcs, int32_t s, DT* dist, uint32_t* vis, int32_t* q0,
+                    int32_t* q1, PlainCtl* ctl, LevelCounters* cnt, PlainRec* rec, uint32_t levels) {
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const unsigned pb = std::min<unsigned>(nb, 2048);
+    hipLaunchKernelGGL((k_plain_init<DT>), dim3(nb), dim3(kBlock), 0, st, n, dist, vis);
+    hipLaunchKernelGGL((k_plain_source<DT>), dim3(1), dim3(64), 0, st, s, dist, vis, q0, out_rp, cnt, ctl, n, arcs);
+    for (uint32_t l = 0; l < levels; l++) {
+        hipLaunchKernelGGL((k_plain_push<DT>), dim3(pb), dim3(kBlock), 0, st, out_rp, out_col, q0, q1, vis, dist,
+                           (const PlainCtl*)ctl, cnt);
+        hipLaunchKernelGGL((k_plain_pull<DT>), dim3(nb), dim3(kBlock), 0, st, in_rp, in_col, out_rp, n, vis, dist,
+                           q0, q1, (const PlainCtl*)ctl, cnt);
+        hipLaunchKernelGGL(k_plain_post, dim3(1), dim3(64), 0, st, ctl, cnt, n, arcs,
+                           (uint32_t)DistT<DT>::max_level);
+    }
+    hipLaunchKernelGGL(k_plain_record, dim3(1), dim3(64), 0, st, (const PlainCtl*)ctl, rec);
+}
+
+// The k searches one after another.  The host enqueues every source with as
+// many levels as the deepest search so far needed (plus two), reads the
+// sources' records once at the end, and runs again, with more levels, any
+// source whose search had not ended.
 template <typename DT>
 int plain_t(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
             const int32_t* in_col, int64_t n, int64_t arcs, const int32_t* samples_host, int32_t k, DT* Dt,
-            void* scratch, LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats) {
+            void* scratch, LevelCounters* cnt_dev, TravStats* stats) {
     char* p = (char*)scratch;
     uint32_t* vis = (uint32_t*)p;
     p += align256(sizeof(uint32_t) * ((n + 31) / 32));
     int32_t* q0 = (int32_t*)p;
     p += align256(sizeof(int32_t) * n);
     int32_t* q1 = (int32_t*)p;
-    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    int rc = 0;
+    p += align256(sizeof(int32_t) * n);
+    PlainCtl* ctl = (PlainCtl*)p;
+    p += align256(sizeof(PlainCtl));
+    PlainRec* rec = (PlainRec*)p;
+    std::vector<PlainRec> hr((size_t)k);
+    // the first source alone, to learn the depth; then all the others at once
+    std::vector<int32_t> todo{0}, rest;
+    for (int32_t i = 1; i < k; i++) rest.push_back(i);
+    uint32_t levels = 16;
     KernelTimer kt;
-    for (int32_t i = 0; i < k; i++) {
-        DT* dist = Dt + (int64_t)i * n;
-        hipLaunchKernelGGL((k_plain_init<DT>), dim3(nb), dim3(kBlock), 0, st, n, dist, vis);
-        hipLaunchKernelGGL((k_plain_source<DT>), dim3(1), dim3(64), 0, st, samples_host[i], dist, vis, q0, out_rp,
-                           cnt_dev);
-        CCG_HIP(hipMemcpyAsync(cnt_host, cnt_dev, sizeof(LevelCounters), hipMemcpyDeviceToHost, st));
+    int rc = 0;
+    while (!todo.empty() || !rest.empty()) {
+        if (todo.empty()) todo.swap(rest);
+        kt.start(st);
+        for (int32_t i : todo)
+            enqueue_source<DT>(st, out_rp, out_col, in_rp, in_col, n, arcs, samples_host[i], Dt + (int64_t)i * n, vis,
+                               q0, q1, ctl, cnt_dev, rec + i, levels);
+        CCG_HIP(hipGetLastError());
+        kt.stop(st);
+        CCG_HIP(hipMemcpyAsync(hr.data(), rec, sizeof(PlainRec) * k, hipMemcpyDeviceToHost, st));
         CCG_HIP(hipStreamSynchronize(st));
-        stats->launches += 2;
-        int32_t nf = 1;
-        int64_t mf = cnt_host->frontier_arcs;
-        int64_t explored = mf;
-        int64_t visited = 1;
-        bool pull = false;
-        int32_t* qin = q0;
-        int32_t* qout = q1;
-        for (uint32_t level = 1;; ++level) {
-            if ((int64_t)level > DistT<DT>::max_level) return 1;
-            const int64_t mu = arcs - explored;
-            if (!pull && mf > mu / 14) pull = true;
-            else if (pull && (int64_t)nf < n / 24) pull = false;
-            hipLaunchKernelGGL(k_zero_counters_plain, dim3(1), dim3(64), 0, st, cnt_dev);
-            kt.start(st);
-            if (pull) {
-                hipLaunchKernelGGL((k_plain_pull<DT>), dim3(nb), dim3(kBlock), 0, st, in_rp, in_col, out_rp, n, vis,
-                                   dist, level, qout, cnt_dev);
-                stats->nodes_visited += n - visited;
-            } else {
-                const unsigned g = (unsigned)((nf + kBlock - 1) / kBlock);
-                hipLaunchKernelGGL((k_plain_push<DT>), dim3(g), dim3(kBlock), 0, st, out_rp, out_col, qin, nf, qout,
-                                   vis, dist, level, cnt_dev);
-                stats->nodes_visited += nf;
+        stats->kernel_ms += kt.ms();
+        stats->kernel_launches += (int64_t)todo.size() * (3 * levels + 3);
+        stats->launches += (int64_t)todo.size() * (3 * levels + 3);
+        std::vector<int32_t> again;
+        uint32_t deepest = 0;
+        for (int32_t i : todo) {
+            const PlainRec& r = hr[(size_t)i];
+            if (r.overflow) return 1;
+            if (!r.done) {
+                again.push_back(i);
+                continue;
             }
-            CCG_HIP(hipGetLastError());
-            kt.stop(st);
-            CCG_HIP(hipMemcpyAsync(cnt_host, cnt_dev, sizeof(LevelCounters), hipMemcpyDeviceToHost, st));
-            CCG_HIP(hipStreamSynchronize(st));
-            stats->kernel_ms += kt.ms();
-            stats->kernel_launches += 1;
-            stats->launches += 1;
-            stats->levels += 1;
-            stats->arcs_scanned += cnt_host->arcs;
-            nf = cnt_host->n_out;
-            mf = cnt_host->frontier_arcs;
-            explored += mf;
-            visited += nf;
-            if (nf == 0) break;
-            if ((int64_t)level > stats->maxd) stats->maxd = level;
-            std::swap(qin, qout);
+            stats->levels += r.levels;
+            stats->arcs_scanned += r.arcs;
+            stats->nodes_visited += r.nodes;
+            if ((int64_t)r.levels - 1 > stats->maxd) stats->maxd = r.levels - 1;
+            deepest = std::max(deepest, r.levels);
+            if (r.visited < n) rc = 2;
         }
-        if (visited < n) rc = 2;
+        // the searches that had not ended run deeper; the others as deep as the deepest one so far, plus two
+        levels = again.empty() ? std::max<uint32_t>(deepest + 2, 4) : std::max(levels * 4, deepest + 2);
+        todo.swap(again);
+        if ((int64_t)levels > (int64_t)DistT<DT>::max_level + 2) levels = (uint32_t)DistT<DT>::max_level + 2;
     }
     return rc;
 }
 
 }  // namespace
 
-size_t bfs_plain_scratch(int64_t n) {
-    return align256(sizeof(uint32_t) * ((n + 31) / 32)) + 2 * align256(sizeof(int32_t) * n) + 1024;
+size_t bfs_plain_scratch(int64_t n, int32_t k) {
+    return align256(sizeof(uint32_t) * ((n + 31) / 32)) + 2 * align256(sizeof(int32_t) * n) +
+           align256(sizeof(PlainCtl)) + align256(sizeof(PlainRec) * (size_t)std::max(k, 1)) + 1024;
 }
 
 bool bfs_plain(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
                const int32_t* in_col, int64_t n, int64_t arcs, const int32_t* samples_host, int32_t k, void* Dt,
                DistKind dk, void* scratch, size_t scratch_size, DevFlags* flags, LevelCounters* cnt_dev,
                LevelCounters* cnt_host, TravStats* stats) {
-    if (scratch_size < bfs_plain_scratch(n)) throw HipError{hipErrorOutOfMemory, "bfs_plain scratch"};
+    if (scratch_size < bfs_plain_scratch(n, k)) throw HipError{hipErrorOutOfMemory, "bfs_plain scratch"};
     int r;
     switch (dk) {
         case DistKind::U8:
             r = plain_t<uint8_t>(st, out_rp, out_col, in_rp, in_col, n, arcs, samples_host, k, (uint8_t*)Dt, scratch,
-                                 cnt_dev, cnt_host, stats);
+                                 cnt_dev, stats);
             break;
         case DistKind::U16:
             r = plain_t<uint16_t>(st, out_rp, out_col, in_rp, in_col, n, arcs, samples_host, k, (uint16_t*)Dt,
-                                  scratch, cnt_dev, cnt_host, stats);
+                                  scratch, cnt_dev, stats);
             break;
         default:
             r = plain_t<uint32_t>(st, out_rp, out_col, in_rp, in_col, n, arcs, samples_host, k, (uint32_t*)Dt,
-                                  scratch, cnt_dev, cnt_host, stats);
+                                  scratch, cnt_dev, stats);
             break;
     }
     if (r == 1) return false;
