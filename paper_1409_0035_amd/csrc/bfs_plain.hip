@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kSmallDeg = 32;
+constexpr uint32_t kChunkArcs = 256;  // out-arcs per chunk of a high-degree frontier node
 
 template <typename DT>
 __global__ __launch_bounds__(kBlock) void k_plain_init(int64_t n, DT* dist, uint32_t* vis) {
@@ -41,6 +42,8 @@ struct PlainCtl {
     int64_t visited;    // nodes found so far
     int64_t arcs;       // arcs scanned, this source
     int64_t nodes;      // frontier / unvisited nodes processed, this source
+    int32_t nchunks;    // chunks of high-degree frontier nodes listed by this push level
+    uint32_t ticket;    // blocks of the level's second launch that have finished
 };
 // What one source's search left: levels run, nodes found, whether it ended
 // inside the levels enqueued for it, overflow.
@@ -105,50 +108,76 @@ __device__ __forceinline__ void claim(int32_t w, uint32_t* vis, DT* dist, uint32
     if (mine) q_out[pos] = w;
 }
 
-// top-down: one lane per low-degree frontier node, the whole wave per
-// high-degree one; the grid strides over the frontier
+// One level, pushing or pulling as the control block says.
+//   push  one lane per frontier node of low degree; a node of higher degree
+//         is cut into chunks of kChunkArcs out-arcs, listed for the second
+//         launch, where a wave takes each chunk (a hub no longer holds one
+//         wave for its whole arc list)
+//   pull  every unvisited node scans its in-arcs for a node of the last level
+//         and stops at the first
 template <typename DT>
-__global__ __launch_bounds__(kBlock) void k_plain_push(const uint32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ col, int32_t* q0, int32_t* q1,
-                                                       uint32_t* vis, DT* dist, const PlainCtl* ctl,
-                                                       LevelCounters* cnt) {
-    if (ctl->done || ctl->pull) return;
+__global__ __launch_bounds__(kBlock) void k_plain_level(const uint32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const uint32_t* __restrict__ in_rp,
+                                                        const int32_t* __restrict__ in_col, int64_t n, uint32_t* vis,
+                                                        DT* dist, int32_t* q0, int32_t* q1, uint64_t* chunks,
+                                                        PlainCtl* ctl, LevelCounters* cnt) {
+    if (ctl->done) return;
     const uint32_t level = ctl->level;
-    const int32_t n_in = ctl->nf;
     const int32_t* q_in = ctl->qsel ? q1 : q0;
     int32_t* q_out = ctl->qsel ? q0 : q1;
     const int lane = lane_id();
     int64_t farcs = 0, scanned = 0;
     int32_t nnew = 0;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_in; base += (int64_t)gridDim.x * kBlock) {
-        const int64_t idx = base + threadIdx.x;
-        const bool valid = idx < n_in;
-        const int32_t u = valid ? q_in[idx] : 0;
-        uint32_t beg = 0, end = 0;
-        if (valid) {
-            beg = rp[u];
-            end = rp[u + 1];
-        }
-        const bool big = valid && (end - beg > kSmallDeg);
-        if (valid && !big) {
-            for (uint32_t e = beg; e < end; ++e) {
-                ++scanned;
-                claim<DT>(col[e], vis, dist, level, rp, q_out, cnt, farcs, nnew);
+    if (!ctl->pull) {
+        const int32_t n_in = ctl->nf;
+        for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n_in; base += (int64_t)gridDim.x * kBlock) {
+            const int64_t idx = base + threadIdx.x;
+            const bool valid = idx < n_in;
+            const int32_t u = valid ? q_in[idx] : 0;
+            uint32_t beg = 0, end = 0;
+            if (valid) {
+                beg = rp[u];
+                end = rp[u + 1];
             }
-        }
-        uint64_t bm = __ballot(big);
-        while (bm) {
-            const int s = __ffsll((unsigned long long)bm) - 1;
-            bm &= bm - 1;
-            const uint32_t b = (uint32_t)readlane32((int)beg, s);
-            const uint32_t en = (uint32_t)readlane32((int)end, s);
-            for (uint32_t e0 = b; e0 < en; e0 += 64) {
-                const uint32_t e = e0 + lane;
-                if (e < en) {
+            const bool big = valid && (end - beg > kSmallDeg);
+            if (valid && !big) {
+                for (uint32_t e = beg; e < end; ++e) {
                     ++scanned;
                     claim<DT>(col[e], vis, dist, level, rp, q_out, cnt, farcs, nnew);
                 }
             }
+            if (big) {  // its chunks, for the second launch
+                const uint32_t c = (end - beg + kChunkArcs - 1) / kChunkArcs;
+                const int32_t at = atomicAdd(&ctl->nchunks, (int32_t)c);
+                for (uint32_t q = 0; q < c; q++) chunks[at + q] = ((uint64_t)(uint32_t)u << 32) | (q * kChunkArcs);
+            }
+        }
+    } else {
+        for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+            const int64_t v = base + threadIdx.x;
+            bool found = false;
+            int64_t fa = 0;
+            if (v < n && !(vis[v >> 5] & (1u << (v & 31)))) {
+                const DT want = (DT)(level - 1);
+                const uint32_t b = in_rp[v], en = in_rp[v + 1];
+                for (uint32_t e = b; e < en; ++e) {
+                    ++scanned;
+                    if (dist[in_col[e]] == want) {
+                        found = true;
+                        break;
+                    }
+                }
+                if (found) {
+                    dist[v] = (DT)level;
+                    atomicOr(&vis[v >> 5], 1u << (v & 31));
+                    fa = rp[v + 1] - rp[v];
+                }
+            }
+            farcs += fa;
+            nnew += found ? 1 : 0;
+            const int pos = wave_append(&cnt->n_out, found);
+            if (found) q_out[pos] = (int32_t)v;
         }
     }
     const int64_t fa = wave_sum64(farcs);
@@ -161,53 +190,58 @@ __global__ __launch_bounds__(kBlock) void k_plain_push(const uint32_t* __restric
     }
 }
 
-// bottom-up: every unvisited node scans its in-arcs for a node at level-1
+// The second launch of a level: the chunks of the high-degree frontier nodes
+// (push levels), one wave per chunk; then the last block ends the level: the
+// next frontier becomes current, the search ends when it is empty, and the
+// next level's direction is decided.
 template <typename DT>
-__global__ __launch_bounds__(kBlock) void k_plain_pull(const uint32_t* __restrict__ in_rp,
-                                                       const int32_t* __restrict__ in_col,
-                                                       const uint32_t* __restrict__ out_rp, int64_t n,
-                                                       uint32_t* vis, DT* dist, int32_t* q0, int32_t* q1,
-                                                       const PlainCtl* ctl, LevelCounters* cnt) {
-    if (ctl->done || !ctl->pull) return;
-    const uint32_t level = ctl->level;
-    int32_t* q_out = ctl->qsel ? q0 : q1;
+__global__ __launch_bounds__(kBlock) void k_plain_chunks_post(const uint32_t* __restrict__ rp,
+                                                              const int32_t* __restrict__ col, int64_t n,
+                                                              int64_t arcs, uint32_t* vis, DT* dist, int32_t* q0,
+                                                              int32_t* q1, const uint64_t* __restrict__ chunks,
+                                                              PlainCtl* ctl, LevelCounters* cnt, uint32_t max_level) {
+    if (ctl->done) return;
     const int lane = lane_id();
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool found = false;
-    int64_t scanned = 0, farcs = 0;
-    if (v < n && !(vis[v >> 5] & (1u << (v & 31)))) {
-        const DT want = (DT)(level - 1);
-        const uint32_t b = in_rp[v], en = in_rp[v + 1];
-        for (uint32_t e = b; e < en; ++e) {
-            ++scanned;
-            if (dist[in_col[e]] == want) {
-                found = true;
-                break;
+    if (!ctl->pull) {
+        const uint32_t level = ctl->level;
+        int32_t* q_out = ctl->qsel ? q0 : q1;
+        const int32_t nc = ctl->nchunks;
+        int64_t farcs = 0, scanned = 0;
+        int32_t nnew = 0;
+        const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+        for (int64_t c = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); c < nc; c += waves) {
+            const uint64_t ent = chunks[c];
+            const int32_t u = (int32_t)(ent >> 32);
+            const uint32_t b = rp[u] + (uint32_t)ent, en = min(rp[u + 1], b + kChunkArcs);
+            for (uint32_t e0 = b; e0 < en; e0 += 64) {  // the same trip count in every lane
+                const uint32_t e = e0 + lane;
+                if (e < en) {
+                    ++scanned;
+                    claim<DT>(col[e], vis, dist, level, rp, q_out, cnt, farcs, nnew);
+                }
             }
         }
-        if (found) {
-            dist[v] = (DT)level;
-            atomicOr(&vis[v >> 5], 1u << (v & 31));
-            farcs = out_rp[v + 1] - out_rp[v];
+        const int64_t fa = wave_sum64(farcs);
+        const int64_t sc = wave_sum64(scanned);
+        const int32_t nn = wave_sum32(nnew);
+        if (lane == 0) {
+            if (fa) atomicAdd((unsigned long long*)&cnt->frontier_arcs, (unsigned long long)fa);
+            if (sc) atomicAdd((unsigned long long*)&cnt->arcs, (unsigned long long)sc);
+            if (nn) atomicAdd(&cnt->n_new, nn);
         }
     }
-    const int pos = wave_append(&cnt->n_out, found);
-    if (found) q_out[pos] = (int32_t)v;
-    const int64_t fa = wave_sum64(farcs);
-    const int64_t sc = wave_sum64(scanned);
-    const int32_t nn = (int32_t)__popcll(__ballot(found));
-    if (lane == 0) {
-        if (fa) atomicAdd((unsigned long long*)&cnt->frontier_arcs, (unsigned long long)fa);
-        if (sc) atomicAdd((unsigned long long*)&cnt->arcs, (unsigned long long)sc);
-        if (nn) atomicAdd(&cnt->n_new, nn);
+    __syncthreads();
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
     }
-}
-
-// After each level: the next frontier becomes current, the search ends when
-// it is empty, and the next level's direction is decided.
-__global__ void k_plain_post(PlainCtl* ctl, LevelCounters* cnt, int64_t n, int64_t arcs, uint32_t max_level) {
-    if (threadIdx.x != 0 || ctl->done) return;
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
     PlainCtl c = *ctl;
+    c.ticket = 0;
+    c.nchunks = 0;
     c.nodes += c.pull ? n - c.visited : c.nf;
     c.arcs += cnt->arcs;
     c.nf = cnt->n_out;
@@ -231,6 +265,7 @@ __global__ void k_plain_post(PlainCtl* ctl, LevelCounters* cnt, int64_t n, int64
         }
     }
     *ctl = c;
+    __threadfence();
 }
 
 __global__ void k_plain_record(const PlainCtl* ctl, PlainRec* rec) {
@@ -273,18 +308,17 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 template <typename DT>
 void enqueue_source(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
                     const int32_t* in_col, int64_t n, int64_t arcs, int32_t s, DT* dist, uint32_t* vis, int32_t* q0,
-                    int32_t* q1, PlainCtl* ctl, LevelCounters* cnt, PlainRec* rec, uint32_t levels) {
+                    int32_t* q1, uint64_t* chunks, PlainCtl* ctl, LevelCounters* cnt, PlainRec* rec,
+                    uint32_t levels) {
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    const unsigned pb = std::min<unsigned>(nb, 2048);
+    const unsigned lb = std::min<unsigned>(nb, 4096), cb = std::min<unsigned>(nb, 2048);
     hipLaunchKernelGGL((k_plain_init<DT>), dim3(nb), dim3(kBlock), 0, st, n, dist, vis);
     hipLaunchKernelGGL((k_plain_source<DT>), dim3(1), dim3(64), 0, st, s, dist, vis, q0, out_rp, cnt, ctl, n, arcs);
     for (uint32_t l = 0; l < levels; l++) {
-        hipLaunchKernelGGL((k_plain_push<DT>), dim3(pb), dim3(kBlock), 0, st, out_rp, out_col, q0, q1, vis, dist,
-                           (const PlainCtl*)ctl, cnt);
-        hipLaunchKernelGGL((k_plain_pull<DT>), dim3(nb), dim3(kBlock), 0, st, in_rp, in_col, out_rp, n, vis, dist,
-                           q0, q1, (const PlainCtl*)ctl, cnt);
-        hipLaunchKernelGGL(k_plain_post, dim3(1), dim3(64), 0, st, ctl, cnt, n, arcs,
-                           (uint32_t)DistT<DT>::max_level);
+        hipLaunchKernelGGL((k_plain_level<DT>), dim3(lb), dim3(kBlock), 0, st, out_rp, out_col, in_rp, in_col, n, vis,
+                           dist, q0, q1, chunks, ctl, cnt);
+        hipLaunchKernelGGL((k_plain_chunks_post<DT>), dim3(cb), dim3(kBlock), 0, st, out_rp, out_col, n, arcs, vis,
+                           dist, q0, q1, (const uint64_t*)chunks, ctl, cnt, (uint32_t)DistT<DT>::max_level);
     }
     hipLaunchKernelGGL(k_plain_record, dim3(1), dim3(64), 0, st, (const PlainCtl*)ctl, rec);
 }
@@ -306,6 +340,8 @@ int plain_t(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, cons
     p += align256(sizeof(int32_t) * n);
     PlainCtl* ctl = (PlainCtl*)p;
     p += align256(sizeof(PlainCtl));
+    uint64_t* chunks = (uint64_t*)p;
+    p += align256(sizeof(uint64_t) * (size_t)(n + arcs / kChunkArcs + 1));
     PlainRec* rec = (PlainRec*)p;
     std::vector<PlainRec> hr((size_t)k);
     // the first source alone, to learn the depth; then all the others at once
@@ -319,14 +355,14 @@ int plain_t(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, cons
         kt.start(st);
         for (int32_t i : todo)
             enqueue_source<DT>(st, out_rp, out_col, in_rp, in_col, n, arcs, samples_host[i], Dt + (int64_t)i * n, vis,
-                               q0, q1, ctl, cnt_dev, rec + i, levels);
+                               q0, q1, chunks, ctl, cnt_dev, rec + i, levels);
         CCG_HIP(hipGetLastError());
         kt.stop(st);
         CCG_HIP(hipMemcpyAsync(hr.data(), rec, sizeof(PlainRec) * k, hipMemcpyDeviceToHost, st));
         CCG_HIP(hipStreamSynchronize(st));
         stats->kernel_ms += kt.ms();
-        stats->kernel_launches += (int64_t)todo.size() * (3 * levels + 3);
-        stats->launches += (int64_t)todo.size() * (3 * levels + 3);
+        stats->kernel_launches += (int64_t)todo.size() * (2 * levels + 3);
+        stats->launches += (int64_t)todo.size() * (2 * levels + 3);
         std::vector<int32_t> again;
         uint32_t deepest = 0;
         for (int32_t i : todo) {
@@ -353,16 +389,17 @@ int plain_t(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, cons
 
 }  // namespace
 
-size_t bfs_plain_scratch(int64_t n, int32_t k) {
+size_t bfs_plain_scratch(int64_t n, int64_t arcs, int32_t k) {
     return align256(sizeof(uint32_t) * ((n + 31) / 32)) + 2 * align256(sizeof(int32_t) * n) +
-           align256(sizeof(PlainCtl)) + align256(sizeof(PlainRec) * (size_t)std::max(k, 1)) + 1024;
+           align256(sizeof(PlainCtl)) + align256(sizeof(uint64_t) * (size_t)(n + arcs / kChunkArcs + 1)) +
+           align256(sizeof(PlainRec) * (size_t)std::max(k, 1)) + 1024;
 }
 
 bool bfs_plain(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
                const int32_t* in_col, int64_t n, int64_t arcs, const int32_t* samples_host, int32_t k, void* Dt,
                DistKind dk, void* scratch, size_t scratch_size, DevFlags* flags, LevelCounters* cnt_dev,
                LevelCounters* cnt_host, TravStats* stats) {
-    if (scratch_size < bfs_plain_scratch(n, k)) throw HipError{hipErrorOutOfMemory, "bfs_plain scratch"};
+    if (scratch_size < bfs_plain_scratch(n, arcs, k)) throw HipError{hipErrorOutOfMemory, "bfs_plain scratch"};
     int r;
     switch (dk) {
         case DistKind::U8:

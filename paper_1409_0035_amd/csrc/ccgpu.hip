@@ -1168,7 +1168,7 @@ size_t job_bytes(const DevGraph& g, int32_t k, int32_t mode, int db) {
     if (g.weighted) {
         b += dbytes * (g.directed ? 3 : 2) + (mode == CC_PLAIN ? sssp_weighted_scratch(n, 1) : sssp_wsearch_scratch(n, k));
     } else if (mode == CC_PLAIN) {
-        b += dbytes * (g.directed ? 3 : 2) + bfs_plain_scratch(n, k);
+        b += dbytes * (g.directed ? 3 : 2) + bfs_plain_scratch(n, g.arcs, k);
     } else {
         const int32_t kg = std::min(k, 256);
         b += bfs_batched_scratch(n, kg, g.nh) + (size_t)32 * n * ((kg + 63) / 64) * 8;
@@ -1298,7 +1298,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         if (g.weighted)
             trav_scratch = mode == CC_PLAIN ? sssp_weighted_scratch(n, 1) : sssp_wsearch_scratch(n, kw);
         else
-            trav_scratch = mode == CC_PLAIN ? bfs_plain_scratch(n, k) : bfs_batched_scratch(n, kg0, g.nh);
+            trav_scratch = mode == CC_PLAIN ? bfs_plain_scratch(n, g.arcs, k) : bfs_batched_scratch(n, kg0, g.nh);
         const size_t hist_elems = bits_path ? (size_t)kHistSlotsBatched * k * cap : 0;
         Carver c(L.arena.get(small + Carver::sz(trav_scratch) + Carver::sz(sizeof(int32_t) * hist_elems)));
         int32_t* samples_dev = c.take<int32_t>(k);

@@ -329,7 +329,7 @@ bool bfs_plain(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, c
                const int32_t* in_col, int64_t n, int64_t arcs, const int32_t* samples_host, int32_t k,
                void* Dt, DistKind dk, void* scratch, size_t scratch_size, DevFlags* flags,
                LevelCounters* cnt_dev, LevelCounters* cnt_host, TravStats* stats);
-size_t bfs_plain_scratch(int64_t n, int32_t k);
+size_t bfs_plain_scratch(int64_t n, int64_t arcs, int32_t k);
 
 // Transpose source-major Dt[k][n] into node-major D[n][k].
 void transpose_dist(hipStream_t st, const void* Dt, void* D, int64_t n, int32_t k, DistKind dk);
