@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate_rows(
     const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
     const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed,
     double* S_hyb, double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out,
-    int64_t* sampsum_out, DevFlags* flags) {
+    int64_t* sampsum_out, uint4* stage, DevFlags* flags) {
     constexpr int PER = RowPiece<DT, RT>::PER;
     const int64_t LIM = (int64_t)1 << 53;
     const int sub = lane_id() & (G - 1);
@@ -288,14 +288,23 @@ __global__ __launch_bounds__(kBlock) void k_estimate_rows(
             piv = src_sum[p];
             pub = piv + (n - 1) * delta;
         }
-        const int64_t o = orig[v];
-        if (S_hyb) S_hyb[o] = hyb;
-        if (S_samp) S_samp[o] = samp;
-        if (S_piv) S_piv[o] = piv;
-        if (S_pub) S_pub[o] = pub;
-        if (pivot_out) pivot_out[o] = p;
-        if (delta_out) delta_out[o] = (int32_t)delta;
-        if (sampsum_out) sampsum_out[o] = sum;
+        if (stage) {  // the node's record in internal order; written out in the caller's order afterwards
+            const uint64_t hb = (uint64_t)__double_as_longlong(hyb), sb = (uint64_t)__double_as_longlong(samp);
+            uint4* r = stage + v * 4;
+            r[0] = make_uint4((uint32_t)hb, (uint32_t)(hb >> 32), (uint32_t)sb, (uint32_t)(sb >> 32));
+            r[1] = make_uint4((uint32_t)piv, (uint32_t)((uint64_t)piv >> 32), (uint32_t)pub,
+                              (uint32_t)((uint64_t)pub >> 32));
+            r[2] = make_uint4((uint32_t)sum, (uint32_t)((uint64_t)sum >> 32), (uint32_t)p, (uint32_t)delta);
+        } else {
+            const int64_t o = orig[v];
+            if (S_hyb) S_hyb[o] = hyb;
+            if (S_samp) S_samp[o] = samp;
+            if (S_piv) S_piv[o] = piv;
+            if (S_pub) S_pub[o] = pub;
+            if (pivot_out) pivot_out[o] = p;
+            if (delta_out) delta_out[o] = (int32_t)delta;
+            if (sampsum_out) sampsum_out[o] = sum;
+        }
         any_ovf = any_ovf || ovf;
         any_unreached = any_unreached || unreached;
     }
@@ -1061,6 +1070,12 @@ int row_lanes(int32_t k) {
     return (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ? (int)g : 0;
 }
 
+// Whether the Sec. 2 outputs go through per-node records (a relabelled graph
+// with at least one of them requested).
+inline bool epilogue_staged(const EpilogueArgs& a) {
+    return a.inv && (a.S_hyb || a.S_samp || a.S_piv || a.S_pub || a.pivot || a.delta || a.sampsum);
+}
+
 template <typename DT, bool RT, typename MT>
 void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* flags) {
     const int64_t n = a.n;
@@ -1108,15 +1123,21 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
     hipLaunchKernelGGL((k_dmat<DT, RT, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, (const DT*)a.D,
                        (const DT*)a.Dr, a.samples, k, a.dmat, dmat_c, flags);
     run_suffix(st, hist, nslots, k, k, hlen, maxd, a.dmat, Tcnt, Tsum, a.src_sum, chunks);
+    const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
     {
         const DT* Dp = (const DT*)a.D;
         const DT* Drp = (const DT*)a.Dr;
         const int G = row_lanes<DT>(k);
         const unsigned eb = grid_for(n * (G > 0 ? G : 1), 8192);
+        // staged records after the histogram and the error pass's scratch
+        uint4* stage = nullptr;
+        if (epilogue_staged(a) && G > 0)
+            stage = (uint4*)(p + (a.hist_done ? 0 : align256(sizeof(int32_t) * k * (maxd + 1))) +
+                             (want_err ? align256(sweep_scratch_bytes(n, k)) : 0));
 #define CCG_EST_ROWS(GG)                                                                                            \
     hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG>), dim3(eb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx,       \
                        a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb, a.S_samp, a.S_piv, \
-                       a.S_pub, a.pivot, a.delta, a.sampsum, flags)
+                       a.S_pub, a.pivot, a.delta, a.sampsum, stage, flags)
         switch (G) {
             case 1: CCG_EST_ROWS(1); break;
             case 2: CCG_EST_ROWS(2); break;
@@ -1129,6 +1150,8 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
                                    a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);
         }
 #undef CCG_EST_ROWS
+        CCG_HIP(hipGetLastError());
+        if (stage) put_outputs(st, n, a.inv, stage, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum);
     }
     CCG_HIP(hipGetLastError());
     if (a.Dout) {
@@ -1321,18 +1344,19 @@ size_t suffix_chunk_scratch(int32_t k, int64_t maxd) {
     return sizeof(int64_t) * 2 * (size_t)k * (size_t)nchunks + 256;
 }
 
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err) {
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err, bool staged) {
     const int64_t tlen = maxd + 2;
     size_t s = align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
                align256(sizeof(uint32_t) * (size_t)k * k) + align256(suffix_chunk_scratch(k, maxd)) + 1024;
     if (!hist_done) s += align256(sizeof(int32_t) * k * (maxd + 1));
-    if (err) s += sweep_scratch_bytes(n, k);
+    if (err) s += align256(sweep_scratch_bytes(n, k));
+    if (staged) s += align256((size_t)64 * n);
     return s;
 }
 
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags) {
     const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
-    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done, want_err))
+    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done, want_err, epilogue_staged(a)))
         throw HipError{hipErrorOutOfMemory, "epilogue scratch"};
     const bool rt = a.Dr != nullptr;
     switch (a.dk) {

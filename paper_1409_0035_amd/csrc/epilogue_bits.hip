@@ -560,4 +560,11 @@ void materialize_distances(hipStream_t st, const uint64_t* snap, size_t plane, i
     CCG_HIP(hipGetLastError());
 }
 
+void put_outputs(hipStream_t st, int64_t n, const int32_t* inv, const void* stage, double* S_hyb, double* S_samp,
+                 int64_t* S_piv, int64_t* S_pub, int32_t* pivot, int32_t* delta, int64_t* sampsum) {
+    hipLaunchKernelGGL(k_put_outputs, dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, n, inv, (const uint4*)stage, S_hyb,
+                       S_samp, S_piv, S_pub, pivot, delta, sampsum);
+    CCG_HIP(hipGetLastError());
+}
+
 }  // namespace ccg

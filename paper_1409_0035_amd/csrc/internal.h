@@ -365,6 +365,10 @@ struct EpilogueArgs {
     const int32_t* samples = nullptr;  // device, internal ids
     const int32_t* sidx = nullptr;     // device, internal id -> sample index or -1
     const int32_t* orig = nullptr;     // device, internal id -> caller's id
+    // device, caller's id -> internal id: when set, the Sec. 2 outputs are staged
+    // as one 64-byte record per node in internal order and then written in the
+    // caller's order (coalesced stores instead of seven scattered ones per node)
+    const int32_t* inv = nullptr;
     int64_t maxd = 0;            // upper bound on every (combined) distance
     int64_t eps_num = 1, eps_den = 1;
     // histogram already counted by the traversal: hist[slot][i][d], rows of hist_len
@@ -393,8 +397,11 @@ struct EpilogueArgs {
 // sample's sorted row of the sample distance matrix and the nodes grouped by
 // pivot; added to an epilogue's scratch when any of its outputs is wanted
 size_t sweep_scratch_bytes(int64_t n, int32_t k);
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err = false);
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err = false, bool staged = false);
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
+// The staged 64-byte node records written out in the caller's order
+void put_outputs(hipStream_t st, int64_t n, const int32_t* inv, const void* stage, double* S_hyb, double* S_samp,
+                 int64_t* S_piv, int64_t* S_pub, int32_t* pivot, int32_t* delta, int64_t* sampsum);
 void compute_sidx(hipStream_t st, const int32_t* samples, int32_t k, int32_t* sidx, int64_t n);
 
 // Tail tables and exact sample sums from a histogram with `nslots` copies.
