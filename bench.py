@@ -417,7 +417,7 @@ def run_config(name, cc, graphgen, torch, steps, warmup, plain_steps, autotune=T
     def step(mode):
         cc.cc_estimate_device(ctx.handle, gh, k, out, mode=mode, seed=seed, stream=stream)
 
-    use_graph = graph and g.w is None and k <= 256
+    use_graph = graph and k <= 256
     main_mode = cc.CC_BATCHED | (cc.CC_GRAPH if use_graph else 0)
     for _ in range(warmup):
         step(main_mode)

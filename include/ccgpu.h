@@ -72,10 +72,11 @@ typedef enum {
 #define CC_PLAIN 1      /* one sample at a time (the one-source baseline) */
 #define CC_GRAPH 0x100  /* or-ed into CC_BATCHED: capture the whole estimate as a HIP graph on the first call
                            and replay it when the same graph, k, eps, output pointers and stream come again
-                           (undirected graphs without arc lengths, k <= 256).  A replay is checked on the host
-                           (the search ended within the captured levels, with the same deepest level) and
-                           otherwise the estimate is recomputed as usual, so results never depend on it.
-                           Samples may change between calls. */
+                           (k <= 256: undirected graphs, round trips on digraphs, and graphs with arc lengths).
+                           A replay is checked on the host (each BFS ended within the captured levels with
+                           the same deepest level; the weighted searches' largest distances within the
+                           captured ones; no error flag) and otherwise the estimate is recomputed as usual,
+                           so results never depend on it.  Samples may change between calls. */
 
 typedef struct cc_context cc_context;
 typedef struct cc_graph cc_graph;

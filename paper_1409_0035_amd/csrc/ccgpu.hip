@@ -293,6 +293,27 @@ __global__ void k_status_out(const uint32_t* __restrict__ ctl, const uint32_t* _
         __hip_atomic_store(flags_host + (t - nc), flags[t - nc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// The samples from the lane's pinned staging buffer (system-scope loads see
+// what the host wrote before the launch): internal ids to samples, the
+// caller's ids to the samples output when one is requested.
+__global__ void k_stage_samples(const int32_t* stage_ids, const int32_t* stage_caller, int32_t k, int32_t* samples,
+                                int32_t* samples_out) {
+    for (int32_t i = threadIdx.x; i < k; i += blockDim.x) {
+        samples[i] = __hip_atomic_load(stage_ids + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (samples_out) samples_out[i] = __hip_atomic_load(stage_caller + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// A captured weighted estimate's last launch: its flags and the largest
+// distance of each direction's searches, into pinned memory.
+__global__ void k_wstatus_out(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ maxd,
+                              uint32_t* flags_host, uint32_t* maxd_host) {
+    constexpr int nf = (int)(sizeof(DevFlags) / 4);
+    const int t = threadIdx.x;
+    if (t < nf) __hip_atomic_store(flags_host + t, flags[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    else if (t < nf + 2) __hip_atomic_store(maxd_host + (t - nf), maxd[t - nf], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 constexpr int32_t kStagedSamples = 256;  // samples of an estimate that can be replayed from a captured graph
 
 struct Lane {
@@ -336,6 +357,7 @@ struct Lane {
         DevFlags flags;
         BfsCtl ctl_fwd;  // a round-trip replay: the forward search's control block
         DevFlags flags_fwd;
+        uint32_t wmaxd[2];  // a weighted replay: the largest distance of each direction's searches
         int32_t ids[kStagedSamples];     // the samples, internal ids (read by the traversal's first launch)
         int32_t caller[kStagedSamples];  // the same, as the caller numbers them
     };
@@ -353,6 +375,7 @@ struct Lane {
         hipGraphExec_t exec = nullptr;
         int32_t lmax = 0, levels = 0;
         int32_t lmax_fwd = -1, levels_fwd = 0;  // round trip: the forward search (the reverse one above)
+        bool weighted = false;  // weighted searches: lmax_fwd, lmax bound each direction's largest distance
     };
     std::vector<Captured> captured;  // most recently used last
     static constexpr size_t kMaxCaptured = 8;
@@ -1260,7 +1283,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
     const size_t small = Carver::sz(sizeof(int32_t) * k) + Carver::sz(sizeof(DevFlags)) +
                          Carver::sz(sizeof(LevelCounters) * kCounterSlots) + Carver::sz(sizeof(int32_t) * n) +
                          Carver::sz(sizeof(int64_t) * k) + Carver::sz(sizeof(int32_t) * (size_t)k * k) +
-                         Carver::sz(sizeof(int32_t) * ngroups);
+                         Carver::sz(sizeof(int32_t) * ngroups) + Carver::sz(sizeof(uint32_t) * 2);
     const int32_t kg0 = std::min(k, 256);
     const int Wg = (kg0 + 63) / 64;
     // free device memory, queried (once) only where a size depends on it: the
@@ -1294,6 +1317,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             const size_t per = sssp_wsearch_scratch(n, 2) - sssp_wsearch_scratch(n, 1);
             kw = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)k, (free_mem() / 4) / std::max<size_t>(per, 1)));
         }
+        // weighted batched searches of up to 256 samples in one launch per direction can be captured
+        const bool w_single = g.weighted && mode != CC_PLAIN && kw >= k && k <= kStagedSamples;
         size_t trav_scratch;
         if (g.weighted)
             trav_scratch = mode == CC_PLAIN ? sssp_weighted_scratch(n, 1) : sssp_wsearch_scratch(n, kw);
@@ -1308,6 +1333,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         int64_t* src_sum = out->src_sum ? out->src_sum : c.take<int64_t>(k);
         int32_t* dmat = out->dmat ? out->dmat : c.take<int32_t>((size_t)k * k);
         int32_t* fill_level = c.take<int32_t>(ngroups);
+        uint32_t* wmaxd_dev = c.take<uint32_t>(2);  // captured weighted searches: each direction's largest distance
         void* ts = c.take<char>(trav_scratch);
         int32_t* hist = bits_path ? c.take<int32_t>(hist_elems) : nullptr;
         // distance matrices and/or level masks
@@ -1323,7 +1349,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
 
         // a single-group traversal takes its samples from the lane's pinned staging
         // buffer in its first launch (replays included), others from a copy
-        const bool stage_samples = (bits_path || rt_single) && k <= kStagedSamples;
+        const bool stage_samples = (bits_path || rt_single || w_single) && k <= kStagedSamples;
         if (stage_samples) {
             CCG_HIP(hipStreamSynchronize(st));  // the lane's earlier launches are done with the buffer
             std::memcpy(L.rb_host->ids, samples_int.data(), sizeof(int32_t) * k);
@@ -1360,7 +1386,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             return gv;
         };
         // a captured estimate is keyed by everything its launches refer to
-        const bool want_graph = r.graph && (bits_path || rt_single);
+        const bool want_graph = r.graph && (bits_path || rt_single || w_single);
         auto graph_key = [&]() {
             return std::vector<uint64_t>{gr->id, (uint64_t)k, (uint64_t)r.en, (uint64_t)r.ed, (uint64_t)cap,
                                          (uint64_t)(uintptr_t)st, L.gen, (uint64_t)(uintptr_t)out->S_hyb,
@@ -1380,6 +1406,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 // flags back itself; a readback that did not land fails the check below
                 L.rb_host->ctl.done = -1;
                 L.rb_host->ctl_fwd.done = -1;
+                L.rb_host->wmaxd[0] = 0xFFFFFFFFu;
                 CCG_HIP(hipEventRecord(L.ev[0], st));
                 CCG_HIP(hipGraphLaunch(cap_e->exec, st));
                 CCG_HIP(hipEventRecord(L.ev[2], st));
@@ -1388,7 +1415,24 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 const DevFlags hf = L.rb_host->flags;
                 // a round trip: the forward search must also have ended where the captured one did
                 bool fwd_ok = true;
-                if (cap_e->lmax_fwd >= 0) {
+                if (cap_e->weighted) {
+                    // the searches' largest distances within the captured ones (the epilogue's tables
+                    // were sized for those); no traversal control block
+                    const DevFlags wf = L.rb_host->flags;
+                    const uint32_t m0 = L.rb_host->wmaxd[0], m1 = L.rb_host->wmaxd[1];
+                    const bool ok = m0 != 0xFFFFFFFFu && !wf.disconnected && !wf.overflow && !wf.bad_sample &&
+                                    !wf.timeout && (int64_t)m0 <= (int64_t)(g.directed ? cap_e->lmax_fwd : cap_e->lmax) &&
+                                    (!g.directed || (int64_t)m1 <= (int64_t)cap_e->lmax);
+                    if (ok) {
+                        if (timing) {
+                            *timing = cc_timing{};
+                            timing->total_ms = timing->traverse_ms = elapsed(L.ev[0], L.ev[2]);
+                            timing->launches = 1;
+                        }
+                        return CC_OK;
+                    }
+                    fwd_ok = false;  // recompute as usual
+                } else if (cap_e->lmax_fwd >= 0) {
                     const BfsCtl hc0 = L.rb_host->ctl_fwd;
                     fwd_ok = hc0.done == 1 && hc0.status == 0 && hc0.lmax == cap_e->lmax_fwd &&
                              hc0.levels <= cap_e->levels_fwd;
@@ -1415,6 +1459,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         // the histogram and fills sidx in its own first launches
         if (!bits_path && !rt_single) fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
         CCG_HIP(hipEventRecord(L.ev[0], st));
+        if (w_single && stage_samples)
+            hipLaunchKernelGGL(k_stage_samples, dim3(1), dim3(256), 0, st, (const int32_t*)L.rb_dev->ids,
+                               (const int32_t*)L.rb_dev->caller, k, samples_dev, out->samples);
         if (!bits_path && !rt_single) compute_sidx(st, samples_dev, k, sidx, n);
 
         // ---- traversal
@@ -1598,7 +1645,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         record_timing(timing, L, stats, bits_path ? 0 : (int)dk);
         if (timing) timing->levels = stats.levels;
         const cc_status fs = finish_flags(hf);
-        if (want_graph && fs == CC_OK && stats.bfs_levels > 0) {
+        if (want_graph && fs == CC_OK && (stats.bfs_levels > 0 || w_single)) {
             // capture the same estimate (exactly the levels this search ran,
             // the epilogue for its deepest level) for replay; nothing runs now
             Lane::Captured cap_e;
@@ -1609,10 +1656,35 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 cap_e.lmax_fwd = lmax_dir[0];
                 cap_e.levels_fwd = levels_dir[0];
             }
+            if (w_single) {
+                cap_e.weighted = true;
+                cap_e.lmax = g.directed ? lmax_dir[1] : lmax_dir[0];
+                cap_e.lmax_fwd = g.directed ? lmax_dir[0] : -1;
+                cap_e.levels = 0;
+            }
             hipGraph_t graph = nullptr;
             const bool began = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
             bool captured_ok = began;
-            if (began) try {
+            if (began && w_single) try {
+                // the weighted searches (one launch per direction), their distances and the D-based epilogue
+                fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+                hipLaunchKernelGGL(k_stage_samples, dim3(1), dim3(256), 0, st, (const int32_t*)L.rb_dev->ids,
+                                   (const int32_t*)L.rb_dev->caller, k, samples_dev, out->samples);
+                compute_sidx(st, samples_dev, k, sidx, n);
+                for (int dir = 0; dir < (g.directed ? 2 : 1); dir++) {
+                    sssp_weighted_batched_enqueue(st, dir == 0 ? g.rp : g.rrp, dir == 0 ? g.cw : g.rcw, n, samples_dev,
+                                                  k, (uint32_t*)Dt, (uint32_t)std::max(1, gr->tune.delta), ts,
+                                                  trav_scratch, flags, wmaxd_dev + dir);
+                    transpose_dist(st, Dt, dir == 0 ? D : Dr, n, k, dk);
+                }
+                run_epilogue(st, ea, ea_scratch, ea_es, flags);
+                hipLaunchKernelGGL(k_wstatus_out, dim3(1), dim3(64), 0, st, (const uint32_t*)flags,
+                                   (const uint32_t*)wmaxd_dev, (uint32_t*)&L.rb_dev->flags, L.rb_dev->wmaxd);
+                CCG_HIP(hipGetLastError());
+            } catch (const HipError&) {
+                captured_ok = false;
+            }
+            else if (began) try {
                 const uint32_t* ctl_dev = (const uint32_t*)bfs_batched_ctl(ts, n, kg0);
                 for (int dir = 0; dir < (rt_single ? 2 : 1); dir++) {
                     int32_t lm = 0;

@@ -352,6 +352,11 @@ int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, in
                           int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch, size_t scratch_size, int64_t* maxd,
                           TravStats* stats);
 size_t sssp_wsearch_scratch(int64_t n, int32_t kg);
+// The same launches without host reads (stream capture): status and largest
+// distance folded into flags and *maxd_out on the device
+void sssp_weighted_batched_enqueue(hipStream_t st, const uint32_t* rp, const int2* cw, int64_t n,
+                                   const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta,
+                                   void* scratch, size_t scratch_size, DevFlags* flags, uint32_t* maxd_out);
 // (end, length) pairs of a weighted adjacency, for the batched searches
 void zip_arcs(hipStream_t st, const int32_t* col, const int32_t* w, int64_t arcs, int2* out);
 

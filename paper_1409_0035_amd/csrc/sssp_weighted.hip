@@ -732,19 +732,28 @@ size_t sssp_wsearch_scratch(int64_t n, int32_t kg) {
            align256((size_t)kg * 16) + align256(16) + 1024;
 }
 
-// The k searches of a batched estimate, one workgroup each (k_wsearch), into
-// Dt[j][v] (device, source-major rows of length n).  Returns 0 = done, 2 =
-// unreached node, 4 = a distance beyond 2^31 - 2, 5 = the time limit expired.
-int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, int64_t n, const int32_t* samples_dev,
-                          int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch, size_t scratch_size, int64_t* maxd,
-                          TravStats* stats) {
-    if (scratch_size < sssp_wsearch_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted_batched scratch"};
-    if (delta < 1) delta = 1;
+// A captured estimate's searches: the launches of sssp_weighted_batched
+// without its host reads.  The searches' status and the decode's largest
+// distance and unreached flag are folded on the device into the job's flags
+// and *maxd_out, which a replay reads back.
+__global__ void k_wfold(const int32_t* __restrict__ status, int32_t kg, const uint32_t* __restrict__ mx,
+                        DevFlags* flags, uint32_t* maxd_out) {
+    for (int32_t q = threadIdx.x; q < kg; q += blockDim.x) {
+        const int32_t st = status[q];
+        if (st == 4) flags->overflow = 1;
+        else if (st == 5) flags->timeout = 1;
+    }
+    if (threadIdx.x == 0) {
+        if (mx[1]) flags->disconnected = 1;
+        *maxd_out = mx[0];
+    }
+}
+
+static SearchBufs carve_search(void* scratch, int64_t n, int32_t kg, uint32_t** mx) {
     char* p = (char*)scratch;
     SearchBufs B;
-    const int64_t pairs = n * kg;
     B.W = (uint64_t*)p;
-    p += align256((size_t)pairs * 8);
+    p += align256((size_t)n * kg * 8);
     B.near = (int32_t*)p;
     p += align256((size_t)kg * 2 * n * 4);
     B.far = (int32_t*)p;
@@ -755,14 +764,52 @@ int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, in
     p += align256((size_t)kg * 4);
     B.work = (int64_t*)p;
     p += align256((size_t)kg * 16);
-    uint32_t* mx = (uint32_t*)p;
-    const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_wfill64, dim3(gz), dim3(256), 0, st, B.W, pairs, kInfW);
-    // a search that has not finished after two minutes is stopped and reported
+    *mx = (uint32_t*)p;
+    return B;
+}
+
+static uint64_t search_time_limit() {
     int rate_khz = 0, device = 0;
     CCG_HIP(hipGetDevice(&device));
     CCG_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device));
-    const uint64_t limit = (uint64_t)std::max(rate_khz, 1) * 120000ull;
+    return (uint64_t)std::max(rate_khz, 1) * 120000ull;  // two minutes
+}
+
+void sssp_weighted_batched_enqueue(hipStream_t st, const uint32_t* rp, const int2* cw, int64_t n,
+                                   const int32_t* samples_dev, int32_t kg, uint32_t* Dt, uint32_t delta,
+                                   void* scratch, size_t scratch_size, DevFlags* flags, uint32_t* maxd_out) {
+    if (scratch_size < sssp_wsearch_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted_batched scratch"};
+    if (delta < 1) delta = 1;
+    uint32_t* mx = nullptr;
+    const SearchBufs B = carve_search(scratch, n, kg, &mx);
+    const int64_t pairs = n * kg;
+    const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_wfill64, dim3(gz), dim3(256), 0, st, B.W, pairs, kInfW);
+    hipLaunchKernelGGL(k_wsearch, dim3((unsigned)kg), dim3(kSBlock), 0, st, rp, cw, n, samples_dev, B, delta,
+                       search_time_limit());
+    hipLaunchKernelGGL(k_wzero, dim3(1), dim3(64), 0, st, mx, (int64_t)2);
+    hipLaunchKernelGGL(k_wdecode, dim3((unsigned)std::min<int64_t>(gz, 1024)), dim3(256), 0, st, B.W, Dt, pairs, mx,
+                       (int32_t*)(mx + 1));
+    hipLaunchKernelGGL(k_wfold, dim3(1), dim3(256), 0, st, (const int32_t*)B.status, kg, (const uint32_t*)mx, flags,
+                       maxd_out);
+    CCG_HIP(hipGetLastError());
+}
+
+// The k searches of a batched estimate, one workgroup each (k_wsearch), into
+// Dt[j][v] (device, source-major rows of length n).  Returns 0 = done, 2 =
+// unreached node, 4 = a distance beyond 2^31 - 2, 5 = the time limit expired.
+int sssp_weighted_batched(hipStream_t st, const uint32_t* rp, const int2* cw, int64_t n, const int32_t* samples_dev,
+                          int32_t kg, uint32_t* Dt, uint32_t delta, void* scratch, size_t scratch_size, int64_t* maxd,
+                          TravStats* stats) {
+    if (scratch_size < sssp_wsearch_scratch(n, kg)) throw HipError{hipErrorOutOfMemory, "sssp_weighted_batched scratch"};
+    if (delta < 1) delta = 1;
+    uint32_t* mx = nullptr;
+    const SearchBufs B = carve_search(scratch, n, kg, &mx);
+    const int64_t pairs = n * kg;
+    const unsigned gz = (unsigned)std::min<int64_t>((pairs + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_wfill64, dim3(gz), dim3(256), 0, st, B.W, pairs, kInfW);
+    // a search that has not finished after two minutes is stopped and reported
+    const uint64_t limit = search_time_limit();
     KernelTimer kt;
     kt.start(st);
     hipLaunchKernelGGL(k_wsearch, dim3((unsigned)kg), dim3(kSBlock), 0, st, rp, cw, n, samples_dev, B, delta, limit);

@@ -101,8 +101,8 @@ def test_fullsize_every_node(ctx, name):
         _say(f"  sweep at node {v}")
         a, ae = oracle.node_sweep(g, ref["samples"], v, reverse_graph=rg)
         assert sweep["S_sweep"][v] == a and sweep["S_sweep_err"][v] == ae, v
-    if name == "rmat22dir":
-        # the benchmark's path on the round trip: CC_GRAPH replays into device tensors
+    if name in ("rmat22dir", "grid2048w"):
+        # the benchmark's path (round trip, weighted): CC_GRAPH replays into device tensors
         import torch
         dt = {"S_hyb": torch.float64, "S_samp": torch.float64, "S_piv": torch.int64, "S_pub": torch.int64,
               "pivot": torch.int32, "delta": torch.int32, "sampsum": torch.int64}
@@ -116,9 +116,9 @@ def test_fullsize_every_node(ctx, name):
                 cc.cc_estimate_device(ctx.handle, gh, k, out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=seed)
                 replays += cc.cc_last_timing(ctx.handle)["launches"] == 1
                 torch.cuda.synchronize()
-                _say(f"  round-trip call {call}: checking every node")
+                _say(f"  {name} call {call}: checking every node")
                 _check({f: t.cpu().numpy() for f, t in out.items()}, ref, BENCH_OUT, f"{name} replay {call}")
-            assert replays >= 2, "the round trip was not replayed from the captured graph"
+            assert replays >= 2, f"{name} was not replayed from the captured graph"
         finally:
             ctx.release(gh)
     if name != "rmat20":  # the replay test reuses rmat20's reference

@@ -175,3 +175,38 @@ def test_round_trip_replays_match_oracle(k):
         _say(f"  k={k}: {replays} replays")
         assert replays >= 3
         ctx.release(gh)
+
+
+@pytest.mark.parametrize("make,k", [(lambda: graphgen.grid(60, 50, 8, 0.1, 1, 1000, seed=3), 64),
+                                    (lambda: graphgen.gnp(400, 0.02, 35, directed=True, wmax=50), 32)],
+                         ids=["grid-weighted-k64", "gnp-dir-weighted-k32-round-trip"])
+def test_weighted_replays_match_oracle(make, k):
+    """Weighted estimates replayed from a captured graph (the searches, the
+    distances and the D-based epilogue), against the oracle for each seed,
+    with seeds whose searches reach further than the captured ones."""
+    import torch
+    import oracle
+    g = make()
+    rg = graphgen.transpose(g) if g.directed else None
+    fields = {**FIELDS, "S_err": "float64", "S_ad": "float64", "S_ad_err": "float64"}
+    refs = {}
+    with cc.Context(0) as ctx:
+        gh = ctx.upload(g)
+        out = _outputs(torch, g.n, fields)
+        replays = 0
+        for it, seed in enumerate([4, 4, 4, 9, 9, 9, 4]):
+            if seed not in refs:
+                samples = np.asarray(oracle.draw_samples(g.n, k, seed), dtype=np.int32)
+                refs[seed] = oracle.estimate_tails(g, samples, threads=8, reverse_graph=rg)
+            for t in out.values():
+                t.fill_(-1)
+            cc.cc_estimate_device(ctx.handle, gh, k, out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=seed)
+            replays += cc.cc_last_timing(ctx.handle)["launches"] == 1
+            torch.cuda.synchronize()
+            ref = refs[seed]
+            for f in fields:
+                got = out[f].cpu().numpy()
+                assert np.array_equal(got, np.asarray(ref[f]).astype(got.dtype)), (it, seed, f)
+        _say(f"  {g.name} k={k}: {replays} replays")
+        assert replays >= 3
+        ctx.release(gh)
