@@ -226,3 +226,40 @@ def test_weighted_deep_path(ctx):
     w = (np.arange(n - 1) * 7919 % 1000 + 1).astype(np.int32)
     g = graphgen.csr_from_arcs(n, i, i + 1, w, name="wpath900")
     parity(ctx, g, 5, seed=2)
+
+
+# ---------------------------------------------------------------- degenerate inputs
+
+DEGENERATE = [
+    ("single-node", lambda: graphgen.csr_from_arcs(1, [], [])),
+    ("one-edge", lambda: graphgen.csr_from_arcs(2, [0], [1])),
+    ("path3", lambda: graphgen.csr_from_arcs(3, [0, 1], [1, 2])),
+    ("two-cycle-directed", lambda: graphgen.csr_from_arcs(2, [0, 1], [1, 0], symmetrize=False, directed=True)),
+    ("one-edge-weighted", lambda: graphgen.csr_from_arcs(2, [0], [1], [7])),
+    ("triangle-directed-weighted", lambda: graphgen.csr_from_arcs(3, [0, 1, 2], [1, 2, 0], [2, 3, 5], symmetrize=False,
+                                                                  directed=True)),
+]
+
+
+@pytest.mark.parametrize("name,make", DEGENERATE, ids=[d[0] for d in DEGENERATE])
+def test_degenerate_graphs(ctx, name, make):
+    """One, two and three nodes, every k from 1 to n, on every path (batched,
+    plain, captured replays): the estimates against the oracle."""
+    import torch
+    g = make()
+    for k in range(1, g.n + 1):
+        parity(ctx, g, k, seed=k)
+        samples = oracle.draw_samples(g.n, k, k)
+        rg = graphgen.transpose(g) if g.directed else None
+        ref = oracle.estimate_all(g, samples, threads=1, reverse_graph=rg)
+        gh = ctx.upload(g)
+        try:
+            out = {"S_hyb": torch.empty(g.n, dtype=torch.float64, device="cuda"),
+                   "pivot": torch.empty(g.n, dtype=torch.int32, device="cuda")}
+            for _ in range(3):
+                cc.cc_estimate_device(ctx.handle, gh, k, out, mode=cc.CC_BATCHED | cc.CC_GRAPH, seed=k)
+                torch.cuda.synchronize()
+                assert np.array_equal(out["S_hyb"].cpu().numpy(), ref["S_hyb"]), (name, k)
+                assert np.array_equal(out["pivot"].cpu().numpy(), ref["pivot"]), (name, k)
+        finally:
+            ctx.release(gh)
