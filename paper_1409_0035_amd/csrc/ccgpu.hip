@@ -1468,6 +1468,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         int rc = 0;
         int32_t lmax_dir[2] = {0, 0};
         int32_t levels_dir[2] = {0, 0};  // levels each direction's batched traversal ran
+        bool rt_summed = false;          // D holds the round-trip distances (no separate reverse array)
         for (int dir = 0; dir < (g.directed ? 2 : 1) && rc == 0; dir++) {
             // forward distances d(c_i -> v): push over out-arcs, pull over in-arcs;
             // reverse distances d(v -> c_i): the same on the transposed graph
@@ -1534,8 +1535,13 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     if (!bits_path) {
                         if ((int64_t)lm > DistT<uint8_t>::max_level && dk == DistKind::U8) { rc = 3; break; }
                         if ((int64_t)lm > DistT<uint16_t>::max_level && dk == DistKind::U16) { rc = 3; break; }
-                        materialize_distances(st, snap, (size_t)n * ((kg + 63) / 64), lm, fill_level, n, kg, s0, k, Dd,
-                                              dk, flags);
+                        // a round trip of one sample group with one-byte rows whose sums fit: the reverse
+                        // distances are added to the forward ones in place, so the epilogue reads one array
+                        const bool sum = g.directed && dir == 1 && kg == k && dk == DistKind::U8 &&
+                                         (int64_t)lmax_dir[0] + lm <= DistT<uint8_t>::max_level;
+                        materialize_distances(st, snap, (size_t)n * ((kg + 63) / 64), lm, fill_level, n, kg, s0, k,
+                                              sum ? D : Dd, dk, flags, sum);
+                        if (sum) rt_summed = true;
                     }
                 }
             }
@@ -1614,7 +1620,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ea.k = k;
             ea.dk = dk;
             ea.D = D;
-            ea.Dr = Dr;
+            ea.Dr = rt_summed ? nullptr : Dr;
             ea.samples = samples_dev;
             ea.sidx = sidx;
             ea.orig = g.orig;
@@ -1706,8 +1712,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     (void)bfs_batched(st, make_view(dir), samples_dev, k, 0, k, lv, sidx, ts, trav_scratch, cnt,
                                       &ignored, nullptr);
                     if (rt_single) {
+                        const bool sum = dir == 1 && rt_summed;
                         materialize_distances(st, snap, (size_t)n * ((k + 63) / 64), lmax_dir[dir], fill_level, n, k,
-                                              0, k, dir == 0 ? D : Dr, dk, flags);
+                                              0, k, (dir == 0 || sum) ? D : Dr, dk, flags, sum);
                         if (dir == 0)  // the forward search's control block, before the reverse one reuses it
                             hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st, ctl_dev,
                                                (const uint32_t*)flags, (uint32_t*)&L.rb_dev->ctl_fwd,

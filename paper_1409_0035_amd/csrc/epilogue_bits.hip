@@ -341,7 +341,7 @@ __device__ __forceinline__ uint64_t spread8(uint32_t b) {
 template <int W, typename OT>
 __global__ __launch_bounds__(kBlock) void k_materialize_words(
     SnapView sv, int32_t lmax, int64_t n, int32_t kg, int32_t src_base, int32_t k, OT* __restrict__ out,
-    const int32_t* __restrict__ orig, int vec, DevFlags* flags) {
+    const int32_t* __restrict__ orig, int vec, DevFlags* flags, int add) {
     const int64_t count = n * W;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = t / W;
@@ -366,6 +366,14 @@ __global__ __launch_bounds__(kBlock) void k_materialize_words(
         if (vec && nb == 64) {
             if constexpr (sizeof(OT) == 1) {
                 uint4* d4 = reinterpret_cast<uint4*>(dst);
+                if (add) {  // the other direction's distances are there: bytewise sums (the host checked they fit)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const uint4 o = d4[q];
+                        acc[2 * q] += ((uint64_t)o.y << 32) | o.x;
+                        acc[2 * q + 1] += ((uint64_t)o.w << 32) | o.z;
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < 4; q++)
                     d4[q] = make_uint4((uint32_t)acc[2 * q], (uint32_t)(acc[2 * q] >> 32), (uint32_t)acc[2 * q + 1],
@@ -382,7 +390,10 @@ __global__ __launch_bounds__(kBlock) void k_materialize_words(
                 }
             }
         } else {
-            for (int i = 0; i < nb; i++) dst[i] = (OT)((acc[i >> 3] >> (8 * (i & 7))) & 0xFF);
+            for (int i = 0; i < nb; i++) {
+                const OT d = (OT)((acc[i >> 3] >> (8 * (i & 7))) & 0xFF);
+                dst[i] = add ? (OT)(dst[i] + d) : d;
+            }
         }
     }
 }
@@ -440,7 +451,7 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
     if (a.Dout) {
         if (lmax < 255) {
             hipLaunchKernelGGL((k_materialize_words<W, int32_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
-                               sv, lmax, n, k, 0, k, a.Dout, a.orig, (int)(k % 4 == 0), flags);
+                               sv, lmax, n, k, 0, k, a.Dout, a.orig, (int)(k % 4 == 0), flags, 0);
         } else {
             hipLaunchKernelGGL((k_materialize<W, uint8_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, sv, lmax,
                                n, k, 0, k, (uint8_t*)nullptr, a.orig, a.Dout, flags);
@@ -476,7 +487,8 @@ void bits_t(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags* 
         if (lmax < 255) {
             ea.dk = DistKind::U8;
             hipLaunchKernelGGL((k_materialize_words<W, uint8_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
-                               sv, lmax, n, k, 0, k, (uint8_t*)dq, (const int32_t*)nullptr, (int)(k % 16 == 0), flags);
+                               sv, lmax, n, k, 0, k, (uint8_t*)dq, (const int32_t*)nullptr, (int)(k % 16 == 0), flags,
+                               0);
         } else if (lmax < 65535) {
             ea.dk = DistKind::U16;
             hipLaunchKernelGGL((k_materialize<W, uint16_t>), dim3(grid_for(n * k, 65536)), dim3(256), 0, st, sv,
@@ -499,27 +511,29 @@ void bits_mt(hipStream_t st, const BitsEpilogueArgs& a, void* scratch, DevFlags*
 
 template <int W, typename DT>
 void materialize_t(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
-                   int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DevFlags* flags) {
+                   int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DevFlags* flags, bool add) {
     const SnapView sv{snap, plane, W, 0, 0, fill_level};
     if constexpr (sizeof(DT) == 1) {
         if (lmax < 255) {
             const int vec = (k % 16 == 0) && (src_base % 16 == 0);
             hipLaunchKernelGGL((k_materialize_words<W, uint8_t>), dim3(grid_for(n * W, 65536)), dim3(kBlock), 0, st,
-                               sv, lmax, n, kg, src_base, k, (uint8_t*)D, (const int32_t*)nullptr, vec, flags);
+                               sv, lmax, n, kg, src_base, k, (uint8_t*)D, (const int32_t*)nullptr, vec, flags,
+                               add ? 1 : 0);
             return;
         }
     }
+    if (add) throw HipError{hipErrorInvalidValue, "summed distances need one-byte rows"};
     hipLaunchKernelGGL((k_materialize<W, DT>), dim3(grid_for(n * kg, 65536)), dim3(256), 0, st, sv, lmax, n, kg,
                        src_base, k, (DT*)D, (const int32_t*)nullptr, (int32_t*)nullptr, flags);
 }
 
 template <int W>
 void materialize_w(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
-                   int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags) {
+                   int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags, bool add) {
     switch (dk) {
-        case DistKind::U8: materialize_t<W, uint8_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags); break;
-        case DistKind::U16: materialize_t<W, uint16_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags); break;
-        default: materialize_t<W, uint32_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags); break;
+        case DistKind::U8: materialize_t<W, uint8_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags, add); break;
+        case DistKind::U16: materialize_t<W, uint16_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags, add); break;
+        default: materialize_t<W, uint32_t>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, flags, add); break;
     }
 }
 
@@ -550,12 +564,13 @@ void run_bits_epilogue(hipStream_t st, const BitsEpilogueArgs& a, void* scratch,
 }
 
 void materialize_distances(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
-                           int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags) {
+                           int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags,
+                           bool add) {
     switch ((kg + 63) / 64) {
-        case 1: materialize_w<1>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
-        case 2: materialize_w<2>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
-        case 3: materialize_w<3>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
-        default: materialize_w<4>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags); break;
+        case 1: materialize_w<1>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags, add); break;
+        case 2: materialize_w<2>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags, add); break;
+        case 3: materialize_w<3>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags, add); break;
+        default: materialize_w<4>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags, add); break;
     }
     CCG_HIP(hipGetLastError());
 }

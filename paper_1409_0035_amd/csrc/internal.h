@@ -322,7 +322,8 @@ BfsCtl* bfs_batched_ctl(void* scratch, int64_t n, int32_t kg);
 // Distances of one sample group from its level masks into the node-major
 // matrix D (columns src_base .. src_base+kg), in the given width.
 void materialize_distances(hipStream_t st, const uint64_t* snap, size_t plane, int32_t lmax, const int32_t* fill_level,
-                           int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags);
+                           int64_t n, int32_t kg, int32_t src_base, int32_t k, void* D, DistKind dk, DevFlags* flags,
+                           bool add = false);
 
 // Plain single-source BFS for every sample, source-major output Dt[k][n].
 bool bfs_plain(hipStream_t st, const uint32_t* out_rp, const int32_t* out_col, const uint32_t* in_rp,
