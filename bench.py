@@ -34,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+ATOMIC_PEAK_GPS = 27.0  # random 64-bit atomic minima completed per second, device-wide (measured, see profiles/)
 METRIC = "GTEPS of k-source SSSP + hybrid estimate, batched vs plain; p99 job latency"
 
 
@@ -356,7 +357,12 @@ def wsearch_roofline(timings, workload: str, n: int, arcs: int, k: int, tuning: 
             "avg_launch_us": round(ms / launches * 1e3, 1), "launches_per_step": launches / len(timings),
             "bytes_per_node_and_arc": 16, "relaxations_per_arc": round(relaxed / (k * arcs), 4),
             "takes_per_node": round(taken / (k * n), 4),
-            "relaxations_per_s": round(relaxed / (ms / len(timings) / 1e3) / 1e9, 3)}
+            "relaxations_per_s": round(relaxed / (ms / len(timings) / 1e3) / 1e9, 3),
+            # every relaxation is one atomic minimum and every take one atomic AND: against the device's
+            # measured rate of random 64-bit atomics (profiles/atomic_rate_probe.md)
+            "atomics_g_per_s": round((relaxed + taken) / (ms / len(timings) / 1e3) / 1e9, 3),
+            "atomic_peak_g_per_s": ATOMIC_PEAK_GPS,
+            "atomic_frac": round((relaxed + taken) / (ms / len(timings) / 1e3) / 1e9 / ATOMIC_PEAK_GPS, 4)}
 
 
 def measured_traffic_kernel(kernel: str, workload: str, source: str, tuning: str):
