@@ -117,6 +117,9 @@ def scatter_roofline(timings, W: int, workload: str, tuning: dict) -> dict:
             "traffic_frac": None if traffic is None else round(traffic / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             # the scatter launches' share of the level batches (the rest: the merge launches and gaps)
             "share_of_level_kernels": round(ms / level_ms, 3) if level_ms > 0 else None,
+            # masks gathered (or pushed along) per second: a random-access rate, between the device's
+            # measured 66 G/s for random loads that miss L2 and 261 G/s for ones that hit it
+            "gathers_g_per_s": round(arcs / (ms / 1e3) / 1e9, 2),
             "pull_levels_gbs": round(pull_arcs * bytes_per_arc(W) / (pull_ms / 1e3) / 1e9, 1) if pull_ms > 0 else None}
 
 

@@ -1,8 +1,9 @@
 // Memory-system rate probe (not part of the library): 1024-thread
 // workgroups issue 64-bit atomic minima, or plain loads, at pseudo-random
-// addresses of a 32 MiB buffer, eight in flight per lane.  It gives the
-// ceiling the weighted searches' relaxations run against: per-CU issue rate
-// with one workgroup, and the device-wide rate with 64 and 256 workgroups.
+// addresses of a 32 MiB buffer (beyond an XCD's L2) or a 2 MiB one (inside
+// it), eight in flight per lane.  It gives the ceilings the weighted
+// searches' relaxations and the BFS's mask gathers run against: per-CU issue
+// rate with one workgroup, and the device-wide rate with 64 and 256.
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstdio>
@@ -45,8 +46,7 @@ __global__ __launch_bounds__(1024) void k_probe(uint64_t* buf, uint32_t mask, in
 }
 
 template <int MODE>
-void run(const char* name, int blocks) {
-    const uint32_t size = 1u << 22;  // 4 Mi words = 32 MiB
+void run(const char* name, int blocks, uint32_t size) {
     uint64_t *buf = nullptr, *sink = nullptr;
     CHECK(hipMalloc(&buf, sizeof(uint64_t) * size));
     CHECK(hipMemset(buf, 0xFF, sizeof(uint64_t) * size));
@@ -63,8 +63,8 @@ void run(const char* name, int blocks) {
     float ms = 0.f;
     CHECK(hipEventElapsedTime(&ms, a, b));
     const double ops = (double)blocks * 1024 * iters * 8;
-    std::printf("%-30s workgroups=%3d: %8.3f ms, %6.2f G lane-ops/s, %6.2f cycles per lane-op per CU at 2.4 GHz\n",
-                name, blocks, ms, ops / ms / 1e6, (ms * 2.4e6) / (ops / blocks));
+    std::printf("%-32s %3u MiB, workgroups=%3d: %8.3f ms, %6.2f G lane-ops/s, %6.2f cycles per lane-op per CU at 2.4 GHz\n",
+                name, (unsigned)(size >> 17), blocks, ms, ops / ms / 1e6, (ms * 2.4e6) / (ops / blocks));
     CHECK(hipFree(buf));
     CHECK(hipFree(sink));
     CHECK(hipEventDestroy(a));
@@ -72,10 +72,12 @@ void run(const char* name, int blocks) {
 }
 
 int main() {
-    for (int blocks : {1, 64, 256}) {
-        run<kAtomicWg>("atomic min u64, workgroup scope", blocks);
-        run<kAtomicAgent>("atomic min u64, agent scope", blocks);
-        run<kLoad>("load u64", blocks);
+    for (uint32_t size : {1u << 22, 1u << 18}) {  // 32 MiB, 2 MiB of 64-bit words
+        for (int blocks : {1, 64, 256}) {
+            run<kAtomicWg>("atomic min u64, workgroup scope", blocks, size);
+            run<kAtomicAgent>("atomic min u64, agent scope", blocks, size);
+            run<kLoad>("load u64", blocks, size);
+        }
     }
     return 0;
 }
