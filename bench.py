@@ -540,8 +540,8 @@ def main():
                          "20%% zeros) on the workload and print its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by sample "
-              "across GPUs by design but no multi-GPU run is part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the estimate shards by sample "
+              "across GPUs by design, but only its one-GPU path is implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
