@@ -263,3 +263,54 @@ def test_degenerate_graphs(ctx, name, make):
                 assert np.array_equal(out["pivot"].cpu().numpy(), ref["pivot"]), (name, k)
         finally:
             ctx.release(gh)
+
+
+# ---------------------------------------------------------------- randomised sweep
+
+def _random_case(rng):
+    kind = rng.choice(["gnp", "ba", "rmat", "grid", "gnp-dir", "rmat-dir"])
+    weighted = bool(rng.random() < 0.35)
+    if kind == "gnp":
+        g = graphgen.gnp(int(rng.integers(5, 400)), float(rng.uniform(0.01, 0.2)), int(rng.integers(1 << 30)),
+                         wmax=int(rng.integers(2, 60)) if weighted else 1)
+    elif kind == "gnp-dir":
+        g = graphgen.gnp(int(rng.integers(5, 300)), float(rng.uniform(0.01, 0.2)), int(rng.integers(1 << 30)),
+                         directed=True, wmax=int(rng.integers(2, 60)) if weighted else 1)
+    elif kind == "ba":
+        g = graphgen.ba(int(rng.integers(10, 3000)), int(rng.integers(1, 5)), seed=int(rng.integers(1 << 30)))
+        if weighted:
+            g = graphgen.with_lengths(g, 1, int(rng.integers(2, 500)), int(rng.integers(1 << 30)))
+    elif kind == "grid":
+        g = graphgen.grid(int(rng.integers(2, 40)), int(rng.integers(2, 40)), int(rng.choice([4, 8])),
+                          float(rng.uniform(0, 0.15)), 1, int(rng.integers(2, 100)) if weighted else 1,
+                          seed=int(rng.integers(1 << 30)))
+    else:
+        g = graphgen.rmat(int(rng.integers(6, 11)), int(rng.integers(4, 17)), seed=int(rng.integers(1 << 30)),
+                          directed=kind == "rmat-dir")
+        if weighted:
+            g = graphgen.with_lengths(g, 1, int(rng.integers(2, 1000)), int(rng.integers(1 << 30)))
+    k = int(min(g.n, rng.choice([1, 2, 7, 64, 65, 128, 200, 256, 300])))
+    den = int(rng.integers(1, 12))
+    eps = None if rng.random() < 0.4 else (int(rng.integers(1, den + 1)), den)
+    mode = int(rng.choice([cc.CC_BATCHED, cc.CC_PLAIN, cc.CC_BATCHED | cc.CC_GRAPH]))
+    return g, k, eps, mode
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_random_configurations(ctx, case):
+    """Seeded random graph family, direction, arc lengths, k, eps and mode
+    (eager, plain, captured), every output against the oracle."""
+    rng = np.random.default_rng(9000 + case)
+    g, k, eps, mode = _random_case(rng)
+    seed = int(rng.integers(1 << 20))
+    samples = oracle.draw_samples(g.n, k, seed)
+    rg = graphgen.transpose(g) if g.directed else None
+    ref = oracle.estimate_all(g, samples, eps=eps, threads=8, reverse_graph=rg)
+    _say(f"  case {case}: {g.name} n={g.n} arcs={g.arcs} weighted={g.w is not None} k={k} eps={eps} mode={mode}")
+    gh = ctx.upload(g)
+    try:
+        for _ in range(2 if mode & cc.CC_GRAPH else 1):
+            res = cc.cc_estimate(ctx.handle, gh, k, mode=mode, seed=seed, eps=eps, outputs=ALL)
+            check_all(res, ref, samples)
+    finally:
+        ctx.release(gh)
