@@ -57,17 +57,18 @@ def bytes_per_arc(W: int) -> int:
     return 4 + 8 * W
 
 
-def source_digest() -> str:
+def source_digest(name: str = "bfs_batched.hip") -> str:
     import hashlib
-    with open(os.path.join(ROOT, "paper_1409_0035_amd", "csrc", "bfs_batched.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_1409_0035_amd", "csrc", name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def measured_traffic(workload: str, tuning: dict, path: str | None = None):
     """HBM bytes per launch of the scatter kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes, each scaled by the same counter on a copy
-    of known size; None once the kernel source has changed since, or when
-    the run's launch knobs differ from the profiled ones."""
+    of known size; None once the kernel source or the graph builder has
+    changed since, or when the run's launch knobs differ from the profiled
+    ones."""
     if path is None:
         path = os.path.join(ROOT, "profiles", f"{SCATTER_KERNEL}_{workload}_pmc.md")
     if not os.path.exists(path):
@@ -79,6 +80,9 @@ def measured_traffic(workload: str, tuning: dict, path: str | None = None):
                 key, _, val = line[2:].partition(": ")
                 vals[key.strip()] = val.strip().strip("`")
     if vals.get("bfs_batched.hip sha256[:16]") != source_digest():
+        return None
+    # the graph builder decides the hub prefix and the node order the kernel gathers in
+    if vals.get("ccgpu.hip sha256[:16]") != source_digest("ccgpu.hip"):
         return None
     prof_tuning = vals.get("tuning", "")
     bfs_knobs = ("alpha", "level_blocks", "scatter_blocks")
