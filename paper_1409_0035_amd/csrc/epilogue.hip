@@ -26,6 +26,11 @@ namespace ccg {
 namespace {
 
 constexpr int kBlock = 256;
+// the row estimate with its tables in LDS: block size, largest table copy,
+// blocks per launch (two per CU of the 256)
+constexpr int kEstBlock = 512;
+constexpr size_t kEstTableLds = 64 * 1024;
+constexpr int64_t kEstTableBlocks = 512;
 
 // Reads element i of a distance row; with RT the reverse row is added.
 template <typename DT, bool RT>
@@ -118,11 +123,8 @@ struct RowPiece {
     static constexpr int PER = 16 / (int)sizeof(DT);
     uint32_t d[PER];
     bool unreached = false;
-    __device__ __forceinline__ void load(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t v, int32_t k,
-                                         int sub) {
-        const uint4 a = ((const uint4*)(D + v * k))[sub];
-        uint4 b = make_uint4(0, 0, 0, 0);
-        if (RT) b = ((const uint4*)(Dr + v * k))[sub];
+    // the lane's 16 bytes of the row (a) and of the reverse row (b)
+    __device__ __forceinline__ void decode(const uint4 a, const uint4 b) {
         const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
         const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
         constexpr uint32_t mask = sizeof(DT) == 4 ? 0xFFFFFFFFu : ((1u << (8 * sizeof(DT))) - 1);
@@ -139,7 +141,56 @@ struct RowPiece {
             }
         }
     }
+    __device__ __forceinline__ void load(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t v, int32_t k,
+                                         int sub) {
+        const uint4 a = ((const uint4*)(D + v * k))[sub];
+        uint4 b = make_uint4(0, 0, 0, 0);
+        if (RT) b = ((const uint4*)(Dr + v * k))[sub];
+        decode(a, b);
+    }
 };
+
+// A lane's undecoded piece of a node's row and the node's sample index, so
+// the next node's loads can be in flight while this one is worked on.
+// The loads are unconditional, of node min(v, n - 1) (n >= 1): a refill past
+// the end reads the last node again and its values go unused, and the
+// registers never merge old and new values (such a merge makes the compiler
+// wait for the loads in flight).
+template <typename DT, bool RT>
+struct RawPiece {
+    uint4 a, b;
+    int32_t j;
+    __device__ __forceinline__ void fetch(const DT* __restrict__ D, const DT* __restrict__ Dr,
+                                          const int32_t* __restrict__ sidx, int64_t v, int64_t n, int32_t k, int sub) {
+        const int64_t vc = v < n ? v : n - 1;
+        a = ((const uint4*)(D + vc * k))[sub];
+        b = make_uint4(0, 0, 0, 0);
+        if (RT) b = ((const uint4*)(Dr + vc * k))[sub];
+        j = sidx[vc];
+    }
+};
+
+// Byte j of the result is byte (j + b) mod 16 of x, for 0 <= b < 16.
+__device__ __forceinline__ uint4 rotate_bytes(const uint4 x, uint32_t b) {
+    uint32_t w0 = x.x, w1 = x.y, w2 = x.z, w3 = x.w;
+    if (b & 4) {
+        const uint32_t t = w0;
+        w0 = w1;
+        w1 = w2;
+        w2 = w3;
+        w3 = t;
+    }
+    if (b & 8) {
+        const uint32_t t0 = w0, t1 = w1;
+        w0 = w2;
+        w1 = w3;
+        w2 = t0;
+        w3 = t1;
+    }
+    const uint32_t s = b & 3;  // alignbyte(hi, lo, s): bytes s .. s+3 of the pair (lo, hi)
+    return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, s), __builtin_amdgcn_alignbyte(w2, w1, s),
+                      __builtin_amdgcn_alignbyte(w3, w2, s), __builtin_amdgcn_alignbyte(w0, w3, s));
+}
 
 template <int G>
 __device__ __forceinline__ int64_t group_sum64(int64_t x) {
@@ -148,153 +199,319 @@ __device__ __forceinline__ int64_t group_sum64(int64_t x) {
     return x;
 }
 
-// histogram over non-sampled nodes (as k_reduce)
-template <typename DT, bool RT, int G>
+template <int G>
+__device__ __forceinline__ uint32_t group_sum32(uint32_t x) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
+    return x;
+}
+
+// Row stride of the LDS histogram of k_reduce_rows: hlen made odd, so that
+// counters (i, d) of samples that differ mod 64 sit in different banks when d
+// is the same.
+__host__ __device__ inline int64_t hist_stride(int64_t hlen) { return hlen | 1; }
+
+// histogram over non-sampled nodes (as k_reduce).  With LDS the block's copy
+// is [k][hist_stride(hlen)], and each lane takes its piece rotated so that the
+// 64 lanes of one update count 64 samples that differ mod 64 (when k allows):
+// without the rotation the node slots of a wave (neighbouring nodes, which
+// mostly share a distance) would all add to the same counter.  (Measured on
+// the round trip of the directed R-MAT scale-22 graph, k = 128: 179 us per
+// launch without the rotation, 84 us rotating by the node slot alone, 64 us
+// as here; a [d][i] layout was slower, 157 us.)  Two pieces are refilled in
+// turn, so the next trip's loads are in flight while one is counted.
+template <typename DT, bool RT, int G, bool USE_LDS>
 __global__ __launch_bounds__(kBlock) void k_reduce_rows(const DT* __restrict__ D, const DT* __restrict__ Dr,
                                                         int64_t n, int32_t k, const int32_t* __restrict__ sidx,
-                                                        int64_t hlen, int32_t* __restrict__ hist, int use_lds,
-                                                        DevFlags* flags) {
-    extern __shared__ int32_t lds_hist[];  // [k][hlen] when use_lds
-    if (use_lds) {
-        for (int64_t t = threadIdx.x; t < (int64_t)k * hlen; t += kBlock) lds_hist[t] = 0;
+                                                        int64_t hlen, int32_t* __restrict__ hist, DevFlags* flags) {
+    extern __shared__ int32_t lds_hist[];  // [k][hist_stride(hlen)] with USE_LDS
+    if (n < 1) return;
+    const int64_t hs = hist_stride(hlen);
+    if (USE_LDS) {
+        for (int64_t t = threadIdx.x; t < (int64_t)k * hs; t += kBlock) lds_hist[t] = 0;
         __syncthreads();
     }
     constexpr int PER = RowPiece<DT, RT>::PER;
+    constexpr int NPW = 64 / G;    // node slots per wave
+    constexpr int SPB = 64 / PER;  // lane pieces per 64 samples
     const int sub = lane_id() & (G - 1);
-    const int64_t per_block = kBlock / G;
+    const uint32_t rot = (uint32_t)((lane_id() / G + NPW * (sub / SPB)) & (PER - 1));
+    const uint32_t hlen32 = (uint32_t)min<int64_t>(hlen, 0xFFFFFFFFll);
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / G);
     bool bad = false;
-    for (int64_t v0 = (int64_t)blockIdx.x * per_block; v0 < n; v0 += (int64_t)gridDim.x * per_block) {
-        const int64_t v = v0 + threadIdx.x / G;
-        if (v >= n || sidx[v] >= 0) continue;
+    // counts the piece in rp (node v), then refills rp with node v + 2 * stride
+    auto step = [&](RawPiece<DT, RT>& rp, int64_t v) {
+        const int32_t j = rp.j;
         RowPiece<DT, RT> r;
-        r.load(D, Dr, v, k, sub);
+        r.decode(rotate_bytes(rp.a, rot * (uint32_t)sizeof(DT)),
+                 RT ? rotate_bytes(rp.b, rot * (uint32_t)sizeof(DT)) : rp.b);
+        rp.fetch(D, Dr, sidx, v + 2 * stride, n, k, sub);
+        if (j >= 0) return;
+        if (r.unreached) {
+            bad = true;
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < PER; e++) {
-            const int64_t i = (int64_t)sub * PER + e;
+            const uint32_t i = (uint32_t)sub * PER + ((e + rot) & (PER - 1));
             const uint32_t d = r.d[e];
-            if ((int64_t)d >= hlen || r.unreached) {
+            if (d >= hlen32) {
                 bad = true;
-            } else if (use_lds) {
-                atomicAdd(&lds_hist[i * hlen + d], 1);
+            } else if (USE_LDS) {
+                atomicAdd(&lds_hist[__umul24(i, (uint32_t)hs) + d], 1);
             } else {
-                atomicAdd(&hist[i * hlen + d], 1);
+                atomicAdd(&hist[(int64_t)i * hlen + d], 1);
             }
         }
+    };
+    const int64_t v0 = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
+    RawPiece<DT, RT> pa, pb;
+    pa.fetch(D, Dr, sidx, v0, n, k, sub);
+    pb.fetch(D, Dr, sidx, v0 + stride, n, k, sub);
+    for (int64_t v = v0; v < n; v += 2 * stride) {
+        step(pa, v);
+        if (v + stride < n) step(pb, v + stride);
     }
     if (bad) flags->disconnected = 1;
-    if (use_lds) {
+    if (USE_LDS) {
         __syncthreads();
-        for (int64_t t = threadIdx.x; t < (int64_t)k * hlen; t += kBlock) {
+        for (int64_t t = threadIdx.x; t < (int64_t)k * hs; t += kBlock) {
+            const int64_t i = t / hs, d = t - i * hs;
             const int32_t c = lds_hist[t];
-            if (c) atomicAdd(&hist[t], c);
+            if (c && d < hlen) atomicAdd(&hist[i * hlen + d], c);
         }
     }
 }
 
-// the estimators (as k_estimate)
-template <typename DT, bool RT, typename MT, int G>
-__global__ __launch_bounds__(kBlock) void k_estimate_rows(
+// Bytes of the estimate's small tables when copied to LDS: Tsum (k x tlen
+// int64), src_sum (k int64), Tcnt (k x tlen int32), then dmat_c (k x k MT) at
+// a 16-byte boundary.
+inline size_t est_table_bytes(int32_t k, int64_t tlen, size_t mt_bytes) {
+    const size_t head = (size_t)k * (size_t)tlen * 12 + (size_t)k * 8;
+    return ((head + 15) & ~size_t(15)) + (size_t)k * (size_t)k * mt_bytes;
+}
+
+// The lane's PER entries of a row of dmat_c, one 16-byte load when the piece
+// is a multiple of 16 bytes (then the row start is aligned too: k * sizeof(DT)
+// is a multiple of 16, so k is a multiple of PER).
+template <typename MT, int PER>
+__device__ __forceinline__ void load_mt_piece(const MT* row, int sub, uint32_t (&m)[PER]) {
+    constexpr int BYTES = PER * (int)sizeof(MT);
+    if constexpr (BYTES % 16 == 0) {
+        constexpr uint32_t mask = sizeof(MT) == 4 ? 0xFFFFFFFFu : ((1u << (8 * sizeof(MT))) - 1);
+        const uint4* p = (const uint4*)row + (int64_t)sub * (BYTES / 16);
+#pragma unroll
+        for (int c = 0; c < BYTES / 16; c++) {
+            const uint4 x = p[c];
+            const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int e = 0; e < 4 / (int)sizeof(MT); e++)
+                    m[c * (16 / (int)sizeof(MT)) + q * (4 / (int)sizeof(MT)) + e] =
+                        (w[q] >> (e * 8 * (int)sizeof(MT))) & mask;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < PER; e++) m[e] = row[(int64_t)sub * PER + e];
+    }
+}
+
+// the estimators (as k_estimate).  With LT the small tables (dmat_c, Tcnt,
+// Tsum, src_sum) are copied to LDS first, so a node's lookups do not wait
+// behind the next node's row loads, which are issued before the node is
+// worked on.
+template <typename DT, bool RT, typename MT, int G, bool LT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
     const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
     const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed,
     double* S_hyb, double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out,
     int64_t* sampsum_out, uint4* stage, DevFlags* flags) {
+    extern __shared__ __align__(16) unsigned char lds_tab[];
+    if (n < 1) return;
     constexpr int PER = RowPiece<DT, RT>::PER;
+    // row sums: a u8 row (either direction) sums below 2^32 for any k < 2^23
+    using AT = typename std::conditional<sizeof(DT) == 1, uint32_t, int64_t>::type;
     const int64_t LIM = (int64_t)1 << 53;
+    int64_t* l_ts = (int64_t*)lds_tab;
+    int64_t* l_ss = l_ts + (int64_t)k * tlen;
+    int32_t* l_tc = (int32_t*)(l_ss + k);
+    MT* l_dm = (MT*)(lds_tab + ((((size_t)k * (size_t)tlen * 12 + (size_t)k * 8) + 15) & ~size_t(15)));
+    if constexpr (LT) {
+        const int64_t kt = (int64_t)k * tlen;
+        for (int64_t t = threadIdx.x; t < kt; t += BLOCK) {
+            l_ts[t] = Tsum[t];
+            l_tc[t] = Tcnt[t];
+        }
+        for (int64_t t = threadIdx.x; t < k; t += BLOCK) l_ss[t] = src_sum[t];
+        const int64_t kk = (int64_t)k * k;
+        if ((kk * (int64_t)sizeof(MT)) % 4 == 0) {
+            const uint32_t* s4 = (const uint32_t*)dmat_c;
+            uint32_t* d4 = (uint32_t*)l_dm;
+            for (int64_t t = threadIdx.x; t < kk * (int64_t)sizeof(MT) / 4; t += BLOCK) d4[t] = s4[t];
+        } else {
+            for (int64_t t = threadIdx.x; t < kk; t += BLOCK) l_dm[t] = dmat_c[t];
+        }
+        __syncthreads();
+    }
     const int sub = lane_id() & (G - 1);
-    const int64_t per_block = kBlock / G;
+    const int64_t per_block = BLOCK / G;
     bool any_ovf = false, any_unreached = false;
     // every lane runs the same number of iterations (the group shuffles need
     // all lanes); nodes past the end are masked, not skipped
     const int64_t steps = (n + per_block - 1) / per_block;
-    for (int64_t s0 = blockIdx.x; s0 < steps; s0 += gridDim.x) {
-        const int64_t v = s0 * per_block + threadIdx.x / G;
+    const int64_t slot = threadIdx.x / G;
+    // two pieces refilled in turn: after a trip's piece is decoded its
+    // registers take the loads of the trip after next, which stay in flight
+    // while this trip and the next are worked on
+    const int64_t g = gridDim.x;
+    auto fetch = [&](RawPiece<DT, RT>& rp, int64_t s) { rp.fetch(D, Dr, sidx, s * per_block + slot, n, k, sub); };
+    // a node's totals, held by one lane of its group until the round's end
+    int trip = 0;
+    int64_t hv = -1;
+    int32_t hj = 0, hp = 0;
+    uint32_t hdelta = 0, hlcnum = 0;
+    AT hrowsum = 0, hlcsum = 0;
+    bool hunr = false;
+    auto step = [&](RawPiece<DT, RT>& rp, int64_t s0, auto&& finish) {
+        const int64_t v = s0 * per_block + slot;
         const bool valid = v < n;
         RowPiece<DT, RT> r;
-        if (valid) {
-            r.load(D, Dr, v, k, sub);
-        } else {
+        r.decode(rp.a, rp.b);
+        const int32_t j = valid ? rp.j : 0;
+        fetch(rp, s0 + 2 * g);
+        if (!valid) {
 #pragma unroll
             for (int e = 0; e < PER; e++) r.d[e] = 0xFFFFFFFFu;
+            r.unreached = false;
         }
         // argmin (lowest index among equal minima) and sum
         uint32_t best = 0xFFFFFFFFu;
         int32_t bi = 0;
-        int64_t sum = 0;
+        AT sum = 0;
 #pragma unroll
         for (int e = 0; e < PER; e++) {
             if (r.d[e] < best) {
                 best = r.d[e];
                 bi = sub * PER + e;
             }
-            sum += valid ? r.d[e] : 0;
+            sum += valid ? (AT)r.d[e] : (AT)0;
         }
+        if constexpr (sizeof(DT) == 1) {
+            // one key: distance (< 2^9, an all-ones placeholder for a masked
+            // node) above the index (k <= 256 for rows of at most 256 bytes)
+            uint32_t key = valid ? ((best << 16) | (uint32_t)bi) : 0xFFFFFFFFu;
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-            const uint32_t ob = (uint32_t)__shfl_xor((int)best, off);
-            const int32_t oi = __shfl_xor(bi, off);
-            if (ob < best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
+            for (int off = G / 2; off > 0; off >>= 1) key = min(key, (uint32_t)__shfl_xor((int)key, off));
+            best = key >> 16;
+            bi = (int32_t)(key & 0xFFFFu);
+        } else {
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                const uint32_t ob = (uint32_t)__shfl_xor((int)best, off);
+                const int32_t oi = __shfl_xor(bi, off);
+                if (ob < best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
             }
         }
-        sum = group_sum64<G>(sum);
+        if constexpr (sizeof(AT) == 4) sum = group_sum32<G>(sum);
+        else sum = group_sum64<G>(sum);
         const int p = bi;
         const int64_t delta = best;
-        const int32_t j = valid ? sidx[v] : 0;
-        // the L cap C split against the pivot's row of the sample distances
+        // the L cap C split against the pivot's row of the sample distances:
+        // dmat * num <= Delta * den  <=>  dmat <= floor(Delta * den / num)
         const int64_t thr = delta * ed;
-        const MT* drow = dmat_c + (int64_t)p * k;
-        int64_t lcsum = 0, lcnum = 0;
+        const int64_t lim = en == 1 ? thr : thr / en;
+        const uint32_t lim32 = (uint32_t)min<int64_t>(lim, 0xFFFFFFFFll);
+        AT lcsum = 0;
+        uint32_t lcnum = 0;
         if (valid && j < 0) {
+            uint32_t m[PER];
+            if constexpr (LT) load_mt_piece<MT, PER>(l_dm + (uint32_t)p * (uint32_t)k, sub, m);
+            else load_mt_piece<MT, PER>(dmat_c + (int64_t)p * k, sub, m);
 #pragma unroll
             for (int e = 0; e < PER; e++) {
-                if ((int64_t)drow[sub * PER + e] * en <= thr) {
-                    lcsum += r.d[e];
+                if (m[e] <= lim32) {
+                    lcsum += (AT)r.d[e];
                     lcnum += 1;
                 }
             }
         }
-        lcsum = group_sum64<G>(lcsum);
-        lcnum = group_sum64<G>(lcnum);
+        if constexpr (sizeof(AT) == 4) lcsum = group_sum32<G>(lcsum);
+        else lcsum = group_sum64<G>(lcsum);
+        lcnum = group_sum32<G>(lcnum);
         bool unreached = r.unreached;
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) unreached = unreached || __shfl_xor((int)unreached, off);
-        if (!valid || sub != 0) continue;
+        // every lane of the group now holds the node's totals: the lane whose
+        // sub index is this trip's number in the round keeps them
+        if (sub == trip) {
+            hv = valid ? v : -1;
+            hj = j;
+            hp = p;
+            hdelta = best;
+            hrowsum = sum;
+            hlcsum = lcsum;
+            hlcnum = lcnum;
+            hunr = unreached;
+        }
+        if (++trip == G) finish();
+    };
+    // the end of Algorithm 1 for the nodes the lanes hold, all lanes at once
+    // (after G trips each lane holds one node)
+    auto finish = [&]() {
+        trip = 0;
+        if (hv < 0) return;
+        const int64_t v = hv;
+        const int32_t j = hj;
+        const int p = hp;
+        const int64_t delta = hdelta;
+        const bool unreached = hunr;
+        hv = -1;
+        const int64_t lim = en == 1 ? delta * ed : delta * ed / en;
         double hyb, samp;
         int64_t piv, pub;
         bool ovf = false;
+        const int64_t sum64 = (int64_t)hrowsum, lcsum64 = (int64_t)hlcsum, lcnum64 = (int64_t)hlcnum;
         if (j >= 0) {
-            const int64_t S = src_sum[j];
+            const int64_t S = LT ? l_ss[j] : src_sum[j];
             hyb = samp = (double)S;
             piv = pub = S;
             ovf = S >= LIM;
         } else {
-            const int64_t tix = thr / en + 1;  // d > floor(Delta/eps)  <=>  d >= tix
+            const int64_t tix = lim + 1;  // d > floor(Delta/eps)  <=>  d >= tix
             int64_t hnum = 0, hsum = 0;
             if (tix < tlen) {
-                hnum = Tcnt[(int64_t)p * tlen + tix];
-                hsum = Tsum[(int64_t)p * tlen + tix];
+                if constexpr (LT) {
+                    hnum = l_tc[(uint32_t)p * (uint32_t)tlen + (uint32_t)tix];
+                    hsum = l_ts[(uint32_t)p * (uint32_t)tlen + (uint32_t)tix];
+                } else {
+                    hnum = Tcnt[(int64_t)p * tlen + tix];
+                    hsum = Tsum[(int64_t)p * tlen + tix];
+                }
             }
-            const int64_t hcsum = sum - lcsum;
-            const int64_t lnum = (n - 1) - hnum - (int64_t)(k - lcnum);
+            const int64_t hcsum = sum64 - lcsum64;
+            const int64_t lnum = (n - 1) - hnum - (int64_t)(k - lcnum64);
             const int64_t a = hsum + hcsum;
             int64_t t1 = 0, t2 = 0, N = 0, ss = 0;
-            ovf = __builtin_mul_overflow(a, lcnum, &t1) || __builtin_mul_overflow(lcsum, lnum, &t2) ||
-                  __builtin_add_overflow(t1, t2, &N) || N >= LIM || lcnum < 1 || lnum < lcnum;
-            hyb = (double)N / (double)lcnum;
-            ovf = ovf || __builtin_mul_overflow(n - 1, sum, &ss) || ss >= LIM;
+            ovf = __builtin_mul_overflow(a, lcnum64, &t1) || __builtin_mul_overflow(lcsum64, lnum, &t2) ||
+                  __builtin_add_overflow(t1, t2, &N) || N >= LIM || lcnum64 < 1 || lnum < lcnum64;
+            hyb = (double)N / (double)lcnum64;
+            ovf = ovf || __builtin_mul_overflow(n - 1, sum64, &ss) || ss >= LIM;
             samp = (double)ss / (double)k;
-            piv = src_sum[p];
+            piv = LT ? l_ss[p] : src_sum[p];
             pub = piv + (n - 1) * delta;
         }
         if (stage) {  // the node's record in internal order; written out in the caller's order afterwards
             const uint64_t hb = (uint64_t)__double_as_longlong(hyb), sb = (uint64_t)__double_as_longlong(samp);
-            uint4* r = stage + v * 4;
-            r[0] = make_uint4((uint32_t)hb, (uint32_t)(hb >> 32), (uint32_t)sb, (uint32_t)(sb >> 32));
-            r[1] = make_uint4((uint32_t)piv, (uint32_t)((uint64_t)piv >> 32), (uint32_t)pub,
-                              (uint32_t)((uint64_t)pub >> 32));
-            r[2] = make_uint4((uint32_t)sum, (uint32_t)((uint64_t)sum >> 32), (uint32_t)p, (uint32_t)delta);
+            uint4* rec = stage + v * 4;
+            rec[0] = make_uint4((uint32_t)hb, (uint32_t)(hb >> 32), (uint32_t)sb, (uint32_t)(sb >> 32));
+            rec[1] = make_uint4((uint32_t)piv, (uint32_t)((uint64_t)piv >> 32), (uint32_t)pub,
+                                (uint32_t)((uint64_t)pub >> 32));
+            rec[2] = make_uint4((uint32_t)sum64, (uint32_t)((uint64_t)sum64 >> 32), (uint32_t)p, (uint32_t)delta);
         } else {
             const int64_t o = orig[v];
             if (S_hyb) S_hyb[o] = hyb;
@@ -303,11 +520,19 @@ __global__ __launch_bounds__(kBlock) void k_estimate_rows(
             if (S_pub) S_pub[o] = pub;
             if (pivot_out) pivot_out[o] = p;
             if (delta_out) delta_out[o] = (int32_t)delta;
-            if (sampsum_out) sampsum_out[o] = sum;
+            if (sampsum_out) sampsum_out[o] = sum64;
         }
         any_ovf = any_ovf || ovf;
         any_unreached = any_unreached || unreached;
+    };
+    RawPiece<DT, RT> pa, pb;
+    fetch(pa, blockIdx.x);
+    fetch(pb, (int64_t)blockIdx.x + g);
+    for (int64_t s0 = blockIdx.x; s0 < steps; s0 += 2 * g) {
+        step(pa, s0, finish);
+        if (s0 + g < steps) step(pb, s0 + g, finish);
     }
+    finish();  // a round cut short by the end
     if (any_ovf) flags->overflow = 1;
     if (any_unreached) flags->disconnected = 1;
 }
@@ -1100,19 +1325,35 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         hlen = maxd + 1;
         nslots = 1;
         fill_u32(st, hist, 0u, (size_t)(k * hlen));
-        const size_t lds = sizeof(int32_t) * (size_t)k * hlen;
-        const int use_lds = lds <= 48 * 1024 ? 1 : 0;
         const int G = row_lanes<DT>(k);
+        // LDS copy of the histogram: [k][hlen] for k_reduce, [k][hist_stride(hlen)] for the row variant
+        const size_t lds = sizeof(int32_t) * (size_t)k * (size_t)(G > 0 ? hist_stride(hlen) : hlen);
+        const int use_lds = lds <= 48 * 1024 ? 1 : 0;
         const unsigned rb = grid_for(n, use_lds ? 1024 : 8192);
         const size_t lb = use_lds ? lds : 0;
         const DT* Dp = (const DT*)a.D;
         const DT* Drp = (const DT*)a.Dr;
         switch (G) {
-            case 1: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 1>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
-            case 2: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 2>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
-            case 4: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 4>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
-            case 8: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 8>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
-            case 16: hipLaunchKernelGGL((k_reduce_rows<DT, RT, 16>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, use_lds, flags); break;
+            case 1:
+                if (use_lds) hipLaunchKernelGGL((k_reduce_rows<DT, RT, 1, true>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                else hipLaunchKernelGGL((k_reduce_rows<DT, RT, 1, false>), dim3(rb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                break;
+            case 2:
+                if (use_lds) hipLaunchKernelGGL((k_reduce_rows<DT, RT, 2, true>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                else hipLaunchKernelGGL((k_reduce_rows<DT, RT, 2, false>), dim3(rb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                break;
+            case 4:
+                if (use_lds) hipLaunchKernelGGL((k_reduce_rows<DT, RT, 4, true>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                else hipLaunchKernelGGL((k_reduce_rows<DT, RT, 4, false>), dim3(rb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                break;
+            case 8:
+                if (use_lds) hipLaunchKernelGGL((k_reduce_rows<DT, RT, 8, true>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                else hipLaunchKernelGGL((k_reduce_rows<DT, RT, 8, false>), dim3(rb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                break;
+            case 16:
+                if (use_lds) hipLaunchKernelGGL((k_reduce_rows<DT, RT, 16, true>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                else hipLaunchKernelGGL((k_reduce_rows<DT, RT, 16, false>), dim3(rb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx, hlen, hist, flags);
+                break;
             default:
                 hipLaunchKernelGGL((k_reduce<DT, RT>), dim3(rb), dim3(kBlock), lb, st, Dp, Drp, n, k, a.sidx, hlen, hist,
                                    use_lds, flags);
@@ -1134,10 +1375,24 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         if (epilogue_staged(a) && G > 0)
             stage = (uint4*)(p + (a.hist_done ? 0 : align256(sizeof(int32_t) * k * (maxd + 1))) +
                              (want_err ? align256(sweep_scratch_bytes(n, k)) : 0));
-#define CCG_EST_ROWS(GG)                                                                                            \
-    hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG>), dim3(eb), dim3(kBlock), 0, st, Dp, Drp, n, k, a.sidx,       \
-                       a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb, a.S_samp, a.S_piv, \
-                       a.S_pub, a.pivot, a.delta, a.sampsum, stage, flags)
+        // small tables in LDS when they fit: blocks of 512 threads, two per CU
+        // (a block copies the tables once, so the grid stays at a few per CU)
+        const size_t tb = est_table_bytes(k, tlen, sizeof(MT));
+        const bool lt = tb <= kEstTableLds;
+        const unsigned ebl = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(kEstTableBlocks, (n + kEstBlock / std::max(G, 1) - 1) / (kEstBlock / std::max(G, 1))));
+#define CCG_EST_ROWS(GG)                                                                                               \
+    do {                                                                                                               \
+        if (lt)                                                                                                        \
+            hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, true, kEstBlock>), dim3(ebl), dim3(kEstBlock), tb, st, \
+                               Dp, Drp, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,          \
+                               a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, stage,     \
+                               flags);                                                                                 \
+        else                                                                                                           \
+            hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, false, kBlock>), dim3(eb), dim3(kBlock), 0, st, Dp,    \
+                               Drp, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den,   \
+                               a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, stage, flags);        \
+    } while (0)
         switch (G) {
             case 1: CCG_EST_ROWS(1); break;
             case 2: CCG_EST_ROWS(2); break;
