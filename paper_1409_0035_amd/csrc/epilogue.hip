@@ -31,6 +31,10 @@ constexpr int kBlock = 256;
 constexpr int kEstBlock = 512;
 constexpr size_t kEstTableLds = 64 * 1024;
 constexpr int64_t kEstTableBlocks = 512;
+// row pieces each lane keeps in flight: the histogram, the estimate (four
+// and three measured the same on the round trip of rmat22dir)
+constexpr int kRowsInFlight = 2;
+constexpr int kEstInFlight = 2;
 
 // Reads element i of a distance row; with RT the reverse row is added.
 template <typename DT, bool RT>
@@ -192,17 +196,110 @@ __device__ __forceinline__ uint4 rotate_bytes(const uint4 x, uint32_t b) {
                       __builtin_amdgcn_alignbyte(w3, w2, s), __builtin_amdgcn_alignbyte(w0, w3, s));
 }
 
-template <int G>
-__device__ __forceinline__ int64_t group_sum64(int64_t x) {
+// ---- byte-packed helpers for rows of u8 distances (a lane's 16-byte piece
+// as four words).  Zero-byte test: (t - 0x01..01) & ~t & 0x80..80 is nonzero
+// iff some byte of t is zero, and its lowest set flag marks the lowest zero
+// byte (a borrow only carries upwards from a zero byte).
+
+__device__ __forceinline__ uint32_t zero_byte_flags(uint32_t t) { return (t - 0x01010101u) & ~t & 0x80808080u; }
+
+// any byte equal to 0xFF (an unreached entry)
+__device__ __forceinline__ bool any_byte_ff(const uint4 a) {
+    return (zero_byte_flags(~a.x) | zero_byte_flags(~a.y) | zero_byte_flags(~a.z) | zero_byte_flags(~a.w)) != 0;
+}
+
+// sum of the 16 bytes plus acc (v_sad_u8 against zero adds a word's four bytes)
+__device__ __forceinline__ uint32_t bytes_sum(const uint4 a, uint32_t acc) {
+    acc = __builtin_amdgcn_sad_u8(a.x, 0u, acc);
+    acc = __builtin_amdgcn_sad_u8(a.y, 0u, acc);
+    acc = __builtin_amdgcn_sad_u8(a.z, 0u, acc);
+    return __builtin_amdgcn_sad_u8(a.w, 0u, acc);
+}
+
+// smallest of the 16 bytes
+__device__ __forceinline__ uint32_t bytes_min(const uint4 a) {
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    uint32_t m = 0xFFu;
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    for (int q = 0; q < 4; q++) {
+        const uint32_t b0 = w[q] & 0xFFu, b1 = (w[q] >> 8) & 0xFFu, b2 = (w[q] >> 16) & 0xFFu, b3 = w[q] >> 24;
+        m = min(m, min(min(b0, b1), min(b2, b3)));
+    }
+    return m;
+}
+
+// index (0..15) of the first byte equal to m, which must occur
+__device__ __forceinline__ uint32_t bytes_first_eq(const uint4 a, uint32_t m) {
+    const uint32_t mb = m * 0x01010101u;
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    uint32_t idx = 0;
+#pragma unroll
+    for (int q = 3; q >= 0; q--) {
+        const uint32_t z = zero_byte_flags(w[q] ^ mb);
+        if (z) idx = 4u * (uint32_t)q + ((uint32_t)__builtin_ctz(z) >> 3);
+    }
+    return idx;
+}
+
+// For the bytes y_b of dm (entries of a row of the sample distance matrix,
+// each < 255) that are <= L (L <= 255): the sum of the matching bytes of d
+// is added to sum and their number to cnt.  Even and odd bytes are compared
+// as 16-bit halves: 0x100 + L - y has bit 8 set iff y <= L, and never borrows
+// across halves.
+__device__ __forceinline__ void bytes_sum_le(const uint4 d, const uint4 dm, uint32_t L, uint32_t& sum,
+                                             uint32_t& cnt) {
+    const uint32_t C = 0x01000100u + L * 0x00010001u;
+    const uint32_t dw[4] = {d.x, d.y, d.z, d.w}, yw[4] = {dm.x, dm.y, dm.z, dm.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint32_t fe = (C - (yw[q] & 0x00FF00FFu)) & 0x01000100u;          // even bytes 0, 2
+        const uint32_t fo = (C - ((yw[q] >> 8) & 0x00FF00FFu)) & 0x01000100u;   // odd bytes 1, 3
+        const uint32_t mask = ((fe >> 8) * 0xFFu) | (((fo >> 8) * 0xFFu) << 8);
+        sum = __builtin_amdgcn_sad_u8(dw[q] & mask, 0u, sum);
+        cnt += (uint32_t)__builtin_popcount(fe | (fo << 1));
+    }
+}
+
+// Value of the partner lane at step s of a reduction over aligned groups of
+// up to 16 lanes, by DPP lane permutations inside a row: swap neighbours,
+// swap pairs, then mirror the half row and the row.  After steps 0 .. lg-1
+// combining x with its partner, every lane holds its 2^lg-lane group's total
+// (mirroring pairs each lane with one of the other half, which by then holds
+// that half's total).
+__device__ __forceinline__ uint32_t dpp_partner(uint32_t x, int s) {
+    switch (s) {
+        case 0: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        default: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false); // row_mirror
+    }
+}
+
+// Group sums and minima over aligned groups of G <= 16 lanes (all lanes active).
+template <int G>
+__device__ __forceinline__ uint32_t group_sum32(uint32_t x) {
+    static_assert(G <= 16, "groups of at most 16 lanes");
+#pragma unroll
+    for (int s = 0; (1 << s) < G; s++) x += dpp_partner(x, s);
     return x;
 }
 
 template <int G>
-__device__ __forceinline__ uint32_t group_sum32(uint32_t x) {
+__device__ __forceinline__ int64_t group_sum64(int64_t x) {
+    static_assert(G <= 16, "groups of at most 16 lanes");
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
+    for (int s = 0; (1 << s) < G; s++) {
+        const uint64_t lo = dpp_partner((uint32_t)x, s), hi = dpp_partner((uint32_t)((uint64_t)x >> 32), s);
+        x += (int64_t)((hi << 32) | lo);
+    }
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t group_min32(uint32_t x) {
+    static_assert(G <= 16, "groups of at most 16 lanes");
+#pragma unroll
+    for (int s = 0; (1 << s) < G; s++) x = min(x, dpp_partner(x, s));
     return x;
 }
 
@@ -218,8 +315,9 @@ __host__ __device__ inline int64_t hist_stride(int64_t hlen) { return hlen | 1; 
 // mostly share a distance) would all add to the same counter.  (Measured on
 // the round trip of the directed R-MAT scale-22 graph, k = 128: 179 us per
 // launch without the rotation, 84 us rotating by the node slot alone, 64 us
-// as here; a [d][i] layout was slower, 157 us.)  Two pieces are refilled in
-// turn, so the next trip's loads are in flight while one is counted.
+// as here; a [d][i] layout was slower, 157 us.)  kRowsInFlight pieces are
+// refilled in turn, so the next trips' loads are in flight while one is
+// counted.
 template <typename DT, bool RT, int G, bool USE_LDS>
 __global__ __launch_bounds__(kBlock) void k_reduce_rows(const DT* __restrict__ D, const DT* __restrict__ Dr,
                                                         int64_t n, int32_t k, const int32_t* __restrict__ sidx,
@@ -239,13 +337,40 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const DT* __restrict__ D
     const uint32_t hlen32 = (uint32_t)min<int64_t>(hlen, 0xFFFFFFFFll);
     const int64_t stride = (int64_t)gridDim.x * (kBlock / G);
     bool bad = false;
-    // counts the piece in rp (node v), then refills rp with node v + 2 * stride
+    // LDS row starts of the lane's samples in rotated order (u8 rows)
+    uint32_t lbase[sizeof(DT) == 1 ? 16 : 1];
+    if constexpr (sizeof(DT) == 1) {
+#pragma unroll
+        for (int e = 0; e < 16; e++) lbase[e] = ((uint32_t)sub * 16u + ((e + rot) & 15u)) * (uint32_t)hs;
+    }
+    // counts the piece in rp (node v), then refills rp with node v + kRowsInFlight * stride
     auto step = [&](RawPiece<DT, RT>& rp, int64_t v) {
         const int32_t j = rp.j;
+        if constexpr (sizeof(DT) == 1 && !RT && USE_LDS) {
+            // u8 rows of one direction: one packed test for an unreached entry
+            // or a distance past the bound (either fails the estimate, so the
+            // node is not counted), then a byte extract and an add per entry
+            const uint4 a = rotate_bytes(rp.a, rot);
+            rp.fetch(D, Dr, sidx, v + kRowsInFlight * stride, n, k, sub);
+            if (j >= 0) return;
+            uint32_t le = 0, dummy = 0;
+            bytes_sum_le(make_uint4(0, 0, 0, 0), a, (uint32_t)min<int64_t>(hlen - 1, 255), dummy, le);
+            if (any_byte_ff(a) || le != 16u) {
+                bad = true;
+                return;
+            }
+            const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const uint32_t d = (w[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+                atomicAdd(&lds_hist[lbase[e] + d], 1);
+            }
+            return;
+        }
         RowPiece<DT, RT> r;
         r.decode(rotate_bytes(rp.a, rot * (uint32_t)sizeof(DT)),
                  RT ? rotate_bytes(rp.b, rot * (uint32_t)sizeof(DT)) : rp.b);
-        rp.fetch(D, Dr, sidx, v + 2 * stride, n, k, sub);
+        rp.fetch(D, Dr, sidx, v + kRowsInFlight * stride, n, k, sub);
         if (j >= 0) return;
         if (r.unreached) {
             bad = true;
@@ -265,12 +390,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const DT* __restrict__ D
         }
     };
     const int64_t v0 = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
-    RawPiece<DT, RT> pa, pb;
-    pa.fetch(D, Dr, sidx, v0, n, k, sub);
-    pb.fetch(D, Dr, sidx, v0 + stride, n, k, sub);
-    for (int64_t v = v0; v < n; v += 2 * stride) {
-        step(pa, v);
-        if (v + stride < n) step(pb, v + stride);
+    RawPiece<DT, RT> pp[kRowsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; u++) pp[u].fetch(D, Dr, sidx, v0 + u * stride, n, k, sub);
+    for (int64_t v = v0; v < n; v += kRowsInFlight * stride) {
+#pragma unroll
+        for (int u = 0; u < kRowsInFlight; u++)
+            if (v + u * stride < n) step(pp[u], v + u * stride);
     }
     if (bad) flags->disconnected = 1;
     if (USE_LDS) {
@@ -334,6 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     // row sums: a u8 row (either direction) sums below 2^32 for any k < 2^23
     using AT = typename std::conditional<sizeof(DT) == 1, uint32_t, int64_t>::type;
     const int64_t LIM = (int64_t)1 << 53;
+    constexpr bool kPacked = sizeof(DT) == 1 && !RT && sizeof(MT) == 1;
     int64_t* l_ts = (int64_t*)lds_tab;
     int64_t* l_ss = l_ts + (int64_t)k * tlen;
     int32_t* l_tc = (int32_t*)(l_ss + k);
@@ -362,9 +489,9 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     // all lanes); nodes past the end are masked, not skipped
     const int64_t steps = (n + per_block - 1) / per_block;
     const int64_t slot = threadIdx.x / G;
-    // two pieces refilled in turn: after a trip's piece is decoded its
-    // registers take the loads of the trip after next, which stay in flight
-    // while this trip and the next are worked on
+    // kEstInFlight pieces refilled in turn: after a trip's piece is decoded
+    // its registers take the loads of the trip kEstInFlight on, which stay in
+    // flight while the trips between are worked on
     const int64_t g = gridDim.x;
     auto fetch = [&](RawPiece<DT, RT>& rp, int64_t s) { rp.fetch(D, Dr, sidx, s * per_block + slot, n, k, sub); };
     // a node's totals, held by one lane of its group until the round's end
@@ -377,75 +504,93 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     auto step = [&](RawPiece<DT, RT>& rp, int64_t s0, auto&& finish) {
         const int64_t v = s0 * per_block + slot;
         const bool valid = v < n;
-        RowPiece<DT, RT> r;
-        r.decode(rp.a, rp.b);
         const int32_t j = valid ? rp.j : 0;
-        fetch(rp, s0 + 2 * g);
-        if (!valid) {
-#pragma unroll
-            for (int e = 0; e < PER; e++) r.d[e] = 0xFFFFFFFFu;
-            r.unreached = false;
-        }
-        // argmin (lowest index among equal minima) and sum
-        uint32_t best = 0xFFFFFFFFu;
-        int32_t bi = 0;
-        AT sum = 0;
-#pragma unroll
-        for (int e = 0; e < PER; e++) {
-            if (r.d[e] < best) {
-                best = r.d[e];
-                bi = sub * PER + e;
-            }
-            sum += valid ? (AT)r.d[e] : (AT)0;
-        }
-        if constexpr (sizeof(DT) == 1) {
-            // one key: distance (< 2^9, an all-ones placeholder for a masked
-            // node) above the index (k <= 256 for rows of at most 256 bytes)
-            uint32_t key = valid ? ((best << 16) | (uint32_t)bi) : 0xFFFFFFFFu;
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) key = min(key, (uint32_t)__shfl_xor((int)key, off));
-            best = key >> 16;
-            bi = (int32_t)(key & 0xFFFFu);
-        } else {
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) {
-                const uint32_t ob = (uint32_t)__shfl_xor((int)best, off);
-                const int32_t oi = __shfl_xor(bi, off);
-                if (ob < best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-        }
-        if constexpr (sizeof(AT) == 4) sum = group_sum32<G>(sum);
-        else sum = group_sum64<G>(sum);
-        const int p = bi;
-        const int64_t delta = best;
-        // the L cap C split against the pivot's row of the sample distances:
-        // dmat * num <= Delta * den  <=>  dmat <= floor(Delta * den / num)
-        const int64_t thr = delta * ed;
-        const int64_t lim = en == 1 ? thr : thr / en;
-        const uint32_t lim32 = (uint32_t)min<int64_t>(lim, 0xFFFFFFFFll);
-        AT lcsum = 0;
+        uint32_t best;
+        int32_t bi;
+        AT sum, lcsum = 0;
         uint32_t lcnum = 0;
-        if (valid && j < 0) {
-            uint32_t m[PER];
-            if constexpr (LT) load_mt_piece<MT, PER>(l_dm + (uint32_t)p * (uint32_t)k, sub, m);
-            else load_mt_piece<MT, PER>(dmat_c + (int64_t)p * k, sub, m);
+        bool unr;
+        if constexpr (kPacked) {
+            // u8 rows, one direction, u8 sample distances: byte-packed arithmetic
+            const uint4 a = rp.a;
+            fetch(rp, s0 + kEstInFlight * g);
+            unr = valid && any_byte_ff(a);
+            const uint32_t m = bytes_min(a);
+            const uint32_t key = group_min32<G>(
+                valid ? ((m << 16) | ((uint32_t)sub * PER + bytes_first_eq(a, m))) : 0xFFFFFFFFu);
+            best = key >> 16;  // the lowest index among equal minima
+            bi = (int32_t)(key & 0xFFFFu);
+            sum = group_sum32<G>(valid ? bytes_sum(a, 0u) : 0u);
+            const int64_t lim = en == 1 ? (int64_t)best * ed : (int64_t)best * ed / en;
+            if (valid && j < 0) {
+                const uint4 dm = LT ? ((const uint4*)(l_dm + (uint32_t)bi * (uint32_t)k))[sub]
+                                    : ((const uint4*)(dmat_c + (int64_t)bi * k))[sub];
+                bytes_sum_le(a, dm, lim >= 255 ? 255u : (uint32_t)lim, lcsum, lcnum);
+            }
+        } else {
+            RowPiece<DT, RT> r;
+            r.decode(rp.a, rp.b);
+            fetch(rp, s0 + kEstInFlight * g);
+            if (!valid) {
+#pragma unroll
+                for (int e = 0; e < PER; e++) r.d[e] = 0xFFFFFFFFu;
+                r.unreached = false;
+            }
+            unr = r.unreached;
+            // argmin (lowest index among equal minima) and sum
+            best = 0xFFFFFFFFu;
+            bi = 0;
+            sum = 0;
 #pragma unroll
             for (int e = 0; e < PER; e++) {
-                if (m[e] <= lim32) {
-                    lcsum += (AT)r.d[e];
-                    lcnum += 1;
+                if (r.d[e] < best) {
+                    best = r.d[e];
+                    bi = sub * PER + e;
+                }
+                sum += valid ? (AT)r.d[e] : (AT)0;
+            }
+            if constexpr (sizeof(DT) == 1) {
+                // one key: distance (< 2^9, an all-ones placeholder for a masked
+                // node) above the index (k <= 256 for rows of at most 256 bytes)
+                const uint32_t key = group_min32<G>(valid ? ((best << 16) | (uint32_t)bi) : 0xFFFFFFFFu);
+                best = key >> 16;
+                bi = (int32_t)(key & 0xFFFFu);
+            } else {
+#pragma unroll
+                for (int st = 0; (1 << st) < G; st++) {
+                    const uint32_t ob = dpp_partner(best, st);
+                    const int32_t oi = (int32_t)dpp_partner((uint32_t)bi, st);
+                    if (ob < best || (ob == best && oi < bi)) {
+                        best = ob;
+                        bi = oi;
+                    }
+                }
+            }
+            if constexpr (sizeof(AT) == 4) sum = group_sum32<G>(sum);
+            else sum = group_sum64<G>(sum);
+            // the L cap C split against the pivot's row of the sample distances:
+            // dmat * num <= Delta * den  <=>  dmat <= floor(Delta * den / num)
+            const int64_t thr = (int64_t)best * ed;
+            const int64_t lim = en == 1 ? thr : thr / en;
+            const uint32_t lim32 = (uint32_t)min<int64_t>(lim, 0xFFFFFFFFll);
+            if (valid && j < 0) {
+                uint32_t m[PER];
+                if constexpr (LT) load_mt_piece<MT, PER>(l_dm + (uint32_t)bi * (uint32_t)k, sub, m);
+                else load_mt_piece<MT, PER>(dmat_c + (int64_t)bi * k, sub, m);
+#pragma unroll
+                for (int e = 0; e < PER; e++) {
+                    if (m[e] <= lim32) {
+                        lcsum += (AT)r.d[e];
+                        lcnum += 1;
+                    }
                 }
             }
         }
         if constexpr (sizeof(AT) == 4) lcsum = group_sum32<G>(lcsum);
         else lcsum = group_sum64<G>(lcsum);
         lcnum = group_sum32<G>(lcnum);
-        bool unreached = r.unreached;
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) unreached = unreached || __shfl_xor((int)unreached, off);
+        const bool unreached = group_sum32<G>(unr ? 1u : 0u) != 0;
+        const int p = bi;
         // every lane of the group now holds the node's totals: the lane whose
         // sub index is this trip's number in the round keeps them
         if (sub == trip) {
@@ -525,12 +670,13 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
         any_ovf = any_ovf || ovf;
         any_unreached = any_unreached || unreached;
     };
-    RawPiece<DT, RT> pa, pb;
-    fetch(pa, blockIdx.x);
-    fetch(pb, (int64_t)blockIdx.x + g);
-    for (int64_t s0 = blockIdx.x; s0 < steps; s0 += 2 * g) {
-        step(pa, s0, finish);
-        if (s0 + g < steps) step(pb, s0 + g, finish);
+    RawPiece<DT, RT> pp[kEstInFlight];
+#pragma unroll
+    for (int u = 0; u < kEstInFlight; u++) fetch(pp[u], (int64_t)blockIdx.x + u * g);
+    for (int64_t s0 = blockIdx.x; s0 < steps; s0 += kEstInFlight * g) {
+#pragma unroll
+        for (int u = 0; u < kEstInFlight; u++)
+            if (s0 + u * g < steps) step(pp[u], s0 + u * g, finish);
     }
     finish();  // a round cut short by the end
     if (any_ovf) flags->overflow = 1;
