@@ -1638,17 +1638,14 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
             ea.samples = samples_dev;
             ea.sidx = sidx;
             ea.orig = g.orig;
-            // relabelled graphs: the outputs go through per-node records written in the caller's order
+            // relabelled graphs: the row estimate walks the nodes in the caller's order
             ea.inv = (g.weighted || gr->borrowed) ? nullptr : g.inv;
             ea.maxd = (int64_t)lmax_dir[0] + lmax_dir[1];
             ea.eps_num = r.en;
             ea.eps_den = r.ed;
             fill_epilogue_outputs(ea, out, src_sum, dmat);
-            const bool ea_staged = ea.inv && (ea.S_hyb || ea.S_samp || ea.S_piv || ea.S_pub || ea.pivot ||
-                                              ea.delta || ea.sampsum);
             ea_es = epilogue_scratch(n, k, ea.maxd, false,
-                                     out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err,
-                                     ea_staged);
+                                     out->S_err || out->S_ad || out->S_ad_err || out->S_sweep || out->S_sweep_err);
             // a round trip that may be replayed keeps the traversal's control block
             // intact: a replay reads it back after the epilogue
             const size_t ts_free =

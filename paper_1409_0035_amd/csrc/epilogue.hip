@@ -31,10 +31,9 @@ constexpr int kBlock = 256;
 constexpr int kEstBlock = 512;
 constexpr size_t kEstTableLds = 64 * 1024;
 constexpr int64_t kEstTableBlocks = 512;
-// row pieces each lane keeps in flight: the histogram, the estimate (four
-// and three measured the same on the round trip of rmat22dir)
+// row pieces each lane of the histogram keeps in flight (four measured the
+// same as two on the round trip of rmat22dir, and three in the estimate)
 constexpr int kRowsInFlight = 2;
-constexpr int kEstInFlight = 2;
 
 // Reads element i of a distance row; with RT the reverse row is added.
 template <typename DT, bool RT>
@@ -443,20 +442,31 @@ __device__ __forceinline__ void load_mt_piece(const MT* row, int sub, uint32_t (
     }
 }
 
-// the estimators (as k_estimate).  With LT the small tables (dmat_c, Tcnt,
-// Tsum, src_sum) are copied to LDS first, so a node's lookups do not wait
-// behind the next node's row loads, which are issued before the node is
-// worked on.
+// the estimators (as k_estimate).  A wave takes rounds of 64 consecutive
+// positions o: caller ids when inv is set (the node is v = inv[o], and the
+// outputs go to o, so a wave's stores are consecutive; a row is whole cache
+// lines, so reading rows in this order wastes nothing), else internal ids
+// (outputs to orig[v]).  Round r of wave gw starts at 64 (gw + r nw), its
+// trip t takes positions t * 64/G + q, one per group q of G lanes; a round's
+// internal ids are loaded a round ahead, one per lane, and handed to the
+// groups by a lane shuffle.  A node is sample c_j exactly when its distance to
+// c_j is 0 (lengths are positive), so the argmin tells sampled nodes apart.
+// With LT the small tables (dmat_c, Tcnt, Tsum, src_sum) are copied to LDS
+// first.  Two row pieces are refilled in turn, so the next trip's loads are in
+// flight while one is worked on; a lane of each group keeps its node's totals
+// until the round ends, and then all 64 lanes finish their nodes at once.
 template <typename DT, bool RT, typename MT, int G, bool LT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
-    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ sidx,
-    const int32_t* __restrict__ orig, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
+    const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ orig,
+    const int32_t* __restrict__ inv, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
     const int64_t* __restrict__ Tsum, int64_t tlen, const int64_t* __restrict__ src_sum, int64_t en, int64_t ed,
     double* S_hyb, double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out,
-    int64_t* sampsum_out, uint4* stage, DevFlags* flags) {
+    int64_t* sampsum_out, DevFlags* flags) {
+    static_assert(G >= 2 && G <= 16, "two to sixteen lanes per node");
     extern __shared__ __align__(16) unsigned char lds_tab[];
     if (n < 1) return;
     constexpr int PER = RowPiece<DT, RT>::PER;
+    constexpr int NPW = 64 / G;  // nodes per wave and trip
     // row sums: a u8 row (either direction) sums below 2^32 for any k < 2^23
     using AT = typename std::conditional<sizeof(DT) == 1, uint32_t, int64_t>::type;
     const int64_t LIM = (int64_t)1 << 53;
@@ -482,147 +492,50 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
         }
         __syncthreads();
     }
-    const int sub = lane_id() & (G - 1);
-    const int64_t per_block = BLOCK / G;
+    const int lane = lane_id();
+    const int sub = lane & (G - 1);
+    const int q = lane / G;
     bool any_ovf = false, any_unreached = false;
-    // every lane runs the same number of iterations (the group shuffles need
-    // all lanes); nodes past the end are masked, not skipped
-    const int64_t steps = (n + per_block - 1) / per_block;
-    const int64_t slot = threadIdx.x / G;
-    // kEstInFlight pieces refilled in turn: after a trip's piece is decoded
-    // its registers take the loads of the trip kEstInFlight on, which stay in
-    // flight while the trips between are worked on
-    const int64_t g = gridDim.x;
-    auto fetch = [&](RawPiece<DT, RT>& rp, int64_t s) { rp.fetch(D, Dr, sidx, s * per_block + slot, n, k, sub); };
+    const int64_t gw = (int64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64;
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / 64);
+    const int64_t rounds = (n + 63) / 64;
+    const int64_t my_rounds = gw < rounds ? (rounds - 1 - gw) / nw + 1 : 0;
+    const int64_t trips = my_rounds * G;  // the same for every lane of the wave
+    // a round's internal ids, one per lane (positions past the end read the last one)
+    auto load_ids = [&](int64_t r) -> int32_t {
+        const int64_t o = min((gw + r * nw) * 64 + lane, n - 1);
+        return inv ? inv[o] : (int32_t)o;
+    };
+    int32_t ids_cur = load_ids(0), ids_nxt = load_ids(1);
+    // the piece of trip s (s at most one round ahead of the trip in hand):
+    // unconditional, so the registers never merge old and new values
+    auto fetch = [&](RawPiece<DT, RT>& rp, int64_t s, int64_t r_now) {
+        const int32_t ids = (s / G == r_now) ? ids_cur : ids_nxt;
+        const int64_t v = __shfl(ids, (int)(s % G) * NPW + q);
+        rp.a = ((const uint4*)(D + v * k))[sub];
+        rp.b = make_uint4(0, 0, 0, 0);
+        if (RT) rp.b = ((const uint4*)(Dr + v * k))[sub];
+    };
     // a node's totals, held by one lane of its group until the round's end
-    int trip = 0;
-    int64_t hv = -1;
-    int32_t hj = 0, hp = 0;
+    int64_t ho = -1, hv = 0;
+    int32_t hp = 0;
     uint32_t hdelta = 0, hlcnum = 0;
     AT hrowsum = 0, hlcsum = 0;
     bool hunr = false;
-    auto step = [&](RawPiece<DT, RT>& rp, int64_t s0, auto&& finish) {
-        const int64_t v = s0 * per_block + slot;
-        const bool valid = v < n;
-        const int32_t j = valid ? rp.j : 0;
-        uint32_t best;
-        int32_t bi;
-        AT sum, lcsum = 0;
-        uint32_t lcnum = 0;
-        bool unr;
-        if constexpr (kPacked) {
-            // u8 rows, one direction, u8 sample distances: byte-packed arithmetic
-            const uint4 a = rp.a;
-            fetch(rp, s0 + kEstInFlight * g);
-            unr = valid && any_byte_ff(a);
-            const uint32_t m = bytes_min(a);
-            const uint32_t key = group_min32<G>(
-                valid ? ((m << 16) | ((uint32_t)sub * PER + bytes_first_eq(a, m))) : 0xFFFFFFFFu);
-            best = key >> 16;  // the lowest index among equal minima
-            bi = (int32_t)(key & 0xFFFFu);
-            sum = group_sum32<G>(valid ? bytes_sum(a, 0u) : 0u);
-            const int64_t lim = en == 1 ? (int64_t)best * ed : (int64_t)best * ed / en;
-            if (valid && j < 0) {
-                const uint4 dm = LT ? ((const uint4*)(l_dm + (uint32_t)bi * (uint32_t)k))[sub]
-                                    : ((const uint4*)(dmat_c + (int64_t)bi * k))[sub];
-                bytes_sum_le(a, dm, lim >= 255 ? 255u : (uint32_t)lim, lcsum, lcnum);
-            }
-        } else {
-            RowPiece<DT, RT> r;
-            r.decode(rp.a, rp.b);
-            fetch(rp, s0 + kEstInFlight * g);
-            if (!valid) {
-#pragma unroll
-                for (int e = 0; e < PER; e++) r.d[e] = 0xFFFFFFFFu;
-                r.unreached = false;
-            }
-            unr = r.unreached;
-            // argmin (lowest index among equal minima) and sum
-            best = 0xFFFFFFFFu;
-            bi = 0;
-            sum = 0;
-#pragma unroll
-            for (int e = 0; e < PER; e++) {
-                if (r.d[e] < best) {
-                    best = r.d[e];
-                    bi = sub * PER + e;
-                }
-                sum += valid ? (AT)r.d[e] : (AT)0;
-            }
-            if constexpr (sizeof(DT) == 1) {
-                // one key: distance (< 2^9, an all-ones placeholder for a masked
-                // node) above the index (k <= 256 for rows of at most 256 bytes)
-                const uint32_t key = group_min32<G>(valid ? ((best << 16) | (uint32_t)bi) : 0xFFFFFFFFu);
-                best = key >> 16;
-                bi = (int32_t)(key & 0xFFFFu);
-            } else {
-#pragma unroll
-                for (int st = 0; (1 << st) < G; st++) {
-                    const uint32_t ob = dpp_partner(best, st);
-                    const int32_t oi = (int32_t)dpp_partner((uint32_t)bi, st);
-                    if (ob < best || (ob == best && oi < bi)) {
-                        best = ob;
-                        bi = oi;
-                    }
-                }
-            }
-            if constexpr (sizeof(AT) == 4) sum = group_sum32<G>(sum);
-            else sum = group_sum64<G>(sum);
-            // the L cap C split against the pivot's row of the sample distances:
-            // dmat * num <= Delta * den  <=>  dmat <= floor(Delta * den / num)
-            const int64_t thr = (int64_t)best * ed;
-            const int64_t lim = en == 1 ? thr : thr / en;
-            const uint32_t lim32 = (uint32_t)min<int64_t>(lim, 0xFFFFFFFFll);
-            if (valid && j < 0) {
-                uint32_t m[PER];
-                if constexpr (LT) load_mt_piece<MT, PER>(l_dm + (uint32_t)bi * (uint32_t)k, sub, m);
-                else load_mt_piece<MT, PER>(dmat_c + (int64_t)bi * k, sub, m);
-#pragma unroll
-                for (int e = 0; e < PER; e++) {
-                    if (m[e] <= lim32) {
-                        lcsum += (AT)r.d[e];
-                        lcnum += 1;
-                    }
-                }
-            }
-        }
-        if constexpr (sizeof(AT) == 4) lcsum = group_sum32<G>(lcsum);
-        else lcsum = group_sum64<G>(lcsum);
-        lcnum = group_sum32<G>(lcnum);
-        const bool unreached = group_sum32<G>(unr ? 1u : 0u) != 0;
-        const int p = bi;
-        // every lane of the group now holds the node's totals: the lane whose
-        // sub index is this trip's number in the round keeps them
-        if (sub == trip) {
-            hv = valid ? v : -1;
-            hj = j;
-            hp = p;
-            hdelta = best;
-            hrowsum = sum;
-            hlcsum = lcsum;
-            hlcnum = lcnum;
-            hunr = unreached;
-        }
-        if (++trip == G) finish();
-    };
     // the end of Algorithm 1 for the nodes the lanes hold, all lanes at once
-    // (after G trips each lane holds one node)
     auto finish = [&]() {
-        trip = 0;
-        if (hv < 0) return;
-        const int64_t v = hv;
-        const int32_t j = hj;
+        if (ho < 0) return;
+        const int64_t o = ho, v = hv;
+        ho = -1;
         const int p = hp;
         const int64_t delta = hdelta;
-        const bool unreached = hunr;
-        hv = -1;
         const int64_t lim = en == 1 ? delta * ed : delta * ed / en;
         double hyb, samp;
         int64_t piv, pub;
         bool ovf = false;
         const int64_t sum64 = (int64_t)hrowsum, lcsum64 = (int64_t)hlcsum, lcnum64 = (int64_t)hlcnum;
-        if (j >= 0) {
-            const int64_t S = LT ? l_ss[j] : src_sum[j];
+        if (delta == 0) {  // the node is sample c_p: its exact sum
+            const int64_t S = LT ? l_ss[p] : src_sum[p];
             hyb = samp = (double)S;
             piv = pub = S;
             ovf = S >= LIM;
@@ -650,35 +563,133 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
             piv = LT ? l_ss[p] : src_sum[p];
             pub = piv + (n - 1) * delta;
         }
-        if (stage) {  // the node's record in internal order; written out in the caller's order afterwards
-            const uint64_t hb = (uint64_t)__double_as_longlong(hyb), sb = (uint64_t)__double_as_longlong(samp);
-            uint4* rec = stage + v * 4;
-            rec[0] = make_uint4((uint32_t)hb, (uint32_t)(hb >> 32), (uint32_t)sb, (uint32_t)(sb >> 32));
-            rec[1] = make_uint4((uint32_t)piv, (uint32_t)((uint64_t)piv >> 32), (uint32_t)pub,
-                                (uint32_t)((uint64_t)pub >> 32));
-            rec[2] = make_uint4((uint32_t)sum64, (uint32_t)((uint64_t)sum64 >> 32), (uint32_t)p, (uint32_t)delta);
-        } else {
-            const int64_t o = orig[v];
-            if (S_hyb) S_hyb[o] = hyb;
-            if (S_samp) S_samp[o] = samp;
-            if (S_piv) S_piv[o] = piv;
-            if (S_pub) S_pub[o] = pub;
-            if (pivot_out) pivot_out[o] = p;
-            if (delta_out) delta_out[o] = (int32_t)delta;
-            if (sampsum_out) sampsum_out[o] = sum64;
-        }
+        const int64_t out = inv ? o : (int64_t)orig[v];
+        if (S_hyb) S_hyb[out] = hyb;
+        if (S_samp) S_samp[out] = samp;
+        if (S_piv) S_piv[out] = piv;
+        if (S_pub) S_pub[out] = pub;
+        if (pivot_out) pivot_out[out] = p;
+        if (delta_out) delta_out[out] = (int32_t)delta;
+        if (sampsum_out) sampsum_out[out] = sum64;
         any_ovf = any_ovf || ovf;
-        any_unreached = any_unreached || unreached;
+        any_unreached = any_unreached || hunr;
     };
-    RawPiece<DT, RT> pp[kEstInFlight];
+    auto step = [&](RawPiece<DT, RT>& rp, int64_t s) {
+        const int t = (int)(s % G);
+        const int64_t r = s / G;
+        if (t == 0 && r > 0) {  // a new round: its ids were loaded a round ago
+            ids_cur = ids_nxt;
+            ids_nxt = load_ids(r + 1);
+        }
+        const int64_t o = (gw + r * nw) * 64 + t * NPW + q;
+        const bool valid = o < n;
+        const int64_t v = __shfl(ids_cur, t * NPW + q);
+        uint32_t best;
+        int32_t bi;
+        AT sum, lcsum = 0;
+        uint32_t lcnum = 0;
+        bool unr;
+        if constexpr (kPacked) {
+            // u8 rows, one direction, u8 sample distances: byte-packed arithmetic
+            const uint4 a = rp.a;
+            fetch(rp, s + 2, r);
+            unr = valid && any_byte_ff(a);
+            const uint32_t m = bytes_min(a);
+            const uint32_t key = group_min32<G>(
+                valid ? ((m << 16) | ((uint32_t)sub * PER + bytes_first_eq(a, m))) : 0xFFFFFFFFu);
+            best = key >> 16;  // the lowest index among equal minima
+            bi = (int32_t)(key & 0xFFFFu);
+            sum = group_sum32<G>(valid ? bytes_sum(a, 0u) : 0u);
+            const int64_t lim = en == 1 ? (int64_t)best * ed : (int64_t)best * ed / en;
+            if (valid && best != 0) {
+                const uint4 dm = LT ? ((const uint4*)(l_dm + (uint32_t)bi * (uint32_t)k))[sub]
+                                    : ((const uint4*)(dmat_c + (int64_t)bi * k))[sub];
+                bytes_sum_le(a, dm, lim >= 255 ? 255u : (uint32_t)lim, lcsum, lcnum);
+            }
+        } else {
+            RowPiece<DT, RT> rw;
+            rw.decode(rp.a, rp.b);
+            fetch(rp, s + 2, r);
+            if (!valid) {
 #pragma unroll
-    for (int u = 0; u < kEstInFlight; u++) fetch(pp[u], (int64_t)blockIdx.x + u * g);
-    for (int64_t s0 = blockIdx.x; s0 < steps; s0 += kEstInFlight * g) {
+                for (int e = 0; e < PER; e++) rw.d[e] = 0xFFFFFFFFu;
+                rw.unreached = false;
+            }
+            unr = rw.unreached;
+            // argmin (lowest index among equal minima) and sum
+            best = 0xFFFFFFFFu;
+            bi = 0;
+            sum = 0;
 #pragma unroll
-        for (int u = 0; u < kEstInFlight; u++)
-            if (s0 + u * g < steps) step(pp[u], s0 + u * g, finish);
+            for (int e = 0; e < PER; e++) {
+                if (rw.d[e] < best) {
+                    best = rw.d[e];
+                    bi = sub * PER + e;
+                }
+                sum += valid ? (AT)rw.d[e] : (AT)0;
+            }
+            if constexpr (sizeof(DT) == 1) {
+                // one key: distance (< 2^9, an all-ones placeholder for a masked
+                // node) above the index (k <= 256 for rows of at most 256 bytes)
+                const uint32_t key = group_min32<G>(valid ? ((best << 16) | (uint32_t)bi) : 0xFFFFFFFFu);
+                best = key >> 16;
+                bi = (int32_t)(key & 0xFFFFu);
+            } else {
+#pragma unroll
+                for (int st = 0; (1 << st) < G; st++) {
+                    const uint32_t ob = dpp_partner(best, st);
+                    const int32_t oi = (int32_t)dpp_partner((uint32_t)bi, st);
+                    if (ob < best || (ob == best && oi < bi)) {
+                        best = ob;
+                        bi = oi;
+                    }
+                }
+            }
+            if constexpr (sizeof(AT) == 4) sum = group_sum32<G>(sum);
+            else sum = group_sum64<G>(sum);
+            // the L cap C split against the pivot's row of the sample distances:
+            // dmat * num <= Delta * den  <=>  dmat <= floor(Delta * den / num)
+            const int64_t thr = (int64_t)best * ed;
+            const int64_t lim = en == 1 ? thr : thr / en;
+            const uint32_t lim32 = (uint32_t)min<int64_t>(lim, 0xFFFFFFFFll);
+            if (valid && best != 0) {
+                uint32_t m[PER];
+                if constexpr (LT) load_mt_piece<MT, PER>(l_dm + (uint32_t)bi * (uint32_t)k, sub, m);
+                else load_mt_piece<MT, PER>(dmat_c + (int64_t)bi * k, sub, m);
+#pragma unroll
+                for (int e = 0; e < PER; e++) {
+                    if (m[e] <= lim32) {
+                        lcsum += (AT)rw.d[e];
+                        lcnum += 1;
+                    }
+                }
+            }
+        }
+        if constexpr (sizeof(AT) == 4) lcsum = group_sum32<G>(lcsum);
+        else lcsum = group_sum64<G>(lcsum);
+        lcnum = group_sum32<G>(lcnum);
+        const bool unreached = group_sum32<G>(unr ? 1u : 0u) != 0;
+        // every lane of the group now holds the node's totals: the lane whose
+        // sub index is this trip's number in the round keeps them
+        if (sub == t) {
+            ho = valid ? o : -1;
+            hv = v;
+            hp = bi;
+            hdelta = best;
+            hrowsum = sum;
+            hlcsum = lcsum;
+            hlcnum = lcnum;
+            hunr = unreached;
+        }
+        if (t == G - 1) finish();
+    };
+    RawPiece<DT, RT> pa, pb;
+    fetch(pa, 0, 0);
+    fetch(pb, 1, 0);
+    for (int64_t s = 0; s < trips; s += 2) {
+        step(pa, s);
+        if (s + 1 < trips) step(pb, s + 1);
     }
-    finish();  // a round cut short by the end
     if (any_ovf) flags->overflow = 1;
     if (any_unreached) flags->disconnected = 1;
 }
@@ -1441,12 +1452,6 @@ int row_lanes(int32_t k) {
     return (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ? (int)g : 0;
 }
 
-// Whether the Sec. 2 outputs go through per-node records (a relabelled graph
-// with at least one of them requested).
-inline bool epilogue_staged(const EpilogueArgs& a) {
-    return a.inv && (a.S_hyb || a.S_samp || a.S_piv || a.S_pub || a.pivot || a.delta || a.sampsum);
-}
-
 template <typename DT, bool RT, typename MT>
 void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* flags) {
     const int64_t n = a.n;
@@ -1510,37 +1515,31 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
     hipLaunchKernelGGL((k_dmat<DT, RT, MT>), dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, st, (const DT*)a.D,
                        (const DT*)a.Dr, a.samples, k, a.dmat, dmat_c, flags);
     run_suffix(st, hist, nslots, k, k, hlen, maxd, a.dmat, Tcnt, Tsum, a.src_sum, chunks);
-    const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
     {
         const DT* Dp = (const DT*)a.D;
         const DT* Drp = (const DT*)a.Dr;
         const int G = row_lanes<DT>(k);
-        const unsigned eb = grid_for(n * (G > 0 ? G : 1), 8192);
-        // staged records after the histogram and the error pass's scratch
-        uint4* stage = nullptr;
-        if (epilogue_staged(a) && G > 0)
-            stage = (uint4*)(p + (a.hist_done ? 0 : align256(sizeof(int32_t) * k * (maxd + 1))) +
-                             (want_err ? align256(sweep_scratch_bytes(n, k)) : 0));
-        // small tables in LDS when they fit: blocks of 512 threads, two per CU
-        // (a block copies the tables once, so the grid stays at a few per CU)
+        // the row kernel: 64 positions per wave and round; small tables in
+        // LDS when they fit (blocks of 512 threads, two per CU: a block copies
+        // the tables once, so the grid stays at a few blocks per CU)
+        const int64_t rounds = (n + 63) / 64;
         const size_t tb = est_table_bytes(k, tlen, sizeof(MT));
         const bool lt = tb <= kEstTableLds;
         const unsigned ebl = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>(kEstTableBlocks, (n + kEstBlock / std::max(G, 1) - 1) / (kEstBlock / std::max(G, 1))));
+            1, std::min<int64_t>(kEstTableBlocks, (rounds + kEstBlock / 64 - 1) / (kEstBlock / 64)));
+        const unsigned eb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (rounds + kBlock / 64 - 1) / (kBlock / 64)));
 #define CCG_EST_ROWS(GG)                                                                                               \
     do {                                                                                                               \
         if (lt)                                                                                                        \
             hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, true, kEstBlock>), dim3(ebl), dim3(kEstBlock), tb, st, \
-                               Dp, Drp, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,          \
-                               a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, stage,     \
-                               flags);                                                                                 \
+                               Dp, Drp, n, k, a.orig, a.inv, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,           \
+                               a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);    \
         else                                                                                                           \
             hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, false, kBlock>), dim3(eb), dim3(kBlock), 0, st, Dp,    \
-                               Drp, n, k, a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den,   \
-                               a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, stage, flags);        \
+                               Drp, n, k, a.orig, a.inv, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den,    \
+                               a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);               \
     } while (0)
         switch (G) {
-            case 1: CCG_EST_ROWS(1); break;
             case 2: CCG_EST_ROWS(2); break;
             case 4: CCG_EST_ROWS(4); break;
             case 8: CCG_EST_ROWS(8); break;
@@ -1552,7 +1551,6 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         }
 #undef CCG_EST_ROWS
         CCG_HIP(hipGetLastError());
-        if (stage) put_outputs(st, n, a.inv, stage, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum);
     }
     CCG_HIP(hipGetLastError());
     if (a.Dout) {
@@ -1745,19 +1743,18 @@ size_t suffix_chunk_scratch(int32_t k, int64_t maxd) {
     return sizeof(int64_t) * 2 * (size_t)k * (size_t)nchunks + 256;
 }
 
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err, bool staged) {
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err) {
     const int64_t tlen = maxd + 2;
     size_t s = align256(sizeof(int32_t) * k * tlen) + align256(sizeof(int64_t) * k * tlen) +
                align256(sizeof(uint32_t) * (size_t)k * k) + align256(suffix_chunk_scratch(k, maxd)) + 1024;
     if (!hist_done) s += align256(sizeof(int32_t) * k * (maxd + 1));
     if (err) s += align256(sweep_scratch_bytes(n, k));
-    if (staged) s += align256((size_t)64 * n);
     return s;
 }
 
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags) {
     const bool want_err = a.S_err || a.S_ad || a.S_ad_err || a.S_sweep || a.S_sweep_err;
-    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done, want_err, epilogue_staged(a)))
+    if (scratch_size < epilogue_scratch(a.n, a.k, a.maxd, a.hist_done, want_err))
         throw HipError{hipErrorOutOfMemory, "epilogue scratch"};
     const bool rt = a.Dr != nullptr;
     switch (a.dk) {

@@ -371,9 +371,9 @@ struct EpilogueArgs {
     const int32_t* samples = nullptr;  // device, internal ids
     const int32_t* sidx = nullptr;     // device, internal id -> sample index or -1
     const int32_t* orig = nullptr;     // device, internal id -> caller's id
-    // device, caller's id -> internal id: when set, the Sec. 2 outputs are staged
-    // as one 64-byte record per node in internal order and then written in the
-    // caller's order (coalesced stores instead of seven scattered ones per node)
+    // device, caller's id -> internal id: when set, the row estimate walks the
+    // nodes in the caller's order (v = inv[o]) and stores the Sec. 2 outputs at
+    // o, consecutive for a wave (instead of seven scattered stores per node)
     const int32_t* inv = nullptr;
     int64_t maxd = 0;            // upper bound on every (combined) distance
     int64_t eps_num = 1, eps_den = 1;
@@ -403,7 +403,7 @@ struct EpilogueArgs {
 // sample's sorted row of the sample distance matrix and the nodes grouped by
 // pivot; added to an epilogue's scratch when any of its outputs is wanted
 size_t sweep_scratch_bytes(int64_t n, int32_t k);
-size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err = false, bool staged = false);
+size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err = false);
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
 // The staged 64-byte node records written out in the caller's order
 void put_outputs(hipStream_t st, int64_t n, const int32_t* inv, const void* stage, double* S_hyb, double* S_samp,
