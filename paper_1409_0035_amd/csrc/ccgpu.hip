@@ -1297,7 +1297,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
     const size_t small = Carver::sz(sizeof(int32_t) * k) + Carver::sz(sizeof(DevFlags)) +
                          Carver::sz(sizeof(LevelCounters) * kCounterSlots) + Carver::sz(sizeof(int32_t) * n) +
                          Carver::sz(sizeof(int64_t) * k) + Carver::sz(sizeof(int32_t) * (size_t)k * k) +
-                         Carver::sz(sizeof(int32_t) * ngroups) + Carver::sz(sizeof(uint32_t) * 2);
+                         Carver::sz(sizeof(int32_t) * ngroups) * 2 + Carver::sz(sizeof(uint32_t) * 2);
     const int32_t kg0 = std::min(k, 256);
     const int Wg = (kg0 + 63) / 64;
     // free device memory, queried (once) only where a size depends on it: the
@@ -1347,16 +1347,19 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         int64_t* src_sum = out->src_sum ? out->src_sum : c.take<int64_t>(k);
         int32_t* dmat = out->dmat ? out->dmat : c.take<int32_t>((size_t)k * k);
         int32_t* fill_level = c.take<int32_t>(ngroups);
+        int32_t* fill_level_r = c.take<int32_t>(ngroups);  // the reverse search's, on a round trip
         uint32_t* wmaxd_dev = c.take<uint32_t>(2);  // captured weighted searches: each direction's largest distance
         void* ts = c.take<char>(trav_scratch);
         int32_t* hist = bits_path ? c.take<int32_t>(hist_elems) : nullptr;
-        // distance matrices and/or level masks
-        const size_t snap_bytes = batched ? Carver::sz((size_t)cap * n * Wg * 8) : 0;
+        // distance matrices and/or level masks (a round trip of one group keeps
+        // both directions' masks, whose distances are then summed in one pass)
+        const size_t snap_bytes = batched ? Carver::sz((size_t)cap * n * Wg * 8) * (rt_single ? 2 : 1) : 0;
         const bool need_Dt = mode == CC_PLAIN || g.weighted;
         const size_t need_D = (bits_path ? 0 : Carver::sz(dbytes) * (g.directed ? 2 : 1)) +
                               (need_Dt ? Carver::sz(dbytes) : 0);
         Carver cd(L.arenaD.get(snap_bytes + need_D + 256));
         uint64_t* snap = batched ? cd.take<uint64_t>((size_t)cap * n * Wg) : nullptr;
+        uint64_t* snap_r = rt_single ? cd.take<uint64_t>((size_t)cap * n * Wg) : nullptr;
         void* D = bits_path ? nullptr : cd.take<char>(dbytes);
         void* Dr = (!bits_path && g.directed) ? cd.take<char>(dbytes) : nullptr;
         void* Dt = need_Dt ? cd.take<char>(dbytes) : nullptr;
@@ -1483,6 +1486,20 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         int32_t lmax_dir[2] = {0, 0};
         int32_t levels_dir[2] = {0, 0};  // levels each direction's batched traversal ran
         bool rt_summed = false;          // D holds the round-trip distances (no separate reverse array)
+        // a round trip of one sample group, after both searches: with one-byte
+        // rows whose sums fit (and whole words), one pass writes the summed
+        // distances to D, so the epilogue reads one array (returns true);
+        // otherwise each direction's distances go to D and Dr
+        auto materialize_rt = [&](int32_t lm_f, int32_t lm_r) -> bool {
+            const size_t plane = (size_t)n * ((k + 63) / 64);
+            if (dk == DistKind::U8 && k % 64 == 0 && (int64_t)lm_f + lm_r <= DistT<uint8_t>::max_level) {
+                materialize_round_trip(st, snap, fill_level, lm_f, snap_r, fill_level_r, lm_r, n, k, D, flags);
+                return true;
+            }
+            materialize_distances(st, snap, plane, lm_f, fill_level, n, k, 0, k, D, dk, flags, false);
+            materialize_distances(st, snap_r, plane, lm_r, fill_level_r, n, k, 0, k, Dr, dk, flags, false);
+            return false;
+        };
         for (int dir = 0; dir < (g.directed ? 2 : 1) && rc == 0; dir++) {
             // forward distances d(c_i -> v): push over out-arcs, pull over in-arcs;
             // reverse distances d(v -> c_i): the same on the transposed graph
@@ -1526,9 +1543,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     const int32_t kg = std::min(256, k - s0);
                     int32_t lm = 0;
                     BfsLevels lv;
-                    lv.snap = snap;
+                    lv.snap = (rt_single && dir == 1) ? snap_r : snap;
                     lv.cap = cap;
-                    lv.fill_level = fill_level;
+                    lv.fill_level = (rt_single && dir == 1) ? fill_level_r : fill_level;
                     lv.hist = hist;
                     lv.hlen = cap;
                     lv.lmax = &lm;
@@ -1549,13 +1566,13 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     if (!bits_path) {
                         if ((int64_t)lm > DistT<uint8_t>::max_level && dk == DistKind::U8) { rc = 3; break; }
                         if ((int64_t)lm > DistT<uint16_t>::max_level && dk == DistKind::U16) { rc = 3; break; }
-                        // a round trip of one sample group with one-byte rows whose sums fit: the reverse
-                        // distances are added to the forward ones in place, so the epilogue reads one array
-                        const bool sum = g.directed && dir == 1 && kg == k && dk == DistKind::U8 &&
-                                         (int64_t)lmax_dir[0] + lm <= DistT<uint8_t>::max_level;
-                        materialize_distances(st, snap, (size_t)n * ((kg + 63) / 64), lm, fill_level, n, kg, s0, k,
-                                              sum ? D : Dd, dk, flags, sum);
-                        if (sum) rt_summed = true;
+                        if (rt_single) {
+                            // both searches first, then the distances from both directions' masks
+                            if (dir == 1) rt_summed = materialize_rt(lmax_dir[0], lm);
+                        } else {
+                            materialize_distances(st, snap, (size_t)n * ((kg + 63) / 64), lm, fill_level, n, kg, s0,
+                                                  k, Dd, dk, flags, false);
+                        }
                     }
                 }
             }
@@ -1563,9 +1580,10 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         }
         if (rc == 1) {  // more levels than the mask buffer holds
             cap = (int32_t)std::min<int64_t>((int64_t)cap * 4, n + 2);
-            if (L.no_alloc && (size_t)cap * n * Wg * 8 > L.arenaD.size)  // the fixed buffers cannot hold the masks
-                throw FixedScratchFull{(size_t)cap * n * Wg * 8, L.arenaD.size};
-            if ((size_t)cap * n * Wg * 8 > mask_budget()) mode = CC_PLAIN;
+            const size_t masks = (size_t)cap * n * Wg * 8 * (rt_single ? 2 : 1);
+            if (L.no_alloc && masks > L.arenaD.size)  // the fixed buffers cannot hold the masks
+                throw FixedScratchFull{masks, L.arenaD.size};
+            if (masks > mask_budget()) mode = CC_PLAIN;
             continue;
         }
         if (rc == 3) {  // distance type too narrow
@@ -1706,9 +1724,9 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 for (int dir = 0; dir < (rt_single ? 2 : 1); dir++) {
                     int32_t lm = 0;
                     BfsLevels lv;
-                    lv.snap = snap;
+                    lv.snap = (rt_single && dir == 1) ? snap_r : snap;
                     lv.cap = cap;
-                    lv.fill_level = fill_level;
+                    lv.fill_level = (rt_single && dir == 1) ? fill_level_r : fill_level;
                     lv.hist = hist;
                     lv.hlen = cap;
                     lv.lmax = &lm;
@@ -1723,13 +1741,12 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                     (void)bfs_batched(st, make_view(dir), samples_dev, k, 0, k, lv, sidx, ts, trav_scratch, cnt,
                                       &ignored, nullptr);
                     if (rt_single) {
-                        const bool sum = dir == 1 && rt_summed;
-                        materialize_distances(st, snap, (size_t)n * ((k + 63) / 64), lmax_dir[dir], fill_level, n, k,
-                                              0, k, (dir == 0 || sum) ? D : Dr, dk, flags, sum);
                         if (dir == 0)  // the forward search's control block, before the reverse one reuses it
                             hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st, ctl_dev,
                                                (const uint32_t*)flags, (uint32_t*)&L.rb_dev->ctl_fwd,
                                                (uint32_t*)&L.rb_dev->flags_fwd);
+                        else  // the same choice as the eager run (replays check that the depths agree)
+                            (void)materialize_rt(lmax_dir[0], lmax_dir[1]);
                     }
                 }
                 if (bits_path) run_bits_epilogue(st, ba, ba_scratch, ba_es, flags);

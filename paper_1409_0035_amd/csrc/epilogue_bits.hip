@@ -398,6 +398,46 @@ __global__ __launch_bounds__(kBlock) void k_materialize_words(
     }
 }
 
+// Round-trip distances of one group of samples (one-byte rows, whole 64-bit
+// words) from both directions' masks in one pass, one thread per (node, word):
+// the forward and the reverse level counts, summed (the host checked that
+// the largest sums fit a byte), written once.  Materialising the forward
+// distances first and adding the reverse ones in place wrote the rows twice
+// and read them back once.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_materialize_round_trip(SnapView fw, int32_t lmax_f, SnapView rv,
+                                                                   int32_t lmax_r, int64_t n, int32_t k,
+                                                                   uint8_t* __restrict__ out, DevFlags* flags) {
+    const int64_t count = n * W;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = t / W;
+        const int w = (int)(t % W);
+        uint64_t acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) acc[q] = 0;
+        bool unreached = false;
+#pragma unroll
+        for (int dir = 0; dir < 2; dir++) {
+            const SnapView& sv = dir == 0 ? fw : rv;
+            const int32_t last = min(sv.fill(v), dir == 0 ? lmax_f : lmax_r);
+            uint64_t miss = ~0ull;
+            for (int32_t L = 0; L <= last; L++) {
+                miss = ~sv.row(L, v)[w];
+                if (!miss) break;
+#pragma unroll
+                for (int q = 0; q < 8; q++) acc[q] += spread8((uint32_t)(miss >> (8 * q)) & 0xFFu);
+            }
+            unreached = unreached || miss != 0;
+        }
+        if (unreached) flags->disconnected = 1;  // a bit still unset when the node stopped changing
+        uint4* d4 = reinterpret_cast<uint4*>(out + v * k + (int64_t)w * 64);
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            d4[q] = make_uint4((uint32_t)acc[2 * q], (uint32_t)(acc[2 * q] >> 32), (uint32_t)acc[2 * q + 1],
+                               (uint32_t)(acc[2 * q + 1] >> 32));
+    }
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 inline unsigned grid_for(int64_t items, int64_t cap) {
@@ -571,6 +611,24 @@ void materialize_distances(hipStream_t st, const uint64_t* snap, size_t plane, i
         case 2: materialize_w<2>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags, add); break;
         case 3: materialize_w<3>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags, add); break;
         default: materialize_w<4>(st, snap, plane, lmax, fill_level, n, kg, src_base, k, D, dk, flags, add); break;
+    }
+    CCG_HIP(hipGetLastError());
+}
+
+void materialize_round_trip(hipStream_t st, const uint64_t* snap_f, const int32_t* fill_f, int32_t lmax_f,
+                            const uint64_t* snap_r, const int32_t* fill_r, int32_t lmax_r, int64_t n, int32_t k,
+                            void* D, DevFlags* flags) {
+    if (k % 64 != 0 || k > 256 || lmax_f + lmax_r > 254)
+        throw HipError{hipErrorInvalidValue, "round-trip rows need whole words and byte sums"};
+    const int W = k / 64;
+    const size_t plane = (size_t)n * W;
+    const SnapView fw{snap_f, plane, W, 0, 0, fill_f}, rv{snap_r, plane, W, 0, 0, fill_r};
+    const dim3 grid(grid_for(n * W, 65536));
+    switch (W) {
+        case 1: hipLaunchKernelGGL((k_materialize_round_trip<1>), grid, dim3(kBlock), 0, st, fw, lmax_f, rv, lmax_r, n, k, (uint8_t*)D, flags); break;
+        case 2: hipLaunchKernelGGL((k_materialize_round_trip<2>), grid, dim3(kBlock), 0, st, fw, lmax_f, rv, lmax_r, n, k, (uint8_t*)D, flags); break;
+        case 3: hipLaunchKernelGGL((k_materialize_round_trip<3>), grid, dim3(kBlock), 0, st, fw, lmax_f, rv, lmax_r, n, k, (uint8_t*)D, flags); break;
+        default: hipLaunchKernelGGL((k_materialize_round_trip<4>), grid, dim3(kBlock), 0, st, fw, lmax_f, rv, lmax_r, n, k, (uint8_t*)D, flags); break;
     }
     CCG_HIP(hipGetLastError());
 }

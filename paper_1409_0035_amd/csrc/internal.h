@@ -405,6 +405,13 @@ struct EpilogueArgs {
 size_t sweep_scratch_bytes(int64_t n, int32_t k);
 size_t epilogue_scratch(int64_t n, int32_t k, int64_t maxd, bool hist_done, bool err = false);
 void run_epilogue(hipStream_t st, const EpilogueArgs& a, void* scratch, size_t scratch_size, DevFlags* flags);
+// Round-trip distances of one group of k (a multiple of 64, at most 256)
+// samples as one-byte rows D[v][i] = d(c_i, v) + d(v, c_i), from the forward
+// and the reverse search's level masks and fill levels in one pass (each
+// direction's largest distance given; their sum must be at most 254)
+void materialize_round_trip(hipStream_t st, const uint64_t* snap_f, const int32_t* fill_f, int32_t lmax_f,
+                            const uint64_t* snap_r, const int32_t* fill_r, int32_t lmax_r, int64_t n, int32_t k,
+                            void* D, DevFlags* flags);
 // The staged 64-byte node records written out in the caller's order
 void put_outputs(hipStream_t st, int64_t n, const int32_t* inv, const void* stage, double* S_hyb, double* S_samp,
                  int64_t* S_piv, int64_t* S_pub, int32_t* pivot, int32_t* delta, int64_t* sampsum);
