@@ -132,6 +132,30 @@ def test_directed_rmat_round_trip(ctx):
     parity(ctx, g, 128, seed=6)
 
 
+@pytest.mark.parametrize("k", [16, 32, 64, 100, 128, 192, 256])
+def test_round_trip_row_widths(ctx, k):
+    """The round trip at every row width of the distance epilogue: k = 16
+    (one 16-byte piece per node, the one-lane kernels), 32, 64, 128 and 256
+    (2, 4, 8 and 16 lanes per node, byte-packed), 100 and 192 (rows that are
+    not 16 * 2^j bytes); k = 64, 128, 192 and 256 sum both directions in one
+    pass, k = 16, 32 and 100 (a partial mask word) write each direction's
+    distances apart.  Eager, then captured and replayed, every output against
+    the oracle's."""
+    g = graphgen.rmat(11, 16, seed=60 + k, directed=True)
+    seed = 70 + k
+    samples = oracle.draw_samples(g.n, k, seed)
+    ref = oracle.estimate_all(g, samples, threads=8, reverse_graph=graphgen.transpose(g))
+    gh = ctx.upload(g)
+    try:
+        for mode, reps in ((cc.CC_BATCHED, 1), (cc.CC_BATCHED | cc.CC_GRAPH, 3)):
+            for rep in range(reps):
+                _say(f"  round trip n={g.n} arcs={g.arcs} k={k} mode={mode} call {rep}")
+                res = cc.cc_estimate(ctx.handle, gh, k, mode=mode, seed=seed, outputs=ALL)
+                check_all(res, ref, samples)
+    finally:
+        ctx.release(gh)
+
+
 def test_symmetric_digraph_round_trip_is_twice(ctx):
     g = graphgen.ba(800, 3, seed=2)
     gd = graphgen.symmetric_digraph(g)
