@@ -364,6 +364,16 @@ struct Lane {
     Readback* rb_host = nullptr;  // pinned: a replay's control block and flags, and the staged samples
     Readback* rb_dev = nullptr;   // its device-visible address
     hipEvent_t ev[4] = {};
+    // a captured round trip runs its reverse search on a second stream, a
+    // parallel branch of the graph (created when first needed)
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    void ensure_side() {
+        if (side) return;
+        CCG_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        CCG_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+        CCG_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+    }
     EventPool events;  // per-launch timing inside the traversals
     uint64_t gen = 0;  // arena generation
     int64_t last_maxd = -1;  // an upper bound on the last job's largest distance (-1: unknown)
@@ -413,6 +423,11 @@ struct Lane {
         captured.clear();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
+        if (side) (void)hipStreamDestroy(side);
+        fork_ev = join_ev = nullptr;
+        side = nullptr;
         if (cnt_host) (void)hipHostFree(cnt_host);
         if (rb_host) (void)hipHostFree(rb_host);
         if (pin) (void)hipHostFree(pin);
@@ -1339,7 +1354,11 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         else
             trav_scratch = mode == CC_PLAIN ? bfs_plain_scratch(n, g.arcs, k) : bfs_batched_scratch(n, kg0, g.nh);
         const size_t hist_elems = bits_path ? (size_t)kHistSlotsBatched * k * cap : 0;
-        Carver c(L.arena.get(small + Carver::sz(trav_scratch) + Carver::sz(sizeof(int32_t) * hist_elems)));
+        // a round trip of one group: the reverse search's own traversal state, so that a captured
+        // estimate can run both searches side by side
+        const size_t rt_extra =
+            rt_single ? Carver::sz(trav_scratch) + Carver::sz(sizeof(LevelCounters) * kCounterSlots) : 0;
+        Carver c(L.arena.get(small + Carver::sz(trav_scratch) + Carver::sz(sizeof(int32_t) * hist_elems) + rt_extra));
         int32_t* samples_dev = c.take<int32_t>(k);
         DevFlags* flags = c.take<DevFlags>(1);
         LevelCounters* cnt = c.take<LevelCounters>(kCounterSlots);
@@ -1350,6 +1369,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
         int32_t* fill_level_r = c.take<int32_t>(ngroups);  // the reverse search's, on a round trip
         uint32_t* wmaxd_dev = c.take<uint32_t>(2);  // captured weighted searches: each direction's largest distance
         void* ts = c.take<char>(trav_scratch);
+        void* ts_r = rt_single ? c.take<char>(trav_scratch) : nullptr;
+        LevelCounters* cnt_r = rt_single ? c.take<LevelCounters>(kCounterSlots) : nullptr;
         int32_t* hist = bits_path ? c.take<int32_t>(hist_elems) : nullptr;
         // distance matrices and/or level masks (a round trip of one group keeps
         // both directions' masks, whose distances are then summed in one pass)
@@ -1698,6 +1719,7 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 cap_e.levels = 0;
             }
             hipGraph_t graph = nullptr;
+            if (rt_single) L.ensure_side();  // created outside the capture
             const bool began = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
             bool captured_ok = began;
             if (began && w_single) try {
@@ -1715,6 +1737,44 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 run_epilogue(st, ea, ea_scratch, ea_es, flags);
                 hipLaunchKernelGGL(k_wstatus_out, dim3(1), dim3(64), 0, st, (const uint32_t*)flags,
                                    (const uint32_t*)wmaxd_dev, (uint32_t*)&L.rb_dev->flags, L.rb_dev->wmaxd);
+                CCG_HIP(hipGetLastError());
+            } catch (const HipError&) {
+                captured_ok = false;
+            }
+            else if (began && rt_single) try {
+                // the round trip: the job's setup, then the forward search on the lane's
+                // stream and the reverse one on the side stream (parallel branches of the
+                // graph, each with its own traversal state), joined for the distances
+                fill_u32(st, flags, 0u, sizeof(DevFlags) / 4);
+                hipLaunchKernelGGL(k_stage_samples, dim3(1), dim3(256), 0, st, (const int32_t*)L.rb_dev->ids,
+                                   (const int32_t*)L.rb_dev->caller, k, samples_dev, out->samples);
+                compute_sidx(st, samples_dev, k, sidx, n);
+                CCG_HIP(hipEventRecord(L.fork_ev, st));
+                CCG_HIP(hipStreamWaitEvent(L.side, L.fork_ev, 0));
+                for (int dir = 0; dir < 2; dir++) {
+                    int32_t lm = 0;
+                    BfsLevels lv;
+                    lv.snap = dir == 0 ? snap : snap_r;
+                    lv.cap = cap;
+                    lv.fill_level = dir == 0 ? fill_level : fill_level_r;
+                    lv.hlen = cap;
+                    lv.lmax = &lm;
+                    lv.enqueue_only = levels_dir[dir];
+                    TravStats ignored;
+                    (void)bfs_batched(dir == 0 ? st : L.side, make_view(dir), samples_dev, k, 0, k, lv, sidx,
+                                      dir == 0 ? ts : ts_r, trav_scratch, dir == 0 ? cnt : cnt_r, &ignored, nullptr);
+                }
+                // the forward search's control block
+                hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st,
+                                   (const uint32_t*)bfs_batched_ctl(ts, n, kg0), (const uint32_t*)flags,
+                                   (uint32_t*)&L.rb_dev->ctl_fwd, (uint32_t*)&L.rb_dev->flags_fwd);
+                CCG_HIP(hipEventRecord(L.join_ev, L.side));
+                CCG_HIP(hipStreamWaitEvent(st, L.join_ev, 0));
+                (void)materialize_rt(lmax_dir[0], lmax_dir[1]);  // the same choice as the eager run
+                run_epilogue(st, ea, ea_scratch, ea_es, flags);
+                hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, st,
+                                   (const uint32_t*)bfs_batched_ctl(ts_r, n, kg0), (const uint32_t*)flags,
+                                   (uint32_t*)&L.rb_dev->ctl, (uint32_t*)&L.rb_dev->flags);
                 CCG_HIP(hipGetLastError());
             } catch (const HipError&) {
                 captured_ok = false;
