@@ -331,9 +331,7 @@ __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, 
 // 0.745 -> 0.641 ms; without the pending test too, 0.703 ms, as hubs then
 // take every atomic).
 template <int W>
-__device__ __forceinline__ void push_arc(const uint64_t* __restrict__ Sprev, uint64_t* NX, int64_t x,
-                                         const uint64_t (&su)[W], int64_t& atomics) {
-    (void)Sprev;
+__device__ __forceinline__ void push_arc(uint64_t* NX, int64_t x, const uint64_t (&su)[W], int64_t& atomics) {
 #pragma unroll
     for (int w = 0; w < W; w++) {
         if (!su[w]) continue;
@@ -369,7 +367,7 @@ __device__ __forceinline__ void push_group(const uint32_t* __restrict__ out_rp, 
         const uint32_t b = out_rp[u], e = out_rp[u + 1];
         for (uint32_t t = b + lane; t < e; t += 64) {
             ++wc.arcs;
-            push_arc<W>(Sprev, NX, out_col[t], su, atomics);
+            push_arc<W>(NX, out_col[t], su, atomics);
         }
     }
 }
@@ -389,7 +387,7 @@ __device__ __forceinline__ void push_chunk(const int32_t* __restrict__ out_col, 
     for (int w = 0; w < W; w++) su[w] = Sprev[h * W + w];
     for (uint32_t t = b + lane_id(); t < e; t += 64) {
         ++wc.arcs;
-        push_arc<W>(Sprev, NX, out_col[t], su, atomics);
+        push_arc<W>(NX, out_col[t], su, atomics);
     }
 }
 
