@@ -1719,8 +1719,15 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 cap_e.levels = 0;
             }
             hipGraph_t graph = nullptr;
-            if (rt_single) L.ensure_side();  // created outside the capture
-            const bool began = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            // the round trip's second stream, created outside the capture; without it, no replay
+            bool side_ok = true;
+            if (rt_single) try {
+                L.ensure_side();
+            } catch (const HipError&) {
+                side_ok = false;
+                (void)hipGetLastError();
+            }
+            const bool began = side_ok && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
             bool captured_ok = began;
             if (began && w_single) try {
                 // the weighted searches (one launch per direction), their distances and the D-based epilogue
@@ -1778,6 +1785,8 @@ cc_status run_job(cc_context* ctx, const cc_graph* gr, const Resolved& r, const 
                 CCG_HIP(hipGetLastError());
             } catch (const HipError&) {
                 captured_ok = false;
+                // rejoin the side stream so that the capture can be ended (a join already made adds nothing)
+                if (hipEventRecord(L.join_ev, L.side) == hipSuccess) (void)hipStreamWaitEvent(st, L.join_ev, 0);
             }
             else if (began) try {
                 const uint32_t* ctl_dev = (const uint32_t*)bfs_batched_ctl(ts, n, kg0);
