@@ -162,6 +162,7 @@ struct RowPiece {
 template <typename DT, bool RT>
 struct RawPiece {
     uint4 a, b;
+    uint4 a2;  // the second 16 bytes of a 32-byte piece (the estimate's wide lanes)
     int32_t j;
     __device__ __forceinline__ void fetch(const DT* __restrict__ D, const DT* __restrict__ Dr,
                                           const int32_t* __restrict__ sidx, int64_t v, int64_t n, int32_t k, int sub) {
@@ -234,6 +235,19 @@ __device__ __forceinline__ uint32_t bytes_first_eq(const uint4 a, uint32_t m) {
     uint32_t idx = 0;
 #pragma unroll
     for (int q = 3; q >= 0; q--) {
+        const uint32_t z = zero_byte_flags(w[q] ^ mb);
+        if (z) idx = 4u * (uint32_t)q + ((uint32_t)__builtin_ctz(z) >> 3);
+    }
+    return idx;
+}
+
+// index (0..31) of the first byte equal to m in the 32 bytes a (low) then a2
+__device__ __forceinline__ uint32_t bytes_first_eq2(const uint4 a, const uint4 a2, uint32_t m) {
+    const uint32_t mb = m * 0x01010101u;
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, a2.x, a2.y, a2.z, a2.w};
+    uint32_t idx = 0;
+#pragma unroll
+    for (int q = 7; q >= 0; q--) {
         const uint32_t z = zero_byte_flags(w[q] ^ mb);
         if (z) idx = 4u * (uint32_t)q + ((uint32_t)__builtin_ctz(z) >> 3);
     }
@@ -455,7 +469,7 @@ __device__ __forceinline__ void load_mt_piece(const MT* row, int sub, uint32_t (
 // first.  Two row pieces are refilled in turn, so the next trip's loads are in
 // flight while one is worked on; a lane of each group keeps its node's totals
 // until the round ends, and then all 64 lanes finish their nodes at once.
-template <typename DT, bool RT, typename MT, int G, bool LT, int BLOCK>
+template <typename DT, bool RT, typename MT, int G, int PC, bool LT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t n, int32_t k, const int32_t* __restrict__ orig,
     const int32_t* __restrict__ inv, const MT* __restrict__ dmat_c, const int32_t* __restrict__ Tcnt,
@@ -463,6 +477,8 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     double* S_hyb, double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out,
     int64_t* sampsum_out, DevFlags* flags) {
     static_assert(G >= 2 && G <= 16, "two to sixteen lanes per node");
+    static_assert(PC == 1 || (PC == 2 && sizeof(DT) == 1 && !RT && sizeof(MT) == 1),
+                  "32-byte lanes for u8 rows of one direction");
     extern __shared__ __align__(16) unsigned char lds_tab[];
     if (n < 1) return;
     constexpr int PER = RowPiece<DT, RT>::PER;
@@ -512,7 +528,8 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     auto fetch = [&](RawPiece<DT, RT>& rp, int64_t s, int64_t r_now) {
         const int32_t ids = (s / G == r_now) ? ids_cur : ids_nxt;
         const int64_t v = __shfl(ids, (int)(s % G) * NPW + q);
-        rp.a = ((const uint4*)(D + v * k))[sub];
+        rp.a = ((const uint4*)(D + v * k))[sub * PC];
+        if (PC == 2) rp.a2 = ((const uint4*)(D + v * k))[sub * PC + 1];
         rp.b = make_uint4(0, 0, 0, 0);
         if (RT) rp.b = ((const uint4*)(Dr + v * k))[sub];
     };
@@ -591,20 +608,24 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
         bool unr;
         if constexpr (kPacked) {
             // u8 rows, one direction, u8 sample distances: byte-packed arithmetic
+            // on the lane's PC pieces of 16 bytes
             const uint4 a = rp.a;
+            const uint4 a2 = PC == 2 ? rp.a2 : make_uint4(0, 0, 0, 0);
             fetch(rp, s + 2, r);
-            unr = valid && any_byte_ff(a);
-            const uint32_t m = bytes_min(a);
-            const uint32_t key = group_min32<G>(
-                valid ? ((m << 16) | ((uint32_t)sub * PER + bytes_first_eq(a, m))) : 0xFFFFFFFFu);
+            unr = valid && (any_byte_ff(a) || (PC == 2 && any_byte_ff(a2)));
+            const uint32_t m = PC == 2 ? min(bytes_min(a), bytes_min(a2)) : bytes_min(a);
+            const uint32_t at = PC == 2 ? bytes_first_eq2(a, a2, m) : bytes_first_eq(a, m);
+            const uint32_t key = group_min32<G>(valid ? ((m << 16) | ((uint32_t)sub * PER * PC + at)) : 0xFFFFFFFFu);
             best = key >> 16;  // the lowest index among equal minima
             bi = (int32_t)(key & 0xFFFFu);
-            sum = group_sum32<G>(valid ? bytes_sum(a, 0u) : 0u);
+            sum = group_sum32<G>(valid ? (PC == 2 ? bytes_sum(a2, bytes_sum(a, 0u)) : bytes_sum(a, 0u)) : 0u);
             const int64_t lim = en == 1 ? (int64_t)best * ed : (int64_t)best * ed / en;
             if (valid && best != 0) {
-                const uint4 dm = LT ? ((const uint4*)(l_dm + (uint32_t)bi * (uint32_t)k))[sub]
-                                    : ((const uint4*)(dmat_c + (int64_t)bi * k))[sub];
-                bytes_sum_le(a, dm, lim >= 255 ? 255u : (uint32_t)lim, lcsum, lcnum);
+                const uint4* dmr = LT ? (const uint4*)(l_dm + (uint32_t)bi * (uint32_t)k)
+                                      : (const uint4*)(dmat_c + (int64_t)bi * k);
+                const uint32_t L8 = lim >= 255 ? 255u : (uint32_t)lim;
+                bytes_sum_le(a, dmr[sub * PC], L8, lcsum, lcnum);
+                if (PC == 2) bytes_sum_le(a2, dmr[sub * PC + 1], L8, lcsum, lcnum);
             }
         } else {
             RowPiece<DT, RT> rw;
@@ -1528,22 +1549,33 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
         const unsigned ebl = (unsigned)std::max<int64_t>(
             1, std::min<int64_t>(kEstTableBlocks, (rounds + kEstBlock / 64 - 1) / (kEstBlock / 64)));
         const unsigned eb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (rounds + kBlock / 64 - 1) / (kBlock / 64)));
-#define CCG_EST_ROWS(GG)                                                                                               \
+#define CCG_EST_ROWS(GG, PP)                                                                                           \
     do {                                                                                                               \
         if (lt)                                                                                                        \
-            hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, true, kEstBlock>), dim3(ebl), dim3(kEstBlock), tb, st, \
-                               Dp, Drp, n, k, a.orig, a.inv, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,           \
+            hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, PP, true, kEstBlock>), dim3(ebl), dim3(kEstBlock), tb, \
+                               st, Dp, Drp, n, k, a.orig, a.inv, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,       \
                                a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);    \
         else                                                                                                           \
-            hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, false, kBlock>), dim3(eb), dim3(kBlock), 0, st, Dp,    \
-                               Drp, n, k, a.orig, a.inv, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den,    \
-                               a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);               \
+            hipLaunchKernelGGL((k_estimate_rows<DT, RT, MT, GG, PP, false, kBlock>), dim3(eb), dim3(kBlock), 0, st,    \
+                               Dp, Drp, n, k, a.orig, a.inv, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,           \
+                               a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);    \
     } while (0)
+        // byte-packed rows take 32 bytes per lane (half the lanes per node) from 64-byte rows up
+        constexpr bool kPk = sizeof(DT) == 1 && !RT && sizeof(MT) == 1;
         switch (G) {
-            case 2: CCG_EST_ROWS(2); break;
-            case 4: CCG_EST_ROWS(4); break;
-            case 8: CCG_EST_ROWS(8); break;
-            case 16: CCG_EST_ROWS(16); break;
+            case 2: CCG_EST_ROWS(2, 1); break;
+            case 4:
+                if constexpr (kPk) CCG_EST_ROWS(2, 2);
+                else CCG_EST_ROWS(4, 1);
+                break;
+            case 8:
+                if constexpr (kPk) CCG_EST_ROWS(4, 2);
+                else CCG_EST_ROWS(8, 1);
+                break;
+            case 16:
+                if constexpr (kPk) CCG_EST_ROWS(8, 2);
+                else CCG_EST_ROWS(16, 1);
+                break;
             default:
                 hipLaunchKernelGGL((k_estimate<DT, RT, MT>), dim3(grid_for(n, 4096)), dim3(kBlock), 0, st, Dp, Drp, n, k,
                                    a.sidx, a.orig, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num, a.eps_den, a.S_hyb,
