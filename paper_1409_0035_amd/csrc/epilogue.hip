@@ -144,13 +144,6 @@ struct RowPiece {
             }
         }
     }
-    __device__ __forceinline__ void load(const DT* __restrict__ D, const DT* __restrict__ Dr, int64_t v, int32_t k,
-                                         int sub) {
-        const uint4 a = ((const uint4*)(D + v * k))[sub];
-        uint4 b = make_uint4(0, 0, 0, 0);
-        if (RT) b = ((const uint4*)(Dr + v * k))[sub];
-        decode(a, b);
-    }
 };
 
 // A lane's undecoded piece of a node's row and the node's sample index, so
