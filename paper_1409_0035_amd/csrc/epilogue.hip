@@ -155,7 +155,7 @@ struct RowPiece {
 template <typename DT, bool RT>
 struct RawPiece {
     uint4 a, b;
-    uint4 a2;  // the second 16 bytes of a 32-byte piece (the estimate's wide lanes)
+    uint4 ax[3];  // the further 16-byte parts of a wider piece (the estimate's wide lanes)
     int32_t j;
     __device__ __forceinline__ void fetch(const DT* __restrict__ D, const DT* __restrict__ Dr,
                                           const int32_t* __restrict__ sidx, int64_t v, int64_t n, int32_t k, int sub) {
@@ -234,14 +234,16 @@ __device__ __forceinline__ uint32_t bytes_first_eq(const uint4 a, uint32_t m) {
     return idx;
 }
 
-// index (0..31) of the first byte equal to m in the 32 bytes a (low) then a2
-__device__ __forceinline__ uint32_t bytes_first_eq2(const uint4 a, const uint4 a2, uint32_t m) {
+// index (0 .. 16 PC - 1) of the first byte equal to m in the parts p[0] (low) .. p[PC - 1]
+template <int PC>
+__device__ __forceinline__ uint32_t bytes_first_eq_n(const uint4 (&p)[PC], uint32_t m) {
     const uint32_t mb = m * 0x01010101u;
-    const uint32_t w[8] = {a.x, a.y, a.z, a.w, a2.x, a2.y, a2.z, a2.w};
     uint32_t idx = 0;
 #pragma unroll
-    for (int q = 7; q >= 0; q--) {
-        const uint32_t z = zero_byte_flags(w[q] ^ mb);
+    for (int q = 4 * PC - 1; q >= 0; q--) {
+        const uint4 x = p[q >> 2];
+        const uint32_t w = (q & 3) == 0 ? x.x : (q & 3) == 1 ? x.y : (q & 3) == 2 ? x.z : x.w;
+        const uint32_t z = zero_byte_flags(w ^ mb);
         if (z) idx = 4u * (uint32_t)q + ((uint32_t)__builtin_ctz(z) >> 3);
     }
     return idx;
@@ -470,8 +472,8 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
     double* S_hyb, double* S_samp, int64_t* S_piv, int64_t* S_pub, int32_t* pivot_out, int32_t* delta_out,
     int64_t* sampsum_out, DevFlags* flags) {
     static_assert(G >= 2 && G <= 16, "two to sixteen lanes per node");
-    static_assert(PC == 1 || (PC == 2 && sizeof(DT) == 1 && !RT && sizeof(MT) == 1),
-                  "32-byte lanes for u8 rows of one direction");
+    static_assert(PC == 1 || ((PC == 2 || PC == 4) && sizeof(DT) == 1 && !RT && sizeof(MT) == 1),
+                  "32- and 64-byte lanes for u8 rows of one direction");
     extern __shared__ __align__(16) unsigned char lds_tab[];
     if (n < 1) return;
     constexpr int PER = RowPiece<DT, RT>::PER;
@@ -522,7 +524,8 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
         const int32_t ids = (s / G == r_now) ? ids_cur : ids_nxt;
         const int64_t v = __shfl(ids, (int)(s % G) * NPW + q);
         rp.a = ((const uint4*)(D + v * k))[sub * PC];
-        if (PC == 2) rp.a2 = ((const uint4*)(D + v * k))[sub * PC + 1];
+#pragma unroll
+        for (int i = 1; i < PC; i++) rp.ax[i - 1] = ((const uint4*)(D + v * k))[sub * PC + i];
         rp.b = make_uint4(0, 0, 0, 0);
         if (RT) rp.b = ((const uint4*)(Dr + v * k))[sub];
     };
@@ -602,23 +605,32 @@ __global__ __launch_bounds__(BLOCK) void k_estimate_rows(
         if constexpr (kPacked) {
             // u8 rows, one direction, u8 sample distances: byte-packed arithmetic
             // on the lane's PC pieces of 16 bytes
-            const uint4 a = rp.a;
-            const uint4 a2 = PC == 2 ? rp.a2 : make_uint4(0, 0, 0, 0);
+            uint4 pc[PC];
+            pc[0] = rp.a;
+#pragma unroll
+            for (int i = 1; i < PC; i++) pc[i] = rp.ax[i - 1];
             fetch(rp, s + 2, r);
-            unr = valid && (any_byte_ff(a) || (PC == 2 && any_byte_ff(a2)));
-            const uint32_t m = PC == 2 ? min(bytes_min(a), bytes_min(a2)) : bytes_min(a);
-            const uint32_t at = PC == 2 ? bytes_first_eq2(a, a2, m) : bytes_first_eq(a, m);
+            bool ff = false;
+            uint32_t m = 0xFFu, rs = 0;
+#pragma unroll
+            for (int i = 0; i < PC; i++) {
+                ff = ff || any_byte_ff(pc[i]);
+                m = min(m, bytes_min(pc[i]));
+                rs = bytes_sum(pc[i], rs);
+            }
+            unr = valid && ff;
+            const uint32_t at = bytes_first_eq_n<PC>(pc, m);
             const uint32_t key = group_min32<G>(valid ? ((m << 16) | ((uint32_t)sub * PER * PC + at)) : 0xFFFFFFFFu);
             best = key >> 16;  // the lowest index among equal minima
             bi = (int32_t)(key & 0xFFFFu);
-            sum = group_sum32<G>(valid ? (PC == 2 ? bytes_sum(a2, bytes_sum(a, 0u)) : bytes_sum(a, 0u)) : 0u);
+            sum = group_sum32<G>(valid ? rs : 0u);
             const int64_t lim = en == 1 ? (int64_t)best * ed : (int64_t)best * ed / en;
             if (valid && best != 0) {
                 const uint4* dmr = LT ? (const uint4*)(l_dm + (uint32_t)bi * (uint32_t)k)
                                       : (const uint4*)(dmat_c + (int64_t)bi * k);
                 const uint32_t L8 = lim >= 255 ? 255u : (uint32_t)lim;
-                bytes_sum_le(a, dmr[sub * PC], L8, lcsum, lcnum);
-                if (PC == 2) bytes_sum_le(a2, dmr[sub * PC + 1], L8, lcsum, lcnum);
+#pragma unroll
+                for (int i = 0; i < PC; i++) bytes_sum_le(pc[i], dmr[sub * PC + i], L8, lcsum, lcnum);
             }
         } else {
             RowPiece<DT, RT> rw;
@@ -1553,7 +1565,7 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
                                Dp, Drp, n, k, a.orig, a.inv, dmat_c, Tcnt, Tsum, tlen, a.src_sum, a.eps_num,           \
                                a.eps_den, a.S_hyb, a.S_samp, a.S_piv, a.S_pub, a.pivot, a.delta, a.sampsum, flags);    \
     } while (0)
-        // byte-packed rows take 32 bytes per lane (half the lanes per node) from 64-byte rows up
+        // byte-packed rows take 32 bytes per lane from 64-byte rows up, 64 bytes from 128-byte rows up
         constexpr bool kPk = sizeof(DT) == 1 && !RT && sizeof(MT) == 1;
         switch (G) {
             case 2: CCG_EST_ROWS(2, 1); break;
@@ -1562,11 +1574,11 @@ void epilogue_t(hipStream_t st, const EpilogueArgs& a, void* scratch, DevFlags* 
                 else CCG_EST_ROWS(4, 1);
                 break;
             case 8:
-                if constexpr (kPk) CCG_EST_ROWS(4, 2);
+                if constexpr (kPk) CCG_EST_ROWS(2, 4);
                 else CCG_EST_ROWS(8, 1);
                 break;
             case 16:
-                if constexpr (kPk) CCG_EST_ROWS(8, 2);
+                if constexpr (kPk) CCG_EST_ROWS(4, 4);
                 else CCG_EST_ROWS(16, 1);
                 break;
             default:
