@@ -233,6 +233,48 @@ def test_weighted_grid8(ctx):
     parity(ctx, g, 64, seed=3)
 
 
+GRID_OUT = ("S_hyb", "S_samp", "S_piv", "S_pub", "pivot", "delta", "sampsum", "src_sum", "samples", "dmat", "D")
+
+
+def _grid_check(got, ref, what):
+    for f in GRID_OUT:
+        assert np.array_equal(got[f], np.asarray(ref[f]).astype(got[f].dtype).reshape(got[f].shape)), (what, f)
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_weighted_grid_seeds(ctx, seed):
+    """The weighted workload's structure at 256 x 256 (65,536 nodes) with 64
+    samples: 64 workgroups relax crowded neighbourhoods at once, so a lost
+    update in the atomic relaxation would leave some distance above the
+    oracle's.  Every output against the oracle (its Algorithm 1 accounting,
+    which the pins tie to the literal Eq. (6))."""
+    g = graphgen.grid(256, 256, 8, 0.10, 1, 1000, seed=seed)
+    samples = np.asarray(oracle.draw_samples(g.n, 64, seed), dtype=np.int32)
+    ref = oracle.estimate_tails(g, samples, threads=8, adaptive_eps=())
+    _say(f"  grid256 seed={seed}")
+    _grid_check(run_gpu(ctx, g, 64, cc.CC_BATCHED, seed=seed), ref, seed)
+
+
+def test_weighted_grid_bucket_widths(ctx):
+    """The same grid under bucket widths far below and far above the default
+    (1, and 40 times the largest arc length): identical outputs, three runs
+    each."""
+    g = graphgen.grid(256, 256, 8, 0.10, 1, 1000, seed=25)
+    samples = np.asarray(oracle.draw_samples(g.n, 64, 25), dtype=np.int32)
+    ref = oracle.estimate_tails(g, samples, threads=8, adaptive_eps=())
+    gh = ctx.upload(g)
+    try:
+        default = cc.cc_graph_get_tuning(gh)
+        for delta in (1, 40_000, default["delta"]):
+            cc.cc_graph_set_tuning(gh, **{**default, "delta": delta})
+            for rep in range(3):
+                _say(f"  grid256 delta={delta} run {rep}")
+                got = cc.cc_estimate(ctx.handle, gh, 64, seed=25, outputs=GRID_OUT)
+                _grid_check(got, ref, (delta, rep))
+    finally:
+        ctx.release(gh)
+
+
 def test_weighted_unit_lengths_match_bfs(ctx):
     g = graphgen.ba(1500, 3, seed=8)
     gw = graphgen.Graph(g.n, g.row_ptr, g.col_idx, np.ones(g.arcs, np.int32), name="ba-unit-w")
