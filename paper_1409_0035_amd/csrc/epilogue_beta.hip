@@ -85,7 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_suffix(const unsigned long long
                                                         const int32_t* __restrict__ samples,
                                                         const uint32_t* __restrict__ beta, int64_t* __restrict__ WT,
                                                         int64_t* __restrict__ WC, int64_t* __restrict__ Sx,
-                                                        DevFlags* flags) {
+                                                        int32_t* __restrict__ farP, int32_t* __restrict__ farCnt,
+                                                        int32_t* __restrict__ farIdx, DevFlags* flags) {
     __shared__ int64_t ws[kBlock / 64], wc[kBlock / 64];
     const int32_t i = blockIdx.x;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -132,18 +133,46 @@ __global__ __launch_bounds__(kBlock) void k_beta_suffix(const unsigned long long
         }
         __syncthreads();
     }
-    // the samples' own part: sum_j beta(c_j) d(c_i, c_j)
+    // the samples' own part: sum_j beta(c_j) d(c_i, c_j); and the largest
+    // d(c_i, c_j), the distance of the samples that stand in for an empty HC
+    // when c_i is the pivot
     int64_t sj = 0;
-    for (int32_t j = threadIdx.x; j < k; j += kBlock) sj += (int64_t)beta[samples[j]] * dmat[(int64_t)i * k + j];
+    int32_t far = INT32_MIN;
+    for (int32_t j = threadIdx.x; j < k; j += kBlock) {
+        const int32_t d = dmat[(int64_t)i * k + j];
+        sj += (int64_t)beta[samples[j]] * d;
+        far = max(far, d);
+    }
     sj = wave_sum64(sj);
-    if (lane == 0) ws[wave] = sj;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) far = max(far, __shfl_xor(far, off));
+    __shared__ int32_t wf[kBlock / 64];
+    if (lane == 0) {
+        ws[wave] = sj;
+        wf[wave] = far;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t tot = carry;
-        for (int w = 0; w < kBlock / 64; w++) tot += ws[w];
+        int32_t f = INT32_MIN;
+        for (int w = 0; w < kBlock / 64; w++) {
+            tot += ws[w];
+            f = max(f, wf[w]);
+        }
         Sx[i] = tot;
+        farP[i] = f;
+        wf[0] = f;
         if (carry < 0 || tot < 0) ovf = true;
     }
+    // the samples at that distance, listed (in any order) for the estimate
+    __shared__ int32_t nfar;
+    if (threadIdx.x == 0) nfar = 0;
+    __syncthreads();
+    const int32_t fmax = wf[0];
+    for (int32_t j = threadIdx.x; j < k; j += kBlock)
+        if (dmat[(int64_t)i * k + j] == fmax) farIdx[(int64_t)i * k + atomicAdd(&nfar, 1)] = j;
+    __syncthreads();
+    if (threadIdx.x == 0) farCnt[i] = nfar;
     if (ovf) flags->overflow = 1;
 }
 
@@ -235,7 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
     const int32_t* __restrict__ D, int64_t n, int32_t k, const int32_t* __restrict__ dmat,
     const int32_t* __restrict__ sidx, const int32_t* __restrict__ samples, const uint32_t* __restrict__ beta,
     const uint8_t* __restrict__ light, int64_t R, int32_t m, int64_t num, int64_t den, const int64_t* __restrict__ WT,
-    const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, double* S, double* var, double* err,
+    const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, const int32_t* __restrict__ farP,
+    const int32_t* __restrict__ farCnt, const int32_t* __restrict__ farIdx, double* S, double* var, double* err,
     DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     const int g = threadIdx.x & (G - 1);
@@ -274,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
                 bi = oi;
             }
         }
-        const int32_t p = bi;
+        const int32_t p = bi < k ? bi : k - 1;  // a row with no finite entry (an error the traversal reports) stays in bounds
         const int64_t delta = best;
         const int32_t* drow = dmat + (int64_t)p * k;
         int64_t HC = 0, Lb = 0, Ls = 0, A = 0, B = 0, HCb = 0, HCsq = 0;
@@ -318,24 +348,16 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
                 __builtin_add_overflow(B, a5, &B) || __builtin_add_overflow(HCb, a6, &HCb) ||
                 __builtin_add_overflow(HCsq, a7, &HCsq);
         }
-        if (err && HCb == 0) {  // the farthest samples stand in for HC (HCb is the group's total)
-            int32_t far = -1;
-            for (int32_t c = g; c < pieces; c += G)
-                far = max(far, max(max(drow[4 * c], drow[4 * c + 1]), max(drow[4 * c + 2], drow[4 * c + 3])));
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) far = max(far, __shfl_xor(far, off, G));
-            for (int32_t c = g; c < pieces; c += G) {
-                const int4 x = row[c];
-                const int32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int32_t i = 4 * c + q;
-                    if (drow[i] != far) continue;
-                    const int64_t b = beta[samples[i]], df = (int64_t)w[q] - far;
-                    int64_t qq = 0;
-                    HCb += b;
-                    e = e || __builtin_mul_overflow(df * df, b, &qq) || __builtin_add_overflow(HCsq, qq, &HCsq);
-                }
+        if (err && HCb == 0) {  // HC has no weight (HCb is the group's total): the samples farthest from the pivot
+            // instead, from the pivot's list; the terms are non-negative, so a
+            // sum overflows in some grouping exactly when the total does
+            const int32_t far = farP[p], cnt = farCnt[p];
+            for (int32_t t = g; t < cnt; t += G) {
+                const int32_t i = farIdx[(int64_t)p * k + t];
+                const int64_t b = beta[samples[i]], df = (int64_t)D[v * k + i] - far;
+                int64_t qq = 0;
+                HCb += b;
+                e = e || __builtin_mul_overflow(df * df, b, &qq) || __builtin_add_overflow(HCsq, qq, &HCsq);
             }
 #pragma unroll
             for (int off = G / 2; off > 0; off >>= 1) {
@@ -384,7 +406,8 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
         maxd = hm;
     }
     const int64_t hlen = maxd + 2;
-    const size_t need = al(sizeof(uint64_t) * (size_t)k * hlen) * 3 + al(sizeof(int64_t) * (size_t)k);
+    const size_t need = al(sizeof(uint64_t) * (size_t)k * hlen) * 3 + al(sizeof(int64_t) * (size_t)k) +
+                        al(sizeof(int32_t) * (size_t)k) * 2 + al(sizeof(int32_t) * (size_t)k * k);
     void* scr = a.get_scratch(need);
     char* q = (char*)scr;
     unsigned long long* hw = (unsigned long long*)q;
@@ -394,6 +417,12 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     int64_t* WC = (int64_t*)q;
     q += al(sizeof(uint64_t) * (size_t)k * hlen);
     int64_t* Sx = (int64_t*)q;
+    q += al(sizeof(int64_t) * (size_t)k);
+    int32_t* farP = (int32_t*)q;
+    q += al(sizeof(int32_t) * (size_t)k);
+    int32_t* farCnt = (int32_t*)q;
+    q += al(sizeof(int32_t) * (size_t)k);
+    int32_t* farIdx = (int32_t*)q;
     fill_u32(st, hw, 0u, (size_t)k * hlen * 2);
     const size_t lds = sizeof(uint64_t) * (size_t)k * hlen;
     const int use_lds = lds <= 48 * 1024 ? 1 : 0;
@@ -401,14 +430,15 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     hipLaunchKernelGGL(k_beta_hist, dim3(hb), dim3(kBlock), use_lds ? lds : 0, st, a.D, n, k, a.sidx, a.beta, hlen, hw,
                        use_lds);
     hipLaunchKernelGGL(k_beta_suffix, dim3((unsigned)k), dim3(kBlock), 0, st, (const unsigned long long*)hw, k, hlen,
-                       a.dmat, a.samples, a.beta, WT, WC, Sx, flags);
+                       a.dmat, a.samples, a.beta, WT, WC, Sx, farP, farCnt, farIdx, flags);
     const int32_t pieces = k % 4 == 0 ? k / 4 : 0;
     const int G = pieces >= 16 ? 16 : (pieces >= 8 ? 8 : (pieces >= 4 ? 4 : 0));
     const unsigned eb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n * (G ? G : 1) + kBlock - 1) / kBlock, 16384));
 #define CCG_BETA_ROWS(GG)                                                                                            \
     hipLaunchKernelGGL((k_beta_estimate_rows<GG>), dim3(eb), dim3(kBlock), 0, st, a.D, n, k, a.dmat, a.sidx,          \
                        a.samples, a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT,                 \
-                       (const int64_t*)WC, hlen, (const int64_t*)Sx, a.S, a.var, a.err, flags)
+                       (const int64_t*)WC, hlen, (const int64_t*)Sx, (const int32_t*)farP,      \
+                       (const int32_t*)farCnt, (const int32_t*)farIdx, a.S, a.var, a.err, flags)
     switch (G) {
         case 16: CCG_BETA_ROWS(16); break;
         case 8: CCG_BETA_ROWS(8); break;

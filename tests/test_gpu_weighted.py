@@ -64,6 +64,28 @@ def test_weighted_matches_oracle(ctx, name, make, k, mode, eps, zero):
     _check(got, ref)
 
 
+@pytest.mark.parametrize("k,front,extra,seed", [(16, 64, {150: 3, 299: 1}, 7), (64, 128, {299: 1}, 8)])
+def test_weighted_error_with_empty_hc(ctx, k, front, extra, seed):
+    """A path of 300 nodes whose positive weights sit at the front (plus a
+    few far nodes the sample leaves out): for the nodes past the samples every
+    sample lies within Delta/eps of the pivot, so HC is empty while H still
+    has weight, and the error estimate takes Sec. 4.1's mean over the samples
+    farthest from the pivot (16 and 64 samples: rows of 4 and 16 pieces)."""
+    g = graphgen.path(300)
+    beta = np.zeros(g.n, np.uint32)
+    beta[:front] = 1
+    for u, b in extra.items():
+        beta[u] = b
+    ref = oracle.estimate_weighted(g, beta, k, seed, eps=(1, 2), threads=8)
+    assert 299 not in set(np.asarray(ref["samples"]).tolist())  # a weighted node beyond every sample
+    gh = ctx.upload(g)
+    try:
+        got = cc.cc_estimate_weighted(ctx.handle, gh, beta, k, seed=seed, eps=(1, 2))
+    finally:
+        ctx.release(gh)
+    _check(got, ref)
+
+
 def test_weighted_exact_when_all_positive_nodes_sampled(ctx):
     g = graphgen.ba(1500, 3, seed=9)
     beta = graphgen.node_weights(g.n, 4, zero_frac=0.9)
