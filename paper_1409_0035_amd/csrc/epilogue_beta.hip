@@ -18,14 +18,17 @@
 //   k_beta_hist      hw[i][d] = sum of beta(u) over u outside C with d(c_i,u) = d,
 //                    per block in LDS when the table fits
 //   k_beta_suffix    WT[i][t] = sum_{d >= t} d * hw[i][d] and WC[i][t] = sum_{d >= t}
-//                    hw[i][d]; exact S_beta(c_i) = WT[i][0] + sum_j beta(c_j) d(c_i, c_j)
+//                    hw[i][d]; exact S_beta(c_i) = WT[i][0] + sum_j beta(c_j) d(c_i, c_j);
+//                    the samples at the largest distance from c_i, listed
 // The error estimate (Sec. 4.1 with beta masses, Sec. 5) adds to the variance
 // estimate beta(H) (from WC) times the beta-weighted mean over HC of
 // (d(v,c_i) - d(c(v),c_i))^2.  When HC has no weight the mean is over the
 // samples at the largest distance from the pivot (Sec. 4.1's suffix of the
-// farthest samples), and 0 if those weigh nothing either.
+// farthest samples, read from the pivot's list), and 0 if those weigh
+// nothing either.
 //   k_beta_estimate  one lane per node: pivot, Delta, the split of the samples,
-//                    the estimate and the variance estimate
+//                    the estimate and the variance estimate (k_beta_estimate_rows:
+//                    G lanes per node, for rows of a multiple of 16 bytes)
 #include "internal.h"
 
 namespace ccg {
@@ -180,7 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
     const int32_t* __restrict__ D, int64_t n, int32_t k, const int32_t* __restrict__ dmat,
     const int32_t* __restrict__ sidx, const int32_t* __restrict__ samples, const uint32_t* __restrict__ beta,
     const uint8_t* __restrict__ light, int64_t R, int32_t m, int64_t num, int64_t den, const int64_t* __restrict__ WT,
-    const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, double* S, double* var, double* err,
+    const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, const int32_t* __restrict__ farP,
+    const int32_t* __restrict__ farCnt, const int32_t* __restrict__ farIdx, double* S, double* var, double* err,
     DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     bool ovf = false;
@@ -228,11 +232,10 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
                     __builtin_mul_overflow(df * df, b, &q) || __builtin_add_overflow(HCsq, q, &HCsq);
             }
         }
-        if (err && HCb == 0) {  // the farthest samples stand in for HC
-            int32_t far = -1;
-            for (int32_t i = 0; i < k; i++) far = max(far, drow[i]);
-            for (int32_t i = 0; i < k; i++) {
-                if (drow[i] != far) continue;
+        if (err && HCb == 0) {  // the samples farthest from the pivot stand in for HC (the pivot's list)
+            const int32_t far = farP[p], cnt = farCnt[p];
+            for (int32_t t = 0; t < cnt; t++) {
+                const int32_t i = farIdx[(int64_t)p * k + t];
                 const int64_t b = beta[samples[i]], df = (int64_t)row[i] - far;
                 int64_t q = 0;
                 HCb += b;
@@ -446,7 +449,8 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
         default:
             hipLaunchKernelGGL(k_beta_estimate, dim3(eb), dim3(kBlock), 0, st, a.D, n, k, a.dmat, a.sidx, a.samples,
                                a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT,
-                               (const int64_t*)WC, hlen, (const int64_t*)Sx, a.S, a.var, a.err, flags);
+                               (const int64_t*)WC, hlen, (const int64_t*)Sx, (const int32_t*)farP,
+                               (const int32_t*)farCnt, (const int32_t*)farIdx, a.S, a.var, a.err, flags);
     }
 #undef CCG_BETA_ROWS
     CCG_HIP(hipGetLastError());

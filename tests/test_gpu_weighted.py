@@ -64,13 +64,15 @@ def test_weighted_matches_oracle(ctx, name, make, k, mode, eps, zero):
     _check(got, ref)
 
 
-@pytest.mark.parametrize("k,front,extra,seed", [(16, 64, {150: 3, 299: 1}, 7), (64, 128, {299: 1}, 8)])
+@pytest.mark.parametrize("k,front,extra,seed", [(16, 64, {150: 3, 299: 1}, 7), (64, 128, {299: 1}, 8),
+                                                (15, 32, {299: 1}, 8)])
 def test_weighted_error_with_empty_hc(ctx, k, front, extra, seed):
     """A path of 300 nodes whose positive weights sit at the front (plus a
     few far nodes the sample leaves out): for the nodes past the samples every
     sample lies within Delta/eps of the pivot, so HC is empty while H still
     has weight, and the error estimate takes Sec. 4.1's mean over the samples
-    farthest from the pivot (16 and 64 samples: rows of 4 and 16 pieces)."""
+    farthest from the pivot (16 and 64 samples: rows of 4 and 16 pieces; 15
+    samples: one lane per node)."""
     g = graphgen.path(300)
     beta = np.zeros(g.n, np.uint32)
     beta[:front] = 1
