@@ -47,14 +47,42 @@ def pct(xs, q):
 
 
 SCATTER_KERNEL = "k_scatter_level"
+MERGE_KERNEL = "k_group_level"
 
 
 def bytes_per_arc(W: int) -> int:
     """Algorithmic bytes per arc of the scatter kernel: 4 B for the arc's end
-    id + 8W B for the far end's seen mask (a pull gathers the neighbour's
-    mask; a push reads the target's mask to drop bits it already has).  The
-    one atomic OR per hub chunk, and the pushes' atomics, are left out."""
+    id + 8W B for the far end's words (a pull gathers the neighbour's seen
+    mask; a push reads the target's pending words, the bits already pushed to
+    it).  The one atomic OR per hub chunk, and the pushes' atomics, are left
+    out."""
     return 4 + 8 * W
+
+
+def merge_bytes_per_node(W: int) -> int:
+    """Algorithmic bytes per node slot of a live group in the merge kernel:
+    the row bound (4 B), the node's seen mask in, its pending words and its
+    next seen mask (the level's snapshot) out, 8W B each."""
+    return 4 + 24 * W
+
+
+def merge_roofline(timings, W: int) -> dict:
+    """The merge kernel (one launch per level after the scatter launch): its
+    own pulls (arcs scanned minus the scatter's) at 4 + 8W B per arc, plus
+    4 + 24W B per node slot of the live groups, over the level batches' time
+    minus the scatter launches' (so the launch gaps count against it)."""
+    launches = sum(t["scatter_launches"] for t in timings)
+    ms = sum(t["kernel_ms"] - t["scatter_ms"] for t in timings)
+    if launches == 0 or ms <= 0:
+        return {"kernel": MERGE_KERNEL, "achieved": None, "frac": None}
+    arcs = sum(t["arcs_scanned"] - t["scatter_arcs"] for t in timings)
+    nodes = sum(t["nodes_visited"] for t in timings)
+    per_launch = (arcs * bytes_per_arc(W) + nodes * merge_bytes_per_node(W)) / launches
+    avg_ms = ms / launches
+    achieved = per_launch / (avg_ms / 1e3) / 1e9
+    return {"kernel": MERGE_KERNEL, "algorithmic_bytes_per_launch": int(per_launch),
+            "avg_launch_us": round(avg_ms * 1e3, 2), "achieved": round(achieved, 1), "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "arcs_per_launch": int(arcs / launches)}
 
 
 def source_digest(name: str = "bfs_batched.hip") -> str:
@@ -124,7 +152,9 @@ def scatter_roofline(timings, W: int, workload: str, tuning: dict) -> dict:
             # masks gathered (or pushed along) per second: a random-access rate, between the device's
             # measured 66 G/s for random loads that miss L2 and 261 G/s for ones that hit it
             "gathers_g_per_s": round(arcs / (ms / 1e3) / 1e9, 2),
-            "pull_levels_gbs": round(pull_arcs * bytes_per_arc(W) / (pull_ms / 1e3) / 1e9, 1) if pull_ms > 0 else None}
+            "pull_levels_gbs": round(pull_arcs * bytes_per_arc(W) / (pull_ms / 1e3) / 1e9, 1) if pull_ms > 0 else None,
+            # the level's other kernel, beside the dominant one
+            "merge": merge_roofline(timings, W)}
 
 
 def cpu_baseline(g, k, seed, rg=None, budget_s=24.0, exact_all_pairs=False):
