@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_suffix(const unsigned long long
                                                         const uint32_t* __restrict__ beta, int64_t* __restrict__ WT,
                                                         int64_t* __restrict__ WC, int64_t* __restrict__ Sx,
                                                         int32_t* __restrict__ farP, int32_t* __restrict__ farCnt,
-                                                        int32_t* __restrict__ farIdx, DevFlags* flags) {
+                                                        int32_t* __restrict__ farIdx, uint32_t* __restrict__ farB,
+                                                        DevFlags* flags) {
     __shared__ int64_t ws[kBlock / 64], wc[kBlock / 64];
     const int32_t i = blockIdx.x;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -173,7 +174,11 @@ __global__ __launch_bounds__(kBlock) void k_beta_suffix(const unsigned long long
     __syncthreads();
     const int32_t fmax = wf[0];
     for (int32_t j = threadIdx.x; j < k; j += kBlock)
-        if (dmat[(int64_t)i * k + j] == fmax) farIdx[(int64_t)i * k + atomicAdd(&nfar, 1)] = j;
+        if (dmat[(int64_t)i * k + j] == fmax) {
+            const int32_t t = atomicAdd(&nfar, 1);
+            farIdx[(int64_t)i * k + t] = j;
+            farB[(int64_t)i * k + t] = beta[samples[j]];
+        }
     __syncthreads();
     if (threadIdx.x == 0) farCnt[i] = nfar;
     if (ovf) flags->overflow = 1;
@@ -184,8 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
     const int32_t* __restrict__ sidx, const int32_t* __restrict__ samples, const uint32_t* __restrict__ beta,
     const uint8_t* __restrict__ light, int64_t R, int32_t m, int64_t num, int64_t den, const int64_t* __restrict__ WT,
     const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, const int32_t* __restrict__ farP,
-    const int32_t* __restrict__ farCnt, const int32_t* __restrict__ farIdx, double* S, double* var, double* err,
-    DevFlags* flags) {
+    const int32_t* __restrict__ farCnt, const int32_t* __restrict__ farIdx, const uint32_t* __restrict__ farB,
+    double* S, double* var, double* err, DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     bool ovf = false;
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate(
             const int32_t far = farP[p], cnt = farCnt[p];
             for (int32_t t = 0; t < cnt; t++) {
                 const int32_t i = farIdx[(int64_t)p * k + t];
-                const int64_t b = beta[samples[i]], df = (int64_t)row[i] - far;
+                const int64_t b = farB[(int64_t)p * k + t], df = (int64_t)row[i] - far;
                 int64_t q = 0;
                 HCb += b;
                 e = e || __builtin_mul_overflow(df * df, b, &q) || __builtin_add_overflow(HCsq, q, &HCsq);
@@ -268,8 +273,8 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
     const int32_t* __restrict__ sidx, const int32_t* __restrict__ samples, const uint32_t* __restrict__ beta,
     const uint8_t* __restrict__ light, int64_t R, int32_t m, int64_t num, int64_t den, const int64_t* __restrict__ WT,
     const int64_t* __restrict__ WC, int64_t hlen, const int64_t* __restrict__ Sx, const int32_t* __restrict__ farP,
-    const int32_t* __restrict__ farCnt, const int32_t* __restrict__ farIdx, double* S, double* var, double* err,
-    DevFlags* flags) {
+    const int32_t* __restrict__ farCnt, const int32_t* __restrict__ farIdx, const uint32_t* __restrict__ farB,
+    double* S, double* var, double* err, DevFlags* flags) {
     const int64_t LIM = (int64_t)1 << 53;
     const int g = threadIdx.x & (G - 1);
     const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
@@ -357,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_beta_estimate_rows(
             const int32_t far = farP[p], cnt = farCnt[p];
             for (int32_t t = g; t < cnt; t += G) {
                 const int32_t i = farIdx[(int64_t)p * k + t];
-                const int64_t b = beta[samples[i]], df = (int64_t)D[v * k + i] - far;
+                const int64_t b = farB[(int64_t)p * k + t], df = (int64_t)D[v * k + i] - far;
                 int64_t qq = 0;
                 HCb += b;
                 e = e || __builtin_mul_overflow(df * df, b, &qq) || __builtin_add_overflow(HCsq, qq, &HCsq);
@@ -410,7 +415,7 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     }
     const int64_t hlen = maxd + 2;
     const size_t need = al(sizeof(uint64_t) * (size_t)k * hlen) * 3 + al(sizeof(int64_t) * (size_t)k) +
-                        al(sizeof(int32_t) * (size_t)k) * 2 + al(sizeof(int32_t) * (size_t)k * k);
+                        al(sizeof(int32_t) * (size_t)k) * 2 + al(sizeof(int32_t) * (size_t)k * k) * 2;
     void* scr = a.get_scratch(need);
     char* q = (char*)scr;
     unsigned long long* hw = (unsigned long long*)q;
@@ -426,6 +431,8 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     int32_t* farCnt = (int32_t*)q;
     q += al(sizeof(int32_t) * (size_t)k);
     int32_t* farIdx = (int32_t*)q;
+    q += al(sizeof(int32_t) * (size_t)k * k);
+    uint32_t* farB = (uint32_t*)q;
     fill_u32(st, hw, 0u, (size_t)k * hlen * 2);
     const size_t lds = sizeof(uint64_t) * (size_t)k * hlen;
     const int use_lds = lds <= 48 * 1024 ? 1 : 0;
@@ -433,7 +440,7 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     hipLaunchKernelGGL(k_beta_hist, dim3(hb), dim3(kBlock), use_lds ? lds : 0, st, a.D, n, k, a.sidx, a.beta, hlen, hw,
                        use_lds);
     hipLaunchKernelGGL(k_beta_suffix, dim3((unsigned)k), dim3(kBlock), 0, st, (const unsigned long long*)hw, k, hlen,
-                       a.dmat, a.samples, a.beta, WT, WC, Sx, farP, farCnt, farIdx, flags);
+                       a.dmat, a.samples, a.beta, WT, WC, Sx, farP, farCnt, farIdx, farB, flags);
     const int32_t pieces = k % 4 == 0 ? k / 4 : 0;
     const int G = pieces >= 16 ? 16 : (pieces >= 8 ? 8 : (pieces >= 4 ? 4 : 0));
     const unsigned eb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n * (G ? G : 1) + kBlock - 1) / kBlock, 16384));
@@ -441,7 +448,7 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
     hipLaunchKernelGGL((k_beta_estimate_rows<GG>), dim3(eb), dim3(kBlock), 0, st, a.D, n, k, a.dmat, a.sidx,          \
                        a.samples, a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT,                 \
                        (const int64_t*)WC, hlen, (const int64_t*)Sx, (const int32_t*)farP,      \
-                       (const int32_t*)farCnt, (const int32_t*)farIdx, a.S, a.var, a.err, flags)
+                       (const int32_t*)farCnt, (const int32_t*)farIdx, (const uint32_t*)farB, a.S, a.var, a.err, flags)
     switch (G) {
         case 16: CCG_BETA_ROWS(16); break;
         case 8: CCG_BETA_ROWS(8); break;
@@ -450,7 +457,8 @@ void run_beta_epilogue(hipStream_t st, const BetaArgs& a, DevFlags* flags) {
             hipLaunchKernelGGL(k_beta_estimate, dim3(eb), dim3(kBlock), 0, st, a.D, n, k, a.dmat, a.sidx, a.samples,
                                a.beta, a.light, a.R, a.m, a.eps_num, a.eps_den, (const int64_t*)WT,
                                (const int64_t*)WC, hlen, (const int64_t*)Sx, (const int32_t*)farP,
-                               (const int32_t*)farCnt, (const int32_t*)farIdx, a.S, a.var, a.err, flags);
+                               (const int32_t*)farCnt, (const int32_t*)farIdx, (const uint32_t*)farB, a.S, a.var,
+                               a.err, flags);
     }
 #undef CCG_BETA_ROWS
     CCG_HIP(hipGetLastError());
