@@ -329,13 +329,17 @@ __device__ void decide_wave(LevelCounters* cnt, BfsCtl* ctl, int32_t* mode_log, 
 // drops them (new = NX & ~S), and skipping the load of x's mask makes the push
 // one random read and at most one atomic per word (rmat22dir: push levels
 // 0.745 -> 0.641 ms; without the pending test too, 0.703 ms, as hubs then
-// take every atomic).
+// take every atomic).  Targets past the hub prefix (ids >= check_below) are
+// rarely pushed to twice in one level, so they take the atomic without the
+// read.
 template <int W>
-__device__ __forceinline__ void push_arc(uint64_t* NX, int64_t x, const uint64_t (&su)[W], int64_t& atomics) {
+__device__ __forceinline__ void push_arc(uint64_t* NX, int64_t x, const uint64_t (&su)[W], int64_t check_below,
+                                         int64_t& atomics) {
 #pragma unroll
     for (int w = 0; w < W; w++) {
         if (!su[w]) continue;
-        const uint64_t pending = __hip_atomic_load(&NX[x * W + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t pending =
+            x < check_below ? __hip_atomic_load(&NX[x * W + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
         const uint64_t r = su[w] & ~pending;
         if (r) {
             atomicOr((unsigned long long*)&NX[x * W + w], (unsigned long long)r);
@@ -351,8 +355,8 @@ template <int W>
 __device__ __forceinline__ void push_group(const uint32_t* __restrict__ out_rp, const int32_t* __restrict__ out_col,
                                            const int32_t* __restrict__ chg, const uint8_t* __restrict__ ghub,
                                            int64_t n, int32_t g, int32_t prev_level,
-                                           const uint64_t* __restrict__ Sprev, uint64_t* NX, WaveCounts& wc,
-                                           int64_t& atomics) {
+                                           const uint64_t* __restrict__ Sprev, uint64_t* NX, int64_t check_below,
+                                           WaveCounts& wc, int64_t& atomics) {
     const int lane = lane_id();
     if (ghub && ghub[g]) return;  // hubs push by chunks
     const int64_t v = (int64_t)g * 64 + lane;
@@ -367,7 +371,7 @@ __device__ __forceinline__ void push_group(const uint32_t* __restrict__ out_rp, 
         const uint32_t b = out_rp[u], e = out_rp[u + 1];
         for (uint32_t t = b + lane; t < e; t += 64) {
             ++wc.arcs;
-            push_arc<W>(NX, out_col[t], su, atomics);
+            push_arc<W>(NX, out_col[t], su, check_below, atomics);
         }
     }
 }
@@ -377,8 +381,8 @@ __device__ __forceinline__ void push_group(const uint32_t* __restrict__ out_rp, 
 template <int W>
 __device__ __forceinline__ void push_chunk(const int32_t* __restrict__ out_col, const int32_t* __restrict__ chunk,
                                            const int32_t* __restrict__ chg, int32_t prev_level,
-                                           const uint64_t* __restrict__ Sprev, uint64_t* NX, WaveCounts& wc,
-                                           int64_t& atomics) {
+                                           const uint64_t* __restrict__ Sprev, uint64_t* NX, int64_t check_below,
+                                           WaveCounts& wc, int64_t& atomics) {
     const int64_t h = chunk[0];
     if (chg[h] != prev_level) return;
     const uint32_t b = (uint32_t)chunk[1], e = (uint32_t)chunk[2];
@@ -387,7 +391,7 @@ __device__ __forceinline__ void push_chunk(const int32_t* __restrict__ out_col, 
     for (int w = 0; w < W; w++) su[w] = Sprev[h * W + w];
     for (uint32_t t = b + lane_id(); t < e; t += 64) {
         ++wc.arcs;
-        push_arc<W>(NX, out_col[t], su, atomics);
+        push_arc<W>(NX, out_col[t], su, check_below, atomics);
     }
 }
 
@@ -477,12 +481,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter_level(
             hub_chunk<W>(col, Sprev, hub_chunks + 3 * (int64_t)c, NX, lastmask, chgbits, sparse, extra);
     } else {
         const int64_t items = (int64_t)n_push_chunks + (ngroups - g0);
+        // only targets in the hub prefix (high in-degree) are likely to hold
+        // pushed bits already; the others take the atomic without the read
+        const int64_t check_below = (ghub || g0 == 0) ? n : (int64_t)g0 * 64;
         for (int64_t t = wid; t < items; t += waves) {
             if (t < n_push_chunks)
-                push_chunk<W>(out_col, push_chunks + 3 * t, chg, prev_level, Sprev, NX, wc, extra);
+                push_chunk<W>(out_col, push_chunks + 3 * t, chg, prev_level, Sprev, NX, check_below, wc, extra);
             else
                 push_group<W>(out_rp, out_col, chg, ghub, n, g0 + (int32_t)(t - n_push_chunks), prev_level, Sprev,
-                              NX, wc, extra);
+                              NX, check_below, wc, extra);
         }
     }
     wc.hub = extra;
